@@ -1,0 +1,178 @@
+"""Throughput of the SUPA propagation path on one MI355X.
+
+One step = one supa_simulate call over the whole batch of the named workload
+(initial conditions resident in HBM before timing): every particle of every
+shower propagated plane by plane, hit clouds and per-layer images written.
+Prints one JSON line (see the keys below).  The CPU oracle is timed on a
+bounded sample on the host's cores and reported beside it.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+CU, LANES, CLOCK_GHZ = 256, 64, 2.4
+PEAK_ALU_TOPS = CU * LANES * CLOCK_GHZ * 1e9 / 1e12      # 39.3 T lane-ops/s (one op/lane/clock)
+
+# algorithmic lane-operations per unit of work (counted from the method's
+# arithmetic, not from compiled code):
+OPS_PER_ARRIVAL = 3       # flight (2 fma) + threshold compare
+OPS_PER_DRAW = 82         # Philox4x32-10: 10 rounds x (2 mul_hi + 2 mul_lo + 4 xor) + 2 compares
+OPS_PER_SPLIT = 65        # energy split, angles, frame, two rotations, two slope divisions
+BYTES_PER_HIT = 16        # x, y, E (f32) + layer (i32)
+BYTES_PER_SHOWER_IO = 12 + 32 + 24 + 8   # e0/polar/azimuth in; ledger, counts, offset out
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="e1to100_20planes_img32_100k")
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=20000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (reference for HBM counters)")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, geom, n_sample: int, images: bool):
+    from oracle import supa_oracle as O
+    from paper_2202_05012_amd import workloads
+    threads = min(os.cpu_count() or 1, 16)
+    e0, pol, az = workloads.initial_conditions(w, n_sample)
+    chunk = 128
+
+    def run(s):
+        r = O.simulate(geom, e0[s:s + chunk], pol[s:s + chunk], az[s:s + chunk], w.seed,
+                       shower_id_base=s)
+        if images:
+            O.images(r, geom["n_planes"], geom["img_nx"], geom["img_ny"], geom["img_x0"],
+                     geom["img_x1"], geom["img_y0"], geom["img_y1"])
+        return int(r["counts"][:, 2].sum())
+
+    from concurrent.futures import ThreadPoolExecutor
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        steps = sum(ex.map(run, range(0, n_sample, chunk)))
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "showers/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_sample} showers of the workload, oracle simulation"
+                      f"{' + image binning' if images else ''}, {threads} host threads",
+            "particle_steps_per_s": steps / dt, "seconds": dt}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(showers shard by shower_id_base; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2202_05012_amd import supa, workloads
+
+    w = workloads.WORKLOADS[args.workload]
+    geom = workloads.geometry(w)
+    outputs = supa.OUT_HITS | (supa.OUT_IMAGES if w.images else 0) | (supa.OUT_TREE if w.tree else 0)
+    dev = torch.device("cuda", 0)
+    e0, pol, az = workloads.initial_conditions(w)
+    te0, tpol, taz = (torch.from_numpy(a).to(dev) for a in (e0, pol, az))
+    sim = supa.Simulator(geom, outputs, waves_per_cu=args.waves_per_cu)
+
+    # size the outputs from one untimed run (also grows the per-wave scratch)
+    probe = sim.allocate(w.n, 0, 0)
+    sim.run(te0, tpol, taz, w.seed, probe)
+    out = sim.allocate(w.n, int(probe["total_hits"] * 1.0) + 1, int(probe["total_nodes"]) + 1)
+    del probe
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for _ in range(args.warmup):
+        st = sim.run(te0, tpol, taz, w.seed, out)
+        assert st == 0
+    torch.cuda.synchronize()
+    kernel_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = sim.run(te0, tpol, taz, w.seed, out)
+        kernel_ms.append(sim.timing()[0])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert st == 0
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+
+    counts = out["counts"].cpu().numpy().astype(np.int64)
+    steps_total = int(counts[:, 2].sum())
+    hits_total = int(counts[:, 1].sum())
+    splits_total = int(counts[:, 3].sum())
+    draws = steps_total - hits_total          # p_stop = 0 in these workloads: every hit is a cut
+    showers_per_s = w.n / (ms_per_step / 1e3)
+
+    k_ms = float(np.mean(kernel_ms))
+    alg_ops = OPS_PER_ARRIVAL * steps_total + OPS_PER_DRAW * draws + OPS_PER_SPLIT * splits_total
+    alg_bytes = BYTES_PER_HIT * hits_total + BYTES_PER_SHOWER_IO * w.n
+    if w.images:
+        alg_bytes += w.n * geom["n_planes"] * geom["img_nx"] * geom["img_ny"] * 4
+    if w.tree:
+        alg_bytes += 24 * int(counts[:, 0].sum()) + 8 * w.n
+    alu = alg_ops / (k_ms / 1e3) / 1e12
+    hbm = alg_bytes / (k_ms / 1e3) / 1e9
+    alu_frac, hbm_frac = alu / PEAK_ALU_TOPS, hbm / PEAK_HBM_GBS
+    if hbm_frac >= alu_frac:
+        roof = {"bound": "hbm", "achieved": round(hbm, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 4), "traffic": None}
+    else:
+        roof = {"bound": "alu", "achieved": round(alu, 3), "peak": round(PEAK_ALU_TOPS, 2),
+                "unit": "T lane-ops/s", "frac": round(alu_frac, 4), "traffic": None}
+    roof.update(kernel="supa_propagate", kernel_ms=round(k_ms, 4),
+                other={"alu_T_lane_ops_s": round(alu, 3), "alu_frac": round(alu_frac, 4),
+                       "hbm_GBs": round(hbm, 1), "hbm_frac": round(hbm_frac, 4),
+                       "alg_bytes": alg_bytes, "alg_lane_ops": alg_ops})
+
+    line = {
+        "metric": "showers/s (1 MI355X)",
+        "value": round(showers_per_s, 1),
+        "unit": "showers/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+u32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "showers": w.n, "planes": w.n_planes,
+                   "outputs": "hits" + ("+images%dx%d" % w.images[:2] if w.images else "")
+                              + ("+tree" if w.tree else "")},
+        "particle_steps_per_s": round(steps_total / (ms_per_step / 1e3), 1),
+        "particle_steps": steps_total,
+        "hits": hits_total,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, geom, min(args.cpu_sample, w.n), bool(w.images))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

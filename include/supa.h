@@ -1,0 +1,218 @@
+/*
+ * supa.h -- C ABI of the MI355X (gfx950) SUPA shower-propagation library.
+ *
+ * The library runs the particle-splitting process of SUPA (paper: section
+ * "Propagation Model" and Algorithm 1 "SUPA - Particle Splitting") for a
+ * batch of showers in hand-written HIP kernels and returns, per shower, its
+ * hit point cloud (section "Propagation Model": deposits collected after the
+ * last slice, z projected out per layer; "Notation": per-layer clouds of
+ * (eta, phi, E)), optional per-layer images (appendix "Downsampling"), the
+ * optional propagation tree (Algorithm 1's tree T), an exact energy ledger
+ * and counts.
+ *
+ * Conventions for every function below:
+ *   - every function returns a supa_status and never throws or aborts;
+ *   - "device pointer" means memory on the context's GPU, allocated and owned
+ *     by the caller (the library never frees it); "host pointer" means CPU
+ *     memory read during the call only;
+ *   - work is enqueued on the HIP stream given to supa_init_geometry;
+ *     supa_simulate synchronises that stream once, at its end, to read back
+ *     totals and error flags;
+ *   - a context is not thread-safe; use one per stream;
+ *   - after an error, supa_last_error(ctx) describes it.
+ *
+ * Numerics (identical in every entry point):
+ *   - energies are unsigned 32-bit fixed point with `energy_frac_bits` (s)
+ *     fractional bits: E_int = round-to-nearest-even(E0 * 2^s); a split gives
+ *     E_a = floor(E_int * F / 2^32) and E_b = E_int - E_a, F the 32-bit energy
+ *     fraction (Algorithm 1's E(theta/2 +- eps)/theta with f = 1/2 + eps/theta);
+ *     float outputs are E_int * 2^-s rounded once to float;
+ *   - randomness: one Philox4x32-10 block (Salmon et al., SC'11) per particle
+ *     arrival, key = seed, counter = (plane k, shower id, path id low, path id
+ *     high); the path id is 1 for the primary and 2p, 2p+1 for the daughters
+ *     of path p, so results do not depend on launch order or batch split;
+ *   - on arrival at plane k a particle below the energy threshold deposits
+ *     (a "cut" hit); otherwise word w0 decides: stop if w0 < C1[k], split if
+ *     C1[k] <= w0 < C2[k], pass otherwise, C1 = floor(p_stop*2^32),
+ *     C2 = C1 + floor(p_split*2^32) (Algorithm 1's three-way choice);
+ *   - a split turns the direction by theta*(1-f) and theta*f to opposite sides
+ *     of the plane at azimuth omega = 2*pi*u(w3) (u(w) = (w + 1/2)/2^32), with
+ *     theta FIXED, UNIFORM or RAYLEIGH from w2 and F from w1;
+ *   - particles fly straight between planes and leave after the last plane or
+ *     when their direction stops pointing to +z.
+ */
+#ifndef SUPA_H
+#define SUPA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SUPA_ABI_VERSION 1
+
+typedef enum supa_status {
+    SUPA_OK = 0,
+    SUPA_ERR_INVALID_ARG = 1, /* bad parameter, NULL where required, bad size   */
+    SUPA_ERR_RANGE = 2,       /* an initial energy is < 0, NaN or >= 2^(32-s)    */
+    SUPA_ERR_CAPACITY = 3,    /* caller's hit or node arrays too small; totals set */
+    SUPA_ERR_DEVICE = 4,      /* a HIP runtime call failed                       */
+    SUPA_ERR_STATE = 5,       /* context unusable (NULL or after a device error) */
+    SUPA_ERR_NOMEM = 6        /* library could not allocate its device scratch   */
+} supa_status;
+
+enum { SUPA_ANGLE_FIXED = 0, SUPA_ANGLE_UNIFORM = 1, SUPA_ANGLE_RAYLEIGH = 2 };
+
+/* Output selection bits for supa_geometry.outputs. */
+enum {
+    SUPA_OUT_HITS = 1,   /* hit point clouds                                 */
+    SUPA_OUT_IMAGES = 2, /* per-layer images (needs SUPA_OUT_HITS)           */
+    SUPA_OUT_TREE = 4,   /* propagation tree                                 */
+    SUPA_OUT_KEYS = 8    /* path ids of hits and nodes (canonical keys)      */
+};
+
+/*
+ * Process parameters (Algorithm 1 "Parameters": p_stop, p_split, layer
+ * configuration, slice gap, splitting angle, deviation angle; Table 2).
+ * Host struct; host arrays are deep-copied by supa_init_geometry.
+ */
+typedef struct supa_geometry {
+    int32_t n_planes;               /* N, 1..63 (path ids must fit in 64 bits)        */
+    double z_first, dz;             /* plane k at z_first + k*dz; z_first > 0, dz > 0;
+                                       the primary starts at z = 0                     */
+    const int32_t *layer_of_plane;  /* host, N entries in [-1, N), or NULL = identity;
+                                       -1 = plane not read out (hits keep layer -1 and
+                                       are left out of images)                        */
+    const double *p_stop;           /* host, N entries, or NULL = all 0               */
+    const double *p_split;          /* host, N entries, or NULL = all 1;
+                                       p_stop[k] + p_split[k] <= 1                    */
+    double e_cut;                   /* energy threshold >= 0 (energy units)            */
+    int32_t angle_mode;             /* SUPA_ANGLE_*                                   */
+    double angle_a, angle_b;        /* FIXED: theta = a; UNIFORM: theta ~ U(a, b);
+                                       RAYLEIGH: theta = a*sqrt(-2 ln u), sigma = a    */
+    double frac_lo, frac_hi;        /* f ~ U(frac_lo, frac_hi), 0 <= lo <= hi <= 1     */
+    int32_t energy_frac_bits;       /* s, 0..31 (21: resolution 2^-21, E0 < 2048)      */
+    int32_t img_nx, img_ny;         /* image grid (used with SUPA_OUT_IMAGES), >= 1    */
+    double img_x0, img_x1;          /* region of interest [x0, x1) x [y0, y1),         */
+    double img_y0, img_y1;          /* cells half-open; x1 > x0, y1 > y0               */
+    uint32_t outputs;               /* SUPA_OUT_* bitmask                             */
+} supa_geometry;
+
+/* Opaque context: the parameters, their device copies and library scratch. */
+typedef struct supa_ctx supa_ctx;
+
+/* Initial conditions of a batch (section "Using SUPA": energy, angle and
+ * position of the incident particle).  Device pointers of n floats each. */
+typedef struct supa_batch {
+    const float *e0;          /* initial energy (energy units), required          */
+    const float *polar;       /* polar angle from +z (radians), required           */
+    const float *azimuth;     /* azimuth (radians), required                        */
+    const float *x0, *y0;     /* impact point at z = 0, or NULL for 0               */
+    int64_t n;                /* showers, 0 <= n <= 2^31 - 1                        */
+    uint32_t shower_id_base;  /* shower i has global id shower_id_base + i          */
+} supa_batch;
+
+/*
+ * Outputs.  All arrays are device pointers owned by the caller.
+ * Layout is segmented: the hits of shower i occupy the contiguous range
+ * [hit_offsets[i], hit_offsets[i] + counts[6*i+1]) of every hit array; the
+ * segments of a batch are disjoint and tile [0, total_hits) with no gap, in an
+ * unspecified order of showers.  Within a segment hits are ordered by plane and
+ * then by the order in which their particles were created.  Nodes likewise.
+ */
+typedef struct supa_output {
+    /* hit point clouds (SUPA_OUT_HITS); hit_key also needs SUPA_OUT_KEYS */
+    int64_t *hit_offsets;            /* n                                        */
+    float *hit_x, *hit_y, *hit_e;    /* hit_capacity each                        */
+    int32_t *hit_layer;              /* hit_capacity                             */
+    uint64_t *hit_key;               /* hit_capacity, or NULL                    */
+    int64_t hit_capacity;
+    /* images (SUPA_OUT_IMAGES): n * L * img_ny * img_nx floats, L = 1 + the
+       largest layer index; pixel [i][l][iy][ix] sums the energies of the
+       shower's hits of layer l with floor((x - x0)*nx/(x1 - x0)) == ix and
+       floor((y - y0)*ny/(y1 - y0)) == iy (appendix "Downsampling") */
+    float *images;
+    /* propagation tree (SUPA_OUT_TREE): per node its parent's index within the
+       shower (-1 for the primary), generation (splits since the primary),
+       vertex (where it was created) and energy */
+    int64_t *node_offsets;           /* n                                        */
+    int32_t *node_parent, *node_gen; /* node_capacity each                       */
+    float *node_vx, *node_vy, *node_vz, *node_e;
+    uint64_t *node_key;              /* node_capacity, or NULL                   */
+    int64_t node_capacity;
+    /* always written: */
+    uint64_t *ledger;                /* n * 4: E0, deposited by stops, deposited
+                                        below threshold, escaped (fixed point);
+                                        E0 == sum of the other three            */
+    int32_t *counts;                 /* n * 6: nodes, hits, particle-steps,
+                                        splits, escaped particles, escapes
+                                        because the direction turned away from +z */
+    /* host outputs, set on SUPA_OK and on SUPA_ERR_CAPACITY: */
+    int64_t total_hits, total_nodes, total_steps;
+} supa_output;
+
+/* Version of this ABI (SUPA_ABI_VERSION). */
+int32_t supa_abi_version(void);
+
+/* Checks parameters on the host only (no device call): SUPA_OK or
+ * SUPA_ERR_INVALID_ARG.  Same checks as supa_init_geometry. */
+supa_status supa_validate_geometry(const supa_geometry *g);
+
+/*
+ * Creates a context for device `device` and HIP stream `hip_stream`
+ * (hipStream_t, may be NULL for the default stream).  Validates `g` on the
+ * host, derives the integer thresholds, copies them to the device and
+ * allocates the library's scratch.  *out receives the context (NULL on error).
+ */
+supa_status supa_init_geometry(const supa_geometry *g, int device, void *hip_stream,
+                               supa_ctx **out);
+
+/* Frees the context and its device scratch (after synchronising its stream). */
+supa_status supa_destroy(supa_ctx *ctx);
+
+/*
+ * Simulates a batch with 64-bit `seed` (Algorithm 1 applied plane by plane to
+ * every live particle of every shower).  Fills `out` as described above.
+ * Errors: INVALID_ARG (NULL pointers for requested outputs, bad n),
+ * RANGE (an initial energy out of range: nothing else is meaningful),
+ * CAPACITY (total hits or nodes exceed the capacities: ledger, counts and the
+ * host totals are valid, hit/node arrays are not; a retry with larger arrays
+ * gives the same per-shower results), DEVICE.
+ */
+supa_status supa_simulate(supa_ctx *ctx, const supa_batch *b, uint64_t seed,
+                          supa_output *out);
+
+/*
+ * Launch settings of the propagation kernel.  waves_per_cu: resident waves
+ * per compute unit (1..16); 0 keeps the current value.  frontier_cap,
+ * hit_cap, node_cap: per-wave scratch capacities in particles, hits, nodes
+ * (0 keeps the current value; they also grow by themselves when a shower needs
+ * more).  Affects speed only, never results.
+ */
+supa_status supa_set_launch(supa_ctx *ctx, int32_t waves_per_cu, int32_t frontier_cap,
+                            int32_t hit_cap, int32_t node_cap);
+
+/*
+ * Device time of the last supa_simulate, in milliseconds, measured with HIP
+ * events on the context's stream: [0] propagation kernel, [1] image kernel,
+ * [2] whole call.  Host pointer to 3 floats.
+ */
+supa_status supa_last_timing(const supa_ctx *ctx, float *ms3);
+
+/*
+ * One Philox4x32-10 block per counter, on the device: ctr and out are device
+ * arrays of 4*n uint32 (counter words c0..c3 / output words w0..w3).  For
+ * checking the device generator against independent implementations.
+ */
+supa_status supa_philox(supa_ctx *ctx, const uint32_t *ctr, int64_t n, uint64_t key,
+                        uint32_t *out);
+
+/* Description of the last error of ctx (or of the last failed
+ * supa_init_geometry when ctx is NULL); owned by the library. */
+const char *supa_last_error(const supa_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

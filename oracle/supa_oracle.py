@@ -156,7 +156,7 @@ def simulate(geom: dict, e0, polar, azimuth, seed: int, x0=None, y0=None,
             raise ValueError(f"oracle error {status}: {ERRORS.get(status, '?')}")
         nh, nn = res.n_hits, res.n_nodes
         out = {
-            "hit_sid": _copy(res.hit_sid, nh, np.int32),
+            "hit_sid": _copy(res.hit_sid, nh, np.int32).view(np.uint32).astype(np.int64),
             "hit_plane": _copy(res.hit_plane, nh, np.int32),
             "hit_layer": _copy(res.hit_layer, nh, np.int32),
             "hit_kind": _copy(res.hit_kind, nh, np.int32),
@@ -164,7 +164,7 @@ def simulate(geom: dict, e0, polar, azimuth, seed: int, x0=None, y0=None,
             "hit_y": _copy(res.hit_y, nh, np.float64),
             "hit_e": _copy(res.hit_e, nh, np.uint32),
             "hit_key": _copy(res.hit_key, nh, np.uint64),
-            "node_sid": _copy(res.node_sid, nn, np.int32),
+            "node_sid": _copy(res.node_sid, nn, np.int32).view(np.uint32).astype(np.int64),
             "node_parent": _copy(res.node_parent, nn, np.int32),
             "node_gen": _copy(res.node_gen, nn, np.int32),
             "node_vx": _copy(res.node_vx, nn, np.float64),

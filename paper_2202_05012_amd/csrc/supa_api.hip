@@ -1,0 +1,438 @@
+// supa_api.hip -- host side of the C ABI declared in include/supa.h.
+//
+// Validates parameters on the host, derives the integer thresholds of the
+// three-way choice and of the energy split, keeps their device copies and the
+// per-wave scratch of the propagation kernel, and launches it on the caller's
+// stream.  Scratch grows (and the batch is rerun, which the counter-based
+// randomness makes bit-identical) when a shower needs more than it holds.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/supa.h"
+#include "supa_device.hpp"
+
+namespace supa {
+hipError_t launch_zero_counters(unsigned long long *ctr, hipStream_t s);
+hipError_t launch_propagate(const Params &P, int blocks, hipStream_t s);
+hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
+                         hipStream_t s);
+int waves_per_block();
+int tile_words();
+}  // namespace supa
+
+struct supa_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    supa_geometry g{};                 // host copy (array pointers cleared)
+    std::vector<int32_t> layer;        // host copies
+    std::vector<double> p_stop, p_split;
+    int32_t n_layers = 0;
+    // derived constants
+    uint64_t t_cut = 0;
+    uint32_t f_lo = 0;
+    uint64_t f_w = 0;
+    // device copies
+    int32_t *d_layer = nullptr;
+    uint64_t *d_c1 = nullptr, *d_c2 = nullptr;
+    unsigned long long *d_ctr = nullptr;
+    unsigned long long *h_ctr = nullptr;   // pinned
+    // per-wave scratch
+    int n_cu = 0;
+    int waves_per_cu = 8;
+    int cap_f = 1024, cap_h = 4096, cap_n = 8192;
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    supa::Params layout{};               // scratch pointers only
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    float timing[3] = {0, 0, 0};
+    std::string err;
+    bool broken = false;
+};
+
+static std::string g_init_error;
+
+static supa_status fail(supa_ctx *c, supa_status s, const std::string &msg) {
+    if (c) c->err = msg; else g_init_error = msg;
+    return s;
+}
+
+static supa_status hip_fail(supa_ctx *c, hipError_t e, const char *what) {
+    if (c) c->broken = true;
+    return fail(c, SUPA_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(c, call)                                 \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return hip_fail(c, e_, #call); \
+    } while (0)
+
+extern "C" int32_t supa_abi_version(void) { return SUPA_ABI_VERSION; }
+
+static bool is_fin(double v) { return std::isfinite(v); }
+
+static supa_status validate(const supa_geometry *g, std::string &why) {
+    if (!g) { why = "geometry is NULL"; return SUPA_ERR_INVALID_ARG; }
+    if (g->n_planes < 1 || g->n_planes > 63) { why = "n_planes must be in [1, 63]"; return SUPA_ERR_INVALID_ARG; }
+    if (!is_fin(g->z_first) || !is_fin(g->dz) || !(g->dz > 0) || !(g->z_first > 0)) {
+        why = "z_first and dz must be finite and > 0";
+        return SUPA_ERR_INVALID_ARG;
+    }
+    if (!is_fin(g->e_cut) || !(g->e_cut >= 0)) { why = "e_cut must be finite and >= 0"; return SUPA_ERR_INVALID_ARG; }
+    if (g->angle_mode < SUPA_ANGLE_FIXED || g->angle_mode > SUPA_ANGLE_RAYLEIGH) {
+        why = "unknown angle_mode";
+        return SUPA_ERR_INVALID_ARG;
+    }
+    if (!is_fin(g->angle_a) || !is_fin(g->angle_b)) { why = "angles must be finite"; return SUPA_ERR_INVALID_ARG; }
+    if (!(g->frac_lo >= 0 && g->frac_lo <= g->frac_hi && g->frac_hi <= 1)) {
+        why = "need 0 <= frac_lo <= frac_hi <= 1";
+        return SUPA_ERR_INVALID_ARG;
+    }
+    if (g->energy_frac_bits < 0 || g->energy_frac_bits > 31) {
+        why = "energy_frac_bits must be in [0, 31]";
+        return SUPA_ERR_INVALID_ARG;
+    }
+    for (int k = 0; k < g->n_planes; ++k) {
+        const double ps = g->p_stop ? g->p_stop[k] : 0.0;
+        const double pl = g->p_split ? g->p_split[k] : 1.0;
+        if (!(ps >= 0 && pl >= 0 && ps + pl <= 1)) {
+            why = "need p_stop, p_split >= 0 and p_stop + p_split <= 1 on every plane";
+            return SUPA_ERR_INVALID_ARG;
+        }
+        if (g->layer_of_plane && (g->layer_of_plane[k] < -1 || g->layer_of_plane[k] >= g->n_planes)) {
+            why = "layer_of_plane entries must be in [-1, n_planes)";
+            return SUPA_ERR_INVALID_ARG;
+        }
+    }
+    if (g->outputs & ~15u) { why = "unknown output bits"; return SUPA_ERR_INVALID_ARG; }
+    if (g->outputs & SUPA_OUT_IMAGES) {
+        if (g->img_nx < 1 || g->img_ny < 1 || g->img_nx > supa::tile_words()) {
+            why = "image grid must have 1 <= nx <= 2048 and ny >= 1";
+            return SUPA_ERR_INVALID_ARG;
+        }
+        if (!is_fin(g->img_x0) || !is_fin(g->img_x1) || !is_fin(g->img_y0) || !is_fin(g->img_y1) ||
+            !(g->img_x1 > g->img_x0) || !(g->img_y1 > g->img_y0)) {
+            why = "image window must be finite with x1 > x0 and y1 > y0";
+            return SUPA_ERR_INVALID_ARG;
+        }
+    }
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_validate_geometry(const supa_geometry *g) {
+    std::string why;
+    supa_status s = validate(g, why);
+    if (s != SUPA_OK) g_init_error = why;
+    return s;
+}
+
+static void free_scratch(supa_ctx *c) {
+    if (c->scratch) (void)hipFree(c->scratch);
+    c->scratch = nullptr;
+    c->scratch_bytes = 0;
+}
+
+// Carves the per-wave scratch out of one allocation (256-byte aligned arrays).
+static supa_status ensure_scratch(supa_ctx *c, bool hits, bool tree) {
+    const int64_t waves = (int64_t)c->n_cu * c->waves_per_cu;
+    const int64_t F = waves * 2 * c->cap_f;
+    const int64_t H = hits ? waves * c->cap_h : 0;
+    const int64_t Nn = tree ? waves * c->cap_n : 0;
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t need = 8 * al(F * 4) + 6 * al(H * 4) + 8 * al(Nn * 4);
+    if (need > c->scratch_bytes) {
+        free_scratch(c);
+        void *p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, SUPA_ERR_NOMEM, "cannot allocate " + std::to_string(need) + " bytes of scratch");
+        }
+        c->scratch = p;
+        c->scratch_bytes = need;
+    }
+    char *p = (char *)c->scratch;
+    auto take = [&](size_t b) { char *q = p; p += al(b); return (void *)q; };
+    supa::Params &L = c->layout;
+    L.cap_f = c->cap_f;
+    L.cap_h = c->cap_h;
+    L.cap_n = c->cap_n;
+    L.fx = (float *)take(F * 4);
+    L.fy = (float *)take(F * 4);
+    L.ftx = (float *)take(F * 4);
+    L.fty = (float *)take(F * 4);
+    L.fe = (uint32_t *)take(F * 4);
+    L.fplo = (uint32_t *)take(F * 4);
+    L.fphi = (uint32_t *)take(F * 4);
+    L.fnode = (int32_t *)take(F * 4);
+    L.jhx = (float *)take(H * 4);
+    L.jhy = (float *)take(H * 4);
+    L.jhe = (uint32_t *)take(H * 4);
+    L.jhl = (int32_t *)take(H * 4);
+    L.jhplo = (uint32_t *)take(H * 4);
+    L.jhphi = (uint32_t *)take(H * 4);
+    L.jnp = (int32_t *)take(Nn * 4);
+    L.jng = (int32_t *)take(Nn * 4);
+    L.jnx = (float *)take(Nn * 4);
+    L.jny = (float *)take(Nn * 4);
+    L.jnz = (float *)take(Nn * 4);
+    L.jne = (uint32_t *)take(Nn * 4);
+    L.jnplo = (uint32_t *)take(Nn * 4);
+    L.jnphi = (uint32_t *)take(Nn * 4);
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, void *hip_stream,
+                                          supa_ctx **out) {
+    if (!out) return fail(nullptr, SUPA_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    supa_status s = validate(g, why);
+    if (s != SUPA_OK) return fail(nullptr, s, why);
+
+    supa_ctx *c = new supa_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->g = *g;
+    const int N = g->n_planes;
+    c->layer.resize(N);
+    c->p_stop.resize(N);
+    c->p_split.resize(N);
+    int32_t max_layer = -1;
+    for (int k = 0; k < N; ++k) {
+        c->layer[k] = g->layer_of_plane ? g->layer_of_plane[k] : k;
+        c->p_stop[k] = g->p_stop ? g->p_stop[k] : 0.0;
+        c->p_split[k] = g->p_split ? g->p_split[k] : 1.0;
+        max_layer = std::max(max_layer, c->layer[k]);
+    }
+    c->n_layers = max_layer + 1;
+    c->g.layer_of_plane = nullptr;
+    c->g.p_stop = nullptr;
+    c->g.p_split = nullptr;
+
+    // integer thresholds: stop iff w0 < C1, split iff C1 <= w0 < C2
+    std::vector<uint64_t> c1(N), c2(N);
+    for (int k = 0; k < N; ++k) {
+        c1[k] = (uint64_t)std::floor(std::ldexp(c->p_stop[k], 32));
+        c2[k] = c1[k] + (uint64_t)std::floor(std::ldexp(c->p_split[k], 32));
+    }
+    const double tc = std::ceil(std::ldexp(g->e_cut, g->energy_frac_bits));
+    c->t_cut = tc >= 18446744073709551615.0 ? ~0ull : (uint64_t)tc;
+    c->f_lo = (uint32_t)std::min(std::floor(std::ldexp(g->frac_lo, 32)), 4294967295.0);
+    c->f_w = (uint64_t)std::floor(std::ldexp(g->frac_hi, 32)) - (uint64_t)std::floor(std::ldexp(g->frac_lo, 32));
+
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) { delete c; return hip_fail(nullptr, e, "hipSetDevice"); }
+    if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        c->n_cu <= 0) {
+        delete c;
+        return fail(nullptr, SUPA_ERR_DEVICE, "cannot query compute units");
+    }
+    bool ok = hipMalloc(&c->d_layer, N * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&c->d_c1, N * sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(&c->d_c2, N * sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(&c->d_ctr, supa::CTR_COUNT * sizeof(unsigned long long)) == hipSuccess &&
+              hipHostMalloc(&c->h_ctr, supa::CTR_COUNT * sizeof(unsigned long long), 0) == hipSuccess &&
+              hipMemcpy(c->d_layer, c->layer.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->d_c1, c1.data(), N * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->d_c2, c2.data(), N * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess;
+    for (int q = 0; q < 3 && ok; ++q) ok = hipEventCreate(&c->ev[q]) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        supa_destroy(c);
+        return fail(nullptr, SUPA_ERR_DEVICE, "device allocation or copy failed in init");
+    }
+    *out = c;
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_destroy(supa_ctx *c) {
+    if (!c) return SUPA_ERR_STATE;
+    (void)hipSetDevice(c->device);
+    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    free_scratch(c);
+    if (c->d_layer) (void)hipFree(c->d_layer);
+    if (c->d_c1) (void)hipFree(c->d_c1);
+    if (c->d_c2) (void)hipFree(c->d_c2);
+    if (c->d_ctr) (void)hipFree(c->d_ctr);
+    if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+    for (auto &ev : c->ev)
+        if (ev) (void)hipEventDestroy(ev);
+    delete c;
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_set_launch(supa_ctx *c, int32_t waves_per_cu, int32_t frontier_cap,
+                                       int32_t hit_cap, int32_t node_cap) {
+    if (!c) return SUPA_ERR_STATE;
+    if (waves_per_cu < 0 || waves_per_cu > 16 || frontier_cap < 0 || hit_cap < 0 || node_cap < 0)
+        return fail(c, SUPA_ERR_INVALID_ARG, "launch settings out of range");
+    if (waves_per_cu) c->waves_per_cu = waves_per_cu;
+    if (frontier_cap) c->cap_f = frontier_cap;
+    if (hit_cap) c->cap_h = hit_cap;
+    if (node_cap) c->cap_n = node_cap;
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_last_timing(const supa_ctx *c, float *ms3) {
+    if (!c) return SUPA_ERR_STATE;
+    if (!ms3) return SUPA_ERR_INVALID_ARG;
+    std::memcpy(ms3, c->timing, sizeof(c->timing));
+    return SUPA_OK;
+}
+
+extern "C" const char *supa_last_error(const supa_ctx *c) {
+    return c ? c->err.c_str() : g_init_error.c_str();
+}
+
+extern "C" supa_status supa_philox(supa_ctx *c, const uint32_t *ctr, int64_t n, uint64_t key,
+                                   uint32_t *out) {
+    if (!c) return SUPA_ERR_STATE;
+    if (n < 0 || (n > 0 && (!ctr || !out))) return fail(c, SUPA_ERR_INVALID_ARG, "bad philox arguments");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, supa::launch_philox(ctr, n, (uint32_t)key, (uint32_t)(key >> 32), out, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SUPA_OK;
+}
+
+static int64_t round_up_pow2(int64_t v) {
+    int64_t p = 64;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t seed,
+                                     supa_output *out) {
+    if (!c) return SUPA_ERR_STATE;
+    if (c->broken) return fail(c, SUPA_ERR_STATE, "context unusable after a device error");
+    c->err.clear();
+    if (!b || !out) return fail(c, SUPA_ERR_INVALID_ARG, "batch or output is NULL");
+    if (b->n < 0 || b->n > 2147483647LL) return fail(c, SUPA_ERR_INVALID_ARG, "n out of range");
+    const uint32_t outs = c->g.outputs;
+    const int64_t n = b->n;
+    out->total_hits = out->total_nodes = out->total_steps = 0;
+    if (n > 0 && (!b->e0 || !b->polar || !b->azimuth))
+        return fail(c, SUPA_ERR_INVALID_ARG, "e0, polar and azimuth are required");
+    if (n > 0 && (!out->ledger || !out->counts)) return fail(c, SUPA_ERR_INVALID_ARG, "ledger and counts are required");
+    if ((outs & SUPA_OUT_HITS) && n > 0 &&
+        (!out->hit_offsets || ((!out->hit_x || !out->hit_y || !out->hit_e || !out->hit_layer) && out->hit_capacity > 0) ||
+         out->hit_capacity < 0 || ((outs & SUPA_OUT_KEYS) && out->hit_capacity > 0 && !out->hit_key)))
+        return fail(c, SUPA_ERR_INVALID_ARG, "hit outputs missing");
+    if ((outs & SUPA_OUT_IMAGES) && n > 0 && !out->images) return fail(c, SUPA_ERR_INVALID_ARG, "images missing");
+    if ((outs & SUPA_OUT_TREE) && n > 0 &&
+        (!out->node_offsets || out->node_capacity < 0 ||
+         ((!out->node_parent || !out->node_gen || !out->node_vx || !out->node_vy || !out->node_vz || !out->node_e) &&
+          out->node_capacity > 0) ||
+         ((outs & SUPA_OUT_KEYS) && out->node_capacity > 0 && !out->node_key)))
+        return fail(c, SUPA_ERR_INVALID_ARG, "tree outputs missing");
+    if (n == 0) return SUPA_OK;
+
+    HIP_TRY(c, hipSetDevice(c->device));
+    const bool hits = (outs & (SUPA_OUT_HITS | SUPA_OUT_IMAGES)) != 0;
+    const bool tree = (outs & SUPA_OUT_TREE) != 0;
+
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        supa_status s = ensure_scratch(c, hits, tree);
+        if (s != SUPA_OK) return s;
+        supa::Params P = c->layout;
+        P.n_planes = c->g.n_planes;
+        P.n_layers = c->n_layers;
+        P.z_first = (float)c->g.z_first;
+        P.dz = (float)c->g.dz;
+        P.layer = c->d_layer;
+        P.c1 = c->d_c1;
+        P.c2 = c->d_c2;
+        P.t_cut = c->t_cut;
+        P.f_lo = c->f_lo;
+        P.f_w = c->f_w;
+        P.angle_mode = c->g.angle_mode;
+        P.angle_a = (float)c->g.angle_a;
+        P.angle_b = (float)c->g.angle_b;
+        P.e_scale = std::ldexp(1.0f, c->g.energy_frac_bits);
+        P.e_unscale = std::ldexp(1.0f, -c->g.energy_frac_bits);
+        P.seed_lo = (uint32_t)seed;
+        P.seed_hi = (uint32_t)(seed >> 32);
+        P.e0 = b->e0;
+        P.polar = b->polar;
+        P.azimuth = b->azimuth;
+        P.x0 = b->x0;
+        P.y0 = b->y0;
+        P.n = (int32_t)n;
+        P.sid_base = b->shower_id_base;
+        P.order = nullptr;
+        P.outputs = outs;
+        P.hit_offsets = out->hit_offsets;
+        P.hit_x = out->hit_x;
+        P.hit_y = out->hit_y;
+        P.hit_e = out->hit_e;
+        P.hit_layer = out->hit_layer;
+        P.hit_key = (outs & SUPA_OUT_KEYS) ? out->hit_key : nullptr;
+        P.hit_capacity = (outs & SUPA_OUT_HITS) ? out->hit_capacity : 0;
+        P.images = out->images;
+        P.img_nx = c->g.img_nx;
+        P.img_ny = c->g.img_ny;
+        P.img_x0 = (float)c->g.img_x0;
+        P.img_y0 = (float)c->g.img_y0;
+        P.img_sx = (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0));
+        P.img_sy = (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0));
+        P.img_rows = (outs & SUPA_OUT_IMAGES) ? std::max(1, std::min(c->g.img_ny, supa::tile_words() / c->g.img_nx)) : 1;
+        P.node_offsets = out->node_offsets;
+        P.node_parent = out->node_parent;
+        P.node_gen = out->node_gen;
+        P.node_vx = out->node_vx;
+        P.node_vy = out->node_vy;
+        P.node_vz = out->node_vz;
+        P.node_e = out->node_e;
+        P.node_key = (outs & SUPA_OUT_KEYS) ? out->node_key : nullptr;
+        P.node_capacity = tree ? out->node_capacity : 0;
+        P.ledger = out->ledger;
+        P.counts = out->counts;
+        P.ctr = c->d_ctr;
+
+        const int wpb = supa::waves_per_block();
+        const int blocks = std::max(1, (c->n_cu * c->waves_per_cu) / wpb);
+        HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+        HIP_TRY(c, supa::launch_zero_counters(c->d_ctr, c->stream));
+        HIP_TRY(c, supa::launch_propagate(P, blocks, c->stream));
+        HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+        HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_COUNT * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        float t01 = 0, t02 = 0;
+        (void)hipEventElapsedTime(&t01, c->ev[0], c->ev[1]);
+        (void)hipEventElapsedTime(&t02, c->ev[0], c->ev[2]);
+        c->timing[0] = t01;
+        c->timing[1] = 0.f;
+        c->timing[2] = t02;
+
+        const unsigned long long flags = c->h_ctr[supa::CTR_FLAGS];
+        if (flags & supa::FLAG_RANGE)
+            return fail(c, SUPA_ERR_RANGE, "an initial energy is negative, NaN or too large for the fixed-point format");
+        if (flags & supa::FLAG_OVERFLOW) {
+            // grow the per-wave scratch to what the largest shower needed, rerun
+            const int64_t nf = (int64_t)c->h_ctr[supa::CTR_NEED_F];
+            const int64_t nh = (int64_t)c->h_ctr[supa::CTR_NEED_H];
+            const int64_t nn = (int64_t)c->h_ctr[supa::CTR_NEED_N];
+            const int64_t cap_max = (int64_t)1 << 30;
+            c->cap_f = (int)std::min(cap_max, std::max<int64_t>(c->cap_f, round_up_pow2(nf + 1)));
+            c->cap_h = (int)std::min(cap_max, std::max<int64_t>(c->cap_h, round_up_pow2(nh + 1)));
+            c->cap_n = (int)std::min(cap_max, std::max<int64_t>(c->cap_n, round_up_pow2(nn + 2)));
+            continue;
+        }
+        out->total_steps = (int64_t)c->h_ctr[supa::CTR_STEPS];
+        out->total_hits = (outs & SUPA_OUT_HITS) ? (int64_t)c->h_ctr[supa::CTR_HITS] : 0;
+        out->total_nodes = tree ? (int64_t)c->h_ctr[supa::CTR_NODES] : 0;
+        if ((outs & SUPA_OUT_HITS) && out->total_hits > out->hit_capacity)
+            return fail(c, SUPA_ERR_CAPACITY, "hit arrays too small: need " + std::to_string(out->total_hits));
+        if (tree && out->total_nodes > out->node_capacity)
+            return fail(c, SUPA_ERR_CAPACITY, "node arrays too small: need " + std::to_string(out->total_nodes));
+        return SUPA_OK;
+    }
+    return fail(c, SUPA_ERR_NOMEM, "per-wave scratch did not converge");
+}

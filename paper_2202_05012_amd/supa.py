@@ -1,0 +1,299 @@
+"""Python binding of libsupa.so (C ABI in include/supa.h).
+
+Argument marshalling only: PyTorch supplies device memory and the stream,
+every step of the simulation runs in the library's HIP kernels.  There is no
+CPU fallback: if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsupa.so")
+
+ANGLE_MODES = {"fixed": 0, "uniform": 1, "rayleigh": 2}
+OUT_HITS, OUT_IMAGES, OUT_TREE, OUT_KEYS = 1, 2, 4, 8
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "RANGE", 3: "CAPACITY", 4: "DEVICE", 5: "STATE",
+          6: "NOMEM"}
+
+
+class SupaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Geometry(C.Structure):
+    _fields_ = [
+        ("n_planes", C.c_int32),
+        ("z_first", C.c_double), ("dz", C.c_double),
+        ("layer_of_plane", C.POINTER(C.c_int32)),
+        ("p_stop", C.POINTER(C.c_double)),
+        ("p_split", C.POINTER(C.c_double)),
+        ("e_cut", C.c_double),
+        ("angle_mode", C.c_int32),
+        ("angle_a", C.c_double), ("angle_b", C.c_double),
+        ("frac_lo", C.c_double), ("frac_hi", C.c_double),
+        ("energy_frac_bits", C.c_int32),
+        ("img_nx", C.c_int32), ("img_ny", C.c_int32),
+        ("img_x0", C.c_double), ("img_x1", C.c_double),
+        ("img_y0", C.c_double), ("img_y1", C.c_double),
+        ("outputs", C.c_uint32),
+    ]
+
+
+class Batch(C.Structure):
+    _fields_ = [
+        ("e0", C.c_void_p), ("polar", C.c_void_p), ("azimuth", C.c_void_p),
+        ("x0", C.c_void_p), ("y0", C.c_void_p),
+        ("n", C.c_int64), ("shower_id_base", C.c_uint32),
+    ]
+
+
+class Output(C.Structure):
+    _fields_ = [
+        ("hit_offsets", C.c_void_p),
+        ("hit_x", C.c_void_p), ("hit_y", C.c_void_p), ("hit_e", C.c_void_p),
+        ("hit_layer", C.c_void_p), ("hit_key", C.c_void_p), ("hit_capacity", C.c_int64),
+        ("images", C.c_void_p),
+        ("node_offsets", C.c_void_p),
+        ("node_parent", C.c_void_p), ("node_gen", C.c_void_p),
+        ("node_vx", C.c_void_p), ("node_vy", C.c_void_p), ("node_vz", C.c_void_p),
+        ("node_e", C.c_void_p), ("node_key", C.c_void_p), ("node_capacity", C.c_int64),
+        ("ledger", C.c_void_p), ("counts", C.c_void_p),
+        ("total_hits", C.c_int64), ("total_nodes", C.c_int64), ("total_steps", C.c_int64),
+    ]
+
+
+EXPORTS = ["supa_abi_version", "supa_validate_geometry", "supa_init_geometry", "supa_destroy",
+           "supa_simulate", "supa_set_launch", "supa_last_timing", "supa_philox",
+           "supa_last_error"]
+
+_lib = None
+
+
+def load():
+    """Load libsupa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m "
+                               "paper_2202_05012_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        L.supa_abi_version.restype = C.c_int32
+        L.supa_validate_geometry.restype = C.c_int
+        L.supa_validate_geometry.argtypes = [C.POINTER(Geometry)]
+        L.supa_init_geometry.restype = C.c_int
+        L.supa_init_geometry.argtypes = [C.POINTER(Geometry), C.c_int, C.c_void_p,
+                                         C.POINTER(C.c_void_p)]
+        L.supa_destroy.restype = C.c_int
+        L.supa_destroy.argtypes = [C.c_void_p]
+        L.supa_simulate.restype = C.c_int
+        L.supa_simulate.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_uint64, C.POINTER(Output)]
+        L.supa_set_launch.restype = C.c_int
+        L.supa_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+        L.supa_last_timing.restype = C.c_int
+        L.supa_last_timing.argtypes = [C.c_void_p, C.POINTER(C.c_float)]
+        L.supa_philox.restype = C.c_int
+        L.supa_philox.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p]
+        L.supa_last_error.restype = C.c_char_p
+        L.supa_last_error.argtypes = [C.c_void_p]
+        _lib = L
+    return _lib
+
+
+def make_geometry(geom: dict, outputs: int):
+    """Fill the C struct from a parameter dict; returns (struct, keep-alive list)."""
+    N = int(geom["n_planes"])
+    keep = []
+
+    def arr(key, ctype):
+        v = geom.get(key)
+        if v is None:
+            return None
+        a = (ctype * N)(*[ctype(x).value for x in v])
+        if len(v) != N:
+            raise ValueError(f"{key} must have n_planes entries")
+        keep.append(a)
+        return C.cast(a, C.POINTER(ctype))
+
+    g = Geometry()
+    g.n_planes = N
+    g.z_first = float(geom.get("z_first", geom["dz"]))
+    g.dz = float(geom["dz"])
+    g.layer_of_plane = arr("layer_of_plane", C.c_int32)
+    g.p_stop = arr("p_stop", C.c_double)
+    g.p_split = arr("p_split", C.c_double)
+    g.e_cut = float(geom["e_cut"])
+    g.angle_mode = ANGLE_MODES[geom["angle_mode"]]
+    g.angle_a = float(geom.get("angle_a", 0.0))
+    g.angle_b = float(geom.get("angle_b", 0.0))
+    g.frac_lo = float(geom.get("frac_lo", 0.0))
+    g.frac_hi = float(geom.get("frac_hi", 1.0))
+    g.energy_frac_bits = int(geom.get("frac_bits", 21))
+    g.img_nx = int(geom.get("img_nx", 0))
+    g.img_ny = int(geom.get("img_ny", 0))
+    g.img_x0 = float(geom.get("img_x0", 0.0))
+    g.img_x1 = float(geom.get("img_x1", 0.0))
+    g.img_y0 = float(geom.get("img_y0", 0.0))
+    g.img_y1 = float(geom.get("img_y1", 0.0))
+    g.outputs = outputs
+    return g, keep
+
+
+def n_layers(geom: dict) -> int:
+    lop = geom.get("layer_of_plane")
+    if lop is None:
+        return int(geom["n_planes"])
+    return int(max(lop)) + 1
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class Simulator:
+    """A library context bound to one device and the current torch stream."""
+
+    def __init__(self, geom: dict, outputs: int = OUT_HITS, device: int = 0,
+                 waves_per_cu: int = 0, frontier_cap: int = 0, hit_cap: int = 0,
+                 node_cap: int = 0):
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libsupa needs a GPU; none is visible")
+        self.geom = dict(geom)
+        self.outputs = outputs
+        self.device = torch.device("cuda", device)
+        self.L = n_layers(geom)
+        g, keep = make_geometry(geom, outputs)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
+        st = self.lib.supa_init_geometry(C.byref(g), device, C.c_void_p(self.stream.cuda_stream),
+                                         C.byref(ctx))
+        if st != 0:
+            raise SupaError(st, self.lib.supa_last_error(None).decode())
+        self.ctx = ctx
+        if waves_per_cu or frontier_cap or hit_cap or node_cap:
+            self.set_launch(waves_per_cu, frontier_cap, hit_cap, node_cap)
+
+    def set_launch(self, waves_per_cu=0, frontier_cap=0, hit_cap=0, node_cap=0):
+        st = self.lib.supa_set_launch(self.ctx, waves_per_cu, frontier_cap, hit_cap, node_cap)
+        self._check(st)
+
+    def _check(self, st):
+        if st != 0:
+            raise SupaError(st, self.lib.supa_last_error(self.ctx).decode())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.supa_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def timing(self):
+        ms = (C.c_float * 3)()
+        self._check(self.lib.supa_last_timing(self.ctx, ms))
+        return list(ms)
+
+    def allocate(self, n: int, hit_capacity: int = 0, node_capacity: int = 0) -> dict:
+        """Output tensors for n showers with the given capacities."""
+        dev = self.device
+        o = {"ledger": torch.empty((n, 4), dtype=torch.int64, device=dev),
+             "counts": torch.empty((n, 6), dtype=torch.int32, device=dev)}
+        if self.outputs & OUT_HITS:
+            o["hit_offsets"] = torch.empty(n, dtype=torch.int64, device=dev)
+            for k in ("hit_x", "hit_y", "hit_e"):
+                o[k] = torch.empty(hit_capacity, dtype=torch.float32, device=dev)
+            o["hit_layer"] = torch.empty(hit_capacity, dtype=torch.int32, device=dev)
+            if self.outputs & OUT_KEYS:
+                o["hit_key"] = torch.empty(hit_capacity, dtype=torch.int64, device=dev)
+        if self.outputs & OUT_IMAGES:
+            o["images"] = torch.empty((n, self.L, int(self.geom["img_ny"]),
+                                       int(self.geom["img_nx"])), dtype=torch.float32, device=dev)
+        if self.outputs & OUT_TREE:
+            o["node_offsets"] = torch.empty(n, dtype=torch.int64, device=dev)
+            o["node_parent"] = torch.empty(node_capacity, dtype=torch.int32, device=dev)
+            o["node_gen"] = torch.empty(node_capacity, dtype=torch.int32, device=dev)
+            for k in ("node_vx", "node_vy", "node_vz", "node_e"):
+                o[k] = torch.empty(node_capacity, dtype=torch.float32, device=dev)
+            if self.outputs & OUT_KEYS:
+                o["node_key"] = torch.empty(node_capacity, dtype=torch.int64, device=dev)
+        o["hit_capacity"] = hit_capacity
+        o["node_capacity"] = node_capacity
+        return o
+
+    def run(self, e0, polar, azimuth, seed: int, out: dict, x0=None, y0=None,
+            shower_id_base: int = 0) -> int:
+        """One supa_simulate call into preallocated outputs; returns the status
+        (OK or CAPACITY) and fills out['total_*']."""
+        n = int(e0.shape[0])
+        for t in (e0, polar, azimuth, x0, y0):
+            if t is not None:
+                if t.device != self.device or t.dtype != torch.float32 or not t.is_contiguous() \
+                        or t.shape != (n,):
+                    raise ValueError("initial conditions must be contiguous float32 device "
+                                     "tensors of equal length on the simulator's device")
+        b = Batch(_ptr(e0), _ptr(polar), _ptr(azimuth), _ptr(x0), _ptr(y0), n,
+                  shower_id_base & 0xFFFFFFFF)
+        o = Output()
+        for name, _ in Output._fields_:
+            if name in out and isinstance(out[name], torch.Tensor):
+                setattr(o, name, out[name].data_ptr())
+        o.hit_capacity = int(out.get("hit_capacity", 0))
+        o.node_capacity = int(out.get("node_capacity", 0))
+        st = self.lib.supa_simulate(self.ctx, C.byref(b), seed & 0xFFFFFFFFFFFFFFFF, C.byref(o))
+        out["total_hits"], out["total_nodes"], out["total_steps"] = (o.total_hits, o.total_nodes,
+                                                                     o.total_steps)
+        if st not in (0, 3):
+            self._check(st)
+        return st
+
+    def simulate(self, e0, polar, azimuth, seed: int, x0=None, y0=None,
+                 shower_id_base: int = 0, hit_capacity: int | None = None,
+                 node_capacity: int | None = None) -> dict:
+        """Simulate a batch; grows the output arrays once if they were too small."""
+        n = int(e0.shape[0])
+        hc = hit_capacity if hit_capacity is not None else max(1024, 64 * n)
+        nc = node_capacity if node_capacity is not None else max(1024, 128 * n)
+        hc = hc if self.outputs & OUT_HITS else 0
+        nc = nc if self.outputs & OUT_TREE else 0
+        out = self.allocate(n, hc, nc)
+        st = self.run(e0, polar, azimuth, seed, out, x0, y0, shower_id_base)
+        if st == 3:
+            out = self.allocate(n, max(hc, out["total_hits"]), max(nc, out["total_nodes"]))
+            st = self.run(e0, polar, azimuth, seed, out, x0, y0, shower_id_base)
+            self._check(st)
+        th, tn = out["total_hits"], out["total_nodes"]
+        for k in ("hit_x", "hit_y", "hit_e", "hit_layer", "hit_key"):
+            if k in out:
+                out[k] = out[k][:th]
+        for k in ("node_parent", "node_gen", "node_vx", "node_vy", "node_vz", "node_e", "node_key"):
+            if k in out:
+                out[k] = out[k][:tn]
+        return out
+
+    def philox(self, ctr: torch.Tensor, key: int) -> torch.Tensor:
+        """Philox4x32-10 blocks on the device: ctr int32/uint32 (n, 4) -> (n, 4)."""
+        ctr = ctr.contiguous()
+        out = torch.empty_like(ctr)
+        self._check(self.lib.supa_philox(self.ctx, ctr.data_ptr(), ctr.shape[0],
+                                         key & 0xFFFFFFFFFFFFFFFF, out.data_ptr()))
+        return out
+
+
+def validate_geometry(geom: dict, outputs: int = OUT_HITS):
+    """Host-only check of the parameters (no GPU needed); raises SupaError."""
+    lib = load()
+    g, keep = make_geometry(geom, outputs)
+    st = lib.supa_validate_geometry(C.byref(g))
+    if st != 0:
+        raise SupaError(st, lib.supa_last_error(None).decode())

@@ -1,0 +1,155 @@
+"""Element-by-element comparison of the HIP path's outputs with the oracle's.
+
+Bar (fixed by the fixed-point and counter-based design):
+  - exact: per-shower counts and energy ledgers; the set of hits and of tree
+    nodes of every shower, keyed by path id; their layers, generations,
+    parents (compared by the parent's path id) and float energies (both sides
+    round E_int * 2^-s once to float32);
+  - |d| <= 1e-5 * max(r, 1) for hit coordinates and node vertices, r the
+    reference point's distance from the beam axis (the error of a point's
+    lateral position scales with how far it has been carried sideways);
+  - images: exact integer cell sums, except cells next to a hit lying within
+    the coordinate tolerance of a cell edge, which may move one cell.
+
+Near grazing flight (direction almost parallel to the planes) a point's
+position is ill-conditioned in the direction: an angle error d(theta) moves
+it by (1 + tan^2 theta) d(theta) per unit depth, so single-precision angles
+cannot reach the bar there.  Tests of such stress geometries pass
+`max_slope` to compare coordinates only where r/z <= max_slope; counts,
+keys, energies and layers stay exact everywhere.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+COORD_RTOL = 1e-5
+
+
+def to_numpy(out: dict) -> dict:
+    r = {}
+    for k, v in out.items():
+        if hasattr(v, "detach"):
+            r[k] = v.detach().cpu().numpy()
+        else:
+            r[k] = v
+    return r
+
+
+def _f32_energy(e_int, frac_bits):
+    return (np.asarray(e_int, np.uint32).astype(np.float32) * np.float32(2.0 ** -frac_bits))
+
+
+def _coord_ok(got, ref, scale):
+    ref = np.asarray(ref, np.float64)
+    return np.abs(np.asarray(got, np.float64) - ref) <= COORD_RTOL * np.maximum(scale, 1.0)
+
+
+def check_counts(gpu: dict, ref: dict, rows=None):
+    """counts and ledger of the showers `rows` of the GPU batch (default all)."""
+    gc = gpu["counts"] if rows is None else gpu["counts"][rows]
+    gl = gpu["ledger"] if rows is None else gpu["ledger"][rows]
+    np.testing.assert_array_equal(gc, ref["counts"], err_msg="counts differ")
+    np.testing.assert_array_equal(gl.astype(np.uint64), ref["ledger"], err_msg="ledger differs")
+
+
+def check_hits(gpu: dict, ref: dict, rows=None, geom=None, max_slope=None):
+    fb = ref["frac_bits"]
+    n = ref["n"]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    base = ref["shower_id_base"]
+    order = np.argsort(ref["hit_sid"], kind="stable")
+    rs = ref["hit_sid"][order]
+    starts = np.searchsorted(rs, base + np.arange(n))
+    ends = np.searchsorted(rs, base + np.arange(n), side="right")
+    key = gpu["hit_key"].astype(np.uint64)
+    for s in range(n):
+        g = rows[s]
+        off, cnt = int(gpu["hit_offsets"][g]), int(gpu["counts"][g, 1])
+        sl = slice(off, off + cnt)
+        ri = order[starts[s]:ends[s]]
+        assert cnt == len(ri), f"shower {s}: {cnt} hits vs {len(ri)}"
+        gk = key[sl]
+        go = np.argsort(gk)
+        ro = ri[np.argsort(ref["hit_key"][ri])]
+        np.testing.assert_array_equal(gk[go], ref["hit_key"][ro], err_msg=f"shower {s}: hit keys")
+        np.testing.assert_array_equal(gpu["hit_layer"][sl][go], ref["hit_layer"][ro])
+        np.testing.assert_array_equal(gpu["hit_e"][sl][go], _f32_energy(ref["hit_e"][ro], fb),
+                                      err_msg=f"shower {s}: hit energies")
+        r = np.hypot(ref["hit_x"][ro], ref["hit_y"][ro])
+        for c in ("x", "y"):
+            ok = _coord_ok(gpu["hit_" + c][sl][go], ref["hit_" + c][ro], r)
+            if max_slope is not None:
+                z = geom["z_first"] + ref["hit_plane"][ro] * geom["dz"]
+                ok |= r / z > max_slope
+            if not ok.all():
+                bad = np.nonzero(~ok)[0][0]
+                raise AssertionError(f"shower {s}: hit {c} {gpu['hit_' + c][sl][go][bad]} vs "
+                                     f"{ref['hit_' + c][ro][bad]}")
+
+
+def check_tree(gpu: dict, ref: dict, rows=None, max_slope=None):
+    fb = ref["frac_bits"]
+    n = ref["n"]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    base = ref["shower_id_base"]
+    rstart = np.concatenate([[0], np.cumsum(ref["counts"][:, 0])])
+    assert np.all(ref["node_sid"] == np.repeat(base + np.arange(n), ref["counts"][:, 0]))
+    key = gpu["node_key"].astype(np.uint64)
+    for s in range(n):
+        g = rows[s]
+        off, cnt = int(gpu["node_offsets"][g]), int(gpu["counts"][g, 0])
+        sl = slice(off, off + cnt)
+        rsl = slice(rstart[s], rstart[s + 1])
+        gk, rk = key[sl], ref["node_key"][rsl]
+        go, ro = np.argsort(gk), np.argsort(rk)
+        np.testing.assert_array_equal(gk[go], rk[ro], err_msg=f"shower {s}: node keys")
+        gpar, rpar = gpu["node_parent"][sl], ref["node_parent"][rsl]
+        gpk = np.where(gpar >= 0, gk[np.maximum(gpar, 0)], 0)
+        rpk = np.where(rpar >= 0, rk[np.maximum(rpar, 0)], 0)
+        np.testing.assert_array_equal(gpk[go], rpk[ro], err_msg=f"shower {s}: parents")
+        np.testing.assert_array_equal(gpu["node_gen"][sl][go], ref["node_gen"][rsl][ro])
+        np.testing.assert_array_equal(gpu["node_e"][sl][go], _f32_energy(ref["node_e"][rsl][ro], fb))
+        r = np.hypot(ref["node_vx"][rsl][ro], ref["node_vy"][rsl][ro])
+        vz = np.abs(ref["node_vz"][rsl][ro])
+        skip = (r / np.maximum(vz, 1e-300) > max_slope) if max_slope is not None else False
+        for c, sc in (("vx", r), ("vy", r), ("vz", vz)):
+            ok = _coord_ok(gpu["node_" + c][sl][go], ref["node_" + c][rsl][ro], sc) | skip
+            assert ok.all(), f"shower {s}: node {c}"
+
+
+def check_images(gpu: dict, ref: dict, geom: dict, rows=None):
+    from oracle import supa_oracle
+    n = ref["n"]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    L = gpu["images"].shape[1]
+    nx, ny = int(geom["img_nx"]), int(geom["img_ny"])
+    x0, x1, y0, y1 = geom["img_x0"], geom["img_x1"], geom["img_y0"], geom["img_y1"]
+    ref_img = supa_oracle.images(ref, L, nx, ny, x0, x1, y0, y1)
+    want = ref_img.astype(np.float64).astype(np.float32) * np.float32(2.0 ** -ref["frac_bits"])
+    got = gpu["images"][rows]
+    # hits within the coordinate tolerance of a cell edge may land in a neighbour
+    sx, sy = nx / (x1 - x0), ny / (y1 - y0)
+    fx = (ref["hit_x"] - x0) * sx
+    fy = (ref["hit_y"] - y0) * sy
+    rr = np.maximum(np.hypot(ref["hit_x"], ref["hit_y"]), 1.0)
+    tx = COORD_RTOL * rr * sx * 2
+    ty = COORD_RTOL * rr * sy * 2
+    near = (np.abs(fx - np.rint(fx)) <= tx) | (np.abs(fy - np.rint(fy)) <= ty)
+    mask = np.zeros(got.shape, bool)
+    for h in np.nonzero(near & (ref["hit_layer"] >= 0))[0]:
+        s = ref["hit_sid"][h] - ref["shower_id_base"]
+        cx, cy = int(np.floor(fx[h])), int(np.floor(fy[h]))
+        mask[s, ref["hit_layer"][h], max(cy - 1, 0):cy + 2, max(cx - 1, 0):cx + 2] = True
+    diff = got != want
+    assert not (diff & ~mask).any(), f"{int((diff & ~mask).sum())} image cells differ"
+    return int((diff & mask).sum())
+
+
+def check_all(gpu: dict, ref: dict, geom: dict, images=False, tree=False, rows=None,
+              max_slope=None):
+    check_counts(gpu, ref, rows)
+    check_hits(gpu, ref, rows, geom, max_slope)
+    if tree:
+        check_tree(gpu, ref, rows, max_slope)
+    if images:
+        check_images(gpu, ref, geom, rows)

@@ -1,0 +1,66 @@
+"""Host-only checks of the C ABI library: it loads, exports every declared
+entry point, and rejects bad parameters before touching a device."""
+import math
+import os
+import re
+
+import pytest
+
+from paper_2202_05012_amd import supa
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(supa_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = supa.load()
+    names = declared_functions()
+    assert "supa_simulate" in names and "supa_init_geometry" in names
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in include/ but not exported"
+    assert lib.supa_abi_version() == 1
+
+
+def base_geom(**kw):
+    g = dict(n_planes=20, z_first=1.0, dz=1.0, e_cut=0.1, angle_mode="rayleigh", angle_a=0.1,
+             frac_lo=0.0, frac_hi=1.0, frac_bits=21, img_nx=32, img_ny=32, img_x0=-5.0,
+             img_x1=5.0, img_y0=-5.0, img_y1=5.0)
+    g.update(kw)
+    return g
+
+
+def test_validation_accepts_workload_parameters():
+    supa.validate_geometry(base_geom(), supa.OUT_HITS | supa.OUT_IMAGES | supa.OUT_TREE)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n_planes=0), dict(n_planes=64), dict(dz=0.0), dict(dz=-1.0), dict(z_first=0.0),
+    dict(e_cut=-0.1), dict(e_cut=math.nan), dict(frac_lo=0.8, frac_hi=0.2),
+    dict(frac_hi=1.5), dict(frac_bits=32), dict(angle_a=math.inf),
+    dict(p_stop=[0.7] * 20, p_split=[0.5] * 20), dict(p_split=[-0.1] * 20),
+    dict(layer_of_plane=[25] * 20), dict(layer_of_plane=[-2] * 20),
+    dict(img_nx=0), dict(img_x1=-5.0), dict(img_nx=4096), dict(img_y0=math.nan),
+])
+def test_validation_rejects(bad):
+    with pytest.raises(supa.SupaError) as e:
+        supa.validate_geometry(base_geom(**bad), supa.OUT_HITS | supa.OUT_IMAGES)
+    assert e.value.status == 1
+
+
+def test_unknown_output_bits_rejected():
+    with pytest.raises(supa.SupaError):
+        supa.validate_geometry(base_geom(), 64)
+
+
+def test_angle_mode_names():
+    with pytest.raises(KeyError):
+        supa.make_geometry(base_geom(angle_mode="gaussian"), 1)

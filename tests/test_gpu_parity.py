@@ -1,0 +1,248 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every test feeds both sides the same seeded float32 initial conditions and
+compares element by element (tests/parity.py states the bar)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import supa_oracle as O
+from paper_2202_05012_amd import supa, workloads
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+ALL = supa.OUT_HITS | supa.OUT_IMAGES | supa.OUT_TREE | supa.OUT_KEYS
+HITS_TREE = supa.OUT_HITS | supa.OUT_TREE | supa.OUT_KEYS
+
+
+def dev_t(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def run_gpu(geom, outputs, e0, pol, az, seed, x0=None, y0=None, base=0, **launch):
+    sim = supa.Simulator(geom, outputs, **launch)
+    out = sim.simulate(dev_t(e0), dev_t(pol), dev_t(az), seed, dev_t(x0), dev_t(y0), base)
+    torch.cuda.synchronize()
+    return parity.to_numpy(out), sim
+
+
+def check(geom, outputs, e0, pol, az, seed, x0=None, y0=None, base=0, max_slope=None, **launch):
+    gpu, _ = run_gpu(geom, outputs, e0, pol, az, seed, x0, y0, base, **launch)
+    ref = O.simulate(geom, e0, pol, az, seed, x0=x0, y0=y0, shower_id_base=base)
+    parity.check_all(gpu, ref, geom, images=bool(outputs & supa.OUT_IMAGES) and max_slope is None,
+                     tree=bool(outputs & supa.OUT_TREE), max_slope=max_slope)
+    return gpu, ref
+
+
+def test_device_philox_matches_oracle():
+    w = workloads.WORKLOADS["e10_normal_5planes_1k"]
+    sim = supa.Simulator(workloads.geometry(w))
+    rng = np.random.default_rng(5)
+    n = 100_000
+    ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:4] = 0
+    ctr[4:8] = 0xFFFFFFFF
+    key = 0xA4093822299F31D0
+    got = sim.philox(torch.from_numpy(ctr.view(np.int32)).cuda(), key).cpu().numpy().view(np.uint32)
+    for i in list(range(16)) + list(rng.integers(0, n, 2000)):
+        assert tuple(int(v) for v in got[i]) == O.philox4x32_10(key, ctr[i]), i
+
+
+def supav1():
+    return dict(n_planes=8, z_first=1.0, dz=1.0, p_stop=[0.0] * 7 + [1.0],
+                p_split=[1.0] * 7 + [0.0], e_cut=0.0, angle_mode="fixed", angle_a=math.pi / 24,
+                frac_lo=0.5, frac_hi=0.5, frac_bits=21, img_nx=16, img_ny=16, img_x0=-2.0,
+                img_x1=2.0, img_y0=-2.0, img_y1=2.0)
+
+
+def test_supav1_gpu():
+    n = 32
+    gpu, ref = check(supav1(), ALL, np.full(n, 65.0), np.linspace(0, 0.4, n),
+                     np.linspace(0, 6, n), seed=7)
+    assert (gpu["counts"][:, 1] == 128).all()
+    assert (gpu["hit_e"] == np.float32(65 / 128)).all()
+
+
+@pytest.mark.parametrize("name,n", [("e10_normal_5planes_1k", 1000),
+                                    ("e1to100_20planes_img32_100k", 300),
+                                    ("loge1to1000_20planes_1m", 150)])
+def test_workload_prefix_parity(name, n):
+    w = workloads.WORKLOADS[name]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w, n)
+    outputs = HITS_TREE | (supa.OUT_IMAGES if w.images else 0)
+    check(geom, outputs, e0, pol, az, w.seed)
+
+
+def test_fifty_planes_tree_and_256_images():
+    w = workloads.WORKLOADS["loge10to1000_50planes_tree_img256_1m"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w, 12)
+    check(geom, ALL, e0, pol, az, w.seed)
+
+
+def random_geometry(rng, N, wide=False):
+    ps = rng.uniform(0, 0.3, N)
+    pl = rng.uniform(0.3, 1, N) * (1 - ps)
+    mode = ["fixed", "uniform", "rayleigh"][int(rng.integers(0, 3))]
+    lo = float(rng.uniform(0, 0.5))
+    lop = rng.integers(-1, max(1, N // 2), N).astype(np.int32)
+    return dict(n_planes=N, z_first=float(rng.uniform(0.2, 2)), dz=float(rng.uniform(0.3, 2)),
+                layer_of_plane=list(lop), p_stop=list(ps), p_split=list(pl),
+                e_cut=float(rng.choice([0.0, 0.05, 0.2])), angle_mode=mode,
+                angle_a=float(rng.uniform(0.02, 0.3 if wide else 0.12)),
+                angle_b=float(rng.uniform(0.3, 0.6) if wide else rng.uniform(0.12, 0.25)),
+                frac_lo=lo, frac_hi=float(rng.uniform(lo, 1)), frac_bits=int(rng.choice([16, 21])),
+                img_nx=int(rng.integers(1, 40)), img_ny=int(rng.integers(1, 40)),
+                img_x0=-3.0, img_x1=float(rng.uniform(1, 4)), img_y0=-2.5, img_y1=2.5)
+
+
+@pytest.mark.parametrize("trial", range(6))
+def test_random_parameters(trial):
+    rng = np.random.default_rng(100 + trial)
+    N = int(rng.integers(1, 30))
+    geom = random_geometry(rng, N)
+    n = 120
+    e0 = rng.uniform(0, 20, n)
+    e0[:3] = [0.0, geom["e_cut"], 2.0 ** -22]
+    pol = rng.uniform(0, 0.9, n)
+    pol[3:6] = [1.8, 2.5, np.pi]          # primaries pointing away from +z leave at once
+    az = rng.uniform(-7, 7, n)
+    x0 = rng.uniform(-1, 1, n)
+    y0 = rng.uniform(-1, 1, n)
+    base = int(rng.integers(0, 2 ** 32 - n))
+    check(geom, ALL, e0, pol, az, seed=int(rng.integers(0, 2 ** 64, dtype=np.uint64)), x0=x0,
+          y0=y0, base=base)
+
+
+@pytest.mark.parametrize("trial", range(3))
+def test_grazing_and_backward_stress(trial):
+    """Wide angles and oblique primaries: many particles fly nearly parallel
+    to the planes or turn back.  Topology, counts, energies and keys stay
+    exact; coordinates are compared where the flight is not grazing."""
+    rng = np.random.default_rng(200 + trial)
+    N = int(rng.integers(5, 30))
+    geom = random_geometry(rng, N, wide=True)
+    n = 120
+    e0 = rng.uniform(0, 20, n)
+    pol = rng.uniform(0, 1.7, n)
+    az = rng.uniform(-7, 7, n)
+    gpu, ref = check(geom, ALL, e0, pol, az, seed=int(rng.integers(0, 2 ** 63)), max_slope=3.0)
+    assert ref["counts"][:, 5].sum() > 0            # the stress reaches backward escapes
+
+
+def test_empty_and_single():
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = workloads.geometry(w)
+    sim = supa.Simulator(geom, ALL)
+    z = torch.zeros(0, device="cuda")
+    out = sim.simulate(z, z, z, 1)
+    assert out["total_hits"] == 0 and out["counts"].shape == (0, 6)
+    check(geom, ALL, np.array([50.0]), np.array([0.1]), np.array([1.0]), seed=3)
+
+
+def test_energy_out_of_range_is_reported():
+    w = workloads.WORKLOADS["e10_normal_5planes_1k"]
+    sim = supa.Simulator(workloads.geometry(w))
+    for bad in (2048.0, -1.0, float("nan")):
+        e0 = torch.tensor([1.0, bad, 3.0], device="cuda")
+        z = torch.zeros(3, device="cuda")
+        with pytest.raises(supa.SupaError) as e:
+            sim.simulate(e0, z, z, 0)
+        assert e.value.status == 2
+
+
+def test_capacity_error_then_identical_retry():
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w, 50)
+    sim = supa.Simulator(geom, HITS_TREE)
+    small = sim.allocate(50, hit_capacity=100, node_capacity=100)
+    st = sim.run(dev_t(e0), dev_t(pol), dev_t(az), 1, small)
+    assert st == 3
+    need_h, need_n = small["total_hits"], small["total_nodes"]
+    ref = O.simulate(geom, e0, pol, az, 1)
+    assert need_h == len(ref["hit_e"]) and need_n == len(ref["node_e"])
+    full = sim.allocate(50, need_h, need_n)
+    assert sim.run(dev_t(e0), dev_t(pol), dev_t(az), 1, full) == 0
+    parity.check_all(parity.to_numpy(full), ref, geom, tree=True)
+
+
+def test_determinism_across_launch_settings():
+    """Tiny scratch forces the grow-and-rerun path; different wave counts
+    change which wave runs which shower; results must not change."""
+    w = workloads.WORKLOADS["loge1to1000_20planes_1m"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w, 200)
+    ref = O.simulate(geom, e0, pol, az, w.seed)
+    for launch in (dict(waves_per_cu=1, frontier_cap=64, hit_cap=64, node_cap=64),
+                   dict(waves_per_cu=16), dict(waves_per_cu=4, frontier_cap=8192)):
+        gpu, _ = run_gpu(geom, HITS_TREE, e0, pol, az, w.seed, **launch)
+        parity.check_all(gpu, ref, geom, tree=True)
+
+
+def test_chunked_batch_equals_whole():
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w, 90)
+    whole, _ = run_gpu(geom, ALL, e0, pol, az, 9)
+    for s in range(0, 90, 30):
+        part, _ = run_gpu(geom, ALL, e0[s:s + 30], pol[s:s + 30], az[s:s + 30], 9, base=s)
+        np.testing.assert_array_equal(part["counts"], whole["counts"][s:s + 30])
+        np.testing.assert_array_equal(part["ledger"], whole["ledger"][s:s + 30])
+        np.testing.assert_array_equal(part["images"], whole["images"][s:s + 30])
+        for i in range(30):
+            a = slice(part["hit_offsets"][i], part["hit_offsets"][i] + part["counts"][i, 1])
+            b = slice(whole["hit_offsets"][s + i], whole["hit_offsets"][s + i] + whole["counts"][s + i, 1])
+            for k in ("hit_x", "hit_y", "hit_e", "hit_key", "hit_layer"):
+                np.testing.assert_array_equal(part[k][a], whole[k][b])
+
+
+def sampled_segments(out, rows):
+    """Copy to host only the segments of the given showers (for full-size runs)."""
+    res = {"counts": out["counts"][rows].cpu().numpy(), "ledger": out["ledger"][rows].cpu().numpy()}
+    for pre, off_key, col, keys in (("hit", "hit_offsets", 1, ("hit_x", "hit_y", "hit_e", "hit_layer", "hit_key")),
+                                    ("node", "node_offsets", 0, ("node_parent", "node_gen", "node_vx",
+                                                                 "node_vy", "node_vz", "node_e", "node_key"))):
+        if off_key not in out:
+            continue
+        offs = out[off_key][rows].cpu().numpy()
+        cnts = res["counts"][:, col]
+        idx = np.concatenate([np.arange(o, o + c) for o, c in zip(offs, cnts)]) if len(rows) else np.zeros(0, int)
+        it = torch.from_numpy(idx).cuda()
+        for k in keys:
+            if k in out:
+                res[k] = out[k][it].cpu().numpy()
+        res[off_key] = np.concatenate([[0], np.cumsum(cnts)[:-1]])
+    if "images" in out:
+        res["images"] = out["images"][rows].cpu().numpy()
+    return res
+
+
+@pytest.mark.slow
+def test_full_size_100k_sampled_parity():
+    """The 100,000-shower, 20-plane, 32x32-image workload at full size in the
+    launch configuration the benchmark times; oracle on sampled blocks."""
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w)
+    sim = supa.Simulator(geom, ALL)
+    out = sim.simulate(dev_t(e0), dev_t(pol), dev_t(az), w.seed)
+    torch.cuda.synchronize()
+    counts = out["counts"].cpu().numpy()
+    ledger = out["ledger"].cpu().numpy().astype(np.uint64)
+    assert (ledger[:, 1] + ledger[:, 2] + ledger[:, 3] == ledger[:, 0]).all()
+    assert (counts[:, 0] == 1 + 2 * counts[:, 3]).all()
+    assert out["total_hits"] == counts[:, 1].sum()
+    offs = out["hit_offsets"].cpu().numpy()
+    o = np.argsort(offs)
+    assert offs[o[0]] == 0 and (offs[o][1:] == (offs[o] + counts[o, 1])[:-1]).all()
+    rng = np.random.default_rng(0)
+    for start in list(rng.integers(0, w.n - 64, 3)) + [w.n - 64]:
+        rows = np.arange(start, start + 64)
+        gpu = sampled_segments(out, rows)
+        ref = O.simulate(geom, e0[rows], pol[rows], az[rows], w.seed, shower_id_base=int(start))
+        parity.check_all(gpu, ref, geom, images=True, tree=True)
