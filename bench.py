@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="e1to100_20planes_img32_100k")
     ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--lds-cap", type=int, default=0,
+                    help="frontier entries per buffer kept in LDS (0 = library default)")
+    ap.add_argument("--outputs", default="",
+                    help="override the workload's outputs: comma list of hits,images,tree")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -88,10 +92,17 @@ def main():
     w = workloads.WORKLOADS[args.workload]
     geom = workloads.geometry(w)
     outputs = supa.OUT_HITS | (supa.OUT_IMAGES if w.images else 0) | (supa.OUT_TREE if w.tree else 0)
+    if args.outputs:
+        names = {"hits": supa.OUT_HITS, "images": supa.OUT_IMAGES, "tree": supa.OUT_TREE}
+        outputs = 0
+        for t in args.outputs.split(","):
+            if t and t != "none":
+                outputs |= names[t]
     dev = torch.device("cuda", 0)
     e0, pol, az = workloads.initial_conditions(w)
     te0, tpol, taz = (torch.from_numpy(a).to(dev) for a in (e0, pol, az))
-    sim = supa.Simulator(geom, outputs, waves_per_cu=args.waves_per_cu)
+    sim = supa.Simulator(geom, outputs, waves_per_cu=args.waves_per_cu,
+                         frontier_cap=args.lds_cap)
 
     # size the outputs from one untimed run (also grows the per-wave scratch)
     probe = sim.allocate(w.n, 0, 0)
@@ -130,9 +141,11 @@ def main():
     k_ms = float(np.mean(kernel_ms))
     alg_ops = OPS_PER_ARRIVAL * steps_total + OPS_PER_DRAW * draws + OPS_PER_SPLIT * splits_total
     alg_bytes = BYTES_PER_HIT * hits_total + BYTES_PER_SHOWER_IO * w.n
-    if w.images:
+    if outputs & supa.OUT_IMAGES:
         alg_bytes += w.n * geom["n_planes"] * geom["img_nx"] * geom["img_ny"] * 4
-    if w.tree:
+    if not outputs & supa.OUT_HITS:
+        alg_bytes -= BYTES_PER_HIT * hits_total
+    if outputs & supa.OUT_TREE:
         alg_bytes += 24 * int(counts[:, 0].sum()) + 8 * w.n
     alu = alg_ops / (k_ms / 1e3) / 1e12
     hbm = alg_bytes / (k_ms / 1e3) / 1e9
@@ -162,8 +175,10 @@ def main():
         "dtype": "f32+u32",
         "data": "synthetic",
         "config": {"workload": w.name, "showers": w.n, "planes": w.n_planes,
-                   "outputs": "hits" + ("+images%dx%d" % w.images[:2] if w.images else "")
-                              + ("+tree" if w.tree else "")},
+                   "outputs": "+".join(n for n, b in (("hits", supa.OUT_HITS),
+                                                      ("images", supa.OUT_IMAGES),
+                                                      ("tree", supa.OUT_TREE)) if outputs & b)
+                              or "counts"},
         "particle_steps_per_s": round(steps_total / (ms_per_step / 1e3), 1),
         "particle_steps": steps_total,
         "hits": hits_total,

@@ -118,8 +118,11 @@ typedef struct supa_batch {
  * Layout is segmented: the hits of shower i occupy the contiguous range
  * [hit_offsets[i], hit_offsets[i] + counts[6*i+1]) of every hit array; the
  * segments of a batch are disjoint and tile [0, total_hits) with no gap, in an
- * unspecified order of showers.  Within a segment hits are ordered by plane and
- * then by the order in which their particles were created.  Nodes likewise.
+ * unspecified order of showers.  Within a segment hits are grouped by plane in
+ * increasing order; their order within a plane is unspecified (the path id,
+ * SUPA_OUT_KEYS, is a canonical key).  Nodes: same segment rule; node_parent
+ * indexes the shower's own segment; their order is unspecified apart from
+ * the primary, which comes first.
  */
 typedef struct supa_output {
     /* hit point clouds (SUPA_OUT_HITS); hit_key also needs SUPA_OUT_KEYS */
@@ -184,11 +187,15 @@ supa_status supa_simulate(supa_ctx *ctx, const supa_batch *b, uint64_t seed,
                           supa_output *out);
 
 /*
- * Launch settings of the propagation kernel.  waves_per_cu: resident waves
- * per compute unit (1..16); 0 keeps the current value.  frontier_cap,
- * hit_cap, node_cap: per-wave scratch capacities in particles, hits, nodes
- * (0 keeps the current value; they also grow by themselves when a shower needs
- * more).  Affects speed only, never results.
+ * Launch settings of the propagation kernel (affect speed only, never
+ * results; 0 keeps the current value of a setting).
+ *   waves_per_cu  waves launched per compute unit, 1..32 (each wave keeps a
+ *                 few showers in flight, taken from the work queue);
+ *   frontier_cap  pending particles per wave kept in LDS: 128, 256, 512 or
+ *                 1024 (more spill to a per-wave global area);
+ *   hit_cap, node_cap  per-shower journal capacities in hits / nodes.
+ * The spill area and the journals grow by themselves (and the batch is rerun)
+ * when a shower needs more.
  */
 supa_status supa_set_launch(supa_ctx *ctx, int32_t waves_per_cu, int32_t frontier_cap,
                             int32_t hit_cap, int32_t node_cap);

@@ -22,9 +22,11 @@ hipError_t launch_zero_counters(unsigned long long *ctr, hipStream_t s);
 hipError_t launch_propagate(const Params &P, int blocks, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t s);
-int waves_per_block();
-int tile_words();
+size_t propagate_lds_bytes(int pool_cap, int tile_words);
 }  // namespace supa
+
+static constexpr int kTileWords = 1024;       // LDS image tile: 4 KB per wave
+static constexpr int kMaxImageWidth = 1024;
 
 struct supa_ctx {
     int device = 0;
@@ -39,13 +41,17 @@ struct supa_ctx {
     uint64_t f_w = 0;
     // device copies
     int32_t *d_layer = nullptr;
+    int32_t *d_layer_plane_start = nullptr, *d_layer_planes = nullptr;
     uint64_t *d_c1 = nullptr, *d_c2 = nullptr;
     unsigned long long *d_ctr = nullptr;
     unsigned long long *h_ctr = nullptr;   // pinned
+    supa::Cold *d_cold = nullptr;          // per-call inputs/outputs block (device)
+    supa::Cold *h_cold = nullptr;          // its pinned host staging copy
     // per-wave scratch
     int n_cu = 0;
     int waves_per_cu = 8;
-    int cap_f = 1024, cap_h = 4096, cap_n = 8192;
+    int pool_cap = 256;                  // particle-pool entries kept in LDS
+    int spill_cap = 1024, cap_h = 4096, cap_n = 8192;   // per-wave spill / journals
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
     supa::Params layout{};               // scratch pointers only
@@ -112,8 +118,8 @@ static supa_status validate(const supa_geometry *g, std::string &why) {
     }
     if (g->outputs & ~15u) { why = "unknown output bits"; return SUPA_ERR_INVALID_ARG; }
     if (g->outputs & SUPA_OUT_IMAGES) {
-        if (g->img_nx < 1 || g->img_ny < 1 || g->img_nx > supa::tile_words()) {
-            why = "image grid must have 1 <= nx <= 2048 and ny >= 1";
+        if (g->img_nx < 1 || g->img_ny < 1 || g->img_nx > kMaxImageWidth) {
+            why = "image grid must have 1 <= nx <= 1024 and ny >= 1";
             return SUPA_ERR_INVALID_ARG;
         }
         if (!is_fin(g->img_x0) || !is_fin(g->img_x1) || !is_fin(g->img_y0) || !is_fin(g->img_y1) ||
@@ -138,14 +144,15 @@ static void free_scratch(supa_ctx *c) {
     c->scratch_bytes = 0;
 }
 
-// Carves the per-wave scratch out of one allocation (256-byte aligned arrays).
-static supa_status ensure_scratch(supa_ctx *c, bool hits, bool tree) {
+// Carves the per-wave scratch out of one allocation.
+static supa_status ensure_scratch(supa_ctx *c, bool tree) {
     const int64_t waves = (int64_t)c->n_cu * c->waves_per_cu;
-    const int64_t F = waves * 2 * c->cap_f;
-    const int64_t H = hits ? waves * c->cap_h : 0;
-    const int64_t Nn = tree ? waves * c->cap_n : 0;
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t need = 8 * al(F * 4) + 6 * al(H * 4) + 8 * al(Nn * 4);
+    const size_t spill_b = al((size_t)waves * supa::POOL_FIELDS * c->spill_cap * 4);
+    const size_t jh_b = al((size_t)waves * supa::SLOTS * supa::JH_COUNT * c->cap_h * 4);
+    const size_t hidx_b = al((size_t)waves * c->cap_h * 4);
+    const size_t jn_b = tree ? al((size_t)waves * supa::SLOTS * supa::JN_COUNT * c->cap_n * 4) : 0;
+    const size_t need = spill_b + jh_b + hidx_b + jn_b;
     if (need > c->scratch_bytes) {
         free_scratch(c);
         void *p = nullptr;
@@ -157,33 +164,14 @@ static supa_status ensure_scratch(supa_ctx *c, bool hits, bool tree) {
         c->scratch_bytes = need;
     }
     char *p = (char *)c->scratch;
-    auto take = [&](size_t b) { char *q = p; p += al(b); return (void *)q; };
     supa::Params &L = c->layout;
-    L.cap_f = c->cap_f;
+    L.spill_cap = c->spill_cap;
     L.cap_h = c->cap_h;
     L.cap_n = c->cap_n;
-    L.fx = (float *)take(F * 4);
-    L.fy = (float *)take(F * 4);
-    L.ftx = (float *)take(F * 4);
-    L.fty = (float *)take(F * 4);
-    L.fe = (uint32_t *)take(F * 4);
-    L.fplo = (uint32_t *)take(F * 4);
-    L.fphi = (uint32_t *)take(F * 4);
-    L.fnode = (int32_t *)take(F * 4);
-    L.jhx = (float *)take(H * 4);
-    L.jhy = (float *)take(H * 4);
-    L.jhe = (uint32_t *)take(H * 4);
-    L.jhl = (int32_t *)take(H * 4);
-    L.jhplo = (uint32_t *)take(H * 4);
-    L.jhphi = (uint32_t *)take(H * 4);
-    L.jnp = (int32_t *)take(Nn * 4);
-    L.jng = (int32_t *)take(Nn * 4);
-    L.jnx = (float *)take(Nn * 4);
-    L.jny = (float *)take(Nn * 4);
-    L.jnz = (float *)take(Nn * 4);
-    L.jne = (uint32_t *)take(Nn * 4);
-    L.jnplo = (uint32_t *)take(Nn * 4);
-    L.jnphi = (uint32_t *)take(Nn * 4);
+    L.spill = (uint32_t *)p;
+    L.jh = (uint32_t *)(p + spill_b);
+    L.hidx = (uint32_t *)(p + spill_b + jh_b);
+    L.jn = tree ? (uint32_t *)(p + spill_b + jh_b + hidx_b) : nullptr;
     return SUPA_OK;
 }
 
@@ -211,6 +199,14 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
         max_layer = std::max(max_layer, c->layer[k]);
     }
     c->n_layers = max_layer + 1;
+    // planes of each layer, as a CSR list (layers need not be contiguous)
+    std::vector<int32_t> lps(c->n_layers + 1, 0), lp;
+    for (int l = 0; l < c->n_layers; ++l) {
+        for (int k = 0; k < N; ++k)
+            if (c->layer[k] == l) lp.push_back(k);
+        lps[l + 1] = (int32_t)lp.size();
+    }
+    if (lp.empty()) lp.push_back(0);
     c->g.layer_of_plane = nullptr;
     c->g.p_stop = nullptr;
     c->g.p_split = nullptr;
@@ -235,9 +231,17 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
     }
     bool ok = hipMalloc(&c->d_layer, N * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&c->d_c1, N * sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(&c->d_layer_plane_start, lps.size() * sizeof(int32_t)) == hipSuccess &&
+              hipMalloc(&c->d_layer_planes, lp.size() * sizeof(int32_t)) == hipSuccess &&
+              hipMemcpy(c->d_layer_plane_start, lps.data(), lps.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->d_layer_planes, lp.data(), lp.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice) == hipSuccess &&
               hipMalloc(&c->d_c2, N * sizeof(uint64_t)) == hipSuccess &&
               hipMalloc(&c->d_ctr, supa::CTR_COUNT * sizeof(unsigned long long)) == hipSuccess &&
               hipHostMalloc(&c->h_ctr, supa::CTR_COUNT * sizeof(unsigned long long), 0) == hipSuccess &&
+              hipMalloc(&c->d_cold, sizeof(supa::Cold)) == hipSuccess &&
+              hipHostMalloc(&c->h_cold, sizeof(supa::Cold), 0) == hipSuccess &&
               hipMemcpy(c->d_layer, c->layer.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->d_c1, c1.data(), N * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->d_c2, c2.data(), N * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess;
@@ -257,10 +261,14 @@ extern "C" supa_status supa_destroy(supa_ctx *c) {
     if (c->stream || true) (void)hipStreamSynchronize(c->stream);
     free_scratch(c);
     if (c->d_layer) (void)hipFree(c->d_layer);
+    if (c->d_layer_plane_start) (void)hipFree(c->d_layer_plane_start);
+    if (c->d_layer_planes) (void)hipFree(c->d_layer_planes);
     if (c->d_c1) (void)hipFree(c->d_c1);
     if (c->d_c2) (void)hipFree(c->d_c2);
     if (c->d_ctr) (void)hipFree(c->d_ctr);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
+    if (c->d_cold) (void)hipFree(c->d_cold);
+    if (c->h_cold) (void)hipHostFree(c->h_cold);
     for (auto &ev : c->ev)
         if (ev) (void)hipEventDestroy(ev);
     delete c;
@@ -270,10 +278,12 @@ extern "C" supa_status supa_destroy(supa_ctx *c) {
 extern "C" supa_status supa_set_launch(supa_ctx *c, int32_t waves_per_cu, int32_t frontier_cap,
                                        int32_t hit_cap, int32_t node_cap) {
     if (!c) return SUPA_ERR_STATE;
-    if (waves_per_cu < 0 || waves_per_cu > 16 || frontier_cap < 0 || hit_cap < 0 || node_cap < 0)
+    const bool pow2 = frontier_cap == 0 || (frontier_cap & (frontier_cap - 1)) == 0;
+    if (waves_per_cu < 0 || waves_per_cu > 32 || frontier_cap < 0 || frontier_cap > 1024 ||
+        (frontier_cap != 0 && frontier_cap < 128) || !pow2 || hit_cap < 0 || node_cap < 0)
         return fail(c, SUPA_ERR_INVALID_ARG, "launch settings out of range");
     if (waves_per_cu) c->waves_per_cu = waves_per_cu;
-    if (frontier_cap) c->cap_f = frontier_cap;
+    if (frontier_cap) c->pool_cap = frontier_cap;
     if (hit_cap) c->cap_h = hit_cap;
     if (node_cap) c->cap_n = node_cap;
     return SUPA_OK;
@@ -333,15 +343,13 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
     if (n == 0) return SUPA_OK;
 
     HIP_TRY(c, hipSetDevice(c->device));
-    const bool hits = (outs & (SUPA_OUT_HITS | SUPA_OUT_IMAGES)) != 0;
     const bool tree = (outs & SUPA_OUT_TREE) != 0;
 
     for (int attempt = 0; attempt < 8; ++attempt) {
-        supa_status s = ensure_scratch(c, hits, tree);
+        supa_status s = ensure_scratch(c, tree);
         if (s != SUPA_OK) return s;
         supa::Params P = c->layout;
         P.n_planes = c->g.n_planes;
-        P.n_layers = c->n_layers;
         P.z_first = (float)c->g.z_first;
         P.dz = (float)c->g.dz;
         P.layer = c->d_layer;
@@ -357,45 +365,56 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         P.e_unscale = std::ldexp(1.0f, -c->g.energy_frac_bits);
         P.seed_lo = (uint32_t)seed;
         P.seed_hi = (uint32_t)(seed >> 32);
-        P.e0 = b->e0;
-        P.polar = b->polar;
-        P.azimuth = b->azimuth;
-        P.x0 = b->x0;
-        P.y0 = b->y0;
         P.n = (int32_t)n;
         P.sid_base = b->shower_id_base;
-        P.order = nullptr;
         P.outputs = outs;
-        P.hit_offsets = out->hit_offsets;
-        P.hit_x = out->hit_x;
-        P.hit_y = out->hit_y;
-        P.hit_e = out->hit_e;
-        P.hit_layer = out->hit_layer;
-        P.hit_key = (outs & SUPA_OUT_KEYS) ? out->hit_key : nullptr;
-        P.hit_capacity = (outs & SUPA_OUT_HITS) ? out->hit_capacity : 0;
-        P.images = out->images;
-        P.img_nx = c->g.img_nx;
-        P.img_ny = c->g.img_ny;
-        P.img_x0 = (float)c->g.img_x0;
-        P.img_y0 = (float)c->g.img_y0;
-        P.img_sx = (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0));
-        P.img_sy = (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0));
-        P.img_rows = (outs & SUPA_OUT_IMAGES) ? std::max(1, std::min(c->g.img_ny, supa::tile_words() / c->g.img_nx)) : 1;
-        P.node_offsets = out->node_offsets;
-        P.node_parent = out->node_parent;
-        P.node_gen = out->node_gen;
-        P.node_vx = out->node_vx;
-        P.node_vy = out->node_vy;
-        P.node_vz = out->node_vz;
-        P.node_e = out->node_e;
-        P.node_key = (outs & SUPA_OUT_KEYS) ? out->node_key : nullptr;
-        P.node_capacity = tree ? out->node_capacity : 0;
-        P.ledger = out->ledger;
-        P.counts = out->counts;
+        P.keys = (outs & SUPA_OUT_KEYS) != 0;
+        P.pool_cap = c->pool_cap;
+        P.tile_words = (outs & SUPA_OUT_IMAGES) ? kTileWords : 0;
         P.ctr = c->d_ctr;
+        P.cold = c->d_cold;
 
-        const int wpb = supa::waves_per_block();
-        const int blocks = std::max(1, (c->n_cu * c->waves_per_cu) / wpb);
+        supa::Cold &K = *c->h_cold;
+        std::memset(&K, 0, sizeof(K));
+        K.e0 = b->e0;
+        K.polar = b->polar;
+        K.azimuth = b->azimuth;
+        K.x0 = b->x0;
+        K.y0 = b->y0;
+        K.order = nullptr;
+        K.hit_offsets = out->hit_offsets;
+        K.hit_x = out->hit_x;
+        K.hit_y = out->hit_y;
+        K.hit_e = out->hit_e;
+        K.hit_layer = out->hit_layer;
+        K.hit_key = (outs & SUPA_OUT_KEYS) ? out->hit_key : nullptr;
+        K.hit_capacity = (outs & SUPA_OUT_HITS) ? out->hit_capacity : 0;
+        K.images = out->images;
+        K.img_nx = c->g.img_nx;
+        K.img_ny = c->g.img_ny;
+        K.img_x0 = (float)c->g.img_x0;
+        K.img_y0 = (float)c->g.img_y0;
+        K.img_sx = (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0));
+        K.img_sy = (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0));
+        K.img_rows = (outs & SUPA_OUT_IMAGES) ? std::max(1, std::min(c->g.img_ny, kTileWords / c->g.img_nx)) : 1;
+        K.n_layers = c->n_layers;
+        K.layer_plane_start = c->d_layer_plane_start;
+        K.layer_planes = c->d_layer_planes;
+        K.node_offsets = out->node_offsets;
+        K.node_parent = out->node_parent;
+        K.node_gen = out->node_gen;
+        K.node_vx = out->node_vx;
+        K.node_vy = out->node_vy;
+        K.node_vz = out->node_vz;
+        K.node_e = out->node_e;
+        K.node_key = (outs & SUPA_OUT_KEYS) ? out->node_key : nullptr;
+        K.node_capacity = tree ? out->node_capacity : 0;
+        K.ledger = out->ledger;
+        K.counts = out->counts;
+
+        const int blocks = std::max(1, c->n_cu * c->waves_per_cu);
+        HIP_TRY(c, hipMemcpyAsync(c->d_cold, c->h_cold, sizeof(supa::Cold), hipMemcpyHostToDevice,
+                                  c->stream));
         HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
         HIP_TRY(c, supa::launch_zero_counters(c->d_ctr, c->stream));
         HIP_TRY(c, supa::launch_propagate(P, blocks, c->stream));
@@ -412,15 +431,19 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         c->timing[2] = t02;
 
         const unsigned long long flags = c->h_ctr[supa::CTR_FLAGS];
+        if (flags & supa::FLAG_INTERNAL) {
+            c->broken = true;
+            return fail(c, SUPA_ERR_DEVICE, "internal particle accounting error in the propagation kernel");
+        }
         if (flags & supa::FLAG_RANGE)
             return fail(c, SUPA_ERR_RANGE, "an initial energy is negative, NaN or too large for the fixed-point format");
         if (flags & supa::FLAG_OVERFLOW) {
             // grow the per-wave scratch to what the largest shower needed, rerun
-            const int64_t nf = (int64_t)c->h_ctr[supa::CTR_NEED_F];
+            const int64_t nf = std::max<int64_t>(0, (int64_t)c->h_ctr[supa::CTR_NEED_F] - c->pool_cap);
             const int64_t nh = (int64_t)c->h_ctr[supa::CTR_NEED_H];
             const int64_t nn = (int64_t)c->h_ctr[supa::CTR_NEED_N];
             const int64_t cap_max = (int64_t)1 << 30;
-            c->cap_f = (int)std::min(cap_max, std::max<int64_t>(c->cap_f, round_up_pow2(nf + 1)));
+            c->spill_cap = (int)std::min(cap_max, std::max<int64_t>(c->spill_cap, round_up_pow2(nf + 1)));
             c->cap_h = (int)std::min(cap_max, std::max<int64_t>(c->cap_h, round_up_pow2(nh + 1)));
             c->cap_n = (int)std::min(cap_max, std::max<int64_t>(c->cap_n, round_up_pow2(nn + 2)));
             continue;

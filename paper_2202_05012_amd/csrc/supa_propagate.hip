@@ -1,27 +1,34 @@
 // supa_propagate.hip -- the SUPA propagation kernel for gfx950.
 //
-// One wave (64 lanes) owns one shower at a time and pulls the next one from a
-// device work queue, so a single launch of a few waves per compute unit runs a
-// whole batch however uneven its showers are.  Within a shower the wave walks
-// the planes in order (section "Propagation Model": at each slice every live
-// particle stops, splits or passes, Algorithm 1), 64 particles per step:
-//   free flight to plane k  ->  threshold test  ->  one Philox block  ->
-//   three-way choice  ->  split kinematics  ->  ballot/prefix compaction of
-//   the next plane's particles, of the new tree nodes and of the hits.
-// Compaction is a wave ballot plus a popcount of the lanes below, so the
-// order of particles, nodes and hits is the creation order a sequential
-// implementation produces, with no atomics.  Particles live in a per-wave
-// structure-of-arrays double buffer; hits and nodes are journaled per wave and
-// copied once per shower into the caller's arrays at a segment reserved with a
-// single atomic.  Per-layer images are binned from the hit journal into an LDS
-// tile (integer sums, order independent) and written once.
+// Each wave (64 lanes, one workgroup) keeps up to SLOTS showers in flight and
+// pulls new ones from a device work queue whenever its work runs low, so one
+// launch of a few waves per compute unit runs a whole batch however uneven
+// its showers are.  A shower is the tree of Algorithm 1 (section "Propagation
+// Model": at each slice every live particle stops, splits or passes); its
+// pending particles, tagged with their shower slot and next plane, sit in a
+// per-wave pool in LDS (a stack: depth-first, so it stays small; its oldest
+// entries spill to global memory only for very large showers).  Work is done
+// in two event phases so that every lane of a phase does the same thing:
+//   A  take 64 particles from the pool: free flight to their plane, threshold
+//      test; particles below threshold deposit (a hit), the others go to a
+//      draw queue;
+//   B  take 64 particles from the draw queue: one Philox block each, the
+//      three-way choice, split kinematics; daughters go back to the pool.
+// Hits and tree nodes are appended to per-shower journals (positions from a
+// wave ballot and a count of the set lanes below, per shower slot).  When a
+// shower's last particle is done, the wave sorts its hits by plane (counting
+// sort in LDS), copies them into the caller's arrays at a segment reserved
+// with one atomic, bins the per-layer images in an LDS tile (integer sums, so
+// the order of the atomics does not matter) and writes the ledger and counts.
+// Results depend only on (seed, shower id, path id): the random stream is
+// keyed by the particle, not by the lane or wave that happens to process it.
 #include "supa_device.hpp"
 
 namespace supa {
 
 constexpr int WAVE = 64;
-constexpr int WAVES_PER_BLOCK = 4;
-constexpr int TILE_WORDS = 2048;          // 8 KB LDS image tile per wave
+// Read a field of the per-call Cold block at its point of use.
+#define COLD(field) (((const volatile Cold *)P.cold)->field)
 
 struct Daughters {
     float txa, tya, txb, tyb;
@@ -49,37 +56,38 @@ __device__ __forceinline__ Daughters split_particle(const Params &P, float tx, f
     } else if (P.angle_mode == 1) {
         theta = fmaf(P.angle_b - P.angle_a, ((float)w.z + 0.5f) * 0x1p-32f, P.angle_a);
     } else {
-        // Rayleigh(sigma): sigma*sqrt(-2 ln u); ln u through log1p(-(1-u)) when
-        // u >= 1/2 so that the argument is exact in single precision
-        float lnu;
-        if (w.z < 0x80000000u)
-            lnu = logf(((float)w.z + 0.5f) * 0x1p-32f);
-        else
-            lnu = log1pf(-(((float)(~w.z) + 0.5f) * 0x1p-32f));
-        theta = P.angle_a * sqrtf(-2.0f * lnu);
+        // Rayleigh(sigma): sigma * sqrt(-2 ln u)
+        theta = P.angle_a * __builtin_amdgcn_sqrtf(2.0f * neg_log_unit(w.z));
     }
     // omega = 2 pi u(w3), taken as pi*(signed w3 + 1/2)/2^31 (same angle mod 2 pi)
     float so, co;
-    sincospif(((float)(int32_t)w.w + 0.5f) * 0x1p-31f, &so, &co);
+    sincos_f32(((float)(int32_t)w.w + 0.5f) * 1.46291808e-09f, &so, &co);   // pi / 2^31
 
     // unit direction from the slopes
-    const float dz = 1.0f / sqrtf(1.0f + fmaf(tx, tx, ty * ty));
+    const float dz = __builtin_amdgcn_rsqf(1.0f + fmaf(tx, tx, ty * ty));
     const float dx = tx * dz, dy = ty * dz;
-    const float c = 1.0f / (1.0f + dz);
+    const float c = __builtin_amdgcn_rcpf(1.0f + dz);
     const float e1x = fmaf(-dx * dx, c, 1.0f), e1y = -dx * dy * c, e1z = -dx;
     const float e2x = e1y, e2y = fmaf(-dy * dy, c, 1.0f), e2z = -dy;
     const float nx = co * e1x + so * e2x;
     const float ny = co * e1y + so * e2y;
     const float nz = co * e1z + so * e2z;
 
+    // the two deflections are at most theta; the reduction to [-pi/4, pi/4]
+    // is skipped when every splitting lane of the wave is already inside
     float sa, ca, sb, cb;
-    sincosf(theta * g, &sa, &ca);
-    sincosf(theta * f, &sb, &cb);
+    if (__ballot(theta > 0.785398163f) == 0ull) {
+        sincos_poly(theta * g, &sa, &ca);
+        sincos_poly(theta * f, &sb, &cb);
+    } else {
+        sincos_f32(theta * g, &sa, &ca);
+        sincos_f32(theta * f, &sb, &cb);
+    }
     const float ax = ca * dx + sa * nx, ay = ca * dy + sa * ny, az = ca * dz + sa * nz;
     const float bx = cb * dx - sb * nx, by = cb * dy - sb * ny, bz = cb * dz - sb * nz;
     D.fwd_a = az > 0.0f;
     D.fwd_b = bz > 0.0f;
-    const float ia = 1.0f / az, ib = 1.0f / bz;
+    const float ia = __builtin_amdgcn_rcpf(az), ib = __builtin_amdgcn_rcpf(bz);
     D.txa = ax * ia;
     D.tya = ay * ia;
     D.txb = bx * ib;
@@ -87,360 +95,568 @@ __device__ __forceinline__ Daughters split_particle(const Params &P, float tx, f
     return D;
 }
 
-__global__ void __launch_bounds__(WAVE *WAVES_PER_BLOCK) supa_propagate(Params P) {
-    __shared__ uint32_t lds_tile[WAVES_PER_BLOCK][TILE_WORDS];
+
+struct Entry {
+    float x, y, tx, ty;
+    uint32_t e, lo, hi;
+    int32_t node;
+    uint32_t ks;        // plane | slot << 8
+};
+
+__device__ __forceinline__ Entry load_entry(const uint32_t *base, int64_t fstride, int64_t j) {
+    Entry p;
+    p.x = __uint_as_float(base[PF_X * fstride + j]);
+    p.y = __uint_as_float(base[PF_Y * fstride + j]);
+    p.tx = __uint_as_float(base[PF_TX * fstride + j]);
+    p.ty = __uint_as_float(base[PF_TY * fstride + j]);
+    p.e = base[PF_E * fstride + j];
+    p.lo = base[PF_LO * fstride + j];
+    p.hi = base[PF_HI * fstride + j];
+    p.node = (int32_t)base[PF_NODE * fstride + j];
+    p.ks = base[PF_KS * fstride + j];
+    return p;
+}
+
+__device__ __forceinline__ void store_entry(uint32_t *base, int64_t fstride, int64_t j, const Entry &p) {
+    base[PF_X * fstride + j] = __float_as_uint(p.x);
+    base[PF_Y * fstride + j] = __float_as_uint(p.y);
+    base[PF_TX * fstride + j] = __float_as_uint(p.tx);
+    base[PF_TY * fstride + j] = __float_as_uint(p.ty);
+    base[PF_E * fstride + j] = p.e;
+    base[PF_LO * fstride + j] = p.lo;
+    base[PF_HI * fstride + j] = p.hi;
+    base[PF_NODE * fstride + j] = (uint32_t)p.node;
+    base[PF_KS * fstride + j] = p.ks;
+}
+
+// Per-shower state, one shower slot per lane 0..SLOTS-1 of a few registers.
+struct Slots {
+    int i;           // batch index of the shower, -1 when the slot is free
+    uint32_t sid;    // global shower id
+    uint32_t e0;     // fixed-point initial energy
+    int live;        // particles of the shower in the pool or the draw queue
+    int hits, nodes, passes, escaped, backward;
+    uint32_t e_esc;  // escaped energy (fits: energies of a shower sum to e0)
+};
+
+__device__ __forceinline__ int slot_get(int v, int s) { return __builtin_amdgcn_readlane(v, s); }
+
+// Calls f(s, m) once for every distinct slot s among the lanes of mask, with
+// m the lanes of mask whose slot is s (mask is wave-uniform).
+template <class F>
+__device__ __forceinline__ void for_each_slot(uint64_t mask, int slot, F f) {
+    while (mask) {
+        const int l0 = __builtin_ctzll(mask);
+        const int s0 = __builtin_amdgcn_readlane(slot, l0);
+        const uint64_t m = mask & wave_ballot(slot == s0);
+        f(s0, m);
+        mask &= ~m;
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v) {
+    int incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if ((int)lane_id() >= off) incl += t;
+    }
+    return incl - v;
+}
+
+// LDS words of one wave: pool + draw queue + per-plane tables + histogram + tile
+__host__ __device__ constexpr int lds_words(int pool_cap, int tile_words) {
+    return POOL_FIELDS * pool_cap + POOL_FIELDS * QCAP + 2 * 2 * 64 + 64 + 64 + tile_words;
+}
+
+// Keeps a wave-uniform value in scalar registers but hides it from loop-
+// invariant code motion, so that quantities derived from it are recomputed
+// where they are used instead of being held (and spilled) through the loop.
+__device__ __forceinline__ uint32_t opaque_u32(uint32_t v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+template <bool TREE, int PC>
+__global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
+    extern __shared__ uint32_t lds[];
     const uint32_t lane = lane_id();
-    const int wib = threadIdx.x / WAVE;
-    const int64_t wave = (int64_t)blockIdx.x * WAVES_PER_BLOCK + wib;
-    uint32_t *tile = lds_tile[wib];
-
-    const int64_t cap_f = P.cap_f, cap_h = P.cap_h, cap_n = P.cap_n;
-    float *const fx = P.fx + wave * 2 * cap_f;
-    float *const fy = P.fy + wave * 2 * cap_f;
-    float *const ftx = P.ftx + wave * 2 * cap_f;
-    float *const fty = P.fty + wave * 2 * cap_f;
-    uint32_t *const fe = P.fe + wave * 2 * cap_f;
-    uint32_t *const fplo = P.fplo + wave * 2 * cap_f;
-    uint32_t *const fphi = P.fphi + wave * 2 * cap_f;
-    int32_t *const fnode = P.fnode + wave * 2 * cap_f;
-
-    const bool want_hits = (P.outputs & 3u) != 0;   // hit clouds or images
-    const bool want_tree = (P.outputs & 4u) != 0;
-    float *const jhx = want_hits ? P.jhx + wave * cap_h : nullptr;
-    float *const jhy = want_hits ? P.jhy + wave * cap_h : nullptr;
-    uint32_t *const jhe = want_hits ? P.jhe + wave * cap_h : nullptr;
-    int32_t *const jhl = want_hits ? P.jhl + wave * cap_h : nullptr;
-    uint32_t *const jhplo = want_hits ? P.jhplo + wave * cap_h : nullptr;
-    uint32_t *const jhphi = want_hits ? P.jhphi + wave * cap_h : nullptr;
-    int32_t *const jnp = want_tree ? P.jnp + wave * cap_n : nullptr;
-    int32_t *const jng = want_tree ? P.jng + wave * cap_n : nullptr;
-    float *const jnx = want_tree ? P.jnx + wave * cap_n : nullptr;
-    float *const jny = want_tree ? P.jny + wave * cap_n : nullptr;
-    float *const jnz = want_tree ? P.jnz + wave * cap_n : nullptr;
-    uint32_t *const jne = want_tree ? P.jne + wave * cap_n : nullptr;
-    uint32_t *const jnplo = want_tree ? P.jnplo + wave * cap_n : nullptr;
-    uint32_t *const jnphi = want_tree ? P.jnphi + wave * cap_n : nullptr;
-
+    const int64_t wave = blockIdx.x;
     const int N = P.n_planes;
+    // PC: pool entries in LDS, a power of two >= 2 * WAVE (compile-time, so
+    // that the field offsets are instruction immediates)
+    uint32_t *const pool = lds;            // [POOL_FIELDS][PC], entry j at slot j & (PC-1)
+    uint32_t *const queue = pool + POOL_FIELDS * PC;           // [POOL_FIELDS][QCAP]
+    uint64_t *const thr = (uint64_t *)(queue + POOL_FIELDS * QCAP);  // c1[64], c2[64]
+    int32_t *const lay = (int32_t *)(thr + 128);               // layer of each plane
+    uint32_t *const hist = (uint32_t *)(lay + 64);             // per-plane counters
+    uint32_t *const tile = hist + 64;
+
+    for (int k = (int)lane; k < 64; k += WAVE) {
+        thr[k] = k < N ? P.c1[k] : 0ull;
+        thr[64 + k] = k < N ? P.c2[k] : 0ull;
+        lay[k] = k < N ? P.layer[k] : -1;
+    }
+
+    const int64_t G = P.spill_cap, cap_h = P.cap_h, cap_n = P.cap_n;
+    uint32_t *const spill = P.spill + wave * POOL_FIELDS * G;
+    uint32_t *const jh_w = P.jh + wave * (int64_t)SLOTS * JH_COUNT * cap_h;
+    uint32_t *const hidx = P.hidx + wave * cap_h;
+    uint32_t *const jn_w = TREE ? P.jn + wave * (int64_t)SLOTS * JN_COUNT * cap_n : nullptr;
+    const bool keys = P.keys;
+
+    Slots S;
+    S.i = -1;
+    S.sid = S.e0 = 0u;
+    S.live = S.hits = S.nodes = S.passes = S.escaped = S.backward = 0;
+    S.e_esc = 0u;
+
+    int top = 0, lo = 0, qn = 0, max_top = 0;
+    bool exhausted = false, overflow = false;
+    const float zf = P.z_first, dzp = P.dz;
+
+    // ---- pool access: logical entries [lo, top) are in LDS, [0, lo) spilled
+    auto pool_load = [&](int j) -> Entry {
+        if (j >= lo) return load_entry(pool, PC, j & (PC - 1));
+        if (j < G) return load_entry(spill, (int64_t)opaque_u32((uint32_t)G), j);
+        overflow = true;          // was never stored: the batch is rerun
+        return Entry{0.f, 0.f, 0.f, 0.f, 0u, 0u, 0u, 0, 0u};
+    };
+    auto pool_store = [&](int j, const Entry &p) {
+        const int sl = j & (PC - 1);
+        if (j - PC >= lo) {            // slot holds live entry j - PC: move it out
+            const Entry old = load_entry(pool, PC, sl);
+            if (j - PC < G) store_entry(spill, (int64_t)opaque_u32((uint32_t)G), j - PC, old);
+            else overflow = true;
+        }
+        store_entry(pool, PC, sl, p);
+    };
+
     for (;;) {
-        int item = 0;
-        if (lane == 0) item = (int)atomicAdd(&P.ctr[CTR_WORK], 1ull);
-        item = wave_uniform(__shfl(item, 0, WAVE));
-        if (item >= P.n) break;
-        const int i = P.order ? wave_uniform(P.order[item]) : item;
-        const uint32_t sid = P.sid_base + (uint32_t)i;
-
-        // ---- initial condition (section "Using SUPA": energy, angle, impact point)
-        const float sc = P.e0[i] * P.e_scale;
-        if (!(sc >= 0.0f) || !(sc < 4294967296.0f)) {
-            if (lane == 0) {
-                atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_RANGE);
-                for (int q = 0; q < 4; ++q) P.ledger[4 * (int64_t)i + q] = 0;
-                for (int q = 0; q < 6; ++q) P.counts[6 * (int64_t)i + q] = 0;
+        // ---- refill: start showers while the pool is short of a full wave
+        while (top < WAVE && !exhausted) {
+            const uint64_t free_slots = wave_ballot((int)lane < SLOTS && S.i < 0);
+            if (!free_slots) break;
+            const int s = __builtin_ctzll(free_slots);
+            int item = 0;
+            if (lane == 0) item = (int)atomicAdd(&P.ctr[CTR_WORK], 1ull);
+            item = wave_uniform(__shfl(item, 0, WAVE));
+            if (item >= P.n) { exhausted = true; break; }
+            const int i = COLD(order) ? wave_uniform(COLD(order)[item]) : item;
+            // initial condition (section "Using SUPA": energy, angle, impact point)
+            const float sc = COLD(e0)[i] * P.e_scale;
+            if (!(sc >= 0.0f) || !(sc < 4294967296.0f)) {
+                if (lane == 0) {
+                    atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_RANGE);
+                    for (int q = 0; q < 4; ++q) COLD(ledger)[4 * (int64_t)i + q] = 0;
+                    for (int q = 0; q < 6; ++q) COLD(counts)[6 * (int64_t)i + q] = 0;
+                }
+                continue;
             }
-            continue;
+            const uint32_t e_first = (uint32_t)rintf(sc);
+            float sp, cp, sa, ca;
+            sincosf(COLD(polar)[i], &sp, &cp);
+            sincosf(COLD(azimuth)[i], &sa, &ca);
+            const bool fwd0 = cp > 0.0f;
+            const float tpol = sp / cp;
+            const float x_first = COLD(x0) ? COLD(x0)[i] : 0.0f;
+            const float y_first = COLD(y0) ? COLD(y0)[i] : 0.0f;
+            if ((int)lane == s) {
+                S.i = i;
+                S.sid = P.sid_base + (uint32_t)i;
+                S.e0 = e_first;
+                S.live = fwd0 ? 1 : 0;
+                S.hits = 0;
+                S.nodes = 1;
+                S.passes = 0;
+                S.escaped = fwd0 ? 0 : 1;
+                S.backward = fwd0 ? 0 : 1;
+                S.e_esc = fwd0 ? 0u : e_first;
+            }
+            if (lane == 0 && fwd0) {
+                const Entry p0{x_first, y_first, tpol * ca, tpol * sa, e_first, 1u, 0u, 0,
+                               (uint32_t)s << 8};
+                pool_store(top, p0);
+            }
+            if (fwd0) {
+                ++top;
+                lo = max(lo, top - PC);
+            }
+            if (TREE && lane == 0) {
+                uint32_t *jn = jn_w + (int64_t)s * JN_COUNT * cap_n;
+                jn[JN_PARENT * cap_n] = (uint32_t)-1;
+                jn[JN_GEN * cap_n] = 0u;
+                jn[JN_X * cap_n] = __float_as_uint(x_first);
+                jn[JN_Y * cap_n] = __float_as_uint(y_first);
+                jn[JN_Z * cap_n] = 0u;
+                jn[JN_E * cap_n] = e_first;
+                jn[JN_LO * cap_n] = 1u;
+                jn[JN_HI * cap_n] = 0u;
+            }
         }
-        const uint32_t e_first = (uint32_t)rintf(sc);
-        float sp, cp, sa, ca;
-        sincosf(P.polar[i], &sp, &cp);
-        sincosf(P.azimuth[i], &sa, &ca);
-        const bool fwd0 = cp > 0.0f;
-        const float tpol = sp / cp;
-        const float x_first = P.x0 ? P.x0[i] : 0.0f;
-        const float y_first = P.y0 ? P.y0[i] : 0.0f;
+        const uint64_t active = wave_ballot((int)lane < SLOTS && S.i >= 0);
+        if (!active) break;
 
-        if (lane == 0 && fwd0) {
-            fx[0] = x_first;
-            fy[0] = y_first;
-            ftx[0] = tpol * ca;
-            fty[0] = tpol * sa;
-            fe[0] = e_first;
-            fplo[0] = 1u;
-            fphi[0] = 0u;
-            fnode[0] = 0;
-        }
-        if (lane == 0 && want_tree) {
-            jnp[0] = -1;
-            jng[0] = 0;
-            jnx[0] = x_first;
-            jny[0] = y_first;
-            jnz[0] = 0.0f;
-            jne[0] = e_first;
-            jnplo[0] = 1u;
-            jnphi[0] = 0u;
-        }
-        int n_cur = fwd0 ? 1 : 0;
-        int n_hits = 0, n_nodes = 1, n_splits = 0, max_front = n_cur;
-        uint64_t e_stop = 0, e_cut = 0, e_esc = 0;
-        int steps = 0, escaped = 0, backward = 0;
-        if (!fwd0 && lane == 0) {
-            e_esc = e_first;
-            escaped = 1;
-            backward = 1;
-        }
-        bool overflow = false;
-        int plane_start = 0;     // lane k: first journal hit of plane k
-        int cur = 0;
-        __threadfence_block();
-
-        for (int k = 0; k < N; ++k) {
-            if ((int)lane == k) plane_start = n_hits;
-            const float h = (k == 0) ? P.z_first : P.dz;
-            const int layer = P.layer[k];
-            const uint64_t c1 = P.c1[k], c2 = P.c2[k];
+        if (qn >= WAVE || (top == 0 && qn > 0)) {
+            // ---- phase B: draw, decide, split (Algorithm 1's three-way choice)
+            const int nb = min(WAVE, qn);
+            const bool valid = (int)lane < nb;
+            Entry p{0.f, 0.f, 0.f, 0.f, 0u, 0u, 0u, 0, 0u};
+            if (valid) p = load_entry(queue, QCAP, qn - 1 - (int)lane);
+            qn -= nb;
+            const int k = (int)(p.ks & 255u), slot = (int)(p.ks >> 8);
+            const uint32_t sid = (uint32_t)__shfl((int)S.sid, slot, WAVE);
+            const uint4 w = philox4x32_10((uint32_t)k, sid, p.lo, p.hi, opaque_u32(P.seed_lo),
+                                          opaque_u32(P.seed_hi));
+            const uint64_t c1 = thr[k], c2 = thr[64 + k];
+            const bool is_stop = valid && (uint64_t)w.x < c1;
+            const bool is_split = valid && !is_stop && (uint64_t)w.x < c2;
+            const bool is_pass = valid && !is_stop && !is_split;
             const bool last = (k == N - 1);
-            const int64_t rb = (int64_t)cur * cap_f, wb = (int64_t)(cur ^ 1) * cap_f;
-            const int n_read = n_cur < (int)cap_f ? n_cur : (int)cap_f;
-            int n_next = 0;
-            for (int base = 0; base < n_read; base += WAVE) {
-                const int j = base + (int)lane;
-                const bool valid = j < n_read;
-                float x = 0.f, y = 0.f, tx = 0.f, ty = 0.f;
-                uint32_t e = 0, plo = 0, phi = 0;
-                int node = 0;
-                if (valid) {
-                    x = fx[rb + j];
-                    y = fy[rb + j];
-                    tx = ftx[rb + j];
-                    ty = fty[rb + j];
-                    e = fe[rb + j];
-                    plo = fplo[rb + j];
-                    phi = fphi[rb + j];
-                    node = fnode[rb + j];
-                }
-                // free flight to plane k
-                x = fmaf(h, tx, x);
-                y = fmaf(h, ty, y);
-                steps += valid ? 1 : 0;
+            const uint64_t path = ((uint64_t)p.hi << 32) | p.lo;
 
-                // threshold, then the three-way choice on one Philox block
-                const bool is_cut = valid && (uint64_t)e < P.t_cut;
-                uint4 w = make_uint4(0u, 0u, 0u, 0u);
-                const bool draw = valid && !is_cut;
-                if (draw) w = philox4x32_10((uint32_t)k, sid, plo, phi, P.seed_lo, P.seed_hi);
-                const bool is_stop = draw && (uint64_t)w.x < c1;
-                const bool is_split = draw && !is_stop && (uint64_t)w.x < c2;
-                const bool is_pass = draw && !is_stop && !is_split;
-
-                // hits: journal in creation order
-                const bool is_hit = is_cut || is_stop;
-                const uint64_t mh = wave_ballot(is_hit);
-                if (is_hit) {
-                    if (is_cut) e_cut += e; else e_stop += e;
-                    if (want_hits) {
-                        const int pos = n_hits + (int)lanes_below(mh);
-                        if (pos < (int)cap_h) {
-                            jhx[pos] = x;
-                            jhy[pos] = y;
-                            jhe[pos] = e;
-                            jhl[pos] = layer;
-                            jhplo[pos] = plo;
-                            jhphi[pos] = phi;
-                        } else {
-                            overflow = true;
-                        }
-                    }
-                }
-                n_hits += (int)__popcll(mh);
-
-                // splits: two daughters, two tree nodes
-                Daughters D;
-                D.fwd_a = D.fwd_b = false;
-                D.ea = D.eb = 0;
-                D.txa = D.tya = D.txb = D.tyb = 0.f;
-                if (is_split) D = split_particle(P, tx, ty, e, w);
-                const uint64_t ms = wave_ballot(is_split);
-                const int node_a = n_nodes + 2 * (int)lanes_below(ms);
-                if (is_split && want_tree) {
-                    if (node_a + 1 < (int)cap_n) {
-                        const float zk = P.z_first + (float)k * P.dz;
-                        jnp[node_a] = node;
-                        jnp[node_a + 1] = node;
-                        const int gen = 63 - __clzll(((uint64_t)phi << 32) | plo);
-                        jng[node_a] = gen + 1;
-                        jng[node_a + 1] = gen + 1;
-                        jnx[node_a] = x;
-                        jnx[node_a + 1] = x;
-                        jny[node_a] = y;
-                        jny[node_a + 1] = y;
-                        jnz[node_a] = zk;
-                        jnz[node_a + 1] = zk;
-                        jne[node_a] = D.ea;
-                        jne[node_a + 1] = D.eb;
-                        const uint64_t pa = (((uint64_t)phi << 32) | plo) << 1;
-                        jnplo[node_a] = (uint32_t)pa;
-                        jnphi[node_a] = (uint32_t)(pa >> 32);
-                        jnplo[node_a + 1] = (uint32_t)pa | 1u;
-                        jnphi[node_a + 1] = (uint32_t)(pa >> 32);
+            // stops deposit: journal per shower
+            const uint64_t mstop = wave_ballot(is_stop);
+            if (mstop) {
+                int pos = 0;
+                for_each_slot(mstop, slot, [&](int s0, uint64_t m) {
+                    const int base = slot_get(S.hits, s0);
+                    if ((m >> lane) & 1ull) pos = base + (int)lanes_below(m);
+                    if ((int)lane == s0) S.hits = base + (int)__popcll(m);
+                    if ((int)lane == s0) S.live -= (int)__popcll(m);
+                });
+                if (is_stop) {
+                    if (pos < cap_h) {
+                        uint32_t *jh = jh_w + (int64_t)slot * JH_COUNT * cap_h;
+                        jh[JH_X * cap_h + pos] = __float_as_uint(p.x);
+                        jh[JH_Y * cap_h + pos] = __float_as_uint(p.y);
+                        jh[JH_E * cap_h + pos] = p.e;
+                        jh[JH_LO * cap_h + pos] = p.lo;
+                        jh[JH_HI * cap_h + pos] = p.hi;
+                        jh[JH_PK * cap_h + pos] = (uint32_t)k | KIND_STOP;
                     } else {
                         overflow = true;
                     }
                 }
-                n_nodes += 2 * (int)__popcll(ms);
-                n_splits += (int)__popcll(ms);
-
-                // particles for plane k+1 (or leaking out after the last plane)
-                const bool out_a = !last && ((is_split && D.fwd_a) || is_pass);
-                const bool out_b = !last && is_split && D.fwd_b;
-                if (last) {
-                    if (is_pass) { e_esc += e; escaped += 1; }
-                    if (is_split) { e_esc += (uint64_t)D.ea + D.eb; escaped += 2; }
-                } else if (is_split) {
-                    if (!D.fwd_a) { e_esc += D.ea; escaped += 1; backward += 1; }
-                    if (!D.fwd_b) { e_esc += D.eb; escaped += 1; backward += 1; }
-                }
-                const uint64_t m1 = wave_ballot(out_a), m2 = wave_ballot(out_b);
-                const int pos = n_next + (int)lanes_below(m1) + (int)lanes_below(m2);
-                if (out_a || out_b) {
-                    const uint64_t path = ((uint64_t)phi << 32) | plo;
-                    const int pa = pos, pb = pos + (out_a ? 1 : 0);
-                    if (out_a) {
-                        if (pa < (int)cap_f) {
-                            fx[wb + pa] = x;
-                            fy[wb + pa] = y;
-                            if (is_split) {
-                                ftx[wb + pa] = D.txa;
-                                fty[wb + pa] = D.tya;
-                                fe[wb + pa] = D.ea;
-                                fplo[wb + pa] = (uint32_t)(path << 1);
-                                fphi[wb + pa] = (uint32_t)(path >> 31);
-                                fnode[wb + pa] = node_a;
-                            } else {
-                                ftx[wb + pa] = tx;
-                                fty[wb + pa] = ty;
-                                fe[wb + pa] = e;
-                                fplo[wb + pa] = plo;
-                                fphi[wb + pa] = phi;
-                                fnode[wb + pa] = node;
-                            }
-                        } else {
-                            overflow = true;
-                        }
-                    }
-                    if (out_b) {
-                        if (pb < (int)cap_f) {
-                            fx[wb + pb] = x;
-                            fy[wb + pb] = y;
-                            ftx[wb + pb] = D.txb;
-                            fty[wb + pb] = D.tyb;
-                            fe[wb + pb] = D.eb;
-                            fplo[wb + pb] = (uint32_t)(path << 1) | 1u;
-                            fphi[wb + pb] = (uint32_t)(path >> 31);
-                            fnode[wb + pb] = node_a + 1;
-                        } else {
-                            overflow = true;
-                        }
-                    }
-                }
-                n_next += (int)__popcll(m1) + (int)__popcll(m2);
             }
-            // the next plane reads what other lanes of this wave just wrote
+
+            Daughters D;
+            D.fwd_a = D.fwd_b = false;
+            D.ea = D.eb = 0;
+            D.txa = D.tya = D.txb = D.tyb = 0.f;
+            if (is_split) D = split_particle(P, p.tx, p.ty, p.e, w);
+            const uint64_t msplit = wave_ballot(is_split);
+            int node_a = 0;
+            if (msplit) {
+                for_each_slot(msplit, slot, [&](int s0, uint64_t m) {
+                    const int base = slot_get(S.nodes, s0);
+                    if ((m >> lane) & 1ull) node_a = base + 2 * (int)lanes_below(m);
+                    if ((int)lane == s0) S.nodes = base + 2 * (int)__popcll(m);
+                });
+                if (TREE && is_split) {
+                    if (node_a + 1 < cap_n) {
+                        uint32_t *q = jn_w + (int64_t)slot * JN_COUNT * cap_n + node_a;
+                        const float zk = zf + (float)k * dzp;
+                        const uint32_t gen = (uint32_t)(64 - __clzll(path));
+                        const uint64_t pa = path << 1;
+                        q[JN_PARENT * cap_n] = (uint32_t)p.node;
+                        q[JN_PARENT * cap_n + 1] = (uint32_t)p.node;
+                        q[JN_GEN * cap_n] = gen;
+                        q[JN_GEN * cap_n + 1] = gen;
+                        q[JN_X * cap_n] = __float_as_uint(p.x);
+                        q[JN_X * cap_n + 1] = __float_as_uint(p.x);
+                        q[JN_Y * cap_n] = __float_as_uint(p.y);
+                        q[JN_Y * cap_n + 1] = __float_as_uint(p.y);
+                        q[JN_Z * cap_n] = __float_as_uint(zk);
+                        q[JN_Z * cap_n + 1] = __float_as_uint(zk);
+                        q[JN_E * cap_n] = D.ea;
+                        q[JN_E * cap_n + 1] = D.eb;
+                        q[JN_LO * cap_n] = (uint32_t)pa;
+                        q[JN_HI * cap_n] = (uint32_t)(pa >> 32);
+                        q[JN_LO * cap_n + 1] = (uint32_t)pa | 1u;
+                        q[JN_HI * cap_n + 1] = (uint32_t)(pa >> 32);
+                    } else {
+                        overflow = true;
+                    }
+                }
+            }
+
+            // particles for plane k+1, or leaking out (after the last plane, or
+            // turned away from +z)
+            const bool out_a = !last && ((is_split && D.fwd_a) || is_pass);
+            const bool out_b = !last && is_split && D.fwd_b;
+            int esc_n = 0, back_n = 0;
+            uint32_t esc_e = 0u;
+            if (last) {
+                if (is_pass) { esc_n = 1; esc_e = p.e; }
+                if (is_split) { esc_n = 2; esc_e = D.ea + D.eb; }
+            } else if (is_split) {
+                if (!D.fwd_a) { esc_n += 1; back_n += 1; esc_e += D.ea; }
+                if (!D.fwd_b) { esc_n += 1; back_n += 1; esc_e += D.eb; }
+            }
+            const uint64_t m1 = wave_ballot(out_a), m2 = wave_ballot(out_b);
+            // live particles per shower: + pushed daughters/passers - drawn
+            const uint64_t mdraw = wave_ballot(is_split || is_pass);
+            const uint64_t mesc = wave_ballot(esc_n > 0);
+            const uint64_t mpass = wave_ballot(is_pass);
+            for_each_slot(mdraw, slot, [&](int s0, uint64_t m) {
+                const int d = (int)__popcll(m1 & m) + (int)__popcll(m2 & m) - (int)__popcll(m);
+                const int np = (int)__popcll(mpass & m);
+                if ((int)lane == s0) {
+                    S.live += d;
+                    S.passes += np;
+                }
+                if (mesc & m) {
+                    const bool mine = (m >> lane) & 1ull;
+                    const int sn = wave_sum_i32(mine ? esc_n : 0);
+                    const int sb = wave_sum_i32(mine ? back_n : 0);
+                    const uint32_t se = wave_sum_u32(mine ? esc_e : 0u);
+                    if ((int)lane == s0) {
+                        S.escaped += sn;
+                        S.backward += sb;
+                        S.e_esc += se;
+                    }
+                }
+            });
+            const int pos = top + (int)lanes_below(m1) + (int)lanes_below(m2);
+            if (out_a) {
+                Entry q = p;
+                q.ks = (uint32_t)(k + 1) | ((uint32_t)slot << 8);
+                if (is_split) {
+                    q.tx = D.txa;
+                    q.ty = D.tya;
+                    q.e = D.ea;
+                    q.lo = (uint32_t)(path << 1);
+                    q.hi = (uint32_t)(path >> 31);
+                    q.node = node_a;
+                }
+                pool_store(pos, q);
+            }
+            if (out_b) {
+                const Entry q{p.x, p.y, D.txb, D.tyb, D.eb, (uint32_t)(path << 1) | 1u,
+                              (uint32_t)(path >> 31), node_a + 1,
+                              (uint32_t)(k + 1) | ((uint32_t)slot << 8)};
+                pool_store(pos + (out_a ? 1 : 0), q);
+            }
+            top += (int)__popcll(m1) + (int)__popcll(m2);
+            lo = max(lo, top - PC);
+            max_top = max(max_top, top);
+        } else if (top > 0) {
+            // ---- phase A: free flight to the next plane, threshold test
+            const int na = min(WAVE, top);
+            const bool valid = (int)lane < na;
+            const int j = top - 1 - (int)lane;
+            if (top - na < lo) __threadfence_block();    // spilled entries: see other lanes' stores
+            Entry p{0.f, 0.f, 0.f, 0.f, 0u, 0u, 0u, 0, 0u};
+            if (valid) p = pool_load(j);
+            top -= na;
+            lo = min(lo, top);
+            const int k = (int)(p.ks & 255u), slot = (int)(p.ks >> 8);
+            const float h = (k == 0) ? zf : dzp;
+            p.x = fmaf(h, p.tx, p.x);
+            p.y = fmaf(h, p.ty, p.y);
+            const bool is_cut = valid && (uint64_t)p.e < P.t_cut;
+            const uint64_t mcut = wave_ballot(is_cut);
+            if (mcut) {
+                int hpos = 0;
+                for_each_slot(mcut, slot, [&](int s0, uint64_t m) {
+                    const int base = slot_get(S.hits, s0);
+                    if ((m >> lane) & 1ull) hpos = base + (int)lanes_below(m);
+                    if ((int)lane == s0) {
+                        S.hits = base + (int)__popcll(m);
+                        S.live -= (int)__popcll(m);
+                    }
+                });
+                if (is_cut) {
+                    if (hpos < cap_h) {
+                        uint32_t *jh = jh_w + (int64_t)slot * JH_COUNT * cap_h;
+                        jh[JH_X * cap_h + hpos] = __float_as_uint(p.x);
+                        jh[JH_Y * cap_h + hpos] = __float_as_uint(p.y);
+                        jh[JH_E * cap_h + hpos] = p.e;
+                        jh[JH_LO * cap_h + hpos] = p.lo;
+                        jh[JH_HI * cap_h + hpos] = p.hi;
+                        jh[JH_PK * cap_h + hpos] = (uint32_t)k;
+                    } else {
+                        overflow = true;
+                    }
+                }
+            }
+            const bool to_q = valid && !is_cut;
+            const uint64_t mq = wave_ballot(to_q);
+            if (to_q) store_entry(queue, QCAP, qn + (int)lanes_below(mq), p);
+            qn += (int)__popcll(mq);
+        } else if (wave_ballot((int)lane < SLOTS && S.i >= 0 && S.live > 0)) {
+            // nothing pending although a shower still counts live particles:
+            // its accounting is inconsistent; report it and close it
+            if (lane == 0) atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_INTERNAL);
+            if ((int)lane < SLOTS) S.live = 0;
+        }
+
+        // ---- showers whose last particle is done
+        uint64_t done = wave_ballot((int)lane < SLOTS && S.i >= 0 && S.live <= 0);
+        while (done) {
+            const int s = __builtin_ctzll(done);
+            done &= done - 1;
+            const int i = slot_get(S.i, s);
+            const int nh = slot_get(S.hits, s);
+            const int nn = slot_get(S.nodes, s);
+            const int npass = slot_get(S.passes, s);
+            const int nesc = slot_get(S.escaped, s);
+            const int nback = slot_get(S.backward, s);
+            const uint32_t eesc = (uint32_t)slot_get((int)S.e_esc, s);
+            const uint32_t e_first = (uint32_t)slot_get((int)S.e0, s);
+            const int nsplit = (nn - 1) / 2;
+            const bool sh_over = wave_ballot(overflow) != 0 || nh > cap_h || (TREE && nn > cap_n);
+            uint32_t *const jh = jh_w + (int64_t)s * JH_COUNT * cap_h;
+            __threadfence_block();      // journal entries written by every lane
+
+            // counting sort of the hits by plane
+            hist[lane] = 0u;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            uint64_t e_stop = 0, e_cut = 0;
+            const int nread = sh_over ? 0 : nh;
+            for (int j = (int)lane; j < nread; j += WAVE) {
+                const uint32_t pk = jh[JH_PK * cap_h + j];
+                const uint32_t e = jh[JH_E * cap_h + j];
+                atomicAdd(&hist[pk & 63u], 1u);
+                if (pk & KIND_STOP) e_stop += e; else e_cut += e;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            const int plane_start = wave_excl_scan((int)hist[lane]);   // lane k: first hit of plane k
+            hist[lane] = (uint32_t)plane_start;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            e_stop = wave_sum_u64(e_stop);
+            e_cut = wave_sum_u64(e_cut);
+
+            long long hit_start = 0, node_start = 0;
+            if (lane == 0) {
+                int64_t *led = (int64_t *)COLD(ledger) + 4 * (int64_t)i;
+                led[0] = e_first;
+                led[1] = (int64_t)e_stop;
+                led[2] = (int64_t)e_cut;
+                led[3] = eesc;
+                int32_t *cnt = COLD(counts) + 6 * (int64_t)i;
+                cnt[0] = nn;
+                cnt[1] = nh;
+                cnt[2] = nh + nsplit + npass;
+                cnt[3] = nsplit;
+                cnt[4] = nesc;
+                cnt[5] = nback;
+                atomicAdd(&P.ctr[CTR_STEPS], (unsigned long long)(nh + nsplit + npass));
+                if (P.outputs & 1u)
+                    hit_start = (long long)atomicAdd(&P.ctr[CTR_HITS], (unsigned long long)nh);
+                if (TREE)
+                    node_start = (long long)atomicAdd(&P.ctr[CTR_NODES], (unsigned long long)nn);
+                atomicMax(&P.ctr[CTR_NEED_F], (unsigned long long)max_top);
+                atomicMax(&P.ctr[CTR_NEED_H], (unsigned long long)nh);
+                atomicMax(&P.ctr[CTR_NEED_N], (unsigned long long)nn);
+                if (sh_over) atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_OVERFLOW);
+            }
+            if ((int)lane == s) S.i = -1;
+            if (sh_over) continue;
+            hit_start = __shfl(hit_start, 0, WAVE);
+            node_start = __shfl(node_start, 0, WAVE);
+            const bool write_hits = (P.outputs & 1u) && hit_start + nh <= COLD(hit_capacity);
+            if ((P.outputs & 1u) && lane == 0) COLD(hit_offsets)[i] = hit_start;
+
+            // hit cloud in plane order; hidx keeps the order for the images
+            float *const hx = COLD(hit_x), *const hy = COLD(hit_y), *const he = COLD(hit_e);
+            int32_t *const hl = COLD(hit_layer);
+            uint64_t *const hk = COLD(hit_key);
+            for (int j = (int)lane; j < nh; j += WAVE) {
+                const uint32_t pk = jh[JH_PK * cap_h + j];
+                const int q = (int)atomicAdd(&hist[pk & 63u], 1u);
+                hidx[q] = (uint32_t)j;
+                if (write_hits) {
+                    const int64_t o = hit_start + q;
+                    hx[o] = __uint_as_float(jh[JH_X * cap_h + j]);
+                    hy[o] = __uint_as_float(jh[JH_Y * cap_h + j]);
+                    he[o] = (float)jh[JH_E * cap_h + j] * P.e_unscale;
+                    hl[o] = lay[pk & 63u];
+                    if (keys) hk[o] = ((uint64_t)jh[JH_HI * cap_h + j] << 32) | jh[JH_LO * cap_h + j];
+                }
+            }
             __threadfence_block();
-            n_cur = n_next;
-            max_front = max_front > n_cur ? max_front : n_cur;
-            cur ^= 1;
-        }
-        if ((int)lane == N) plane_start = n_hits;
-        if (n_cur > (int)cap_f) overflow = true;
-        const bool wave_overflow = wave_ballot(overflow) != 0;
 
-        // ---- per-shower ledger and counts
-        e_stop = wave_sum_u64(e_stop);
-        e_cut = wave_sum_u64(e_cut);
-        e_esc = wave_sum_u64(e_esc);
-        steps = wave_sum_i32(steps);
-        escaped = wave_sum_i32(escaped);
-        backward = wave_sum_i32(backward);
-
-        long long hit_start = 0, node_start = 0;
-        if (lane == 0) {
-            P.ledger[4 * (int64_t)i + 0] = e_first;
-            P.ledger[4 * (int64_t)i + 1] = e_stop;
-            P.ledger[4 * (int64_t)i + 2] = e_cut;
-            P.ledger[4 * (int64_t)i + 3] = e_esc;
-            int32_t *cnt = P.counts + 6 * (int64_t)i;
-            cnt[0] = n_nodes;
-            cnt[1] = n_hits;
-            cnt[2] = steps;
-            cnt[3] = n_splits;
-            cnt[4] = escaped;
-            cnt[5] = backward;
-            atomicAdd(&P.ctr[CTR_STEPS], (unsigned long long)steps);
-            if (P.outputs & 1u)
-                hit_start = (long long)atomicAdd(&P.ctr[CTR_HITS], (unsigned long long)n_hits);
-            if (want_tree)
-                node_start = (long long)atomicAdd(&P.ctr[CTR_NODES], (unsigned long long)n_nodes);
-            atomicMax(&P.ctr[CTR_NEED_F], (unsigned long long)max_front);
-            atomicMax(&P.ctr[CTR_NEED_H], (unsigned long long)n_hits);
-            atomicMax(&P.ctr[CTR_NEED_N], (unsigned long long)n_nodes);
-            if (wave_overflow) atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_OVERFLOW);
-        }
-        if (wave_overflow) continue;
-        hit_start = __shfl(hit_start, 0, WAVE);
-        node_start = __shfl(node_start, 0, WAVE);
-
-        // ---- hit point cloud: copy the journal into the reserved segment
-        if (P.outputs & 1u) {
-            if (lane == 0) P.hit_offsets[i] = hit_start;
-            if (hit_start + n_hits <= P.hit_capacity) {
-                for (int j = (int)lane; j < n_hits; j += WAVE) {
-                    const int64_t o = hit_start + j;
-                    P.hit_x[o] = jhx[j];
-                    P.hit_y[o] = jhy[j];
-                    P.hit_e[o] = (float)jhe[j] * P.e_unscale;
-                    P.hit_layer[o] = jhl[j];
-                    if (P.hit_key) P.hit_key[o] = ((uint64_t)jhphi[j] << 32) | jhplo[j];
+            // propagation tree
+            if (TREE) {
+                if (lane == 0) COLD(node_offsets)[i] = node_start;
+                if (node_start + nn <= COLD(node_capacity)) {
+                    const uint32_t *jn = jn_w + (int64_t)s * JN_COUNT * cap_n;
+                    int32_t *const np_ = COLD(node_parent), *const ng = COLD(node_gen);
+                    float *const nvx = COLD(node_vx), *const nvy = COLD(node_vy);
+                    float *const nvz = COLD(node_vz), *const ne = COLD(node_e);
+                    uint64_t *const nk = COLD(node_key);
+                    for (int j = (int)lane; j < nn; j += WAVE) {
+                        const int64_t o = node_start + j;
+                        np_[o] = (int32_t)jn[JN_PARENT * cap_n + j];
+                        ng[o] = (int32_t)jn[JN_GEN * cap_n + j];
+                        nvx[o] = __uint_as_float(jn[JN_X * cap_n + j]);
+                        nvy[o] = __uint_as_float(jn[JN_Y * cap_n + j]);
+                        nvz[o] = __uint_as_float(jn[JN_Z * cap_n + j]);
+                        ne[o] = (float)jn[JN_E * cap_n + j] * P.e_unscale;
+                        if (keys) nk[o] = ((uint64_t)jn[JN_HI * cap_n + j] << 32) | jn[JN_LO * cap_n + j];
+                    }
                 }
             }
-        }
-        // ---- propagation tree
-        if (want_tree) {
-            if (lane == 0) P.node_offsets[i] = node_start;
-            if (node_start + n_nodes <= P.node_capacity) {
-                for (int j = (int)lane; j < n_nodes; j += WAVE) {
-                    const int64_t o = node_start + j;
-                    P.node_parent[o] = jnp[j];
-                    P.node_gen[o] = jng[j];
-                    P.node_vx[o] = jnx[j];
-                    P.node_vy[o] = jny[j];
-                    P.node_vz[o] = jnz[j];
-                    P.node_e[o] = (float)jne[j] * P.e_unscale;
-                    if (P.node_key) P.node_key[o] = ((uint64_t)jnphi[j] << 32) | jnplo[j];
-                }
-            }
-        }
-        // ---- per-layer images (appendix "Downsampling"): integer sums per cell
-        if (P.outputs & 2u) {
-            const int nx = P.img_nx, ny = P.img_ny, rows = P.img_rows;
-            const int64_t img_layer = (int64_t)ny * nx;
-            for (int l = 0; l < P.n_layers; ++l) {
-                float *img = P.images + ((int64_t)i * P.n_layers + l) * img_layer;
-                for (int r0 = 0; r0 < ny; r0 += rows) {
-                    const int nr = (ny - r0) < rows ? (ny - r0) : rows;
-                    const int words = nr * nx;
-                    for (int q = (int)lane; q < words; q += WAVE) tile[q] = 0u;
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    for (int k = 0; k < N; ++k) {
-                        if (P.layer[k] != l) continue;
-                        const int hs = __shfl(plane_start, k, WAVE);
-                        const int he = __shfl(plane_start, k + 1, WAVE);
-                        for (int j = hs + (int)lane; j < he; j += WAVE) {
-                            const float cx = floorf((jhx[j] - P.img_x0) * P.img_sx);
-                            const float cy = floorf((jhy[j] - P.img_y0) * P.img_sy);
-                            if (cx >= 0.0f && cx < (float)nx && cy >= (float)r0 &&
-                                cy < (float)(r0 + nr)) {
-                                atomicAdd(&tile[((int)cy - r0) * nx + (int)cx], jhe[j]);
+
+            // per-layer images (appendix "Downsampling"): integer sums per cell
+            if (P.outputs & 2u) {
+                const int nx = COLD(img_nx), ny = COLD(img_ny), rows = COLD(img_rows);
+                const int L = COLD(n_layers);
+                const float ix0 = COLD(img_x0), iy0 = COLD(img_y0);
+                const float isx = COLD(img_sx), isy = COLD(img_sy);
+                const int32_t *lps = COLD(layer_plane_start), *lpl = COLD(layer_planes);
+                const int64_t img_layer = (int64_t)ny * nx;
+                float *const images = COLD(images);
+                for (int l = 0; l < L; ++l) {
+                    float *img = images + ((int64_t)i * L + l) * img_layer;
+                    const int lp0 = lps[l], lp1 = lps[l + 1];
+                    for (int r0 = 0; r0 < ny; r0 += rows) {
+                        const int nr = min(ny - r0, rows);
+                        const int words = nr * nx;
+                        for (int q = (int)lane; q < words; q += WAVE) tile[q] = 0u;
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        for (int t = lp0; t < lp1; ++t) {
+                            const int k = lpl[t];
+                            const int hs = __shfl(plane_start, k, WAVE);
+                            const int he2 = __shfl(plane_start, k + 1, WAVE);
+                            for (int q = hs + (int)lane; q < he2; q += WAVE) {
+                                const uint32_t j = hidx[q];
+                                const float cx = floorf((__uint_as_float(jh[JH_X * cap_h + j]) - ix0) * isx);
+                                const float cy = floorf((__uint_as_float(jh[JH_Y * cap_h + j]) - iy0) * isy);
+                                if (cx >= 0.0f && cx < (float)nx && cy >= (float)r0 &&
+                                    cy < (float)(r0 + nr))
+                                    atomicAdd(&tile[((int)cy - r0) * nx + (int)cx], jh[JH_E * cap_h + j]);
                             }
                         }
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                        float *dst = img + (int64_t)r0 * nx;
+                        if ((words & 3) == 0 && (((uintptr_t)dst) & 15) == 0) {
+                            for (int q = 4 * (int)lane; q < words; q += 4 * WAVE) {
+                                const float4 v = make_float4((float)tile[q] * P.e_unscale,
+                                                             (float)tile[q + 1] * P.e_unscale,
+                                                             (float)tile[q + 2] * P.e_unscale,
+                                                             (float)tile[q + 3] * P.e_unscale);
+                                *(float4 *)(dst + q) = v;
+                            }
+                        } else {
+                            for (int q = (int)lane; q < words; q += WAVE)
+                                dst[q] = (float)tile[q] * P.e_unscale;
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     }
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                    for (int q = (int)lane; q < words; q += WAVE)
-                        img[(int64_t)r0 * nx + q] = (float)tile[q] * P.e_unscale;
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 }
             }
         }
     }
+    if (wave_ballot(overflow) && lane == 0) atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_OVERFLOW);
 }
 
 __global__ void supa_zero_counters(unsigned long long *ctr) {
@@ -459,16 +675,32 @@ __global__ void supa_philox_kernel(const uint32_t *ctr, int64_t n, uint32_t k0, 
 }
 
 // ---------------------------------------------------------------------------
-// host-side launchers (called by the C ABI in supa_api.cpp)
+// host-side launchers (called by the C ABI in supa_api.hip)
 // ---------------------------------------------------------------------------
 hipError_t launch_zero_counters(unsigned long long *ctr, hipStream_t s) {
     hipLaunchKernelGGL(supa_zero_counters, dim3(1), dim3(64), 0, s, ctr);
     return hipGetLastError();
 }
 
-hipError_t launch_propagate(const Params &P, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(supa_propagate, dim3(blocks), dim3(WAVE * WAVES_PER_BLOCK), 0, s, P);
+size_t propagate_lds_bytes(int pool_cap, int tile_words) {
+    return (size_t)lds_words(pool_cap, tile_words) * 4;
+}
+
+template <bool TREE>
+static hipError_t launch_pc(const Params &P, int blocks, size_t lds, hipStream_t s) {
+    switch (P.pool_cap) {
+    case 128: hipLaunchKernelGGL((supa_propagate<TREE, 128>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 256: hipLaunchKernelGGL((supa_propagate<TREE, 256>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 512: hipLaunchKernelGGL((supa_propagate<TREE, 512>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 1024: hipLaunchKernelGGL((supa_propagate<TREE, 1024>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
+}
+
+hipError_t launch_propagate(const Params &P, int blocks, hipStream_t s) {
+    const size_t lds = propagate_lds_bytes(P.pool_cap, P.tile_words);
+    return (P.outputs & 4u) ? launch_pc<true>(P, blocks, lds, s) : launch_pc<false>(P, blocks, lds, s);
 }
 
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
@@ -480,8 +712,5 @@ hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k
                        k1, out);
     return hipGetLastError();
 }
-
-int waves_per_block() { return WAVES_PER_BLOCK; }
-int tile_words() { return TILE_WORDS; }
 
 }  // namespace supa
