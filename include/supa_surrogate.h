@@ -1,0 +1,126 @@
+/*
+ * supa_surrogate.h -- C ABI of the learned surrogate's kernels (gfx950).
+ *
+ * The surrogate extends the paper's method: a conditional MLP maps a shower's
+ * initial condition (energy, polar angle, azimuth; the conditioning variables
+ * of the paper's section "Extensions") plus Gaussian noise to the mean and
+ * log-variance of its coarse per-layer deposit images (the image
+ * representation of the appendix "Downsampling").  It is trained with the
+ * Gaussian negative log-likelihood on images made by supa_simulate, and at
+ * inference showers whose predicted uncertainty is above a threshold are
+ * simulated instead (fallback); per-layer energy distributions of the result
+ * are compared with the simulator's by the 1-D Wasserstein distance, the
+ * metric of the paper's section "Performance Analysis of Generative Models".
+ *
+ * Conventions (all entry points):
+ *   - pointers are device pointers owned by the caller; bf16 arrays are
+ *     uint16_t holding bfloat16 bit patterns; matrices are row-major with the
+ *     given leading dimension (elements);
+ *   - work is enqueued on `hip_stream` (hipStream_t, NULL = default stream)
+ *     and nothing is synchronised; errors of a kernel launch are returned;
+ *   - return SUPA_OK, SUPA_ERR_INVALID_ARG (bad sizes or NULL pointers,
+ *     nothing launched) or SUPA_ERR_DEVICE; supa_surrogate_last_error() gives
+ *     the message of the calling thread's last error.
+ */
+#ifndef SUPA_SURROGATE_H
+#define SUPA_SURROGATE_H
+
+#include <stdint.h>
+
+#include "supa.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { SUPA_EPI_F32 = 0, SUPA_EPI_BIAS_F32 = 1, SUPA_EPI_BIAS_GELU = 2, SUPA_EPI_GELU_GRAD = 3 };
+
+/*
+ * C = op(A) op(B), bf16 inputs, float32 accumulation on the matrix cores.
+ *   trans_a = 0: A is M x K ([M][lda]);  1: A is stored K x M ([K][lda]).
+ *   trans_b = 0: B is K x N ([K][ldb]);  1: B is stored N x K ([N][ldb]).
+ * Supported (trans_a, trans_b, epilogue): (0,0,F32), (0,0,BIAS_F32),
+ * (0,0,BIAS_GELU), (0,1,F32), (0,1,GELU_GRAD), (1,0,F32).  Epilogues:
+ *   F32        C float [M][ldc] = acc
+ *   BIAS_F32   C float = acc + bias[n]
+ *   BIAS_GELU  pre bf16 [M][ldc] = acc + bias[n]; C bf16 = GELU(pre),
+ *              GELU(a) = a Phi(a) (exact, erf form)
+ *   GELU_GRAD  C bf16 = acc * GELU'(pre[m][n]) (pre read, bf16 [M][ldc])
+ * M, N, K >= 1 and multiples of 8; leading dimensions multiples of 8.
+ */
+supa_status supa_gemm_bf16(void *hip_stream, int trans_a, int trans_b, int epilogue, int M, int N,
+                           int K, const uint16_t *A, int lda, const uint16_t *B, int ldb,
+                           const float *bias, void *C, int ldc, uint16_t *pre);
+
+/*
+ * Gaussian NLL of targets y[b][j] = img[b][j] * y_scale / e0[b] under
+ * out[b] = [mu | s_raw] (float [B][2D]), s = clamp(s_raw, -s_clamp, s_clamp):
+ * adds sum over b, j of 1/2 (s + (y - mu)^2 exp(-s)) to *loss (float, device)
+ * and writes dout = d mean / d out as bf16 [B][2D] (zero for clamped s).
+ */
+supa_status supa_nll_grad(void *hip_stream, int B, int D, const float *out, const float *img,
+                          const float *e0, float y_scale, float s_clamp, uint16_t *dout,
+                          float *loss);
+
+/* out[n] = sum over m < M of X[m][n] for n < N (X bf16 [M][ld]). */
+supa_status supa_colsum_bf16(void *hip_stream, int M, int N, const uint16_t *X, int ld, float *out);
+
+/* Adam (Kingma & Ba, 2015) step `step` (>= 1) on n float32 parameters p with
+ * gradients g and moments m, v; p_bf16 (may be NULL) receives bf16(p). */
+supa_status supa_adam(void *hip_stream, int64_t n, float *p, const float *g, float *m, float *v,
+                      uint16_t *p_bf16, float lr, float beta1, float beta2, float eps, int step);
+
+/* y[i] = bf16(x[i]) (round to nearest even) for i < n. */
+supa_status supa_to_bf16(void *hip_stream, int64_t n, const float *x, uint16_t *y);
+
+/*
+ * Input rows x bf16 [B][ld]: e0*e_scale, polar*polar_scale, azimuth*az_scale,
+ * then n_noise standard normals, zeros up to ld.  Normal pairs come from the
+ * Box-Muller transform of the words of Philox4x32-10 blocks keyed by `seed`
+ * and counted by (row_base + row, stream_id, 0x5eed, q) for q = 0, 4, 8, ...
+ * 3 + n_noise <= ld, ld multiple of 8.
+ */
+supa_status supa_surrogate_features(void *hip_stream, int B, int ld, int n_noise, const float *e0,
+                                    const float *polar, const float *azimuth, float e_scale,
+                                    float polar_scale, float az_scale, uint32_t row_base,
+                                    uint32_t stream_id, uint64_t seed, uint16_t *x);
+
+/*
+ * From out (float [B][2D], D = L * bins) per shower b: layer_e[b][l] =
+ * e0[b] / y_scale * sum of mu over the bins of layer l; unc[b] =
+ * sqrt(sum exp(s)) / max(sum mu, 1e-6); img (may be NULL) [B][D] =
+ * e0[b] / y_scale * mu.  With 0 <= rho <= 1 the per-layer energies are
+ * samples: e0/y_scale * (sum mu + sd z), sd^2 = rho (sum sigma)^2 +
+ * (1 - rho) sum sigma^2 (bins of a layer correlated with coefficient rho),
+ * z = Box-Muller normal from the Philox4x32-10 block keyed by `seed` and
+ * counted by (row_base + b, l, 0x9a7e, 0); rho < 0: no sampling.
+ */
+supa_status supa_surrogate_gate(void *hip_stream, int B, int D, int L, const float *out,
+                                const float *e0, float y_scale, float s_clamp, float *layer_e,
+                                float *unc, float *img, float rho, uint32_t row_base, uint64_t seed);
+
+/*
+ * idx[0..*count) = the indices i < n with v[i] > tau, increasing.  idx holds
+ * n int32; count is one device int32; block_scratch holds ceil(n/1024) int32.
+ */
+supa_status supa_select_above(void *hip_stream, int n, const float *v, float tau, int32_t *idx,
+                              int32_t *count, int32_t *block_scratch);
+
+/* out_k[j] = in_k[idx[j]] for j < m, three float arrays. */
+supa_status supa_gather3(void *hip_stream, int m, const int32_t *idx, const float *a,
+                         const float *b, const float *c, float *oa, float *ob, float *oc);
+
+/* dst[idx[j]][0..w) = src[j][0..w) for j < m (float rows). */
+supa_status supa_scatter_rows(void *hip_stream, int m, int w, const int32_t *idx, const float *src,
+                              float *dst);
+
+/* out[r][l] = sum over q < g of x[r][l*g + q] (float), r < rows, l < L. */
+supa_status supa_group_sums(void *hip_stream, int rows, int L, int g, const float *x, float *out);
+
+/* Message of the calling thread's last surrogate-kernel error. */
+const char *supa_surrogate_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -22,10 +22,10 @@ hipError_t launch_zero_counters(unsigned long long *ctr, hipStream_t s);
 hipError_t launch_propagate(const Params &P, int blocks, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t s);
-size_t propagate_lds_bytes(int pool_cap, int tile_words);
+size_t propagate_lds_bytes(int pool_cap);
+hipError_t launch_images(const ImgParams &P, int n_cu, hipStream_t s);
 }  // namespace supa
 
-static constexpr int kTileWords = 1024;       // LDS image tile: 4 KB per wave
 static constexpr int kMaxImageWidth = 1024;
 
 struct supa_ctx {
@@ -49,13 +49,17 @@ struct supa_ctx {
     supa::Cold *h_cold = nullptr;          // its pinned host staging copy
     // per-wave scratch
     int n_cu = 0;
-    int waves_per_cu = 8;
-    int pool_cap = 256;                  // particle-pool entries kept in LDS
-    int spill_cap = 1024, cap_h = 4096, cap_n = 8192;   // per-wave spill / journals
+    int waves_per_cu = 10;
+    int pool_cap = 128;                  // particle-pool entries kept in LDS
+    int spill_cap = 4096, cap_h = 4096, cap_n = 8192;   // per-wave spill / journals
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
     supa::Params layout{};               // scratch pointers only
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    // per-batch hand-over to the image kernel (grows with the batch)
+    void *iscratch = nullptr;
+    size_t iscratch_bytes = 0;
+    int64_t img_cap = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float timing[3] = {0, 0, 0};
     std::string err;
     bool broken = false;
@@ -150,7 +154,7 @@ static supa_status ensure_scratch(supa_ctx *c, bool tree) {
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t spill_b = al((size_t)waves * supa::POOL_FIELDS * c->spill_cap * 4);
     const size_t jh_b = al((size_t)waves * supa::SLOTS * supa::JH_COUNT * c->cap_h * 4);
-    const size_t hidx_b = al((size_t)waves * c->cap_h * 4);
+    const size_t hidx_b = 0;
     const size_t jn_b = tree ? al((size_t)waves * supa::SLOTS * supa::JN_COUNT * c->cap_n * 4) : 0;
     const size_t need = spill_b + jh_b + hidx_b + jn_b;
     if (need > c->scratch_bytes) {
@@ -170,8 +174,38 @@ static supa_status ensure_scratch(supa_ctx *c, bool tree) {
     L.cap_n = c->cap_n;
     L.spill = (uint32_t *)p;
     L.jh = (uint32_t *)(p + spill_b);
-    L.hidx = (uint32_t *)(p + spill_b + jh_b);
+    L.hidx = nullptr;
     L.jn = tree ? (uint32_t *)(p + spill_b + jh_b + hidx_b) : nullptr;
+    return SUPA_OK;
+}
+
+// Hand-over buffers between the propagation and the image kernel.
+static supa_status ensure_image_scratch(supa_ctx *c, int64_t n, int64_t cap, bool xy) {
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t cnt_b = al((size_t)n * 4), seg_b = xy ? al((size_t)n * 8) : 0;
+    const size_t e_b = al((size_t)cap * 4), xy_b = xy ? 3 * al((size_t)cap * 4) : 0;
+    const size_t need = cnt_b + seg_b + e_b + xy_b;
+    if (need > c->iscratch_bytes) {
+        if (c->iscratch) (void)hipFree(c->iscratch);
+        c->iscratch = nullptr;
+        c->iscratch_bytes = 0;
+        void *p = nullptr;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, SUPA_ERR_NOMEM, "cannot allocate " + std::to_string(need) + " bytes of image scratch");
+        }
+        c->iscratch = p;
+        c->iscratch_bytes = need;
+    }
+    char *p = (char *)c->iscratch;
+    supa::Cold &K = *c->h_cold;
+    K.img_count = (int32_t *)p;
+    K.img_seg = xy ? (int64_t *)(p + cnt_b) : nullptr;
+    K.img_e = (uint32_t *)(p + cnt_b + seg_b);
+    K.img_x = xy ? (float *)(p + cnt_b + seg_b + e_b) : nullptr;
+    K.img_y = xy ? (float *)(p + cnt_b + seg_b + e_b + al((size_t)cap * 4)) : nullptr;
+    K.img_layer = xy ? (int32_t *)(p + cnt_b + seg_b + e_b + 2 * al((size_t)cap * 4)) : nullptr;
+    K.img_cap = cap;
     return SUPA_OK;
 }
 
@@ -245,7 +279,7 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
               hipMemcpy(c->d_layer, c->layer.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->d_c1, c1.data(), N * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->d_c2, c2.data(), N * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess;
-    for (int q = 0; q < 3 && ok; ++q) ok = hipEventCreate(&c->ev[q]) == hipSuccess;
+    for (int q = 0; q < 4 && ok; ++q) ok = hipEventCreate(&c->ev[q]) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         supa_destroy(c);
@@ -260,6 +294,7 @@ extern "C" supa_status supa_destroy(supa_ctx *c) {
     (void)hipSetDevice(c->device);
     if (c->stream || true) (void)hipStreamSynchronize(c->stream);
     free_scratch(c);
+    if (c->iscratch) (void)hipFree(c->iscratch);
     if (c->d_layer) (void)hipFree(c->d_layer);
     if (c->d_layer_plane_start) (void)hipFree(c->d_layer_plane_start);
     if (c->d_layer_planes) (void)hipFree(c->d_layer_planes);
@@ -370,7 +405,7 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         P.outputs = outs;
         P.keys = (outs & SUPA_OUT_KEYS) != 0;
         P.pool_cap = c->pool_cap;
-        P.tile_words = (outs & SUPA_OUT_IMAGES) ? kTileWords : 0;
+        P.tile_words = 0;
         P.ctr = c->d_ctr;
         P.cold = c->d_cold;
 
@@ -396,7 +431,7 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         K.img_y0 = (float)c->g.img_y0;
         K.img_sx = (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0));
         K.img_sy = (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0));
-        K.img_rows = (outs & SUPA_OUT_IMAGES) ? std::max(1, std::min(c->g.img_ny, kTileWords / c->g.img_nx)) : 1;
+        K.img_rows = 0;
         K.n_layers = c->n_layers;
         K.layer_plane_start = c->d_layer_plane_start;
         K.layer_planes = c->d_layer_planes;
@@ -411,6 +446,14 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         K.node_capacity = tree ? out->node_capacity : 0;
         K.ledger = out->ledger;
         K.counts = out->counts;
+        const bool images = (outs & SUPA_OUT_IMAGES) != 0;
+        if (images) {
+            const bool hits_out = (outs & SUPA_OUT_HITS) != 0;
+            if (!hits_out && c->img_cap == 0) c->img_cap = std::max<int64_t>(1024, 64 * n);
+            const int64_t cap = hits_out ? std::max<int64_t>(out->hit_capacity, 1) : c->img_cap;
+            supa_status si = ensure_image_scratch(c, n, cap, !hits_out);
+            if (si != SUPA_OK) return si;
+        }
 
         const int blocks = std::max(1, c->n_cu * c->waves_per_cu);
         HIP_TRY(c, hipMemcpyAsync(c->d_cold, c->h_cold, sizeof(supa::Cold), hipMemcpyHostToDevice,
@@ -419,22 +462,46 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         HIP_TRY(c, supa::launch_zero_counters(c->d_ctr, c->stream));
         HIP_TRY(c, supa::launch_propagate(P, blocks, c->stream));
         HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+        if (images) {
+            supa::ImgParams Q{};
+            const supa::Cold &K2 = *c->h_cold;
+            Q.n = (int32_t)n;
+            Q.L = c->n_layers;
+            Q.nx = c->g.img_nx;
+            Q.ny = c->g.img_ny;
+            Q.n_planes = c->g.n_planes;
+            Q.x0 = K2.img_x0;
+            Q.y0 = K2.img_y0;
+            Q.sx = K2.img_sx;
+            Q.sy = K2.img_sy;
+            Q.e_unscale = P.e_unscale;
+            const bool hits_out = (outs & SUPA_OUT_HITS) != 0;
+            Q.seg = hits_out ? out->hit_offsets : K2.img_seg;
+            Q.count = K2.img_count;
+            Q.cap = K2.img_cap;
+            Q.x = hits_out ? out->hit_x : K2.img_x;
+            Q.y = hits_out ? out->hit_y : K2.img_y;
+            Q.e = K2.img_e;
+            Q.layer = hits_out ? out->hit_layer : K2.img_layer;
+            Q.layer_plane_start = c->d_layer_plane_start;
+            Q.layer_planes = c->d_layer_planes;
+            Q.images = out->images;
+            HIP_TRY(c, supa::launch_images(Q, c->n_cu, c->stream));
+        }
+        HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_COUNT * sizeof(unsigned long long),
                                   hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
+        HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        float t01 = 0, t02 = 0;
+        float t01 = 0, t12 = 0, t03 = 0;
         (void)hipEventElapsedTime(&t01, c->ev[0], c->ev[1]);
-        (void)hipEventElapsedTime(&t02, c->ev[0], c->ev[2]);
+        (void)hipEventElapsedTime(&t12, c->ev[1], c->ev[2]);
+        (void)hipEventElapsedTime(&t03, c->ev[0], c->ev[3]);
         c->timing[0] = t01;
-        c->timing[1] = 0.f;
-        c->timing[2] = t02;
+        c->timing[1] = images ? t12 : 0.f;
+        c->timing[2] = t03;
 
         const unsigned long long flags = c->h_ctr[supa::CTR_FLAGS];
-        if (flags & supa::FLAG_INTERNAL) {
-            c->broken = true;
-            return fail(c, SUPA_ERR_DEVICE, "internal particle accounting error in the propagation kernel");
-        }
         if (flags & supa::FLAG_RANGE)
             return fail(c, SUPA_ERR_RANGE, "an initial energy is negative, NaN or too large for the fixed-point format");
         if (flags & supa::FLAG_OVERFLOW) {
@@ -446,10 +513,19 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
             c->spill_cap = (int)std::min(cap_max, std::max<int64_t>(c->spill_cap, round_up_pow2(nf + 1)));
             c->cap_h = (int)std::min(cap_max, std::max<int64_t>(c->cap_h, round_up_pow2(nh + 1)));
             c->cap_n = (int)std::min(cap_max, std::max<int64_t>(c->cap_n, round_up_pow2(nn + 2)));
+            if (images && !(outs & SUPA_OUT_HITS))
+                c->img_cap = std::max<int64_t>(c->img_cap, (int64_t)c->h_ctr[supa::CTR_HITS] + 1);
             continue;
+        }
+        // only meaningful when nothing overflowed (a lost spill entry breaks
+        // the particle accounting of its wave, and the batch is rerun anyway)
+        if (flags & supa::FLAG_INTERNAL) {
+            c->broken = true;
+            return fail(c, SUPA_ERR_DEVICE, "internal particle accounting error in the propagation kernel");
         }
         out->total_steps = (int64_t)c->h_ctr[supa::CTR_STEPS];
         out->total_hits = (outs & SUPA_OUT_HITS) ? (int64_t)c->h_ctr[supa::CTR_HITS] : 0;
+        (void)0;
         out->total_nodes = tree ? (int64_t)c->h_ctr[supa::CTR_NODES] : 0;
         if ((outs & SUPA_OUT_HITS) && out->total_hits > out->hit_capacity)
             return fail(c, SUPA_ERR_CAPACITY, "hit arrays too small: need " + std::to_string(out->total_hits));

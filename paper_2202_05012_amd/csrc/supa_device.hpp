@@ -90,6 +90,15 @@ struct Cold {
     int64_t node_capacity;
     uint64_t *ledger;
     int32_t *counts;
+    // hand-over to the image kernel (library scratch): per shower the start and
+    // number of its hits, per hit its integer energy, and its coordinates and
+    // layer when the caller's hit arrays are not written
+    int64_t *img_seg;           // [n] (when hits are not an output)
+    int32_t *img_count;         // [n] hits handed over (0 when they were not written)
+    uint32_t *img_e;            // [img_cap]
+    float *img_x, *img_y;       // [img_cap] (when hits are not an output)
+    int32_t *img_layer;
+    int64_t img_cap;
 };
 
 // Parameters of one simulate call that the hot loop reads, by value.
@@ -121,6 +130,35 @@ struct Params {
     uint32_t *hidx;                           // per wave: cap_h (plane-sorted hit order)
     uint32_t *jn;                             // per wave: SLOTS x JN_COUNT x cap_n
     unsigned long long *ctr;                  // device counters, see CTR_*
+};
+
+// Arguments of the surrogate's matrix product (supa_mlp.hip).
+struct GemmArgs {
+    int M, N, K;
+    const uint16_t *A;   // TA == 0: [M][lda] (row-major M x K); TA == 1: [K][lda] (K x M)
+    const uint16_t *B;   // TB == 0: [K][ldb] (K x N);           TB == 1: [N][ldb] (N x K)
+    int lda, ldb;
+    const float *bias;   // [N] or null
+    void *C;             // float [M][ldc] (EPI_F32, EPI_BIAS_F32) or bf16 [M][ldc]
+    int ldc;
+    uint16_t *pre;       // EPI_BIAS_GELU: pre-activation out; EPI_GELU_GRAD: in (bf16 [M][ldc])
+};
+
+// Parameters of the image kernel (supa_images.hip).
+struct ImgParams {
+    int32_t n, L, nx, ny, n_planes;
+    float x0, y0, sx, sy;        // cell = floor((x - x0) * sx)
+    float e_unscale;             // 2^-s
+    const int64_t *seg;          // [n] first hit of each shower
+    const int32_t *count;        // [n] hits of each shower that were written
+    int64_t cap;                 // entries of x, y, e, layer
+    const float *x, *y;          // hit coordinates
+    const uint32_t *e;           // integer hit energies
+    const int32_t *layer;        // hit layers (-1: not read out)
+    const int32_t *layer_plane_start, *layer_planes;   // planes of each layer (CSR)
+    float *images;               // [n][L][ny][nx]
+    int32_t slab_layers;         // whole layers per slab (0: bands of rows)
+    int32_t slab_rows;           // rows per band when one layer does not fit
 };
 
 enum {

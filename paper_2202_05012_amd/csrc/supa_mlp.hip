@@ -1,0 +1,500 @@
+// supa_mlp.hip -- kernels of the learned surrogate for gfx950.
+//
+// The surrogate is a conditional MLP: initial condition (energy, polar angle,
+// azimuth; the conditioning variables of the paper's section "Extensions")
+// plus Gaussian noise -> hidden layers with GELU -> mean and log-variance of
+// the coarse per-layer deposit images (appendix "Downsampling").  Weights and
+// activations are bfloat16, every product is accumulated in float32 by the
+// matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+//   gemm      C = op(A) op(B) with A, B bf16 and three layouts: NN (forward),
+//             NT (gradient of the input), TN (gradient of the weights); fused
+//             epilogues: bias, bias + GELU (keeping the pre-activation),
+//             multiplication by GELU' of a stored pre-activation.  128x128
+//             tiles per 256-thread workgroup, 64x64 per wave (4x4 MFMA
+//             tiles), K in steps of 32 through LDS.
+//   nll       Gaussian negative log-likelihood of the targets (image / E0)
+//             and its gradient with respect to the outputs.
+//   colsum    bias gradients.
+//   adam      Adam step on float32 master weights, refreshing the bf16 copy.
+//   features  input rows: scaled initial condition and Philox/Box-Muller noise.
+//   gate      per shower: predicted per-layer energies, uncertainty score.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "supa_device.hpp"
+
+namespace supa {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// float -> bfloat16, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float gelu_f(float a) {
+    return 0.5f * a * (1.0f + erff(a * 0.707106781f));
+}
+
+__device__ __forceinline__ float gelu_grad_f(float a) {
+    return 0.5f * (1.0f + erff(a * 0.707106781f)) + a * 0.398942280f * __expf(-0.5f * a * a);
+}
+
+enum { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
+
+constexpr int GT = 128;         // tile edge
+constexpr int GK = 32;          // K step
+constexpr int GPAD = GK + 8;    // LDS row length (bf16), staggers banks
+
+template <int TA, int TB>
+__device__ __forceinline__ void load_tiles(const GemmArgs &g, int m0, int n0, int k0,
+                                           uint16_t (*As)[GPAD], uint16_t (*Bs)[GPAD]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int c = tid + r * 256;     // 512 chunks of 8 bf16 per operand tile
+        // ---- A
+        if (TA == 0) {
+            const int m = c >> 2, kc = (c & 3) * 8;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (m0 + m < g.M && k0 + kc < g.K)
+                v = *(const uint4 *)(g.A + (int64_t)(m0 + m) * g.lda + k0 + kc);
+            *(uint4 *)&As[m][kc] = v;
+        } else {
+            const int k = c >> 4, mc = (c & 15) * 8;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (k0 + k < g.K && m0 + mc < g.M)
+                v = *(const uint4 *)(g.A + (int64_t)(k0 + k) * g.lda + m0 + mc);
+            const uint16_t *e = (const uint16_t *)&v;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) As[mc + q][k] = e[q];
+        }
+        // ---- B
+        if (TB == 1) {
+            const int n = c >> 2, kc = (c & 3) * 8;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (n0 + n < g.N && k0 + kc < g.K)
+                v = *(const uint4 *)(g.B + (int64_t)(n0 + n) * g.ldb + k0 + kc);
+            *(uint4 *)&Bs[n][kc] = v;
+        } else {
+            const int k = c >> 4, nc = (c & 15) * 8;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (k0 + k < g.K && n0 + nc < g.N)
+                v = *(const uint4 *)(g.B + (int64_t)(k0 + k) * g.ldb + n0 + nc);
+            const uint16_t *e = (const uint16_t *)&v;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) Bs[nc + q][k] = e[q];
+        }
+    }
+}
+
+template <int TA, int TB, int EPI>
+__global__ void __launch_bounds__(256) gemm_bf16(GemmArgs g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[GT][GPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[GT][GPAD];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    const int lr = lane & 15, lk = (lane >> 4) * 8;
+
+    floatx4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < g.K; k0 += GK) {
+        load_tiles<TA, TB>(g, m0, n0, k0, As, Bs);
+        __syncthreads();
+        bf16x8_t a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8_t *)&As[wm + i * 16 + lr][lk];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8_t *)&Bs[wn + j * 16 + lr][lk];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+
+    // accumulator element r of tile (i, j): row 4*(lane/16) + r, column lane%16
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+                const int n = n0 + wn + j * 16 + lr;
+                if (m >= g.M || n >= g.N) continue;
+                const int64_t o = (int64_t)m * g.ldc + n;
+                float v = acc[i][j][r];
+                if (EPI == EPI_F32) {
+                    ((float *)g.C)[o] = v;
+                } else if (EPI == EPI_BIAS_F32) {
+                    ((float *)g.C)[o] = v + g.bias[n];
+                } else if (EPI == EPI_BIAS_GELU) {
+                    v += g.bias[n];
+                    g.pre[o] = f2bf(v);
+                    ((uint16_t *)g.C)[o] = f2bf(gelu_f(v));
+                } else {   // EPI_GELU_GRAD
+                    ((uint16_t *)g.C)[o] = f2bf(v * gelu_grad_f(bf2f(g.pre[o])));
+                }
+            }
+}
+
+hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs &g, hipStream_t s) {
+    const dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT), block(256);
+#define SUPA_GEMM_CASE(TA, TB, EPI)                                              \
+    if (ta == TA && tb == TB && epi == EPI) {                                     \
+        hipLaunchKernelGGL((gemm_bf16<TA, TB, EPI>), grid, block, 0, s, g);     \
+        return hipGetLastError();                                                 \
+    }
+    SUPA_GEMM_CASE(0, 0, EPI_F32)
+    SUPA_GEMM_CASE(0, 0, EPI_BIAS_F32)
+    SUPA_GEMM_CASE(0, 0, EPI_BIAS_GELU)
+    SUPA_GEMM_CASE(0, 1, EPI_F32)
+    SUPA_GEMM_CASE(0, 1, EPI_GELU_GRAD)
+    SUPA_GEMM_CASE(1, 0, EPI_F32)
+#undef SUPA_GEMM_CASE
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian NLL over rows b < B and bins j < D: out = [mu | s_raw] (float
+// [B][2D]), target y = img[b][j] * y_scale / e0[b].  Writes d(loss)/d(out)
+// as bf16 (the backward GEMMs' input) and adds the loss sum into *loss.
+// ---------------------------------------------------------------------------
+__global__ void nll_kernel(int B, int D, const float *out, const float *img, const float *e0,
+                           float y_scale, float s_clamp, uint16_t *dout, float *loss) {
+    __shared__ float part[256];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = (int64_t)B * D;
+    const float inv_n = 1.0f / (float)total;
+    float l = 0.0f;
+    for (int64_t q = t; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = q / D, j = q - b * D;
+        const float mu = out[b * 2 * D + j];
+        const float sr = out[b * 2 * D + D + j];
+        const float s = fminf(fmaxf(sr, -s_clamp), s_clamp);
+        const float y = img[b * D + j] * y_scale / e0[b];
+        const float r = y - mu;
+        const float ie = __expf(-s);
+        l += 0.5f * (s + r * r * ie);
+        dout[b * 2 * D + j] = f2bf(-r * ie * inv_n);
+        dout[b * 2 * D + D + j] = f2bf(fabsf(sr) <= s_clamp ? 0.5f * (1.0f - r * r * ie) * inv_n : 0.0f);
+    }
+    part[threadIdx.x] = l;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(loss, part[0]);
+}
+
+// column sums of a bf16 matrix [M][ld] (first N columns) -> float [N]
+__global__ void colsum_kernel(int M, int N, const uint16_t *X, int ld, float *out) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int m = 0; m < M; ++m) s += bf2f(X[(int64_t)m * ld + n]);
+    out[n] = s;
+}
+
+// Adam step (Kingma & Ba 2015) on float32 parameters, bf16 copy refreshed.
+__global__ void adam_kernel(int64_t n, float *p, const float *grad, float *m, float *v,
+                            uint16_t *p_bf16, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const float g = grad[t];
+    const float mm = b1 * m[t] + (1.0f - b1) * g;
+    const float vv = b2 * v[t] + (1.0f - b2) * g * g;
+    m[t] = mm;
+    v[t] = vv;
+    const float w = p[t] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    p[t] = w;
+    if (p_bf16) p_bf16[t] = f2bf(w);
+}
+
+__global__ void to_bf16_kernel(int64_t n, const float *x, uint16_t *y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] = f2bf(x[t]);
+}
+
+// Input rows [B][ld]: e0 * e_scale, polar * polar_scale, azimuth * az_scale,
+// then n_noise standard normals (Box-Muller on Philox words keyed by
+// (seed; row id, stream, 0x5eed, 0)), then zeros up to ld.
+__global__ void features_kernel(int B, int ld, int n_noise, const float *e0, const float *polar,
+                                const float *az, float e_scale, float polar_scale, float az_scale,
+                                uint32_t row_base, uint32_t stream, uint32_t k0, uint32_t k1,
+                                uint16_t *x) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    uint16_t *row = x + (int64_t)b * ld;
+    row[0] = f2bf(e0[b] * e_scale);
+    row[1] = f2bf(polar[b] * polar_scale);
+    row[2] = f2bf(az[b] * az_scale);
+    for (int q = 0; q < n_noise; q += 4) {
+        const uint4 w = philox4x32_10(row_base + (uint32_t)b, stream, 0x5eedu, (uint32_t)q, k0, k1);
+        const float u1 = ((float)w.x + 0.5f) * 0x1p-32f, u2 = ((float)w.y + 0.5f) * 0x1p-32f;
+        const float u3 = ((float)w.z + 0.5f) * 0x1p-32f, u4 = ((float)w.w + 0.5f) * 0x1p-32f;
+        const float r1 = sqrtf(-2.0f * logf(u1)), r2 = sqrtf(-2.0f * logf(u3));
+        float s1, c1, s2, c2;
+        sincospif(2.0f * u2, &s1, &c1);
+        sincospif(2.0f * u4, &s2, &c2);
+        const float z[4] = {r1 * c1, r1 * s1, r2 * c2, r2 * s2};
+        for (int e = 0; e < 4 && q + e < n_noise; ++e) row[3 + q + e] = f2bf(z[e]);
+    }
+    for (int c = 3 + n_noise; c < ld; ++c) row[c] = 0;
+}
+
+// Per shower b: predicted per-layer energies E0 * sum_bins mu (float [B][L]),
+// uncertainty sqrt(sum sigma^2) / max(sum mu, tiny), and optionally the
+// predicted image E0 * mu (float [B][D]).  With rho >= 0 the per-layer
+// energies are samples instead: E0 * (sum mu + sd * z), z standard normal
+// (Box-Muller on Philox words keyed by seed and counted by (row, layer, 0x9a7e, 0)),
+// sd^2 = rho (sum sigma)^2 + (1 - rho) sum sigma^2: bins of a layer with
+// correlation rho.
+__global__ void gate_kernel(int B, int D, int L, const float *out, const float *e0,
+                            float y_scale, float s_clamp, float *layer_e, float *unc,
+                            float *img, float rho, uint32_t row_base, uint32_t k0, uint32_t k1) {
+    const int b = blockIdx.x;
+    const int bins = D / L;
+    __shared__ float sm[256], sv[256];
+    __shared__ float ss[256];
+    const float *row = out + (int64_t)b * 2 * D;
+    const float scale = e0[b] / y_scale;
+    float tm = 0.f, tv = 0.f;
+    for (int l = 0; l < L; ++l) {
+        float pm = 0.f, pv = 0.f, ps = 0.f;
+        for (int j = threadIdx.x; j < bins; j += blockDim.x) {
+            const float mu = row[l * bins + j];
+            const float s = fminf(fmaxf(row[D + l * bins + j], -s_clamp), s_clamp);
+            pm += mu;
+            pv += __expf(s);
+            ps += __expf(0.5f * s);
+            if (img) img[(int64_t)b * D + l * bins + j] = mu * scale;
+        }
+        sm[threadIdx.x] = pm;
+        sv[threadIdx.x] = pv;
+        ss[threadIdx.x] = ps;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) {
+                sm[threadIdx.x] += sm[threadIdx.x + w];
+                sv[threadIdx.x] += sv[threadIdx.x + w];
+                ss[threadIdx.x] += ss[threadIdx.x + w];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            float v = sm[0];
+            if (rho >= 0.0f) {
+                const uint4 w = philox4x32_10(row_base + (uint32_t)b, (uint32_t)l, 0x9a7eu, 0u, k0, k1);
+                const float u1 = ((float)w.x + 0.5f) * 0x1p-32f, u2 = ((float)w.y + 0.5f) * 0x1p-32f;
+                float sn, cs;
+                sincospif(2.0f * u2, &sn, &cs);
+                const float z = sqrtf(-2.0f * logf(u1)) * cs;
+                const float sd = sqrtf(rho * ss[0] * ss[0] + (1.0f - rho) * sv[0]);
+                v += sd * z;
+            }
+            layer_e[(int64_t)b * L + l] = v * scale;
+            tm += sm[0];
+            tv += sv[0];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) unc[b] = sqrtf(tv) / fmaxf(tm, 1e-6f);
+}
+
+hipError_t launch_nll(int B, int D, const float *out, const float *img, const float *e0,
+                      float y_scale, float s_clamp, uint16_t *dout, float *loss, hipStream_t s) {
+    const int64_t total = (int64_t)B * D;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(nll_kernel, dim3(blocks), dim3(256), 0, s, B, D, out, img, e0, y_scale,
+                       s_clamp, dout, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsum(int M, int N, const uint16_t *X, int ld, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, s, M, N, X, ld, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(int64_t n, float *p, const float *g, float *m, float *v, uint16_t *pb,
+                       float lr, float b1, float b2, float eps, int step, hipStream_t s) {
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, p, g, m,
+                       v, pb, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(int64_t n, const float *x, uint16_t *y, hipStream_t s) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_features(int B, int ld, int n_noise, const float *e0, const float *polar,
+                           const float *az, float e_scale, float polar_scale, float az_scale,
+                           uint32_t row_base, uint32_t stream, uint64_t seed, uint16_t *x,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(features_kernel, dim3((B + 127) / 128), dim3(128), 0, s, B, ld, n_noise, e0,
+                       polar, az, e_scale, polar_scale, az_scale, row_base, stream, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), x);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate(int B, int D, int L, const float *out, const float *e0, float y_scale,
+                       float s_clamp, float *layer_e, float *unc, float *img, float rho,
+                       uint32_t row_base, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(gate_kernel, dim3(B), dim3(256), 0, s, B, D, L, out, e0, y_scale, s_clamp,
+                       layer_e, unc, img, rho, row_base, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return hipGetLastError();
+}
+
+}  // namespace supa
+
+namespace supa {
+
+// ---------------------------------------------------------------------------
+// Fallback selection: indices i with v[i] > tau, in increasing order
+// (deterministic): per-block counts, one-block scan of the counts, write.
+// ---------------------------------------------------------------------------
+constexpr int SEL_THREADS = 1024;
+
+__global__ void select_count_kernel(int n, const float *v, float tau, int32_t *block_counts) {
+    const int i = blockIdx.x * SEL_THREADS + threadIdx.x;
+    const bool p = i < n && v[i] > tau;
+    __shared__ int total;
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    const uint64_t m = __ballot(p);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&total, (int)__popcll(m));
+    __syncthreads();
+    if (threadIdx.x == 0) block_counts[blockIdx.x] = total;
+}
+
+__global__ void select_scan_kernel(int blocks, int32_t *block_counts, int32_t *count) {
+    // exclusive scan in place, one thread block of SEL_THREADS, serial over chunks
+    __shared__ int buf[SEL_THREADS];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < blocks; base += SEL_THREADS) {
+        const int i = base + threadIdx.x;
+        const int v = i < blocks ? block_counts[i] : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < SEL_THREADS; off <<= 1) {
+            const int t = (int)threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < blocks) block_counts[i] = carry + buf[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += buf[SEL_THREADS - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *count = carry;
+}
+
+__global__ void select_write_kernel(int n, const float *v, float tau, const int32_t *block_offsets,
+                                    int32_t *idx) {
+    const int i = blockIdx.x * SEL_THREADS + threadIdx.x;
+    const bool p = i < n && v[i] > tau;
+    __shared__ int wave_base[SEL_THREADS / 64];
+    const uint64_t m = __ballot(p);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) wave_base[w] = (int)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int q = 0; q < SEL_THREADS / 64; ++q) {
+            const int c = wave_base[q];
+            wave_base[q] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    if (p) idx[block_offsets[blockIdx.x] + wave_base[w] + (int)lanes_below(m)] = i;
+}
+
+// gather float arrays by index: out_k[j] = in_k[idx[j]] for three arrays
+__global__ void gather3_kernel(int m, const int32_t *idx, const float *a, const float *b,
+                               const float *c, float *oa, float *ob, float *oc) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m) return;
+    const int i = idx[j];
+    oa[j] = a[i];
+    ob[j] = b[i];
+    oc[j] = c[i];
+}
+
+// rows: dst[idx[j]][0..w) = src[j][0..w)
+__global__ void scatter_rows_kernel(int m, int w, const int32_t *idx, const float *src, float *dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)m * w) return;
+    const int j = (int)(t / w), c = (int)(t - (int64_t)j * w);
+    dst[(int64_t)idx[j] * w + c] = src[t];
+}
+
+// per-row sums of groups: out[b][l] = sum_{q < g} x[b][l*g + q]
+__global__ void group_sums_kernel(int rows, int L, int g, const float *x, float *out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rows * L) return;
+    const float *p = x + t * g;
+    float s = 0.f;
+    for (int q = 0; q < g; ++q) s += p[q];
+    out[t] = s;
+}
+
+hipError_t launch_select(int n, const float *v, float tau, int32_t *idx, int32_t *count,
+                         int32_t *block_scratch, hipStream_t s) {
+    const int blocks = (n + SEL_THREADS - 1) / SEL_THREADS;
+    if (blocks == 0) {
+        hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(SEL_THREADS), 0, s, 0, block_scratch, count);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(select_count_kernel, dim3(blocks), dim3(SEL_THREADS), 0, s, n, v, tau, block_scratch);
+    hipLaunchKernelGGL(select_scan_kernel, dim3(1), dim3(SEL_THREADS), 0, s, blocks, block_scratch, count);
+    hipLaunchKernelGGL(select_write_kernel, dim3(blocks), dim3(SEL_THREADS), 0, s, n, v, tau,
+                       block_scratch, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather3(int m, const int32_t *idx, const float *a, const float *b, const float *c,
+                          float *oa, float *ob, float *oc, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather3_kernel, dim3((m + 255) / 256), dim3(256), 0, s, m, idx, a, b, c, oa, ob, oc);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(int m, int w, const int32_t *idx, const float *src, float *dst,
+                               hipStream_t s) {
+    const int64_t t = (int64_t)m * w;
+    if (t <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_rows_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, m, w,
+                       idx, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_sums(int rows, int L, int g, const float *x, float *out, hipStream_t s) {
+    const int64_t t = (int64_t)rows * L;
+    if (t <= 0) return hipSuccess;
+    hipLaunchKernelGGL(group_sums_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, rows, L,
+                       g, x, out);
+    return hipGetLastError();
+}
+
+}  // namespace supa

@@ -16,10 +16,11 @@
 //      three-way choice, split kinematics; daughters go back to the pool.
 // Hits and tree nodes are appended to per-shower journals (positions from a
 // wave ballot and a count of the set lanes below, per shower slot).  When a
-// shower's last particle is done, the wave sorts its hits by plane (counting
-// sort in LDS), copies them into the caller's arrays at a segment reserved
-// with one atomic, bins the per-layer images in an LDS tile (integer sums, so
-// the order of the atomics does not matter) and writes the ledger and counts.
+// shower's last particle is done, the wave sorts its hits by plane (a
+// counting sort on per-plane counts kept in LDS), copies them into the
+// caller's arrays at a segment reserved with one atomic, and writes the
+// ledger and counts; per-layer images are binned afterwards by the image
+// kernel (supa_images.hip) from the plane-sorted hits.
 // Results depend only on (seed, shower id, path id): the random stream is
 // keyed by the particle, not by the lane or wave that happens to process it.
 #include "supa_device.hpp"
@@ -170,9 +171,10 @@ __device__ __forceinline__ int wave_excl_scan(int v) {
     return incl - v;
 }
 
-// LDS words of one wave: pool + draw queue + per-plane tables + histogram + tile
-__host__ __device__ constexpr int lds_words(int pool_cap, int tile_words) {
-    return POOL_FIELDS * pool_cap + POOL_FIELDS * QCAP + 2 * 2 * 64 + 64 + 64 + tile_words;
+// LDS words of one wave: pool + draw queue + per-plane tables + per-shower
+// plane histograms of the hits
+__host__ __device__ constexpr int lds_words(int pool_cap) {
+    return POOL_FIELDS * pool_cap + POOL_FIELDS * QCAP + 2 * 2 * 64 + 64 + SLOTS * 64;
 }
 
 // Keeps a wave-uniform value in scalar registers but hides it from loop-
@@ -195,21 +197,21 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
     uint32_t *const queue = pool + POOL_FIELDS * PC;           // [POOL_FIELDS][QCAP]
     uint64_t *const thr = (uint64_t *)(queue + POOL_FIELDS * QCAP);  // c1[64], c2[64]
     int32_t *const lay = (int32_t *)(thr + 128);               // layer of each plane
-    uint32_t *const hist = (uint32_t *)(lay + 64);             // per-plane counters
-    uint32_t *const tile = hist + 64;
+    uint32_t *const shist = (uint32_t *)(lay + 64);            // [SLOTS][64] hits per plane
 
     for (int k = (int)lane; k < 64; k += WAVE) {
         thr[k] = k < N ? P.c1[k] : 0ull;
         thr[64 + k] = k < N ? P.c2[k] : 0ull;
         lay[k] = k < N ? P.layer[k] : -1;
     }
+    for (int q = (int)lane; q < SLOTS * 64; q += WAVE) shist[q] = 0u;
 
     const int64_t G = P.spill_cap, cap_h = P.cap_h, cap_n = P.cap_n;
     uint32_t *const spill = P.spill + wave * POOL_FIELDS * G;
     uint32_t *const jh_w = P.jh + wave * (int64_t)SLOTS * JH_COUNT * cap_h;
-    uint32_t *const hidx = P.hidx + wave * cap_h;
     uint32_t *const jn_w = TREE ? P.jn + wave * (int64_t)SLOTS * JN_COUNT * cap_n : nullptr;
     const bool keys = P.keys;
+    const bool want_xy = (P.outputs & 3u) != 0;     // hit clouds or images need positions
 
     Slots S;
     S.i = -1;
@@ -257,6 +259,7 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                     for (int q = 0; q < 4; ++q) COLD(ledger)[4 * (int64_t)i + q] = 0;
                     for (int q = 0; q < 6; ++q) COLD(counts)[6 * (int64_t)i + q] = 0;
                 }
+                if ((P.outputs & 2u) && lane == 0) COLD(img_count)[i] = 0;
                 continue;
             }
             const uint32_t e_first = (uint32_t)rintf(sc);
@@ -332,13 +335,18 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                     if ((int)lane == s0) S.live -= (int)__popcll(m);
                 });
                 if (is_stop) {
+                    atomicAdd(&shist[slot * 64 + k], 1u);
                     if (pos < cap_h) {
                         uint32_t *jh = jh_w + (int64_t)slot * JH_COUNT * cap_h;
-                        jh[JH_X * cap_h + pos] = __float_as_uint(p.x);
-                        jh[JH_Y * cap_h + pos] = __float_as_uint(p.y);
+                        if (want_xy) {
+                            jh[JH_X * cap_h + pos] = __float_as_uint(p.x);
+                            jh[JH_Y * cap_h + pos] = __float_as_uint(p.y);
+                        }
                         jh[JH_E * cap_h + pos] = p.e;
-                        jh[JH_LO * cap_h + pos] = p.lo;
-                        jh[JH_HI * cap_h + pos] = p.hi;
+                        if (keys) {
+                            jh[JH_LO * cap_h + pos] = p.lo;
+                            jh[JH_HI * cap_h + pos] = p.hi;
+                        }
                         jh[JH_PK * cap_h + pos] = (uint32_t)k | KIND_STOP;
                     } else {
                         overflow = true;
@@ -474,13 +482,18 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                     }
                 });
                 if (is_cut) {
+                    atomicAdd(&shist[slot * 64 + k], 1u);
                     if (hpos < cap_h) {
                         uint32_t *jh = jh_w + (int64_t)slot * JH_COUNT * cap_h;
-                        jh[JH_X * cap_h + hpos] = __float_as_uint(p.x);
-                        jh[JH_Y * cap_h + hpos] = __float_as_uint(p.y);
+                        if (want_xy) {
+                            jh[JH_X * cap_h + hpos] = __float_as_uint(p.x);
+                            jh[JH_Y * cap_h + hpos] = __float_as_uint(p.y);
+                        }
                         jh[JH_E * cap_h + hpos] = p.e;
-                        jh[JH_LO * cap_h + hpos] = p.lo;
-                        jh[JH_HI * cap_h + hpos] = p.hi;
+                        if (keys) {
+                            jh[JH_LO * cap_h + hpos] = p.lo;
+                            jh[JH_HI * cap_h + hpos] = p.hi;
+                        }
                         jh[JH_PK * cap_h + hpos] = (uint32_t)k;
                     } else {
                         overflow = true;
@@ -516,25 +529,98 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             uint32_t *const jh = jh_w + (int64_t)s * JH_COUNT * cap_h;
             __threadfence_block();      // journal entries written by every lane
 
-            // counting sort of the hits by plane
-            hist[lane] = 0u;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            uint64_t e_stop = 0, e_cut = 0;
-            const int nread = sh_over ? 0 : nh;
-            for (int j = (int)lane; j < nread; j += WAVE) {
-                const uint32_t pk = jh[JH_PK * cap_h + j];
-                const uint32_t e = jh[JH_E * cap_h + j];
-                atomicAdd(&hist[pk & 63u], 1u);
-                if (pk & KIND_STOP) e_stop += e; else e_cut += e;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            // counting sort of the hits by plane: the per-plane counts were
+            // kept in LDS while the shower ran
+            uint32_t *const hist = shist + s * 64;
             const int plane_start = wave_excl_scan((int)hist[lane]);   // lane k: first hit of plane k
             hist[lane] = (uint32_t)plane_start;
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            e_stop = wave_sum_u64(e_stop);
-            e_cut = wave_sum_u64(e_cut);
 
             long long hit_start = 0, node_start = 0;
+            if (lane == 0) {
+                if (P.outputs & 3u)
+                    hit_start = (long long)atomicAdd(&P.ctr[CTR_HITS], (unsigned long long)nh);
+                if (TREE)
+                    node_start = (long long)atomicAdd(&P.ctr[CTR_NODES], (unsigned long long)nn);
+                atomicAdd(&P.ctr[CTR_STEPS], (unsigned long long)(nh + nsplit + npass));
+                atomicMax(&P.ctr[CTR_NEED_F], (unsigned long long)max_top);
+                atomicMax(&P.ctr[CTR_NEED_H], (unsigned long long)nh);
+                atomicMax(&P.ctr[CTR_NEED_N], (unsigned long long)nn);
+                if (sh_over) atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_OVERFLOW);
+            }
+            hit_start = __shfl(hit_start, 0, WAVE);
+            node_start = __shfl(node_start, 0, WAVE);
+            const bool out_hits = (P.outputs & 1u) != 0, out_img = (P.outputs & 2u) != 0;
+            const bool write_hits = !sh_over && out_hits && hit_start + nh <= COLD(hit_capacity);
+            const bool write_img = !sh_over && out_img && hit_start + nh <= COLD(img_cap);
+            // library-owned hand-over buffer too small: grow and rerun (when the
+            // caller's hit arrays are the hand-over, the call reports CAPACITY)
+            if (out_img && !out_hits && !write_img && lane == 0)
+                atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_OVERFLOW);
+            if (lane == 0) {
+                if (out_hits) COLD(hit_offsets)[i] = hit_start;
+                if (out_img && !out_hits) COLD(img_seg)[i] = hit_start;
+            }
+            // the image kernel reads exactly this many hits of the shower: none
+            // when they could not be handed over (arrays too small, overflow)
+            if (out_img && lane == 0) COLD(img_count)[i] = write_img ? nh : 0;
+
+            // hit cloud in plane order (and the image kernel's copy), two
+            // journal entries per lane in flight
+            float *const hx = COLD(hit_x), *const hy = COLD(hit_y), *const he = COLD(hit_e);
+            int32_t *const hl = COLD(hit_layer);
+            uint64_t *const hk = COLD(hit_key);
+            uint32_t *const ie = COLD(img_e);
+            float *const ix = COLD(img_x), *const iy = COLD(img_y);
+            int32_t *const il = COLD(img_layer);
+            uint64_t e_stop = 0, e_cut = 0;
+            const int nread = sh_over ? 0 : nh;
+            for (int j0 = (int)lane; j0 < nread; j0 += 2 * WAVE) {
+                uint32_t pk[2], e[2], xb[2] = {0u, 0u}, yb[2] = {0u, 0u}, lo2[2] = {0u, 0u}, hi2[2] = {0u, 0u};
+                bool ok[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int j = j0 + u * WAVE;
+                    ok[u] = j < nread;
+                    const int jj = ok[u] ? j : j0;
+                    pk[u] = jh[JH_PK * cap_h + jj];
+                    e[u] = jh[JH_E * cap_h + jj];
+                    if (want_xy) {
+                        xb[u] = jh[JH_X * cap_h + jj];
+                        yb[u] = jh[JH_Y * cap_h + jj];
+                    }
+                    if (keys) {
+                        lo2[u] = jh[JH_LO * cap_h + jj];
+                        hi2[u] = jh[JH_HI * cap_h + jj];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    if (!ok[u]) continue;
+                    if (pk[u] & KIND_STOP) e_stop += e[u]; else e_cut += e[u];
+                    const int q = (int)atomicAdd(&hist[pk[u] & 63u], 1u);
+                    const int64_t o = hit_start + q;
+                    const int layer = lay[pk[u] & 63u];
+                    if (write_hits) {
+                        hx[o] = __uint_as_float(xb[u]);
+                        hy[o] = __uint_as_float(yb[u]);
+                        he[o] = (float)e[u] * P.e_unscale;
+                        hl[o] = layer;
+                        if (keys) hk[o] = ((uint64_t)hi2[u] << 32) | lo2[u];
+                    }
+                    if (write_img) {
+                        ie[o] = e[u];
+                        if (!out_hits) {
+                            ix[o] = __uint_as_float(xb[u]);
+                            iy[o] = __uint_as_float(yb[u]);
+                            il[o] = layer;
+                        }
+                    }
+                }
+            }
+            e_stop = wave_sum_u64(e_stop);
+            e_cut = wave_sum_u64(e_cut);
+            hist[lane] = 0u;                 // ready for the slot's next shower
             if (lane == 0) {
                 int64_t *led = (int64_t *)COLD(ledger) + 4 * (int64_t)i;
                 led[0] = e_first;
@@ -548,44 +634,11 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                 cnt[3] = nsplit;
                 cnt[4] = nesc;
                 cnt[5] = nback;
-                atomicAdd(&P.ctr[CTR_STEPS], (unsigned long long)(nh + nsplit + npass));
-                if (P.outputs & 1u)
-                    hit_start = (long long)atomicAdd(&P.ctr[CTR_HITS], (unsigned long long)nh);
-                if (TREE)
-                    node_start = (long long)atomicAdd(&P.ctr[CTR_NODES], (unsigned long long)nn);
-                atomicMax(&P.ctr[CTR_NEED_F], (unsigned long long)max_top);
-                atomicMax(&P.ctr[CTR_NEED_H], (unsigned long long)nh);
-                atomicMax(&P.ctr[CTR_NEED_N], (unsigned long long)nn);
-                if (sh_over) atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_OVERFLOW);
             }
             if ((int)lane == s) S.i = -1;
-            if (sh_over) continue;
-            hit_start = __shfl(hit_start, 0, WAVE);
-            node_start = __shfl(node_start, 0, WAVE);
-            const bool write_hits = (P.outputs & 1u) && hit_start + nh <= COLD(hit_capacity);
-            if ((P.outputs & 1u) && lane == 0) COLD(hit_offsets)[i] = hit_start;
-
-            // hit cloud in plane order; hidx keeps the order for the images
-            float *const hx = COLD(hit_x), *const hy = COLD(hit_y), *const he = COLD(hit_e);
-            int32_t *const hl = COLD(hit_layer);
-            uint64_t *const hk = COLD(hit_key);
-            for (int j = (int)lane; j < nh; j += WAVE) {
-                const uint32_t pk = jh[JH_PK * cap_h + j];
-                const int q = (int)atomicAdd(&hist[pk & 63u], 1u);
-                hidx[q] = (uint32_t)j;
-                if (write_hits) {
-                    const int64_t o = hit_start + q;
-                    hx[o] = __uint_as_float(jh[JH_X * cap_h + j]);
-                    hy[o] = __uint_as_float(jh[JH_Y * cap_h + j]);
-                    he[o] = (float)jh[JH_E * cap_h + j] * P.e_unscale;
-                    hl[o] = lay[pk & 63u];
-                    if (keys) hk[o] = ((uint64_t)jh[JH_HI * cap_h + j] << 32) | jh[JH_LO * cap_h + j];
-                }
-            }
-            __threadfence_block();
 
             // propagation tree
-            if (TREE) {
+            if (TREE && !sh_over) {
                 if (lane == 0) COLD(node_offsets)[i] = node_start;
                 if (node_start + nn <= COLD(node_capacity)) {
                     const uint32_t *jn = jn_w + (int64_t)s * JN_COUNT * cap_n;
@@ -602,55 +655,6 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                         nvz[o] = __uint_as_float(jn[JN_Z * cap_n + j]);
                         ne[o] = (float)jn[JN_E * cap_n + j] * P.e_unscale;
                         if (keys) nk[o] = ((uint64_t)jn[JN_HI * cap_n + j] << 32) | jn[JN_LO * cap_n + j];
-                    }
-                }
-            }
-
-            // per-layer images (appendix "Downsampling"): integer sums per cell
-            if (P.outputs & 2u) {
-                const int nx = COLD(img_nx), ny = COLD(img_ny), rows = COLD(img_rows);
-                const int L = COLD(n_layers);
-                const float ix0 = COLD(img_x0), iy0 = COLD(img_y0);
-                const float isx = COLD(img_sx), isy = COLD(img_sy);
-                const int32_t *lps = COLD(layer_plane_start), *lpl = COLD(layer_planes);
-                const int64_t img_layer = (int64_t)ny * nx;
-                float *const images = COLD(images);
-                for (int l = 0; l < L; ++l) {
-                    float *img = images + ((int64_t)i * L + l) * img_layer;
-                    const int lp0 = lps[l], lp1 = lps[l + 1];
-                    for (int r0 = 0; r0 < ny; r0 += rows) {
-                        const int nr = min(ny - r0, rows);
-                        const int words = nr * nx;
-                        for (int q = (int)lane; q < words; q += WAVE) tile[q] = 0u;
-                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                        for (int t = lp0; t < lp1; ++t) {
-                            const int k = lpl[t];
-                            const int hs = __shfl(plane_start, k, WAVE);
-                            const int he2 = __shfl(plane_start, k + 1, WAVE);
-                            for (int q = hs + (int)lane; q < he2; q += WAVE) {
-                                const uint32_t j = hidx[q];
-                                const float cx = floorf((__uint_as_float(jh[JH_X * cap_h + j]) - ix0) * isx);
-                                const float cy = floorf((__uint_as_float(jh[JH_Y * cap_h + j]) - iy0) * isy);
-                                if (cx >= 0.0f && cx < (float)nx && cy >= (float)r0 &&
-                                    cy < (float)(r0 + nr))
-                                    atomicAdd(&tile[((int)cy - r0) * nx + (int)cx], jh[JH_E * cap_h + j]);
-                            }
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                        float *dst = img + (int64_t)r0 * nx;
-                        if ((words & 3) == 0 && (((uintptr_t)dst) & 15) == 0) {
-                            for (int q = 4 * (int)lane; q < words; q += 4 * WAVE) {
-                                const float4 v = make_float4((float)tile[q] * P.e_unscale,
-                                                             (float)tile[q + 1] * P.e_unscale,
-                                                             (float)tile[q + 2] * P.e_unscale,
-                                                             (float)tile[q + 3] * P.e_unscale);
-                                *(float4 *)(dst + q) = v;
-                            }
-                        } else {
-                            for (int q = (int)lane; q < words; q += WAVE)
-                                dst[q] = (float)tile[q] * P.e_unscale;
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     }
                 }
             }
@@ -682,8 +686,8 @@ hipError_t launch_zero_counters(unsigned long long *ctr, hipStream_t s) {
     return hipGetLastError();
 }
 
-size_t propagate_lds_bytes(int pool_cap, int tile_words) {
-    return (size_t)lds_words(pool_cap, tile_words) * 4;
+size_t propagate_lds_bytes(int pool_cap) {
+    return (size_t)lds_words(pool_cap) * 4;
 }
 
 template <bool TREE>
@@ -699,7 +703,7 @@ static hipError_t launch_pc(const Params &P, int blocks, size_t lds, hipStream_t
 }
 
 hipError_t launch_propagate(const Params &P, int blocks, hipStream_t s) {
-    const size_t lds = propagate_lds_bytes(P.pool_cap, P.tile_words);
+    const size_t lds = propagate_lds_bytes(P.pool_cap);
     return (P.outputs & 4u) ? launch_pc<true>(P, blocks, lds, s) : launch_pc<false>(P, blocks, lds, s);
 }
 

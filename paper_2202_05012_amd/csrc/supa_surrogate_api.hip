@@ -1,0 +1,138 @@
+// supa_surrogate_api.hip -- C ABI of include/supa_surrogate.h: argument
+// checks on the host, then the kernels of supa_mlp.hip on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/supa_surrogate.h"
+#include "supa_device.hpp"
+
+namespace supa {
+hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs &g, hipStream_t s);
+hipError_t launch_nll(int B, int D, const float *out, const float *img, const float *e0,
+                      float y_scale, float s_clamp, uint16_t *dout, float *loss, hipStream_t s);
+hipError_t launch_colsum(int M, int N, const uint16_t *X, int ld, float *out, hipStream_t s);
+hipError_t launch_adam(int64_t n, float *p, const float *g, float *m, float *v, uint16_t *pb,
+                       float lr, float b1, float b2, float eps, int step, hipStream_t s);
+hipError_t launch_to_bf16(int64_t n, const float *x, uint16_t *y, hipStream_t s);
+hipError_t launch_features(int B, int ld, int n_noise, const float *e0, const float *polar,
+                           const float *az, float e_scale, float polar_scale, float az_scale,
+                           uint32_t row_base, uint32_t stream, uint64_t seed, uint16_t *x,
+                           hipStream_t s);
+hipError_t launch_gate(int B, int D, int L, const float *out, const float *e0, float y_scale,
+                       float s_clamp, float *layer_e, float *unc, float *img, float rho,
+                       uint32_t row_base, uint64_t seed, hipStream_t s);
+hipError_t launch_select(int n, const float *v, float tau, int32_t *idx, int32_t *count,
+                         int32_t *block_scratch, hipStream_t s);
+hipError_t launch_gather3(int m, const int32_t *idx, const float *a, const float *b, const float *c,
+                          float *oa, float *ob, float *oc, hipStream_t s);
+hipError_t launch_scatter_rows(int m, int w, const int32_t *idx, const float *src, float *dst,
+                               hipStream_t s);
+hipError_t launch_group_sums(int rows, int L, int g, const float *x, float *out, hipStream_t s);
+}  // namespace supa
+
+static thread_local std::string t_err;
+
+static supa_status bad(const char *msg) {
+    t_err = msg;
+    return SUPA_ERR_INVALID_ARG;
+}
+
+static supa_status dev(hipError_t e, const char *what) {
+    if (e == hipSuccess) return SUPA_OK;
+    t_err = std::string(what) + ": " + hipGetErrorString(e);
+    return SUPA_ERR_DEVICE;
+}
+
+extern "C" const char *supa_surrogate_last_error(void) { return t_err.c_str(); }
+
+extern "C" supa_status supa_gemm_bf16(void *stream, int trans_a, int trans_b, int epilogue, int M,
+                                      int N, int K, const uint16_t *A, int lda, const uint16_t *B,
+                                      int ldb, const float *bias, void *C, int ldc, uint16_t *pre) {
+    if (M < 1 || N < 1 || K < 1 || (M | N | K) % 8 != 0) return bad("M, N, K must be positive multiples of 8");
+    if (lda % 8 || ldb % 8 || ldc < N || lda < 1 || ldb < 1) return bad("bad leading dimensions");
+    if (lda < (trans_a ? M : K) || ldb < (trans_b ? K : N)) return bad("leading dimension too small");
+    if (!A || !B || !C) return bad("NULL matrix");
+    const bool ok = (trans_a == 0 && trans_b == 0 &&
+                     (epilogue == SUPA_EPI_F32 || epilogue == SUPA_EPI_BIAS_F32 || epilogue == SUPA_EPI_BIAS_GELU)) ||
+                    (trans_a == 0 && trans_b == 1 && (epilogue == SUPA_EPI_F32 || epilogue == SUPA_EPI_GELU_GRAD)) ||
+                    (trans_a == 1 && trans_b == 0 && epilogue == SUPA_EPI_F32);
+    if (!ok) return bad("unsupported layout / epilogue combination");
+    if ((epilogue == SUPA_EPI_BIAS_F32 || epilogue == SUPA_EPI_BIAS_GELU) && !bias) return bad("bias is NULL");
+    if ((epilogue == SUPA_EPI_BIAS_GELU || epilogue == SUPA_EPI_GELU_GRAD) && !pre) return bad("pre is NULL");
+    supa::GemmArgs g{M, N, K, A, B, lda, ldb, bias, C, ldc, pre};
+    return dev(supa::launch_gemm(trans_a, trans_b, epilogue, g, (hipStream_t)stream), "gemm");
+}
+
+extern "C" supa_status supa_nll_grad(void *stream, int B, int D, const float *out, const float *img,
+                                     const float *e0, float y_scale, float s_clamp, uint16_t *dout,
+                                     float *loss) {
+    if (B < 1 || D < 1) return bad("B and D must be positive");
+    if (!out || !img || !e0 || !dout || !loss) return bad("NULL pointer");
+    if (!(s_clamp > 0)) return bad("s_clamp must be positive");
+    return dev(supa::launch_nll(B, D, out, img, e0, y_scale, s_clamp, dout, loss, (hipStream_t)stream), "nll");
+}
+
+extern "C" supa_status supa_colsum_bf16(void *stream, int M, int N, const uint16_t *X, int ld, float *out) {
+    if (M < 1 || N < 1 || ld < N || !X || !out) return bad("bad colsum arguments");
+    return dev(supa::launch_colsum(M, N, X, ld, out, (hipStream_t)stream), "colsum");
+}
+
+extern "C" supa_status supa_adam(void *stream, int64_t n, float *p, const float *g, float *m, float *v,
+                                 uint16_t *p_bf16, float lr, float beta1, float beta2, float eps, int step) {
+    if (n < 0 || step < 1 || !p || !g || !m || !v) return bad("bad adam arguments");
+    if (n == 0) return SUPA_OK;
+    return dev(supa::launch_adam(n, p, g, m, v, p_bf16, lr, beta1, beta2, eps, step, (hipStream_t)stream), "adam");
+}
+
+extern "C" supa_status supa_to_bf16(void *stream, int64_t n, const float *x, uint16_t *y) {
+    if (n < 0 || (n > 0 && (!x || !y))) return bad("bad to_bf16 arguments");
+    if (n == 0) return SUPA_OK;
+    return dev(supa::launch_to_bf16(n, x, y, (hipStream_t)stream), "to_bf16");
+}
+
+extern "C" supa_status supa_surrogate_features(void *stream, int B, int ld, int n_noise, const float *e0,
+                                               const float *polar, const float *azimuth, float e_scale,
+                                               float polar_scale, float az_scale, uint32_t row_base,
+                                               uint32_t stream_id, uint64_t seed, uint16_t *x) {
+    if (B < 0 || n_noise < 0 || ld % 8 || 3 + n_noise > ld) return bad("bad feature sizes");
+    if (B == 0) return SUPA_OK;
+    if (!e0 || !polar || !azimuth || !x) return bad("NULL pointer");
+    return dev(supa::launch_features(B, ld, n_noise, e0, polar, azimuth, e_scale, polar_scale, az_scale,
+                                     row_base, stream_id, seed, x, (hipStream_t)stream), "features");
+}
+
+extern "C" supa_status supa_surrogate_gate(void *stream, int B, int D, int L, const float *out,
+                                           const float *e0, float y_scale, float s_clamp, float *layer_e,
+                                           float *unc, float *img, float rho, uint32_t row_base,
+                                           uint64_t seed) {
+    if (B < 0 || L < 1 || D < L || D % L) return bad("bad gate sizes");
+    if (rho > 1.0f) return bad("rho must be <= 1 (negative: no sampling)");
+    if (B == 0) return SUPA_OK;
+    if (!out || !e0 || !layer_e || !unc) return bad("NULL pointer");
+    return dev(supa::launch_gate(B, D, L, out, e0, y_scale, s_clamp, layer_e, unc, img, rho, row_base,
+                                 seed, (hipStream_t)stream), "gate");
+}
+
+extern "C" supa_status supa_select_above(void *stream, int n, const float *v, float tau, int32_t *idx,
+                                         int32_t *count, int32_t *block_scratch) {
+    if (n < 0 || !count || !block_scratch || (n > 0 && (!v || !idx))) return bad("bad select arguments");
+    return dev(supa::launch_select(n, v, tau, idx, count, block_scratch, (hipStream_t)stream), "select");
+}
+
+extern "C" supa_status supa_gather3(void *stream, int m, const int32_t *idx, const float *a, const float *b,
+                                    const float *c, float *oa, float *ob, float *oc) {
+    if (m < 0 || (m > 0 && (!idx || !a || !b || !c || !oa || !ob || !oc))) return bad("bad gather arguments");
+    return dev(supa::launch_gather3(m, idx, a, b, c, oa, ob, oc, (hipStream_t)stream), "gather3");
+}
+
+extern "C" supa_status supa_scatter_rows(void *stream, int m, int w, const int32_t *idx, const float *src,
+                                         float *dst) {
+    if (m < 0 || w < 0 || (m > 0 && w > 0 && (!idx || !src || !dst))) return bad("bad scatter arguments");
+    return dev(supa::launch_scatter_rows(m, w, idx, src, dst, (hipStream_t)stream), "scatter_rows");
+}
+
+extern "C" supa_status supa_group_sums(void *stream, int rows, int L, int g, const float *x, float *out) {
+    if (rows < 0 || L < 1 || g < 1 || (rows > 0 && (!x || !out))) return bad("bad group_sums arguments");
+    return dev(supa::launch_group_sums(rows, L, g, x, out, (hipStream_t)stream), "group_sums");
+}

@@ -1,0 +1,247 @@
+"""Learned surrogate: conditional MLP trained on simulated showers, with an
+uncertainty gate that sends doubtful showers back to the simulator.
+
+Argument marshalling over the C ABI of include/supa_surrogate.h: every
+product, activation, loss, gradient, optimiser step, noise draw, gate and
+compaction runs in the library's HIP kernels; PyTorch only holds device memory.
+
+Model (the reading of the extension, not part of the paper): inputs
+(E0 / 100, polar / 15 deg, azimuth / 2 pi) and 16 standard normals, four
+hidden layers of 256 with GELU, output 2 * D with D = 20 layers x 16 x 16:
+mean and log-variance of the per-bin deposit fraction y = image / E0.
+Trained with the Gaussian negative log-likelihood and Adam.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from . import supa
+
+IN_FEATURES = 3
+N_NOISE = 16
+IN_PAD = 32                 # input row length (multiple of 32 for the matrix cores)
+S_CLAMP = 20.0
+Y_SCALE = 1.0               # targets are image / E0
+
+
+def _lib():
+    L = supa.load()
+    if not hasattr(L, "_surrogate_bound"):
+        vp, i, i64, f, u32, u64 = C.c_void_p, C.c_int, C.c_int64, C.c_float, C.c_uint32, C.c_uint64
+        sig = {
+            "supa_gemm_bf16": [vp, i, i, i, i, i, i, vp, i, vp, i, vp, vp, i, vp],
+            "supa_nll_grad": [vp, i, i, vp, vp, vp, f, f, vp, vp],
+            "supa_colsum_bf16": [vp, i, i, vp, i, vp],
+            "supa_adam": [vp, i64, vp, vp, vp, vp, vp, f, f, f, f, i],
+            "supa_to_bf16": [vp, i64, vp, vp],
+            "supa_surrogate_features": [vp, i, i, i, vp, vp, vp, f, f, f, u32, u32, u64, vp],
+            "supa_surrogate_gate": [vp, i, i, i, vp, vp, f, f, vp, vp, vp, f, u32, u64],
+            "supa_select_above": [vp, i, vp, f, vp, vp, vp],
+            "supa_gather3": [vp, i, vp, vp, vp, vp, vp, vp, vp],
+            "supa_scatter_rows": [vp, i, i, vp, vp, vp],
+            "supa_group_sums": [vp, i, i, i, vp, vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.restype = C.c_int
+            fn.argtypes = args
+        L.supa_surrogate_last_error.restype = C.c_char_p
+        L._surrogate_bound = True
+    return L
+
+
+def _check(st):
+    if st != 0:
+        raise supa.SupaError(st, _lib().supa_surrogate_last_error().decode())
+
+
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ---------------------------------------------------------------------------
+# thin wrappers, one per entry point
+# ---------------------------------------------------------------------------
+def gemm(A, B, C_out, trans_a=0, trans_b=0, epilogue=0, bias=None, pre=None, M=None, N=None,
+         K=None):
+    """C = op(A) op(B) on bf16 (int16-typed) tensors; see supa_surrogate.h."""
+    M = M if M is not None else (A.shape[1] if trans_a else A.shape[0])
+    K = K if K is not None else (A.shape[0] if trans_a else A.shape[1])
+    N = N if N is not None else (B.shape[0] if trans_b else B.shape[1])
+    _check(_lib().supa_gemm_bf16(_stream(), trans_a, trans_b, epilogue, M, N, K, _p(A), A.stride(0),
+                                 _p(B), B.stride(0), _p(bias), _p(C_out), C_out.stride(0), _p(pre)))
+
+
+def to_bf16(x: torch.Tensor) -> torch.Tensor:
+    """float32 tensor -> bf16 bit patterns (int16 tensor) via the library."""
+    x = x.contiguous()
+    y = torch.empty(x.shape, dtype=torch.int16, device=x.device)
+    _check(_lib().supa_to_bf16(_stream(), x.numel(), _p(x), _p(y)))
+    return y
+
+
+def bf16_to_float(y: torch.Tensor) -> torch.Tensor:
+    """bf16 bit patterns -> float32 values (exact; a reinterpretation)."""
+    return (y.to(torch.int32) << 16).view(torch.float32)
+
+
+def features(e0, polar, az, seed, row_base=0, stream_id=0):
+    B = int(e0.shape[0])
+    x = torch.empty((B, IN_PAD), dtype=torch.int16, device=e0.device)
+    _check(_lib().supa_surrogate_features(_stream(), B, IN_PAD, N_NOISE, _p(e0), _p(polar), _p(az),
+                                          1.0 / 100.0, 1.0 / math.radians(15.0), 1.0 / (2 * math.pi),
+                                          row_base & 0xFFFFFFFF, stream_id & 0xFFFFFFFF,
+                                          seed & 0xFFFFFFFFFFFFFFFF, _p(x)))
+    return x
+
+
+def gate(out, e0, n_layers, want_image=False, rho=-1.0, seed=0, row_base=0):
+    """Per-layer energies (means, or samples when rho >= 0), uncertainty
+    scores and optionally the predicted images; see supa_surrogate.h."""
+    B, D2 = out.shape
+    D = D2 // 2
+    layer_e = torch.empty((B, n_layers), dtype=torch.float32, device=out.device)
+    unc = torch.empty(B, dtype=torch.float32, device=out.device)
+    img = torch.empty((B, D), dtype=torch.float32, device=out.device) if want_image else None
+    _check(_lib().supa_surrogate_gate(_stream(), B, D, n_layers, _p(out), _p(e0), Y_SCALE, S_CLAMP,
+                                      _p(layer_e), _p(unc), _p(img), float(rho),
+                                      row_base & 0xFFFFFFFF, seed & 0xFFFFFFFFFFFFFFFF))
+    return layer_e, unc, img
+
+
+def select_above(v, tau):
+    n = int(v.shape[0])
+    idx = torch.empty(max(n, 1), dtype=torch.int32, device=v.device)
+    count = torch.zeros(1, dtype=torch.int32, device=v.device)
+    scratch = torch.empty(max(1, (n + 1023) // 1024), dtype=torch.int32, device=v.device)
+    _check(_lib().supa_select_above(_stream(), n, _p(v), float(tau), _p(idx), _p(count),
+                                    _p(scratch)))
+    m = int(count.item())
+    return idx[:m]
+
+
+def gather3(idx, a, b, c):
+    m = int(idx.shape[0])
+    oa, ob, oc = (torch.empty(m, dtype=torch.float32, device=a.device) for _ in range(3))
+    _check(_lib().supa_gather3(_stream(), m, _p(idx), _p(a), _p(b), _p(c), _p(oa), _p(ob), _p(oc)))
+    return oa, ob, oc
+
+
+def scatter_rows(idx, src, dst):
+    m, w = src.shape
+    _check(_lib().supa_scatter_rows(_stream(), m, w, _p(idx), _p(src), _p(dst)))
+
+
+def group_sums(x, n_groups):
+    rows, width = x.shape
+    out = torch.empty((rows, n_groups), dtype=torch.float32, device=x.device)
+    _check(_lib().supa_group_sums(_stream(), rows, n_groups, width // n_groups, _p(x), _p(out)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the MLP
+# ---------------------------------------------------------------------------
+class MLP:
+    """bf16 weights with float32 master copies and Adam moments, on device."""
+
+    def __init__(self, dims, device="cuda", seed=0):
+        self.dims = list(dims)            # [IN_PAD, h, ..., out]
+        self.device = torch.device(device)
+        rng = np.random.default_rng(seed)
+        self.W, self.b = [], []
+        for l, (din, dout) in enumerate(zip(self.dims[:-1], self.dims[1:])):
+            fan_in = din if l > 0 else IN_FEATURES + N_NOISE
+            w = rng.normal(0.0, math.sqrt(2.0 / fan_in), size=(din, dout)).astype(np.float32)
+            if l == 0:
+                w[IN_FEATURES + N_NOISE:] = 0.0       # padding inputs
+            if l == len(self.dims) - 2:
+                w *= 0.1                              # start near mu = 0, log var = 0
+            self.W.append(torch.from_numpy(w).to(self.device))
+            self.b.append(torch.zeros(dout, dtype=torch.float32, device=self.device))
+        self.Wb = [to_bf16(w) for w in self.W]
+        self.mW = [torch.zeros_like(w) for w in self.W]
+        self.vW = [torch.zeros_like(w) for w in self.W]
+        self.mb = [torch.zeros_like(b) for b in self.b]
+        self.vb = [torch.zeros_like(b) for b in self.b]
+        self.step = 0
+
+    def load_float_weights(self, Ws, bs):
+        for l, (w, b) in enumerate(zip(Ws, bs)):
+            self.W[l].copy_(torch.as_tensor(w, dtype=torch.float32))
+            self.b[l].copy_(torch.as_tensor(b, dtype=torch.float32))
+            self.Wb[l] = to_bf16(self.W[l])
+
+    def forward(self, x, keep=False):
+        """x: bf16 [B, IN_PAD] -> float32 [B, out]; keep=True also returns
+        the activations and pre-activations the backward needs."""
+        B = x.shape[0]
+        h = x
+        acts, pres = [x], []
+        nl = len(self.Wb)
+        for l in range(nl):
+            dout = self.dims[l + 1]
+            if l < nl - 1:
+                y = torch.empty((B, dout), dtype=torch.int16, device=self.device)
+                pre = torch.empty((B, dout), dtype=torch.int16, device=self.device)
+                gemm(h, self.Wb[l], y, epilogue=2, bias=self.b[l], pre=pre)
+                pres.append(pre)
+                acts.append(y)
+                h = y
+            else:
+                out = torch.empty((B, dout), dtype=torch.float32, device=self.device)
+                gemm(h, self.Wb[l], out, epilogue=1, bias=self.b[l])
+        return (out, acts, pres) if keep else out
+
+    def backward(self, acts, pres, dout):
+        """dout: bf16 [B, out] = d loss / d out; returns float32 (dW, db) lists."""
+        B = dout.shape[0]
+        nl = len(self.Wb)
+        dWs, dbs = [None] * nl, [None] * nl
+        g = dout
+        for l in range(nl - 1, -1, -1):
+            din, dout_l = self.dims[l], self.dims[l + 1]
+            dW = torch.empty((din, dout_l), dtype=torch.float32, device=self.device)
+            gemm(acts[l], g, dW, trans_a=1, trans_b=0, epilogue=0)          # h^T g
+            db = torch.empty(dout_l, dtype=torch.float32, device=self.device)
+            _check(_lib().supa_colsum_bf16(_stream(), B, dout_l, _p(g), g.stride(0), _p(db)))
+            dWs[l], dbs[l] = dW, db
+            if l > 0:
+                gn = torch.empty((B, din), dtype=torch.int16, device=self.device)
+                gemm(g, self.Wb[l], gn, trans_a=0, trans_b=1, epilogue=3, pre=pres[l - 1])
+                g = gn
+        return dWs, dbs
+
+    def adam(self, dWs, dbs, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.step += 1
+        L = _lib()
+        for l in range(len(self.W)):
+            _check(L.supa_adam(_stream(), self.W[l].numel(), _p(self.W[l]), _p(dWs[l]),
+                               _p(self.mW[l]), _p(self.vW[l]), _p(self.Wb[l]), lr, b1, b2, eps,
+                               self.step))
+            _check(L.supa_adam(_stream(), self.b[l].numel(), _p(self.b[l]), _p(dbs[l]),
+                               _p(self.mb[l]), _p(self.vb[l]), None, lr, b1, b2, eps, self.step))
+
+    def train_step(self, x, img, e0, lr=1e-3):
+        """One NLL step on targets img / e0 (img float [B, D]); returns the loss."""
+        out, acts, pres = self.forward(x, keep=True)
+        B, D2 = out.shape
+        dout = torch.empty((B, D2), dtype=torch.int16, device=self.device)
+        loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        _check(_lib().supa_nll_grad(_stream(), B, D2 // 2, _p(out), _p(img), _p(e0), Y_SCALE,
+                                    S_CLAMP, _p(dout), _p(loss)))
+        dWs, dbs = self.backward(acts, pres, dout)
+        self.adam(dWs, dbs, lr=lr)
+        return loss / (B * (D2 // 2))
+
+
+def surrogate_dims(n_layers=20, bins=256, hidden=256, depth=4):
+    return [IN_PAD] + [hidden] * depth + [2 * n_layers * bins]

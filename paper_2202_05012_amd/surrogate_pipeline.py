@@ -1,0 +1,111 @@
+"""Training of the surrogate on simulated showers, and surrogate-plus-fallback
+inference (argument marshalling; every step runs in the library's kernels).
+
+Workload: initial conditions of the 100,000-shower, 20-plane workload
+(E0 ~ U[1, 100], polar ~ U[0, 15 deg], azimuth ~ U[0, 2 pi)), images of
+20 layers x 16 x 16 cells over [-5, 5)^2, drawn online (never stored).
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import supa, surrogate as S, workloads
+
+N_LAYERS = 20
+GRID = 16
+BINS = GRID * GRID
+D = N_LAYERS * BINS
+
+
+def geometry():
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    return workloads.geometry(w, img_nx=GRID, img_ny=GRID, img_x0=-5.0, img_x1=5.0,
+                              img_y0=-5.0, img_y1=5.0)
+
+
+def draw_ics(n, seed, device):
+    """Initial conditions of the 100,000-shower workload's distribution."""
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    e0, pol, az = workloads.initial_conditions(w, n, seed=seed)
+    t = lambda a: torch.from_numpy(a).to(device)
+    return t(e0), t(pol), t(az)
+
+
+class ImageSimulator:
+    """supa_simulate producing only 16x16 per-layer images (no hit arrays)."""
+
+    def __init__(self, device=0):
+        self.sim = supa.Simulator(geometry(), supa.OUT_IMAGES, device=device)
+
+    def images(self, e0, pol, az, seed, shower_id_base=0):
+        n = int(e0.shape[0])
+        out = self.sim.allocate(n)
+        st = self.sim.run(e0, pol, az, seed, out, shower_id_base=shower_id_base)
+        assert st == 0
+        return out["images"].view(n, D), out
+
+
+def train(model: S.MLP, steps: int, batch: int, seed: int = 100, lr: float = 1e-3,
+          log_every: int = 0, sim: ImageSimulator | None = None, device="cuda"):
+    """Online training: every step simulates a fresh batch (shower ids never
+    repeat) and takes one Adam step on the Gaussian NLL."""
+    sim = sim or ImageSimulator()
+    losses = []
+    t0 = time.perf_counter()
+    for step in range(steps):
+        e0, pol, az = draw_ics(batch, seed + 1000003 * (step + 1), device)
+        img, _ = sim.images(e0, pol, az, seed, shower_id_base=step * batch)
+        x = S.features(e0, pol, az, seed, row_base=step * batch, stream_id=1)
+        cur_lr = lr * (0.5 * (1 + math.cos(math.pi * step / max(steps, 1))) * 0.9 + 0.1)
+        loss = model.train_step(x, img, e0, lr=cur_lr)
+        if log_every and (step % log_every == 0 or step == steps - 1):
+            losses.append((step, float(loss.item())))
+    torch.cuda.synchronize()
+    return losses, time.perf_counter() - t0
+
+
+def surrogate_layer_energies(model: S.MLP, e0, pol, az, seed, chunk=65536, row_base=0, rho=-1.0):
+    """Predicted per-layer energies (sampled when rho >= 0) and uncertainty
+    scores, in chunks."""
+    n = int(e0.shape[0])
+    layer_e = torch.empty((n, N_LAYERS), dtype=torch.float32, device=e0.device)
+    unc = torch.empty(n, dtype=torch.float32, device=e0.device)
+    for s in range(0, n, chunk):
+        sl = slice(s, min(n, s + chunk))
+        x = S.features(e0[sl], pol[sl], az[sl], seed, row_base=row_base + s, stream_id=2)
+        out = model.forward(x)
+        le, u, _ = S.gate(out, e0[sl], N_LAYERS, rho=rho, seed=seed, row_base=row_base + s)
+        layer_e[sl] = le
+        unc[sl] = u
+    return layer_e, unc
+
+
+def surrogate_with_fallback(model: S.MLP, e0, pol, az, seed, tau, sim: ImageSimulator,
+                            chunk=65536, rho=-1.0):
+    """Per-layer energies: the surrogate's, replaced by the simulator's for
+    every shower whose uncertainty exceeds tau.  Returns (layer_e, n_fallback)."""
+    layer_e, unc = surrogate_layer_energies(model, e0, pol, az, seed, chunk, rho=rho)
+    idx = S.select_above(unc, tau)
+    m = int(idx.shape[0])
+    if m:
+        fe, fp, fa = S.gather3(idx, e0, pol, az)
+        img, _ = sim.images(fe, fp, fa, seed, shower_id_base=0x40000000)
+        S.scatter_rows(idx, S.group_sums(img, N_LAYERS), layer_e)
+    return layer_e, m
+
+
+def simulated_layer_energies(e0, pol, az, seed, sim: ImageSimulator, shower_id_base=0):
+    img, _ = sim.images(e0, pol, az, seed, shower_id_base=shower_id_base)
+    return S.group_sums(img, N_LAYERS)
+
+
+def w1_per_layer(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Per-layer 1-D Wasserstein-1 distances of two samples of equal size:
+    mean |a_(i) - b_(i)| of the sorted columns (evaluation, on the host)."""
+    a = np.sort(a, axis=0)
+    b = np.sort(b, axis=0)
+    return np.abs(a - b).mean(axis=0)

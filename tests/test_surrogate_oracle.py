@@ -1,0 +1,94 @@
+"""Pins of the surrogate oracle: library routines and finite differences."""
+import math
+
+import numpy as np
+from scipy import stats
+
+from oracle import surrogate_oracle as S
+
+
+def test_gelu_is_x_times_normal_cdf():
+    a = np.linspace(-6, 6, 1001)
+    np.testing.assert_allclose(S.gelu(a), a * stats.norm.cdf(a), rtol=1e-13, atol=1e-15)
+
+
+def test_gelu_grad_finite_difference():
+    a = np.linspace(-5, 5, 101)
+    h = 1e-6
+    fd = (S.gelu(a + h) - S.gelu(a - h)) / (2 * h)
+    np.testing.assert_allclose(S.gelu_grad(a), fd, rtol=1e-7, atol=1e-9)
+
+
+def test_nll_is_gaussian_logpdf_up_to_constant():
+    rng = np.random.default_rng(1)
+    mu = rng.normal(size=(7, 5))
+    s = rng.uniform(-3, 3, size=(7, 5))
+    y = rng.normal(size=(7, 5))
+    out = np.concatenate([mu, s], axis=1)
+    ref = -stats.norm.logpdf(y, loc=mu, scale=np.exp(0.5 * s)) - 0.5 * math.log(2 * math.pi)
+    assert abs(S.nll(out, y) - ref.mean()) < 1e-12
+
+
+def test_backward_matches_finite_differences():
+    rng = np.random.default_rng(2)
+    dims = [5, 8, 8, 6]          # toy width 8, 3 outputs mu + 3 log-variances
+    params = S.init_params(dims, rng)
+    for W, b in params:
+        b += rng.normal(0, 0.1, size=b.shape)
+    x = rng.normal(size=(4, 5))
+    y = rng.normal(size=(4, 3))
+    out, cache = S.forward(params, x)
+    grads = S.backward(params, cache, S.nll_grad(out, y))
+    h = 1e-6
+    for l, (W, b) in enumerate(params):
+        for arr, g in ((W, grads[l][0]), (b, grads[l][1])):
+            it = np.nditer(arr, flags=["multi_index"])
+            for _ in it:
+                idx = it.multi_index
+                old = arr[idx]
+                arr[idx] = old + h
+                up = S.nll(S.forward(params, x)[0], y)
+                arr[idx] = old - h
+                dn = S.nll(S.forward(params, x)[0], y)
+                arr[idx] = old
+                fd = (up - dn) / (2 * h)
+                assert abs(g[idx] - fd) <= 1e-7 * max(1.0, abs(fd)) + 1e-9, (l, idx, g[idx], fd)
+
+
+def test_clamped_log_variance_has_no_gradient():
+    out = np.array([[0.0, 25.0], [0.0, -30.0]])
+    y = np.array([[1.0], [1.0]])
+    g = S.nll_grad(out, y)
+    assert g[0, 1] == 0.0 and g[1, 1] == 0.0
+
+
+def test_adam_first_step_moves_by_lr_times_sign():
+    p = [[np.array([1.0, -2.0, 3.0]), np.array([0.5])]]
+    g = [(np.array([0.3, -4.0, 1e-3]), np.array([-2.0]))]
+    m = [[np.zeros(3), np.zeros(1)]]
+    v = [[np.zeros(3), np.zeros(1)]]
+    S.adam_step(p, g, m, v, t=1, lr=0.01, eps=0.0)
+    np.testing.assert_allclose(p[0][0], [1.0 - 0.01, -2.0 + 0.01, 3.0 - 0.01], rtol=1e-12)
+    np.testing.assert_allclose(p[0][1], [0.5 + 0.01], rtol=1e-12)
+
+
+def test_w1_matches_scipy():
+    rng = np.random.default_rng(3)
+    for na, nb in ((100, 100), (57, 230), (1, 9)):
+        a = rng.gamma(2.0, size=na)
+        b = rng.normal(1.0, 2.0, size=nb)
+        assert abs(S.w1(a, b) - stats.wasserstein_distance(a, b)) < 1e-12
+
+
+def test_w1_shift_and_identity():
+    a = np.random.default_rng(4).normal(size=500)
+    assert S.w1(a, a) == 0.0
+    assert abs(S.w1(a, a + 0.7) - 0.7) < 1e-12
+
+
+def test_uncertainty_and_layer_sums():
+    mu = np.array([[1.0, 2.0, 3.0, 4.0]])
+    s = np.log(np.array([[1.0, 4.0, 0.0 + 1e-300, 4.0]]))
+    u = S.uncertainty(mu, s, 2)
+    assert abs(u[0] - 3.0 / 10.0) < 1e-12
+    np.testing.assert_array_equal(S.layer_sums(mu, 2), [[3.0, 7.0]])
