@@ -109,3 +109,25 @@ def w1_per_layer(a: np.ndarray, b: np.ndarray) -> np.ndarray:
     a = np.sort(a, axis=0)
     b = np.sort(b, axis=0)
     return np.abs(a - b).mean(axis=0)
+
+
+def calibrate_rho(model: S.MLP, sim: ImageSimulator, n: int, seed: int, device="cuda"):
+    """The bin correlation rho that matches the spread of the simulated
+    per-layer energies around the predicted ones on a validation batch:
+    E[(E_sim - E_pred)^2] = rho * A + (1 - rho) * B with A = (sum sigma)^2,
+    B = sum sigma^2 (scaled by E0), least squares over showers and layers,
+    clipped to [0, 1].  A one-off fit, done on the host in float64."""
+    e0, pol, az = draw_ics(n, seed, device)
+    sim_e = simulated_layer_energies(e0, pol, az, seed, sim, shower_id_base=0x60000000)
+    x = S.features(e0, pol, az, seed, row_base=0x60000000, stream_id=3)
+    out = model.forward(x)
+    mean_e, _, _ = S.gate(out, e0, N_LAYERS)
+    o = out.cpu().numpy().astype(np.float64)
+    e0h = e0.cpu().numpy().astype(np.float64)[:, None] / S.Y_SCALE
+    sig = np.exp(0.5 * np.clip(o[:, D:], -S.S_CLAMP, S.S_CLAMP)).reshape(n, N_LAYERS, BINS)
+    A = (sig.sum(-1) * e0h) ** 2
+    Bv = (sig ** 2).sum(-1) * e0h ** 2
+    resid = (sim_e.cpu().numpy().astype(np.float64) - mean_e.cpu().numpy()) ** 2
+    a = (A - Bv).ravel()
+    r = (resid - Bv).ravel()
+    return float(np.clip((a @ r) / max(a @ a, 1e-300), 0.0, 1.0))
