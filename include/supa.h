@@ -67,7 +67,7 @@ enum { SUPA_ANGLE_FIXED = 0, SUPA_ANGLE_UNIFORM = 1, SUPA_ANGLE_RAYLEIGH = 2 };
 /* Output selection bits for supa_geometry.outputs. */
 enum {
     SUPA_OUT_HITS = 1,   /* hit point clouds                                 */
-    SUPA_OUT_IMAGES = 2, /* per-layer images (needs SUPA_OUT_HITS)           */
+    SUPA_OUT_IMAGES = 2, /* per-layer images (with or without hit clouds)    */
     SUPA_OUT_TREE = 4,   /* propagation tree                                 */
     SUPA_OUT_KEYS = 8    /* path ids of hits and nodes (canonical keys)      */
 };
@@ -115,14 +115,16 @@ typedef struct supa_batch {
 
 /*
  * Outputs.  All arrays are device pointers owned by the caller.
- * Layout is segmented: the hits of shower i occupy the contiguous range
- * [hit_offsets[i], hit_offsets[i] + counts[6*i+1]) of every hit array; the
- * segments of a batch are disjoint and tile [0, total_hits) with no gap, in an
- * unspecified order of showers.  Within a segment hits are grouped by plane in
- * increasing order; their order within a plane is unspecified (the path id,
- * SUPA_OUT_KEYS, is a canonical key).  Nodes: same segment rule; node_parent
- * indexes the shower's own segment; their order is unspecified apart from
- * the primary, which comes first.
+ * Layout is segmented (CSR): the hits of shower i occupy the contiguous range
+ * [hit_offsets[i], hit_offsets[i] + counts[6*i+1]) of every hit array, with
+ * hit_offsets the exclusive prefix sums of the hit counts in batch order, so
+ * the segments tile [0, total_hits) in shower order.  Within a segment hits
+ * are grouped by plane in increasing order; their order within a plane is
+ * unspecified (the path id, SUPA_OUT_KEYS, is a canonical key).  Nodes: same
+ * rule with node_offsets and counts[6*i]; within a segment node j is the one
+ * node_parent of its children refers to: the primary is node 0 and the two
+ * daughters of a split are consecutive (a first), in the order the splits
+ * were processed.
  */
 typedef struct supa_output {
     /* hit point clouds (SUPA_OUT_HITS); hit_key also needs SUPA_OUT_KEYS */
@@ -180,8 +182,8 @@ supa_status supa_destroy(supa_ctx *ctx);
  * Errors: INVALID_ARG (NULL pointers for requested outputs, bad n),
  * RANGE (an initial energy out of range: nothing else is meaningful),
  * CAPACITY (total hits or nodes exceed the capacities: ledger, counts and the
- * host totals are valid, hit/node arrays are not; a retry with larger arrays
- * gives the same per-shower results), DEVICE.
+ * host totals are valid, hit/node arrays and images are not written; a retry
+ * with larger arrays gives the same per-shower results), DEVICE.
  */
 supa_status supa_simulate(supa_ctx *ctx, const supa_batch *b, uint64_t seed,
                           supa_output *out);
@@ -193,17 +195,21 @@ supa_status supa_simulate(supa_ctx *ctx, const supa_batch *b, uint64_t seed,
  *                 few showers in flight, taken from the work queue);
  *   frontier_cap  pending particles per wave kept in LDS: 128, 256, 512 or
  *                 1024 (more spill to a per-wave global area);
- *   hit_cap, node_cap  per-shower journal capacities in hits / nodes.
- * The spill area and the journals grow by themselves (and the batch is rerun)
- * when a shower needs more.
+ *   hit_cap, node_cap  sizes (records) of the library's hit and node logs,
+ *                 where the propagation kernel leaves hits and nodes before
+ *                 they are placed into the output arrays (default: sized
+ *                 from the output capacities).
+ * The spill area and the logs grow by themselves (and the batch is rerun)
+ * when a batch needs more.
  */
 supa_status supa_set_launch(supa_ctx *ctx, int32_t waves_per_cu, int32_t frontier_cap,
                             int32_t hit_cap, int32_t node_cap);
 
 /*
  * Device time of the last supa_simulate, in milliseconds, measured with HIP
- * events on the context's stream: [0] propagation kernel, [1] image kernel,
- * [2] whole call.  Host pointer to 3 floats.
+ * events on the context's stream: [0] propagation kernel, [1] the kernels
+ * after it (segment offsets, placement of hits and nodes, images), [2] whole
+ * call.  Host pointer to 3 floats.
  */
 supa_status supa_last_timing(const supa_ctx *ctx, float *ms3);
 

@@ -24,7 +24,34 @@ hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k
                          hipStream_t s);
 size_t propagate_lds_bytes(int pool_cap);
 hipError_t launch_images(const ImgParams &P, int n_cu, hipStream_t s);
+int64_t scan_partial_words(int64_t n);
+hipError_t launch_scan(const ScanParams &S, hipStream_t s);
+hipError_t launch_scatter(const ScatterParams &Q, int32_t n, bool hits, bool nodes, int n_cu,
+                          hipStream_t s);
 }  // namespace supa
+
+// A device buffer that only grows (its contents are scratch).
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    bool ensure(size_t need) {
+        if (need <= bytes) return true;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (hipMalloc(&p, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        bytes = need;
+        return true;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
 
 static constexpr int kMaxImageWidth = 1024;
 
@@ -47,18 +74,14 @@ struct supa_ctx {
     unsigned long long *h_ctr = nullptr;   // pinned
     supa::Cold *d_cold = nullptr;          // per-call inputs/outputs block (device)
     supa::Cold *h_cold = nullptr;          // its pinned host staging copy
-    // per-wave scratch
+    // launch settings and scratch
     int n_cu = 0;
     int waves_per_cu = 10;
     int pool_cap = 128;                  // particle-pool entries kept in LDS
-    int spill_cap = 4096, cap_h = 4096, cap_n = 8192;   // per-wave spill / journals
-    void *scratch = nullptr;
-    size_t scratch_bytes = 0;
-    supa::Params layout{};               // scratch pointers only
-    // per-batch hand-over to the image kernel (grows with the batch)
-    void *iscratch = nullptr;
-    size_t iscratch_bytes = 0;
-    int64_t img_cap = 0;
+    int spill_cap = 4096;                // per-wave spill entries
+    int64_t h_chunks = 0, n_chunks = 0;  // log chunks (grow on demand)
+    int64_t img_cap = 0;                 // hand-over hits to the image kernel
+    DevBuf spill, hlog, nlog, shower, himg;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float timing[3] = {0, 0, 0};
     std::string err;
@@ -142,71 +165,16 @@ extern "C" supa_status supa_validate_geometry(const supa_geometry *g) {
     return s;
 }
 
-static void free_scratch(supa_ctx *c) {
-    if (c->scratch) (void)hipFree(c->scratch);
-    c->scratch = nullptr;
-    c->scratch_bytes = 0;
+static constexpr int64_t kChunkWaste = 127;   // records a closed chunk may leave unused
+
+// log chunks that hold `records` records for `waves` waves
+static int64_t chunks_for(int64_t records, int64_t waves) {
+    return (records + supa::LOG_CHUNK - kChunkWaste - 1) / (supa::LOG_CHUNK - kChunkWaste) + waves + 8;
 }
 
-// Carves the per-wave scratch out of one allocation.
-static supa_status ensure_scratch(supa_ctx *c, bool tree) {
-    const int64_t waves = (int64_t)c->n_cu * c->waves_per_cu;
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t spill_b = al((size_t)waves * supa::POOL_FIELDS * c->spill_cap * 4);
-    const size_t jh_b = al((size_t)waves * supa::SLOTS * supa::JH_COUNT * c->cap_h * 4);
-    const size_t hidx_b = 0;
-    const size_t jn_b = tree ? al((size_t)waves * supa::SLOTS * supa::JN_COUNT * c->cap_n * 4) : 0;
-    const size_t need = spill_b + jh_b + hidx_b + jn_b;
-    if (need > c->scratch_bytes) {
-        free_scratch(c);
-        void *p = nullptr;
-        if (hipMalloc(&p, need) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(c, SUPA_ERR_NOMEM, "cannot allocate " + std::to_string(need) + " bytes of scratch");
-        }
-        c->scratch = p;
-        c->scratch_bytes = need;
-    }
-    char *p = (char *)c->scratch;
-    supa::Params &L = c->layout;
-    L.spill_cap = c->spill_cap;
-    L.cap_h = c->cap_h;
-    L.cap_n = c->cap_n;
-    L.spill = (uint32_t *)p;
-    L.jh = (uint32_t *)(p + spill_b);
-    L.hidx = nullptr;
-    L.jn = tree ? (uint32_t *)(p + spill_b + jh_b + hidx_b) : nullptr;
-    return SUPA_OK;
-}
-
-// Hand-over buffers between the propagation and the image kernel.
-static supa_status ensure_image_scratch(supa_ctx *c, int64_t n, int64_t cap, bool xy) {
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    const size_t cnt_b = al((size_t)n * 4), seg_b = xy ? al((size_t)n * 8) : 0;
-    const size_t e_b = al((size_t)cap * 4), xy_b = xy ? 3 * al((size_t)cap * 4) : 0;
-    const size_t need = cnt_b + seg_b + e_b + xy_b;
-    if (need > c->iscratch_bytes) {
-        if (c->iscratch) (void)hipFree(c->iscratch);
-        c->iscratch = nullptr;
-        c->iscratch_bytes = 0;
-        void *p = nullptr;
-        if (hipMalloc(&p, need) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(c, SUPA_ERR_NOMEM, "cannot allocate " + std::to_string(need) + " bytes of image scratch");
-        }
-        c->iscratch = p;
-        c->iscratch_bytes = need;
-    }
-    char *p = (char *)c->iscratch;
-    supa::Cold &K = *c->h_cold;
-    K.img_count = (int32_t *)p;
-    K.img_seg = xy ? (int64_t *)(p + cnt_b) : nullptr;
-    K.img_e = (uint32_t *)(p + cnt_b + seg_b);
-    K.img_x = xy ? (float *)(p + cnt_b + seg_b + e_b) : nullptr;
-    K.img_y = xy ? (float *)(p + cnt_b + seg_b + e_b + al((size_t)cap * 4)) : nullptr;
-    K.img_layer = xy ? (int32_t *)(p + cnt_b + seg_b + e_b + 2 * al((size_t)cap * 4)) : nullptr;
-    K.img_cap = cap;
-    return SUPA_OK;
+static supa_status nomem(supa_ctx *c, const char *what, size_t bytes) {
+    return fail(c, SUPA_ERR_NOMEM, std::string("cannot allocate ") + std::to_string(bytes) +
+                                       " bytes of " + what);
 }
 
 extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, void *hip_stream,
@@ -293,8 +261,7 @@ extern "C" supa_status supa_destroy(supa_ctx *c) {
     if (!c) return SUPA_ERR_STATE;
     (void)hipSetDevice(c->device);
     if (c->stream || true) (void)hipStreamSynchronize(c->stream);
-    free_scratch(c);
-    if (c->iscratch) (void)hipFree(c->iscratch);
+    for (DevBuf *d : {&c->spill, &c->hlog, &c->nlog, &c->shower, &c->himg}) d->release();
     if (c->d_layer) (void)hipFree(c->d_layer);
     if (c->d_layer_plane_start) (void)hipFree(c->d_layer_plane_start);
     if (c->d_layer_planes) (void)hipFree(c->d_layer_planes);
@@ -319,8 +286,10 @@ extern "C" supa_status supa_set_launch(supa_ctx *c, int32_t waves_per_cu, int32_
         return fail(c, SUPA_ERR_INVALID_ARG, "launch settings out of range");
     if (waves_per_cu) c->waves_per_cu = waves_per_cu;
     if (frontier_cap) c->pool_cap = frontier_cap;
-    if (hit_cap) c->cap_h = hit_cap;
-    if (node_cap) c->cap_n = node_cap;
+    // initial log sizes in records (the logs grow by themselves when a batch
+    // needs more; small values exercise that path)
+    if (hit_cap) c->h_chunks = std::max<int64_t>(1, (hit_cap + supa::LOG_CHUNK - 1) / supa::LOG_CHUNK);
+    if (node_cap) c->n_chunks = std::max<int64_t>(1, (node_cap + supa::LOG_CHUNK - 1) / supa::LOG_CHUNK);
     return SUPA_OK;
 }
 
@@ -379,12 +348,56 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
 
     HIP_TRY(c, hipSetDevice(c->device));
     const bool tree = (outs & SUPA_OUT_TREE) != 0;
+    const bool hits_out = (outs & SUPA_OUT_HITS) != 0;
+    const bool images = (outs & SUPA_OUT_IMAGES) != 0;
+    const bool recs = hits_out || images;
+    const int N = c->g.n_planes;
+    const int64_t waves = std::max(1, c->n_cu * c->waves_per_cu);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    // first sizes of the logs: the caller's capacities (or 64 hits per shower
+    // for images only), unless earlier batches needed more
+    if (recs) {
+        const int64_t hint = hits_out ? out->hit_capacity : 64 * n;
+        if (c->h_chunks == 0) c->h_chunks = chunks_for(std::min<int64_t>(hint, (int64_t)1 << 28), waves);
+    }
+    if (tree && c->n_chunks == 0)
+        c->n_chunks = chunks_for(std::min<int64_t>(out->node_capacity, (int64_t)1 << 28), waves);
+    if (images && !hits_out && c->img_cap == 0) c->img_cap = std::max<int64_t>(1024, 64 * n);
 
     for (int attempt = 0; attempt < 8; ++attempt) {
-        supa_status s = ensure_scratch(c, tree);
-        if (s != SUPA_OK) return s;
-        supa::Params P = c->layout;
-        P.n_planes = c->g.n_planes;
+        // scratch: per-wave spill, logs, per-shower plane starts / offsets / scan
+        // tile sums, and the image kernel's hand-over
+        const size_t spill_b = al((size_t)waves * supa::POOL_FIELDS * c->spill_cap * 4);
+        if (!c->spill.ensure(spill_b)) return nomem(c, "spill area", spill_b);
+        const size_t hfill_b = recs ? al((size_t)c->h_chunks * 4) : 0;
+        const size_t hlog_b = recs ? hfill_b + (size_t)c->h_chunks * supa::HL_FIELDS * supa::LOG_CHUNK * 4 : 0;
+        if (recs && !c->hlog.ensure(hlog_b)) return nomem(c, "hit log", hlog_b);
+        const size_t nfill_b = tree ? al((size_t)c->n_chunks * 4) : 0;
+        const size_t nlog_b = tree ? nfill_b + (size_t)c->n_chunks * supa::NL_FIELDS * supa::LOG_CHUNK * 4 : 0;
+        if (tree && !c->nlog.ensure(nlog_b)) return nomem(c, "node log", nlog_b);
+        const size_t pstart_b = recs ? al((size_t)n * N * 4) : 0;
+        const size_t hoff_b = (images && !hits_out) ? al((size_t)n * 8) : 0;
+        const size_t part_b = al((size_t)supa::scan_partial_words(n) * 8);
+        const size_t shower_b = pstart_b + hoff_b + part_b;
+        if (!c->shower.ensure(shower_b)) return nomem(c, "per-shower scratch", shower_b);
+        // hand-over to the image kernel: integer energies (and, without hit
+        // outputs, positions and layers) at the hits' final places
+        const int64_t icap = images ? (hits_out ? out->hit_capacity : c->img_cap) : 0;
+        const size_t ie_b = al((size_t)std::max<int64_t>(icap, 1) * 4);
+        const size_t himg_b = images ? (hits_out ? ie_b : 4 * ie_b) : 0;
+        if (images && !c->himg.ensure(himg_b)) return nomem(c, "image hand-over", himg_b);
+        char *sh = (char *)c->shower.p;
+        uint32_t *d_pstart = recs ? (uint32_t *)sh : nullptr;
+        int64_t *d_hoff_img = (images && !hits_out) ? (int64_t *)(sh + pstart_b) : nullptr;
+        int64_t *d_part = (int64_t *)(sh + pstart_b + hoff_b);
+        char *hi = (char *)c->himg.p;
+        uint32_t *d_img_e = images ? (uint32_t *)hi : nullptr;
+        float *d_img_x = (images && !hits_out) ? (float *)(hi + ie_b) : nullptr;
+        float *d_img_y = (images && !hits_out) ? (float *)(hi + 2 * ie_b) : nullptr;
+        int32_t *d_img_l = (images && !hits_out) ? (int32_t *)(hi + 3 * ie_b) : nullptr;
+
+        supa::Params P{};
+        P.n_planes = N;
         P.z_first = (float)c->g.z_first;
         P.dz = (float)c->g.dz;
         P.layer = c->d_layer;
@@ -404,10 +417,17 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         P.sid_base = b->shower_id_base;
         P.outputs = outs;
         P.keys = (outs & SUPA_OUT_KEYS) != 0;
-        P.pool_cap = c->pool_cap;
-        P.tile_words = 0;
-        P.ctr = c->d_ctr;
         P.cold = c->d_cold;
+        P.pool_cap = c->pool_cap;
+        P.spill_cap = c->spill_cap;
+        P.spill = (uint32_t *)c->spill.p;
+        P.hfill = recs ? (uint32_t *)c->hlog.p : nullptr;
+        P.hlog = recs ? (uint32_t *)((char *)c->hlog.p + hfill_b) : nullptr;
+        P.h_chunks = recs ? (int32_t)c->h_chunks : 0;
+        P.nfill = tree ? (uint32_t *)c->nlog.p : nullptr;
+        P.nlog = tree ? (uint32_t *)((char *)c->nlog.p + nfill_b) : nullptr;
+        P.n_chunks = tree ? (int32_t)c->n_chunks : 0;
+        P.ctr = c->d_ctr;
 
         supa::Cold &K = *c->h_cold;
         std::memset(&K, 0, sizeof(K));
@@ -417,76 +437,86 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         K.x0 = b->x0;
         K.y0 = b->y0;
         K.order = nullptr;
-        K.hit_offsets = out->hit_offsets;
-        K.hit_x = out->hit_x;
-        K.hit_y = out->hit_y;
-        K.hit_e = out->hit_e;
-        K.hit_layer = out->hit_layer;
-        K.hit_key = (outs & SUPA_OUT_KEYS) ? out->hit_key : nullptr;
-        K.hit_capacity = (outs & SUPA_OUT_HITS) ? out->hit_capacity : 0;
-        K.images = out->images;
-        K.img_nx = c->g.img_nx;
-        K.img_ny = c->g.img_ny;
-        K.img_x0 = (float)c->g.img_x0;
-        K.img_y0 = (float)c->g.img_y0;
-        K.img_sx = (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0));
-        K.img_sy = (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0));
-        K.img_rows = 0;
-        K.n_layers = c->n_layers;
-        K.layer_plane_start = c->d_layer_plane_start;
-        K.layer_planes = c->d_layer_planes;
-        K.node_offsets = out->node_offsets;
-        K.node_parent = out->node_parent;
-        K.node_gen = out->node_gen;
-        K.node_vx = out->node_vx;
-        K.node_vy = out->node_vy;
-        K.node_vz = out->node_vz;
-        K.node_e = out->node_e;
-        K.node_key = (outs & SUPA_OUT_KEYS) ? out->node_key : nullptr;
-        K.node_capacity = tree ? out->node_capacity : 0;
         K.ledger = out->ledger;
         K.counts = out->counts;
-        const bool images = (outs & SUPA_OUT_IMAGES) != 0;
-        if (images) {
-            const bool hits_out = (outs & SUPA_OUT_HITS) != 0;
-            if (!hits_out && c->img_cap == 0) c->img_cap = std::max<int64_t>(1024, 64 * n);
-            const int64_t cap = hits_out ? std::max<int64_t>(out->hit_capacity, 1) : c->img_cap;
-            supa_status si = ensure_image_scratch(c, n, cap, !hits_out);
-            if (si != SUPA_OK) return si;
-        }
+        K.pstart = d_pstart;
 
-        const int blocks = std::max(1, c->n_cu * c->waves_per_cu);
+        supa::ScanParams SP{};
+        SP.n = (int32_t)n;
+        SP.counts = out->counts;
+        SP.hoff = hits_out ? out->hit_offsets : d_hoff_img;
+        SP.noff = tree ? out->node_offsets : nullptr;
+        SP.partial = d_part;
+        SP.ctr = c->d_ctr;
+
+        supa::ScatterParams Q{};
+        Q.n_planes = N;
+        Q.layer = c->d_layer;
+        Q.z_first = P.z_first;
+        Q.dz = P.dz;
+        Q.e_unscale = P.e_unscale;
+        Q.keys = P.keys;
+        Q.ctr = c->d_ctr;
+        Q.hlog = P.hlog;
+        Q.hfill = P.hfill;
+        Q.nlog = P.nlog;
+        Q.nfill = P.nfill;
+        Q.h_chunks = P.h_chunks;
+        Q.n_chunks = P.n_chunks;
+        Q.hoff = SP.hoff;
+        Q.pstart = d_pstart;
+        Q.hcap = hits_out ? out->hit_capacity : c->img_cap;
+        Q.hx = hits_out ? out->hit_x : d_img_x;
+        Q.hy = hits_out ? out->hit_y : d_img_y;
+        Q.he = hits_out ? out->hit_e : nullptr;
+        Q.hl = hits_out ? out->hit_layer : d_img_l;
+        Q.hk = (hits_out && P.keys) ? out->hit_key : nullptr;
+        Q.hei = d_img_e;
+        Q.noff = SP.noff;
+        Q.ncap = tree ? out->node_capacity : 0;
+        Q.np = out->node_parent;
+        Q.ng = out->node_gen;
+        Q.nvx = out->node_vx;
+        Q.nvy = out->node_vy;
+        Q.nvz = out->node_vz;
+        Q.ne = out->node_e;
+        Q.nk = (tree && P.keys) ? out->node_key : nullptr;
+
         HIP_TRY(c, hipMemcpyAsync(c->d_cold, c->h_cold, sizeof(supa::Cold), hipMemcpyHostToDevice,
                                   c->stream));
         HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
         HIP_TRY(c, supa::launch_zero_counters(c->d_ctr, c->stream));
-        HIP_TRY(c, supa::launch_propagate(P, blocks, c->stream));
+        HIP_TRY(c, supa::launch_propagate(P, (int)waves, c->stream));
         HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
+        if (recs || tree) {
+            HIP_TRY(c, supa::launch_scan(SP, c->stream));
+            HIP_TRY(c, supa::launch_scatter(Q, (int32_t)n, recs, tree, c->n_cu, c->stream));
+        }
         if (images) {
-            supa::ImgParams Q{};
-            const supa::Cold &K2 = *c->h_cold;
-            Q.n = (int32_t)n;
-            Q.L = c->n_layers;
-            Q.nx = c->g.img_nx;
-            Q.ny = c->g.img_ny;
-            Q.n_planes = c->g.n_planes;
-            Q.x0 = K2.img_x0;
-            Q.y0 = K2.img_y0;
-            Q.sx = K2.img_sx;
-            Q.sy = K2.img_sy;
-            Q.e_unscale = P.e_unscale;
-            const bool hits_out = (outs & SUPA_OUT_HITS) != 0;
-            Q.seg = hits_out ? out->hit_offsets : K2.img_seg;
-            Q.count = K2.img_count;
-            Q.cap = K2.img_cap;
-            Q.x = hits_out ? out->hit_x : K2.img_x;
-            Q.y = hits_out ? out->hit_y : K2.img_y;
-            Q.e = K2.img_e;
-            Q.layer = hits_out ? out->hit_layer : K2.img_layer;
-            Q.layer_plane_start = c->d_layer_plane_start;
-            Q.layer_planes = c->d_layer_planes;
-            Q.images = out->images;
-            HIP_TRY(c, supa::launch_images(Q, c->n_cu, c->stream));
+            supa::ImgParams I{};
+            I.n = (int32_t)n;
+            I.L = c->n_layers;
+            I.nx = c->g.img_nx;
+            I.ny = c->g.img_ny;
+            I.n_planes = N;
+            I.x0 = (float)c->g.img_x0;
+            I.y0 = (float)c->g.img_y0;
+            I.sx = (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0));
+            I.sy = (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0));
+            I.e_unscale = P.e_unscale;
+            I.seg = SP.hoff;
+            I.count = out->counts + 1;
+            I.count_stride = 6;
+            I.ctr = c->d_ctr;
+            I.cap = Q.hcap;
+            I.x = Q.hx;
+            I.y = Q.hy;
+            I.e = d_img_e;
+            I.layer = Q.hl;
+            I.layer_plane_start = c->d_layer_plane_start;
+            I.layer_planes = c->d_layer_planes;
+            I.images = out->images;
+            HIP_TRY(c, supa::launch_images(I, c->n_cu, c->stream));
         }
         HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_COUNT * sizeof(unsigned long long),
@@ -498,23 +528,24 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         (void)hipEventElapsedTime(&t12, c->ev[1], c->ev[2]);
         (void)hipEventElapsedTime(&t03, c->ev[0], c->ev[3]);
         c->timing[0] = t01;
-        c->timing[1] = images ? t12 : 0.f;
+        c->timing[1] = t12;
         c->timing[2] = t03;
 
-        const unsigned long long flags = c->h_ctr[supa::CTR_FLAGS];
+        const unsigned long long *h = c->h_ctr;
+        const unsigned long long flags = h[supa::CTR_FLAGS];
         if (flags & supa::FLAG_RANGE)
             return fail(c, SUPA_ERR_RANGE, "an initial energy is negative, NaN or too large for the fixed-point format");
+        const int64_t total_hits = (int64_t)h[supa::CTR_HITS], total_nodes = (int64_t)h[supa::CTR_NODES];
         if (flags & supa::FLAG_OVERFLOW) {
-            // grow the per-wave scratch to what the largest shower needed, rerun
-            const int64_t nf = std::max<int64_t>(0, (int64_t)c->h_ctr[supa::CTR_NEED_F] - c->pool_cap);
-            const int64_t nh = (int64_t)c->h_ctr[supa::CTR_NEED_H];
-            const int64_t nn = (int64_t)c->h_ctr[supa::CTR_NEED_N];
-            const int64_t cap_max = (int64_t)1 << 30;
-            c->spill_cap = (int)std::min(cap_max, std::max<int64_t>(c->spill_cap, round_up_pow2(nf + 1)));
-            c->cap_h = (int)std::min(cap_max, std::max<int64_t>(c->cap_h, round_up_pow2(nh + 1)));
-            c->cap_n = (int)std::min(cap_max, std::max<int64_t>(c->cap_n, round_up_pow2(nn + 2)));
-            if (images && !(outs & SUPA_OUT_HITS))
-                c->img_cap = std::max<int64_t>(c->img_cap, (int64_t)c->h_ctr[supa::CTR_HITS] + 1);
+            // grow what ran out and rerun: the spill area to the largest pool
+            // seen, a log to the totals (exact unless the spill overflowed too)
+            const int64_t nf = std::max<int64_t>(0, (int64_t)h[supa::CTR_NEED_F] - c->pool_cap);
+            c->spill_cap = (int)std::min<int64_t>((int64_t)1 << 30,
+                                                  std::max<int64_t>(c->spill_cap, round_up_pow2(nf + 1)));
+            if (recs && (int64_t)h[supa::CTR_HCHUNK] > c->h_chunks)
+                c->h_chunks = std::max(2 * c->h_chunks, chunks_for(total_hits, waves));
+            if (tree && (int64_t)h[supa::CTR_NCHUNK] > c->n_chunks)
+                c->n_chunks = std::max(2 * c->n_chunks, chunks_for(total_nodes, waves));
             continue;
         }
         // only meaningful when nothing overflowed (a lost spill entry breaks
@@ -523,15 +554,19 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
             c->broken = true;
             return fail(c, SUPA_ERR_DEVICE, "internal particle accounting error in the propagation kernel");
         }
-        out->total_steps = (int64_t)c->h_ctr[supa::CTR_STEPS];
-        out->total_hits = (outs & SUPA_OUT_HITS) ? (int64_t)c->h_ctr[supa::CTR_HITS] : 0;
-        (void)0;
-        out->total_nodes = tree ? (int64_t)c->h_ctr[supa::CTR_NODES] : 0;
-        if ((outs & SUPA_OUT_HITS) && out->total_hits > out->hit_capacity)
-            return fail(c, SUPA_ERR_CAPACITY, "hit arrays too small: need " + std::to_string(out->total_hits));
-        if (tree && out->total_nodes > out->node_capacity)
-            return fail(c, SUPA_ERR_CAPACITY, "node arrays too small: need " + std::to_string(out->total_nodes));
+        if (images && !hits_out && total_hits > c->img_cap) {
+            // the library's own hand-over was too small: grow it and rerun
+            c->img_cap = total_hits + total_hits / 8 + 1024;
+            continue;
+        }
+        out->total_steps = (int64_t)h[supa::CTR_STEPS];
+        out->total_hits = hits_out ? total_hits : 0;
+        out->total_nodes = tree ? total_nodes : 0;
+        if (hits_out && total_hits > out->hit_capacity)
+            return fail(c, SUPA_ERR_CAPACITY, "hit arrays too small: need " + std::to_string(total_hits));
+        if (tree && total_nodes > out->node_capacity)
+            return fail(c, SUPA_ERR_CAPACITY, "node arrays too small: need " + std::to_string(total_nodes));
         return SUPA_OK;
     }
-    return fail(c, SUPA_ERR_NOMEM, "per-wave scratch did not converge");
+    return fail(c, SUPA_ERR_NOMEM, "scratch sizes did not converge");
 }

@@ -65,41 +65,32 @@ __device__ __forceinline__ int wave_sum_i32(int v) {
 // ---------------------------------------------------------------------------
 // Parameters of one simulate call, passed by value to the kernels.
 // ---------------------------------------------------------------------------
-// Inputs and outputs used once per shower.  They live in device memory and
-// are read at their point of use, so that they do not occupy scalar
-// registers through the hot loop.
+// Inputs and outputs the propagation kernel touches once per shower.  They
+// live in device memory and are read at their point of use, so that they do
+// not occupy scalar registers through the hot loop.
 struct Cold {
     const float *e0, *polar, *azimuth, *x0, *y0;
     const int32_t *order;       // work order (permutation of 0..n-1) or null
-    int64_t *hit_offsets;
-    float *hit_x, *hit_y, *hit_e;
-    int32_t *hit_layer;
-    uint64_t *hit_key;
-    int64_t hit_capacity;
-    float *images;
-    int32_t img_nx, img_ny;
-    float img_x0, img_y0, img_sx, img_sy;   // cell = floor((x - x0) * sx)
-    int32_t img_rows;                       // image rows binned per LDS pass
-    int32_t n_layers;
-    const int32_t *layer_plane_start;       // [n_layers + 1] CSR of the planes of each layer
-    const int32_t *layer_planes;            // [n_planes]
-    int64_t *node_offsets;
-    int32_t *node_parent, *node_gen;
-    float *node_vx, *node_vy, *node_vz, *node_e;
-    uint64_t *node_key;
-    int64_t node_capacity;
-    uint64_t *ledger;
-    int32_t *counts;
-    // hand-over to the image kernel (library scratch): per shower the start and
-    // number of its hits, per hit its integer energy, and its coordinates and
-    // layer when the caller's hit arrays are not written
-    int64_t *img_seg;           // [n] (when hits are not an output)
-    int32_t *img_count;         // [n] hits handed over (0 when they were not written)
-    uint32_t *img_e;            // [img_cap]
-    float *img_x, *img_y;       // [img_cap] (when hits are not an output)
-    int32_t *img_layer;
-    int64_t img_cap;
+    uint64_t *ledger;           // [n][4]
+    int32_t *counts;            // [n][6]
+    uint32_t *pstart;           // [n][n_planes]: first hit of each plane within the shower
 };
+
+// Hit and node records leave the propagation kernel through logs: chunks of
+// LOG_CHUNK records that a wave fills in the order its phases produce them
+// (fields stored as separate arrays within a chunk, so a wave's stores are
+// contiguous); a chunk is claimed with one atomic and its fill count is
+// written when it is closed.  The scatter kernel moves every record to its
+// final place once all showers are counted.
+constexpr int LOG_CHUNK = 2048;
+// hit record: shower index, plane | rank within (shower, plane) << 6,
+// position, integer energy, path id (with keys)
+enum { HL_I = 0, HL_KR, HL_X, HL_Y, HL_E, HL_LO, HL_HI, HL_FIELDS };
+// node record: shower index, index within the shower, parent index,
+// generation | plane << 8 (plane 255: the primary, vertex z = 0), vertex
+// x and y, integer energy, path id (with keys)
+enum { NL_I = 0, NL_IDX, NL_PARENT, NL_GK, NL_X, NL_Y, NL_E, NL_LO, NL_HI, NL_FIELDS };
+constexpr uint32_t GK_PRIMARY = 255u << 8;
 
 // Parameters of one simulate call that the hot loop reads, by value.
 struct Params {
@@ -120,16 +111,47 @@ struct Params {
     uint32_t outputs;
     bool keys;                  // write path ids of hits and nodes
     const Cold *cold;
-    // per-wave scratch in global memory (wave w owns a contiguous slice)
-    int32_t pool_cap;                         // particle-pool entries kept in LDS (power of 2, >= 128)
-    int32_t tile_words;                       // LDS image tile size (32-bit words)
-    int32_t spill_cap;                        // pool entries that can spill to global memory
-    int32_t cap_h, cap_n;                     // per-shower hit / node journal capacity
-    uint32_t *spill;                          // per wave: POOL_FIELDS x spill_cap
-    uint32_t *jh;                             // per wave: SLOTS x JH_COUNT x cap_h
-    uint32_t *hidx;                           // per wave: cap_h (plane-sorted hit order)
-    uint32_t *jn;                             // per wave: SLOTS x JN_COUNT x cap_n
-    unsigned long long *ctr;                  // device counters, see CTR_*
+    int32_t pool_cap;           // particle-pool entries kept in LDS (power of 2, >= 128)
+    int32_t spill_cap;          // pool entries per wave that can spill to global memory
+    uint32_t *spill;            // per wave: POOL_FIELDS x spill_cap
+    uint32_t *hlog, *hfill;     // hit log: h_chunks x HL_FIELDS x LOG_CHUNK, fill counts
+    uint32_t *nlog, *nfill;     // node log: n_chunks x NL_FIELDS x LOG_CHUNK, fill counts
+    int32_t h_chunks, n_chunks;
+    unsigned long long *ctr;    // device counters, see CTR_*
+};
+
+// Offsets of the showers' segments: exclusive prefix sums of their hit and
+// node counts in batch order (supa_scatter.hip).
+struct ScanParams {
+    int32_t n;
+    const int32_t *counts;      // [n][6]: [0] nodes, [1] hits
+    int64_t *hoff, *noff;       // [n] outputs (either may be null)
+    int64_t *partial;           // [2][ceil(n / SCAN_TILE)] tile sums, then tile offsets
+    unsigned long long *ctr;    // CTR_HITS / CTR_NODES receive the totals
+};
+constexpr int SCAN_THREADS = 256, SCAN_ITEMS = 16, SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+// Moves log records to their final places (supa_scatter.hip).
+struct ScatterParams {
+    int32_t n_planes;
+    const int32_t *layer;       // [n_planes]
+    float z_first, dz, e_unscale;
+    bool keys;
+    const unsigned long long *ctr;
+    const uint32_t *hlog, *hfill, *nlog, *nfill;
+    int32_t h_chunks, n_chunks;
+    const int64_t *hoff;        // [n] segment starts of the hits
+    const uint32_t *pstart;     // [n][n_planes]
+    int64_t hcap;               // entries of the hit arrays below
+    float *hx, *hy, *he;        // positions; float energies (or null)
+    int32_t *hl;                // layers
+    uint64_t *hk;               // path ids (or null)
+    uint32_t *hei;              // integer energies for the image kernel (or null)
+    const int64_t *noff;        // [n] segment starts of the nodes
+    int64_t ncap;
+    int32_t *np, *ng;
+    float *nvx, *nvy, *nvz, *ne;
+    uint64_t *nk;
 };
 
 // Arguments of the surrogate's matrix product (supa_mlp.hip).
@@ -150,7 +172,10 @@ struct ImgParams {
     float x0, y0, sx, sy;        // cell = floor((x - x0) * sx)
     float e_unscale;             // 2^-s
     const int64_t *seg;          // [n] first hit of each shower
-    const int32_t *count;        // [n] hits of each shower that were written
+    const int32_t *count;        // hits of shower i: count[count_stride * i]
+    int32_t count_stride;
+    const unsigned long long *ctr;   // the call's counters: nothing is binned unless
+                                     // every hit was placed (no overflow, total <= cap)
     int64_t cap;                 // entries of x, y, e, layer
     const float *x, *y;          // hit coordinates
     const uint32_t *e;           // integer hit energies
@@ -163,28 +188,29 @@ struct ImgParams {
 
 enum {
     CTR_WORK = 0,        // next work item
-    CTR_HITS = 1,        // hits allocated
-    CTR_NODES = 2,       // nodes allocated
+    CTR_HITS = 1,        // total hits (from the scan)
+    CTR_NODES = 2,       // total nodes (from the scan)
     CTR_STEPS = 3,       // particle-steps
-    CTR_FLAGS = 4,       // bit 0: scratch overflow, bit 1: energy out of range
+    CTR_FLAGS = 4,       // FLAG_* bits
     CTR_NEED_F = 5,      // largest particle pool seen
-    CTR_NEED_H = 6,      // largest per-shower hit count seen
-    CTR_NEED_N = 7,      // largest per-shower node count seen
+    CTR_HCHUNK = 6,      // hit-log chunks claimed
+    CTR_NCHUNK = 7,      // node-log chunks claimed
     CTR_COUNT = 8
 };
 
 enum { FLAG_OVERFLOW = 1, FLAG_RANGE = 2, FLAG_INTERNAL = 4 };
+
+// true when the propagation of this call failed (its outputs are rerun or
+// discarded): the later kernels then write nothing
+__device__ __forceinline__ bool batch_failed(const unsigned long long *ctr) {
+    return (ctr[CTR_FLAGS] & (unsigned long long)(FLAG_OVERFLOW | FLAG_RANGE | FLAG_INTERNAL)) != 0;
+}
 
 constexpr int SLOTS = 4;              // showers in flight per wave
 constexpr int QCAP = 128;             // draw-queue entries per wave
 
 // fields of a pending particle (pool, draw queue, spill); KS = plane | slot << 8
 enum { PF_X = 0, PF_Y, PF_TX, PF_TY, PF_E, PF_LO, PF_HI, PF_NODE, PF_KS, POOL_FIELDS };
-// hit journal fields; PK = plane | KIND_STOP for stops
-enum { JH_X = 0, JH_Y, JH_E, JH_LO, JH_HI, JH_PK, JH_COUNT };
-constexpr uint32_t KIND_STOP = 0x100u;
-// node journal fields
-enum { JN_PARENT = 0, JN_GEN, JN_X, JN_Y, JN_Z, JN_E, JN_LO, JN_HI, JN_COUNT };
 
 // ---------------------------------------------------------------------------
 // Single-precision elementary functions for the split kinematics.

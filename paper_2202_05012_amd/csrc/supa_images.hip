@@ -2,7 +2,7 @@
 // "Downsampling": a region of interest per layer, a grid of cells, and per
 // cell the sum of the energies of the points that fall in it).
 //
-// Runs after the propagation kernel, which leaves every shower's hits (with
+// Runs after the scatter kernel, which leaves every shower's hits (with
 // their integer, fixed-point energies) in one contiguous segment.  One
 // 256-thread workgroup takes one shower at a time: it clears an LDS slab that
 // holds several whole layers (or a band of rows of one large layer), adds the
@@ -88,10 +88,12 @@ __device__ __forceinline__ void bin_cells(const ImgParams &Q, uint32_t *slab, co
 
 __global__ void __launch_bounds__(IMG_THREADS) supa_images(ImgParams Q) {
     extern __shared__ uint32_t slab[];
+    // hits are in place only when the propagation succeeded and they fit
+    if (batch_failed(Q.ctr) || (int64_t)Q.ctr[CTR_HITS] > Q.cap) return;
     const int total_rows = Q.L * Q.ny;
     for (int i = blockIdx.x; i < Q.n; i += gridDim.x) {
         const int64_t seg = Q.seg[i];
-        int nh = Q.count[i];
+        int nh = Q.count[(int64_t)Q.count_stride * i];
         if (seg < 0 || seg + nh > Q.cap) nh = 0;     // never read outside the hit arrays
         float *img = Q.images + (int64_t)i * total_rows * Q.nx;
         // up to IMG_THREADS * IMG_UNROLL hits stay in registers for every slab

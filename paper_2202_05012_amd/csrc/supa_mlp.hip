@@ -38,12 +38,13 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
     return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
+// Phi(a) = erfc(-a / sqrt 2) / 2: no cancellation for negative a
 __device__ __forceinline__ float gelu_f(float a) {
-    return 0.5f * a * (1.0f + erff(a * 0.707106781f));
+    return 0.5f * a * erfcf(-a * 0.707106781f);
 }
 
 __device__ __forceinline__ float gelu_grad_f(float a) {
-    return 0.5f * (1.0f + erff(a * 0.707106781f)) + a * 0.398942280f * __expf(-0.5f * a * a);
+    return 0.5f * erfcf(-a * 0.707106781f) + a * 0.398942280f * __expf(-0.5f * a * a);
 }
 
 enum { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };

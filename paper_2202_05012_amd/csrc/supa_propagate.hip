@@ -171,10 +171,10 @@ __device__ __forceinline__ int wave_excl_scan(int v) {
     return incl - v;
 }
 
-// LDS words of one wave: pool + draw queue + per-plane tables + per-shower
-// plane histograms of the hits
+// LDS words of one wave: pool + draw queue + the stop / split thresholds of
+// every plane + per-shower plane histograms of the hits
 __host__ __device__ constexpr int lds_words(int pool_cap) {
-    return POOL_FIELDS * pool_cap + POOL_FIELDS * QCAP + 2 * 2 * 64 + 64 + SLOTS * 64;
+    return POOL_FIELDS * pool_cap + POOL_FIELDS * QCAP + 2 * 2 * 64 + SLOTS * 64;
 }
 
 // Keeps a wave-uniform value in scalar registers but hides it from loop-
@@ -184,6 +184,30 @@ __device__ __forceinline__ uint32_t opaque_u32(uint32_t v) {
     asm volatile("" : "+s"(v));
     return v;
 }
+
+// One 32-bit value per shower slot in every lane, as named registers (an
+// array indexed by a run-time slot would be placed in scratch memory).
+static_assert(SLOTS == 4, "SlotSums holds four slots");
+struct SlotSums {
+    uint32_t v0, v1, v2, v3;
+    __device__ __forceinline__ void zero() { v0 = v1 = v2 = v3 = 0u; }
+    // adds x to the slot of this lane's particle
+    __device__ __forceinline__ void add(int slot, uint32_t x) {
+        v0 += slot == 0 ? x : 0u;
+        v1 += slot == 1 ? x : 0u;
+        v2 += slot == 2 ? x : 0u;
+        v3 += slot == 3 ? x : 0u;
+    }
+    // value of slot s (wave-uniform), which is cleared
+    __device__ __forceinline__ uint32_t take(int s) {
+        const uint32_t r = s == 0 ? v0 : s == 1 ? v1 : s == 2 ? v2 : v3;
+        v0 = s == 0 ? 0u : v0;
+        v1 = s == 1 ? 0u : v1;
+        v2 = s == 2 ? 0u : v2;
+        v3 = s == 3 ? 0u : v3;
+        return r;
+    }
+};
 
 template <bool TREE, int PC>
 __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
@@ -196,32 +220,66 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
     uint32_t *const pool = lds;            // [POOL_FIELDS][PC], entry j at slot j & (PC-1)
     uint32_t *const queue = pool + POOL_FIELDS * PC;           // [POOL_FIELDS][QCAP]
     uint64_t *const thr = (uint64_t *)(queue + POOL_FIELDS * QCAP);  // c1[64], c2[64]
-    int32_t *const lay = (int32_t *)(thr + 128);               // layer of each plane
-    uint32_t *const shist = (uint32_t *)(lay + 64);            // [SLOTS][64] hits per plane
+    uint32_t *const shist = (uint32_t *)(thr + 128);           // [SLOTS][64] hits per plane
 
     for (int k = (int)lane; k < 64; k += WAVE) {
         thr[k] = k < N ? P.c1[k] : 0ull;
         thr[64 + k] = k < N ? P.c2[k] : 0ull;
-        lay[k] = k < N ? P.layer[k] : -1;
     }
     for (int q = (int)lane; q < SLOTS * 64; q += WAVE) shist[q] = 0u;
 
-    const int64_t G = P.spill_cap, cap_h = P.cap_h, cap_n = P.cap_n;
+    const int64_t G = P.spill_cap;
     uint32_t *const spill = P.spill + wave * POOL_FIELDS * G;
-    uint32_t *const jh_w = P.jh + wave * (int64_t)SLOTS * JH_COUNT * cap_h;
-    uint32_t *const jn_w = TREE ? P.jn + wave * (int64_t)SLOTS * JN_COUNT * cap_n : nullptr;
     const bool keys = P.keys;
-    const bool want_xy = (P.outputs & 3u) != 0;     // hit clouds or images need positions
+    const bool recs = (P.outputs & 3u) != 0;        // hit records (clouds or images)
 
     Slots S;
     S.i = -1;
     S.sid = S.e0 = 0u;
     S.live = S.hits = S.nodes = S.passes = S.escaped = S.backward = 0;
     S.e_esc = 0u;
+    // per-lane partial sums of the energy each slot's shower deposited by
+    // cuts and by stops (a shower's energies sum to e0 < 2^32)
+    SlotSums ecut, estop;
+    ecut.zero();
+    estop.zero();
 
     int top = 0, lo = 0, qn = 0, max_top = 0;
     bool exhausted = false, overflow = false;
+    unsigned long long steps = 0;
     const float zf = P.z_first, dzp = P.dz;
+
+    // open log chunks (-1: none yet, -2: log full) and their fill
+    int hc = -1, hf = 0, nc = -1, nf = 0;
+    // room for m more records in the open chunk of a log: closes it and
+    // claims the next one when they do not fit; false once the log is full
+    // (the batch is then rerun with a larger log)
+    auto claim = [&](int &c, int &f, int m, uint32_t *fill, int cmax, int which) -> bool {
+        if (c >= 0 && f + m <= LOG_CHUNK) return true;
+        if (c == -2) return false;
+        if (c >= 0 && lane == 0) fill[c] = (uint32_t)f;
+        unsigned long long got = 0;
+        if (lane == 0) got = atomicAdd(&P.ctr[which], 1ull);
+        const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)got);
+        if (g >= (uint32_t)cmax) {
+            overflow = true;
+            c = -2;
+            return false;
+        }
+        c = (int)g;
+        f = 0;
+        return true;
+    };
+
+    // work comes in batches of SLOTS items; lane q < SLOTS prepares the
+    // initial state of item base + q.  The next batch is claimed one batch
+    // ahead, so its atomic has long returned when it is needed.
+    unsigned long long next_base = 0;
+    if (lane == 0) next_base = atomicAdd(&P.ctr[CTR_WORK], (unsigned long long)SLOTS);
+    int b_left = 0, b_at = 0;
+    int w_i = 0, w_ok = 0, w_fwd = 0;
+    uint32_t w_e = 0u;
+    float w_x = 0.f, w_y = 0.f, w_tx = 0.f, w_ty = 0.f;
 
     // ---- pool access: logical entries [lo, top) are in LDS, [0, lo) spilled
     auto pool_load = [&](int j) -> Entry {
@@ -246,30 +304,52 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             const uint64_t free_slots = wave_ballot((int)lane < SLOTS && S.i < 0);
             if (!free_slots) break;
             const int s = __builtin_ctzll(free_slots);
-            int item = 0;
-            if (lane == 0) item = (int)atomicAdd(&P.ctr[CTR_WORK], 1ull);
-            item = wave_uniform(__shfl(item, 0, WAVE));
-            if (item >= P.n) { exhausted = true; break; }
-            const int i = COLD(order) ? wave_uniform(COLD(order)[item]) : item;
-            // initial condition (section "Using SUPA": energy, angle, impact point)
-            const float sc = COLD(e0)[i] * P.e_scale;
-            if (!(sc >= 0.0f) || !(sc < 4294967296.0f)) {
-                if (lane == 0) {
-                    atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_RANGE);
-                    for (int q = 0; q < 4; ++q) COLD(ledger)[4 * (int64_t)i + q] = 0;
-                    for (int q = 0; q < 6; ++q) COLD(counts)[6 * (int64_t)i + q] = 0;
+            if (b_at == b_left) {
+                const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)next_base);
+                if (base >= (uint32_t)P.n) {
+                    exhausted = true;
+                    break;
                 }
-                if ((P.outputs & 2u) && lane == 0) COLD(img_count)[i] = 0;
+                if (lane == 0) next_base = atomicAdd(&P.ctr[CTR_WORK], (unsigned long long)SLOTS);
+                b_left = min(SLOTS, P.n - (int)base);
+                b_at = 0;
+                if ((int)lane < b_left) {
+                    // initial condition (section "Using SUPA": energy, angle, impact point)
+                    const int item = (int)base + (int)lane;
+                    const int32_t *ord = COLD(order);
+                    const int i = ord ? ord[item] : item;
+                    const float sc = COLD(e0)[i] * P.e_scale;
+                    const bool ok = sc >= 0.0f && sc < 4294967296.0f;
+                    float sp, cp, sa, ca;
+                    sincosf(COLD(polar)[i], &sp, &cp);
+                    sincosf(COLD(azimuth)[i], &sa, &ca);
+                    const float tpol = sp / cp;
+                    const float *x0p = COLD(x0), *y0p = COLD(y0);
+                    w_i = i;
+                    w_ok = ok ? 1 : 0;
+                    w_e = ok ? (uint32_t)rintf(sc) : 0u;
+                    w_fwd = cp > 0.0f ? 1 : 0;
+                    w_tx = tpol * ca;
+                    w_ty = tpol * sa;
+                    w_x = x0p ? x0p[i] : 0.0f;
+                    w_y = y0p ? y0p[i] : 0.0f;
+                }
+            }
+            const int i = __builtin_amdgcn_readlane(w_i, b_at);
+            const bool ok = __builtin_amdgcn_readlane(w_ok, b_at) != 0;
+            const bool fwd0 = __builtin_amdgcn_readlane(w_fwd, b_at) != 0;
+            const uint32_t e_first = (uint32_t)__builtin_amdgcn_readlane((int)w_e, b_at);
+            const float x_first = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w_x), b_at));
+            const float y_first = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w_y), b_at));
+            const float tx0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w_tx), b_at));
+            const float ty0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(w_ty), b_at));
+            ++b_at;
+            if (!ok) {
+                if (lane == 0) atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_RANGE);
+                if ((int)lane < 4) COLD(ledger)[4 * (int64_t)i + lane] = 0;
+                if ((int)lane < 6) COLD(counts)[6 * (int64_t)i + lane] = 0;
                 continue;
             }
-            const uint32_t e_first = (uint32_t)rintf(sc);
-            float sp, cp, sa, ca;
-            sincosf(COLD(polar)[i], &sp, &cp);
-            sincosf(COLD(azimuth)[i], &sa, &ca);
-            const bool fwd0 = cp > 0.0f;
-            const float tpol = sp / cp;
-            const float x_first = COLD(x0) ? COLD(x0)[i] : 0.0f;
-            const float y_first = COLD(y0) ? COLD(y0)[i] : 0.0f;
             if ((int)lane == s) {
                 S.i = i;
                 S.sid = P.sid_base + (uint32_t)i;
@@ -283,24 +363,29 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                 S.e_esc = fwd0 ? 0u : e_first;
             }
             if (lane == 0 && fwd0) {
-                const Entry p0{x_first, y_first, tpol * ca, tpol * sa, e_first, 1u, 0u, 0,
-                               (uint32_t)s << 8};
+                const Entry p0{x_first, y_first, tx0, ty0, e_first, 1u, 0u, 0, (uint32_t)s << 8};
                 pool_store(top, p0);
             }
             if (fwd0) {
                 ++top;
                 lo = max(lo, top - PC);
             }
-            if (TREE && lane == 0) {
-                uint32_t *jn = jn_w + (int64_t)s * JN_COUNT * cap_n;
-                jn[JN_PARENT * cap_n] = (uint32_t)-1;
-                jn[JN_GEN * cap_n] = 0u;
-                jn[JN_X * cap_n] = __float_as_uint(x_first);
-                jn[JN_Y * cap_n] = __float_as_uint(y_first);
-                jn[JN_Z * cap_n] = 0u;
-                jn[JN_E * cap_n] = e_first;
-                jn[JN_LO * cap_n] = 1u;
-                jn[JN_HI * cap_n] = 0u;
+            if (TREE && claim(nc, nf, 1, P.nfill, P.n_chunks, CTR_NCHUNK)) {
+                if (lane == 0) {
+                    uint32_t *r = P.nlog + (int64_t)nc * (NL_FIELDS * LOG_CHUNK) + nf;
+                    r[NL_I * LOG_CHUNK] = (uint32_t)i;
+                    r[NL_IDX * LOG_CHUNK] = 0u;
+                    r[NL_PARENT * LOG_CHUNK] = (uint32_t)-1;
+                    r[NL_GK * LOG_CHUNK] = GK_PRIMARY;
+                    r[NL_X * LOG_CHUNK] = __float_as_uint(x_first);
+                    r[NL_Y * LOG_CHUNK] = __float_as_uint(y_first);
+                    r[NL_E * LOG_CHUNK] = e_first;
+                    if (keys) {
+                        r[NL_LO * LOG_CHUNK] = 1u;
+                        r[NL_HI * LOG_CHUNK] = 0u;
+                    }
+                }
+                nf += 1;
             }
         }
         const uint64_t active = wave_ballot((int)lane < SLOTS && S.i >= 0);
@@ -315,6 +400,7 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             qn -= nb;
             const int k = (int)(p.ks & 255u), slot = (int)(p.ks >> 8);
             const uint32_t sid = (uint32_t)__shfl((int)S.sid, slot, WAVE);
+            const int ish = __shfl(S.i, slot, WAVE);
             const uint4 w = philox4x32_10((uint32_t)k, sid, p.lo, p.hi, opaque_u32(P.seed_lo),
                                           opaque_u32(P.seed_hi));
             const uint64_t c1 = thr[k], c2 = thr[64 + k];
@@ -324,32 +410,35 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             const bool last = (k == N - 1);
             const uint64_t path = ((uint64_t)p.hi << 32) | p.lo;
 
-            // stops deposit: journal per shower
+            // stops deposit
             const uint64_t mstop = wave_ballot(is_stop);
             if (mstop) {
-                int pos = 0;
                 for_each_slot(mstop, slot, [&](int s0, uint64_t m) {
-                    const int base = slot_get(S.hits, s0);
-                    if ((m >> lane) & 1ull) pos = base + (int)lanes_below(m);
-                    if ((int)lane == s0) S.hits = base + (int)__popcll(m);
-                    if ((int)lane == s0) S.live -= (int)__popcll(m);
+                    if ((int)lane == s0) {
+                        S.hits += (int)__popcll(m);
+                        S.live -= (int)__popcll(m);
+                    }
                 });
-                if (is_stop) {
-                    atomicAdd(&shist[slot * 64 + k], 1u);
-                    if (pos < cap_h) {
-                        uint32_t *jh = jh_w + (int64_t)slot * JH_COUNT * cap_h;
-                        if (want_xy) {
-                            jh[JH_X * cap_h + pos] = __float_as_uint(p.x);
-                            jh[JH_Y * cap_h + pos] = __float_as_uint(p.y);
+                estop.add(slot, is_stop ? p.e : 0u);
+                if (recs) {
+                    uint32_t r = 0u;
+                    if (is_stop) r = atomicAdd(&shist[slot * 64 + k], 1u);
+                    const int m = (int)__popcll(mstop);
+                    if (claim(hc, hf, m, P.hfill, P.h_chunks, CTR_HCHUNK)) {
+                        if (is_stop) {
+                            uint32_t *rec = P.hlog + (int64_t)hc * (HL_FIELDS * LOG_CHUNK) + hf +
+                                            (int)lanes_below(mstop);
+                            rec[HL_I * LOG_CHUNK] = (uint32_t)ish;
+                            rec[HL_KR * LOG_CHUNK] = (uint32_t)k | (r << 6);
+                            rec[HL_X * LOG_CHUNK] = __float_as_uint(p.x);
+                            rec[HL_Y * LOG_CHUNK] = __float_as_uint(p.y);
+                            rec[HL_E * LOG_CHUNK] = p.e;
+                            if (keys) {
+                                rec[HL_LO * LOG_CHUNK] = p.lo;
+                                rec[HL_HI * LOG_CHUNK] = p.hi;
+                            }
                         }
-                        jh[JH_E * cap_h + pos] = p.e;
-                        if (keys) {
-                            jh[JH_LO * cap_h + pos] = p.lo;
-                            jh[JH_HI * cap_h + pos] = p.hi;
-                        }
-                        jh[JH_PK * cap_h + pos] = (uint32_t)k | KIND_STOP;
-                    } else {
-                        overflow = true;
+                        hf += m;
                     }
                 }
             }
@@ -367,30 +456,36 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                     if ((m >> lane) & 1ull) node_a = base + 2 * (int)lanes_below(m);
                     if ((int)lane == s0) S.nodes = base + 2 * (int)__popcll(m);
                 });
-                if (TREE && is_split) {
-                    if (node_a + 1 < cap_n) {
-                        uint32_t *q = jn_w + (int64_t)slot * JN_COUNT * cap_n + node_a;
-                        const float zk = zf + (float)k * dzp;
-                        const uint32_t gen = (uint32_t)(64 - __clzll(path));
-                        const uint64_t pa = path << 1;
-                        q[JN_PARENT * cap_n] = (uint32_t)p.node;
-                        q[JN_PARENT * cap_n + 1] = (uint32_t)p.node;
-                        q[JN_GEN * cap_n] = gen;
-                        q[JN_GEN * cap_n + 1] = gen;
-                        q[JN_X * cap_n] = __float_as_uint(p.x);
-                        q[JN_X * cap_n + 1] = __float_as_uint(p.x);
-                        q[JN_Y * cap_n] = __float_as_uint(p.y);
-                        q[JN_Y * cap_n + 1] = __float_as_uint(p.y);
-                        q[JN_Z * cap_n] = __float_as_uint(zk);
-                        q[JN_Z * cap_n + 1] = __float_as_uint(zk);
-                        q[JN_E * cap_n] = D.ea;
-                        q[JN_E * cap_n + 1] = D.eb;
-                        q[JN_LO * cap_n] = (uint32_t)pa;
-                        q[JN_HI * cap_n] = (uint32_t)(pa >> 32);
-                        q[JN_LO * cap_n + 1] = (uint32_t)pa | 1u;
-                        q[JN_HI * cap_n + 1] = (uint32_t)(pa >> 32);
-                    } else {
-                        overflow = true;
+                if (TREE) {
+                    const int m = 2 * (int)__popcll(msplit);
+                    if (claim(nc, nf, m, P.nfill, P.n_chunks, CTR_NCHUNK)) {
+                        if (is_split) {
+                            uint32_t *r = P.nlog + (int64_t)nc * (NL_FIELDS * LOG_CHUNK) + nf +
+                                          2 * (int)lanes_below(msplit);
+                            const uint32_t gk = (uint32_t)(64 - __clzll(path)) | ((uint32_t)k << 8);
+                            const uint64_t pa = path << 1;
+                            r[NL_I * LOG_CHUNK] = (uint32_t)ish;
+                            r[NL_I * LOG_CHUNK + 1] = (uint32_t)ish;
+                            r[NL_IDX * LOG_CHUNK] = (uint32_t)node_a;
+                            r[NL_IDX * LOG_CHUNK + 1] = (uint32_t)node_a + 1u;
+                            r[NL_PARENT * LOG_CHUNK] = (uint32_t)p.node;
+                            r[NL_PARENT * LOG_CHUNK + 1] = (uint32_t)p.node;
+                            r[NL_GK * LOG_CHUNK] = gk;
+                            r[NL_GK * LOG_CHUNK + 1] = gk;
+                            r[NL_X * LOG_CHUNK] = __float_as_uint(p.x);
+                            r[NL_X * LOG_CHUNK + 1] = __float_as_uint(p.x);
+                            r[NL_Y * LOG_CHUNK] = __float_as_uint(p.y);
+                            r[NL_Y * LOG_CHUNK + 1] = __float_as_uint(p.y);
+                            r[NL_E * LOG_CHUNK] = D.ea;
+                            r[NL_E * LOG_CHUNK + 1] = D.eb;
+                            if (keys) {
+                                r[NL_LO * LOG_CHUNK] = (uint32_t)pa;
+                                r[NL_HI * LOG_CHUNK] = (uint32_t)(pa >> 32);
+                                r[NL_LO * LOG_CHUNK + 1] = (uint32_t)pa | 1u;
+                                r[NL_HI * LOG_CHUNK + 1] = (uint32_t)(pa >> 32);
+                            }
+                        }
+                        nf += m;
                     }
                 }
             }
@@ -472,31 +567,33 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             const bool is_cut = valid && (uint64_t)p.e < P.t_cut;
             const uint64_t mcut = wave_ballot(is_cut);
             if (mcut) {
-                int hpos = 0;
+                const int ish = __shfl(S.i, slot, WAVE);
                 for_each_slot(mcut, slot, [&](int s0, uint64_t m) {
-                    const int base = slot_get(S.hits, s0);
-                    if ((m >> lane) & 1ull) hpos = base + (int)lanes_below(m);
                     if ((int)lane == s0) {
-                        S.hits = base + (int)__popcll(m);
+                        S.hits += (int)__popcll(m);
                         S.live -= (int)__popcll(m);
                     }
                 });
-                if (is_cut) {
-                    atomicAdd(&shist[slot * 64 + k], 1u);
-                    if (hpos < cap_h) {
-                        uint32_t *jh = jh_w + (int64_t)slot * JH_COUNT * cap_h;
-                        if (want_xy) {
-                            jh[JH_X * cap_h + hpos] = __float_as_uint(p.x);
-                            jh[JH_Y * cap_h + hpos] = __float_as_uint(p.y);
+                ecut.add(slot, is_cut ? p.e : 0u);
+                if (recs) {
+                    uint32_t r = 0u;
+                    if (is_cut) r = atomicAdd(&shist[slot * 64 + k], 1u);
+                    const int m = (int)__popcll(mcut);
+                    if (claim(hc, hf, m, P.hfill, P.h_chunks, CTR_HCHUNK)) {
+                        if (is_cut) {
+                            uint32_t *rec = P.hlog + (int64_t)hc * (HL_FIELDS * LOG_CHUNK) + hf +
+                                            (int)lanes_below(mcut);
+                            rec[HL_I * LOG_CHUNK] = (uint32_t)ish;
+                            rec[HL_KR * LOG_CHUNK] = (uint32_t)k | (r << 6);
+                            rec[HL_X * LOG_CHUNK] = __float_as_uint(p.x);
+                            rec[HL_Y * LOG_CHUNK] = __float_as_uint(p.y);
+                            rec[HL_E * LOG_CHUNK] = p.e;
+                            if (keys) {
+                                rec[HL_LO * LOG_CHUNK] = p.lo;
+                                rec[HL_HI * LOG_CHUNK] = p.hi;
+                            }
                         }
-                        jh[JH_E * cap_h + hpos] = p.e;
-                        if (keys) {
-                            jh[JH_LO * cap_h + hpos] = p.lo;
-                            jh[JH_HI * cap_h + hpos] = p.hi;
-                        }
-                        jh[JH_PK * cap_h + hpos] = (uint32_t)k;
-                    } else {
-                        overflow = true;
+                        hf += m;
                     }
                 }
             }
@@ -511,7 +608,8 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             if ((int)lane < SLOTS) S.live = 0;
         }
 
-        // ---- showers whose last particle is done
+        // ---- showers whose last particle is done: ledger, counts and the
+        // start of each plane's hits within the shower (only stores)
         uint64_t done = wave_ballot((int)lane < SLOTS && S.i >= 0 && S.live <= 0);
         while (done) {
             const int s = __builtin_ctzll(done);
@@ -525,140 +623,34 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             const uint32_t eesc = (uint32_t)slot_get((int)S.e_esc, s);
             const uint32_t e_first = (uint32_t)slot_get((int)S.e0, s);
             const int nsplit = (nn - 1) / 2;
-            const bool sh_over = wave_ballot(overflow) != 0 || nh > cap_h || (TREE && nn > cap_n);
-            uint32_t *const jh = jh_w + (int64_t)s * JH_COUNT * cap_h;
-            __threadfence_block();      // journal entries written by every lane
-
-            // counting sort of the hits by plane: the per-plane counts were
-            // kept in LDS while the shower ran
-            uint32_t *const hist = shist + s * 64;
-            const int plane_start = wave_excl_scan((int)hist[lane]);   // lane k: first hit of plane k
-            hist[lane] = (uint32_t)plane_start;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-
-            long long hit_start = 0, node_start = 0;
-            if (lane == 0) {
-                if (P.outputs & 3u)
-                    hit_start = (long long)atomicAdd(&P.ctr[CTR_HITS], (unsigned long long)nh);
-                if (TREE)
-                    node_start = (long long)atomicAdd(&P.ctr[CTR_NODES], (unsigned long long)nn);
-                atomicAdd(&P.ctr[CTR_STEPS], (unsigned long long)(nh + nsplit + npass));
-                atomicMax(&P.ctr[CTR_NEED_F], (unsigned long long)max_top);
-                atomicMax(&P.ctr[CTR_NEED_H], (unsigned long long)nh);
-                atomicMax(&P.ctr[CTR_NEED_N], (unsigned long long)nn);
-                if (sh_over) atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_OVERFLOW);
+            const uint32_t e_cut = wave_sum_u32(ecut.take(s));
+            const uint32_t e_stop = wave_sum_u32(estop.take(s));
+            if (recs) {
+                uint32_t *const hist = shist + s * 64;
+                const int plane_start = wave_excl_scan((int)hist[lane]);
+                if ((int)lane < N) COLD(pstart)[(int64_t)i * N + lane] = (uint32_t)plane_start;
+                hist[lane] = 0u;             // ready for the slot's next shower
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             }
-            hit_start = __shfl(hit_start, 0, WAVE);
-            node_start = __shfl(node_start, 0, WAVE);
-            const bool out_hits = (P.outputs & 1u) != 0, out_img = (P.outputs & 2u) != 0;
-            const bool write_hits = !sh_over && out_hits && hit_start + nh <= COLD(hit_capacity);
-            const bool write_img = !sh_over && out_img && hit_start + nh <= COLD(img_cap);
-            // library-owned hand-over buffer too small: grow and rerun (when the
-            // caller's hit arrays are the hand-over, the call reports CAPACITY)
-            if (out_img && !out_hits && !write_img && lane == 0)
-                atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_OVERFLOW);
-            if (lane == 0) {
-                if (out_hits) COLD(hit_offsets)[i] = hit_start;
-                if (out_img && !out_hits) COLD(img_seg)[i] = hit_start;
+            steps += (unsigned long long)(nh + nsplit + npass);
+            if ((int)lane < 4) {
+                const uint32_t v = lane == 0 ? e_first : lane == 1 ? e_stop : lane == 2 ? e_cut : eesc;
+                COLD(ledger)[4 * (int64_t)i + lane] = v;
             }
-            // the image kernel reads exactly this many hits of the shower: none
-            // when they could not be handed over (arrays too small, overflow)
-            if (out_img && lane == 0) COLD(img_count)[i] = write_img ? nh : 0;
-
-            // hit cloud in plane order (and the image kernel's copy), two
-            // journal entries per lane in flight
-            float *const hx = COLD(hit_x), *const hy = COLD(hit_y), *const he = COLD(hit_e);
-            int32_t *const hl = COLD(hit_layer);
-            uint64_t *const hk = COLD(hit_key);
-            uint32_t *const ie = COLD(img_e);
-            float *const ix = COLD(img_x), *const iy = COLD(img_y);
-            int32_t *const il = COLD(img_layer);
-            uint64_t e_stop = 0, e_cut = 0;
-            const int nread = sh_over ? 0 : nh;
-            for (int j0 = (int)lane; j0 < nread; j0 += 2 * WAVE) {
-                uint32_t pk[2], e[2], xb[2] = {0u, 0u}, yb[2] = {0u, 0u}, lo2[2] = {0u, 0u}, hi2[2] = {0u, 0u};
-                bool ok[2];
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int j = j0 + u * WAVE;
-                    ok[u] = j < nread;
-                    const int jj = ok[u] ? j : j0;
-                    pk[u] = jh[JH_PK * cap_h + jj];
-                    e[u] = jh[JH_E * cap_h + jj];
-                    if (want_xy) {
-                        xb[u] = jh[JH_X * cap_h + jj];
-                        yb[u] = jh[JH_Y * cap_h + jj];
-                    }
-                    if (keys) {
-                        lo2[u] = jh[JH_LO * cap_h + jj];
-                        hi2[u] = jh[JH_HI * cap_h + jj];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    if (!ok[u]) continue;
-                    if (pk[u] & KIND_STOP) e_stop += e[u]; else e_cut += e[u];
-                    const int q = (int)atomicAdd(&hist[pk[u] & 63u], 1u);
-                    const int64_t o = hit_start + q;
-                    const int layer = lay[pk[u] & 63u];
-                    if (write_hits) {
-                        hx[o] = __uint_as_float(xb[u]);
-                        hy[o] = __uint_as_float(yb[u]);
-                        he[o] = (float)e[u] * P.e_unscale;
-                        hl[o] = layer;
-                        if (keys) hk[o] = ((uint64_t)hi2[u] << 32) | lo2[u];
-                    }
-                    if (write_img) {
-                        ie[o] = e[u];
-                        if (!out_hits) {
-                            ix[o] = __uint_as_float(xb[u]);
-                            iy[o] = __uint_as_float(yb[u]);
-                            il[o] = layer;
-                        }
-                    }
-                }
-            }
-            e_stop = wave_sum_u64(e_stop);
-            e_cut = wave_sum_u64(e_cut);
-            hist[lane] = 0u;                 // ready for the slot's next shower
-            if (lane == 0) {
-                int64_t *led = (int64_t *)COLD(ledger) + 4 * (int64_t)i;
-                led[0] = e_first;
-                led[1] = (int64_t)e_stop;
-                led[2] = (int64_t)e_cut;
-                led[3] = eesc;
-                int32_t *cnt = COLD(counts) + 6 * (int64_t)i;
-                cnt[0] = nn;
-                cnt[1] = nh;
-                cnt[2] = nh + nsplit + npass;
-                cnt[3] = nsplit;
-                cnt[4] = nesc;
-                cnt[5] = nback;
+            if ((int)lane < 6) {
+                const int v = lane == 0 ? nn : lane == 1 ? nh : lane == 2 ? nh + nsplit + npass
+                            : lane == 3 ? nsplit : lane == 4 ? nesc : nback;
+                COLD(counts)[6 * (int64_t)i + lane] = v;
             }
             if ((int)lane == s) S.i = -1;
-
-            // propagation tree
-            if (TREE && !sh_over) {
-                if (lane == 0) COLD(node_offsets)[i] = node_start;
-                if (node_start + nn <= COLD(node_capacity)) {
-                    const uint32_t *jn = jn_w + (int64_t)s * JN_COUNT * cap_n;
-                    int32_t *const np_ = COLD(node_parent), *const ng = COLD(node_gen);
-                    float *const nvx = COLD(node_vx), *const nvy = COLD(node_vy);
-                    float *const nvz = COLD(node_vz), *const ne = COLD(node_e);
-                    uint64_t *const nk = COLD(node_key);
-                    for (int j = (int)lane; j < nn; j += WAVE) {
-                        const int64_t o = node_start + j;
-                        np_[o] = (int32_t)jn[JN_PARENT * cap_n + j];
-                        ng[o] = (int32_t)jn[JN_GEN * cap_n + j];
-                        nvx[o] = __uint_as_float(jn[JN_X * cap_n + j]);
-                        nvy[o] = __uint_as_float(jn[JN_Y * cap_n + j]);
-                        nvz[o] = __uint_as_float(jn[JN_Z * cap_n + j]);
-                        ne[o] = (float)jn[JN_E * cap_n + j] * P.e_unscale;
-                        if (keys) nk[o] = ((uint64_t)jn[JN_HI * cap_n + j] << 32) | jn[JN_LO * cap_n + j];
-                    }
-                }
-            }
         }
+    }
+    // close the open log chunks
+    if (lane == 0) {
+        if (hc >= 0) P.hfill[hc] = (uint32_t)hf;
+        if (TREE && nc >= 0) P.nfill[nc] = (uint32_t)nf;
+        atomicAdd(&P.ctr[CTR_STEPS], steps);
+        atomicMax(&P.ctr[CTR_NEED_F], (unsigned long long)max_top);
     }
     if (wave_ballot(overflow) && lane == 0) atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_OVERFLOW);
 }

@@ -1,0 +1,205 @@
+// supa_scatter.hip -- segment offsets and record placement after propagation.
+//
+// The propagation kernel leaves every hit and tree node as a record in a log
+// (chunks filled in whatever order the waves produced them) and, per shower,
+// its counts and the start of each plane's hits within the shower.  Here:
+//   scan     hit and node segment offsets = exclusive prefix sums of the
+//            showers' counts in batch order (three small kernels: tile sums,
+//            one-block scan of the tile sums, per-tile scan), so the output
+//            layout is the same on every run;
+//   scatter  every record goes to segment start + plane start + its rank
+//            within (shower, plane) for hits, segment start + its index
+//            within the shower for nodes.  Pure data movement, bounded by
+//            HBM bandwidth.
+// Nothing is written when the propagation reported an overflow (the batch is
+// rerun) or when the totals exceed the destination capacity.
+#include <algorithm>
+
+#include "supa_device.hpp"
+
+namespace supa {
+
+__device__ __forceinline__ long long block_sum_ll(long long v, long long *sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int w = (int)threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    long long t = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += sh[q];
+    __syncthreads();
+    return t;
+}
+
+// Exclusive scan across the block of one value per thread (blockDim.x a
+// multiple of 64, at most 1024); also returns the block total.
+__device__ __forceinline__ long long block_excl_scan_ll(long long v, long long *sh, long long *total) {
+    const int lane = (int)(threadIdx.x & 63), w = (int)threadIdx.x >> 6;
+    long long incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) sh[w] = incl;
+    __syncthreads();
+    long long before = 0, all = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+        if (q < w) before += sh[q];
+        all += sh[q];
+    }
+    __syncthreads();
+    *total = all;
+    return before + incl - v;
+}
+
+// tile sums of the hit and node counts
+__global__ void __launch_bounds__(SCAN_THREADS) scan_tiles(ScanParams S) {
+    __shared__ long long sh[SCAN_THREADS / 64];
+    const int64_t t0 = (int64_t)blockIdx.x * SCAN_TILE;
+    long long h = 0, nn = 0;
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        const int64_t i = t0 + q * SCAN_THREADS + threadIdx.x;
+        if (i < S.n) {
+            nn += S.counts[6 * i];
+            h += S.counts[6 * i + 1];
+        }
+    }
+    h = block_sum_ll(h, sh);
+    nn = block_sum_ll(nn, sh);
+    const int nt = (int)((S.n + SCAN_TILE - 1) / SCAN_TILE);
+    if (threadIdx.x == 0) {
+        S.partial[blockIdx.x] = h;
+        S.partial[nt + blockIdx.x] = nn;
+    }
+}
+
+// one block: tile sums -> tile offsets (in place), totals into the counters
+__global__ void __launch_bounds__(1024) scan_top(ScanParams S) {
+    __shared__ long long sh[16];
+    const int nt = (int)((S.n + SCAN_TILE - 1) / SCAN_TILE);
+    for (int a = 0; a < 2; ++a) {
+        long long carry = 0;
+        for (int b0 = 0; b0 < nt; b0 += 1024) {
+            const int b = b0 + (int)threadIdx.x;
+            const long long v = b < nt ? S.partial[a * nt + b] : 0;
+            long long tot = 0;
+            const long long ex = block_excl_scan_ll(v, sh, &tot);
+            if (b < nt) S.partial[a * nt + b] = carry + ex;
+            carry += tot;
+        }
+        if (threadIdx.x == 0) S.ctr[a == 0 ? CTR_HITS : CTR_NODES] = (unsigned long long)carry;
+    }
+}
+
+// per tile: offsets of its showers (SCAN_ITEMS consecutive showers per thread)
+__global__ void __launch_bounds__(SCAN_THREADS) scan_apply(ScanParams S) {
+    __shared__ long long sh[SCAN_THREADS / 64];
+    __shared__ int32_t cnt[2][SCAN_TILE];
+    const int64_t t0 = (int64_t)blockIdx.x * SCAN_TILE;
+    const int nt = (int)((S.n + SCAN_TILE - 1) / SCAN_TILE);
+    for (int q = 0; q < SCAN_ITEMS; ++q) {
+        const int l = q * SCAN_THREADS + (int)threadIdx.x;
+        const int64_t i = t0 + l;
+        cnt[0][l] = i < S.n ? S.counts[6 * i + 1] : 0;
+        cnt[1][l] = i < S.n ? S.counts[6 * i] : 0;
+    }
+    __syncthreads();
+    const int l0 = (int)threadIdx.x * SCAN_ITEMS;
+    for (int a = 0; a < 2; ++a) {
+        int64_t *out = a == 0 ? S.hoff : S.noff;
+        long long mine = 0;
+        for (int q = 0; q < SCAN_ITEMS; ++q) mine += cnt[a][l0 + q];
+        long long tot = 0;
+        long long o = S.partial[a * nt + blockIdx.x] + block_excl_scan_ll(mine, sh, &tot);
+        if (out) {
+            for (int q = 0; q < SCAN_ITEMS; ++q) {
+                const int64_t i = t0 + l0 + q;
+                if (i < S.n) out[i] = o;
+                o += cnt[a][l0 + q];
+            }
+        }
+    }
+}
+
+constexpr int SCATTER_THREADS = 256;
+
+__global__ void __launch_bounds__(SCATTER_THREADS) scatter_hits(ScatterParams Q, int32_t n) {
+    if (batch_failed(Q.ctr) || (int64_t)Q.ctr[CTR_HITS] > Q.hcap) return;
+    const int nch = (int)min(Q.ctr[CTR_HCHUNK], (unsigned long long)Q.h_chunks);
+    const int N = Q.n_planes;
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int fill = min((int)Q.hfill[c], LOG_CHUNK);
+        const uint32_t *rec = Q.hlog + (int64_t)c * (HL_FIELDS * LOG_CHUNK);
+        for (int j = (int)threadIdx.x; j < fill; j += SCATTER_THREADS) {
+            const uint32_t i = rec[HL_I * LOG_CHUNK + j];
+            const uint32_t kr = rec[HL_KR * LOG_CHUNK + j];
+            const int k = (int)(kr & 63u);
+            if (i >= (uint32_t)n || k >= N) continue;
+            const int64_t o = Q.hoff[i] + Q.pstart[(int64_t)i * N + k] + (kr >> 6);
+            if (o < 0 || o >= Q.hcap) continue;
+            const uint32_t x = rec[HL_X * LOG_CHUNK + j], y = rec[HL_Y * LOG_CHUNK + j];
+            const uint32_t e = rec[HL_E * LOG_CHUNK + j];
+            Q.hx[o] = __uint_as_float(x);
+            Q.hy[o] = __uint_as_float(y);
+            Q.hl[o] = Q.layer[k];
+            if (Q.he) Q.he[o] = (float)e * Q.e_unscale;
+            if (Q.hei) Q.hei[o] = e;
+            if (Q.hk)
+                Q.hk[o] = ((uint64_t)rec[HL_HI * LOG_CHUNK + j] << 32) | rec[HL_LO * LOG_CHUNK + j];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(SCATTER_THREADS) scatter_nodes(ScatterParams Q, int32_t n) {
+    if (batch_failed(Q.ctr) || (int64_t)Q.ctr[CTR_NODES] > Q.ncap) return;
+    const int nch = (int)min(Q.ctr[CTR_NCHUNK], (unsigned long long)Q.n_chunks);
+    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+        const int fill = min((int)Q.nfill[c], LOG_CHUNK);
+        const uint32_t *rec = Q.nlog + (int64_t)c * (NL_FIELDS * LOG_CHUNK);
+        for (int j = (int)threadIdx.x; j < fill; j += SCATTER_THREADS) {
+            const uint32_t i = rec[NL_I * LOG_CHUNK + j];
+            if (i >= (uint32_t)n) continue;
+            const int64_t o = Q.noff[i] + rec[NL_IDX * LOG_CHUNK + j];
+            if (o < 0 || o >= Q.ncap) continue;
+            const uint32_t gk = rec[NL_GK * LOG_CHUNK + j];
+            const uint32_t k = gk >> 8;
+            Q.np[o] = (int32_t)rec[NL_PARENT * LOG_CHUNK + j];
+            Q.ng[o] = (int32_t)(gk & 255u);
+            Q.nvx[o] = __uint_as_float(rec[NL_X * LOG_CHUNK + j]);
+            Q.nvy[o] = __uint_as_float(rec[NL_Y * LOG_CHUNK + j]);
+            Q.nvz[o] = k == 255u ? 0.0f : Q.z_first + (float)k * Q.dz;
+            Q.ne[o] = (float)rec[NL_E * LOG_CHUNK + j] * Q.e_unscale;
+            if (Q.nk)
+                Q.nk[o] = ((uint64_t)rec[NL_HI * LOG_CHUNK + j] << 32) | rec[NL_LO * LOG_CHUNK + j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+int64_t scan_partial_words(int64_t n) { return 2 * ((n + SCAN_TILE - 1) / SCAN_TILE); }
+
+hipError_t launch_scan(const ScanParams &S, hipStream_t s) {
+    if (S.n <= 0) return hipSuccess;
+    const int nt = (int)((S.n + SCAN_TILE - 1) / SCAN_TILE);
+    hipLaunchKernelGGL(scan_tiles, dim3(nt), dim3(SCAN_THREADS), 0, s, S);
+    hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, S);
+    hipLaunchKernelGGL(scan_apply, dim3(nt), dim3(SCAN_THREADS), 0, s, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const ScatterParams &Q, int32_t n, bool hits, bool nodes, int n_cu,
+                          hipStream_t s) {
+    const int blocks = n_cu * 8;
+    if (hits && Q.h_chunks > 0)
+        hipLaunchKernelGGL(scatter_hits, dim3(std::min(blocks, Q.h_chunks)), dim3(SCATTER_THREADS),
+                           0, s, Q, n);
+    if (nodes && Q.n_chunks > 0)
+        hipLaunchKernelGGL(scatter_nodes, dim3(std::min(blocks, Q.n_chunks)), dim3(SCATTER_THREADS),
+                           0, s, Q, n);
+    return hipGetLastError();
+}
+
+}  // namespace supa

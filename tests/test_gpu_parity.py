@@ -192,6 +192,10 @@ def test_chunked_batch_equals_whole():
     geom = workloads.geometry(w)
     e0, pol, az = workloads.initial_conditions(w, 90)
     whole, _ = run_gpu(geom, ALL, e0, pol, az, 9)
+    # segments are the exclusive prefix sums of the counts, in batch order
+    for off, col in (("hit_offsets", 1), ("node_offsets", 0)):
+        c = whole["counts"][:, col].astype(np.int64)
+        np.testing.assert_array_equal(whole[off], np.concatenate([[0], np.cumsum(c)[:-1]]))
     for s in range(0, 90, 30):
         part, _ = run_gpu(geom, ALL, e0[s:s + 30], pol[s:s + 30], az[s:s + 30], 9, base=s)
         np.testing.assert_array_equal(part["counts"], whole["counts"][s:s + 30])
@@ -200,8 +204,13 @@ def test_chunked_batch_equals_whole():
         for i in range(30):
             a = slice(part["hit_offsets"][i], part["hit_offsets"][i] + part["counts"][i, 1])
             b = slice(whole["hit_offsets"][s + i], whole["hit_offsets"][s + i] + whole["counts"][s + i, 1])
+            # same hits, bit for bit; compared in path-id order (the order
+            # within a plane is left open)
+            oa, ob = np.argsort(part["hit_key"][a]), np.argsort(whole["hit_key"][b])
             for k in ("hit_x", "hit_y", "hit_e", "hit_key", "hit_layer"):
-                np.testing.assert_array_equal(part[k][a], whole[k][b])
+                np.testing.assert_array_equal(part[k][a][oa], whole[k][b][ob])
+            # plane grouping: layers non-decreasing within the segment
+            assert (np.diff(part["hit_layer"][a]) >= 0).all()
 
 
 def sampled_segments(out, rows):
