@@ -23,11 +23,10 @@ hipError_t launch_propagate(const Params &P, int blocks, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t s);
 size_t propagate_lds_bytes(int pool_cap);
-hipError_t launch_images(const ImgParams &P, int n_cu, hipStream_t s);
+hipError_t launch_place(const PlaceParams &P, int n_cu, hipStream_t s);
 int64_t scan_partial_words(int64_t n);
 hipError_t launch_scan(const ScanParams &S, hipStream_t s);
-hipError_t launch_scatter(const ScatterParams &Q, int32_t n, bool hits, bool nodes, int n_cu,
-                          hipStream_t s);
+hipError_t launch_scatter_nodes(const ScatterParams &Q, int32_t n, int n_cu, hipStream_t s);
 }  // namespace supa
 
 // A device buffer that only grows (its contents are scratch).
@@ -80,8 +79,7 @@ struct supa_ctx {
     int pool_cap = 128;                  // particle-pool entries kept in LDS
     int spill_cap = 4096;                // per-wave spill entries
     int64_t h_chunks = 0, n_chunks = 0;  // log chunks (grow on demand)
-    int64_t img_cap = 0;                 // hand-over hits to the image kernel
-    DevBuf spill, hlog, nlog, shower, himg;
+    DevBuf spill, hlog, nlog, shower;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     float timing[3] = {0, 0, 0};
     std::string err;
@@ -165,11 +163,17 @@ extern "C" supa_status supa_validate_geometry(const supa_geometry *g) {
     return s;
 }
 
-static constexpr int64_t kChunkWaste = 127;   // records a closed chunk may leave unused
+// hit-log chunks that hold `records` records for `waves` waves: full chunks,
+// plus the partly filled chunk every shower slot may leave at the end
+static int64_t hit_chunks_for(int64_t records, int64_t waves) {
+    return (records + supa::HIT_CHUNK - 1) / supa::HIT_CHUNK + waves * supa::SLOTS + 8;
+}
 
-// log chunks that hold `records` records for `waves` waves
-static int64_t chunks_for(int64_t records, int64_t waves) {
-    return (records + supa::LOG_CHUNK - kChunkWaste - 1) / (supa::LOG_CHUNK - kChunkWaste) + waves + 8;
+// node-log chunks: a closed chunk may leave up to 127 records unused (a
+// phase appends at most 2 per lane), plus one open chunk per wave
+static int64_t node_chunks_for(int64_t records, int64_t waves) {
+    const int64_t per = supa::LOG_CHUNK - 127;
+    return (records + per - 1) / per + waves + 8;
 }
 
 static supa_status nomem(supa_ctx *c, const char *what, size_t bytes) {
@@ -261,7 +265,7 @@ extern "C" supa_status supa_destroy(supa_ctx *c) {
     if (!c) return SUPA_ERR_STATE;
     (void)hipSetDevice(c->device);
     if (c->stream || true) (void)hipStreamSynchronize(c->stream);
-    for (DevBuf *d : {&c->spill, &c->hlog, &c->nlog, &c->shower, &c->himg}) d->release();
+    for (DevBuf *d : {&c->spill, &c->hlog, &c->nlog, &c->shower}) d->release();
     if (c->d_layer) (void)hipFree(c->d_layer);
     if (c->d_layer_plane_start) (void)hipFree(c->d_layer_plane_start);
     if (c->d_layer_planes) (void)hipFree(c->d_layer_planes);
@@ -288,7 +292,7 @@ extern "C" supa_status supa_set_launch(supa_ctx *c, int32_t waves_per_cu, int32_
     if (frontier_cap) c->pool_cap = frontier_cap;
     // initial log sizes in records (the logs grow by themselves when a batch
     // needs more; small values exercise that path)
-    if (hit_cap) c->h_chunks = std::max<int64_t>(1, (hit_cap + supa::LOG_CHUNK - 1) / supa::LOG_CHUNK);
+    if (hit_cap) c->h_chunks = std::max<int64_t>(1, (hit_cap + supa::HIT_CHUNK - 1) / supa::HIT_CHUNK);
     if (node_cap) c->n_chunks = std::max<int64_t>(1, (node_cap + supa::LOG_CHUNK - 1) / supa::LOG_CHUNK);
     return SUPA_OK;
 }
@@ -358,49 +362,34 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
     // for images only), unless earlier batches needed more
     if (recs) {
         const int64_t hint = hits_out ? out->hit_capacity : 64 * n;
-        if (c->h_chunks == 0) c->h_chunks = chunks_for(std::min<int64_t>(hint, (int64_t)1 << 28), waves);
+        c->h_chunks = std::max(c->h_chunks, hit_chunks_for(std::min<int64_t>(hint, (int64_t)1 << 28), waves));
     }
-    if (tree && c->n_chunks == 0)
-        c->n_chunks = chunks_for(std::min<int64_t>(out->node_capacity, (int64_t)1 << 28), waves);
-    if (images && !hits_out && c->img_cap == 0) c->img_cap = std::max<int64_t>(1024, 64 * n);
+    if (tree)
+        c->n_chunks = std::max(c->n_chunks,
+                               node_chunks_for(std::min<int64_t>(out->node_capacity, (int64_t)1 << 28), waves));
 
     for (int attempt = 0; attempt < 8; ++attempt) {
-        // scratch: per-wave spill, logs, per-shower plane starts / offsets / scan
-        // tile sums, and the image kernel's hand-over
+        // scratch: per-wave spill, logs, per-shower log starts and scan tile sums
         const size_t spill_b = al((size_t)waves * supa::POOL_FIELDS * c->spill_cap * 4);
         if (!c->spill.ensure(spill_b)) return nomem(c, "spill area", spill_b);
-        const size_t hfill_b = recs ? al((size_t)c->h_chunks * 4) : 0;
-        const size_t hlog_b = recs ? hfill_b + (size_t)c->h_chunks * supa::HL_FIELDS * supa::LOG_CHUNK * 4 : 0;
+        const size_t hnext_b = recs ? al((size_t)c->h_chunks * 4) : 0;
+        const size_t hlog_b = recs ? hnext_b + (size_t)c->h_chunks * supa::HL_FIELDS * supa::HIT_CHUNK * 4 : 0;
         if (recs && !c->hlog.ensure(hlog_b)) return nomem(c, "hit log", hlog_b);
         const size_t nfill_b = tree ? al((size_t)c->n_chunks * 4) : 0;
         const size_t nlog_b = tree ? nfill_b + (size_t)c->n_chunks * supa::NL_FIELDS * supa::LOG_CHUNK * 4 : 0;
         if (tree && !c->nlog.ensure(nlog_b)) return nomem(c, "node log", nlog_b);
-        const size_t pstart_b = recs ? al((size_t)n * N * 4) : 0;
-        const size_t hoff_b = (images && !hits_out) ? al((size_t)n * 8) : 0;
+        const size_t hstart_b = recs ? al((size_t)n * 8) : 0;
         const size_t part_b = al((size_t)supa::scan_partial_words(n) * 8);
-        const size_t shower_b = pstart_b + hoff_b + part_b;
+        const size_t shower_b = hstart_b + part_b;
         if (!c->shower.ensure(shower_b)) return nomem(c, "per-shower scratch", shower_b);
-        // hand-over to the image kernel: integer energies (and, without hit
-        // outputs, positions and layers) at the hits' final places
-        const int64_t icap = images ? (hits_out ? out->hit_capacity : c->img_cap) : 0;
-        const size_t ie_b = al((size_t)std::max<int64_t>(icap, 1) * 4);
-        const size_t himg_b = images ? (hits_out ? ie_b : 4 * ie_b) : 0;
-        if (images && !c->himg.ensure(himg_b)) return nomem(c, "image hand-over", himg_b);
         char *sh = (char *)c->shower.p;
-        uint32_t *d_pstart = recs ? (uint32_t *)sh : nullptr;
-        int64_t *d_hoff_img = (images && !hits_out) ? (int64_t *)(sh + pstart_b) : nullptr;
-        int64_t *d_part = (int64_t *)(sh + pstart_b + hoff_b);
-        char *hi = (char *)c->himg.p;
-        uint32_t *d_img_e = images ? (uint32_t *)hi : nullptr;
-        float *d_img_x = (images && !hits_out) ? (float *)(hi + ie_b) : nullptr;
-        float *d_img_y = (images && !hits_out) ? (float *)(hi + 2 * ie_b) : nullptr;
-        int32_t *d_img_l = (images && !hits_out) ? (int32_t *)(hi + 3 * ie_b) : nullptr;
+        int64_t *d_hstart = recs ? (int64_t *)sh : nullptr;
+        int64_t *d_part = (int64_t *)(sh + hstart_b);
 
         supa::Params P{};
         P.n_planes = N;
         P.z_first = (float)c->g.z_first;
         P.dz = (float)c->g.dz;
-        P.layer = c->d_layer;
         P.c1 = c->d_c1;
         P.c2 = c->d_c2;
         P.t_cut = c->t_cut;
@@ -410,7 +399,6 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         P.angle_a = (float)c->g.angle_a;
         P.angle_b = (float)c->g.angle_b;
         P.e_scale = std::ldexp(1.0f, c->g.energy_frac_bits);
-        P.e_unscale = std::ldexp(1.0f, -c->g.energy_frac_bits);
         P.seed_lo = (uint32_t)seed;
         P.seed_hi = (uint32_t)(seed >> 32);
         P.n = (int32_t)n;
@@ -421,13 +409,14 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         P.pool_cap = c->pool_cap;
         P.spill_cap = c->spill_cap;
         P.spill = (uint32_t *)c->spill.p;
-        P.hfill = recs ? (uint32_t *)c->hlog.p : nullptr;
-        P.hlog = recs ? (uint32_t *)((char *)c->hlog.p + hfill_b) : nullptr;
+        P.hnext = recs ? (uint32_t *)c->hlog.p : nullptr;
+        P.hlog = recs ? (uint32_t *)((char *)c->hlog.p + hnext_b) : nullptr;
         P.h_chunks = recs ? (int32_t)c->h_chunks : 0;
         P.nfill = tree ? (uint32_t *)c->nlog.p : nullptr;
         P.nlog = tree ? (uint32_t *)((char *)c->nlog.p + nfill_b) : nullptr;
         P.n_chunks = tree ? (int32_t)c->n_chunks : 0;
         P.ctr = c->d_ctr;
+        const float e_unscale = std::ldexp(1.0f, -c->g.energy_frac_bits);
 
         supa::Cold &K = *c->h_cold;
         std::memset(&K, 0, sizeof(K));
@@ -439,39 +428,51 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         K.order = nullptr;
         K.ledger = out->ledger;
         K.counts = out->counts;
-        K.pstart = d_pstart;
+        K.hstart = d_hstart;
 
         supa::ScanParams SP{};
         SP.n = (int32_t)n;
         SP.counts = out->counts;
-        SP.hoff = hits_out ? out->hit_offsets : d_hoff_img;
+        SP.hoff = hits_out ? out->hit_offsets : nullptr;
         SP.noff = tree ? out->node_offsets : nullptr;
         SP.partial = d_part;
         SP.ctr = c->d_ctr;
 
+        supa::PlaceParams H{};
+        H.n = (int32_t)n;
+        H.n_planes = N;
+        H.L = c->n_layers;
+        H.nx = c->g.img_nx;
+        H.ny = c->g.img_ny;
+        H.x0 = (float)c->g.img_x0;
+        H.y0 = (float)c->g.img_y0;
+        H.sx = images ? (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0)) : 0.0f;
+        H.sy = images ? (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0)) : 0.0f;
+        H.e_unscale = e_unscale;
+        H.ctr = c->d_ctr;
+        H.counts = out->counts;
+        H.hstart = d_hstart;
+        H.hlog = P.hlog;
+        H.hnext = P.hnext;
+        H.h_chunks = P.h_chunks;
+        H.layer = c->d_layer;
+        H.hoff = SP.hoff;
+        H.hcap = hits_out ? out->hit_capacity : 0;
+        H.hx = hits_out ? out->hit_x : nullptr;
+        H.hy = hits_out ? out->hit_y : nullptr;
+        H.he = hits_out ? out->hit_e : nullptr;
+        H.hl = hits_out ? out->hit_layer : nullptr;
+        H.hk = (hits_out && P.keys) ? out->hit_key : nullptr;
+        H.images = images ? out->images : nullptr;
+
         supa::ScatterParams Q{};
-        Q.n_planes = N;
-        Q.layer = c->d_layer;
         Q.z_first = P.z_first;
         Q.dz = P.dz;
-        Q.e_unscale = P.e_unscale;
-        Q.keys = P.keys;
+        Q.e_unscale = e_unscale;
         Q.ctr = c->d_ctr;
-        Q.hlog = P.hlog;
-        Q.hfill = P.hfill;
         Q.nlog = P.nlog;
         Q.nfill = P.nfill;
-        Q.h_chunks = P.h_chunks;
         Q.n_chunks = P.n_chunks;
-        Q.hoff = SP.hoff;
-        Q.pstart = d_pstart;
-        Q.hcap = hits_out ? out->hit_capacity : c->img_cap;
-        Q.hx = hits_out ? out->hit_x : d_img_x;
-        Q.hy = hits_out ? out->hit_y : d_img_y;
-        Q.he = hits_out ? out->hit_e : nullptr;
-        Q.hl = hits_out ? out->hit_layer : d_img_l;
-        Q.hk = (hits_out && P.keys) ? out->hit_key : nullptr;
-        Q.hei = d_img_e;
         Q.noff = SP.noff;
         Q.ncap = tree ? out->node_capacity : 0;
         Q.np = out->node_parent;
@@ -488,36 +489,9 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         HIP_TRY(c, supa::launch_zero_counters(c->d_ctr, c->stream));
         HIP_TRY(c, supa::launch_propagate(P, (int)waves, c->stream));
         HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
-        if (recs || tree) {
-            HIP_TRY(c, supa::launch_scan(SP, c->stream));
-            HIP_TRY(c, supa::launch_scatter(Q, (int32_t)n, recs, tree, c->n_cu, c->stream));
-        }
-        if (images) {
-            supa::ImgParams I{};
-            I.n = (int32_t)n;
-            I.L = c->n_layers;
-            I.nx = c->g.img_nx;
-            I.ny = c->g.img_ny;
-            I.n_planes = N;
-            I.x0 = (float)c->g.img_x0;
-            I.y0 = (float)c->g.img_y0;
-            I.sx = (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0));
-            I.sy = (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0));
-            I.e_unscale = P.e_unscale;
-            I.seg = SP.hoff;
-            I.count = out->counts + 1;
-            I.count_stride = 6;
-            I.ctr = c->d_ctr;
-            I.cap = Q.hcap;
-            I.x = Q.hx;
-            I.y = Q.hy;
-            I.e = d_img_e;
-            I.layer = Q.hl;
-            I.layer_plane_start = c->d_layer_plane_start;
-            I.layer_planes = c->d_layer_planes;
-            I.images = out->images;
-            HIP_TRY(c, supa::launch_images(I, c->n_cu, c->stream));
-        }
+        if (recs || tree) HIP_TRY(c, supa::launch_scan(SP, c->stream));
+        if (recs) HIP_TRY(c, supa::launch_place(H, c->n_cu, c->stream));
+        if (tree) HIP_TRY(c, supa::launch_scatter_nodes(Q, (int32_t)n, c->n_cu, c->stream));
         HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
         HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_COUNT * sizeof(unsigned long long),
                                   hipMemcpyDeviceToHost, c->stream));
@@ -543,9 +517,9 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
             c->spill_cap = (int)std::min<int64_t>((int64_t)1 << 30,
                                                   std::max<int64_t>(c->spill_cap, round_up_pow2(nf + 1)));
             if (recs && (int64_t)h[supa::CTR_HCHUNK] > c->h_chunks)
-                c->h_chunks = std::max(2 * c->h_chunks, chunks_for(total_hits, waves));
+                c->h_chunks = std::max(2 * c->h_chunks, hit_chunks_for(total_hits, waves));
             if (tree && (int64_t)h[supa::CTR_NCHUNK] > c->n_chunks)
-                c->n_chunks = std::max(2 * c->n_chunks, chunks_for(total_nodes, waves));
+                c->n_chunks = std::max(2 * c->n_chunks, node_chunks_for(total_nodes, waves));
             continue;
         }
         // only meaningful when nothing overflowed (a lost spill entry breaks
@@ -553,11 +527,6 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         if (flags & supa::FLAG_INTERNAL) {
             c->broken = true;
             return fail(c, SUPA_ERR_DEVICE, "internal particle accounting error in the propagation kernel");
-        }
-        if (images && !hits_out && total_hits > c->img_cap) {
-            // the library's own hand-over was too small: grow it and rerun
-            c->img_cap = total_hits + total_hits / 8 + 1024;
-            continue;
         }
         out->total_steps = (int64_t)h[supa::CTR_STEPS];
         out->total_hits = hits_out ? total_hits : 0;

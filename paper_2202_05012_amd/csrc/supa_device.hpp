@@ -73,19 +73,26 @@ struct Cold {
     const int32_t *order;       // work order (permutation of 0..n-1) or null
     uint64_t *ledger;           // [n][4]
     int32_t *counts;            // [n][6]
-    uint32_t *pstart;           // [n][n_planes]: first hit of each plane within the shower
+    int64_t *hstart;            // [n]: log position of the shower's first hit record
 };
 
-// Hit and node records leave the propagation kernel through logs: chunks of
-// LOG_CHUNK records that a wave fills in the order its phases produce them
-// (fields stored as separate arrays within a chunk, so a wave's stores are
-// contiguous); a chunk is claimed with one atomic and its fill count is
-// written when it is closed.  The scatter kernel moves every record to its
-// final place once all showers are counted.
+// Hit records leave the propagation kernel through a log of chunks of
+// HIT_CHUNK records (fields stored as separate arrays within a chunk).  Each
+// shower slot of a wave fills its own chain of chunks: when the slot's chunk
+// is full the next one is claimed with one atomic and linked from it, so the
+// records of one shower follow each other along the chain, starting at the
+// position (chunk * HIT_CHUNK + offset) noted when the shower started.  The
+// placement kernel walks each shower's chain once.
+constexpr int HIT_CHUNK_LOG2 = 10;
+constexpr int HIT_CHUNK = 1 << HIT_CHUNK_LOG2;
+// hit record: position, integer energy, plane, path id (with keys)
+enum { HL_X = 0, HL_Y, HL_E, HL_K, HL_LO, HL_HI, HL_FIELDS };
+
+// Tree nodes go to a log of chunks of LOG_CHUNK records that a wave fills in
+// the order its phases produce them (a chunk is claimed with one atomic and
+// its fill count written when it is closed); the scatter kernel moves every
+// record to its place once all showers are counted.
 constexpr int LOG_CHUNK = 2048;
-// hit record: shower index, plane | rank within (shower, plane) << 6,
-// position, integer energy, path id (with keys)
-enum { HL_I = 0, HL_KR, HL_X, HL_Y, HL_E, HL_LO, HL_HI, HL_FIELDS };
 // node record: shower index, index within the shower, parent index,
 // generation | plane << 8 (plane 255: the primary, vertex z = 0), vertex
 // x and y, integer energy, path id (with keys)
@@ -96,7 +103,6 @@ constexpr uint32_t GK_PRIMARY = 255u << 8;
 struct Params {
     int32_t n_planes;
     float z_first, dz;          // flight lengths: first plane from z = 0, then dz
-    const int32_t *layer;       // [n_planes]
     const uint64_t *c1, *c2;    // [n_planes] stop / split thresholds (<= 2^32)
     uint64_t t_cut;             // energy threshold in fixed point
     uint32_t f_lo;              // energy fraction F = f_lo + floor(w1 * f_w / 2^32)
@@ -104,7 +110,6 @@ struct Params {
     int32_t angle_mode;
     float angle_a, angle_b;
     float e_scale;              // 2^s
-    float e_unscale;            // 2^-s
     uint32_t seed_lo, seed_hi;
     int32_t n;                  // showers in the batch
     uint32_t sid_base;
@@ -114,8 +119,8 @@ struct Params {
     int32_t pool_cap;           // particle-pool entries kept in LDS (power of 2, >= 128)
     int32_t spill_cap;          // pool entries per wave that can spill to global memory
     uint32_t *spill;            // per wave: POOL_FIELDS x spill_cap
-    uint32_t *hlog, *hfill;     // hit log: h_chunks x HL_FIELDS x LOG_CHUNK, fill counts
-    uint32_t *nlog, *nfill;     // node log: n_chunks x NL_FIELDS x LOG_CHUNK, fill counts
+    uint32_t *hlog, *hnext;     // hit log: h_chunks x HL_FIELDS x HIT_CHUNK; chain links
+    uint32_t *nlog, *nfill;     // node log: n_chunks x NL_FIELDS x LOG_CHUNK; fill counts
     int32_t h_chunks, n_chunks;
     unsigned long long *ctr;    // device counters, see CTR_*
 };
@@ -131,27 +136,38 @@ struct ScanParams {
 };
 constexpr int SCAN_THREADS = 256, SCAN_ITEMS = 16, SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 
-// Moves log records to their final places (supa_scatter.hip).
+// Moves node records to their final places (supa_scatter.hip).
 struct ScatterParams {
-    int32_t n_planes;
-    const int32_t *layer;       // [n_planes]
     float z_first, dz, e_unscale;
-    bool keys;
     const unsigned long long *ctr;
-    const uint32_t *hlog, *hfill, *nlog, *nfill;
-    int32_t h_chunks, n_chunks;
-    const int64_t *hoff;        // [n] segment starts of the hits
-    const uint32_t *pstart;     // [n][n_planes]
-    int64_t hcap;               // entries of the hit arrays below
-    float *hx, *hy, *he;        // positions; float energies (or null)
-    int32_t *hl;                // layers
-    uint64_t *hk;               // path ids (or null)
-    uint32_t *hei;              // integer energies for the image kernel (or null)
+    const uint32_t *nlog, *nfill;
+    int32_t n_chunks;
     const int64_t *noff;        // [n] segment starts of the nodes
     int64_t ncap;
     int32_t *np, *ng;
     float *nvx, *nvy, *nvz, *ne;
-    uint64_t *nk;
+    uint64_t *nk;               // path ids (or null)
+};
+
+// Per shower: hit records from the log to the output arrays (grouped by
+// plane) and per-layer images binned from them (supa_place.hip).
+struct PlaceParams {
+    int32_t n, n_planes, L, nx, ny;
+    float x0, y0, sx, sy;        // cell = floor((x - x0) * sx)
+    float e_unscale;             // 2^-s
+    const unsigned long long *ctr;
+    const int32_t *counts;       // [n][6]: [1] hits
+    const int64_t *hstart;       // [n] log position of each shower's first record
+    const uint32_t *hlog, *hnext;
+    int32_t h_chunks;
+    const int32_t *layer;        // [n_planes]
+    const int64_t *hoff;         // [n] segment starts (with hit outputs)
+    int64_t hcap;
+    float *hx, *hy, *he;         // hit outputs, or null
+    int32_t *hl;
+    uint64_t *hk;                // path ids, or null
+    float *images;               // [n][L][ny][nx], or null
+    int32_t slab_rows;           // image rows binned per LDS pass
 };
 
 // Arguments of the surrogate's matrix product (supa_mlp.hip).
@@ -164,26 +180,6 @@ struct GemmArgs {
     void *C;             // float [M][ldc] (EPI_F32, EPI_BIAS_F32) or bf16 [M][ldc]
     int ldc;
     uint16_t *pre;       // EPI_BIAS_GELU: pre-activation out; EPI_GELU_GRAD: in (bf16 [M][ldc])
-};
-
-// Parameters of the image kernel (supa_images.hip).
-struct ImgParams {
-    int32_t n, L, nx, ny, n_planes;
-    float x0, y0, sx, sy;        // cell = floor((x - x0) * sx)
-    float e_unscale;             // 2^-s
-    const int64_t *seg;          // [n] first hit of each shower
-    const int32_t *count;        // hits of shower i: count[count_stride * i]
-    int32_t count_stride;
-    const unsigned long long *ctr;   // the call's counters: nothing is binned unless
-                                     // every hit was placed (no overflow, total <= cap)
-    int64_t cap;                 // entries of x, y, e, layer
-    const float *x, *y;          // hit coordinates
-    const uint32_t *e;           // integer hit energies
-    const int32_t *layer;        // hit layers (-1: not read out)
-    const int32_t *layer_plane_start, *layer_planes;   // planes of each layer (CSR)
-    float *images;               // [n][L][ny][nx]
-    int32_t slab_layers;         // whole layers per slab (0: bands of rows)
-    int32_t slab_rows;           // rows per band when one layer does not fit
 };
 
 enum {

@@ -1,0 +1,280 @@
+// supa_place.hip -- hit clouds and per-layer images from the hit log.
+//
+// One 512-thread workgroup takes one shower at a time and walks the chain of
+// log chunks that holds its hit records (the propagation kernel wrote them
+// there in the order it produced them):
+//   hit clouds  count the records per plane (LDS), turn the counts into plane
+//               starts within the shower's segment, and write every record
+//               to segment start + the next free place of its plane, so the
+//               segment is grouped by plane (order within a plane is free);
+//   images      (paper, appendix "Downsampling": a region of interest per
+//               layer, a grid of cells, and per cell the summed energy of the
+//               points in it) an LDS slab holding whole layers, or a band of
+//               rows of one large layer, is cleared, the integer energies of
+//               its hits are added with LDS atomics (integer sums: order-free
+//               and exact) and the slab is streamed out as float once, so
+//               every image byte is written exactly once.
+// Up to PL_WIN records per shower stay in registers between these passes;
+// larger showers are read again per pass.
+#include <algorithm>
+
+#include "supa_device.hpp"
+
+namespace supa {
+
+constexpr int PL_THREADS = 512;
+constexpr int PL_UNROLL = 4;
+constexpr int PL_WIN = PL_THREADS * PL_UNROLL;      // records per window (two chunks)
+constexpr int PL_SLAB_WORDS = 8192;                 // 32 KB of LDS per workgroup
+static_assert(PL_WIN <= 2 * HIT_CHUNK, "a window spans at most three chunks");
+
+// Barrier for hand-offs through LDS only: waits for this wave's LDS
+// operations, not for its global stores, which stay in flight (a full
+// __syncthreads would also wait for every store to reach memory).
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+struct Window {
+    float x[PL_UNROLL], y[PL_UNROLL];
+    uint32_t e[PL_UNROLL], lo[PL_UNROLL], hi[PL_UNROLL];
+    int k[PL_UNROLL];            // plane, -1 for no record
+};
+
+// Shared state of the chain walk of the current shower.
+struct Chain {
+    int c0, f0;                  // chunk and offset of the first record
+    int cur_h, cur_c;            // last chunk reached (hop index, chunk id)
+    int win[3];                  // chunks of the current window
+    int bad;                     // a link pointed outside the log
+};
+
+// Thread 0 follows the links up to the chunks of window w (records
+// [w*PL_WIN, min(nh, (w+1)*PL_WIN))); every thread then reads them from ch.
+__device__ __forceinline__ void walk_to_window(const PlaceParams &Q, Chain &ch, int w, int nh) {
+    if (threadIdx.x == 0 && !ch.bad) {
+        const int lo = (ch.f0 + w * PL_WIN) >> HIT_CHUNK_LOG2;
+        const int hi = (ch.f0 + min(nh, (w + 1) * PL_WIN) - 1) >> HIT_CHUNK_LOG2;
+        int h = ch.cur_h, c = ch.cur_c;
+        if (h > lo) {                // new pass: start over
+            h = 0;
+            c = ch.c0;
+        }
+        while (h < lo && c >= 0) {
+            c = (int)Q.hnext[c];
+            c = c < Q.h_chunks ? c : -1;
+            ++h;
+        }
+        ch.cur_h = h;
+        ch.cur_c = c;
+        for (int q = 0; q <= hi - lo; ++q) {
+            ch.win[q] = c;
+            if (c < 0) ch.bad = 1;
+            if (q < hi - lo && c >= 0) {
+                c = (int)Q.hnext[c];
+                c = c < Q.h_chunks ? c : -1;
+            }
+        }
+    }
+    lds_barrier();
+}
+
+__device__ __forceinline__ Window empty_window() {
+    Window W;
+#pragma unroll
+    for (int u = 0; u < PL_UNROLL; ++u) {
+        W.x[u] = W.y[u] = 0.0f;
+        W.e[u] = W.lo[u] = W.hi[u] = 0u;
+        W.k[u] = -1;
+    }
+    return W;
+}
+
+// Records of window w held by this thread (after walk_to_window(w); nothing
+// when a link of the chain was bad).
+__device__ __forceinline__ Window load_window(const PlaceParams &Q, const Chain &ch, int w, int nh,
+                                              bool keys) {
+    Window W = empty_window();
+    if (ch.bad) return W;
+    const int lo = (ch.f0 + w * PL_WIN) >> HIT_CHUNK_LOG2;
+#pragma unroll
+    for (int u = 0; u < PL_UNROLL; ++u) {
+        const int j = w * PL_WIN + u * PL_THREADS + (int)threadIdx.x;
+        if (j < nh) {
+            const int pos = ch.f0 + j;
+            const int c = ch.win[(pos >> HIT_CHUNK_LOG2) - lo];
+            const uint32_t *rec = Q.hlog + (int64_t)c * (HL_FIELDS * HIT_CHUNK) + (pos & (HIT_CHUNK - 1));
+            W.x[u] = __uint_as_float(rec[HL_X * HIT_CHUNK]);
+            W.y[u] = __uint_as_float(rec[HL_Y * HIT_CHUNK]);
+            W.e[u] = rec[HL_E * HIT_CHUNK];
+            W.k[u] = (int)rec[HL_K * HIT_CHUNK];
+            if (keys) {
+                W.lo[u] = rec[HL_LO * HIT_CHUNK];
+                W.hi[u] = rec[HL_HI * HIT_CHUNK];
+            }
+        }
+    }
+    return W;
+}
+
+__device__ __forceinline__ void count_planes(const Window &W, uint32_t *cnt, int N) {
+#pragma unroll
+    for (int u = 0; u < PL_UNROLL; ++u)
+        if (W.k[u] >= 0 && W.k[u] < N) atomicAdd(&cnt[W.k[u]], 1u);
+}
+
+__device__ __forceinline__ void place_hits(const PlaceParams &Q, const Window &W, uint32_t *cur,
+                                           const int32_t *lay, int64_t seg, int N) {
+#pragma unroll
+    for (int u = 0; u < PL_UNROLL; ++u) {
+        const int k = W.k[u];
+        if (k < 0 || k >= N) continue;
+        const int64_t o = seg + atomicAdd(&cur[k], 1u);
+        Q.hx[o] = W.x[u];
+        Q.hy[o] = W.y[u];
+        Q.he[o] = (float)W.e[u] * Q.e_unscale;
+        Q.hl[o] = lay[k];
+        if (Q.hk) Q.hk[o] = ((uint64_t)W.hi[u] << 32) | W.lo[u];
+    }
+}
+
+// adds the window's hits that fall in image rows [row0, row0 + rows) to the slab
+__device__ __forceinline__ void bin_window(const PlaceParams &Q, const Window &W, const int32_t *lay,
+                                           uint32_t *slab, int row0, int rows, int N) {
+#pragma unroll
+    for (int u = 0; u < PL_UNROLL; ++u) {
+        const int k = W.k[u];
+        const int l = (k >= 0 && k < N) ? lay[k] : -1;
+        const float cx = floorf((W.x[u] - Q.x0) * Q.sx);
+        const float cy = floorf((W.y[u] - Q.y0) * Q.sy);
+        const bool in = l >= 0 && cx >= 0.0f && cx < (float)Q.nx && cy >= 0.0f && cy < (float)Q.ny;
+        const int r = (in ? l * Q.ny + (int)cy : -1) - row0;
+        if (in && r >= 0 && r < rows) atomicAdd(&slab[r * Q.nx + (int)cx], W.e[u]);
+    }
+}
+
+__device__ __forceinline__ void write_slab(const PlaceParams &Q, const uint32_t *slab, float *dst,
+                                           int words) {
+    if ((words & 3) == 0 && (((uintptr_t)dst) & 15) == 0) {
+        for (int q = 4 * (int)threadIdx.x; q < words; q += 4 * PL_THREADS) {
+            const uint4 v = *(const uint4 *)(slab + q);
+            // streamed out once: non-temporal
+            typedef float f4 __attribute__((ext_vector_type(4)));
+            const f4 f = {(float)v.x * Q.e_unscale, (float)v.y * Q.e_unscale,
+                          (float)v.z * Q.e_unscale, (float)v.w * Q.e_unscale};
+            __builtin_nontemporal_store(f, (f4 *)(dst + q));
+        }
+    } else {
+        for (int q = (int)threadIdx.x; q < words; q += PL_THREADS) dst[q] = (float)slab[q] * Q.e_unscale;
+    }
+}
+
+__device__ __forceinline__ void clear_slab(uint32_t *slab, int words) {
+    int q = 4 * (int)threadIdx.x;
+    for (; q + 3 < words; q += 4 * PL_THREADS) *(uint4 *)(slab + q) = make_uint4(0u, 0u, 0u, 0u);
+    for (int r = (words & ~3) + (int)threadIdx.x; r < words; r += PL_THREADS) slab[r] = 0u;
+}
+
+__global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
+    extern __shared__ uint32_t slab[];
+    __shared__ int32_t lay[64];
+    __shared__ uint32_t cnt[64];
+    __shared__ Chain ch;
+    // records are valid only when the propagation succeeded; hit outputs
+    // only when they all fit
+    if (batch_failed(Q.ctr)) return;
+    const bool hits = Q.hx != nullptr, img = Q.images != nullptr;
+    if (hits && (int64_t)Q.ctr[CTR_HITS] > Q.hcap) return;
+    const int N = Q.n_planes;
+    const bool keys = Q.hk != nullptr;
+    if (threadIdx.x < 64) lay[threadIdx.x] = (int)threadIdx.x < N ? Q.layer[threadIdx.x] : -1;
+    const int total_rows = Q.L * Q.ny;
+
+    for (int i = blockIdx.x; i < Q.n; i += gridDim.x) {
+        const int nh = Q.counts[6 * (int64_t)i + 1];
+        const int64_t st = Q.hstart[i];
+        if (threadIdx.x == 0) {
+            ch.c0 = st >= 0 ? (int)(st >> HIT_CHUNK_LOG2) : -1;
+            ch.f0 = (int)(st & (HIT_CHUNK - 1));
+            ch.cur_h = 0;
+            ch.cur_c = ch.c0;
+            ch.bad = (nh > 0 && (st < 0 || ch.c0 >= Q.h_chunks)) ? 1 : 0;
+        }
+        if (threadIdx.x < 64) cnt[threadIdx.x] = 0u;
+        lds_barrier();
+        const int nwin = (nh + PL_WIN - 1) / PL_WIN;
+        // window 0 stays in registers for every pass
+        walk_to_window(Q, ch, 0, nh);
+        const bool ok = !ch.bad;
+        const Window W0 = load_window(Q, ch, 0, nh, keys);
+
+        if (hits && ok) {
+            const int64_t seg = Q.hoff[i];
+            if (seg >= 0 && seg + nh <= Q.hcap) {
+                // hits per plane -> first place of each plane in the segment
+                count_planes(W0, cnt, N);
+                for (int w = 1; w < nwin; ++w) {
+                    walk_to_window(Q, ch, w, nh);
+                    count_planes(load_window(Q, ch, w, nh, false), cnt, N);
+                }
+                lds_barrier();
+                if (threadIdx.x < 64) {
+                    const uint32_t v = cnt[threadIdx.x];
+                    uint32_t incl = v;
+#pragma unroll
+                    for (int off = 1; off < 64; off <<= 1) {
+                        const uint32_t t = __shfl_up(incl, off, 64);
+                        if ((int)threadIdx.x >= off) incl += t;
+                    }
+                    cnt[threadIdx.x] = incl - v;
+                }
+                lds_barrier();
+                place_hits(Q, W0, cnt, lay, seg, N);
+                for (int w = 1; w < nwin; ++w) {
+                    walk_to_window(Q, ch, w, nh);
+                    place_hits(Q, load_window(Q, ch, w, nh, keys), cnt, lay, seg, N);
+                }
+            }
+        }
+
+        if (img) {
+            float *dst = Q.images + (int64_t)i * total_rows * Q.nx;
+            for (int row0 = 0; row0 < total_rows; row0 += Q.slab_rows) {
+                const int rows = min(total_rows - row0, Q.slab_rows);
+                const int words = rows * Q.nx;
+                clear_slab(slab, words);
+                lds_barrier();
+                if (ok) {
+                    bin_window(Q, W0, lay, slab, row0, rows, N);
+                    for (int w = 1; w < nwin; ++w) {
+                        walk_to_window(Q, ch, w, nh);
+                        bin_window(Q, load_window(Q, ch, w, nh, false), lay, slab, row0, rows, N);
+                    }
+                }
+                lds_barrier();
+                write_slab(Q, slab, dst + (int64_t)row0 * Q.nx, words);
+                lds_barrier();
+            }
+        }
+        lds_barrier();
+    }
+}
+
+hipError_t launch_place(const PlaceParams &P0, int n_cu, hipStream_t s) {
+    if (P0.n <= 0 || (!P0.hx && !P0.images)) return hipSuccess;
+    PlaceParams P = P0;
+    if (P.images) {
+        // whole layers per slab when they fit, else bands of rows
+        const int64_t lw = (int64_t)P.ny * P.nx;
+        P.slab_rows = lw <= PL_SLAB_WORDS ? (int)(PL_SLAB_WORDS / lw) * P.ny
+                                          : std::max(1, PL_SLAB_WORDS / P.nx);
+    }
+    const int blocks = std::min(P.n, n_cu * 4);
+    hipLaunchKernelGGL(supa_place, dim3(blocks), dim3(PL_THREADS),
+                       P.images ? PL_SLAB_WORDS * 4 : 0, s, P);
+    return hipGetLastError();
+}
+
+}  // namespace supa

@@ -138,6 +138,8 @@ struct Slots {
     int live;        // particles of the shower in the pool or the draw queue
     int hits, nodes, passes, escaped, backward;
     uint32_t e_esc;  // escaped energy (fits: energies of a shower sum to e0)
+    int hc, hf;      // the slot's hit-log chunk (-1: none) and its fill
+    int hs_c, hs_f;  // where the shower's first hit record goes
 };
 
 __device__ __forceinline__ int slot_get(int v, int s) { return __builtin_amdgcn_readlane(v, s); }
@@ -172,9 +174,9 @@ __device__ __forceinline__ int wave_excl_scan(int v) {
 }
 
 // LDS words of one wave: pool + draw queue + the stop / split thresholds of
-// every plane + per-shower plane histograms of the hits
+// every plane
 __host__ __device__ constexpr int lds_words(int pool_cap) {
-    return POOL_FIELDS * pool_cap + POOL_FIELDS * QCAP + 2 * 2 * 64 + SLOTS * 64;
+    return POOL_FIELDS * pool_cap + POOL_FIELDS * QCAP + 2 * 2 * 64;
 }
 
 // Keeps a wave-uniform value in scalar registers but hides it from loop-
@@ -220,13 +222,11 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
     uint32_t *const pool = lds;            // [POOL_FIELDS][PC], entry j at slot j & (PC-1)
     uint32_t *const queue = pool + POOL_FIELDS * PC;           // [POOL_FIELDS][QCAP]
     uint64_t *const thr = (uint64_t *)(queue + POOL_FIELDS * QCAP);  // c1[64], c2[64]
-    uint32_t *const shist = (uint32_t *)(thr + 128);           // [SLOTS][64] hits per plane
 
     for (int k = (int)lane; k < 64; k += WAVE) {
         thr[k] = k < N ? P.c1[k] : 0ull;
         thr[64 + k] = k < N ? P.c2[k] : 0ull;
     }
-    for (int q = (int)lane; q < SLOTS * 64; q += WAVE) shist[q] = 0u;
 
     const int64_t G = P.spill_cap;
     uint32_t *const spill = P.spill + wave * POOL_FIELDS * G;
@@ -238,6 +238,8 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
     S.sid = S.e0 = 0u;
     S.live = S.hits = S.nodes = S.passes = S.escaped = S.backward = 0;
     S.e_esc = 0u;
+    S.hc = S.hs_c = -1;
+    S.hf = S.hs_f = 0;
     // per-lane partial sums of the energy each slot's shower deposited by
     // cuts and by stops (a shower's energies sum to e0 < 2^32)
     SlotSums ecut, estop;
@@ -249,26 +251,78 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
     unsigned long long steps = 0;
     const float zf = P.z_first, dzp = P.dz;
 
-    // open log chunks (-1: none yet, -2: log full) and their fill
-    int hc = -1, hf = 0, nc = -1, nf = 0;
-    // room for m more records in the open chunk of a log: closes it and
-    // claims the next one when they do not fit; false once the log is full
-    // (the batch is then rerun with a larger log)
-    auto claim = [&](int &c, int &f, int m, uint32_t *fill, int cmax, int which) -> bool {
-        if (c >= 0 && f + m <= LOG_CHUNK) return true;
-        if (c == -2) return false;
-        if (c >= 0 && lane == 0) fill[c] = (uint32_t)f;
+    // open node-log chunk (-1: none yet, -2: log full) and its fill
+    int nc = -1, nf = 0;
+    // room for m more node records in the open chunk: closes it and claims
+    // the next one when they do not fit; false once the log is full (the
+    // batch is then rerun with a larger log)
+    auto claim_nodes = [&](int m) -> bool {
+        if (nc >= 0 && nf + m <= LOG_CHUNK) return true;
+        if (nc == -2) return false;
+        if (nc >= 0 && lane == 0) P.nfill[nc] = (uint32_t)nf;
         unsigned long long got = 0;
-        if (lane == 0) got = atomicAdd(&P.ctr[which], 1ull);
+        if (lane == 0) got = atomicAdd(&P.ctr[CTR_NCHUNK], 1ull);
         const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)got);
-        if (g >= (uint32_t)cmax) {
+        if (g >= (uint32_t)P.n_chunks) {
             overflow = true;
-            c = -2;
+            nc = -2;
             return false;
         }
-        c = (int)g;
-        f = 0;
+        nc = (int)g;
+        nf = 0;
         return true;
+    };
+    // a fresh hit-log chunk, or -1 once the log is full
+    bool hlog_full = false;
+    auto claim_hit_chunk = [&]() -> int {
+        if (hlog_full) return -1;
+        unsigned long long got = 0;
+        if (lane == 0) got = atomicAdd(&P.ctr[CTR_HCHUNK], 1ull);
+        const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)got);
+        if (g >= (uint32_t)P.h_chunks) {
+            hlog_full = true;
+            overflow = true;
+            return -1;
+        }
+        return (int)g;
+    };
+    // appends the hit records of the lanes of m (all of slot s0) to the
+    // slot's chain; x, y, e, k, lo, hi are this lane's hit
+    auto append_hits = [&](int s0, uint64_t m, float x, float y, uint32_t e, int k, uint32_t lo,
+                           uint32_t hi) {
+        int c = slot_get(S.hc, s0), f = slot_get(S.hf, s0);
+        if (c < 0) return;
+        const int cnt = (int)__popcll(m);
+        int c2 = -1;
+        if (f + cnt > HIT_CHUNK) {
+            c2 = claim_hit_chunk();
+            if (c2 >= 0 && lane == 0) P.hnext[c] = (uint32_t)c2;
+        }
+        if ((m >> lane) & 1ull) {
+            const int pos = f + (int)lanes_below(m);
+            const int cc = pos < HIT_CHUNK ? c : c2;
+            if (cc >= 0) {
+                uint32_t *rec = P.hlog + (int64_t)cc * (HL_FIELDS * HIT_CHUNK) + (pos & (HIT_CHUNK - 1));
+                rec[HL_X * HIT_CHUNK] = __float_as_uint(x);
+                rec[HL_Y * HIT_CHUNK] = __float_as_uint(y);
+                rec[HL_E * HIT_CHUNK] = e;
+                rec[HL_K * HIT_CHUNK] = (uint32_t)k;
+                if (keys) {
+                    rec[HL_LO * HIT_CHUNK] = lo;
+                    rec[HL_HI * HIT_CHUNK] = hi;
+                }
+            }
+        }
+        if (f + cnt > HIT_CHUNK) {
+            c = c2;
+            f += cnt - HIT_CHUNK;
+        } else {
+            f += cnt;
+        }
+        if ((int)lane == s0) {
+            S.hc = c;
+            S.hf = f;
+        }
     };
 
     // work comes in batches of SLOTS items; lane q < SLOTS prepares the
@@ -350,7 +404,19 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                 if ((int)lane < 6) COLD(counts)[6 * (int64_t)i + lane] = 0;
                 continue;
             }
+            int hc0 = -1, hf0 = 0;
+            if (recs) {
+                // the shower's hits start at its slot's chain position
+                hc0 = slot_get(S.hc, s);
+                hf0 = slot_get(S.hf, s);
+                if (hc0 < 0 || hf0 >= HIT_CHUNK) {
+                    hc0 = claim_hit_chunk();
+                    hf0 = 0;
+                }
+            }
             if ((int)lane == s) {
+                S.hc = S.hs_c = hc0;
+                S.hf = S.hs_f = hf0;
                 S.i = i;
                 S.sid = P.sid_base + (uint32_t)i;
                 S.e0 = e_first;
@@ -370,7 +436,7 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                 ++top;
                 lo = max(lo, top - PC);
             }
-            if (TREE && claim(nc, nf, 1, P.nfill, P.n_chunks, CTR_NCHUNK)) {
+            if (TREE && claim_nodes(1)) {
                 if (lane == 0) {
                     uint32_t *r = P.nlog + (int64_t)nc * (NL_FIELDS * LOG_CHUNK) + nf;
                     r[NL_I * LOG_CHUNK] = (uint32_t)i;
@@ -400,7 +466,6 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             qn -= nb;
             const int k = (int)(p.ks & 255u), slot = (int)(p.ks >> 8);
             const uint32_t sid = (uint32_t)__shfl((int)S.sid, slot, WAVE);
-            const int ish = __shfl(S.i, slot, WAVE);
             const uint4 w = philox4x32_10((uint32_t)k, sid, p.lo, p.hi, opaque_u32(P.seed_lo),
                                           opaque_u32(P.seed_hi));
             const uint64_t c1 = thr[k], c2 = thr[64 + k];
@@ -418,29 +483,9 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                         S.hits += (int)__popcll(m);
                         S.live -= (int)__popcll(m);
                     }
+                    if (recs) append_hits(s0, m, p.x, p.y, p.e, k, p.lo, p.hi);
                 });
                 estop.add(slot, is_stop ? p.e : 0u);
-                if (recs) {
-                    uint32_t r = 0u;
-                    if (is_stop) r = atomicAdd(&shist[slot * 64 + k], 1u);
-                    const int m = (int)__popcll(mstop);
-                    if (claim(hc, hf, m, P.hfill, P.h_chunks, CTR_HCHUNK)) {
-                        if (is_stop) {
-                            uint32_t *rec = P.hlog + (int64_t)hc * (HL_FIELDS * LOG_CHUNK) + hf +
-                                            (int)lanes_below(mstop);
-                            rec[HL_I * LOG_CHUNK] = (uint32_t)ish;
-                            rec[HL_KR * LOG_CHUNK] = (uint32_t)k | (r << 6);
-                            rec[HL_X * LOG_CHUNK] = __float_as_uint(p.x);
-                            rec[HL_Y * LOG_CHUNK] = __float_as_uint(p.y);
-                            rec[HL_E * LOG_CHUNK] = p.e;
-                            if (keys) {
-                                rec[HL_LO * LOG_CHUNK] = p.lo;
-                                rec[HL_HI * LOG_CHUNK] = p.hi;
-                            }
-                        }
-                        hf += m;
-                    }
-                }
             }
 
             Daughters D;
@@ -458,7 +503,8 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                 });
                 if (TREE) {
                     const int m = 2 * (int)__popcll(msplit);
-                    if (claim(nc, nf, m, P.nfill, P.n_chunks, CTR_NCHUNK)) {
+                    const int ish = __shfl(S.i, slot, WAVE);
+                    if (claim_nodes(m)) {
                         if (is_split) {
                             uint32_t *r = P.nlog + (int64_t)nc * (NL_FIELDS * LOG_CHUNK) + nf +
                                           2 * (int)lanes_below(msplit);
@@ -567,35 +613,14 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             const bool is_cut = valid && (uint64_t)p.e < P.t_cut;
             const uint64_t mcut = wave_ballot(is_cut);
             if (mcut) {
-                const int ish = __shfl(S.i, slot, WAVE);
                 for_each_slot(mcut, slot, [&](int s0, uint64_t m) {
                     if ((int)lane == s0) {
                         S.hits += (int)__popcll(m);
                         S.live -= (int)__popcll(m);
                     }
+                    if (recs) append_hits(s0, m, p.x, p.y, p.e, k, p.lo, p.hi);
                 });
                 ecut.add(slot, is_cut ? p.e : 0u);
-                if (recs) {
-                    uint32_t r = 0u;
-                    if (is_cut) r = atomicAdd(&shist[slot * 64 + k], 1u);
-                    const int m = (int)__popcll(mcut);
-                    if (claim(hc, hf, m, P.hfill, P.h_chunks, CTR_HCHUNK)) {
-                        if (is_cut) {
-                            uint32_t *rec = P.hlog + (int64_t)hc * (HL_FIELDS * LOG_CHUNK) + hf +
-                                            (int)lanes_below(mcut);
-                            rec[HL_I * LOG_CHUNK] = (uint32_t)ish;
-                            rec[HL_KR * LOG_CHUNK] = (uint32_t)k | (r << 6);
-                            rec[HL_X * LOG_CHUNK] = __float_as_uint(p.x);
-                            rec[HL_Y * LOG_CHUNK] = __float_as_uint(p.y);
-                            rec[HL_E * LOG_CHUNK] = p.e;
-                            if (keys) {
-                                rec[HL_LO * LOG_CHUNK] = p.lo;
-                                rec[HL_HI * LOG_CHUNK] = p.hi;
-                            }
-                        }
-                        hf += m;
-                    }
-                }
             }
             const bool to_q = valid && !is_cut;
             const uint64_t mq = wave_ballot(to_q);
@@ -608,8 +633,8 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             if ((int)lane < SLOTS) S.live = 0;
         }
 
-        // ---- showers whose last particle is done: ledger, counts and the
-        // start of each plane's hits within the shower (only stores)
+        // ---- showers whose last particle is done: ledger, counts and where
+        // its hit records start (only stores)
         uint64_t done = wave_ballot((int)lane < SLOTS && S.i >= 0 && S.live <= 0);
         while (done) {
             const int s = __builtin_ctzll(done);
@@ -625,12 +650,9 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             const int nsplit = (nn - 1) / 2;
             const uint32_t e_cut = wave_sum_u32(ecut.take(s));
             const uint32_t e_stop = wave_sum_u32(estop.take(s));
-            if (recs) {
-                uint32_t *const hist = shist + s * 64;
-                const int plane_start = wave_excl_scan((int)hist[lane]);
-                if ((int)lane < N) COLD(pstart)[(int64_t)i * N + lane] = (uint32_t)plane_start;
-                hist[lane] = 0u;             // ready for the slot's next shower
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (recs && lane == 0) {
+                const int hs_c = slot_get(S.hs_c, s), hs_f = slot_get(S.hs_f, s);
+                COLD(hstart)[i] = hs_c < 0 ? -1 : (int64_t)hs_c * HIT_CHUNK + hs_f;
             }
             steps += (unsigned long long)(nh + nsplit + npass);
             if ((int)lane < 4) {
@@ -645,9 +667,8 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             if ((int)lane == s) S.i = -1;
         }
     }
-    // close the open log chunks
+    // close the open node-log chunk
     if (lane == 0) {
-        if (hc >= 0) P.hfill[hc] = (uint32_t)hf;
         if (TREE && nc >= 0) P.nfill[nc] = (uint32_t)nf;
         atomicAdd(&P.ctr[CTR_STEPS], steps);
         atomicMax(&P.ctr[CTR_NEED_F], (unsigned long long)max_top);

@@ -1,16 +1,12 @@
-// supa_scatter.hip -- segment offsets and record placement after propagation.
+// supa_scatter.hip -- segment offsets, and tree nodes to their places.
 //
-// The propagation kernel leaves every hit and tree node as a record in a log
-// (chunks filled in whatever order the waves produced them) and, per shower,
-// its counts and the start of each plane's hits within the shower.  Here:
 //   scan     hit and node segment offsets = exclusive prefix sums of the
 //            showers' counts in batch order (three small kernels: tile sums,
 //            one-block scan of the tile sums, per-tile scan), so the output
 //            layout is the same on every run;
-//   scatter  every record goes to segment start + plane start + its rank
-//            within (shower, plane) for hits, segment start + its index
-//            within the shower for nodes.  Pure data movement, bounded by
-//            HBM bandwidth.
+//   scatter  every node record of the log (chunks filled in whatever order
+//            the waves produced them) goes to its shower's segment start +
+//            its index within the shower.  Pure data movement.
 // Nothing is written when the propagation reported an overflow (the batch is
 // rerun) or when the totals exceed the destination capacity.
 #include <algorithm>
@@ -124,33 +120,6 @@ __global__ void __launch_bounds__(SCAN_THREADS) scan_apply(ScanParams S) {
 
 constexpr int SCATTER_THREADS = 256;
 
-__global__ void __launch_bounds__(SCATTER_THREADS) scatter_hits(ScatterParams Q, int32_t n) {
-    if (batch_failed(Q.ctr) || (int64_t)Q.ctr[CTR_HITS] > Q.hcap) return;
-    const int nch = (int)min(Q.ctr[CTR_HCHUNK], (unsigned long long)Q.h_chunks);
-    const int N = Q.n_planes;
-    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
-        const int fill = min((int)Q.hfill[c], LOG_CHUNK);
-        const uint32_t *rec = Q.hlog + (int64_t)c * (HL_FIELDS * LOG_CHUNK);
-        for (int j = (int)threadIdx.x; j < fill; j += SCATTER_THREADS) {
-            const uint32_t i = rec[HL_I * LOG_CHUNK + j];
-            const uint32_t kr = rec[HL_KR * LOG_CHUNK + j];
-            const int k = (int)(kr & 63u);
-            if (i >= (uint32_t)n || k >= N) continue;
-            const int64_t o = Q.hoff[i] + Q.pstart[(int64_t)i * N + k] + (kr >> 6);
-            if (o < 0 || o >= Q.hcap) continue;
-            const uint32_t x = rec[HL_X * LOG_CHUNK + j], y = rec[HL_Y * LOG_CHUNK + j];
-            const uint32_t e = rec[HL_E * LOG_CHUNK + j];
-            Q.hx[o] = __uint_as_float(x);
-            Q.hy[o] = __uint_as_float(y);
-            Q.hl[o] = Q.layer[k];
-            if (Q.he) Q.he[o] = (float)e * Q.e_unscale;
-            if (Q.hei) Q.hei[o] = e;
-            if (Q.hk)
-                Q.hk[o] = ((uint64_t)rec[HL_HI * LOG_CHUNK + j] << 32) | rec[HL_LO * LOG_CHUNK + j];
-        }
-    }
-}
-
 __global__ void __launch_bounds__(SCATTER_THREADS) scatter_nodes(ScatterParams Q, int32_t n) {
     if (batch_failed(Q.ctr) || (int64_t)Q.ctr[CTR_NODES] > Q.ncap) return;
     const int nch = (int)min(Q.ctr[CTR_NCHUNK], (unsigned long long)Q.n_chunks);
@@ -190,15 +159,10 @@ hipError_t launch_scan(const ScanParams &S, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const ScatterParams &Q, int32_t n, bool hits, bool nodes, int n_cu,
-                          hipStream_t s) {
-    const int blocks = n_cu * 8;
-    if (hits && Q.h_chunks > 0)
-        hipLaunchKernelGGL(scatter_hits, dim3(std::min(blocks, Q.h_chunks)), dim3(SCATTER_THREADS),
-                           0, s, Q, n);
-    if (nodes && Q.n_chunks > 0)
-        hipLaunchKernelGGL(scatter_nodes, dim3(std::min(blocks, Q.n_chunks)), dim3(SCATTER_THREADS),
-                           0, s, Q, n);
+hipError_t launch_scatter_nodes(const ScatterParams &Q, int32_t n, int n_cu, hipStream_t s) {
+    if (Q.n_chunks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(scatter_nodes, dim3(std::min(n_cu * 8, Q.n_chunks)), dim3(SCATTER_THREADS), 0,
+                       s, Q, n);
     return hipGetLastError();
 }
 
