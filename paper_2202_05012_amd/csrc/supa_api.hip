@@ -75,7 +75,7 @@ struct supa_ctx {
     supa::Cold *h_cold = nullptr;          // its pinned host staging copy
     // launch settings and scratch
     int n_cu = 0;
-    int waves_per_cu = 10;
+    int waves_per_cu = 16;
     int pool_cap = 128;                  // particle-pool entries kept in LDS
     int spill_cap = 4096;                // per-wave spill entries
     int64_t h_chunks = 0, n_chunks = 0;  // log chunks (grow on demand)

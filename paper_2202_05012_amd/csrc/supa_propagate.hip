@@ -1,26 +1,26 @@
 // supa_propagate.hip -- the SUPA propagation kernel for gfx950.
 //
 // Each wave (64 lanes, one workgroup) keeps up to SLOTS showers in flight and
-// pulls new ones from a device work queue whenever its work runs low, so one
-// launch of a few waves per compute unit runs a whole batch however uneven
-// its showers are.  A shower is the tree of Algorithm 1 (section "Propagation
-// Model": at each slice every live particle stops, splits or passes); its
-// pending particles, tagged with their shower slot and next plane, sit in a
+// pulls new ones from a device work queue, SLOTS at a time, whenever its work
+// runs low, so one launch of a few waves per compute unit runs a whole batch
+// however uneven its showers are.  A shower is the tree of Algorithm 1
+// (section "Propagation Model": at each slice every live particle stops,
+// splits or passes).  Every pending particle has already flown to the plane
+// where it must draw, and sits, tagged with its shower slot and plane, in a
 // per-wave pool in LDS (a stack: depth-first, so it stays small; its oldest
-// entries spill to global memory only for very large showers).  Work is done
-// in two event phases so that every lane of a phase does the same thing:
-//   A  take 64 particles from the pool: free flight to their plane, threshold
-//      test; particles below threshold deposit (a hit), the others go to a
-//      draw queue;
-//   B  take 64 particles from the draw queue: one Philox block each, the
-//      three-way choice, split kinematics; daughters go back to the pool.
-// Hits and tree nodes are appended to per-shower journals (positions from a
-// wave ballot and a count of the set lanes below, per shower slot).  When a
-// shower's last particle is done, the wave sorts its hits by plane (a
-// counting sort on per-plane counts kept in LDS), copies them into the
-// caller's arrays at a segment reserved with one atomic, and writes the
-// ledger and counts; per-layer images are binned afterwards by the image
-// kernel (supa_images.hip) from the plane-sorted hits.
+// entries spill to global memory only for very large showers).  One step
+// takes up to 64 particles off the pool: one Philox block each, the three-way
+// choice, the split kinematics; whatever goes on (daughters, passers) flies
+// straight to the next plane, where it either deposits at once (below the
+// energy threshold) or goes back on the pool.  So every lane of a step does
+// the same work, and a particle costs one pool round trip per plane.
+// Deposits become hit records in a log: each shower slot fills its own chain
+// of log chunks (positions from a wave ballot and a count of the set lanes
+// below), so a shower's records follow each other; the ledger sums live in
+// registers.  When a shower's last particle is done the wave writes its
+// ledger, counts and the log position of its first hit -- stores only.  The
+// placement kernel (supa_place.hip) later puts the hits into the caller's
+// arrays and bins the images; tree nodes go through a log of their own.
 // Results depend only on (seed, shower id, path id): the random stream is
 // keyed by the particle, not by the lane or wave that happens to process it.
 #include "supa_device.hpp"
@@ -135,7 +135,7 @@ struct Slots {
     int i;           // batch index of the shower, -1 when the slot is free
     uint32_t sid;    // global shower id
     uint32_t e0;     // fixed-point initial energy
-    int live;        // particles of the shower in the pool or the draw queue
+    int live;        // particles of the shower in the pool
     int hits, nodes, passes, escaped, backward;
     uint32_t e_esc;  // escaped energy (fits: energies of a shower sum to e0)
     int hc, hf;      // the slot's hit-log chunk (-1: none) and its fill
@@ -173,10 +173,9 @@ __device__ __forceinline__ int wave_excl_scan(int v) {
     return incl - v;
 }
 
-// LDS words of one wave: pool + draw queue + the stop / split thresholds of
-// every plane
+// LDS words of one wave: pool + the stop / split thresholds of every plane
 __host__ __device__ constexpr int lds_words(int pool_cap) {
-    return POOL_FIELDS * pool_cap + POOL_FIELDS * QCAP + 2 * 2 * 64;
+    return POOL_FIELDS * pool_cap + 2 * 2 * 64;
 }
 
 // Keeps a wave-uniform value in scalar registers but hides it from loop-
@@ -220,8 +219,7 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
     // PC: pool entries in LDS, a power of two >= 2 * WAVE (compile-time, so
     // that the field offsets are instruction immediates)
     uint32_t *const pool = lds;            // [POOL_FIELDS][PC], entry j at slot j & (PC-1)
-    uint32_t *const queue = pool + POOL_FIELDS * PC;           // [POOL_FIELDS][QCAP]
-    uint64_t *const thr = (uint64_t *)(queue + POOL_FIELDS * QCAP);  // c1[64], c2[64]
+    uint64_t *const thr = (uint64_t *)(pool + POOL_FIELDS * PC);    // c1[64], c2[64]
 
     for (int k = (int)lane; k < 64; k += WAVE) {
         thr[k] = k < N ? P.c1[k] : 0ull;
@@ -246,7 +244,7 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
     ecut.zero();
     estop.zero();
 
-    int top = 0, lo = 0, qn = 0, max_top = 0;
+    int top = 0, lo = 0, max_top = 0;
     bool exhausted = false, overflow = false;
     unsigned long long steps = 0;
     const float zf = P.z_first, dzp = P.dz;
@@ -286,32 +284,42 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
         }
         return (int)g;
     };
-    // appends the hit records of the lanes of m (all of slot s0) to the
-    // slot's chain; x, y, e, k, lo, hi are this lane's hit
-    auto append_hits = [&](int s0, uint64_t m, float x, float y, uint32_t e, int k, uint32_t lo,
-                           uint32_t hi) {
+    struct Hit {
+        float x, y;
+        uint32_t e, k, lo, hi;
+    };
+    auto write_hit = [&](int c, int pos, const Hit &h) {
+        uint32_t *rec = P.hlog + (int64_t)c * (HL_FIELDS * HIT_CHUNK) + pos;
+        rec[HL_X * HIT_CHUNK] = __float_as_uint(h.x);
+        rec[HL_Y * HIT_CHUNK] = __float_as_uint(h.y);
+        rec[HL_E * HIT_CHUNK] = h.e;
+        rec[HL_K * HIT_CHUNK] = h.k;
+        if (keys) {
+            rec[HL_LO * HIT_CHUNK] = h.lo;
+            rec[HL_HI * HIT_CHUNK] = h.hi;
+        }
+    };
+    // appends the hit records of slot s0 to the slot's chain: lanes of m1
+    // have hit h1, lanes of m2 hit h2 (a lane of both: h1 first)
+    auto append_hits = [&](int s0, uint64_t m1, uint64_t m2, const Hit &h1, const Hit &h2) {
         int c = slot_get(S.hc, s0), f = slot_get(S.hf, s0);
         if (c < 0) return;
-        const int cnt = (int)__popcll(m);
+        const int cnt = (int)__popcll(m1) + (int)__popcll(m2);
         int c2 = -1;
         if (f + cnt > HIT_CHUNK) {
             c2 = claim_hit_chunk();
             if (c2 >= 0 && lane == 0) P.hnext[c] = (uint32_t)c2;
         }
-        if ((m >> lane) & 1ull) {
-            const int pos = f + (int)lanes_below(m);
-            const int cc = pos < HIT_CHUNK ? c : c2;
-            if (cc >= 0) {
-                uint32_t *rec = P.hlog + (int64_t)cc * (HL_FIELDS * HIT_CHUNK) + (pos & (HIT_CHUNK - 1));
-                rec[HL_X * HIT_CHUNK] = __float_as_uint(x);
-                rec[HL_Y * HIT_CHUNK] = __float_as_uint(y);
-                rec[HL_E * HIT_CHUNK] = e;
-                rec[HL_K * HIT_CHUNK] = (uint32_t)k;
-                if (keys) {
-                    rec[HL_LO * HIT_CHUNK] = lo;
-                    rec[HL_HI * HIT_CHUNK] = hi;
-                }
-            }
+        const bool in1 = (m1 >> lane) & 1ull, in2 = (m2 >> lane) & 1ull;
+        const int p1 = f + (int)lanes_below(m1) + (int)lanes_below(m2);
+        const int p2 = p1 + (in1 ? 1 : 0);
+        if (in1) {
+            const int cc = p1 < HIT_CHUNK ? c : c2;
+            if (cc >= 0) write_hit(cc, p1 & (HIT_CHUNK - 1), h1);
+        }
+        if (in2) {
+            const int cc = p2 < HIT_CHUNK ? c : c2;
+            if (cc >= 0) write_hit(cc, p2 & (HIT_CHUNK - 1), h2);
         }
         if (f + cnt > HIT_CHUNK) {
             c = c2;
@@ -414,13 +422,17 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                     hf0 = 0;
                 }
             }
+            // the primary flies from z = 0 to the first plane (a particle
+            // below threshold deposits on arrival)
+            const float x1 = fmaf(zf, tx0, x_first), y1 = fmaf(zf, ty0, y_first);
+            const bool cut0 = fwd0 && (uint64_t)e_first < P.t_cut;
             if ((int)lane == s) {
                 S.hc = S.hs_c = hc0;
                 S.hf = S.hs_f = hf0;
                 S.i = i;
                 S.sid = P.sid_base + (uint32_t)i;
                 S.e0 = e_first;
-                S.live = fwd0 ? 1 : 0;
+                S.live = (fwd0 && !cut0) ? 1 : 0;
                 S.hits = 0;
                 S.nodes = 1;
                 S.passes = 0;
@@ -428,11 +440,16 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                 S.backward = fwd0 ? 0 : 1;
                 S.e_esc = fwd0 ? 0u : e_first;
             }
-            if (lane == 0 && fwd0) {
-                const Entry p0{x_first, y_first, tx0, ty0, e_first, 1u, 0u, 0, (uint32_t)s << 8};
-                pool_store(top, p0);
-            }
-            if (fwd0) {
+            if (cut0) {
+                const Hit h{x1, y1, e_first, 0u, 1u, 0u};
+                if (recs) append_hits(s, 1ull, 0ull, h, h);
+                if ((int)lane == s) S.hits = 1;
+                ecut.add(s, lane == 0 ? e_first : 0u);
+            } else if (fwd0) {
+                if (lane == 0) {
+                    const Entry p0{x1, y1, tx0, ty0, e_first, 1u, 0u, 0, (uint32_t)s << 8};
+                    pool_store(top, p0);
+                }
                 ++top;
                 lo = max(lo, top - PC);
             }
@@ -457,13 +474,18 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
         const uint64_t active = wave_ballot((int)lane < SLOTS && S.i >= 0);
         if (!active) break;
 
-        if (qn >= WAVE || (top == 0 && qn > 0)) {
-            // ---- phase B: draw, decide, split (Algorithm 1's three-way choice)
-            const int nb = min(WAVE, qn);
+        if (top > 0) {
+            // ---- one step of Algorithm 1 for up to 64 particles, each at its
+            // own plane k: draw, three-way choice, split; what goes on flies
+            // to plane k+1 at once, and deposits there if below threshold
+            const int nb = min(WAVE, top);
             const bool valid = (int)lane < nb;
+            const int j = top - 1 - (int)lane;
+            if (top - nb < lo) __threadfence_block();    // spilled entries: see other lanes' stores
             Entry p{0.f, 0.f, 0.f, 0.f, 0u, 0u, 0u, 0, 0u};
-            if (valid) p = load_entry(queue, QCAP, qn - 1 - (int)lane);
-            qn -= nb;
+            if (valid) p = pool_load(j);
+            top -= nb;
+            lo = min(lo, top);
             const int k = (int)(p.ks & 255u), slot = (int)(p.ks >> 8);
             const uint32_t sid = (uint32_t)__shfl((int)S.sid, slot, WAVE);
             const uint4 w = philox4x32_10((uint32_t)k, sid, p.lo, p.hi, opaque_u32(P.seed_lo),
@@ -475,91 +497,54 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             const bool last = (k == N - 1);
             const uint64_t path = ((uint64_t)p.hi << 32) | p.lo;
 
-            // stops deposit
-            const uint64_t mstop = wave_ballot(is_stop);
-            if (mstop) {
-                for_each_slot(mstop, slot, [&](int s0, uint64_t m) {
-                    if ((int)lane == s0) {
-                        S.hits += (int)__popcll(m);
-                        S.live -= (int)__popcll(m);
-                    }
-                    if (recs) append_hits(s0, m, p.x, p.y, p.e, k, p.lo, p.hi);
-                });
-                estop.add(slot, is_stop ? p.e : 0u);
-            }
-
             Daughters D;
             D.fwd_a = D.fwd_b = false;
             D.ea = D.eb = 0;
             D.txa = D.tya = D.txb = D.tyb = 0.f;
             if (is_split) D = split_particle(P, p.tx, p.ty, p.e, w);
-            const uint64_t msplit = wave_ballot(is_split);
-            int node_a = 0;
-            if (msplit) {
-                for_each_slot(msplit, slot, [&](int s0, uint64_t m) {
-                    const int base = slot_get(S.nodes, s0);
-                    if ((m >> lane) & 1ull) node_a = base + 2 * (int)lanes_below(m);
-                    if ((int)lane == s0) S.nodes = base + 2 * (int)__popcll(m);
-                });
-                if (TREE) {
-                    const int m = 2 * (int)__popcll(msplit);
-                    const int ish = __shfl(S.i, slot, WAVE);
-                    if (claim_nodes(m)) {
-                        if (is_split) {
-                            uint32_t *r = P.nlog + (int64_t)nc * (NL_FIELDS * LOG_CHUNK) + nf +
-                                          2 * (int)lanes_below(msplit);
-                            const uint32_t gk = (uint32_t)(64 - __clzll(path)) | ((uint32_t)k << 8);
-                            const uint64_t pa = path << 1;
-                            r[NL_I * LOG_CHUNK] = (uint32_t)ish;
-                            r[NL_I * LOG_CHUNK + 1] = (uint32_t)ish;
-                            r[NL_IDX * LOG_CHUNK] = (uint32_t)node_a;
-                            r[NL_IDX * LOG_CHUNK + 1] = (uint32_t)node_a + 1u;
-                            r[NL_PARENT * LOG_CHUNK] = (uint32_t)p.node;
-                            r[NL_PARENT * LOG_CHUNK + 1] = (uint32_t)p.node;
-                            r[NL_GK * LOG_CHUNK] = gk;
-                            r[NL_GK * LOG_CHUNK + 1] = gk;
-                            r[NL_X * LOG_CHUNK] = __float_as_uint(p.x);
-                            r[NL_X * LOG_CHUNK + 1] = __float_as_uint(p.x);
-                            r[NL_Y * LOG_CHUNK] = __float_as_uint(p.y);
-                            r[NL_Y * LOG_CHUNK + 1] = __float_as_uint(p.y);
-                            r[NL_E * LOG_CHUNK] = D.ea;
-                            r[NL_E * LOG_CHUNK + 1] = D.eb;
-                            if (keys) {
-                                r[NL_LO * LOG_CHUNK] = (uint32_t)pa;
-                                r[NL_HI * LOG_CHUNK] = (uint32_t)(pa >> 32);
-                                r[NL_LO * LOG_CHUNK + 1] = (uint32_t)pa | 1u;
-                                r[NL_HI * LOG_CHUNK + 1] = (uint32_t)(pa >> 32);
-                            }
-                        }
-                        nf += m;
-                    }
-                }
-            }
-
-            // particles for plane k+1, or leaking out (after the last plane, or
-            // turned away from +z)
-            const bool out_a = !last && ((is_split && D.fwd_a) || is_pass);
-            const bool out_b = !last && is_split && D.fwd_b;
+            // outgoing particles: a = first daughter or the passer, b = second daughter
+            const bool has_a = is_split || is_pass, has_b = is_split;
+            const uint32_t ea = is_split ? D.ea : p.e, eb = D.eb;
+            const float txa = is_split ? D.txa : p.tx, tya = is_split ? D.tya : p.ty;
+            const bool fwd_a = is_split ? D.fwd_a : true, fwd_b = D.fwd_b;
+            const bool go_a = has_a && !last && fwd_a, go_b = has_b && !last && fwd_b;
+            // flight to plane k+1
+            const float xa = fmaf(dzp, txa, p.x), ya = fmaf(dzp, tya, p.y);
+            const float xb = fmaf(dzp, D.txb, p.x), yb = fmaf(dzp, D.tyb, p.y);
+            const bool cut_a = go_a && (uint64_t)ea < P.t_cut, cut_b = go_b && (uint64_t)eb < P.t_cut;
+            const bool push_a = go_a && !cut_a, push_b = go_b && !cut_b;
+            // leaking out: after the last plane, or turned away from +z
             int esc_n = 0, back_n = 0;
             uint32_t esc_e = 0u;
             if (last) {
-                if (is_pass) { esc_n = 1; esc_e = p.e; }
-                if (is_split) { esc_n = 2; esc_e = D.ea + D.eb; }
-            } else if (is_split) {
-                if (!D.fwd_a) { esc_n += 1; back_n += 1; esc_e += D.ea; }
-                if (!D.fwd_b) { esc_n += 1; back_n += 1; esc_e += D.eb; }
+                if (has_a) { esc_n += 1; esc_e += ea; }
+                if (has_b) { esc_n += 1; esc_e += eb; }
+            } else {
+                if (has_a && !fwd_a) { esc_n += 1; back_n += 1; esc_e += ea; }
+                if (has_b && !fwd_b) { esc_n += 1; back_n += 1; esc_e += eb; }
             }
-            const uint64_t m1 = wave_ballot(out_a), m2 = wave_ballot(out_b);
-            // live particles per shower: + pushed daughters/passers - drawn
-            const uint64_t mdraw = wave_ballot(is_split || is_pass);
+            // deposits: a stop at plane k, daughters below threshold at k+1
+            const bool hit1 = is_stop || cut_a, hit2 = cut_b;
+            const uint64_t pa = path << 1;
+            estop.add(slot, is_stop ? p.e : 0u);
+            ecut.add(slot, (cut_a ? ea : 0u) + (cut_b ? eb : 0u));
+
+            const uint64_t mvalid = wave_ballot(valid);
+            const uint64_t mh1 = wave_ballot(hit1), mh2 = wave_ballot(hit2);
+            const uint64_t mpa = wave_ballot(push_a), mpb = wave_ballot(push_b);
+            const uint64_t msplit = wave_ballot(is_split), mpass = wave_ballot(is_pass);
             const uint64_t mesc = wave_ballot(esc_n > 0);
-            const uint64_t mpass = wave_ballot(is_pass);
-            for_each_slot(mdraw, slot, [&](int s0, uint64_t m) {
-                const int d = (int)__popcll(m1 & m) + (int)__popcll(m2 & m) - (int)__popcll(m);
-                const int np = (int)__popcll(mpass & m);
+            int node_a = 0;
+            for_each_slot(mvalid, slot, [&](int s0, uint64_t m) {
+                const uint64_t ms = msplit & m;
+                const int base = slot_get(S.nodes, s0);
+                if ((ms >> lane) & 1ull) node_a = base + 2 * (int)lanes_below(ms);
+                const int nh = (int)__popcll(mh1 & m) + (int)__popcll(mh2 & m);
                 if ((int)lane == s0) {
-                    S.live += d;
-                    S.passes += np;
+                    S.nodes = base + 2 * (int)__popcll(ms);
+                    S.hits += nh;
+                    S.live += (int)__popcll(mpa & m) + (int)__popcll(mpb & m) - (int)__popcll(m);
+                    S.passes += (int)__popcll(mpass & m);
                 }
                 if (mesc & m) {
                     const bool mine = (m >> lane) & 1ull;
@@ -572,60 +557,63 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                         S.e_esc += se;
                     }
                 }
-            });
-            const int pos = top + (int)lanes_below(m1) + (int)lanes_below(m2);
-            if (out_a) {
-                Entry q = p;
-                q.ks = (uint32_t)(k + 1) | ((uint32_t)slot << 8);
-                if (is_split) {
-                    q.tx = D.txa;
-                    q.ty = D.tya;
-                    q.e = D.ea;
-                    q.lo = (uint32_t)(path << 1);
-                    q.hi = (uint32_t)(path >> 31);
-                    q.node = node_a;
+                if (recs && nh) {
+                    const Hit h1 = is_stop ? Hit{p.x, p.y, p.e, (uint32_t)k, p.lo, p.hi}
+                                           : Hit{xa, ya, ea, (uint32_t)k + 1u, (uint32_t)pa,
+                                                 (uint32_t)(pa >> 32)};
+                    const Hit h2{xb, yb, eb, (uint32_t)k + 1u, (uint32_t)pa | 1u, (uint32_t)(pa >> 32)};
+                    append_hits(s0, mh1 & m, mh2 & m, h1, h2);
                 }
+            });
+            if (TREE && msplit) {
+                const int m = 2 * (int)__popcll(msplit);
+                const int ish = __shfl(S.i, slot, WAVE);
+                if (claim_nodes(m)) {
+                    if (is_split) {
+                        uint32_t *r = P.nlog + (int64_t)nc * (NL_FIELDS * LOG_CHUNK) + nf +
+                                      2 * (int)lanes_below(msplit);
+                        const uint32_t gk = (uint32_t)(64 - __clzll(path)) | ((uint32_t)k << 8);
+                        r[NL_I * LOG_CHUNK] = (uint32_t)ish;
+                        r[NL_I * LOG_CHUNK + 1] = (uint32_t)ish;
+                        r[NL_IDX * LOG_CHUNK] = (uint32_t)node_a;
+                        r[NL_IDX * LOG_CHUNK + 1] = (uint32_t)node_a + 1u;
+                        r[NL_PARENT * LOG_CHUNK] = (uint32_t)p.node;
+                        r[NL_PARENT * LOG_CHUNK + 1] = (uint32_t)p.node;
+                        r[NL_GK * LOG_CHUNK] = gk;
+                        r[NL_GK * LOG_CHUNK + 1] = gk;
+                        r[NL_X * LOG_CHUNK] = __float_as_uint(p.x);
+                        r[NL_X * LOG_CHUNK + 1] = __float_as_uint(p.x);
+                        r[NL_Y * LOG_CHUNK] = __float_as_uint(p.y);
+                        r[NL_Y * LOG_CHUNK + 1] = __float_as_uint(p.y);
+                        r[NL_E * LOG_CHUNK] = D.ea;
+                        r[NL_E * LOG_CHUNK + 1] = D.eb;
+                        if (keys) {
+                            r[NL_LO * LOG_CHUNK] = (uint32_t)pa;
+                            r[NL_HI * LOG_CHUNK] = (uint32_t)(pa >> 32);
+                            r[NL_LO * LOG_CHUNK + 1] = (uint32_t)pa | 1u;
+                            r[NL_HI * LOG_CHUNK + 1] = (uint32_t)(pa >> 32);
+                        }
+                    }
+                    nf += m;
+                }
+            }
+            // survivors go back on the pool, bound for plane k+1
+            const int pos = top + (int)lanes_below(mpa) + (int)lanes_below(mpb);
+            const uint32_t ks1 = (uint32_t)(k + 1) | ((uint32_t)slot << 8);
+            if (push_a) {
+                const Entry q = is_split ? Entry{xa, ya, txa, tya, ea, (uint32_t)pa, (uint32_t)(pa >> 32),
+                                                 node_a, ks1}
+                                         : Entry{xa, ya, txa, tya, ea, p.lo, p.hi, p.node, ks1};
                 pool_store(pos, q);
             }
-            if (out_b) {
-                const Entry q{p.x, p.y, D.txb, D.tyb, D.eb, (uint32_t)(path << 1) | 1u,
-                              (uint32_t)(path >> 31), node_a + 1,
-                              (uint32_t)(k + 1) | ((uint32_t)slot << 8)};
-                pool_store(pos + (out_a ? 1 : 0), q);
+            if (push_b) {
+                const Entry q{xb, yb, D.txb, D.tyb, eb, (uint32_t)pa | 1u, (uint32_t)(pa >> 32),
+                              node_a + 1, ks1};
+                pool_store(pos + (push_a ? 1 : 0), q);
             }
-            top += (int)__popcll(m1) + (int)__popcll(m2);
+            top += (int)__popcll(mpa) + (int)__popcll(mpb);
             lo = max(lo, top - PC);
             max_top = max(max_top, top);
-        } else if (top > 0) {
-            // ---- phase A: free flight to the next plane, threshold test
-            const int na = min(WAVE, top);
-            const bool valid = (int)lane < na;
-            const int j = top - 1 - (int)lane;
-            if (top - na < lo) __threadfence_block();    // spilled entries: see other lanes' stores
-            Entry p{0.f, 0.f, 0.f, 0.f, 0u, 0u, 0u, 0, 0u};
-            if (valid) p = pool_load(j);
-            top -= na;
-            lo = min(lo, top);
-            const int k = (int)(p.ks & 255u), slot = (int)(p.ks >> 8);
-            const float h = (k == 0) ? zf : dzp;
-            p.x = fmaf(h, p.tx, p.x);
-            p.y = fmaf(h, p.ty, p.y);
-            const bool is_cut = valid && (uint64_t)p.e < P.t_cut;
-            const uint64_t mcut = wave_ballot(is_cut);
-            if (mcut) {
-                for_each_slot(mcut, slot, [&](int s0, uint64_t m) {
-                    if ((int)lane == s0) {
-                        S.hits += (int)__popcll(m);
-                        S.live -= (int)__popcll(m);
-                    }
-                    if (recs) append_hits(s0, m, p.x, p.y, p.e, k, p.lo, p.hi);
-                });
-                ecut.add(slot, is_cut ? p.e : 0u);
-            }
-            const bool to_q = valid && !is_cut;
-            const uint64_t mq = wave_ballot(to_q);
-            if (to_q) store_entry(queue, QCAP, qn + (int)lanes_below(mq), p);
-            qn += (int)__popcll(mq);
         } else if (wave_ballot((int)lane < SLOTS && S.i >= 0 && S.live > 0)) {
             // nothing pending although a shower still counts live particles:
             // its accounting is inconsistent; report it and close it
