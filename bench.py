@@ -46,6 +46,8 @@ def parse():
                     help="frontier entries per buffer kept in LDS (0 = library default)")
     ap.add_argument("--outputs", default="",
                     help="override the workload's outputs: comma list of hits,images,tree")
+    ap.add_argument("--sub-batches", type=int, default=0,
+                    help="sub-batches whose placement overlaps the next propagation (0: automatic)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -163,7 +165,7 @@ def main():
     e0, pol, az = workloads.initial_conditions(w)
     te0, tpol, taz = (torch.from_numpy(a).to(dev) for a in (e0, pol, az))
     sim = supa.Simulator(geom, outputs, waves_per_cu=args.waves_per_cu,
-                         frontier_cap=args.lds_cap)
+                         frontier_cap=args.lds_cap, sub_batches=args.sub_batches)
 
     # size the outputs from one untimed run (also grows the per-wave scratch)
     probe = sim.allocate(w.n, 0, 0)

@@ -182,8 +182,8 @@ supa_status supa_destroy(supa_ctx *ctx);
  * Errors: INVALID_ARG (NULL pointers for requested outputs, bad n),
  * RANGE (an initial energy out of range: nothing else is meaningful),
  * CAPACITY (total hits or nodes exceed the capacities: ledger, counts and the
- * host totals are valid, hit/node arrays and images are not written; a retry
- * with larger arrays gives the same per-shower results), DEVICE.
+ * host totals are valid, hit/node arrays and images are not; a retry with
+ * larger arrays gives the same per-shower results), DEVICE.
  */
 supa_status supa_simulate(supa_ctx *ctx, const supa_batch *b, uint64_t seed,
                           supa_output *out);
@@ -206,10 +206,19 @@ supa_status supa_set_launch(supa_ctx *ctx, int32_t waves_per_cu, int32_t frontie
                             int32_t hit_cap, int32_t node_cap);
 
 /*
+ * Sub-batches of supa_simulate (affects speed only, never results): the batch
+ * runs as this many consecutive sub-batches, and the placement of the hits,
+ * nodes and images of one (on a second, library-owned stream) overlaps the
+ * propagation of the next.  0 (default) = 1; 1..8 = that many (never more
+ * than n).  Counts-only calls use one.
+ */
+supa_status supa_set_pipeline(supa_ctx *ctx, int32_t sub_batches);
+
+/*
  * Device time of the last supa_simulate, in milliseconds, measured with HIP
- * events on the context's stream: [0] propagation kernel, [1] the kernels
- * after it (segment offsets, placement of hits and nodes, images), [2] whole
- * call.  Host pointer to 3 floats.
+ * events: [0] propagation kernels (summed over sub-batches), [1] the kernels
+ * after them (segment offsets, placement of hits and nodes, images; summed,
+ * they overlap [0]), [2] whole call.  Host pointer to 3 floats.
  */
 supa_status supa_last_timing(const supa_ctx *ctx, float *ms3);
 

@@ -19,6 +19,7 @@
 
 namespace supa {
 hipError_t launch_zero_counters(unsigned long long *ctr, hipStream_t s);
+hipError_t launch_note_chunks(const unsigned long long *ctr, unsigned long long *sub, hipStream_t s);
 hipError_t launch_propagate(const Params &P, int blocks, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t s);
@@ -71,16 +72,23 @@ struct supa_ctx {
     uint64_t *d_c1 = nullptr, *d_c2 = nullptr;
     unsigned long long *d_ctr = nullptr;
     unsigned long long *h_ctr = nullptr;   // pinned
-    supa::Cold *d_cold = nullptr;          // per-call inputs/outputs block (device)
-    supa::Cold *h_cold = nullptr;          // its pinned host staging copy
+    supa::Cold *d_cold = nullptr;          // per-sub-batch inputs/outputs blocks (device)
+    supa::Cold *h_cold = nullptr;          // their pinned host staging copy
     // launch settings and scratch
     int n_cu = 0;
     int waves_per_cu = 16;
     int pool_cap = 128;                  // particle-pool entries kept in LDS
     int spill_cap = 4096;                // per-wave spill entries
     int64_t h_chunks = 0, n_chunks = 0;  // log chunks (grow on demand)
+    int sub_batches = 0;                 // 0: chosen from the batch size
+    int last_sub_batches = 0;
     DevBuf spill, hlog, nlog, shower;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // the placement of a sub-batch runs on a second stream, overlapping the
+    // propagation of the next one
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr, ev_joined = nullptr;
+    hipEvent_t ev_prop[supa::MAX_SUB][2] = {};    // propagation start / end (stream)
+    hipEvent_t ev_post[supa::MAX_SUB][2] = {};    // placement start / end (aux)
     float timing[3] = {0, 0, 0};
     std::string err;
     bool broken = false;
@@ -244,14 +252,20 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
               hipMemcpy(c->d_layer_planes, lp.data(), lp.size() * sizeof(int32_t),
                         hipMemcpyHostToDevice) == hipSuccess &&
               hipMalloc(&c->d_c2, N * sizeof(uint64_t)) == hipSuccess &&
-              hipMalloc(&c->d_ctr, supa::CTR_COUNT * sizeof(unsigned long long)) == hipSuccess &&
-              hipHostMalloc(&c->h_ctr, supa::CTR_COUNT * sizeof(unsigned long long), 0) == hipSuccess &&
-              hipMalloc(&c->d_cold, sizeof(supa::Cold)) == hipSuccess &&
-              hipHostMalloc(&c->h_cold, sizeof(supa::Cold), 0) == hipSuccess &&
+              hipMalloc(&c->d_ctr, supa::CTR_WORDS * sizeof(unsigned long long)) == hipSuccess &&
+              hipHostMalloc(&c->h_ctr, supa::CTR_WORDS * sizeof(unsigned long long), 0) == hipSuccess &&
+              hipMalloc(&c->d_cold, supa::MAX_SUB * sizeof(supa::Cold)) == hipSuccess &&
+              hipHostMalloc(&c->h_cold, supa::MAX_SUB * sizeof(supa::Cold), 0) == hipSuccess &&
               hipMemcpy(c->d_layer, c->layer.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->d_c1, c1.data(), N * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->d_c2, c2.data(), N * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess;
-    for (int q = 0; q < 4 && ok; ++q) ok = hipEventCreate(&c->ev[q]) == hipSuccess;
+    // default priority, and no implicit synchronisation with the null stream
+    ok = ok && hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
+    for (hipEvent_t *e : {&c->ev_begin, &c->ev_end, &c->ev_joined})
+        ok = ok && hipEventCreate(e) == hipSuccess;
+    for (int b = 0; b < supa::MAX_SUB && ok; ++b)
+        for (int q = 0; q < 2 && ok; ++q)
+            ok = hipEventCreate(&c->ev_prop[b][q]) == hipSuccess && hipEventCreate(&c->ev_post[b][q]) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         supa_destroy(c);
@@ -275,8 +289,15 @@ extern "C" supa_status supa_destroy(supa_ctx *c) {
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     if (c->d_cold) (void)hipFree(c->d_cold);
     if (c->h_cold) (void)hipHostFree(c->h_cold);
-    for (auto &ev : c->ev)
-        if (ev) (void)hipEventDestroy(ev);
+    if (c->aux) (void)hipStreamSynchronize(c->aux);
+    for (hipEvent_t e : {c->ev_begin, c->ev_end, c->ev_joined})
+        if (e) (void)hipEventDestroy(e);
+    for (int b = 0; b < supa::MAX_SUB; ++b)
+        for (int q = 0; q < 2; ++q) {
+            if (c->ev_prop[b][q]) (void)hipEventDestroy(c->ev_prop[b][q]);
+            if (c->ev_post[b][q]) (void)hipEventDestroy(c->ev_post[b][q]);
+        }
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     delete c;
     return SUPA_OK;
 }
@@ -294,6 +315,14 @@ extern "C" supa_status supa_set_launch(supa_ctx *c, int32_t waves_per_cu, int32_
     // needs more; small values exercise that path)
     if (hit_cap) c->h_chunks = std::max<int64_t>(1, (hit_cap + supa::HIT_CHUNK - 1) / supa::HIT_CHUNK);
     if (node_cap) c->n_chunks = std::max<int64_t>(1, (node_cap + supa::LOG_CHUNK - 1) / supa::LOG_CHUNK);
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_set_pipeline(supa_ctx *c, int32_t sub_batches) {
+    if (!c) return SUPA_ERR_STATE;
+    if (sub_batches < 0 || sub_batches > supa::MAX_SUB)
+        return fail(c, SUPA_ERR_INVALID_ARG, "sub_batches must be in [0, 8]");
+    c->sub_batches = sub_batches;
     return SUPA_OK;
 }
 
@@ -373,7 +402,7 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         const size_t spill_b = al((size_t)waves * supa::POOL_FIELDS * c->spill_cap * 4);
         if (!c->spill.ensure(spill_b)) return nomem(c, "spill area", spill_b);
         const size_t hnext_b = recs ? al((size_t)c->h_chunks * 4) : 0;
-        const size_t hlog_b = recs ? hnext_b + (size_t)c->h_chunks * supa::HL_FIELDS * supa::HIT_CHUNK * 4 : 0;
+        const size_t hlog_b = recs ? hnext_b + (size_t)c->h_chunks * supa::HIT_CHUNK_WORDS * 4 : 0;
         if (recs && !c->hlog.ensure(hlog_b)) return nomem(c, "hit log", hlog_b);
         const size_t nfill_b = tree ? al((size_t)c->n_chunks * 4) : 0;
         const size_t nlog_b = tree ? nfill_b + (size_t)c->n_chunks * supa::NL_FIELDS * supa::LOG_CHUNK * 4 : 0;
@@ -416,100 +445,139 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         P.nlog = tree ? (uint32_t *)((char *)c->nlog.p + nfill_b) : nullptr;
         P.n_chunks = tree ? (int32_t)c->n_chunks : 0;
         P.ctr = c->d_ctr;
+        P.sub = nullptr;
         const float e_unscale = std::ldexp(1.0f, -c->g.energy_frac_bits);
 
-        supa::Cold &K = *c->h_cold;
-        std::memset(&K, 0, sizeof(K));
-        K.e0 = b->e0;
-        K.polar = b->polar;
-        K.azimuth = b->azimuth;
-        K.x0 = b->x0;
-        K.y0 = b->y0;
-        K.order = nullptr;
-        K.ledger = out->ledger;
-        K.counts = out->counts;
-        K.hstart = d_hstart;
-
-        supa::ScanParams SP{};
-        SP.n = (int32_t)n;
-        SP.counts = out->counts;
-        SP.hoff = hits_out ? out->hit_offsets : nullptr;
-        SP.noff = tree ? out->node_offsets : nullptr;
-        SP.partial = d_part;
-        SP.ctr = c->d_ctr;
-
-        supa::PlaceParams H{};
-        H.n = (int32_t)n;
-        H.n_planes = N;
-        H.L = c->n_layers;
-        H.nx = c->g.img_nx;
-        H.ny = c->g.img_ny;
-        H.x0 = (float)c->g.img_x0;
-        H.y0 = (float)c->g.img_y0;
-        H.sx = images ? (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0)) : 0.0f;
-        H.sy = images ? (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0)) : 0.0f;
-        H.e_unscale = e_unscale;
-        H.ctr = c->d_ctr;
-        H.counts = out->counts;
-        H.hstart = d_hstart;
-        H.hlog = P.hlog;
-        H.hnext = P.hnext;
-        H.h_chunks = P.h_chunks;
-        H.layer = c->d_layer;
-        H.hoff = SP.hoff;
-        H.hcap = hits_out ? out->hit_capacity : 0;
-        H.hx = hits_out ? out->hit_x : nullptr;
-        H.hy = hits_out ? out->hit_y : nullptr;
-        H.he = hits_out ? out->hit_e : nullptr;
-        H.hl = hits_out ? out->hit_layer : nullptr;
-        H.hk = (hits_out && P.keys) ? out->hit_key : nullptr;
-        H.images = images ? out->images : nullptr;
-
-        supa::ScatterParams Q{};
-        Q.z_first = P.z_first;
-        Q.dz = P.dz;
-        Q.e_unscale = e_unscale;
-        Q.ctr = c->d_ctr;
-        Q.nlog = P.nlog;
-        Q.nfill = P.nfill;
-        Q.n_chunks = P.n_chunks;
-        Q.noff = SP.noff;
-        Q.ncap = tree ? out->node_capacity : 0;
-        Q.np = out->node_parent;
-        Q.ng = out->node_gen;
-        Q.nvx = out->node_vx;
-        Q.nvy = out->node_vy;
-        Q.nvz = out->node_vz;
-        Q.ne = out->node_e;
-        Q.nk = (tree && P.keys) ? out->node_key : nullptr;
-
-        HIP_TRY(c, hipMemcpyAsync(c->d_cold, c->h_cold, sizeof(supa::Cold), hipMemcpyHostToDevice,
+        // sub-batches: the placement of sub-batch j (aux stream) overlaps the
+        // propagation of sub-batch j+1 (the context's stream)
+        const bool post = recs || tree;
+        // default one: measured on MI355X, the propagation kernel holds every
+        // register slot, so placement cannot run beside it and each extra
+        // sub-batch only adds a propagation tail
+        int nsub = c->sub_batches > 0 ? c->sub_batches : 1;
+        if (!post) nsub = 1;
+        nsub = (int)std::min<int64_t>(std::min(nsub, supa::MAX_SUB), n);
+        const int64_t img_words = images ? (int64_t)c->n_layers * c->g.img_ny * c->g.img_nx : 0;
+        auto off = [&](int j) { return n * j / nsub; };
+        auto sub_ctr = [&](int j) { return c->d_ctr + supa::CTR_BLOCK * (1 + j); };
+        for (int j = 0; j < nsub; ++j) {
+            const int64_t o = off(j);
+            supa::Cold &K = c->h_cold[j];
+            std::memset(&K, 0, sizeof(K));
+            K.e0 = b->e0 + o;
+            K.polar = b->polar + o;
+            K.azimuth = b->azimuth + o;
+            K.x0 = b->x0 ? b->x0 + o : nullptr;
+            K.y0 = b->y0 ? b->y0 + o : nullptr;
+            K.order = nullptr;
+            K.ledger = out->ledger + 4 * o;
+            K.counts = out->counts + 6 * o;
+            K.hstart = d_hstart ? d_hstart + o : nullptr;
+        }
+        HIP_TRY(c, hipMemcpyAsync(c->d_cold, c->h_cold, nsub * sizeof(supa::Cold), hipMemcpyHostToDevice,
                                   c->stream));
-        HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+        HIP_TRY(c, hipEventRecord(c->ev_begin, c->stream));
         HIP_TRY(c, supa::launch_zero_counters(c->d_ctr, c->stream));
-        HIP_TRY(c, supa::launch_propagate(P, (int)waves, c->stream));
-        HIP_TRY(c, hipEventRecord(c->ev[1], c->stream));
-        if (recs || tree) HIP_TRY(c, supa::launch_scan(SP, c->stream));
-        if (recs) HIP_TRY(c, supa::launch_place(H, c->n_cu, c->stream));
-        if (tree) HIP_TRY(c, supa::launch_scatter_nodes(Q, (int32_t)n, c->n_cu, c->stream));
-        HIP_TRY(c, hipEventRecord(c->ev[2], c->stream));
-        HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_COUNT * sizeof(unsigned long long),
+        for (int j = 0; j < nsub; ++j) {
+            const int64_t o = off(j), nj = off(j + 1) - o;
+            supa::Params Pj = P;
+            Pj.n = (int32_t)nj;
+            Pj.sid_base = b->shower_id_base + (uint32_t)o;
+            Pj.cold = c->d_cold + j;
+            Pj.sub = sub_ctr(j);
+            HIP_TRY(c, hipEventRecord(c->ev_prop[j][0], c->stream));
+            HIP_TRY(c, supa::launch_propagate(Pj, (int)waves, c->stream));
+            if (tree) HIP_TRY(c, supa::launch_note_chunks(c->d_ctr, sub_ctr(j), c->stream));
+            HIP_TRY(c, hipEventRecord(c->ev_prop[j][1], c->stream));
+            if (!post) continue;
+
+            supa::ScanParams SP{};
+            SP.n = (int32_t)nj;
+            SP.counts = out->counts + 6 * o;
+            SP.hoff = hits_out ? out->hit_offsets + o : nullptr;
+            SP.noff = tree ? out->node_offsets + o : nullptr;
+            SP.partial = d_part;
+            SP.sub = sub_ctr(j);
+            SP.prev = j > 0 ? sub_ctr(j - 1) : nullptr;
+
+            supa::PlaceParams H{};
+            H.n = (int32_t)nj;
+            H.n_planes = N;
+            H.L = c->n_layers;
+            H.nx = c->g.img_nx;
+            H.ny = c->g.img_ny;
+            H.x0 = (float)c->g.img_x0;
+            H.y0 = (float)c->g.img_y0;
+            H.sx = images ? (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0)) : 0.0f;
+            H.sy = images ? (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0)) : 0.0f;
+            H.e_unscale = e_unscale;
+            H.ctr = c->d_ctr;
+            H.sub = sub_ctr(j);
+            H.counts = SP.counts;
+            H.hstart = d_hstart ? d_hstart + o : nullptr;
+            H.hlog = P.hlog;
+            H.hnext = P.hnext;
+            H.h_chunks = P.h_chunks;
+            H.layer = c->d_layer;
+            H.hoff = SP.hoff;
+            H.hcap = hits_out ? out->hit_capacity : 0;
+            H.hx = hits_out ? out->hit_x : nullptr;
+            H.hy = hits_out ? out->hit_y : nullptr;
+            H.he = hits_out ? out->hit_e : nullptr;
+            H.hl = hits_out ? out->hit_layer : nullptr;
+            H.hk = (hits_out && P.keys) ? out->hit_key : nullptr;
+            H.images = images ? out->images + img_words * o : nullptr;
+
+            supa::ScatterParams Q{};
+            Q.z_first = P.z_first;
+            Q.dz = P.dz;
+            Q.e_unscale = e_unscale;
+            Q.ctr = c->d_ctr;
+            Q.sub = sub_ctr(j);
+            Q.prev = SP.prev;
+            Q.nlog = P.nlog;
+            Q.nfill = P.nfill;
+            Q.n_chunks = P.n_chunks;
+            Q.noff = SP.noff;
+            Q.ncap = tree ? out->node_capacity : 0;
+            Q.np = out->node_parent;
+            Q.ng = out->node_gen;
+            Q.nvx = out->node_vx;
+            Q.nvy = out->node_vy;
+            Q.nvz = out->node_vz;
+            Q.ne = out->node_e;
+            Q.nk = (tree && P.keys) ? out->node_key : nullptr;
+
+            HIP_TRY(c, hipStreamWaitEvent(c->aux, c->ev_prop[j][1], 0));
+            HIP_TRY(c, hipEventRecord(c->ev_post[j][0], c->aux));
+            HIP_TRY(c, supa::launch_scan(SP, c->aux));
+            if (recs) HIP_TRY(c, supa::launch_place(H, c->n_cu, c->aux));
+            if (tree) HIP_TRY(c, supa::launch_scatter_nodes(Q, (int32_t)nj, c->n_cu, c->aux));
+            HIP_TRY(c, hipEventRecord(c->ev_post[j][1], c->aux));
+        }
+        if (post) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_post[nsub - 1][1], 0));
+        HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_WORDS * sizeof(unsigned long long),
                                   hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(c, hipEventRecord(c->ev[3], c->stream));
+        HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        float t01 = 0, t12 = 0, t03 = 0;
-        (void)hipEventElapsedTime(&t01, c->ev[0], c->ev[1]);
-        (void)hipEventElapsedTime(&t12, c->ev[1], c->ev[2]);
-        (void)hipEventElapsedTime(&t03, c->ev[0], c->ev[3]);
-        c->timing[0] = t01;
-        c->timing[1] = t12;
-        c->timing[2] = t03;
+        float t_prop = 0, t_post = 0, t_all = 0, t = 0;
+        for (int j = 0; j < nsub; ++j) {
+            if (hipEventElapsedTime(&t, c->ev_prop[j][0], c->ev_prop[j][1]) == hipSuccess) t_prop += t;
+            if (post && hipEventElapsedTime(&t, c->ev_post[j][0], c->ev_post[j][1]) == hipSuccess) t_post += t;
+        }
+        (void)hipEventElapsedTime(&t_all, c->ev_begin, c->ev_end);
+        (void)hipGetLastError();
+        c->timing[0] = t_prop;
+        c->timing[1] = t_post;
+        c->timing[2] = t_all;
+        c->last_sub_batches = nsub;
 
         const unsigned long long *h = c->h_ctr;
         const unsigned long long flags = h[supa::CTR_FLAGS];
         if (flags & supa::FLAG_RANGE)
             return fail(c, SUPA_ERR_RANGE, "an initial energy is negative, NaN or too large for the fixed-point format");
-        const int64_t total_hits = (int64_t)h[supa::CTR_HITS], total_nodes = (int64_t)h[supa::CTR_NODES];
+        const unsigned long long *last = h + supa::CTR_BLOCK * nsub;    // running totals
+        const int64_t total_hits = (int64_t)last[supa::SUB_HITS], total_nodes = (int64_t)last[supa::SUB_NODES];
         if (flags & supa::FLAG_OVERFLOW) {
             // grow what ran out and rerun: the spill area to the largest pool
             // seen, a log to the totals (exact unless the spill overflowed too)

@@ -77,7 +77,8 @@ struct Cold {
 };
 
 // Hit records leave the propagation kernel through a log of chunks of
-// HIT_CHUNK records (fields stored as separate arrays within a chunk).  Each
+// HIT_CHUNK records: per record one 16-byte word {x, y, integer energy,
+// plane}, and with keys the path id in a second array of the chunk.  Each
 // shower slot of a wave fills its own chain of chunks: when the slot's chunk
 // is full the next one is claimed with one atomic and linked from it, so the
 // records of one shower follow each other along the chain, starting at the
@@ -85,8 +86,9 @@ struct Cold {
 // placement kernel walks each shower's chain once.
 constexpr int HIT_CHUNK_LOG2 = 10;
 constexpr int HIT_CHUNK = 1 << HIT_CHUNK_LOG2;
-// hit record: position, integer energy, plane, path id (with keys)
-enum { HL_X = 0, HL_Y, HL_E, HL_K, HL_LO, HL_HI, HL_FIELDS };
+constexpr int HIT_REC_WORDS = 4;                  // x, y, e, k
+constexpr int HIT_KEY_WORDS = 2;                  // path id low, high
+constexpr int64_t HIT_CHUNK_WORDS = (int64_t)HIT_CHUNK * (HIT_REC_WORDS + HIT_KEY_WORDS);
 
 // Tree nodes go to a log of chunks of LOG_CHUNK records that a wave fills in
 // the order its phases produce them (a chunk is claimed with one atomic and
@@ -119,10 +121,11 @@ struct Params {
     int32_t pool_cap;           // particle-pool entries kept in LDS (power of 2, >= 128)
     int32_t spill_cap;          // pool entries per wave that can spill to global memory
     uint32_t *spill;            // per wave: POOL_FIELDS x spill_cap
-    uint32_t *hlog, *hnext;     // hit log: h_chunks x HL_FIELDS x HIT_CHUNK; chain links
+    uint32_t *hlog, *hnext;     // hit log: h_chunks x HIT_CHUNK_WORDS; chain links
     uint32_t *nlog, *nfill;     // node log: n_chunks x NL_FIELDS x LOG_CHUNK; fill counts
     int32_t h_chunks, n_chunks;
-    unsigned long long *ctr;    // device counters, see CTR_*
+    unsigned long long *ctr;    // the call's counters (CTR_*)
+    unsigned long long *sub;    // the sub-batch's counters (SUB_*)
 };
 
 // Offsets of the showers' segments: exclusive prefix sums of their hit and
@@ -132,14 +135,17 @@ struct ScanParams {
     const int32_t *counts;      // [n][6]: [0] nodes, [1] hits
     int64_t *hoff, *noff;       // [n] outputs (either may be null)
     int64_t *partial;           // [2][ceil(n / SCAN_TILE)] tile sums, then tile offsets
-    unsigned long long *ctr;    // CTR_HITS / CTR_NODES receive the totals
+    unsigned long long *sub;    // SUB_HITS / SUB_NODES receive the running totals
+    const unsigned long long *prev;   // the previous sub-batch's counters, or null
 };
 constexpr int SCAN_THREADS = 256, SCAN_ITEMS = 16, SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 
 // Moves node records to their final places (supa_scatter.hip).
 struct ScatterParams {
     float z_first, dz, e_unscale;
-    const unsigned long long *ctr;
+    const unsigned long long *ctr;    // the call's counters (flags)
+    const unsigned long long *sub;    // the sub-batch's (node total, end of its chunks)
+    const unsigned long long *prev;   // the previous sub-batch's (start of its chunks), or null
     const uint32_t *nlog, *nfill;
     int32_t n_chunks;
     const int64_t *noff;        // [n] segment starts of the nodes
@@ -155,7 +161,8 @@ struct PlaceParams {
     int32_t n, n_planes, L, nx, ny;
     float x0, y0, sx, sy;        // cell = floor((x - x0) * sx)
     float e_unscale;             // 2^-s
-    const unsigned long long *ctr;
+    const unsigned long long *ctr;    // the call's counters (flags)
+    const unsigned long long *sub;    // the sub-batch's (running hit total)
     const int32_t *counts;       // [n][6]: [1] hits
     const int64_t *hstart;       // [n] log position of each shower's first record
     const uint32_t *hlog, *hnext;
@@ -182,17 +189,26 @@ struct GemmArgs {
     uint16_t *pre;       // EPI_BIAS_GELU: pre-activation out; EPI_GELU_GRAD: in (bf16 [M][ldc])
 };
 
+// Device counters of one call: a block for the whole call, then one block
+// per sub-batch (a call runs its batch as up to MAX_SUB consecutive
+// sub-batches, so that the placement of one overlaps the propagation of the
+// next).
 enum {
-    CTR_WORK = 0,        // next work item
-    CTR_HITS = 1,        // total hits (from the scan)
-    CTR_NODES = 2,       // total nodes (from the scan)
-    CTR_STEPS = 3,       // particle-steps
-    CTR_FLAGS = 4,       // FLAG_* bits
-    CTR_NEED_F = 5,      // largest particle pool seen
-    CTR_HCHUNK = 6,      // hit-log chunks claimed
-    CTR_NCHUNK = 7,      // node-log chunks claimed
-    CTR_COUNT = 8
+    CTR_STEPS = 0,       // particle-steps
+    CTR_FLAGS = 1,       // FLAG_* bits
+    CTR_NEED_F = 2,      // largest particle pool seen
+    CTR_HCHUNK = 3,      // hit-log chunks claimed
+    CTR_NCHUNK = 4,      // node-log chunks claimed
+    CTR_BLOCK = 8        // words per block
 };
+enum {
+    SUB_WORK = 0,        // next work item of the sub-batch
+    SUB_HITS = 1,        // hits of the batch up to and including this sub-batch
+    SUB_NODES = 2,       // the same for nodes
+    SUB_NCHUNK_END = 3   // node-log chunks claimed when the sub-batch's propagation ended
+};
+constexpr int MAX_SUB = 8;
+constexpr int CTR_WORDS = CTR_BLOCK * (1 + MAX_SUB);
 
 enum { FLAG_OVERFLOW = 1, FLAG_RANGE = 2, FLAG_INTERNAL = 4 };
 

@@ -37,10 +37,13 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("" ::: "memory");
 }
 
+// records of one window held by a thread (path ids only with KEYS)
+template <bool KEYS>
 struct Window {
     float x[PL_UNROLL], y[PL_UNROLL];
-    uint32_t e[PL_UNROLL], lo[PL_UNROLL], hi[PL_UNROLL];
+    uint32_t e[PL_UNROLL];
     int k[PL_UNROLL];            // plane, -1 for no record
+    uint32_t lo[KEYS ? PL_UNROLL : 1], hi[KEYS ? PL_UNROLL : 1];
 };
 
 // Shared state of the chain walk of the current shower.
@@ -81,22 +84,24 @@ __device__ __forceinline__ void walk_to_window(const PlaceParams &Q, Chain &ch, 
     lds_barrier();
 }
 
-__device__ __forceinline__ Window empty_window() {
-    Window W;
+template <bool KEYS>
+__device__ __forceinline__ Window<KEYS> empty_window() {
+    Window<KEYS> W;
 #pragma unroll
     for (int u = 0; u < PL_UNROLL; ++u) {
         W.x[u] = W.y[u] = 0.0f;
-        W.e[u] = W.lo[u] = W.hi[u] = 0u;
+        W.e[u] = 0u;
         W.k[u] = -1;
+        if (KEYS) W.lo[KEYS ? u : 0] = W.hi[KEYS ? u : 0] = 0u;
     }
     return W;
 }
 
 // Records of window w held by this thread (after walk_to_window(w); nothing
 // when a link of the chain was bad).
-__device__ __forceinline__ Window load_window(const PlaceParams &Q, const Chain &ch, int w, int nh,
-                                              bool keys) {
-    Window W = empty_window();
+template <bool KEYS>
+__device__ __forceinline__ Window<KEYS> load_window(const PlaceParams &Q, const Chain &ch, int w, int nh) {
+    Window<KEYS> W = empty_window<KEYS>();
     if (ch.bad) return W;
     const int lo = (ch.f0 + w * PL_WIN) >> HIT_CHUNK_LOG2;
 #pragma unroll
@@ -105,27 +110,32 @@ __device__ __forceinline__ Window load_window(const PlaceParams &Q, const Chain 
         if (j < nh) {
             const int pos = ch.f0 + j;
             const int c = ch.win[(pos >> HIT_CHUNK_LOG2) - lo];
-            const uint32_t *rec = Q.hlog + (int64_t)c * (HL_FIELDS * HIT_CHUNK) + (pos & (HIT_CHUNK - 1));
-            W.x[u] = __uint_as_float(rec[HL_X * HIT_CHUNK]);
-            W.y[u] = __uint_as_float(rec[HL_Y * HIT_CHUNK]);
-            W.e[u] = rec[HL_E * HIT_CHUNK];
-            W.k[u] = (int)rec[HL_K * HIT_CHUNK];
-            if (keys) {
-                W.lo[u] = rec[HL_LO * HIT_CHUNK];
-                W.hi[u] = rec[HL_HI * HIT_CHUNK];
+            const uint32_t *chunk = Q.hlog + (int64_t)c * HIT_CHUNK_WORDS;
+            const int o = pos & (HIT_CHUNK - 1);
+            const uint4 r = *(const uint4 *)(chunk + HIT_REC_WORDS * o);
+            W.x[u] = __uint_as_float(r.x);
+            W.y[u] = __uint_as_float(r.y);
+            W.e[u] = r.z;
+            W.k[u] = (int)r.w;
+            if (KEYS) {
+                const uint2 kk = *(const uint2 *)(chunk + HIT_REC_WORDS * HIT_CHUNK + HIT_KEY_WORDS * o);
+                W.lo[KEYS ? u : 0] = kk.x;
+                W.hi[KEYS ? u : 0] = kk.y;
             }
         }
     }
     return W;
 }
 
-__device__ __forceinline__ void count_planes(const Window &W, uint32_t *cnt, int N) {
+template <bool KEYS>
+__device__ __forceinline__ void count_planes(const Window<KEYS> &W, uint32_t *cnt, int N) {
 #pragma unroll
     for (int u = 0; u < PL_UNROLL; ++u)
         if (W.k[u] >= 0 && W.k[u] < N) atomicAdd(&cnt[W.k[u]], 1u);
 }
 
-__device__ __forceinline__ void place_hits(const PlaceParams &Q, const Window &W, uint32_t *cur,
+template <bool KEYS>
+__device__ __forceinline__ void place_hits(const PlaceParams &Q, const Window<KEYS> &W, uint32_t *cur,
                                            const int32_t *lay, int64_t seg, int N) {
 #pragma unroll
     for (int u = 0; u < PL_UNROLL; ++u) {
@@ -136,12 +146,13 @@ __device__ __forceinline__ void place_hits(const PlaceParams &Q, const Window &W
         Q.hy[o] = W.y[u];
         Q.he[o] = (float)W.e[u] * Q.e_unscale;
         Q.hl[o] = lay[k];
-        if (Q.hk) Q.hk[o] = ((uint64_t)W.hi[u] << 32) | W.lo[u];
+        if (KEYS) Q.hk[o] = ((uint64_t)W.hi[KEYS ? u : 0] << 32) | W.lo[KEYS ? u : 0];
     }
 }
 
 // adds the window's hits that fall in image rows [row0, row0 + rows) to the slab
-__device__ __forceinline__ void bin_window(const PlaceParams &Q, const Window &W, const int32_t *lay,
+template <bool KEYS>
+__device__ __forceinline__ void bin_window(const PlaceParams &Q, const Window<KEYS> &W, const int32_t *lay,
                                            uint32_t *slab, int row0, int rows, int N) {
 #pragma unroll
     for (int u = 0; u < PL_UNROLL; ++u) {
@@ -177,6 +188,7 @@ __device__ __forceinline__ void clear_slab(uint32_t *slab, int words) {
     for (int r = (words & ~3) + (int)threadIdx.x; r < words; r += PL_THREADS) slab[r] = 0u;
 }
 
+template <bool KEYS>
 __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
     extern __shared__ uint32_t slab[];
     __shared__ int32_t lay[64];
@@ -186,9 +198,8 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
     // only when they all fit
     if (batch_failed(Q.ctr)) return;
     const bool hits = Q.hx != nullptr, img = Q.images != nullptr;
-    if (hits && (int64_t)Q.ctr[CTR_HITS] > Q.hcap) return;
+    if (hits && (int64_t)Q.sub[SUB_HITS] > Q.hcap) return;
     const int N = Q.n_planes;
-    const bool keys = Q.hk != nullptr;
     if (threadIdx.x < 64) lay[threadIdx.x] = (int)threadIdx.x < N ? Q.layer[threadIdx.x] : -1;
     const int total_rows = Q.L * Q.ny;
 
@@ -208,7 +219,7 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
         // window 0 stays in registers for every pass
         walk_to_window(Q, ch, 0, nh);
         const bool ok = !ch.bad;
-        const Window W0 = load_window(Q, ch, 0, nh, keys);
+        const Window<KEYS> W0 = load_window<KEYS>(Q, ch, 0, nh);
 
         if (hits && ok) {
             const int64_t seg = Q.hoff[i];
@@ -217,7 +228,7 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
                 count_planes(W0, cnt, N);
                 for (int w = 1; w < nwin; ++w) {
                     walk_to_window(Q, ch, w, nh);
-                    count_planes(load_window(Q, ch, w, nh, false), cnt, N);
+                    count_planes(load_window<false>(Q, ch, w, nh), cnt, N);
                 }
                 lds_barrier();
                 if (threadIdx.x < 64) {
@@ -234,7 +245,7 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
                 place_hits(Q, W0, cnt, lay, seg, N);
                 for (int w = 1; w < nwin; ++w) {
                     walk_to_window(Q, ch, w, nh);
-                    place_hits(Q, load_window(Q, ch, w, nh, keys), cnt, lay, seg, N);
+                    place_hits(Q, load_window<KEYS>(Q, ch, w, nh), cnt, lay, seg, N);
                 }
             }
         }
@@ -250,7 +261,7 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
                     bin_window(Q, W0, lay, slab, row0, rows, N);
                     for (int w = 1; w < nwin; ++w) {
                         walk_to_window(Q, ch, w, nh);
-                        bin_window(Q, load_window(Q, ch, w, nh, false), lay, slab, row0, rows, N);
+                        bin_window(Q, load_window<false>(Q, ch, w, nh), lay, slab, row0, rows, N);
                     }
                 }
                 lds_barrier();
@@ -271,9 +282,20 @@ hipError_t launch_place(const PlaceParams &P0, int n_cu, hipStream_t s) {
         P.slab_rows = lw <= PL_SLAB_WORDS ? (int)(PL_SLAB_WORDS / lw) * P.ny
                                           : std::max(1, PL_SLAB_WORDS / P.nx);
     }
-    const int blocks = std::min(P.n, n_cu * 4);
-    hipLaunchKernelGGL(supa_place, dim3(blocks), dim3(PL_THREADS),
-                       P.images ? PL_SLAB_WORDS * 4 : 0, s, P);
+    const size_t lds = P.images ? PL_SLAB_WORDS * 4 : 0;
+    // as many workgroups as fit on the device at once (each loops over showers)
+    int per_cu = 0;
+    const void *fn = P.hk ? (const void *)supa_place<true> : (const void *)supa_place<false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PL_THREADS, lds) != hipSuccess ||
+        per_cu < 1) {
+        (void)hipGetLastError();
+        per_cu = 1;
+    }
+    const int blocks = (int)std::min<int64_t>(P.n, (int64_t)n_cu * per_cu);
+    if (P.hk)
+        hipLaunchKernelGGL(supa_place<true>, dim3(blocks), dim3(PL_THREADS), lds, s, P);
+    else
+        hipLaunchKernelGGL(supa_place<false>, dim3(blocks), dim3(PL_THREADS), lds, s, P);
     return hipGetLastError();
 }
 

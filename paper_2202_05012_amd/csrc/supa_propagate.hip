@@ -289,15 +289,9 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
         uint32_t e, k, lo, hi;
     };
     auto write_hit = [&](int c, int pos, const Hit &h) {
-        uint32_t *rec = P.hlog + (int64_t)c * (HL_FIELDS * HIT_CHUNK) + pos;
-        rec[HL_X * HIT_CHUNK] = __float_as_uint(h.x);
-        rec[HL_Y * HIT_CHUNK] = __float_as_uint(h.y);
-        rec[HL_E * HIT_CHUNK] = h.e;
-        rec[HL_K * HIT_CHUNK] = h.k;
-        if (keys) {
-            rec[HL_LO * HIT_CHUNK] = h.lo;
-            rec[HL_HI * HIT_CHUNK] = h.hi;
-        }
+        uint32_t *chunk = P.hlog + (int64_t)c * HIT_CHUNK_WORDS;
+        *(uint4 *)(chunk + HIT_REC_WORDS * pos) = make_uint4(__float_as_uint(h.x), __float_as_uint(h.y), h.e, h.k);
+        if (keys) *(uint2 *)(chunk + HIT_REC_WORDS * HIT_CHUNK + HIT_KEY_WORDS * pos) = make_uint2(h.lo, h.hi);
     };
     // appends the hit records of slot s0 to the slot's chain: lanes of m1
     // have hit h1, lanes of m2 hit h2 (a lane of both: h1 first)
@@ -337,7 +331,7 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
     // initial state of item base + q.  The next batch is claimed one batch
     // ahead, so its atomic has long returned when it is needed.
     unsigned long long next_base = 0;
-    if (lane == 0) next_base = atomicAdd(&P.ctr[CTR_WORK], (unsigned long long)SLOTS);
+    if (lane == 0) next_base = atomicAdd(&P.sub[SUB_WORK], (unsigned long long)SLOTS);
     int b_left = 0, b_at = 0;
     int w_i = 0, w_ok = 0, w_fwd = 0;
     uint32_t w_e = 0u;
@@ -372,7 +366,7 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
                     exhausted = true;
                     break;
                 }
-                if (lane == 0) next_base = atomicAdd(&P.ctr[CTR_WORK], (unsigned long long)SLOTS);
+                if (lane == 0) next_base = atomicAdd(&P.sub[SUB_WORK], (unsigned long long)SLOTS);
                 b_left = min(SLOTS, P.n - (int)base);
                 b_at = 0;
                 if ((int)lane < b_left) {
@@ -665,7 +659,12 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
 }
 
 __global__ void supa_zero_counters(unsigned long long *ctr) {
-    if (threadIdx.x < CTR_COUNT) ctr[threadIdx.x] = 0ull;
+    if (threadIdx.x < CTR_WORDS) ctr[threadIdx.x] = 0ull;
+}
+
+// the node-log chunks claimed so far, noted for a sub-batch
+__global__ void supa_note_chunks(const unsigned long long *ctr, unsigned long long *sub) {
+    if (threadIdx.x == 0) sub[SUB_NCHUNK_END] = ctr[CTR_NCHUNK];
 }
 
 __global__ void supa_philox_kernel(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1,
@@ -683,7 +682,13 @@ __global__ void supa_philox_kernel(const uint32_t *ctr, int64_t n, uint32_t k0, 
 // host-side launchers (called by the C ABI in supa_api.hip)
 // ---------------------------------------------------------------------------
 hipError_t launch_zero_counters(unsigned long long *ctr, hipStream_t s) {
-    hipLaunchKernelGGL(supa_zero_counters, dim3(1), dim3(64), 0, s, ctr);
+    static_assert(CTR_WORDS <= 128, "one workgroup clears the counters");
+    hipLaunchKernelGGL(supa_zero_counters, dim3(1), dim3(128), 0, s, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_note_chunks(const unsigned long long *ctr, unsigned long long *sub, hipStream_t s) {
+    hipLaunchKernelGGL(supa_note_chunks, dim3(1), dim3(64), 0, s, ctr, sub);
     return hipGetLastError();
 }
 

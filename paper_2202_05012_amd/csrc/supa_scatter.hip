@@ -75,7 +75,8 @@ __global__ void __launch_bounds__(1024) scan_top(ScanParams S) {
     __shared__ long long sh[16];
     const int nt = (int)((S.n + SCAN_TILE - 1) / SCAN_TILE);
     for (int a = 0; a < 2; ++a) {
-        long long carry = 0;
+        // sub-batches after the first continue the previous running total
+        long long carry = S.prev ? (long long)S.prev[a == 0 ? SUB_HITS : SUB_NODES] : 0;
         for (int b0 = 0; b0 < nt; b0 += 1024) {
             const int b = b0 + (int)threadIdx.x;
             const long long v = b < nt ? S.partial[a * nt + b] : 0;
@@ -84,7 +85,7 @@ __global__ void __launch_bounds__(1024) scan_top(ScanParams S) {
             if (b < nt) S.partial[a * nt + b] = carry + ex;
             carry += tot;
         }
-        if (threadIdx.x == 0) S.ctr[a == 0 ? CTR_HITS : CTR_NODES] = (unsigned long long)carry;
+        if (threadIdx.x == 0) S.sub[a == 0 ? SUB_HITS : SUB_NODES] = (unsigned long long)carry;
     }
 }
 
@@ -121,9 +122,11 @@ __global__ void __launch_bounds__(SCAN_THREADS) scan_apply(ScanParams S) {
 constexpr int SCATTER_THREADS = 256;
 
 __global__ void __launch_bounds__(SCATTER_THREADS) scatter_nodes(ScatterParams Q, int32_t n) {
-    if (batch_failed(Q.ctr) || (int64_t)Q.ctr[CTR_NODES] > Q.ncap) return;
-    const int nch = (int)min(Q.ctr[CTR_NCHUNK], (unsigned long long)Q.n_chunks);
-    for (int c = blockIdx.x; c < nch; c += gridDim.x) {
+    if (batch_failed(Q.ctr) || (int64_t)Q.sub[SUB_NODES] > Q.ncap) return;
+    // the chunks this sub-batch's propagation claimed
+    const int c_end = (int)min(Q.sub[SUB_NCHUNK_END], (unsigned long long)Q.n_chunks);
+    const int c_begin = Q.prev ? (int)min(Q.prev[SUB_NCHUNK_END], (unsigned long long)c_end) : 0;
+    for (int c = c_begin + (int)blockIdx.x; c < c_end; c += gridDim.x) {
         const int fill = min((int)Q.nfill[c], LOG_CHUNK);
         const uint32_t *rec = Q.nlog + (int64_t)c * (NL_FIELDS * LOG_CHUNK);
         for (int j = (int)threadIdx.x; j < fill; j += SCATTER_THREADS) {

@@ -69,7 +69,7 @@ class Output(C.Structure):
 
 
 EXPORTS = ["supa_abi_version", "supa_validate_geometry", "supa_init_geometry", "supa_destroy",
-           "supa_simulate", "supa_set_launch", "supa_last_timing", "supa_philox",
+           "supa_simulate", "supa_set_launch", "supa_set_pipeline", "supa_last_timing", "supa_philox",
            "supa_last_error"]
 
 _lib = None
@@ -95,6 +95,8 @@ def load():
         L.supa_simulate.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_uint64, C.POINTER(Output)]
         L.supa_set_launch.restype = C.c_int
         L.supa_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+        L.supa_set_pipeline.restype = C.c_int
+        L.supa_set_pipeline.argtypes = [C.c_void_p, C.c_int32]
         L.supa_last_timing.restype = C.c_int
         L.supa_last_timing.argtypes = [C.c_void_p, C.POINTER(C.c_float)]
         L.supa_philox.restype = C.c_int
@@ -160,7 +162,7 @@ class Simulator:
 
     def __init__(self, geom: dict, outputs: int = OUT_HITS, device: int = 0,
                  waves_per_cu: int = 0, frontier_cap: int = 0, hit_cap: int = 0,
-                 node_cap: int = 0):
+                 node_cap: int = 0, sub_batches: int = 0):
         self.lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("libsupa needs a GPU; none is visible")
@@ -179,10 +181,15 @@ class Simulator:
         self.ctx = ctx
         if waves_per_cu or frontier_cap or hit_cap or node_cap:
             self.set_launch(waves_per_cu, frontier_cap, hit_cap, node_cap)
+        if sub_batches:
+            self.set_pipeline(sub_batches)
 
     def set_launch(self, waves_per_cu=0, frontier_cap=0, hit_cap=0, node_cap=0):
         st = self.lib.supa_set_launch(self.ctx, waves_per_cu, frontier_cap, hit_cap, node_cap)
         self._check(st)
+
+    def set_pipeline(self, sub_batches=0):
+        self._check(self.lib.supa_set_pipeline(self.ctx, sub_batches))
 
     def _check(self, st):
         if st != 0:

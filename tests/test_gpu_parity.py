@@ -172,17 +172,19 @@ def test_capacity_error_then_identical_retry():
 
 
 def test_determinism_across_launch_settings():
-    """Tiny journals force the grow-and-rerun path, a small LDS pool makes
-    large showers spill to global memory, different wave counts change which
-    wave runs which shower and which showers share a wave; results must not
-    change."""
+    """Tiny logs force the grow-and-rerun path, a small LDS pool makes large
+    showers spill to global memory, different wave counts change which wave
+    runs which shower and which showers share a wave, sub-batches split the
+    call into overlapping propagation and placement launches; results must
+    not change."""
     w = workloads.WORKLOADS["loge1to1000_20planes_1m"]
     geom = workloads.geometry(w)
     e0, pol, az = workloads.initial_conditions(w, 200)
     ref = O.simulate(geom, e0, pol, az, w.seed)
     for launch in (dict(waves_per_cu=1, frontier_cap=128, hit_cap=64, node_cap=64),
                    dict(waves_per_cu=16), dict(waves_per_cu=4, frontier_cap=512),
-                   dict(waves_per_cu=12, frontier_cap=128)):
+                   dict(waves_per_cu=12, frontier_cap=128),
+                   dict(sub_batches=3), dict(waves_per_cu=2, sub_batches=8, hit_cap=64, node_cap=64)):
         gpu, _ = run_gpu(geom, HITS_TREE, e0, pol, az, w.seed, **launch)
         parity.check_all(gpu, ref, geom, tree=True)
 
