@@ -4,9 +4,11 @@
 // log chunks that holds its hit records (the propagation kernel wrote them
 // there in the order it produced them):
 //   hit clouds  count the records per plane (LDS), turn the counts into plane
-//               starts within the shower's segment, and write every record
-//               to segment start + the next free place of its plane, so the
+//               starts within the shower's segment, and put every record at
+//               segment start + the next free place of its plane, so the
 //               segment is grouped by plane (order within a plane is free);
+//               a segment of up to PL_WIN hits is sorted in LDS first and
+//               leaves with contiguous stores;
 //   images      (paper, appendix "Downsampling": a region of interest per
 //               layer, a grid of cells, and per cell the summed energy of the
 //               points in it) an LDS slab holding whole layers, or a band of
@@ -150,6 +152,36 @@ __device__ __forceinline__ void place_hits(const PlaceParams &Q, const Window<KE
     }
 }
 
+// Hit fields of a segment staged in the LDS slab: x, y, energy (float bits)
+// and layer, PL_WIN words each, at the hit's place within the segment.
+static_assert(4 * PL_WIN <= PL_SLAB_WORDS, "a staged segment fits the slab");
+
+template <bool KEYS>
+__device__ __forceinline__ void stage_hits(const PlaceParams &Q, const Window<KEYS> &W, uint32_t *cur,
+                                           const int32_t *lay, uint32_t *slab, int64_t seg, int N) {
+#pragma unroll
+    for (int u = 0; u < PL_UNROLL; ++u) {
+        const int k = W.k[u];
+        if (k < 0 || k >= N) continue;
+        const uint32_t r = atomicAdd(&cur[k], 1u);
+        slab[r] = __float_as_uint(W.x[u]);
+        slab[PL_WIN + r] = __float_as_uint(W.y[u]);
+        slab[2 * PL_WIN + r] = __float_as_uint((float)W.e[u] * Q.e_unscale);
+        slab[3 * PL_WIN + r] = (uint32_t)lay[k];
+        if (KEYS) Q.hk[seg + r] = ((uint64_t)W.hi[KEYS ? u : 0] << 32) | W.lo[KEYS ? u : 0];
+    }
+}
+
+__device__ __forceinline__ void copy_out_hits(const PlaceParams &Q, const uint32_t *slab, int64_t seg,
+                                              int nh) {
+    for (int q = (int)threadIdx.x; q < nh; q += PL_THREADS) {
+        Q.hx[seg + q] = __uint_as_float(slab[q]);
+        Q.hy[seg + q] = __uint_as_float(slab[PL_WIN + q]);
+        Q.he[seg + q] = __uint_as_float(slab[2 * PL_WIN + q]);
+        Q.hl[seg + q] = (int32_t)slab[3 * PL_WIN + q];
+    }
+}
+
 // adds the window's hits that fall in image rows [row0, row0 + rows) to the slab
 template <bool KEYS>
 __device__ __forceinline__ void bin_window(const PlaceParams &Q, const Window<KEYS> &W, const int32_t *lay,
@@ -242,10 +274,19 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
                     cnt[threadIdx.x] = incl - v;
                 }
                 lds_barrier();
-                place_hits(Q, W0, cnt, lay, seg, N);
-                for (int w = 1; w < nwin; ++w) {
-                    walk_to_window(Q, ch, w, nh);
-                    place_hits(Q, load_window<KEYS>(Q, ch, w, nh), cnt, lay, seg, N);
+                if (nh <= PL_WIN) {
+                    // the whole segment fits the LDS slab: sort into it, then
+                    // write it out with contiguous stores
+                    stage_hits(Q, W0, cnt, lay, slab, seg, N);
+                    lds_barrier();
+                    copy_out_hits(Q, slab, seg, nh);
+                    lds_barrier();
+                } else {
+                    place_hits(Q, W0, cnt, lay, seg, N);
+                    for (int w = 1; w < nwin; ++w) {
+                        walk_to_window(Q, ch, w, nh);
+                        place_hits(Q, load_window<KEYS>(Q, ch, w, nh), cnt, lay, seg, N);
+                    }
                 }
             }
         }
@@ -282,7 +323,8 @@ hipError_t launch_place(const PlaceParams &P0, int n_cu, hipStream_t s) {
         P.slab_rows = lw <= PL_SLAB_WORDS ? (int)(PL_SLAB_WORDS / lw) * P.ny
                                           : std::max(1, PL_SLAB_WORDS / P.nx);
     }
-    const size_t lds = P.images ? PL_SLAB_WORDS * 4 : 0;
+    // the slab: image rows, or a staged segment of hits
+    const size_t lds = PL_SLAB_WORDS * 4;
     // as many workgroups as fit on the device at once (each loops over showers)
     int per_cu = 0;
     const void *fn = P.hk ? (const void *)supa_place<true> : (const void *)supa_place<false>;

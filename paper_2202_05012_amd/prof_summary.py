@@ -1,0 +1,184 @@
+"""Condenses rocprofv3 output into the short per-kernel summaries kept under
+profiles/, and reads them back.
+
+Inputs are the directories of three rocprofv3 runs of the same bench command:
+  --kernel-trace --stats             per-kernel durations
+  --pmc FETCH_SIZE  (with --copy-calibration)
+  --pmc WRITE_SIZE  (with --copy-calibration)
+The bench's --copy-calibration run includes one device copy of exactly
+1 GiB; what FETCH_SIZE and WRITE_SIZE read for it gives the factor that
+turns each counter into bytes.  HBM traffic per launch of a kernel is
+(FETCH_SIZE * fetch factor + WRITE_SIZE * write factor), KiB -> bytes,
+averaged over the timed launches.
+
+  python -m paper_2202_05012_amd.prof_summary TRACE_DIR FETCH_DIR WRITE_DIR \\
+      --workload NAME --command "..." --out DIR
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import re
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+COPY_BYTES = 1 << 30          # the calibration copy
+
+# the sources each kernel is built from (a summary is valid while they hash
+# to the value it records)
+KERNEL_SOURCES = {
+    "supa_propagate": ["supa_propagate.hip", "supa_device.hpp"],
+    "supa_place": ["supa_place.hip", "supa_device.hpp"],
+    "scatter_nodes": ["supa_scatter.hip", "supa_device.hpp"],
+}
+
+
+def source_hash(kernel: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def short_name(full: str) -> str:
+    m = re.search(r"(supa_propagate|supa_place|scatter_nodes|scan_tiles|scan_top|scan_apply)", full)
+    return m.group(1) if m else full
+
+
+def _rows(d: str, suffix: str):
+    files = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    with open(files[0]) as fh:
+        return list(csv.DictReader(fh))
+
+
+def durations(trace_dir: str):
+    """Per kernel: durations (ms) of its dispatches, in order."""
+    out = {}
+    for r in _rows(trace_dir, "kernel_trace.csv"):
+        out.setdefault(short_name(r["Kernel_Name"]), []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    return out
+
+
+def counter(pmc_dir: str, name: str):
+    """Per kernel: counter values (KiB) of its dispatches, in order, and the
+    value for the 1 GiB calibration copy."""
+    out, copy = {}, None
+    for r in _rows(pmc_dir, "counter_collection.csv"):
+        if r["Counter_Name"] != name:
+            continue
+        v = float(r["Counter_Value"])
+        k = short_name(r["Kernel_Name"])
+        if "copyBuffer" in r["Kernel_Name"]:
+            if copy is None or v > copy:
+                copy = v
+            continue
+        out.setdefault(k, []).append(v)
+    return out, copy
+
+
+def steady(vals, skip):
+    """Mean over the dispatches after the first `skip` (sizing probe and
+    warm-up)."""
+    v = vals[skip:] if len(vals) > skip else vals
+    return statistics.fmean(v) if v else float("nan")
+
+
+def summarize(trace_dir, fetch_dir, write_dir, workload, commands, out_dir, skip=2):
+    dur = durations(trace_dir)
+    fetch, fcopy = counter(fetch_dir, "FETCH_SIZE")
+    write, wcopy = counter(write_dir, "WRITE_SIZE")
+    f_scale = COPY_BYTES / 1024.0 / fcopy if fcopy else float("nan")
+    w_scale = COPY_BYTES / 1024.0 / wcopy if wcopy else float("nan")
+    written = []
+    for k in KERNEL_SOURCES:
+        if k not in dur:
+            continue
+        ms = steady(dur[k], skip)
+        fk = steady(fetch.get(k, []), skip)
+        wk = steady(write.get(k, []), skip)
+        traffic = (fk * f_scale + wk * w_scale) * 1024.0
+        lines = [
+            f"# {k} -- {workload}",
+            "",
+            "Commands (run from the repository root; `cd /tmp && export TMPDIR=/tmp` first):",
+            "",
+            *[f"    {c}" for c in commands],
+            "",
+            f"source_sha256: {source_hash(k)}",
+            f"dispatches_traced: {len(dur[k])} (first {skip} skipped: sizing probe, first warm-up)",
+            f"avg_duration_ms: {ms:.4f}",
+            f"min_duration_ms: {min(dur[k][skip:] or dur[k]):.4f}",
+            f"max_duration_ms: {max(dur[k][skip:] or dur[k]):.4f}",
+            f"fetch_kib_per_dispatch: {fk:.1f}",
+            f"write_kib_per_dispatch: {wk:.1f}",
+            f"copy_calibration_fetch_kib: {fcopy:.1f} (1 GiB copy; factor {f_scale:.4f})",
+            f"copy_calibration_write_kib: {wcopy:.1f} (1 GiB copy; factor {w_scale:.4f})",
+            f"traffic_bytes_per_launch: {traffic:.0f}",
+            f"traffic_GBps_at_avg_duration: {traffic / (ms / 1e3) / 1e9:.1f}",
+            "",
+            "All kernels of the traced run (avg ms over dispatches after the first "
+            f"{skip}):",
+            "",
+            "| kernel | dispatches | avg ms |",
+            "|---|---|---|",
+            *[f"| {n} | {len(v)} | {steady(v, skip):.4f} |" for n, v in sorted(dur.items())],
+            "",
+        ]
+        path = os.path.join(out_dir, f"{k}_{workload}.md")
+        with open(path, "w") as fh:
+            fh.write("\n".join(lines))
+        written.append(path)
+    return written
+
+
+def read_summary(path: str) -> dict:
+    """key: value lines of a summary (values as strings)."""
+    d = {}
+    with open(path) as fh:
+        for line in fh:
+            m = re.match(r"^([a-z_0-9]+): (\S+)", line)
+            if m:
+                d[m.group(1)] = m.group(2)
+    return d
+
+
+def traffic_if_current(profiles_dir: str, kernel: str, workload: str):
+    """Measured HBM bytes per launch, or None when there is no summary or
+    the kernel's sources changed since it was taken."""
+    path = os.path.join(profiles_dir, f"{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    d = read_summary(path)
+    if d.get("source_sha256") != source_hash(kernel):
+        return None
+    try:
+        return float(d["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("trace_dir")
+    ap.add_argument("fetch_dir")
+    ap.add_argument("write_dir")
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--skip", type=int, default=2)
+    a = ap.parse_args()
+    os.makedirs(a.out, exist_ok=True)
+    for p in summarize(a.trace_dir, a.fetch_dir, a.write_dir, a.workload, a.command, a.out, a.skip):
+        print(p)
+
+
+if __name__ == "__main__":
+    main()
