@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--surrogate", action="store_true",
                     help="train the surrogate online, then time surrogate + fallback against "
                          "the plain simulator at the W1 <= 2%% target")
-    ap.add_argument("--train-showers", type=int, default=2_000_000)
+    ap.add_argument("--train-showers", type=int, default=10_000_000)
     ap.add_argument("--eval-showers", type=int, default=1_000_000)
     ap.add_argument("--batch", type=int, default=8192)
     return ap.parse_args()
@@ -96,7 +96,7 @@ def bench_surrogate(args):
     sim = SP.ImageSimulator()
     model = S.MLP(S.surrogate_dims(), device=dev, seed=1)
     steps = max(1, args.train_showers // args.batch)
-    losses, t_train = SP.train(model, steps, args.batch, seed=7, lr=2e-3,
+    losses, t_train = SP.train(model, steps, args.batch, seed=7, lr=1e-3,
                                log_every=max(1, steps // 10), sim=sim)
     rho = SP.calibrate_rho(model, sim, 8192, seed=11)
     n = args.eval_showers
@@ -116,7 +116,7 @@ def bench_surrogate(args):
     mean_layer = float(ref.mean(axis=0).mean())
     unc_h = unc.cpu().numpy()
     rows = []
-    for frac in (0.0, 0.01, 0.02, 0.05, 0.1, 0.2, 0.3, 0.5, 0.75, 1.0):
+    for frac in (0.0, 0.1, 0.3, 0.5, 0.6, 0.7, 0.75, 0.8, 0.85, 0.9, 0.95, 1.0):
         tau = float(np.quantile(unc_h, 1.0 - frac)) if 0 < frac < 1 else (np.inf if frac == 0 else -np.inf)
         (le, m), t = timed(lambda: SP.surrogate_with_fallback(model, e0, pol, az, 5, tau, sim, rho=rho))
         w = SP.w1_per_layer(le.cpu().numpy(), ref)

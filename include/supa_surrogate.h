@@ -57,10 +57,14 @@ supa_status supa_gemm_bf16(void *hip_stream, int trans_a, int trans_b, int epilo
  * out[b] = [mu | s_raw] (float [B][2D]), s = clamp(s_raw, -s_clamp, s_clamp):
  * adds sum over b, j of 1/2 (s + (y - mu)^2 exp(-s)) to *loss (float, device)
  * and writes dout = d mean / d out as bf16 [B][2D] (zero for clamped s).
+ * s_clamp >= 0; 0 holds s at 0: a squared-error fit of the means alone.
+ * mse_mean = 1: the mean half of dout is the gradient of the mean of
+ * 1/2 (y - mu)^2 instead (means fitted by squared error, variances by the
+ * NLL at those means); 0: the NLL gradient throughout.
  */
 supa_status supa_nll_grad(void *hip_stream, int B, int D, const float *out, const float *img,
-                          const float *e0, float y_scale, float s_clamp, uint16_t *dout,
-                          float *loss);
+                          const float *e0, float y_scale, float s_clamp, int32_t mse_mean,
+                          uint16_t *dout, float *loss);
 
 /* out[n] = sum over m < M of X[m][n] for n < N (X bf16 [M][ld]). */
 supa_status supa_colsum_bf16(void *hip_stream, int M, int N, const uint16_t *X, int ld, float *out);

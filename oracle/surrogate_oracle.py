@@ -62,28 +62,36 @@ def forward(params, x):
     return h, cache
 
 
-def split_out(out):
+def split_out(out, s_clamp=S_CLAMP):
     d = out.shape[1] // 2
     mu = out[:, :d]
     s_raw = out[:, d:]
-    s = np.clip(s_raw, -S_CLAMP, S_CLAMP)
+    s = np.clip(s_raw, -s_clamp, s_clamp)
     return mu, s, s_raw
 
 
-def nll(out, y):
+def nll(out, y, s_clamp=S_CLAMP):
     """Mean Gaussian NLL (without 1/2 log 2 pi) over all bins and rows."""
-    mu, s, _ = split_out(out)
+    mu, s, _ = split_out(out, s_clamp)
     return float(np.mean(0.5 * (s + (y - mu) ** 2 * np.exp(-s))))
 
 
-def nll_grad(out, y):
-    """d NLL / d out (the clamp passes no gradient outside [-S, S])."""
-    mu, s, s_raw = split_out(out)
+def mse(out, y):
+    """Half the mean squared error of the means."""
+    mu = out[:, :out.shape[1] // 2]
+    return float(np.mean(0.5 * (y - mu) ** 2))
+
+
+def nll_grad(out, y, s_clamp=S_CLAMP, mse_mean=False):
+    """d NLL / d out (the clamp passes no gradient outside [-S, S]).  With
+    mse_mean the mean half is instead d mse / d mu (means fitted by squared
+    error), and the log-variance half stays d NLL / d s at the given means."""
+    mu, s, s_raw = split_out(out, s_clamp)
     n = y.size
     r = (y - mu) * np.exp(-s)
-    d_mu = -r / n
+    d_mu = -(y - mu) / n if mse_mean else -r / n
     d_s = 0.5 * (1.0 - (y - mu) * r) / n
-    d_s = np.where(np.abs(s_raw) <= S_CLAMP, d_s, 0.0)
+    d_s = np.where(np.abs(s_raw) <= s_clamp, d_s, 0.0)
     return np.concatenate([d_mu, d_s], axis=1)
 
 

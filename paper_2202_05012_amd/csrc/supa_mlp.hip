@@ -175,7 +175,7 @@ hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs &g, hipStream_t s
 // as bf16 (the backward GEMMs' input) and adds the loss sum into *loss.
 // ---------------------------------------------------------------------------
 __global__ void nll_kernel(int B, int D, const float *out, const float *img, const float *e0,
-                           float y_scale, float s_clamp, uint16_t *dout, float *loss) {
+                           float y_scale, float s_clamp, int mse_mean, uint16_t *dout, float *loss) {
     __shared__ float part[256];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t total = (int64_t)B * D;
@@ -190,7 +190,7 @@ __global__ void nll_kernel(int B, int D, const float *out, const float *img, con
         const float r = y - mu;
         const float ie = __expf(-s);
         l += 0.5f * (s + r * r * ie);
-        dout[b * 2 * D + j] = f2bf(-r * ie * inv_n);
+        dout[b * 2 * D + j] = f2bf(-r * (mse_mean ? 1.0f : ie) * inv_n);
         dout[b * 2 * D + D + j] = f2bf(fabsf(sr) <= s_clamp ? 0.5f * (1.0f - r * r * ie) * inv_n : 0.0f);
     }
     part[threadIdx.x] = l;
@@ -319,11 +319,12 @@ __global__ void gate_kernel(int B, int D, int L, const float *out, const float *
 }
 
 hipError_t launch_nll(int B, int D, const float *out, const float *img, const float *e0,
-                      float y_scale, float s_clamp, uint16_t *dout, float *loss, hipStream_t s) {
+                      float y_scale, float s_clamp, int mse_mean, uint16_t *dout, float *loss,
+                      hipStream_t s) {
     const int64_t total = (int64_t)B * D;
     const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(nll_kernel, dim3(blocks), dim3(256), 0, s, B, D, out, img, e0, y_scale,
-                       s_clamp, dout, loss);
+                       s_clamp, mse_mean, dout, loss);
     return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 // checks on the host, then the kernels of supa_mlp.hip on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
 
 #include "../../include/supa_surrogate.h"
@@ -10,7 +11,8 @@
 namespace supa {
 hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs &g, hipStream_t s);
 hipError_t launch_nll(int B, int D, const float *out, const float *img, const float *e0,
-                      float y_scale, float s_clamp, uint16_t *dout, float *loss, hipStream_t s);
+                      float y_scale, float s_clamp, int mse_mean, uint16_t *dout, float *loss,
+                      hipStream_t s);
 hipError_t launch_colsum(int M, int N, const uint16_t *X, int ld, float *out, hipStream_t s);
 hipError_t launch_adam(int64_t n, float *p, const float *g, float *m, float *v, uint16_t *pb,
                        float lr, float b1, float b2, float eps, int step, hipStream_t s);
@@ -65,12 +67,15 @@ extern "C" supa_status supa_gemm_bf16(void *stream, int trans_a, int trans_b, in
 }
 
 extern "C" supa_status supa_nll_grad(void *stream, int B, int D, const float *out, const float *img,
-                                     const float *e0, float y_scale, float s_clamp, uint16_t *dout,
+                                     const float *e0, float y_scale, float s_clamp, int32_t mse_mean,
+                                     uint16_t *dout,
                                      float *loss) {
     if (B < 1 || D < 1) return bad("B and D must be positive");
     if (!out || !img || !e0 || !dout || !loss) return bad("NULL pointer");
-    if (!(s_clamp > 0)) return bad("s_clamp must be positive");
-    return dev(supa::launch_nll(B, D, out, img, e0, y_scale, s_clamp, dout, loss, (hipStream_t)stream), "nll");
+    if (!(s_clamp >= 0) || !std::isfinite(s_clamp)) return bad("s_clamp must be finite and >= 0");
+    if (mse_mean != 0 && mse_mean != 1) return bad("mse_mean must be 0 or 1");
+    return dev(supa::launch_nll(B, D, out, img, e0, y_scale, s_clamp, mse_mean, dout, loss,
+                                (hipStream_t)stream), "nll");
 }
 
 extern "C" supa_status supa_colsum_bf16(void *stream, int M, int N, const uint16_t *X, int ld, float *out) {

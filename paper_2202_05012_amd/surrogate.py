@@ -25,7 +25,7 @@ IN_FEATURES = 3
 N_NOISE = 16
 IN_PAD = 32                 # input row length (multiple of 32 for the matrix cores)
 S_CLAMP = 20.0
-Y_SCALE = 1.0               # targets are image / E0
+Y_SCALE = 1000.0            # targets are 1000 * image / E0: per-bin values of order 1
 
 
 def _lib():
@@ -34,7 +34,7 @@ def _lib():
         vp, i, i64, f, u32, u64 = C.c_void_p, C.c_int, C.c_int64, C.c_float, C.c_uint32, C.c_uint64
         sig = {
             "supa_gemm_bf16": [vp, i, i, i, i, i, i, vp, i, vp, i, vp, vp, i, vp],
-            "supa_nll_grad": [vp, i, i, vp, vp, vp, f, f, vp, vp],
+            "supa_nll_grad": [vp, i, i, vp, vp, vp, f, f, i, vp, vp],
             "supa_colsum_bf16": [vp, i, i, vp, i, vp],
             "supa_adam": [vp, i64, vp, vp, vp, vp, vp, f, f, f, f, i],
             "supa_to_bf16": [vp, i64, vp, vp],
@@ -230,14 +230,18 @@ class MLP:
             _check(L.supa_adam(_stream(), self.b[l].numel(), _p(self.b[l]), _p(dbs[l]),
                                _p(self.mb[l]), _p(self.vb[l]), None, lr, b1, b2, eps, self.step))
 
-    def train_step(self, x, img, e0, lr=1e-3):
-        """One NLL step on targets img / e0 (img float [B, D]); returns the loss."""
+    def train_step(self, x, img, e0, lr=1e-3, s_clamp=None, mse_mean=True):
+        """One step on targets Y_SCALE * img / e0 (img float [B, D]); returns
+        the mean NLL.  Means are fitted by squared error (mse_mean) or by the
+        NLL, log-variances by the NLL; s_clamp = 0 holds the log-variances
+        at 0."""
         out, acts, pres = self.forward(x, keep=True)
         B, D2 = out.shape
         dout = torch.empty((B, D2), dtype=torch.int16, device=self.device)
         loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        sc = S_CLAMP if s_clamp is None else s_clamp
         _check(_lib().supa_nll_grad(_stream(), B, D2 // 2, _p(out), _p(img), _p(e0), Y_SCALE,
-                                    S_CLAMP, _p(dout), _p(loss)))
+                                    sc, 1 if mse_mean else 0, _p(dout), _p(loss)))
         dWs, dbs = self.backward(acts, pres, dout)
         self.adam(dWs, dbs, lr=lr)
         return loss / (B * (D2 // 2))

@@ -50,9 +50,12 @@ class ImageSimulator:
 
 
 def train(model: S.MLP, steps: int, batch: int, seed: int = 100, lr: float = 1e-3,
-          log_every: int = 0, sim: ImageSimulator | None = None, device="cuda"):
+          log_every: int = 0, sim: ImageSimulator | None = None, device="cuda",
+          mean_first: float = 0.0):
     """Online training: every step simulates a fresh batch (shower ids never
-    repeat) and takes one Adam step on the Gaussian NLL."""
+    repeat) and takes one Adam step on the Gaussian NLL; the first
+    `mean_first` fraction of the steps fit the means only (log-variance held
+    at 0, i.e. squared error)."""
     sim = sim or ImageSimulator()
     losses = []
     t0 = time.perf_counter()
@@ -61,7 +64,8 @@ def train(model: S.MLP, steps: int, batch: int, seed: int = 100, lr: float = 1e-
         img, _ = sim.images(e0, pol, az, seed, shower_id_base=step * batch)
         x = S.features(e0, pol, az, seed, row_base=step * batch, stream_id=1)
         cur_lr = lr * (0.5 * (1 + math.cos(math.pi * step / max(steps, 1))) * 0.9 + 0.1)
-        loss = model.train_step(x, img, e0, lr=cur_lr)
+        loss = model.train_step(x, img, e0, lr=cur_lr,
+                                s_clamp=0.0 if step < mean_first * steps else None)
         if log_every and (step % log_every == 0 or step == steps - 1):
             losses.append((step, float(loss.item())))
     torch.cuda.synchronize()

@@ -108,17 +108,20 @@ def test_network_forward_backward_vs_oracle():
     img = rng.uniform(0, 1, size=(B, D)).astype(np.float32)
     e0 = rng.uniform(1, 10, size=B).astype(np.float32)
     y = img.astype(np.float64) / e0[:, None]
-    dout = torch.empty((B, 2 * D), dtype=torch.int16, device="cuda")
-    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-    S._check(S._lib().supa_nll_grad(S._stream(), B, D, S._p(out), S._p(torch.from_numpy(img).cuda()),
-                                    S._p(torch.from_numpy(e0).cuda()), 1.0, S.S_CLAMP, S._p(dout),
-                                    S._p(loss)))
-    # the loss and its gradient on the device's own outputs
     o64 = out.cpu().numpy().astype(np.float64)
-    assert abs(loss.item() / (B * D) - SO.nll(o64, y)) < 1e-5 * max(1.0, abs(SO.nll(o64, y)))
-    g_ref = SO.nll_grad(o64, y)
-    g_got = bf16_to_np(host16(dout)).astype(np.float64)
-    assert rel_fro(g_got, g_ref) < 2 ** -7
+    sc = 3.0          # small enough that some log-variances are clamped
+    for mse_mean in (0, 1):
+        dout = torch.empty((B, 2 * D), dtype=torch.int16, device="cuda")
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        S._check(S._lib().supa_nll_grad(S._stream(), B, D, S._p(out), S._p(torch.from_numpy(img).cuda()),
+                                        S._p(torch.from_numpy(e0).cuda()), 1.0, sc, mse_mean,
+                                        S._p(dout), S._p(loss)))
+        # the loss and its gradient on the device's own outputs
+        want = SO.nll(o64, y, s_clamp=sc)
+        assert abs(loss.item() / (B * D) - want) < 1e-5 * max(1.0, abs(want))
+        g_ref = SO.nll_grad(o64, y, s_clamp=sc, mse_mean=bool(mse_mean))
+        g_got = bf16_to_np(host16(dout)).astype(np.float64)
+        assert rel_fro(g_got, g_ref) < 2 ** -7, mse_mean
     # backward through the network from the same output gradient
     dWs, dbs = net.backward(acts, pres, dout)
     ref_g = SO.backward([[W, b] for W, b in zip(Ws, bs)], cache, g_got)
@@ -176,9 +179,11 @@ def test_gate_select_gather_scatter():
     layer_e, unc, img = S.gate(torch.from_numpy(out).cuda(), torch.from_numpy(e0).cuda(), L,
                                want_image=True)
     mu, s = out[:, :D].astype(np.float64), out[:, D:].astype(np.float64)
-    np.testing.assert_allclose(layer_e.cpu().numpy(), SO.layer_sums(mu, L) * e0[:, None], rtol=1e-5, atol=1e-5)
+    ys = S.Y_SCALE
+    np.testing.assert_allclose(layer_e.cpu().numpy(), SO.layer_sums(mu, L) * e0[:, None] / ys,
+                               rtol=1e-5, atol=1e-5 / ys)
     np.testing.assert_allclose(unc.cpu().numpy(), SO.uncertainty(mu, s, L), rtol=1e-4)
-    np.testing.assert_allclose(img.cpu().numpy(), mu * e0[:, None], rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(img.cpu().numpy(), mu * e0[:, None] / ys, rtol=1e-6, atol=1e-6 / ys)
     v = rng.normal(size=5000).astype(np.float32)
     idx = S.select_above(torch.from_numpy(v).cuda(), 0.7).cpu().numpy()
     np.testing.assert_array_equal(idx, np.nonzero(v > 0.7)[0])

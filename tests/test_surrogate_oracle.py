@@ -92,3 +92,29 @@ def test_uncertainty_and_layer_sums():
     u = S.uncertainty(mu, s, 2)
     assert abs(u[0] - 3.0 / 10.0) < 1e-12
     np.testing.assert_array_equal(S.layer_sums(mu, 2), [[3.0, 7.0]])
+
+
+def test_mse_mean_gradient_finite_differences():
+    """Means fitted by squared error, log-variances by the NLL: each half of
+    the gradient is the central difference of its own objective."""
+    rng = np.random.default_rng(11)
+    out = rng.normal(size=(5, 8))
+    y = rng.normal(size=(5, 4))
+    g = S.nll_grad(out, y, s_clamp=20.0, mse_mean=True)
+    h = 1e-6
+    for (r, c) in [(0, 0), (2, 3), (4, 1)]:          # mean half
+        up, dn = out.copy(), out.copy()
+        up[r, c] += h
+        dn[r, c] -= h
+        fd = (S.mse(up, y) - S.mse(dn, y)) / (2 * h)
+        assert abs(fd - g[r, c]) < 1e-7 * max(1.0, abs(fd))
+    for (r, c) in [(1, 4), (3, 7)]:                  # log-variance half
+        up, dn = out.copy(), out.copy()
+        up[r, c] += h
+        dn[r, c] -= h
+        fd = (S.nll(up, y, 20.0) - S.nll(dn, y, 20.0)) / (2 * h)
+        assert abs(fd - g[r, c]) < 1e-7 * max(1.0, abs(fd))
+    # and the plain mode differs from it only in the mean half
+    g0 = S.nll_grad(out, y, s_clamp=20.0)
+    np.testing.assert_array_equal(g0[:, 4:], g[:, 4:])
+    assert not np.allclose(g0[:, :4], g[:, :4])
