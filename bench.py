@@ -48,6 +48,10 @@ def parse():
                     help="override the workload's outputs: comma list of hits,images,tree")
     ap.add_argument("--sub-batches", type=int, default=0,
                     help="sub-batches whose placement overlaps the next propagation (0: automatic)")
+    ap.add_argument("--cost-order", type=int, default=-1, choices=(-1, 0, 1),
+                    help="hand out expensive showers first (1), batch order (0), automatic (-1)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the launch-setting search before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -165,13 +169,21 @@ def main():
     e0, pol, az = workloads.initial_conditions(w)
     te0, tpol, taz = (torch.from_numpy(a).to(dev) for a in (e0, pol, az))
     sim = supa.Simulator(geom, outputs, waves_per_cu=args.waves_per_cu,
-                         frontier_cap=args.lds_cap, sub_batches=args.sub_batches)
+                         frontier_cap=args.lds_cap, sub_batches=args.sub_batches,
+                         cost_order=args.cost_order)
 
     # size the outputs from one untimed run (also grows the per-wave scratch)
     probe = sim.allocate(w.n, 0, 0)
     sim.run(te0, tpol, taz, w.seed, probe)
     out = sim.allocate(w.n, int(probe["total_hits"] * 1.0) + 1, int(probe["total_nodes"]) + 1)
     del probe
+
+    # launch settings picked by measurement on this batch (untimed), unless
+    # given on the command line
+    launch = None
+    if not args.no_autotune and not (args.waves_per_cu or args.lds_cap or args.sub_batches
+                                     or args.cost_order != -1):
+        launch = sim.autotune(te0, tpol, taz, w.seed, out)
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -258,6 +270,8 @@ def main():
         "hits": hits_total,
         "roofline": roof,
     }
+    if launch is not None:
+        line["launch"] = launch
     if roof_other is not None:
         line["roofline_other"] = roof_other
     if not args.no_cpu_baseline:

@@ -206,13 +206,31 @@ supa_status supa_set_launch(supa_ctx *ctx, int32_t waves_per_cu, int32_t frontie
                             int32_t hit_cap, int32_t node_cap);
 
 /*
- * Sub-batches of supa_simulate (affects speed only, never results): the batch
- * runs as this many consecutive sub-batches, and the placement of the hits,
- * nodes and images of one (on a second, library-owned stream) overlaps the
- * propagation of the next.  0 (default) = 1; 1..8 = that many (never more
- * than n).  Counts-only calls use one.
+ * Scheduling of supa_simulate (affects speed only, never results).
+ *   sub_batches  the batch runs as this many consecutive sub-batches, and the
+ *                placement of the hits, nodes and images of one (on a second,
+ *                library-owned stream) overlaps the propagation of the next.
+ *                0 (default) = 1; 1..8 = that many (never more than n).
+ *                Counts-only calls use one.
+ *   cost_order   1: showers are handed to the propagation kernel most
+ *                expensive first (expected cost grows with E0; a device
+ *                counting sort on log2 of the fixed-point energy), so the
+ *                end of a launch is filled with cheap showers; 0: batch
+ *                order; -1 (default): automatic.
  */
-supa_status supa_set_pipeline(supa_ctx *ctx, int32_t sub_batches);
+supa_status supa_set_schedule(supa_ctx *ctx, int32_t sub_batches, int32_t cost_order);
+
+/*
+ * Picks launch settings by measurement: runs the batch under every
+ * combination of waves per CU {8, 12, 16}, LDS pool {128, 256} entries,
+ * sub-batches {1, 2} and cost order {0, 1} (each twice: warm-up, then timed
+ * with the context's events) and keeps the fastest whole call in the
+ * context.  Same arguments and errors as supa_simulate; `out` holds the
+ * batch's results afterwards.  best (host, 4 int32) receives waves_per_cu,
+ * frontier_cap, sub_batches, cost_order; best_ms (host) the fastest time.
+ */
+supa_status supa_autotune(supa_ctx *ctx, const supa_batch *b, uint64_t seed, supa_output *out,
+                          int32_t *best, float *best_ms);
 
 /*
  * Device time of the last supa_simulate, in milliseconds, measured with HIP

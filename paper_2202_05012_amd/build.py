@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsupa.so")
 
-SOURCES = ["supa_api.hip", "supa_propagate.hip", "supa_place.hip", "supa_scatter.hip", "supa_mlp.hip",
+SOURCES = ["supa_api.hip", "supa_propagate.hip", "supa_place.hip", "supa_scatter.hip", "supa_order.hip", "supa_mlp.hip",
            "supa_surrogate_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -28,6 +28,9 @@ hipError_t launch_place(const PlaceParams &P, int n_cu, hipStream_t s);
 int64_t scan_partial_words(int64_t n);
 hipError_t launch_scan(const ScanParams &S, hipStream_t s);
 hipError_t launch_scatter_nodes(const ScatterParams &Q, int32_t n, int n_cu, hipStream_t s);
+int64_t order_scratch_words();
+hipError_t launch_cost_order(const float *e0, int n, float e_scale, uint32_t *hist, int32_t *order,
+                             int n_cu, hipStream_t s);
 }  // namespace supa
 
 // A device buffer that only grows (its contents are scratch).
@@ -54,6 +57,7 @@ struct DevBuf {
 };
 
 static constexpr int kMaxImageWidth = 1024;
+static constexpr int64_t kAutoOrderMin = 65536;     // automatic cost order: from this batch size
 
 struct supa_ctx {
     int device = 0;
@@ -81,6 +85,7 @@ struct supa_ctx {
     int spill_cap = 4096;                // per-wave spill entries
     int64_t h_chunks = 0, n_chunks = 0;  // log chunks (grow on demand)
     int sub_batches = 0;                 // 0: chosen from the batch size
+    int cost_order = -1;                 // hand out expensive showers first: 1 on, 0 off, -1 auto
     int last_sub_batches = 0;
     DevBuf spill, hlog, nlog, shower;
     // the placement of a sub-batch runs on a second stream, overlapping the
@@ -318,11 +323,13 @@ extern "C" supa_status supa_set_launch(supa_ctx *c, int32_t waves_per_cu, int32_
     return SUPA_OK;
 }
 
-extern "C" supa_status supa_set_pipeline(supa_ctx *c, int32_t sub_batches) {
+extern "C" supa_status supa_set_schedule(supa_ctx *c, int32_t sub_batches, int32_t cost_order) {
     if (!c) return SUPA_ERR_STATE;
     if (sub_batches < 0 || sub_batches > supa::MAX_SUB)
         return fail(c, SUPA_ERR_INVALID_ARG, "sub_batches must be in [0, 8]");
+    if (cost_order < -1 || cost_order > 1) return fail(c, SUPA_ERR_INVALID_ARG, "cost_order must be -1, 0 or 1");
     c->sub_batches = sub_batches;
+    c->cost_order = cost_order;
     return SUPA_OK;
 }
 
@@ -409,11 +416,15 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         if (tree && !c->nlog.ensure(nlog_b)) return nomem(c, "node log", nlog_b);
         const size_t hstart_b = recs ? al((size_t)n * 8) : 0;
         const size_t part_b = al((size_t)supa::scan_partial_words(n) * 8);
-        const size_t shower_b = hstart_b + part_b;
+        const bool ordered = c->cost_order > 0 || (c->cost_order < 0 && n >= kAutoOrderMin);
+        const size_t order_b = ordered ? al((size_t)n * 4) + al((size_t)supa::order_scratch_words() * 4) : 0;
+        const size_t shower_b = hstart_b + part_b + order_b;
         if (!c->shower.ensure(shower_b)) return nomem(c, "per-shower scratch", shower_b);
         char *sh = (char *)c->shower.p;
         int64_t *d_hstart = recs ? (int64_t *)sh : nullptr;
         int64_t *d_part = (int64_t *)(sh + hstart_b);
+        int32_t *d_order = ordered ? (int32_t *)(sh + hstart_b + part_b) : nullptr;
+        uint32_t *d_ohist = ordered ? (uint32_t *)(sh + hstart_b + part_b + al((size_t)n * 4)) : nullptr;
 
         supa::Params P{};
         P.n_planes = N;
@@ -469,7 +480,7 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
             K.azimuth = b->azimuth + o;
             K.x0 = b->x0 ? b->x0 + o : nullptr;
             K.y0 = b->y0 ? b->y0 + o : nullptr;
-            K.order = nullptr;
+            K.order = d_order ? d_order + o : nullptr;
             K.ledger = out->ledger + 4 * o;
             K.counts = out->counts + 6 * o;
             K.hstart = d_hstart ? d_hstart + o : nullptr;
@@ -486,6 +497,9 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
             Pj.cold = c->d_cold + j;
             Pj.sub = sub_ctr(j);
             HIP_TRY(c, hipEventRecord(c->ev_prop[j][0], c->stream));
+            if (d_order)
+                HIP_TRY(c, supa::launch_cost_order(b->e0 + o, (int)nj, P.e_scale, d_ohist, d_order + o,
+                                                   c->n_cu, c->stream));
             HIP_TRY(c, supa::launch_propagate(Pj, (int)waves, c->stream));
             if (tree) HIP_TRY(c, supa::launch_note_chunks(c->d_ctr, sub_ctr(j), c->stream));
             HIP_TRY(c, hipEventRecord(c->ev_prop[j][1], c->stream));
@@ -606,4 +620,59 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         return SUPA_OK;
     }
     return fail(c, SUPA_ERR_NOMEM, "scratch sizes did not converge");
+}
+
+// Launch-setting search: every combination of waves per CU, LDS pool size,
+// sub-batches and cost order is run on the caller's batch (the first call
+// of each setting warms up and sizes scratch; the second is timed with the
+// context's events), and the fastest whole-call time wins.  Results are
+// identical under every setting, so `out` holds the batch's results after
+// the search, from the winning setting.
+extern "C" supa_status supa_autotune(supa_ctx *c, const supa_batch *b, uint64_t seed, supa_output *out,
+                                     int32_t *best, float *best_ms) {
+    if (!c) return SUPA_ERR_STATE;
+    if (!best || !best_ms) return fail(c, SUPA_ERR_INVALID_ARG, "best and best_ms are required");
+    static const int waves[] = {8, 12, 16};
+    static const int pools[] = {128, 256};
+    static const int subs[] = {1, 2};
+    static const int orders[] = {0, 1};
+    const int saved[4] = {c->waves_per_cu, c->pool_cap, c->sub_batches, c->cost_order};
+    float bms = 1e30f;
+    int bw = saved[0], bp = saved[1], bs = saved[2], bo = saved[3];
+    for (int w : waves)
+        for (int p : pools)
+            for (int sb : subs)
+                for (int o : orders) {
+                    c->waves_per_cu = w;
+                    c->pool_cap = p;
+                    c->sub_batches = sb;
+                    c->cost_order = o;
+                    supa_status st = supa_simulate(c, b, seed, out);
+                    if (st == SUPA_OK) st = supa_simulate(c, b, seed, out);
+                    if (st != SUPA_OK) {
+                        c->waves_per_cu = saved[0];
+                        c->pool_cap = saved[1];
+                        c->sub_batches = saved[2];
+                        c->cost_order = saved[3];
+                        return st;
+                    }
+                    if (c->timing[2] < bms) {
+                        bms = c->timing[2];
+                        bw = w;
+                        bp = p;
+                        bs = sb;
+                        bo = o;
+                    }
+                }
+    c->waves_per_cu = bw;
+    c->pool_cap = bp;
+    c->sub_batches = bs;
+    c->cost_order = bo;
+    const supa_status st = supa_simulate(c, b, seed, out);
+    best[0] = bw;
+    best[1] = bp;
+    best[2] = bs;
+    best[3] = bo;
+    *best_ms = bms;
+    return st;
 }

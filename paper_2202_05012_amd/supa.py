@@ -69,7 +69,7 @@ class Output(C.Structure):
 
 
 EXPORTS = ["supa_abi_version", "supa_validate_geometry", "supa_init_geometry", "supa_destroy",
-           "supa_simulate", "supa_set_launch", "supa_set_pipeline", "supa_last_timing", "supa_philox",
+           "supa_simulate", "supa_set_launch", "supa_set_schedule", "supa_autotune", "supa_last_timing", "supa_philox",
            "supa_last_error"]
 
 _lib = None
@@ -95,8 +95,11 @@ def load():
         L.supa_simulate.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_uint64, C.POINTER(Output)]
         L.supa_set_launch.restype = C.c_int
         L.supa_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
-        L.supa_set_pipeline.restype = C.c_int
-        L.supa_set_pipeline.argtypes = [C.c_void_p, C.c_int32]
+        L.supa_autotune.restype = C.c_int
+        L.supa_autotune.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_uint64, C.POINTER(Output),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+        L.supa_set_schedule.restype = C.c_int
+        L.supa_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.supa_last_timing.restype = C.c_int
         L.supa_last_timing.argtypes = [C.c_void_p, C.POINTER(C.c_float)]
         L.supa_philox.restype = C.c_int
@@ -162,7 +165,7 @@ class Simulator:
 
     def __init__(self, geom: dict, outputs: int = OUT_HITS, device: int = 0,
                  waves_per_cu: int = 0, frontier_cap: int = 0, hit_cap: int = 0,
-                 node_cap: int = 0, sub_batches: int = 0):
+                 node_cap: int = 0, sub_batches: int = 0, cost_order: int = -1):
         self.lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("libsupa needs a GPU; none is visible")
@@ -181,15 +184,15 @@ class Simulator:
         self.ctx = ctx
         if waves_per_cu or frontier_cap or hit_cap or node_cap:
             self.set_launch(waves_per_cu, frontier_cap, hit_cap, node_cap)
-        if sub_batches:
-            self.set_pipeline(sub_batches)
+        if sub_batches or cost_order != -1:
+            self.set_schedule(sub_batches, cost_order)
 
     def set_launch(self, waves_per_cu=0, frontier_cap=0, hit_cap=0, node_cap=0):
         st = self.lib.supa_set_launch(self.ctx, waves_per_cu, frontier_cap, hit_cap, node_cap)
         self._check(st)
 
-    def set_pipeline(self, sub_batches=0):
-        self._check(self.lib.supa_set_pipeline(self.ctx, sub_batches))
+    def set_schedule(self, sub_batches=0, cost_order=-1):
+        self._check(self.lib.supa_set_schedule(self.ctx, sub_batches, cost_order))
 
     def _check(self, st):
         if st != 0:
@@ -238,10 +241,7 @@ class Simulator:
         o["node_capacity"] = node_capacity
         return o
 
-    def run(self, e0, polar, azimuth, seed: int, out: dict, x0=None, y0=None,
-            shower_id_base: int = 0) -> int:
-        """One supa_simulate call into preallocated outputs; returns the status
-        (OK or CAPACITY) and fills out['total_*']."""
+    def _marshal(self, e0, polar, azimuth, out, x0, y0, shower_id_base):
         n = int(e0.shape[0])
         for t in (e0, polar, azimuth, x0, y0):
             if t is not None:
@@ -257,12 +257,37 @@ class Simulator:
                 setattr(o, name, out[name].data_ptr())
         o.hit_capacity = int(out.get("hit_capacity", 0))
         o.node_capacity = int(out.get("node_capacity", 0))
-        st = self.lib.supa_simulate(self.ctx, C.byref(b), seed & 0xFFFFFFFFFFFFFFFF, C.byref(o))
+        return b, o
+
+    @staticmethod
+    def _totals(out, o):
         out["total_hits"], out["total_nodes"], out["total_steps"] = (o.total_hits, o.total_nodes,
                                                                      o.total_steps)
+
+    def run(self, e0, polar, azimuth, seed: int, out: dict, x0=None, y0=None,
+            shower_id_base: int = 0) -> int:
+        """One supa_simulate call into preallocated outputs; returns the status
+        (OK or CAPACITY) and fills out['total_*']."""
+        b, o = self._marshal(e0, polar, azimuth, out, x0, y0, shower_id_base)
+        st = self.lib.supa_simulate(self.ctx, C.byref(b), seed & 0xFFFFFFFFFFFFFFFF, C.byref(o))
+        self._totals(out, o)
         if st not in (0, 3):
             self._check(st)
         return st
+
+    def autotune(self, e0, polar, azimuth, seed: int, out: dict, x0=None, y0=None,
+                 shower_id_base: int = 0) -> dict:
+        """supa_autotune on this batch (outputs preallocated and large
+        enough); returns the chosen settings and the fastest call time."""
+        b, o = self._marshal(e0, polar, azimuth, out, x0, y0, shower_id_base)
+        best = (C.c_int32 * 4)()
+        ms = C.c_float()
+        st = self.lib.supa_autotune(self.ctx, C.byref(b), seed & 0xFFFFFFFFFFFFFFFF, C.byref(o),
+                                    best, C.byref(ms))
+        self._totals(out, o)
+        self._check(st)
+        return {"waves_per_cu": best[0], "frontier_cap": best[1], "sub_batches": best[2],
+                "cost_order": best[3], "ms": round(ms.value, 4)}
 
     def simulate(self, e0, polar, azimuth, seed: int, x0=None, y0=None,
                  shower_id_base: int = 0, hit_capacity: int | None = None,

@@ -184,7 +184,8 @@ def test_determinism_across_launch_settings():
     for launch in (dict(waves_per_cu=1, frontier_cap=128, hit_cap=64, node_cap=64),
                    dict(waves_per_cu=16), dict(waves_per_cu=4, frontier_cap=512),
                    dict(waves_per_cu=12, frontier_cap=128),
-                   dict(sub_batches=3), dict(waves_per_cu=2, sub_batches=8, hit_cap=64, node_cap=64)):
+                   dict(sub_batches=3, cost_order=1), dict(waves_per_cu=4, cost_order=1),
+                   dict(waves_per_cu=2, sub_batches=8, hit_cap=64, node_cap=64)):
         gpu, _ = run_gpu(geom, HITS_TREE, e0, pol, az, w.seed, **launch)
         parity.check_all(gpu, ref, geom, tree=True)
 
@@ -260,3 +261,19 @@ def test_full_size_100k_sampled_parity():
         gpu = sampled_segments(out, rows)
         ref = O.simulate(geom, e0[rows], pol[rows], az[rows], w.seed, shower_id_base=int(start))
         parity.check_all(gpu, ref, geom, images=True, tree=True)
+
+
+def test_autotune_keeps_results():
+    """The launch-setting search leaves one setting of its grid in the
+    context, and the outputs (from the winning setting) match the oracle."""
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w, 300)
+    ref = O.simulate(geom, e0, pol, az, w.seed)
+    sim = supa.Simulator(geom, ALL)
+    out = sim.allocate(300, len(ref["hit_e"]), len(ref["node_e"]))
+    best = sim.autotune(dev_t(e0), dev_t(pol), dev_t(az), w.seed, out)
+    assert best["waves_per_cu"] in (8, 12, 16) and best["frontier_cap"] in (128, 256)
+    assert best["sub_batches"] in (1, 2) and best["cost_order"] in (0, 1) and best["ms"] > 0
+    torch.cuda.synchronize()
+    parity.check_all(parity.to_numpy(out), ref, geom, tree=True)
