@@ -233,6 +233,33 @@ supa_status supa_autotune(supa_ctx *ctx, const supa_batch *b, uint64_t seed, sup
                           int32_t *best, float *best_ms);
 
 /*
+ * Captured calls (HIP graphs).  supa_graph_create runs supa_simulate once on
+ * the batch (sizing the library's scratch and checking the capacities), then
+ * captures the launch sequence of that call -- counters cleared, work order,
+ * propagation, offsets, placement, images, tree -- as one HIP graph with no
+ * host work, no allocation and no memset nodes.  The graph keeps the batch and
+ * output pointers of `b` and `out`; replays recompute the outputs from the
+ * current contents of the input arrays (so new initial conditions of the same
+ * count can be written in place between replays).
+ *   supa_graph_launch  enqueues one replay on hip_stream (NULL = the
+ *                      context's stream); nothing is synchronised.
+ *   supa_graph_check   synchronises hip_stream and reads the replay's
+ *                      counters: OK, RANGE, CAPACITY (outputs or library
+ *                      scratch too small for this replay: its results are not
+ *                      valid), DEVICE; totals3 (host, may be NULL) receives
+ *                      total hits, nodes, steps.
+ *   supa_graph_destroy frees the graph.
+ * A graph shares the context's counters and scratch: replays and other calls
+ * on one context must not overlap in time.
+ */
+typedef struct supa_graph supa_graph;
+supa_status supa_graph_create(supa_ctx *ctx, const supa_batch *b, uint64_t seed, supa_output *out,
+                              supa_graph **graph);
+supa_status supa_graph_launch(supa_graph *graph, void *hip_stream);
+supa_status supa_graph_check(supa_graph *graph, void *hip_stream, int64_t *totals3);
+supa_status supa_graph_destroy(supa_graph *graph);
+
+/*
  * Device time of the last supa_simulate, in milliseconds, measured with HIP
  * events: [0] propagation kernels (summed over sub-batches), [1] the kernels
  * after them (segment offsets, placement of hits and nodes, images; summed,

@@ -360,8 +360,8 @@ static int64_t round_up_pow2(int64_t v) {
     return p;
 }
 
-extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t seed,
-                                     supa_output *out) {
+// Argument checks of a simulate call (host only).
+static supa_status check_call(supa_ctx *c, const supa_batch *b, supa_output *out) {
     if (!c) return SUPA_ERR_STATE;
     if (c->broken) return fail(c, SUPA_ERR_STATE, "context unusable after a device error");
     c->err.clear();
@@ -384,242 +384,386 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
           out->node_capacity > 0) ||
          ((outs & SUPA_OUT_KEYS) && out->node_capacity > 0 && !out->node_key)))
         return fail(c, SUPA_ERR_INVALID_ARG, "tree outputs missing");
-    if (n == 0) return SUPA_OK;
+    return SUPA_OK;
+}
 
-    HIP_TRY(c, hipSetDevice(c->device));
-    const bool tree = (outs & SUPA_OUT_TREE) != 0;
-    const bool hits_out = (outs & SUPA_OUT_HITS) != 0;
-    const bool images = (outs & SUPA_OUT_IMAGES) != 0;
-    const bool recs = hits_out || images;
-    const int N = c->g.n_planes;
+// Everything one call launches: parameters and scratch pointers.
+struct Plan {
+    bool tree, hits_out, images, recs, post;
+    int N, nsub;
+    int64_t n, waves, img_words;
+    supa::Params P;
+    float e_unscale;
+    int64_t *d_hstart, *d_part;
+    int32_t *d_order;
+    uint32_t *d_ohist;
+    int64_t off(int j) const { return n * j / nsub; }
+};
+
+static constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Sizes the scratch for the call (growing it when needed) and fills the plan.
+static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa_output *out, Plan &L,
+                           int force_nsub) {
+    const uint32_t outs = c->g.outputs;
+    const int64_t n = b->n;
+    L.n = n;
+    L.tree = (outs & SUPA_OUT_TREE) != 0;
+    L.hits_out = (outs & SUPA_OUT_HITS) != 0;
+    L.images = (outs & SUPA_OUT_IMAGES) != 0;
+    L.recs = L.hits_out || L.images;
+    L.post = L.recs || L.tree;
+    L.N = c->g.n_planes;
+    L.waves = std::max(1, c->n_cu * c->waves_per_cu);
+    L.img_words = L.images ? (int64_t)c->n_layers * c->g.img_ny * c->g.img_nx : 0;
+    // sub-batches: the placement of sub-batch j (aux stream) overlaps the
+    // propagation of sub-batch j+1 (the context's stream); one by default
+    int nsub = force_nsub > 0 ? force_nsub : (c->sub_batches > 0 ? c->sub_batches : 1);
+    if (!L.post) nsub = 1;
+    L.nsub = (int)std::min<int64_t>(std::min(nsub, supa::MAX_SUB), n);
+
+    // scratch: per-wave spill, logs, per-shower log starts, scan tile sums, work order
+    const size_t spill_b = al256((size_t)L.waves * supa::POOL_FIELDS * c->spill_cap * 4);
+    if (!c->spill.ensure(spill_b)) return nomem(c, "spill area", spill_b);
+    const size_t hnext_b = L.recs ? al256((size_t)c->h_chunks * 4) : 0;
+    const size_t hlog_b = L.recs ? hnext_b + (size_t)c->h_chunks * supa::HIT_CHUNK_WORDS * 4 : 0;
+    if (L.recs && !c->hlog.ensure(hlog_b)) return nomem(c, "hit log", hlog_b);
+    const size_t nfill_b = L.tree ? al256((size_t)c->n_chunks * 4) : 0;
+    const size_t nlog_b = L.tree ? nfill_b + (size_t)c->n_chunks * supa::NL_FIELDS * supa::LOG_CHUNK * 4 : 0;
+    if (L.tree && !c->nlog.ensure(nlog_b)) return nomem(c, "node log", nlog_b);
+    const size_t hstart_b = L.recs ? al256((size_t)n * 8) : 0;
+    const size_t part_b = al256((size_t)supa::scan_partial_words(n) * 8);
+    const bool ordered = c->cost_order > 0 || (c->cost_order < 0 && n >= kAutoOrderMin);
+    const size_t order_b = ordered ? al256((size_t)n * 4) + al256((size_t)supa::order_scratch_words() * 4) : 0;
+    const size_t shower_b = hstart_b + part_b + order_b;
+    if (!c->shower.ensure(shower_b)) return nomem(c, "per-shower scratch", shower_b);
+    char *sh = (char *)c->shower.p;
+    L.d_hstart = L.recs ? (int64_t *)sh : nullptr;
+    L.d_part = (int64_t *)(sh + hstart_b);
+    L.d_order = ordered ? (int32_t *)(sh + hstart_b + part_b) : nullptr;
+    L.d_ohist = ordered ? (uint32_t *)(sh + hstart_b + part_b + al256((size_t)n * 4)) : nullptr;
+
+    supa::Params &P = L.P;
+    P = supa::Params{};
+    P.n_planes = L.N;
+    P.z_first = (float)c->g.z_first;
+    P.dz = (float)c->g.dz;
+    P.c1 = c->d_c1;
+    P.c2 = c->d_c2;
+    P.t_cut = c->t_cut;
+    P.f_lo = c->f_lo;
+    P.f_w = c->f_w;
+    P.angle_mode = c->g.angle_mode;
+    P.angle_a = (float)c->g.angle_a;
+    P.angle_b = (float)c->g.angle_b;
+    P.e_scale = std::ldexp(1.0f, c->g.energy_frac_bits);
+    P.seed_lo = (uint32_t)seed;
+    P.seed_hi = (uint32_t)(seed >> 32);
+    P.n = (int32_t)n;
+    P.sid_base = b->shower_id_base;
+    P.outputs = outs;
+    P.keys = (outs & SUPA_OUT_KEYS) != 0;
+    P.pool_cap = c->pool_cap;
+    P.spill_cap = c->spill_cap;
+    P.spill = (uint32_t *)c->spill.p;
+    P.hnext = L.recs ? (uint32_t *)c->hlog.p : nullptr;
+    P.hlog = L.recs ? (uint32_t *)((char *)c->hlog.p + hnext_b) : nullptr;
+    P.h_chunks = L.recs ? (int32_t)c->h_chunks : 0;
+    P.nfill = L.tree ? (uint32_t *)c->nlog.p : nullptr;
+    P.nlog = L.tree ? (uint32_t *)((char *)c->nlog.p + nfill_b) : nullptr;
+    P.n_chunks = L.tree ? (int32_t)c->n_chunks : 0;
+    P.ctr = c->d_ctr;
+    P.sub = nullptr;
+    L.e_unscale = std::ldexp(1.0f, -c->g.energy_frac_bits);
+
+    // the per-sub-batch input/output blocks, staged on the host
+    for (int j = 0; j < L.nsub; ++j) {
+        const int64_t o = L.off(j);
+        supa::Cold &K = c->h_cold[j];
+        std::memset(&K, 0, sizeof(K));
+        K.e0 = b->e0 + o;
+        K.polar = b->polar + o;
+        K.azimuth = b->azimuth + o;
+        K.x0 = b->x0 ? b->x0 + o : nullptr;
+        K.y0 = b->y0 ? b->y0 + o : nullptr;
+        K.order = L.d_order ? L.d_order + o : nullptr;
+        K.ledger = out->ledger + 4 * o;
+        K.counts = out->counts + 6 * o;
+        K.hstart = L.d_hstart ? L.d_hstart + o : nullptr;
+    }
+    return SUPA_OK;
+}
+
+// Launches the call: counters cleared, then per sub-batch the work order,
+// the propagation (main stream) and the scan, placement and node scatter
+// (second stream, after the propagation of the same sub-batch).  d_cold
+// holds the per-sub-batch blocks.  With timed, events bracket the parts.
+static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, const Plan &L,
+                           supa::Cold *d_cold, hipStream_t s_main, hipStream_t s_aux, bool timed) {
+    auto sub_ctr = [&](int j) { return c->d_ctr + supa::CTR_BLOCK * (1 + j); };
+    const supa::Params &P = L.P;
+    if (timed) HIP_TRY(c, hipEventRecord(c->ev_begin, s_main));
+    HIP_TRY(c, supa::launch_zero_counters(c->d_ctr, s_main));
+    for (int j = 0; j < L.nsub; ++j) {
+        const int64_t o = L.off(j), nj = L.off(j + 1) - o;
+        supa::Params Pj = P;
+        Pj.n = (int32_t)nj;
+        Pj.sid_base = b->shower_id_base + (uint32_t)o;
+        Pj.cold = d_cold + j;
+        Pj.sub = sub_ctr(j);
+        if (timed) HIP_TRY(c, hipEventRecord(c->ev_prop[j][0], s_main));
+        if (L.d_order)
+            HIP_TRY(c, supa::launch_cost_order(b->e0 + o, (int)nj, P.e_scale, L.d_ohist, L.d_order + o,
+                                               c->n_cu, s_main));
+        HIP_TRY(c, supa::launch_propagate(Pj, (int)L.waves, s_main));
+        if (L.tree) HIP_TRY(c, supa::launch_note_chunks(c->d_ctr, sub_ctr(j), s_main));
+        // the second stream waits on this event (none inside a capture, where
+        // both are one stream)
+        const bool two = s_aux != s_main;
+        if (timed || two) HIP_TRY(c, hipEventRecord(c->ev_prop[j][1], s_main));
+        if (!L.post) continue;
+
+        supa::ScanParams SP{};
+        SP.n = (int32_t)nj;
+        SP.counts = out->counts + 6 * o;
+        SP.hoff = L.hits_out ? out->hit_offsets + o : nullptr;
+        SP.noff = L.tree ? out->node_offsets + o : nullptr;
+        SP.partial = L.d_part;
+        SP.sub = sub_ctr(j);
+        SP.prev = j > 0 ? sub_ctr(j - 1) : nullptr;
+
+        supa::PlaceParams H{};
+        H.n = (int32_t)nj;
+        H.n_planes = L.N;
+        H.L = c->n_layers;
+        H.nx = c->g.img_nx;
+        H.ny = c->g.img_ny;
+        H.x0 = (float)c->g.img_x0;
+        H.y0 = (float)c->g.img_y0;
+        H.sx = L.images ? (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0)) : 0.0f;
+        H.sy = L.images ? (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0)) : 0.0f;
+        H.e_unscale = L.e_unscale;
+        H.ctr = c->d_ctr;
+        H.sub = sub_ctr(j);
+        H.counts = SP.counts;
+        H.hstart = L.d_hstart ? L.d_hstart + o : nullptr;
+        H.hlog = P.hlog;
+        H.hnext = P.hnext;
+        H.h_chunks = P.h_chunks;
+        H.layer = c->d_layer;
+        H.hoff = SP.hoff;
+        H.hcap = L.hits_out ? out->hit_capacity : 0;
+        H.hx = L.hits_out ? out->hit_x : nullptr;
+        H.hy = L.hits_out ? out->hit_y : nullptr;
+        H.he = L.hits_out ? out->hit_e : nullptr;
+        H.hl = L.hits_out ? out->hit_layer : nullptr;
+        H.hk = (L.hits_out && P.keys) ? out->hit_key : nullptr;
+        H.images = L.images ? out->images + L.img_words * o : nullptr;
+
+        supa::ScatterParams Q{};
+        Q.z_first = P.z_first;
+        Q.dz = P.dz;
+        Q.e_unscale = L.e_unscale;
+        Q.ctr = c->d_ctr;
+        Q.sub = sub_ctr(j);
+        Q.prev = SP.prev;
+        Q.nlog = P.nlog;
+        Q.nfill = P.nfill;
+        Q.n_chunks = P.n_chunks;
+        Q.noff = SP.noff;
+        Q.ncap = L.tree ? out->node_capacity : 0;
+        Q.np = out->node_parent;
+        Q.ng = out->node_gen;
+        Q.nvx = out->node_vx;
+        Q.nvy = out->node_vy;
+        Q.nvz = out->node_vz;
+        Q.ne = out->node_e;
+        Q.nk = (L.tree && P.keys) ? out->node_key : nullptr;
+
+        if (two) HIP_TRY(c, hipStreamWaitEvent(s_aux, c->ev_prop[j][1], 0));
+        if (timed) HIP_TRY(c, hipEventRecord(c->ev_post[j][0], s_aux));
+        HIP_TRY(c, supa::launch_scan(SP, s_aux));
+        if (L.recs) HIP_TRY(c, supa::launch_place(H, c->n_cu, s_aux));
+        if (L.tree) HIP_TRY(c, supa::launch_scatter_nodes(Q, (int32_t)nj, c->n_cu, s_aux));
+        if (timed || two) HIP_TRY(c, hipEventRecord(c->ev_post[j][1], s_aux));
+    }
+    if (L.post && s_aux != s_main) HIP_TRY(c, hipStreamWaitEvent(s_main, c->ev_post[L.nsub - 1][1], 0));
+    return SUPA_OK;
+}
+
+// Outcome of a call from the counters it left (host copy in c->h_ctr):
+// OK, CAPACITY, RANGE, DEVICE, or -1 when scratch ran out (grown here; rerun).
+static int finish(supa_ctx *c, const Plan &L, supa_output *out) {
+    const unsigned long long *h = c->h_ctr;
+    const unsigned long long flags = h[supa::CTR_FLAGS];
+    if (flags & supa::FLAG_RANGE)
+        return fail(c, SUPA_ERR_RANGE, "an initial energy is negative, NaN or too large for the fixed-point format");
+    const unsigned long long *last = h + supa::CTR_BLOCK * L.nsub;    // running totals
+    const int64_t total_hits = (int64_t)last[supa::SUB_HITS], total_nodes = (int64_t)last[supa::SUB_NODES];
+    if (flags & supa::FLAG_OVERFLOW) {
+        // grow what ran out: the spill area to the largest pool seen, a log
+        // to the totals (exact unless the spill overflowed too)
+        const int64_t nf = std::max<int64_t>(0, (int64_t)h[supa::CTR_NEED_F] - c->pool_cap);
+        c->spill_cap = (int)std::min<int64_t>((int64_t)1 << 30,
+                                              std::max<int64_t>(c->spill_cap, round_up_pow2(nf + 1)));
+        if (L.recs && (int64_t)h[supa::CTR_HCHUNK] > c->h_chunks)
+            c->h_chunks = std::max(2 * c->h_chunks, hit_chunks_for(total_hits, L.waves));
+        if (L.tree && (int64_t)h[supa::CTR_NCHUNK] > c->n_chunks)
+            c->n_chunks = std::max(2 * c->n_chunks, node_chunks_for(total_nodes, L.waves));
+        return -1;
+    }
+    // only meaningful when nothing overflowed (a lost spill entry breaks
+    // the particle accounting of its wave, and the batch is rerun anyway)
+    if (flags & supa::FLAG_INTERNAL) {
+        c->broken = true;
+        return fail(c, SUPA_ERR_DEVICE, "internal particle accounting error in the propagation kernel");
+    }
+    out->total_steps = (int64_t)h[supa::CTR_STEPS];
+    out->total_hits = L.hits_out ? total_hits : 0;
+    out->total_nodes = L.tree ? total_nodes : 0;
+    if (L.hits_out && total_hits > out->hit_capacity)
+        return fail(c, SUPA_ERR_CAPACITY, "hit arrays too small: need " + std::to_string(total_hits));
+    if (L.tree && total_nodes > out->node_capacity)
+        return fail(c, SUPA_ERR_CAPACITY, "node arrays too small: need " + std::to_string(total_nodes));
+    return SUPA_OK;
+}
+
+// first sizes of the logs: the caller's capacities (or 64 hits per shower
+// for images only), unless earlier batches needed more
+static void size_logs(supa_ctx *c, const supa_batch *b, const supa_output *out) {
+    const uint32_t outs = c->g.outputs;
     const int64_t waves = std::max(1, c->n_cu * c->waves_per_cu);
-    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    // first sizes of the logs: the caller's capacities (or 64 hits per shower
-    // for images only), unless earlier batches needed more
-    if (recs) {
-        const int64_t hint = hits_out ? out->hit_capacity : 64 * n;
+    if (outs & (SUPA_OUT_HITS | SUPA_OUT_IMAGES)) {
+        const int64_t hint = (outs & SUPA_OUT_HITS) ? out->hit_capacity : 64 * b->n;
         c->h_chunks = std::max(c->h_chunks, hit_chunks_for(std::min<int64_t>(hint, (int64_t)1 << 28), waves));
     }
-    if (tree)
+    if (outs & SUPA_OUT_TREE)
         c->n_chunks = std::max(c->n_chunks,
                                node_chunks_for(std::min<int64_t>(out->node_capacity, (int64_t)1 << 28), waves));
+}
 
+extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t seed,
+                                     supa_output *out) {
+    supa_status st = check_call(c, b, out);
+    if (st != SUPA_OK || b->n == 0) return st;
+    HIP_TRY(c, hipSetDevice(c->device));
+    size_logs(c, b, out);
     for (int attempt = 0; attempt < 8; ++attempt) {
-        // scratch: per-wave spill, logs, per-shower log starts and scan tile sums
-        const size_t spill_b = al((size_t)waves * supa::POOL_FIELDS * c->spill_cap * 4);
-        if (!c->spill.ensure(spill_b)) return nomem(c, "spill area", spill_b);
-        const size_t hnext_b = recs ? al((size_t)c->h_chunks * 4) : 0;
-        const size_t hlog_b = recs ? hnext_b + (size_t)c->h_chunks * supa::HIT_CHUNK_WORDS * 4 : 0;
-        if (recs && !c->hlog.ensure(hlog_b)) return nomem(c, "hit log", hlog_b);
-        const size_t nfill_b = tree ? al((size_t)c->n_chunks * 4) : 0;
-        const size_t nlog_b = tree ? nfill_b + (size_t)c->n_chunks * supa::NL_FIELDS * supa::LOG_CHUNK * 4 : 0;
-        if (tree && !c->nlog.ensure(nlog_b)) return nomem(c, "node log", nlog_b);
-        const size_t hstart_b = recs ? al((size_t)n * 8) : 0;
-        const size_t part_b = al((size_t)supa::scan_partial_words(n) * 8);
-        const bool ordered = c->cost_order > 0 || (c->cost_order < 0 && n >= kAutoOrderMin);
-        const size_t order_b = ordered ? al((size_t)n * 4) + al((size_t)supa::order_scratch_words() * 4) : 0;
-        const size_t shower_b = hstart_b + part_b + order_b;
-        if (!c->shower.ensure(shower_b)) return nomem(c, "per-shower scratch", shower_b);
-        char *sh = (char *)c->shower.p;
-        int64_t *d_hstart = recs ? (int64_t *)sh : nullptr;
-        int64_t *d_part = (int64_t *)(sh + hstart_b);
-        int32_t *d_order = ordered ? (int32_t *)(sh + hstart_b + part_b) : nullptr;
-        uint32_t *d_ohist = ordered ? (uint32_t *)(sh + hstart_b + part_b + al((size_t)n * 4)) : nullptr;
-
-        supa::Params P{};
-        P.n_planes = N;
-        P.z_first = (float)c->g.z_first;
-        P.dz = (float)c->g.dz;
-        P.c1 = c->d_c1;
-        P.c2 = c->d_c2;
-        P.t_cut = c->t_cut;
-        P.f_lo = c->f_lo;
-        P.f_w = c->f_w;
-        P.angle_mode = c->g.angle_mode;
-        P.angle_a = (float)c->g.angle_a;
-        P.angle_b = (float)c->g.angle_b;
-        P.e_scale = std::ldexp(1.0f, c->g.energy_frac_bits);
-        P.seed_lo = (uint32_t)seed;
-        P.seed_hi = (uint32_t)(seed >> 32);
-        P.n = (int32_t)n;
-        P.sid_base = b->shower_id_base;
-        P.outputs = outs;
-        P.keys = (outs & SUPA_OUT_KEYS) != 0;
-        P.cold = c->d_cold;
-        P.pool_cap = c->pool_cap;
-        P.spill_cap = c->spill_cap;
-        P.spill = (uint32_t *)c->spill.p;
-        P.hnext = recs ? (uint32_t *)c->hlog.p : nullptr;
-        P.hlog = recs ? (uint32_t *)((char *)c->hlog.p + hnext_b) : nullptr;
-        P.h_chunks = recs ? (int32_t)c->h_chunks : 0;
-        P.nfill = tree ? (uint32_t *)c->nlog.p : nullptr;
-        P.nlog = tree ? (uint32_t *)((char *)c->nlog.p + nfill_b) : nullptr;
-        P.n_chunks = tree ? (int32_t)c->n_chunks : 0;
-        P.ctr = c->d_ctr;
-        P.sub = nullptr;
-        const float e_unscale = std::ldexp(1.0f, -c->g.energy_frac_bits);
-
-        // sub-batches: the placement of sub-batch j (aux stream) overlaps the
-        // propagation of sub-batch j+1 (the context's stream)
-        const bool post = recs || tree;
-        // default one: measured on MI355X, the propagation kernel holds every
-        // register slot, so placement cannot run beside it and each extra
-        // sub-batch only adds a propagation tail
-        int nsub = c->sub_batches > 0 ? c->sub_batches : 1;
-        if (!post) nsub = 1;
-        nsub = (int)std::min<int64_t>(std::min(nsub, supa::MAX_SUB), n);
-        const int64_t img_words = images ? (int64_t)c->n_layers * c->g.img_ny * c->g.img_nx : 0;
-        auto off = [&](int j) { return n * j / nsub; };
-        auto sub_ctr = [&](int j) { return c->d_ctr + supa::CTR_BLOCK * (1 + j); };
-        for (int j = 0; j < nsub; ++j) {
-            const int64_t o = off(j);
-            supa::Cold &K = c->h_cold[j];
-            std::memset(&K, 0, sizeof(K));
-            K.e0 = b->e0 + o;
-            K.polar = b->polar + o;
-            K.azimuth = b->azimuth + o;
-            K.x0 = b->x0 ? b->x0 + o : nullptr;
-            K.y0 = b->y0 ? b->y0 + o : nullptr;
-            K.order = d_order ? d_order + o : nullptr;
-            K.ledger = out->ledger + 4 * o;
-            K.counts = out->counts + 6 * o;
-            K.hstart = d_hstart ? d_hstart + o : nullptr;
-        }
-        HIP_TRY(c, hipMemcpyAsync(c->d_cold, c->h_cold, nsub * sizeof(supa::Cold), hipMemcpyHostToDevice,
+        Plan L{};
+        st = prepare(c, b, seed, out, L, 0);
+        if (st != SUPA_OK) return st;
+        HIP_TRY(c, hipMemcpyAsync(c->d_cold, c->h_cold, L.nsub * sizeof(supa::Cold), hipMemcpyHostToDevice,
                                   c->stream));
-        HIP_TRY(c, hipEventRecord(c->ev_begin, c->stream));
-        HIP_TRY(c, supa::launch_zero_counters(c->d_ctr, c->stream));
-        for (int j = 0; j < nsub; ++j) {
-            const int64_t o = off(j), nj = off(j + 1) - o;
-            supa::Params Pj = P;
-            Pj.n = (int32_t)nj;
-            Pj.sid_base = b->shower_id_base + (uint32_t)o;
-            Pj.cold = c->d_cold + j;
-            Pj.sub = sub_ctr(j);
-            HIP_TRY(c, hipEventRecord(c->ev_prop[j][0], c->stream));
-            if (d_order)
-                HIP_TRY(c, supa::launch_cost_order(b->e0 + o, (int)nj, P.e_scale, d_ohist, d_order + o,
-                                                   c->n_cu, c->stream));
-            HIP_TRY(c, supa::launch_propagate(Pj, (int)waves, c->stream));
-            if (tree) HIP_TRY(c, supa::launch_note_chunks(c->d_ctr, sub_ctr(j), c->stream));
-            HIP_TRY(c, hipEventRecord(c->ev_prop[j][1], c->stream));
-            if (!post) continue;
-
-            supa::ScanParams SP{};
-            SP.n = (int32_t)nj;
-            SP.counts = out->counts + 6 * o;
-            SP.hoff = hits_out ? out->hit_offsets + o : nullptr;
-            SP.noff = tree ? out->node_offsets + o : nullptr;
-            SP.partial = d_part;
-            SP.sub = sub_ctr(j);
-            SP.prev = j > 0 ? sub_ctr(j - 1) : nullptr;
-
-            supa::PlaceParams H{};
-            H.n = (int32_t)nj;
-            H.n_planes = N;
-            H.L = c->n_layers;
-            H.nx = c->g.img_nx;
-            H.ny = c->g.img_ny;
-            H.x0 = (float)c->g.img_x0;
-            H.y0 = (float)c->g.img_y0;
-            H.sx = images ? (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0)) : 0.0f;
-            H.sy = images ? (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0)) : 0.0f;
-            H.e_unscale = e_unscale;
-            H.ctr = c->d_ctr;
-            H.sub = sub_ctr(j);
-            H.counts = SP.counts;
-            H.hstart = d_hstart ? d_hstart + o : nullptr;
-            H.hlog = P.hlog;
-            H.hnext = P.hnext;
-            H.h_chunks = P.h_chunks;
-            H.layer = c->d_layer;
-            H.hoff = SP.hoff;
-            H.hcap = hits_out ? out->hit_capacity : 0;
-            H.hx = hits_out ? out->hit_x : nullptr;
-            H.hy = hits_out ? out->hit_y : nullptr;
-            H.he = hits_out ? out->hit_e : nullptr;
-            H.hl = hits_out ? out->hit_layer : nullptr;
-            H.hk = (hits_out && P.keys) ? out->hit_key : nullptr;
-            H.images = images ? out->images + img_words * o : nullptr;
-
-            supa::ScatterParams Q{};
-            Q.z_first = P.z_first;
-            Q.dz = P.dz;
-            Q.e_unscale = e_unscale;
-            Q.ctr = c->d_ctr;
-            Q.sub = sub_ctr(j);
-            Q.prev = SP.prev;
-            Q.nlog = P.nlog;
-            Q.nfill = P.nfill;
-            Q.n_chunks = P.n_chunks;
-            Q.noff = SP.noff;
-            Q.ncap = tree ? out->node_capacity : 0;
-            Q.np = out->node_parent;
-            Q.ng = out->node_gen;
-            Q.nvx = out->node_vx;
-            Q.nvy = out->node_vy;
-            Q.nvz = out->node_vz;
-            Q.ne = out->node_e;
-            Q.nk = (tree && P.keys) ? out->node_key : nullptr;
-
-            HIP_TRY(c, hipStreamWaitEvent(c->aux, c->ev_prop[j][1], 0));
-            HIP_TRY(c, hipEventRecord(c->ev_post[j][0], c->aux));
-            HIP_TRY(c, supa::launch_scan(SP, c->aux));
-            if (recs) HIP_TRY(c, supa::launch_place(H, c->n_cu, c->aux));
-            if (tree) HIP_TRY(c, supa::launch_scatter_nodes(Q, (int32_t)nj, c->n_cu, c->aux));
-            HIP_TRY(c, hipEventRecord(c->ev_post[j][1], c->aux));
-        }
-        if (post) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_post[nsub - 1][1], 0));
+        st = enqueue(c, b, out, L, c->d_cold, c->stream, c->aux, true);
+        if (st != SUPA_OK) return st;
         HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_WORDS * sizeof(unsigned long long),
                                   hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         float t_prop = 0, t_post = 0, t_all = 0, t = 0;
-        for (int j = 0; j < nsub; ++j) {
+        for (int j = 0; j < L.nsub; ++j) {
             if (hipEventElapsedTime(&t, c->ev_prop[j][0], c->ev_prop[j][1]) == hipSuccess) t_prop += t;
-            if (post && hipEventElapsedTime(&t, c->ev_post[j][0], c->ev_post[j][1]) == hipSuccess) t_post += t;
+            if (L.post && hipEventElapsedTime(&t, c->ev_post[j][0], c->ev_post[j][1]) == hipSuccess) t_post += t;
         }
         (void)hipEventElapsedTime(&t_all, c->ev_begin, c->ev_end);
         (void)hipGetLastError();
         c->timing[0] = t_prop;
         c->timing[1] = t_post;
         c->timing[2] = t_all;
-        c->last_sub_batches = nsub;
-
-        const unsigned long long *h = c->h_ctr;
-        const unsigned long long flags = h[supa::CTR_FLAGS];
-        if (flags & supa::FLAG_RANGE)
-            return fail(c, SUPA_ERR_RANGE, "an initial energy is negative, NaN or too large for the fixed-point format");
-        const unsigned long long *last = h + supa::CTR_BLOCK * nsub;    // running totals
-        const int64_t total_hits = (int64_t)last[supa::SUB_HITS], total_nodes = (int64_t)last[supa::SUB_NODES];
-        if (flags & supa::FLAG_OVERFLOW) {
-            // grow what ran out and rerun: the spill area to the largest pool
-            // seen, a log to the totals (exact unless the spill overflowed too)
-            const int64_t nf = std::max<int64_t>(0, (int64_t)h[supa::CTR_NEED_F] - c->pool_cap);
-            c->spill_cap = (int)std::min<int64_t>((int64_t)1 << 30,
-                                                  std::max<int64_t>(c->spill_cap, round_up_pow2(nf + 1)));
-            if (recs && (int64_t)h[supa::CTR_HCHUNK] > c->h_chunks)
-                c->h_chunks = std::max(2 * c->h_chunks, hit_chunks_for(total_hits, waves));
-            if (tree && (int64_t)h[supa::CTR_NCHUNK] > c->n_chunks)
-                c->n_chunks = std::max(2 * c->n_chunks, node_chunks_for(total_nodes, waves));
-            continue;
-        }
-        // only meaningful when nothing overflowed (a lost spill entry breaks
-        // the particle accounting of its wave, and the batch is rerun anyway)
-        if (flags & supa::FLAG_INTERNAL) {
-            c->broken = true;
-            return fail(c, SUPA_ERR_DEVICE, "internal particle accounting error in the propagation kernel");
-        }
-        out->total_steps = (int64_t)h[supa::CTR_STEPS];
-        out->total_hits = hits_out ? total_hits : 0;
-        out->total_nodes = tree ? total_nodes : 0;
-        if (hits_out && total_hits > out->hit_capacity)
-            return fail(c, SUPA_ERR_CAPACITY, "hit arrays too small: need " + std::to_string(total_hits));
-        if (tree && total_nodes > out->node_capacity)
-            return fail(c, SUPA_ERR_CAPACITY, "node arrays too small: need " + std::to_string(total_nodes));
-        return SUPA_OK;
+        c->last_sub_batches = L.nsub;
+        const int r = finish(c, L, out);
+        if (r >= 0) return (supa_status)r;
     }
     return fail(c, SUPA_ERR_NOMEM, "scratch sizes did not converge");
+}
+
+// A captured call: the launch sequence of one supa_simulate (one sub-batch,
+// no host work) as an instantiated HIP graph, with its own copy of the
+// per-call input/output block so that replays do not depend on later calls.
+struct supa_graph {
+    supa_ctx *ctx = nullptr;
+    hipGraphExec_t exec = nullptr;
+    supa::Cold *d_cold = nullptr;
+    Plan plan{};
+    supa_output out{};
+};
+
+extern "C" supa_status supa_graph_create(supa_ctx *c, const supa_batch *b, uint64_t seed,
+                                         supa_output *out, supa_graph **gout) {
+    if (!c) return SUPA_ERR_STATE;
+    if (!gout) return fail(c, SUPA_ERR_INVALID_ARG, "graph out pointer is NULL");
+    *gout = nullptr;
+    supa_status st = check_call(c, b, out);
+    if (st != SUPA_OK) return st;
+    if (b->n == 0) return fail(c, SUPA_ERR_INVALID_ARG, "an empty batch has no graph");
+    // one eager call sizes every scratch buffer and checks the capacities
+    const int saved_sub = c->sub_batches;
+    c->sub_batches = 1;
+    st = supa_simulate(c, b, seed, out);
+    c->sub_batches = saved_sub;
+    if (st != SUPA_OK) return st;
+    supa_graph *g = new supa_graph();
+    g->ctx = c;
+    g->out = *out;
+    st = prepare(c, b, seed, out, g->plan, 1);         // sizes suffice: allocates nothing
+    if (st != SUPA_OK) {
+        delete g;
+        return st;
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipMalloc(&g->d_cold, sizeof(supa::Cold));
+    if (e == hipSuccess) e = hipMemcpy(g->d_cold, c->h_cold, sizeof(supa::Cold), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamBeginCapture(c->aux, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        st = enqueue(c, b, out, g->plan, g->d_cold, c->aux, c->aux, false);
+        const hipError_t e2 = hipStreamEndCapture(c->aux, &graph);
+        if (st == SUPA_OK && e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess && st == SUPA_OK) e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess || st != SUPA_OK) {
+        if (g->d_cold) (void)hipFree(g->d_cold);
+        delete g;
+        (void)hipGetLastError();
+        return st != SUPA_OK ? st : fail(c, SUPA_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    *gout = g;
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_graph_launch(supa_graph *g, void *hip_stream) {
+    if (!g || !g->ctx) return SUPA_ERR_STATE;
+    supa_ctx *c = g->ctx;
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipGraphLaunch(g->exec, hip_stream ? (hipStream_t)hip_stream : c->stream));
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_graph_check(supa_graph *g, void *hip_stream, int64_t *totals3) {
+    if (!g || !g->ctx) return SUPA_ERR_STATE;
+    supa_ctx *c = g->ctx;
+    const hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_WORDS * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    supa_output o = g->out;
+    int r = finish(c, g->plan, &o);
+    if (r < 0) r = fail(c, SUPA_ERR_CAPACITY, "library scratch too small for this replay: create the graph again");
+    if (totals3) {
+        totals3[0] = o.total_hits;
+        totals3[1] = o.total_nodes;
+        totals3[2] = o.total_steps;
+    }
+    return (supa_status)r;
+}
+
+extern "C" supa_status supa_graph_destroy(supa_graph *g) {
+    if (!g) return SUPA_ERR_STATE;
+    if (g->ctx) (void)hipSetDevice(g->ctx->device);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->d_cold) (void)hipFree(g->d_cold);
+    delete g;
+    return SUPA_OK;
 }
 
 // Launch-setting search: every combination of waves per CU, LDS pool size,

@@ -326,12 +326,18 @@ hipError_t launch_place(const PlaceParams &P0, int n_cu, hipStream_t s) {
     // the slab: image rows, or a staged segment of hits
     const size_t lds = PL_SLAB_WORDS * 4;
     // as many workgroups as fit on the device at once (each loops over showers)
-    int per_cu = 0;
-    const void *fn = P.hk ? (const void *)supa_place<true> : (const void *)supa_place<false>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, PL_THREADS, lds) != hipSuccess ||
-        per_cu < 1) {
-        (void)hipGetLastError();
-        per_cu = 1;
+    // (queried once per variant, so no runtime query happens while a caller
+    // captures a graph)
+    static int cached[2] = {0, 0};
+    int &per_cu = cached[P.hk ? 1 : 0];
+    if (per_cu == 0) {
+        const void *fn = P.hk ? (const void *)supa_place<true> : (const void *)supa_place<false>;
+        int q = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, fn, PL_THREADS, lds) != hipSuccess || q < 1) {
+            (void)hipGetLastError();
+            q = 1;
+        }
+        per_cu = q;
     }
     const int blocks = (int)std::min<int64_t>(P.n, (int64_t)n_cu * per_cu);
     if (P.hk)

@@ -69,7 +69,8 @@ class Output(C.Structure):
 
 
 EXPORTS = ["supa_abi_version", "supa_validate_geometry", "supa_init_geometry", "supa_destroy",
-           "supa_simulate", "supa_set_launch", "supa_set_schedule", "supa_autotune", "supa_last_timing", "supa_philox",
+           "supa_simulate", "supa_set_launch", "supa_set_schedule", "supa_autotune",
+           "supa_graph_create", "supa_graph_launch", "supa_graph_check", "supa_graph_destroy", "supa_last_timing", "supa_philox",
            "supa_last_error"]
 
 _lib = None
@@ -98,6 +99,15 @@ def load():
         L.supa_autotune.restype = C.c_int
         L.supa_autotune.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_uint64, C.POINTER(Output),
                                     C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+        L.supa_graph_create.restype = C.c_int
+        L.supa_graph_create.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_uint64, C.POINTER(Output),
+                                        C.POINTER(C.c_void_p)]
+        L.supa_graph_launch.restype = C.c_int
+        L.supa_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
+        L.supa_graph_check.restype = C.c_int
+        L.supa_graph_check.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]
+        L.supa_graph_destroy.restype = C.c_int
+        L.supa_graph_destroy.argtypes = [C.c_void_p]
         L.supa_set_schedule.restype = C.c_int
         L.supa_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.supa_last_timing.restype = C.c_int
@@ -289,6 +299,17 @@ class Simulator:
         return {"waves_per_cu": best[0], "frontier_cap": best[1], "sub_batches": best[2],
                 "cost_order": best[3], "ms": round(ms.value, 4)}
 
+    def graph(self, e0, polar, azimuth, seed: int, out: dict, x0=None, y0=None,
+              shower_id_base: int = 0) -> "Graph":
+        """Captures this call as a HIP graph (see supa_graph_create)."""
+        b, o = self._marshal(e0, polar, azimuth, out, x0, y0, shower_id_base)
+        g = C.c_void_p()
+        st = self.lib.supa_graph_create(self.ctx, C.byref(b), seed & 0xFFFFFFFFFFFFFFFF, C.byref(o),
+                                        C.byref(g))
+        self._totals(out, o)
+        self._check(st)
+        return Graph(self, g, (e0, polar, azimuth, x0, y0), out)
+
     def simulate(self, e0, polar, azimuth, seed: int, x0=None, y0=None,
                  shower_id_base: int = 0, hit_capacity: int | None = None,
                  node_capacity: int | None = None) -> dict:
@@ -329,3 +350,32 @@ def validate_geometry(geom: dict, outputs: int = OUT_HITS):
     st = lib.supa_validate_geometry(C.byref(g))
     if st != 0:
         raise SupaError(st, lib.supa_last_error(None).decode())
+
+
+class Graph:
+    """A captured supa_simulate call; keeps its tensors alive."""
+
+    def __init__(self, sim: Simulator, handle, inputs, out):
+        self.sim, self.handle, self.inputs, self.out = sim, handle, inputs, out
+
+    def launch(self, stream=None):
+        s = (stream or torch.cuda.current_stream(self.sim.device)).cuda_stream
+        self.sim._check(self.sim.lib.supa_graph_launch(self.handle, C.c_void_p(s)))
+
+    def check(self, stream=None):
+        s = (stream or torch.cuda.current_stream(self.sim.device)).cuda_stream
+        t = (C.c_int64 * 3)()
+        st = self.sim.lib.supa_graph_check(self.handle, C.c_void_p(s), t)
+        self.out["total_hits"], self.out["total_nodes"], self.out["total_steps"] = t[0], t[1], t[2]
+        self.sim._check(st)
+
+    def close(self):
+        if self.handle:
+            self.sim.lib.supa_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -277,3 +277,42 @@ def test_autotune_keeps_results():
     assert best["sub_batches"] in (1, 2) and best["cost_order"] in (0, 1) and best["ms"] > 0
     torch.cuda.synchronize()
     parity.check_all(parity.to_numpy(out), ref, geom, tree=True)
+
+
+def test_graph_replays_match_oracle():
+    """A captured call replays correctly several times, with other eager work
+    and synchronisations between the replays, and picks up new initial
+    conditions written into its input arrays."""
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = workloads.geometry(w)
+    n = 1000
+    e0, pol, az = workloads.initial_conditions(w, n)
+    e0b, polb, azb = workloads.initial_conditions(w, n, seed=77)
+    ref = O.simulate(geom, e0, pol, az, w.seed)
+    refb = O.simulate(geom, e0b, polb, azb, w.seed)
+    cap_h = int(1.25 * max(len(ref["hit_e"]), len(refb["hit_e"])))
+    cap_n = int(1.25 * max(len(ref["node_e"]), len(refb["node_e"])))
+    te0, tpol, taz = dev_t(e0), dev_t(pol), dev_t(az)
+    sim = supa.Simulator(geom, ALL)
+    out = sim.allocate(n, cap_h, cap_n)
+    g = sim.graph(te0, tpol, taz, w.seed, out)
+    other = supa.Simulator(geom, supa.OUT_HITS)
+    for rep in range(3):
+        for k, v in out.items():
+            if isinstance(v, torch.Tensor):
+                v.fill_(-7)                      # every replay must rewrite its outputs
+        g.launch()
+        g.check()
+        torch.cuda.synchronize()
+        parity.check_all(parity.to_numpy(out), ref, geom, tree=True)
+        assert out["total_hits"] == len(ref["hit_e"]) and out["total_nodes"] == len(ref["node_e"])
+        # unrelated eager work and a synchronisation between replays
+        other.simulate(te0[:200], tpol[:200], taz[:200], 5)
+        torch.cuda.synchronize()
+    for t, a in ((te0, e0b), (tpol, polb), (taz, azb)):
+        t.copy_(torch.from_numpy(a))
+    g.launch()
+    g.check()
+    torch.cuda.synchronize()
+    parity.check_all(parity.to_numpy(out), refb, geom, tree=True)
+    g.close()
