@@ -50,6 +50,8 @@ def parse():
                     help="sub-batches whose placement overlaps the next propagation (0: automatic)")
     ap.add_argument("--cost-order", type=int, default=-1, choices=(-1, 0, 1),
                     help="hand out expensive showers first (1), batch order (0), automatic (-1)")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of a captured HIP graph of the call")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the launch-setting search before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -197,14 +199,32 @@ def main():
         assert st == 0
     torch.cuda.synchronize()
     prop_ms, post_ms = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = sim.run(te0, tpol, taz, w.seed, out)
+    if args.graph:
+        # one captured call replayed: no host work between steps
+        g = sim.graph(te0, tpol, taz, w.seed, out)
+        sim.run(te0, tpol, taz, w.seed, out)          # kernel times of one eager call
         tm = sim.timing()
         prop_ms.append(tm[0])
         post_ms.append(tm[1])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+        for _ in range(args.warmup):
+            g.launch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.launch()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.check()
+        st = 0
+    else:
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            st = sim.run(te0, tpol, taz, w.seed, out)
+            tm = sim.timing()
+            prop_ms.append(tm[0])
+            post_ms.append(tm[1])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     assert st == 0
     ms_per_step = (t1 - t0) * 1e3 / args.steps
 
@@ -272,6 +292,8 @@ def main():
     }
     if launch is not None:
         line["launch"] = launch
+    if args.graph:
+        line["graph"] = True
     if roof_other is not None:
         line["roofline_other"] = roof_other
     if not args.no_cpu_baseline:
