@@ -523,42 +523,79 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
             estop.add(slot, is_stop ? p.e : 0u);
             ecut.add(slot, (cut_a ? ea : 0u) + (cut_b ? eb : 0u));
 
-            const uint64_t mvalid = wave_ballot(valid);
             const uint64_t mh1 = wave_ballot(hit1), mh2 = wave_ballot(hit2);
             const uint64_t mpa = wave_ballot(push_a), mpb = wave_ballot(push_b);
             const uint64_t msplit = wave_ballot(is_split), mpass = wave_ballot(is_pass);
             const uint64_t mesc = wave_ballot(esc_n > 0);
-            int node_a = 0;
-            for_each_slot(mvalid, slot, [&](int s0, uint64_t m) {
-                const uint64_t ms = msplit & m;
-                const int base = slot_get(S.nodes, s0);
-                if ((ms >> lane) & 1ull) node_a = base + 2 * (int)lanes_below(ms);
-                const int nh = (int)__popcll(mh1 & m) + (int)__popcll(mh2 & m);
-                if ((int)lane == s0) {
-                    S.nodes = base + 2 * (int)__popcll(ms);
-                    S.hits += nh;
-                    S.live += (int)__popcll(mpa & m) + (int)__popcll(mpb & m) - (int)__popcll(m);
-                    S.passes += (int)__popcll(mpass & m);
+            // the lanes of each shower slot; `mine`: this lane's slot, `own`:
+            // in lanes 0..SLOTS-1, the lanes of slot `lane` (whose state the
+            // lane holds).  Named registers: a run-time-indexed array would
+            // go to scratch memory.
+            const uint64_t sm0 = wave_ballot(valid && slot == 0), sm1 = wave_ballot(valid && slot == 1);
+            const uint64_t sm2 = wave_ballot(valid && slot == 2), sm3 = wave_ballot(valid && slot == 3);
+            const uint64_t mine = slot == 0 ? sm0 : slot == 1 ? sm1 : slot == 2 ? sm2 : sm3;
+            const uint64_t own = lane == 0 ? sm0 : lane == 1 ? sm1 : lane == 2 ? sm2 : lane == 3 ? sm3 : 0ull;
+            // node index of daughter a: the slot's node count + 2 per split below
+            const int node_a = __shfl(S.nodes, slot, WAVE) + 2 * (int)lanes_below(msplit & mine);
+            if (recs && (mh1 | mh2)) {
+                // hit records of every slot at once: the slot's chain position
+                // + this lane's rank among the slot's records of the step
+                const int c = __shfl(S.hc, slot, WAVE), f = __shfl(S.hf, slot, WAVE);
+                const int cnt_own = (int)__popcll(mh1 & own) + (int)__popcll(mh2 & own);
+                const bool over_own = S.hc >= 0 && S.hf + cnt_own > HIT_CHUNK;
+                // a slot whose chunk fills up links a fresh one (rare)
+                int c2_own = -1;
+                for (uint64_t mo = wave_ballot(over_own); mo; mo &= mo - 1) {
+                    const int q = __builtin_ctzll(mo);
+                    const int c2 = claim_hit_chunk();
+                    const int hc_q = slot_get(S.hc, q);
+                    if (c2 >= 0 && lane == 0) P.hnext[hc_q] = (uint32_t)c2;
+                    if ((int)lane == q) c2_own = c2;
                 }
-                if (mesc & m) {
-                    const bool mine = (m >> lane) & 1ull;
-                    const int sn = wave_sum_i32(mine ? esc_n : 0);
-                    const int sb = wave_sum_i32(mine ? back_n : 0);
-                    const uint32_t se = wave_sum_u32(mine ? esc_e : 0u);
+                const int c2 = __shfl(c2_own, slot, WAVE);
+                const int p1 = f + (int)lanes_below(mh1 & mine) + (int)lanes_below(mh2 & mine);
+                const int p2 = p1 + (hit1 ? 1 : 0);
+                if (hit1) {
+                    const int cc = p1 < HIT_CHUNK ? c : c2;
+                    const Hit h1 = is_stop ? Hit{p.x, p.y, p.e, (uint32_t)k, p.lo, p.hi}
+                                           : Hit{xa, ya, ea, (uint32_t)k + 1u, (uint32_t)pa, (uint32_t)(pa >> 32)};
+                    if (cc >= 0) write_hit(cc, p1 & (HIT_CHUNK - 1), h1);
+                }
+                if (hit2) {
+                    const int cc = p2 < HIT_CHUNK ? c : c2;
+                    const Hit h2{xb, yb, eb, (uint32_t)k + 1u, (uint32_t)pa | 1u, (uint32_t)(pa >> 32)};
+                    if (cc >= 0) write_hit(cc, p2 & (HIT_CHUNK - 1), h2);
+                }
+                if ((int)lane < SLOTS && S.hc >= 0) {
+                    if (over_own) {
+                        S.hc = c2_own;
+                        S.hf += cnt_own - HIT_CHUNK;
+                    } else {
+                        S.hf += cnt_own;
+                    }
+                }
+            }
+            // per-shower counts of slot `lane` (lanes 0..SLOTS-1)
+            if ((int)lane < SLOTS) {
+                S.hits += (int)__popcll(mh1 & own) + (int)__popcll(mh2 & own);
+                S.live += (int)__popcll(mpa & own) + (int)__popcll(mpb & own) - (int)__popcll(own);
+                S.passes += (int)__popcll(mpass & own);
+                S.nodes += 2 * (int)__popcll(msplit & own);
+            }
+            // leaks (after the last plane or backward): rare, per slot
+            if (mesc) {
+                for_each_slot(mesc, slot, [&](int s0, uint64_t m) {
+                    const bool in = (m >> lane) & 1ull;
+                    const int sn = wave_sum_i32(in ? esc_n : 0);
+                    const int sb = wave_sum_i32(in ? back_n : 0);
+                    const uint32_t se = wave_sum_u32(in ? esc_e : 0u);
                     if ((int)lane == s0) {
                         S.escaped += sn;
                         S.backward += sb;
                         S.e_esc += se;
                     }
-                }
-                if (recs && nh) {
-                    const Hit h1 = is_stop ? Hit{p.x, p.y, p.e, (uint32_t)k, p.lo, p.hi}
-                                           : Hit{xa, ya, ea, (uint32_t)k + 1u, (uint32_t)pa,
-                                                 (uint32_t)(pa >> 32)};
-                    const Hit h2{xb, yb, eb, (uint32_t)k + 1u, (uint32_t)pa | 1u, (uint32_t)(pa >> 32)};
-                    append_hits(s0, mh1 & m, mh2 & m, h1, h2);
-                }
-            });
+                });
+            }
             if (TREE && msplit) {
                 const int m = 2 * (int)__popcll(msplit);
                 const int ish = __shfl(S.i, slot, WAVE);
