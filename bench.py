@@ -52,8 +52,8 @@ def parse():
                     help="hand out expensive showers first (1), batch order (0), automatic (-1)")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of a captured HIP graph of the call")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="skip the launch-setting search before timing")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick launch settings by measurement before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -183,8 +183,7 @@ def main():
     # launch settings picked by measurement on this batch (untimed), unless
     # given on the command line
     launch = None
-    if not args.no_autotune and not (args.waves_per_cu or args.lds_cap or args.sub_batches
-                                     or args.cost_order != -1):
+    if args.autotune:
         launch = sim.autotune(te0, tpol, taz, w.seed, out)
 
     if args.copy_calibration:

@@ -261,9 +261,10 @@ supa_status supa_graph_destroy(supa_graph *graph);
 
 /*
  * Device time of the last supa_simulate, in milliseconds, measured with HIP
- * events: [0] propagation kernels (summed over sub-batches), [1] the kernels
- * after them (segment offsets, placement of hits and nodes, images; summed,
- * they overlap [0]), [2] whole call.  Host pointer to 3 floats.
+ * events: [0] propagation kernels (summed over sub-batches), [1] placement
+ * of hits, images and nodes (summed; with sub-batches they overlap [0]),
+ * [2] whole call (including work ordering and segment offsets).  Host
+ * pointer to 3 floats.
  */
 supa_status supa_last_timing(const supa_ctx *ctx, float *ms3);
 

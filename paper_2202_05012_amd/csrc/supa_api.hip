@@ -511,10 +511,10 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
         Pj.sid_base = b->shower_id_base + (uint32_t)o;
         Pj.cold = d_cold + j;
         Pj.sub = sub_ctr(j);
-        if (timed) HIP_TRY(c, hipEventRecord(c->ev_prop[j][0], s_main));
         if (L.d_order)
             HIP_TRY(c, supa::launch_cost_order(b->e0 + o, (int)nj, P.e_scale, L.d_ohist, L.d_order + o,
                                                c->n_cu, s_main));
+        if (timed) HIP_TRY(c, hipEventRecord(c->ev_prop[j][0], s_main));
         HIP_TRY(c, supa::launch_propagate(Pj, (int)L.waves, s_main));
         if (L.tree) HIP_TRY(c, supa::launch_note_chunks(c->d_ctr, sub_ctr(j), s_main));
         // the second stream waits on this event (none inside a capture, where
@@ -581,8 +581,8 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
         Q.nk = (L.tree && P.keys) ? out->node_key : nullptr;
 
         if (two) HIP_TRY(c, hipStreamWaitEvent(s_aux, c->ev_prop[j][1], 0));
-        if (timed) HIP_TRY(c, hipEventRecord(c->ev_post[j][0], s_aux));
         HIP_TRY(c, supa::launch_scan(SP, s_aux));
+        if (timed) HIP_TRY(c, hipEventRecord(c->ev_post[j][0], s_aux));
         if (L.recs) HIP_TRY(c, supa::launch_place(H, c->n_cu, s_aux));
         if (L.tree) HIP_TRY(c, supa::launch_scatter_nodes(Q, (int32_t)nj, c->n_cu, s_aux));
         if (timed || two) HIP_TRY(c, hipEventRecord(c->ev_post[j][1], s_aux));
