@@ -25,6 +25,7 @@ hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k
                          hipStream_t s);
 size_t propagate_lds_bytes(int pool_cap);
 hipError_t launch_place(const PlaceParams &P, int n_cu, hipStream_t s);
+void place_bucket_size(int L, int nx, int ny, bool keys, int n_cu, int64_t *per_block, int64_t *blocks);
 int64_t scan_partial_words(int64_t n);
 hipError_t launch_scan(const ScanParams &S, hipStream_t s);
 hipError_t launch_scatter_nodes(const ScatterParams &Q, int32_t n, int n_cu, hipStream_t s);
@@ -87,7 +88,7 @@ struct supa_ctx {
     int sub_batches = 0;                 // 0: chosen from the batch size
     int cost_order = -1;                 // hand out expensive showers first: 1 on, 0 off, -1 auto
     int last_sub_batches = 0;
-    DevBuf spill, hlog, nlog, shower;
+    DevBuf spill, hlog, nlog, shower, bucket;
     // the placement of a sub-batch runs on a second stream, overlapping the
     // propagation of the next one
     hipStream_t aux = nullptr;
@@ -284,7 +285,7 @@ extern "C" supa_status supa_destroy(supa_ctx *c) {
     if (!c) return SUPA_ERR_STATE;
     (void)hipSetDevice(c->device);
     if (c->stream || true) (void)hipStreamSynchronize(c->stream);
-    for (DevBuf *d : {&c->spill, &c->hlog, &c->nlog, &c->shower}) d->release();
+    for (DevBuf *d : {&c->spill, &c->hlog, &c->nlog, &c->shower, &c->bucket}) d->release();
     if (c->d_layer) (void)hipFree(c->d_layer);
     if (c->d_layer_plane_start) (void)hipFree(c->d_layer_plane_start);
     if (c->d_layer_planes) (void)hipFree(c->d_layer_planes);
@@ -397,6 +398,8 @@ struct Plan {
     int64_t *d_hstart, *d_part;
     int32_t *d_order;
     uint32_t *d_ohist;
+    uint2 *d_bucket;                 // placement's per-workgroup hit buckets, or null
+    int32_t bucket_cap;
     int64_t off(int j) const { return n * j / nsub; }
 };
 
@@ -442,6 +445,20 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
     L.d_part = (int64_t *)(sh + hstart_b);
     L.d_order = ordered ? (int32_t *)(sh + hstart_b + part_b) : nullptr;
     L.d_ohist = ordered ? (uint32_t *)(sh + hstart_b + part_b + al256((size_t)n * 4)) : nullptr;
+    // images of many slabs: per-workgroup buckets sorting a shower's hits by slab
+    L.d_bucket = nullptr;
+    L.bucket_cap = 0;
+    if (L.images) {
+        int64_t per = 0, blocks = 0;
+        supa::place_bucket_size(c->n_layers, c->g.img_nx, c->g.img_ny, L.hits_out && (outs & SUPA_OUT_KEYS),
+                                c->n_cu, &per, &blocks);
+        if (per > 0) {
+            const size_t bb = (size_t)per * blocks * sizeof(uint2);
+            if (!c->bucket.ensure(bb)) return nomem(c, "image buckets", bb);
+            L.d_bucket = (uint2 *)c->bucket.p;
+            L.bucket_cap = (int32_t)per;
+        }
+    }
 
     supa::Params &P = L.P;
     P = supa::Params{};
@@ -559,6 +576,8 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
         H.hl = L.hits_out ? out->hit_layer : nullptr;
         H.hk = (L.hits_out && P.keys) ? out->hit_key : nullptr;
         H.images = L.images ? out->images + L.img_words * o : nullptr;
+        H.bucket = L.d_bucket;
+        H.bucket_cap = L.bucket_cap;
 
         supa::ScatterParams Q{};
         Q.z_first = P.z_first;

@@ -175,6 +175,8 @@ struct PlaceParams {
     uint64_t *hk;                // path ids, or null
     float *images;               // [n][L][ny][nx], or null
     int32_t slab_rows;           // image rows binned per LDS pass
+    uint2 *bucket;               // per workgroup bucket_cap entries: a shower's binned
+    int32_t bucket_cap;          //   hits sorted by slab (images of many slabs), or null
 };
 
 // Arguments of the surrogate's matrix product (supa_mlp.hip).

@@ -28,6 +28,8 @@ constexpr int PL_THREADS = 512;
 constexpr int PL_UNROLL = 4;
 constexpr int PL_WIN = PL_THREADS * PL_UNROLL;      // records per window (two chunks)
 constexpr int PL_SLAB_WORDS = 8192;                 // 32 KB of LDS per workgroup
+constexpr int PL_MAX_SLABS = 2048;                  // slabs per image bucketed in LDS counts
+constexpr int PL_BUCKET_MIN_SLABS = 9;              // fewer slabs: bin the cached hits per slab
 static_assert(PL_WIN <= 2 * HIT_CHUNK, "a window spans at most three chunks");
 
 // Barrier for hand-offs through LDS only: waits for this wave's LDS
@@ -182,6 +184,23 @@ __device__ __forceinline__ void copy_out_hits(const PlaceParams &Q, const uint32
     }
 }
 
+// Image row and column of each hit of a window (row -1: outside the window or
+// not read out); the same arithmetic as binning.
+template <bool KEYS>
+__device__ __forceinline__ void cells(const PlaceParams &Q, const Window<KEYS> &W, const int32_t *lay,
+                                      int N, int (&row)[PL_UNROLL], int (&col)[PL_UNROLL]) {
+#pragma unroll
+    for (int u = 0; u < PL_UNROLL; ++u) {
+        const int k = W.k[u];
+        const int l = (k >= 0 && k < N) ? lay[k] : -1;
+        const float cx = floorf((W.x[u] - Q.x0) * Q.sx);
+        const float cy = floorf((W.y[u] - Q.y0) * Q.sy);
+        const bool in = l >= 0 && cx >= 0.0f && cx < (float)Q.nx && cy >= 0.0f && cy < (float)Q.ny;
+        row[u] = in ? l * Q.ny + (int)cy : -1;
+        col[u] = in ? (int)cx : 0;
+    }
+}
+
 // adds the window's hits that fall in image rows [row0, row0 + rows) to the slab
 template <bool KEYS>
 __device__ __forceinline__ void bin_window(const PlaceParams &Q, const Window<KEYS> &W, const int32_t *lay,
@@ -214,6 +233,18 @@ __device__ __forceinline__ void write_slab(const PlaceParams &Q, const uint32_t 
     }
 }
 
+// a slab without hits: zeros straight to memory
+__device__ __forceinline__ void write_zeros(float *dst, int words) {
+    if ((words & 3) == 0 && (((uintptr_t)dst) & 15) == 0) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int q = 4 * (int)threadIdx.x; q < words; q += 4 * PL_THREADS)
+            __builtin_nontemporal_store(z, (f4 *)(dst + q));
+    } else {
+        for (int q = (int)threadIdx.x; q < words; q += PL_THREADS) dst[q] = 0.0f;
+    }
+}
+
 __device__ __forceinline__ void clear_slab(uint32_t *slab, int words) {
     int q = 4 * (int)threadIdx.x;
     for (; q + 3 < words; q += 4 * PL_THREADS) *(uint4 *)(slab + q) = make_uint4(0u, 0u, 0u, 0u);
@@ -223,6 +254,7 @@ __device__ __forceinline__ void clear_slab(uint32_t *slab, int words) {
 template <bool KEYS>
 __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
     extern __shared__ uint32_t slab[];
+    __shared__ uint32_t scnt[PL_MAX_SLABS + 1];
     __shared__ int32_t lay[64];
     __shared__ uint32_t cnt[64];
     __shared__ Chain ch;
@@ -291,7 +323,81 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
             }
         }
 
-        if (img) {
+        const int nslab = (total_rows + Q.slab_rows - 1) / Q.slab_rows;
+        if (img && ok && Q.bucket && nslab >= PL_BUCKET_MIN_SLABS && nslab <= PL_MAX_SLABS &&
+            nh <= Q.bucket_cap) {
+            // many slabs: sort the shower's binned hits by slab first (counts
+            // in LDS, entries in the workgroup's global bucket), so that each
+            // slab adds only its own hits
+            float *dst = Q.images + (int64_t)i * total_rows * Q.nx;
+            uint2 *bk = Q.bucket + (int64_t)blockIdx.x * Q.bucket_cap;
+            for (int q = (int)threadIdx.x; q <= nslab; q += PL_THREADS) scnt[q] = 0u;
+            lds_barrier();
+            for (int w = 0; w < nwin; ++w) {
+                if (w > 0) walk_to_window(Q, ch, w, nh);
+                const Window<KEYS> W = w == 0 ? W0 : load_window<KEYS>(Q, ch, w, nh);
+                int row[PL_UNROLL], col[PL_UNROLL];
+                cells(Q, W, lay, N, row, col);
+#pragma unroll
+                for (int u = 0; u < PL_UNROLL; ++u)
+                    if (row[u] >= 0) atomicAdd(&scnt[row[u] / Q.slab_rows + 1], 1u);
+            }
+            lds_barrier();
+            if (threadIdx.x < 64) {
+                // scnt[1 + s] -> start of slab s, in place (one wave, 64 per pass)
+                uint32_t carry = 0u;
+                for (int b0 = 1; b0 <= nslab; b0 += 64) {
+                    const int q = b0 + (int)threadIdx.x;
+                    const uint32_t v = q <= nslab ? scnt[q] : 0u;
+                    uint32_t incl = v;
+#pragma unroll
+                    for (int off = 1; off < 64; off <<= 1) {
+                        const uint32_t t = __shfl_up(incl, off, 64);
+                        if ((int)threadIdx.x >= off) incl += t;
+                    }
+                    if (q <= nslab) scnt[q] = carry + incl - v;
+                    carry += __shfl(incl, 63, 64);
+                }
+                if (threadIdx.x == 0) scnt[0] = carry;      // binned hits in all
+            }
+            lds_barrier();
+            // scnt[1 + s] now runs as the fill cursor of slab s
+            for (int w = 0; w < nwin; ++w) {
+                if (w > 0) walk_to_window(Q, ch, w, nh);
+                const Window<KEYS> W = w == 0 ? W0 : load_window<KEYS>(Q, ch, w, nh);
+                int row[PL_UNROLL], col[PL_UNROLL];
+                cells(Q, W, lay, N, row, col);
+#pragma unroll
+                for (int u = 0; u < PL_UNROLL; ++u) {
+                    if (row[u] < 0) continue;
+                    const int sl = row[u] / Q.slab_rows;
+                    const uint32_t pos = atomicAdd(&scnt[sl + 1], 1u);
+                    bk[pos] = make_uint2((uint32_t)((row[u] - sl * Q.slab_rows) * Q.nx + col[u]), W.e[u]);
+                }
+            }
+            __syncthreads();                 // the bucket entries (global) are visible
+            // after the fill, scnt[1 + s] is the end of slab s: starts are the
+            // previous slab's end
+            for (int sl = 0; sl < nslab; ++sl) {
+                const int row0 = sl * Q.slab_rows;
+                const int rows = min(total_rows - row0, Q.slab_rows);
+                const int words = rows * Q.nx;
+                const uint32_t b0 = sl == 0 ? 0u : scnt[sl], b1 = scnt[sl + 1];
+                if (b0 == b1) {
+                    write_zeros(dst + (int64_t)row0 * Q.nx, words);
+                    continue;
+                }
+                clear_slab(slab, words);
+                lds_barrier();
+                for (uint32_t q = b0 + threadIdx.x; q < b1; q += PL_THREADS) {
+                    const uint2 v = bk[q];
+                    atomicAdd(&slab[v.x], v.y);
+                }
+                lds_barrier();
+                write_slab(Q, slab, dst + (int64_t)row0 * Q.nx, words);
+                lds_barrier();
+            }
+        } else if (img) {
             float *dst = Q.images + (int64_t)i * total_rows * Q.nx;
             for (int row0 = 0; row0 < total_rows; row0 += Q.slab_rows) {
                 const int rows = min(total_rows - row0, Q.slab_rows);
@@ -314,32 +420,45 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
     }
 }
 
-hipError_t launch_place(const PlaceParams &P0, int n_cu, hipStream_t s) {
-    if (P0.n <= 0 || (!P0.hx && !P0.images)) return hipSuccess;
-    PlaceParams P = P0;
-    if (P.images) {
-        // whole layers per slab when they fit, else bands of rows
-        const int64_t lw = (int64_t)P.ny * P.nx;
-        P.slab_rows = lw <= PL_SLAB_WORDS ? (int)(PL_SLAB_WORDS / lw) * P.ny
-                                          : std::max(1, PL_SLAB_WORDS / P.nx);
-    }
-    // the slab: image rows, or a staged segment of hits
-    const size_t lds = PL_SLAB_WORDS * 4;
-    // as many workgroups as fit on the device at once (each loops over showers)
-    // (queried once per variant, so no runtime query happens while a caller
-    // captures a graph)
+// rows of one LDS slab: whole layers when they fit, else bands of rows
+static int slab_rows_for(int nx, int ny) {
+    const int64_t lw = (int64_t)ny * nx;
+    return lw <= PL_SLAB_WORDS ? (int)(PL_SLAB_WORDS / lw) * ny : std::max(1, PL_SLAB_WORDS / nx);
+}
+
+// workgroups of one launch per compute unit (queried once per variant, so no
+// runtime query happens while a caller captures a graph)
+static int place_per_cu(bool keys) {
     static int cached[2] = {0, 0};
-    int &per_cu = cached[P.hk ? 1 : 0];
+    int &per_cu = cached[keys ? 1 : 0];
     if (per_cu == 0) {
-        const void *fn = P.hk ? (const void *)supa_place<true> : (const void *)supa_place<false>;
+        const void *fn = keys ? (const void *)supa_place<true> : (const void *)supa_place<false>;
         int q = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, fn, PL_THREADS, lds) != hipSuccess || q < 1) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, fn, PL_THREADS, PL_SLAB_WORDS * 4) != hipSuccess ||
+            q < 1) {
             (void)hipGetLastError();
             q = 1;
         }
         per_cu = q;
     }
-    const int blocks = (int)std::min<int64_t>(P.n, (int64_t)n_cu * per_cu);
+    return per_cu;
+}
+
+// Bucket scratch the placement of images of L x ny x nx needs: entries per
+// workgroup (0: none) and workgroups.
+void place_bucket_size(int L, int nx, int ny, bool keys, int n_cu, int64_t *per_block, int64_t *blocks) {
+    const int slabs = (L * ny + slab_rows_for(nx, ny) - 1) / slab_rows_for(nx, ny);
+    *per_block = (slabs >= PL_BUCKET_MIN_SLABS && slabs <= PL_MAX_SLABS) ? 65536 : 0;
+    *blocks = (int64_t)n_cu * place_per_cu(keys);
+}
+
+hipError_t launch_place(const PlaceParams &P0, int n_cu, hipStream_t s) {
+    if (P0.n <= 0 || (!P0.hx && !P0.images)) return hipSuccess;
+    PlaceParams P = P0;
+    if (P.images) P.slab_rows = slab_rows_for(P.nx, P.ny);
+    const size_t lds = PL_SLAB_WORDS * 4;
+    // as many workgroups as fit on the device at once (each loops over showers)
+    const int blocks = (int)std::min<int64_t>(P.n, (int64_t)n_cu * place_per_cu(P.hk != nullptr));
     if (P.hk)
         hipLaunchKernelGGL(supa_place<true>, dim3(blocks), dim3(PL_THREADS), lds, s, P);
     else
