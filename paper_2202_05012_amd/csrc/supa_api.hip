@@ -398,6 +398,7 @@ struct Plan {
     int64_t *d_hstart, *d_part;
     int32_t *d_order;
     uint32_t *d_ohist;
+    bool place_keys;                 // placement writes path ids
     uint2 *d_bucket;                 // placement's per-workgroup hit buckets, or null
     int32_t bucket_cap;
     int64_t off(int j) const { return n * j / nsub; }
@@ -445,13 +446,14 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
     L.d_part = (int64_t *)(sh + hstart_b);
     L.d_order = ordered ? (int32_t *)(sh + hstart_b + part_b) : nullptr;
     L.d_ohist = ordered ? (uint32_t *)(sh + hstart_b + part_b + al256((size_t)n * 4)) : nullptr;
+    // the placement kernel's variant (with path ids): sizes and launch must agree
+    L.place_keys = L.hits_out && (outs & SUPA_OUT_KEYS) && out->hit_key != nullptr;
     // images of many slabs: per-workgroup buckets sorting a shower's hits by slab
     L.d_bucket = nullptr;
     L.bucket_cap = 0;
     if (L.images) {
         int64_t per = 0, blocks = 0;
-        supa::place_bucket_size(c->n_layers, c->g.img_nx, c->g.img_ny, L.hits_out && (outs & SUPA_OUT_KEYS),
-                                c->n_cu, &per, &blocks);
+        supa::place_bucket_size(c->n_layers, c->g.img_nx, c->g.img_ny, L.place_keys, c->n_cu, &per, &blocks);
         if (per > 0) {
             const size_t bb = (size_t)per * blocks * sizeof(uint2);
             if (!c->bucket.ensure(bb)) return nomem(c, "image buckets", bb);
@@ -574,7 +576,7 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
         H.hy = L.hits_out ? out->hit_y : nullptr;
         H.he = L.hits_out ? out->hit_e : nullptr;
         H.hl = L.hits_out ? out->hit_layer : nullptr;
-        H.hk = (L.hits_out && P.keys) ? out->hit_key : nullptr;
+        H.hk = L.place_keys ? out->hit_key : nullptr;
         H.images = L.images ? out->images + L.img_words * o : nullptr;
         H.bucket = L.d_bucket;
         H.bucket_cap = L.bucket_cap;

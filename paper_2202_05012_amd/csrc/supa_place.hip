@@ -60,7 +60,10 @@ struct Chain {
 
 // Thread 0 follows the links up to the chunks of window w (records
 // [w*PL_WIN, min(nh, (w+1)*PL_WIN))); every thread then reads them from ch.
+// The barrier on entry keeps thread 0 from rewriting the window's chunk ids
+// while other waves still read those of the previous window.
 __device__ __forceinline__ void walk_to_window(const PlaceParams &Q, Chain &ch, int w, int nh) {
+    lds_barrier();
     if (threadIdx.x == 0 && !ch.bad) {
         const int lo = (ch.f0 + w * PL_WIN) >> HIT_CHUNK_LOG2;
         const int hi = (ch.f0 + min(nh, (w + 1) * PL_WIN) - 1) >> HIT_CHUNK_LOG2;
@@ -113,7 +116,9 @@ __device__ __forceinline__ Window<KEYS> load_window(const PlaceParams &Q, const 
         const int j = w * PL_WIN + u * PL_THREADS + (int)threadIdx.x;
         if (j < nh) {
             const int pos = ch.f0 + j;
-            const int c = ch.win[(pos >> HIT_CHUNK_LOG2) - lo];
+            const int hop = (pos >> HIT_CHUNK_LOG2) - lo;
+            const int c = (hop >= 0 && hop < 3) ? ch.win[hop] : -1;
+            if (c < 0 || c >= Q.h_chunks) continue;          // never outside the log
             const uint32_t *chunk = Q.hlog + (int64_t)c * HIT_CHUNK_WORDS;
             const int o = pos & (HIT_CHUNK - 1);
             const uint4 r = *(const uint4 *)(chunk + HIT_REC_WORDS * o);
@@ -140,12 +145,14 @@ __device__ __forceinline__ void count_planes(const Window<KEYS> &W, uint32_t *cn
 
 template <bool KEYS>
 __device__ __forceinline__ void place_hits(const PlaceParams &Q, const Window<KEYS> &W, uint32_t *cur,
-                                           const int32_t *lay, int64_t seg, int N) {
+                                           const int32_t *lay, int64_t seg, int nh, int N) {
 #pragma unroll
     for (int u = 0; u < PL_UNROLL; ++u) {
         const int k = W.k[u];
         if (k < 0 || k >= N) continue;
-        const int64_t o = seg + atomicAdd(&cur[k], 1u);
+        const uint32_t r = atomicAdd(&cur[k], 1u);
+        if (r >= (uint32_t)nh) continue;                  // never outside the segment
+        const int64_t o = seg + r;
         Q.hx[o] = W.x[u];
         Q.hy[o] = W.y[u];
         Q.he[o] = (float)W.e[u] * Q.e_unscale;
@@ -160,12 +167,13 @@ static_assert(4 * PL_WIN <= PL_SLAB_WORDS, "a staged segment fits the slab");
 
 template <bool KEYS>
 __device__ __forceinline__ void stage_hits(const PlaceParams &Q, const Window<KEYS> &W, uint32_t *cur,
-                                           const int32_t *lay, uint32_t *slab, int64_t seg, int N) {
+                                           const int32_t *lay, uint32_t *slab, int64_t seg, int nh, int N) {
 #pragma unroll
     for (int u = 0; u < PL_UNROLL; ++u) {
         const int k = W.k[u];
         if (k < 0 || k >= N) continue;
         const uint32_t r = atomicAdd(&cur[k], 1u);
+        if (r >= (uint32_t)nh) continue;                  // nh <= PL_WIN: inside the slab
         slab[r] = __float_as_uint(W.x[u]);
         slab[PL_WIN + r] = __float_as_uint(W.y[u]);
         slab[2 * PL_WIN + r] = __float_as_uint((float)W.e[u] * Q.e_unscale);
@@ -309,15 +317,15 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
                 if (nh <= PL_WIN) {
                     // the whole segment fits the LDS slab: sort into it, then
                     // write it out with contiguous stores
-                    stage_hits(Q, W0, cnt, lay, slab, seg, N);
+                    stage_hits(Q, W0, cnt, lay, slab, seg, nh, N);
                     lds_barrier();
                     copy_out_hits(Q, slab, seg, nh);
                     lds_barrier();
                 } else {
-                    place_hits(Q, W0, cnt, lay, seg, N);
+                    place_hits(Q, W0, cnt, lay, seg, nh, N);
                     for (int w = 1; w < nwin; ++w) {
                         walk_to_window(Q, ch, w, nh);
-                        place_hits(Q, load_window<KEYS>(Q, ch, w, nh), cnt, lay, seg, N);
+                        place_hits(Q, load_window<KEYS>(Q, ch, w, nh), cnt, lay, seg, nh, N);
                     }
                 }
             }
@@ -372,7 +380,8 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
                     if (row[u] < 0) continue;
                     const int sl = row[u] / Q.slab_rows;
                     const uint32_t pos = atomicAdd(&scnt[sl + 1], 1u);
-                    bk[pos] = make_uint2((uint32_t)((row[u] - sl * Q.slab_rows) * Q.nx + col[u]), W.e[u]);
+                    if (pos < (uint32_t)Q.bucket_cap)
+                        bk[pos] = make_uint2((uint32_t)((row[u] - sl * Q.slab_rows) * Q.nx + col[u]), W.e[u]);
                 }
             }
             __syncthreads();                 // the bucket entries (global) are visible
@@ -382,7 +391,8 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
                 const int row0 = sl * Q.slab_rows;
                 const int rows = min(total_rows - row0, Q.slab_rows);
                 const int words = rows * Q.nx;
-                const uint32_t b0 = sl == 0 ? 0u : scnt[sl], b1 = scnt[sl + 1];
+                const uint32_t b0 = sl == 0 ? 0u : scnt[sl];
+                const uint32_t b1 = min(scnt[sl + 1], (uint32_t)Q.bucket_cap);
                 if (b0 == b1) {
                     write_zeros(dst + (int64_t)row0 * Q.nx, words);
                     continue;
@@ -391,7 +401,7 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
                 lds_barrier();
                 for (uint32_t q = b0 + threadIdx.x; q < b1; q += PL_THREADS) {
                     const uint2 v = bk[q];
-                    atomicAdd(&slab[v.x], v.y);
+                    if (v.x < (uint32_t)words) atomicAdd(&slab[v.x], v.y);
                 }
                 lds_barrier();
                 write_slab(Q, slab, dst + (int64_t)row0 * Q.nx, words);

@@ -84,6 +84,21 @@ def test_fifty_planes_tree_and_256_images():
     check(geom, ALL, e0, pol, az, w.seed)
 
 
+def test_many_large_showers_at_once():
+    """Hundreds of showers of thousands of hits each in one placement launch:
+    every workgroup walks chains of many record windows at the same time.
+    The hit clouds (placed by plane) and, on a smaller set, the bucketed
+    256x256 images match the oracle exactly."""
+    w = workloads.WORKLOADS["loge10to1000_50planes_tree_img256_1m"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w, 4000)
+    top = np.argsort(-e0)
+    for rows, outputs in ((top[:400], supa.OUT_HITS | supa.OUT_KEYS),
+                          (top[400:424], supa.OUT_HITS | supa.OUT_IMAGES)):
+        gpu, ref = check(geom, outputs, e0[rows], pol[rows], az[rows], w.seed)
+        assert ref["counts"][:, 1].min() > 2 * 2048      # several windows per shower
+
+
 def random_geometry(rng, N, wide=False):
     ps = rng.uniform(0, 0.3, N)
     pl = rng.uniform(0.3, 1, N) * (1 - ps)
