@@ -94,7 +94,7 @@ def test_many_large_showers_at_once():
     e0, pol, az = workloads.initial_conditions(w, 4000)
     top = np.argsort(-e0)
     for rows, outputs in ((top[:400], supa.OUT_HITS | supa.OUT_KEYS),
-                          (top[400:424], supa.OUT_HITS | supa.OUT_IMAGES)):
+                          (top[400:424], supa.OUT_HITS | supa.OUT_IMAGES | supa.OUT_KEYS)):
         gpu, ref = check(geom, outputs, e0[rows], pol[rows], az[rows], w.seed)
         assert ref["counts"][:, 1].min() > 2 * 2048      # several windows per shower
 
