@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="pick launch settings by measurement before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=20000)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="wall time of the oracle's host-CPU baseline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--surrogate", action="store_true",
@@ -67,30 +68,48 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, geom, n_sample: int, images: bool):
+def cpu_baseline(w, geom, seconds: float, images: bool):
+    """The oracle on the host: blocks of 128 showers of the workload, taken
+    in order (wrapping around) by min(cores, 16) threads until `seconds` of
+    wall time have passed; rate = showers finished / elapsed time."""
+    import threading
     from oracle import supa_oracle as O
     from paper_2202_05012_amd import workloads
     threads = min(os.cpu_count() or 1, 16)
-    e0, pol, az = workloads.initial_conditions(w, n_sample)
-    chunk = 128
-
-    def run(s):
-        r = O.simulate(geom, e0[s:s + chunk], pol[s:s + chunk], az[s:s + chunk], w.seed,
-                       shower_id_base=s)
-        if images:
-            O.images(r, geom["n_planes"], geom["img_nx"], geom["img_ny"], geom["img_x0"],
-                     geom["img_x1"], geom["img_y0"], geom["img_y1"])
-        return int(r["counts"][:, 2].sum())
-
-    from concurrent.futures import ThreadPoolExecutor
+    e0, pol, az = workloads.initial_conditions(w)
+    block = 128
+    nblocks = (w.n + block - 1) // block
+    lock = threading.Lock()
+    state = {"next": 0, "showers": 0, "steps": 0}
     t0 = time.perf_counter()
-    with ThreadPoolExecutor(max_workers=threads) as ex:
-        steps = sum(ex.map(run, range(0, n_sample, chunk)))
+
+    def worker():
+        while time.perf_counter() - t0 < seconds:
+            with lock:
+                b = state["next"]
+                state["next"] += 1
+            s = (b % nblocks) * block
+            m = min(block, w.n - s)
+            r = O.simulate(geom, e0[s:s + m], pol[s:s + m], az[s:s + m], w.seed, shower_id_base=s)
+            if images:
+                O.images(r, geom["n_planes"], geom["img_nx"], geom["img_ny"], geom["img_x0"],
+                         geom["img_x1"], geom["img_y0"], geom["img_y1"])
+            with lock:
+                state["showers"] += m
+                state["steps"] += int(r["counts"][:, 2].sum())
+
+    ts = [threading.Thread(target=worker) for _ in range(threads)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
     dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "showers/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_sample} showers of the workload, oracle simulation"
-                      f"{' + image binning' if images else ''}, {threads} host threads",
-            "particle_steps_per_s": steps / dt, "seconds": dt}
+    n = state["showers"]
+    return {"value": n / dt, "unit": "showers/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} showers ({n / w.n:.2f} passes over the workload's showers, in blocks of "
+                      f"{block}), oracle simulation{' + image binning' if images else ''}, "
+                      f"{threads} host threads, {dt:.1f} s",
+            "particle_steps_per_s": state["steps"] / dt, "seconds": dt}
 
 
 def bench_surrogate(args):
@@ -159,6 +178,11 @@ def main():
     from paper_2202_05012_amd import supa, workloads
 
     w = workloads.WORKLOADS[args.workload]
+    if w.tree and w.images:
+        # batched runs of this workload (hit clouds + 50 x 256x256 images +
+        # tree) ended in a GPU memory fault whose cause is not found yet; only
+        # the parity tests run it, on up to 400 showers
+        sys.exit(f"bench.py does not run {w.name}: its batched run is disabled (open GPU fault)")
     geom = workloads.geometry(w)
     outputs = supa.OUT_HITS | (supa.OUT_IMAGES if w.images else 0) | (supa.OUT_TREE if w.tree else 0)
     if args.outputs:
@@ -296,7 +320,7 @@ def main():
     if roof_other is not None:
         line["roofline_other"] = roof_other
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, geom, min(args.cpu_sample, w.n), bool(w.images))
+        line["cpu_baseline"] = cpu_baseline(w, geom, args.cpu_seconds, bool(w.images))
     print(json.dumps(line), flush=True)
 
 
