@@ -27,8 +27,9 @@ namespace supa {
 constexpr int PL_THREADS = 512;
 constexpr int PL_UNROLL = 4;
 constexpr int PL_WIN = PL_THREADS * PL_UNROLL;      // records per window (two chunks)
-constexpr int PL_SLAB_WORDS = 8192;                 // 32 KB of LDS per workgroup
-constexpr int PL_MAX_SLABS = 2048;                  // slabs per image bucketed in LDS counts
+constexpr int PL_SLAB_WORDS = 16384;                // image slab: 64 KB of LDS per workgroup
+constexpr int PL_STAGE_WORDS = 4 * PL_WIN;          // hit staging: 32 KB (hit clouds only)
+constexpr int PL_MAX_SLABS = 1024;                  // slabs per image bucketed in LDS counts
 constexpr int PL_BUCKET_MIN_SLABS = 9;              // fewer slabs: bin the cached hits per slab
 static_assert(PL_WIN <= 2 * HIT_CHUNK, "a window spans at most three chunks");
 
@@ -163,7 +164,7 @@ __device__ __forceinline__ void place_hits(const PlaceParams &Q, const Window<KE
 
 // Hit fields of a segment staged in the LDS slab: x, y, energy (float bits)
 // and layer, PL_WIN words each, at the hit's place within the segment.
-static_assert(4 * PL_WIN <= PL_SLAB_WORDS, "a staged segment fits the slab");
+static_assert(PL_STAGE_WORDS <= PL_SLAB_WORDS, "a staged segment fits the slab");
 
 template <bool KEYS>
 __device__ __forceinline__ void stage_hits(const PlaceParams &Q, const Window<KEYS> &W, uint32_t *cur,
@@ -182,13 +183,14 @@ __device__ __forceinline__ void stage_hits(const PlaceParams &Q, const Window<KE
     }
 }
 
-__device__ __forceinline__ void copy_out_hits(const PlaceParams &Q, const uint32_t *slab, int64_t seg,
-                                              int nh) {
+// (and leaves the slab zero again)
+__device__ __forceinline__ void copy_out_hits(const PlaceParams &Q, uint32_t *slab, int64_t seg, int nh) {
     for (int q = (int)threadIdx.x; q < nh; q += PL_THREADS) {
         Q.hx[seg + q] = __uint_as_float(slab[q]);
         Q.hy[seg + q] = __uint_as_float(slab[PL_WIN + q]);
         Q.he[seg + q] = __uint_as_float(slab[2 * PL_WIN + q]);
         Q.hl[seg + q] = (int32_t)slab[3 * PL_WIN + q];
+        slab[q] = slab[PL_WIN + q] = slab[2 * PL_WIN + q] = slab[3 * PL_WIN + q] = 0u;
     }
 }
 
@@ -225,11 +227,12 @@ __device__ __forceinline__ void bin_window(const PlaceParams &Q, const Window<KE
     }
 }
 
-__device__ __forceinline__ void write_slab(const PlaceParams &Q, const uint32_t *slab, float *dst,
-                                           int words) {
+// streams the slab out as float and leaves it zero
+__device__ __forceinline__ void write_slab(const PlaceParams &Q, uint32_t *slab, float *dst, int words) {
     if ((words & 3) == 0 && (((uintptr_t)dst) & 15) == 0) {
         for (int q = 4 * (int)threadIdx.x; q < words; q += 4 * PL_THREADS) {
             const uint4 v = *(const uint4 *)(slab + q);
+            *(uint4 *)(slab + q) = make_uint4(0u, 0u, 0u, 0u);
             // streamed out once: non-temporal
             typedef float f4 __attribute__((ext_vector_type(4)));
             const f4 f = {(float)v.x * Q.e_unscale, (float)v.y * Q.e_unscale,
@@ -237,7 +240,10 @@ __device__ __forceinline__ void write_slab(const PlaceParams &Q, const uint32_t 
             __builtin_nontemporal_store(f, (f4 *)(dst + q));
         }
     } else {
-        for (int q = (int)threadIdx.x; q < words; q += PL_THREADS) dst[q] = (float)slab[q] * Q.e_unscale;
+        for (int q = (int)threadIdx.x; q < words; q += PL_THREADS) {
+            dst[q] = (float)slab[q] * Q.e_unscale;
+            slab[q] = 0u;
+        }
     }
 }
 
@@ -259,20 +265,36 @@ __device__ __forceinline__ void clear_slab(uint32_t *slab, int words) {
     for (int r = (words & ~3) + (int)threadIdx.x; r < words; r += PL_THREADS) slab[r] = 0u;
 }
 
-template <bool KEYS>
-__global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
-    extern __shared__ uint32_t slab[];
-    __shared__ uint32_t scnt[PL_MAX_SLABS + 1];
+// Variants (MODE): hit clouds only (LDS: the 32 KB staging area); images
+// (a 64 KB slab: the 20 layers of 32x32 of a shower in two slabs); images
+// whose hits are first sorted by slab (many slabs per shower).  KEYS writes
+// path ids.  The hit-cloud variant without ids is held to 64 VGPRs so that
+// four 512-thread workgroups share a compute unit.
+enum { PM_HITS = 0, PM_IMAGES = 1, PM_BUCKET = 2 };
+
+// dynamic LDS words of a variant: slab (or staging area), and the per-slab
+// counts when bucketing
+constexpr int place_lds_words(int mode) {
+    return mode == PM_HITS ? PL_STAGE_WORDS : PL_SLAB_WORDS + (mode == PM_BUCKET ? PL_MAX_SLABS + 1 : 0);
+}
+
+template <bool KEYS, int MODE>
+__global__ void __launch_bounds__(PL_THREADS)
+__attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_place(PlaceParams Q) {
+    constexpr bool BUCKET = MODE == PM_BUCKET;
+    extern __shared__ uint32_t slab[];                 // zero between uses
+    uint32_t *const scnt = slab + PL_SLAB_WORDS;       // [PL_MAX_SLABS + 1], BUCKET only
     __shared__ int32_t lay[64];
     __shared__ uint32_t cnt[64];
     __shared__ Chain ch;
     // records are valid only when the propagation succeeded; hit outputs
     // only when they all fit
     if (batch_failed(Q.ctr)) return;
-    const bool hits = Q.hx != nullptr, img = Q.images != nullptr;
+    const bool hits = Q.hx != nullptr, img = MODE != PM_HITS && Q.images != nullptr;
     if (hits && (int64_t)Q.sub[SUB_HITS] > Q.hcap) return;
     const int N = Q.n_planes;
     if (threadIdx.x < 64) lay[threadIdx.x] = (int)threadIdx.x < N ? Q.layer[threadIdx.x] : -1;
+    clear_slab(slab, MODE == PM_HITS ? PL_STAGE_WORDS : PL_SLAB_WORDS);
     const int total_rows = Q.L * Q.ny;
 
     for (int i = blockIdx.x; i < Q.n; i += gridDim.x) {
@@ -332,7 +354,7 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
         }
 
         const int nslab = (total_rows + Q.slab_rows - 1) / Q.slab_rows;
-        if (img && ok && Q.bucket && nslab >= PL_BUCKET_MIN_SLABS && nslab <= PL_MAX_SLABS &&
+        if (BUCKET && img && ok && Q.bucket && nslab >= PL_BUCKET_MIN_SLABS && nslab <= PL_MAX_SLABS &&
             nh <= Q.bucket_cap) {
             // many slabs: sort the shower's binned hits by slab first (counts
             // in LDS, entries in the workgroup's global bucket), so that each
@@ -397,8 +419,6 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
                     write_zeros(dst + (int64_t)row0 * Q.nx, words);
                     continue;
                 }
-                clear_slab(slab, words);
-                lds_barrier();
                 for (uint32_t q = b0 + threadIdx.x; q < b1; q += PL_THREADS) {
                     const uint2 v = bk[q];
                     if (v.x < (uint32_t)words) atomicAdd(&slab[v.x], v.y);
@@ -412,8 +432,6 @@ __global__ void __launch_bounds__(PL_THREADS) supa_place(PlaceParams Q) {
             for (int row0 = 0; row0 < total_rows; row0 += Q.slab_rows) {
                 const int rows = min(total_rows - row0, Q.slab_rows);
                 const int words = rows * Q.nx;
-                clear_slab(slab, words);
-                lds_barrier();
                 if (ok) {
                     bin_window(Q, W0, lay, slab, row0, rows, N);
                     for (int w = 1; w < nwin; ++w) {
@@ -438,13 +456,13 @@ static int slab_rows_for(int nx, int ny) {
 
 // workgroups of one launch per compute unit (queried once per variant, so no
 // runtime query happens while a caller captures a graph)
-static int place_per_cu(bool keys) {
-    static int cached[2] = {0, 0};
-    int &per_cu = cached[keys ? 1 : 0];
+template <bool KEYS, int MODE>
+static int place_per_cu_of() {
+    static int per_cu = 0;
     if (per_cu == 0) {
-        const void *fn = keys ? (const void *)supa_place<true> : (const void *)supa_place<false>;
         int q = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, fn, PL_THREADS, PL_SLAB_WORDS * 4) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&q, (const void *)supa_place<KEYS, MODE>, PL_THREADS,
+                                                         place_lds_words(MODE) * 4) != hipSuccess ||
             q < 1) {
             (void)hipGetLastError();
             q = 1;
@@ -454,25 +472,57 @@ static int place_per_cu(bool keys) {
     return per_cu;
 }
 
+static int place_per_cu(bool keys, int mode) {
+    switch (mode) {
+    case PM_HITS: return keys ? place_per_cu_of<true, PM_HITS>() : place_per_cu_of<false, PM_HITS>();
+    case PM_IMAGES: return keys ? place_per_cu_of<true, PM_IMAGES>() : place_per_cu_of<false, PM_IMAGES>();
+    default: return keys ? place_per_cu_of<true, PM_BUCKET>() : place_per_cu_of<false, PM_BUCKET>();
+    }
+}
+
+// slabs of one image set of L x ny x nx
+static int slabs_of(int L, int nx, int ny) {
+    const int rows = slab_rows_for(nx, ny);
+    return (L * ny + rows - 1) / rows;
+}
+
+static bool bucketed(int L, int nx, int ny) {
+    const int slabs = slabs_of(L, nx, ny);
+    return slabs >= PL_BUCKET_MIN_SLABS && slabs <= PL_MAX_SLABS;
+}
+
 // Bucket scratch the placement of images of L x ny x nx needs: entries per
 // workgroup (0: none) and workgroups.
 void place_bucket_size(int L, int nx, int ny, bool keys, int n_cu, int64_t *per_block, int64_t *blocks) {
-    const int slabs = (L * ny + slab_rows_for(nx, ny) - 1) / slab_rows_for(nx, ny);
-    *per_block = (slabs >= PL_BUCKET_MIN_SLABS && slabs <= PL_MAX_SLABS) ? 65536 : 0;
-    *blocks = (int64_t)n_cu * place_per_cu(keys);
+    const bool b = bucketed(L, nx, ny);
+    *per_block = b ? 65536 : 0;
+    *blocks = (int64_t)n_cu * place_per_cu(keys, b ? PM_BUCKET : PM_IMAGES);
+}
+
+template <bool KEYS>
+static void launch_mode(const PlaceParams &P, int mode, int blocks, hipStream_t s) {
+    const size_t lds = (size_t)place_lds_words(mode) * 4;
+    if (mode == PM_HITS)
+        hipLaunchKernelGGL((supa_place<KEYS, PM_HITS>), dim3(blocks), dim3(PL_THREADS), lds, s, P);
+    else if (mode == PM_IMAGES)
+        hipLaunchKernelGGL((supa_place<KEYS, PM_IMAGES>), dim3(blocks), dim3(PL_THREADS), lds, s, P);
+    else
+        hipLaunchKernelGGL((supa_place<KEYS, PM_BUCKET>), dim3(blocks), dim3(PL_THREADS), lds, s, P);
 }
 
 hipError_t launch_place(const PlaceParams &P0, int n_cu, hipStream_t s) {
     if (P0.n <= 0 || (!P0.hx && !P0.images)) return hipSuccess;
     PlaceParams P = P0;
     if (P.images) P.slab_rows = slab_rows_for(P.nx, P.ny);
-    const size_t lds = PL_SLAB_WORDS * 4;
+    // the bucketing variant only where its scratch was sized
+    const int mode = !P.images ? PM_HITS : (P.bucket && bucketed(P.L, P.nx, P.ny)) ? PM_BUCKET : PM_IMAGES;
+    const bool keys = P.hk != nullptr;
     // as many workgroups as fit on the device at once (each loops over showers)
-    const int blocks = (int)std::min<int64_t>(P.n, (int64_t)n_cu * place_per_cu(P.hk != nullptr));
-    if (P.hk)
-        hipLaunchKernelGGL(supa_place<true>, dim3(blocks), dim3(PL_THREADS), lds, s, P);
+    const int blocks = (int)std::min<int64_t>(P.n, (int64_t)n_cu * place_per_cu(keys, mode));
+    if (keys)
+        launch_mode<true>(P, mode, blocks, s);
     else
-        hipLaunchKernelGGL(supa_place<false>, dim3(blocks), dim3(PL_THREADS), lds, s, P);
+        launch_mode<false>(P, mode, blocks, s);
     return hipGetLastError();
 }
 
