@@ -134,7 +134,10 @@ def bench_surrogate(args):
         torch.cuda.synchronize()
         return r, time.perf_counter() - t0
 
-    SP.simulated_layer_energies(e0[:8192], pol[:8192], az[:8192], 3, sim)     # warm-up
+    # warm-up at full size: the simulator's logs and the caching allocator
+    # reach their sizes before anything is timed
+    SP.simulated_layer_energies(e0, pol, az, 3, sim)
+    SP.surrogate_layer_energies(model, e0, pol, az, 5, rho=rho)
     sim_e, t_sim = timed(lambda: SP.simulated_layer_energies(e0, pol, az, 3, sim))
     (sur_e, unc), t_sur = timed(lambda: SP.surrogate_layer_energies(model, e0, pol, az, 5, rho=rho))
     ref = sim_e.cpu().numpy()

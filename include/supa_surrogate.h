@@ -104,6 +104,25 @@ supa_status supa_surrogate_gate(void *hip_stream, int B, int D, int L, const flo
                                 float *unc, float *img, float rho, uint32_t row_base, uint64_t seed);
 
 /*
+ * The final layer and the gate in one pass, without the [B][2D] output: the
+ * same layer_e and unc as supa_surrogate_gate on out = h W + bias (up to the
+ * order of float additions), for W given transposed.  h bf16 [B][ldh] (the
+ * last hidden activations, K columns), w_t bf16 [2D][ldw] (row n = column n
+ * of W, K entries), bias float [2D].  Each 128-column tile of a row (half
+ * of a layer's bins, means or log-variances) is reduced in the product's
+ * epilogue into partial (float scratch, caller-owned, B * (2D / 128) * 2
+ * floats); a second kernel combines them per shower.  Requirements: K a
+ * multiple of 8, L <= 64, D / L a multiple of 128.
+ */
+supa_status supa_surrogate_gate_fused(void *hip_stream, int B, int K, int D, int L, const uint16_t *h, int ldh,
+                                      const uint16_t *w_t, int ldw, const float *bias, const float *e0,
+                                      float y_scale, float s_clamp, float *partial, float *layer_e, float *unc,
+                                      float rho, uint32_t row_base, uint64_t seed);
+
+/* y[c][r] = bf16(x[r][c]): float [rows][cols] to bf16 [cols][rows] (round to nearest even). */
+supa_status supa_transpose_to_bf16(void *hip_stream, int rows, int cols, const float *x, uint16_t *y);
+
+/*
  * idx[0..*count) = the indices i < n with v[i] > tau, increasing.  idx holds
  * n int32; count is one device int32; block_scratch holds ceil(n/1024) int32.
  */

@@ -189,6 +189,8 @@ struct GemmArgs {
     void *C;             // float [M][ldc] (EPI_F32, EPI_BIAS_F32) or bf16 [M][ldc]
     int ldc;
     uint16_t *pre;       // EPI_BIAS_GELU: pre-activation out; EPI_GELU_GRAD: in (bf16 [M][ldc])
+    int split;           // EPI_GATE: columns from split on are log-variances
+    float s_clamp;       // EPI_GATE: log-variance clamp
 };
 
 // Device counters of one call: a block for the whole call, then one block

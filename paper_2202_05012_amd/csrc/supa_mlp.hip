@@ -47,7 +47,7 @@ __device__ __forceinline__ float gelu_grad_f(float a) {
     return 0.5f * erfcf(-a * 0.707106781f) + a * 0.398942280f * __expf(-0.5f * a * a);
 }
 
-enum { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
+enum { EPI_F32 = 0, EPI_BIAS_F32 = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3, EPI_GATE = 4 };
 
 constexpr int GT = 128;         // tile edge
 constexpr int GK = 32;          // K step
@@ -126,6 +126,49 @@ __global__ void __launch_bounds__(256) gemm_bf16(GemmArgs g) {
         __syncthreads();
     }
 
+    if constexpr (EPI == EPI_GATE) {
+        // Final layer without its output: per row, the tile's 128 columns
+        // (all means, or all log-variances, of half a layer) reduce to
+        // sum mu, or to sum exp(s) and sum exp(s/2) with s clamped; written
+        // as C[m][tile][2] (float).  N is a multiple of GT.
+        __shared__ float red[2][GT][2];
+        const bool var = n0 >= g.split;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float p0 = 0.f, p1 = 0.f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const float v = acc[i][j][r] + g.bias[n0 + wn + j * 16 + lr];
+                    if (!var) {
+                        p0 += v;
+                    } else {
+                        const float sv = fminf(fmaxf(v, -g.s_clamp), g.s_clamp);
+                        p0 += __expf(sv);
+                        p1 += __expf(0.5f * sv);
+                    }
+                }
+#pragma unroll
+                for (int off = 1; off < 16; off <<= 1) {
+                    p0 += __shfl_xor(p0, off, 64);
+                    p1 += __shfl_xor(p1, off, 64);
+                }
+                if (lr == 0) {
+                    const int row = wm + i * 16 + (lane >> 4) * 4 + r;
+                    red[wave & 1][row][0] = p0;
+                    red[wave & 1][row][1] = p1;
+                }
+            }
+        __syncthreads();
+        if (tid < GT && m0 + tid < g.M) {
+            float *P = (float *)g.C + ((int64_t)(m0 + tid) * gridDim.x + blockIdx.x) * 2;
+            P[0] = red[0][tid][0] + red[1][tid][0];
+            P[1] = red[0][tid][1] + red[1][tid][1];
+        }
+        return;
+    }
+
     // accumulator element r of tile (i, j): row 4*(lane/16) + r, column lane%16
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -165,6 +208,7 @@ hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs &g, hipStream_t s
     SUPA_GEMM_CASE(0, 1, EPI_F32)
     SUPA_GEMM_CASE(0, 1, EPI_GELU_GRAD)
     SUPA_GEMM_CASE(1, 0, EPI_F32)
+    SUPA_GEMM_CASE(0, 1, EPI_GATE)
 #undef SUPA_GEMM_CASE
     return hipErrorInvalidValue;
 }
@@ -318,6 +362,89 @@ __global__ void gate_kernel(int B, int D, int L, const float *out, const float *
     if (threadIdx.x == 0) unc[b] = sqrtf(tv) / fmaxf(tm, 1e-6f);
 }
 
+// Per shower b (one wave; lane l < L takes layer l): the per-tile sums of
+// the fused final layer (P[b][tile][2], tiles of GT columns) combined into
+// what gate_kernel computes from the full output: per-layer energies (or
+// samples, same Philox counters) and the uncertainty score.
+__global__ void __launch_bounds__(256) gate_tiles_kernel(int B, int D, int L, const float *P, const float *e0,
+                                                         float y_scale, float *layer_e, float *unc, float rho,
+                                                         uint32_t row_base, uint32_t k0, uint32_t k1) {
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= B) return;                                   // whole waves leave together
+    const int tiles = 2 * D / GT, tpl = D / L / GT;
+    const float *row = P + (int64_t)b * tiles * 2;
+    float sm = 0.f, sv = 0.f, ss = 0.f;
+    if (lane < L) {
+        for (int t = 0; t < tpl; ++t) {
+            sm += row[2 * (lane * tpl + t)];
+            sv += row[2 * (D / GT + lane * tpl + t)];
+            ss += row[2 * (D / GT + lane * tpl + t) + 1];
+        }
+        float v = sm;
+        if (rho >= 0.0f) {
+            const uint4 w = philox4x32_10(row_base + (uint32_t)b, (uint32_t)lane, 0x9a7eu, 0u, k0, k1);
+            const float u1 = ((float)w.x + 0.5f) * 0x1p-32f, u2 = ((float)w.y + 0.5f) * 0x1p-32f;
+            float sn, cs;
+            sincospif(2.0f * u2, &sn, &cs);
+            const float z = sqrtf(-2.0f * logf(u1)) * cs;
+            v += sqrtf(rho * ss * ss + (1.0f - rho) * sv) * z;
+        }
+        layer_e[(int64_t)b * L + lane] = v * (e0[b] / y_scale);
+    }
+    float tm = sm, tv = sv;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        tm += __shfl_xor(tm, off, 64);
+        tv += __shfl_xor(tv, off, 64);
+    }
+    if (lane == 0) unc[b] = sqrtf(tv) / fmaxf(tm, 1e-6f);
+}
+
+// y[c][r] = bf16(x[r][c]) (float [rows][cols] -> bf16 [cols][rows])
+__global__ void transpose_bf16_kernel(int rows, int cols, const float *x, uint16_t *y) {
+    __shared__ float t[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    for (int q = threadIdx.y; q < 32; q += 8) {
+        const int r = r0 + q, c = c0 + threadIdx.x;
+        t[q][threadIdx.x] = (r < rows && c < cols) ? x[(int64_t)r * cols + c] : 0.0f;
+    }
+    __syncthreads();
+    for (int q = threadIdx.y; q < 32; q += 8) {
+        const int c = c0 + q, r = r0 + threadIdx.x;
+        if (c < cols && r < rows) y[(int64_t)c * rows + r] = f2bf(t[threadIdx.x][q]);
+    }
+}
+
+hipError_t launch_gate_fused(int B, int K, int D, int L, const uint16_t *h, int ldh, const uint16_t *wt, int ldw,
+                             const float *bias, const float *e0, float y_scale, float s_clamp, float *partial,
+                             float *layer_e, float *unc, float rho, uint32_t row_base, uint64_t seed,
+                             hipStream_t s) {
+    GemmArgs g{};
+    g.M = B;
+    g.N = 2 * D;
+    g.K = K;
+    g.A = h;
+    g.lda = ldh;
+    g.B = wt;
+    g.ldb = ldw;
+    g.bias = bias;
+    g.C = partial;
+    g.split = D;
+    g.s_clamp = s_clamp;
+    hipError_t e = launch_gemm(0, 1, EPI_GATE, g, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gate_tiles_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, B, D, L, partial, e0,
+                       y_scale, layer_e, unc, rho, row_base, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_bf16(int rows, int cols, const float *x, uint16_t *y, hipStream_t s) {
+    hipLaunchKernelGGL(transpose_bf16_kernel, dim3((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32)),
+                       dim3(32, 8), 0, s, rows, cols, x, y);
+    return hipGetLastError();
+}
+
 hipError_t launch_nll(int B, int D, const float *out, const float *img, const float *e0,
                       float y_scale, float s_clamp, int mse_mean, uint16_t *dout, float *loss,
                       hipStream_t s) {
@@ -452,13 +579,20 @@ __global__ void scatter_rows_kernel(int m, int w, const int32_t *idx, const floa
 }
 
 // per-row sums of groups: out[b][l] = sum_{q < g} x[b][l*g + q]
-__global__ void group_sums_kernel(int rows, int L, int g, const float *x, float *out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)rows * L) return;
+// one wave per group: its lanes read the group's g values with unit stride
+// (coalesced) and the partial sums meet in a butterfly reduction
+constexpr int GS_WAVES = 4;
+__global__ void __launch_bounds__(64 * GS_WAVES) group_sums_kernel(int rows, int L, int g, const float *x,
+                                                                  float *out) {
+    const int64_t t = (int64_t)blockIdx.x * GS_WAVES + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (t >= (int64_t)rows * L) return;              // whole waves leave together
     const float *p = x + t * g;
     float s = 0.f;
-    for (int q = 0; q < g; ++q) s += p[q];
-    out[t] = s;
+    for (int q = lane; q < g; q += 64) s += p[q];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) out[t] = s;
 }
 
 hipError_t launch_select(int n, const float *v, float tau, int32_t *idx, int32_t *count,
@@ -494,8 +628,8 @@ hipError_t launch_scatter_rows(int m, int w, const int32_t *idx, const float *sr
 hipError_t launch_group_sums(int rows, int L, int g, const float *x, float *out, hipStream_t s) {
     const int64_t t = (int64_t)rows * L;
     if (t <= 0) return hipSuccess;
-    hipLaunchKernelGGL(group_sums_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, s, rows, L,
-                       g, x, out);
+    hipLaunchKernelGGL(group_sums_kernel, dim3((unsigned)((t + GS_WAVES - 1) / GS_WAVES)), dim3(64 * GS_WAVES),
+                       0, s, rows, L, g, x, out);
     return hipGetLastError();
 }
 

@@ -54,10 +54,27 @@ __global__ void __launch_bounds__(ORDER_BUCKETS) order_scan(uint32_t *hist) {
     hist[t] = s[t] - hist[t];
 }
 
+// Each block takes a contiguous run of ORDER_RUN showers: counts per bucket
+// in LDS, one global reservation per bucket it holds (instead of one atomic
+// per shower on a few hot counters), then LDS ranks within its reservation.
+constexpr int ORDER_RUN = ORDER_THREADS * 16;
+
 __global__ void __launch_bounds__(ORDER_THREADS) order_scatter(const float *e0, int n, float e_scale,
                                                                 uint32_t *cursor, int32_t *order) {
-    for (int i = blockIdx.x * ORDER_THREADS + threadIdx.x; i < n; i += gridDim.x * ORDER_THREADS) {
-        const uint32_t pos = atomicAdd(&cursor[cost_bucket(e0[i], e_scale)], 1u);
+    __shared__ uint32_t cnt[ORDER_BUCKETS], base[ORDER_BUCKETS];
+    const int i0 = blockIdx.x * ORDER_RUN, i1 = min(n, i0 + ORDER_RUN);
+    for (int q = threadIdx.x; q < ORDER_BUCKETS; q += ORDER_THREADS) cnt[q] = 0u;
+    __syncthreads();
+    for (int i = i0 + threadIdx.x; i < i1; i += ORDER_THREADS) atomicAdd(&cnt[cost_bucket(e0[i], e_scale)], 1u);
+    __syncthreads();
+    for (int q = threadIdx.x; q < ORDER_BUCKETS; q += ORDER_THREADS) {
+        base[q] = cnt[q] ? atomicAdd(&cursor[q], cnt[q]) : 0u;
+        cnt[q] = 0u;
+    }
+    __syncthreads();
+    for (int i = i0 + threadIdx.x; i < i1; i += ORDER_THREADS) {
+        const int b = cost_bucket(e0[i], e_scale);
+        const uint32_t pos = base[b] + atomicAdd(&cnt[b], 1u);
         if (pos < (uint32_t)n) order[pos] = i;
     }
 }
@@ -77,8 +94,8 @@ hipError_t launch_cost_order(const float *e0, int n, float e_scale, uint32_t *hi
     hipLaunchKernelGGL(order_clear, dim3(ORDER_BUCKETS / 256), dim3(256), 0, s, hist);
     hipLaunchKernelGGL(order_hist, dim3(blocks), dim3(ORDER_THREADS), 0, s, e0, n, e_scale, hist);
     hipLaunchKernelGGL(order_scan, dim3(1), dim3(ORDER_BUCKETS), 0, s, hist);
-    hipLaunchKernelGGL(order_scatter, dim3(blocks), dim3(ORDER_THREADS), 0, s, e0, n, e_scale, hist,
-                       order);
+    hipLaunchKernelGGL(order_scatter, dim3((n + ORDER_RUN - 1) / ORDER_RUN), dim3(ORDER_THREADS), 0, s, e0, n,
+                       e_scale, hist, order);
     return hipGetLastError();
 }
 

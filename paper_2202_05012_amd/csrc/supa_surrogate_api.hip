@@ -31,6 +31,11 @@ hipError_t launch_gather3(int m, const int32_t *idx, const float *a, const float
 hipError_t launch_scatter_rows(int m, int w, const int32_t *idx, const float *src, float *dst,
                                hipStream_t s);
 hipError_t launch_group_sums(int rows, int L, int g, const float *x, float *out, hipStream_t s);
+hipError_t launch_gate_fused(int B, int K, int D, int L, const uint16_t *h, int ldh, const uint16_t *wt, int ldw,
+                             const float *bias, const float *e0, float y_scale, float s_clamp, float *partial,
+                             float *layer_e, float *unc, float rho, uint32_t row_base, uint64_t seed,
+                             hipStream_t s);
+hipError_t launch_transpose_bf16(int rows, int cols, const float *x, uint16_t *y, hipStream_t s);
 }  // namespace supa
 
 static thread_local std::string t_err;
@@ -117,6 +122,29 @@ extern "C" supa_status supa_surrogate_gate(void *stream, int B, int D, int L, co
     if (!out || !e0 || !layer_e || !unc) return bad("NULL pointer");
     return dev(supa::launch_gate(B, D, L, out, e0, y_scale, s_clamp, layer_e, unc, img, rho, row_base,
                                  seed, (hipStream_t)stream), "gate");
+}
+
+extern "C" supa_status supa_surrogate_gate_fused(void *stream, int B, int K, int D, int L, const uint16_t *h,
+                                                 int ldh, const uint16_t *w_t, int ldw, const float *bias,
+                                                 const float *e0, float y_scale, float s_clamp, float *partial,
+                                                 float *layer_e, float *unc, float rho, uint32_t row_base,
+                                                 uint64_t seed) {
+    if (B < 0 || K < 8 || K % 8 || L < 1 || L > 64 || D < L || D % L || (D / L) % 128)
+        return bad("bad fused gate sizes (K multiple of 8, L <= 64, bins per layer multiple of 128)");
+    if (ldh < K || ldw < K || ldh % 8 || ldw % 8) return bad("bad leading dimensions");
+    if (!(s_clamp >= 0) || !std::isfinite(s_clamp)) return bad("s_clamp must be finite and >= 0");
+    if (rho > 1.0f) return bad("rho must be <= 1 (negative: no sampling)");
+    if (B == 0) return SUPA_OK;
+    if (!h || !w_t || !bias || !e0 || !partial || !layer_e || !unc) return bad("NULL pointer");
+    return dev(supa::launch_gate_fused(B, K, D, L, h, ldh, w_t, ldw, bias, e0, y_scale, s_clamp, partial, layer_e,
+                                       unc, rho, row_base, seed, (hipStream_t)stream),
+               "gate_fused");
+}
+
+extern "C" supa_status supa_transpose_to_bf16(void *stream, int rows, int cols, const float *x, uint16_t *y) {
+    if (rows < 0 || cols < 0 || ((int64_t)rows * cols > 0 && (!x || !y))) return bad("bad transpose arguments");
+    if ((int64_t)rows * cols == 0) return SUPA_OK;
+    return dev(supa::launch_transpose_bf16(rows, cols, x, y, (hipStream_t)stream), "transpose_to_bf16");
 }
 
 extern "C" supa_status supa_select_above(void *stream, int n, const float *v, float tau, int32_t *idx,

@@ -44,6 +44,9 @@ def _lib():
             "supa_gather3": [vp, i, vp, vp, vp, vp, vp, vp, vp],
             "supa_scatter_rows": [vp, i, i, vp, vp, vp],
             "supa_group_sums": [vp, i, i, i, vp, vp],
+            "supa_surrogate_gate_fused": [vp, i, i, i, i, vp, i, vp, i, vp, vp, f, f, vp, vp, vp, f, u32,
+                                          u64],
+            "supa_transpose_to_bf16": [vp, i, i, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -117,6 +120,30 @@ def gate(out, e0, n_layers, want_image=False, rho=-1.0, seed=0, row_base=0):
     return layer_e, unc, img
 
 
+def transpose_to_bf16(x: torch.Tensor) -> torch.Tensor:
+    """float32 [r, c] -> bf16 bit patterns of its transpose [c, r] (library kernel)."""
+    x = x.contiguous()
+    r, c = x.shape
+    y = torch.empty((c, r), dtype=torch.int16, device=x.device)
+    _check(_lib().supa_transpose_to_bf16(_stream(), r, c, _p(x), _p(y)))
+    return y
+
+
+def gate_fused(h, w_t, bias, e0, n_layers, rho=-1.0, seed=0, row_base=0):
+    """Final layer + gate in one pass (supa_surrogate_gate_fused): h bf16 [B, K]
+    last hidden activations, w_t bf16 [2D, K] the final weights transposed."""
+    B, K = h.shape
+    D = w_t.shape[0] // 2
+    layer_e = torch.empty((B, n_layers), dtype=torch.float32, device=h.device)
+    unc = torch.empty(B, dtype=torch.float32, device=h.device)
+    partial = torch.empty((max(B, 1), (2 * D) // 128, 2), dtype=torch.float32, device=h.device)
+    _check(_lib().supa_surrogate_gate_fused(_stream(), B, K, D, n_layers, _p(h), h.stride(0), _p(w_t),
+                                            w_t.stride(0), _p(bias), _p(e0), Y_SCALE, S_CLAMP, _p(partial),
+                                            _p(layer_e), _p(unc), float(rho), row_base & 0xFFFFFFFF,
+                                            seed & 0xFFFFFFFFFFFFFFFF))
+    return layer_e, unc
+
+
 def select_above(v, tau):
     n = int(v.shape[0])
     idx = torch.empty(max(n, 1), dtype=torch.int32, device=v.device)
@@ -179,6 +206,7 @@ class MLP:
             self.W[l].copy_(torch.as_tensor(w, dtype=torch.float32))
             self.b[l].copy_(torch.as_tensor(b, dtype=torch.float32))
             self.Wb[l] = to_bf16(self.W[l])
+        self._wt_step = None
 
     def forward(self, x, keep=False):
         """x: bf16 [B, IN_PAD] -> float32 [B, out]; keep=True also returns
@@ -200,6 +228,29 @@ class MLP:
                 out = torch.empty((B, dout), dtype=torch.float32, device=self.device)
                 gemm(h, self.Wb[l], out, epilogue=1, bias=self.b[l])
         return (out, acts, pres) if keep else out
+
+    def hidden(self, x):
+        """x: bf16 [B, IN_PAD] -> the last hidden activations, bf16 [B, hidden]."""
+        h = x
+        for l in range(len(self.Wb) - 1):
+            y = torch.empty((x.shape[0], self.dims[l + 1]), dtype=torch.int16, device=self.device)
+            pre = torch.empty_like(y)
+            gemm(h, self.Wb[l], y, epilogue=2, bias=self.b[l], pre=pre)
+            h = y
+        return h
+
+    def final_weights_t(self):
+        """bf16 transpose of the final layer's weights (cached per optimiser step)."""
+        if getattr(self, "_wt_step", None) != self.step:
+            self._wt = transpose_to_bf16(self.W[-1])
+            self._wt_step = self.step
+        return self._wt
+
+    def layer_energies(self, x, e0, n_layers, rho=-1.0, seed=0, row_base=0):
+        """Per-layer energies and uncertainty scores of the inputs x, with the
+        final layer fused into the gate (no [B, 2D] output)."""
+        return gate_fused(self.hidden(x), self.final_weights_t(), self.b[-1], e0, n_layers, rho=rho,
+                          seed=seed, row_base=row_base)
 
     def backward(self, acts, pres, dout):
         """dout: bf16 [B, out] = d loss / d out; returns float32 (dW, db) lists."""

@@ -81,8 +81,7 @@ def surrogate_layer_energies(model: S.MLP, e0, pol, az, seed, chunk=65536, row_b
     for s in range(0, n, chunk):
         sl = slice(s, min(n, s + chunk))
         x = S.features(e0[sl], pol[sl], az[sl], seed, row_base=row_base + s, stream_id=2)
-        out = model.forward(x)
-        le, u, _ = S.gate(out, e0[sl], N_LAYERS, rho=rho, seed=seed, row_base=row_base + s)
+        le, u = model.layer_energies(x, e0[sl], N_LAYERS, rho=rho, seed=seed, row_base=row_base + s)
         layer_e[sl] = le
         unc[sl] = u
     return layer_e, unc

@@ -198,3 +198,39 @@ def test_gate_select_gather_scatter():
     assert torch.equal(dst[ti.long()], src)
     gs = S.group_sums(torch.from_numpy(out[:, :D]).cuda(), L).cpu().numpy()
     np.testing.assert_allclose(gs, SO.layer_sums(mu, L), rtol=1e-5, atol=1e-5)
+
+
+@pytest.mark.parametrize("rho", [-1.0, 0.5])
+def test_gate_fused_matches_gate_and_oracle(rho):
+    """The final layer fused into the gate (per-tile reductions in the matrix
+    product's epilogue, no [B, 2D] output) gives the per-layer energies and
+    uncertainty scores of the unfused product + gate, and of the FP64 oracle
+    on the same bf16 inputs (exact sums of the float32-accumulated products
+    up to the order of additions)."""
+    rng = np.random.default_rng(31)
+    B, K, L, bins = 296, 64, 4, 128                 # B ragged against the 128-row tiles
+    D = L * bins
+    h = bf16_round(rng.normal(size=(B, K)))
+    W = (rng.normal(size=(K, 2 * D)) * 0.1).astype(np.float32)
+    W[:, D:] *= 3.0                                 # log-variances over a few units
+    bias = rng.normal(size=2 * D).astype(np.float32) * 0.1
+    bias[:D] += 1.0                                 # positive means: a well-conditioned score
+    e0 = rng.uniform(1, 100, size=B).astype(np.float32)
+    Wb = bf16_round(W)
+    tW = torch.from_numpy(W).cuda()
+    wt = S.transpose_to_bf16(tW)
+    assert np.array_equal(host16(wt), np.ascontiguousarray(Wb.T))
+    th, tb, te = dev16(h), torch.from_numpy(bias).cuda(), torch.from_numpy(e0).cuda()
+    le_f, unc_f = S.gate_fused(th, wt, tb, te, L, rho=rho, seed=9, row_base=77)
+    out = torch.empty((B, 2 * D), dtype=torch.float32, device="cuda")
+    S.gemm(th, dev16(Wb), out, 0, 0, 1, bias=tb)
+    le_u, unc_u, _ = S.gate(out, te, L, rho=rho, seed=9, row_base=77)
+    np.testing.assert_allclose(le_f.cpu().numpy(), le_u.cpu().numpy(), rtol=2e-4, atol=1e-5)
+    np.testing.assert_allclose(unc_f.cpu().numpy(), unc_u.cpu().numpy(), rtol=2e-4)
+    if rho < 0:
+        o = bf16_to_np(h).astype(np.float64) @ bf16_to_np(Wb).astype(np.float64) + bias
+        mu, s = o[:, :D], o[:, D:]
+        ys = S.Y_SCALE
+        np.testing.assert_allclose(le_f.cpu().numpy(), SO.layer_sums(mu, L) * e0[:, None] / ys,
+                                   rtol=2e-4, atol=2e-4 * np.abs(mu).sum() / B / ys)
+        np.testing.assert_allclose(unc_f.cpu().numpy(), SO.uncertainty(mu, s, L), rtol=2e-4)
