@@ -53,6 +53,20 @@ supa_status supa_gemm_bf16(void *hip_stream, int trans_a, int trans_b, int epilo
                            const float *bias, void *C, int ldc, uint16_t *pre);
 
 /*
+ * C = op(A) op(B) (float [M][N], ldc = N, no epilogue) with K split into
+ * `parts` ranges computed by separate workgroups (for products with few
+ * output tiles and a long K, such as weight gradients over a batch), then
+ * summed in order: deterministic.  scratch: caller-owned float workspace of
+ * parts * M * N entries (unused when parts == 1).  Layouts as in
+ * supa_gemm_bf16 (NN, NT, TN).  supa_gemm_splitk_parts gives a part count
+ * that fills the device (about 1024 workgroups).
+ */
+supa_status supa_gemm_bf16_splitk(void *hip_stream, int trans_a, int trans_b, int M, int N, int K,
+                                  const uint16_t *A, int lda, const uint16_t *B, int ldb, float *C, int parts,
+                                  float *scratch);
+int32_t supa_gemm_splitk_parts(int M, int N, int K);
+
+/*
  * Gaussian NLL of targets y[b][j] = img[b][j] * y_scale / e0[b] under
  * out[b] = [mu | s_raw] (float [B][2D]), s = clamp(s_raw, -s_clamp, s_clamp):
  * adds sum over b, j of 1/2 (s + (y - mu)^2 exp(-s)) to *loss (float, device)
@@ -66,8 +80,17 @@ supa_status supa_nll_grad(void *hip_stream, int B, int D, const float *out, cons
                           const float *e0, float y_scale, float s_clamp, int32_t mse_mean,
                           uint16_t *dout, float *loss);
 
-/* out[n] = sum over m < M of X[m][n] for n < N (X bf16 [M][ld]). */
-supa_status supa_colsum_bf16(void *hip_stream, int M, int N, const uint16_t *X, int ld, float *out);
+/*
+ * out[n] = sum over m < M of X[m][n] for n < N (X bf16 [M][ld]).  scratch:
+ * caller-owned float workspace of supa_colsum_scratch_floats(M, N) entries
+ * (row slices are summed in parallel, then per column in slice order:
+ * deterministic); NULL sums each column in one thread (slow, no workspace).
+ */
+supa_status supa_colsum_bf16(void *hip_stream, int M, int N, const uint16_t *X, int ld, float *out,
+                             float *scratch);
+
+/* Workspace entries (float) supa_colsum_bf16 needs for M x N; 0 for empty sizes. */
+int64_t supa_colsum_scratch_floats(int M, int N);
 
 /* Adam (Kingma & Ba, 2015) step `step` (>= 1) on n float32 parameters p with
  * gradients g and moments m, v; p_bf16 (may be NULL) receives bf16(p). */

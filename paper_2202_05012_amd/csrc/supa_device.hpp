@@ -189,6 +189,8 @@ struct GemmArgs {
     void *C;             // float [M][ldc] (EPI_F32, EPI_BIAS_F32) or bf16 [M][ldc]
     int ldc;
     uint16_t *pre;       // EPI_BIAS_GELU: pre-activation out; EPI_GELU_GRAD: in (bf16 [M][ldc])
+    int k_chunk;         // > 0: block z covers K range [z k_chunk, (z+1) k_chunk) and writes
+                         //   its partial product at C + z M ldc (EPI_F32); 0: all of K
     int split;           // EPI_GATE: columns from split on are log-variances
     float s_clamp;       // EPI_GATE: log-variance clamp
 };

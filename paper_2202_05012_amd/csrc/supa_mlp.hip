@@ -110,7 +110,9 @@ __global__ void __launch_bounds__(256) gemm_bf16(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = floatx4_t{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = 0; k0 < g.K; k0 += GK) {
+    const int kb = g.k_chunk > 0 ? blockIdx.z * g.k_chunk : 0;
+    const int ke = g.k_chunk > 0 ? min(g.K, kb + g.k_chunk) : g.K;
+    for (int k0 = kb; k0 < ke; k0 += GK) {
         load_tiles<TA, TB>(g, m0, n0, k0, As, Bs);
         __syncthreads();
         bf16x8_t a[4], b[4];
@@ -182,7 +184,7 @@ __global__ void __launch_bounds__(256) gemm_bf16(GemmArgs g) {
                 const int64_t o = (int64_t)m * g.ldc + n;
                 float v = acc[i][j][r];
                 if (EPI == EPI_F32) {
-                    ((float *)g.C)[o] = v;
+                    ((float *)g.C)[o + (int64_t)blockIdx.z * g.M * g.ldc] = v;
                 } else if (EPI == EPI_BIAS_F32) {
                     ((float *)g.C)[o] = v + g.bias[n];
                 } else if (EPI == EPI_BIAS_GELU) {
@@ -195,8 +197,23 @@ __global__ void __launch_bounds__(256) gemm_bf16(GemmArgs g) {
             }
 }
 
+// out[i] = sum over z < parts of part[z][i], in order (split-K reduction)
+__global__ void sum_parts_kernel(int64_t n, int parts, const float *part, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int z = 0; z < parts; ++z) s += part[(int64_t)z * n + i];
+    out[i] = s;
+}
+
+hipError_t launch_sum_parts(int64_t n, int parts, const float *part, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, parts, part, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs &g, hipStream_t s) {
-    const dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT), block(256);
+    const int parts = g.k_chunk > 0 ? (g.K + g.k_chunk - 1) / g.k_chunk : 1;
+    const dim3 grid((g.N + GT - 1) / GT, (g.M + GT - 1) / GT, parts), block(256);
 #define SUPA_GEMM_CASE(TA, TB, EPI)                                              \
     if (ta == TA && tb == TB && epi == EPI) {                                     \
         hipLaunchKernelGGL((gemm_bf16<TA, TB, EPI>), grid, block, 0, s, g);     \
@@ -252,6 +269,32 @@ __global__ void colsum_kernel(int M, int N, const uint16_t *X, int ld, float *ou
     if (n >= N) return;
     float s = 0.0f;
     for (int m = 0; m < M; ++m) s += bf2f(X[(int64_t)m * ld + n]);
+    out[n] = s;
+}
+
+// Column sums in two deterministic passes: block (column tile of 64, slice
+// of CS_ROWS rows) -> part[slice][n] (four waves take interleaved rows, lane
+// = column, then the four partial sums meet in LDS); then per column the
+// slices in order.
+constexpr int CS_ROWS = 256;
+__global__ void __launch_bounds__(256) colsum_part_kernel(int M, int N, const uint16_t *X, int ld, float *part) {
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + lane;
+    const int m0 = blockIdx.y * CS_ROWS, m1 = min(M, m0 + CS_ROWS);
+    float s = 0.0f;
+    if (n < N)
+        for (int m = m0 + w; m < m1; m += 4) s += bf2f(X[(int64_t)m * ld + n]);
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && n < N) part[(int64_t)blockIdx.y * N + n] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+}
+
+__global__ void colsum_final_kernel(int slices, int N, const float *part, float *out) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.0f;
+    for (int q = 0; q < slices; ++q) s += part[(int64_t)q * N + n];
     out[n] = s;
 }
 
@@ -455,8 +498,16 @@ hipError_t launch_nll(int B, int D, const float *out, const float *img, const fl
     return hipGetLastError();
 }
 
-hipError_t launch_colsum(int M, int N, const uint16_t *X, int ld, float *out, hipStream_t s) {
-    hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, s, M, N, X, ld, out);
+int64_t colsum_scratch_floats(int M, int N) { return (int64_t)((M + CS_ROWS - 1) / CS_ROWS) * N; }
+
+hipError_t launch_colsum(int M, int N, const uint16_t *X, int ld, float *out, float *scratch, hipStream_t s) {
+    if (!scratch) {
+        hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, s, M, N, X, ld, out);
+        return hipGetLastError();
+    }
+    const int slices = (M + CS_ROWS - 1) / CS_ROWS;
+    hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, slices), dim3(256), 0, s, M, N, X, ld, scratch);
+    hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 255) / 256), dim3(256), 0, s, slices, N, scratch, out);
     return hipGetLastError();
 }
 

@@ -2,6 +2,7 @@
 // checks on the host, then the kernels of supa_mlp.hip on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 
@@ -13,7 +14,9 @@ hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs &g, hipStream_t s
 hipError_t launch_nll(int B, int D, const float *out, const float *img, const float *e0,
                       float y_scale, float s_clamp, int mse_mean, uint16_t *dout, float *loss,
                       hipStream_t s);
-hipError_t launch_colsum(int M, int N, const uint16_t *X, int ld, float *out, hipStream_t s);
+hipError_t launch_colsum(int M, int N, const uint16_t *X, int ld, float *out, float *scratch, hipStream_t s);
+int64_t colsum_scratch_floats(int M, int N);
+hipError_t launch_sum_parts(int64_t n, int parts, const float *part, float *out, hipStream_t s);
 hipError_t launch_adam(int64_t n, float *p, const float *g, float *m, float *v, uint16_t *pb,
                        float lr, float b1, float b2, float eps, int step, hipStream_t s);
 hipError_t launch_to_bf16(int64_t n, const float *x, uint16_t *y, hipStream_t s);
@@ -71,6 +74,44 @@ extern "C" supa_status supa_gemm_bf16(void *stream, int trans_a, int trans_b, in
     return dev(supa::launch_gemm(trans_a, trans_b, epilogue, g, (hipStream_t)stream), "gemm");
 }
 
+extern "C" int32_t supa_gemm_splitk_parts(int M, int N, int K) {
+    if (M < 1 || N < 1 || K < 1) return 1;
+    // about 1024 workgroups in all, each with at least 8 K steps of 32
+    const int64_t tiles = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
+    const int64_t want = (1024 + tiles - 1) / tiles;
+    const int64_t most = std::max<int64_t>(1, K / 256);
+    return (int32_t)std::max<int64_t>(1, std::min(want, most));
+}
+
+extern "C" supa_status supa_gemm_bf16_splitk(void *stream, int trans_a, int trans_b, int M, int N, int K,
+                                             const uint16_t *A, int lda, const uint16_t *B, int ldb, float *C,
+                                             int parts, float *scratch) {
+    if (M < 1 || N < 1 || K < 1 || (M | N | K) % 8 != 0) return bad("M, N, K must be positive multiples of 8");
+    if (lda % 8 || ldb % 8 || lda < 1 || ldb < 1) return bad("bad leading dimensions");
+    if (lda < (trans_a ? M : K) || ldb < (trans_b ? K : N)) return bad("leading dimension too small");
+    if (!A || !B || !C) return bad("NULL matrix");
+    if (parts < 1 || parts > 256 || (parts > 1 && !scratch)) return bad("parts in [1, 256]; scratch needed for > 1");
+    const bool ok = (trans_a == 0 && trans_b == 0) || (trans_a == 0 && trans_b == 1) || (trans_a == 1 && trans_b == 0);
+    if (!ok) return bad("unsupported layout");
+    // K range per part: a multiple of the 32-wide K step
+    const int chunk = ((K + parts - 1) / parts + 31) / 32 * 32;
+    const int used = (K + chunk - 1) / chunk;
+    supa::GemmArgs g{};
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.A = A;
+    g.B = B;
+    g.lda = lda;
+    g.ldb = ldb;
+    g.C = used > 1 ? (void *)scratch : (void *)C;
+    g.ldc = N;
+    g.k_chunk = used > 1 ? chunk : 0;
+    supa_status st = dev(supa::launch_gemm(trans_a, trans_b, SUPA_EPI_F32, g, (hipStream_t)stream), "gemm");
+    if (st != SUPA_OK || used == 1) return st;
+    return dev(supa::launch_sum_parts((int64_t)M * N, used, scratch, C, (hipStream_t)stream), "gemm parts");
+}
+
 extern "C" supa_status supa_nll_grad(void *stream, int B, int D, const float *out, const float *img,
                                      const float *e0, float y_scale, float s_clamp, int32_t mse_mean,
                                      uint16_t *dout,
@@ -83,9 +124,14 @@ extern "C" supa_status supa_nll_grad(void *stream, int B, int D, const float *ou
                                 (hipStream_t)stream), "nll");
 }
 
-extern "C" supa_status supa_colsum_bf16(void *stream, int M, int N, const uint16_t *X, int ld, float *out) {
+extern "C" supa_status supa_colsum_bf16(void *stream, int M, int N, const uint16_t *X, int ld, float *out,
+                                        float *scratch) {
     if (M < 1 || N < 1 || ld < N || !X || !out) return bad("bad colsum arguments");
-    return dev(supa::launch_colsum(M, N, X, ld, out, (hipStream_t)stream), "colsum");
+    return dev(supa::launch_colsum(M, N, X, ld, out, scratch, (hipStream_t)stream), "colsum");
+}
+
+extern "C" int64_t supa_colsum_scratch_floats(int M, int N) {
+    return (M < 1 || N < 1) ? 0 : supa::colsum_scratch_floats(M, N);
 }
 
 extern "C" supa_status supa_adam(void *stream, int64_t n, float *p, const float *g, float *m, float *v,

@@ -35,7 +35,7 @@ def _lib():
         sig = {
             "supa_gemm_bf16": [vp, i, i, i, i, i, i, vp, i, vp, i, vp, vp, i, vp],
             "supa_nll_grad": [vp, i, i, vp, vp, vp, f, f, i, vp, vp],
-            "supa_colsum_bf16": [vp, i, i, vp, i, vp],
+            "supa_colsum_bf16": [vp, i, i, vp, i, vp, vp],
             "supa_adam": [vp, i64, vp, vp, vp, vp, vp, f, f, f, f, i],
             "supa_to_bf16": [vp, i64, vp, vp],
             "supa_surrogate_features": [vp, i, i, i, vp, vp, vp, f, f, f, u32, u32, u64, vp],
@@ -47,6 +47,8 @@ def _lib():
             "supa_surrogate_gate_fused": [vp, i, i, i, i, vp, i, vp, i, vp, vp, f, f, vp, vp, vp, f, u32,
                                           u64],
             "supa_transpose_to_bf16": [vp, i, i, vp, vp],
+            "supa_gemm_bf16_splitk": [vp, i, i, i, i, i, vp, i, vp, i, vp, i, vp],
+            "supa_gemm_splitk_parts": [i, i, i],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -81,6 +83,19 @@ def gemm(A, B, C_out, trans_a=0, trans_b=0, epilogue=0, bias=None, pre=None, M=N
     N = N if N is not None else (B.shape[0] if trans_b else B.shape[1])
     _check(_lib().supa_gemm_bf16(_stream(), trans_a, trans_b, epilogue, M, N, K, _p(A), A.stride(0),
                                  _p(B), B.stride(0), _p(bias), _p(C_out), C_out.stride(0), _p(pre)))
+
+
+def gemm_splitk(A, B, C_out, trans_a=0, trans_b=0):
+    """C = op(A) op(B) (float32 C, contiguous) with K split over workgroups."""
+    M = A.shape[1] if trans_a else A.shape[0]
+    K = A.shape[0] if trans_a else A.shape[1]
+    N = B.shape[0] if trans_b else B.shape[1]
+    L = _lib()
+    L.supa_gemm_splitk_parts.restype = C.c_int32
+    parts = int(L.supa_gemm_splitk_parts(M, N, K))
+    scratch = torch.empty(parts * M * N if parts > 1 else 1, dtype=torch.float32, device=C_out.device)
+    _check(L.supa_gemm_bf16_splitk(_stream(), trans_a, trans_b, M, N, K, _p(A), A.stride(0), _p(B),
+                                   B.stride(0), _p(C_out), parts, _p(scratch)))
 
 
 def to_bf16(x: torch.Tensor) -> torch.Tensor:
@@ -177,6 +192,13 @@ def group_sums(x, n_groups):
 # ---------------------------------------------------------------------------
 # the MLP
 # ---------------------------------------------------------------------------
+def _colsum_scratch(M, N, device):
+    L = _lib()
+    L.supa_colsum_scratch_floats.restype = C.c_int64
+    L.supa_colsum_scratch_floats.argtypes = [C.c_int, C.c_int]
+    return torch.empty(max(1, L.supa_colsum_scratch_floats(M, N)), dtype=torch.float32, device=device)
+
+
 class MLP:
     """bf16 weights with float32 master copies and Adam moments, on device."""
 
@@ -261,9 +283,10 @@ class MLP:
         for l in range(nl - 1, -1, -1):
             din, dout_l = self.dims[l], self.dims[l + 1]
             dW = torch.empty((din, dout_l), dtype=torch.float32, device=self.device)
-            gemm(acts[l], g, dW, trans_a=1, trans_b=0, epilogue=0)          # h^T g
+            gemm_splitk(acts[l], g, dW, trans_a=1, trans_b=0)              # h^T g
             db = torch.empty(dout_l, dtype=torch.float32, device=self.device)
-            _check(_lib().supa_colsum_bf16(_stream(), B, dout_l, _p(g), g.stride(0), _p(db)))
+            _check(_lib().supa_colsum_bf16(_stream(), B, dout_l, _p(g), g.stride(0), _p(db),
+                                           _p(_colsum_scratch(B, dout_l, self.device))))
             dWs[l], dbs[l] = dW, db
             if l > 0:
                 gn = torch.empty((B, din), dtype=torch.int16, device=self.device)

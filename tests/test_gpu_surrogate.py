@@ -234,3 +234,40 @@ def test_gate_fused_matches_gate_and_oracle(rho):
         np.testing.assert_allclose(le_f.cpu().numpy(), SO.layer_sums(mu, L) * e0[:, None] / ys,
                                    rtol=2e-4, atol=2e-4 * np.abs(mu).sum() / B / ys)
         np.testing.assert_allclose(unc_f.cpu().numpy(), SO.uncertainty(mu, s, L), rtol=2e-4)
+
+
+@pytest.mark.parametrize("ta,tb", [(1, 0), (0, 0), (0, 1)])
+def test_gemm_splitk_matches_numpy(ta, tb):
+    """K split over workgroups, partial products summed in order: same bar
+    as the single-pass product (float32 accumulation of bf16 inputs)."""
+    rng = np.random.default_rng(40 + 2 * ta + tb)
+    M, N, K = 136, 264, 1000                # ragged tiles; K not a multiple of the parts
+    A = bf16_round(rng.normal(size=(M, K)))
+    B = bf16_round(rng.normal(size=(K, N)))
+    Af, Bf = bf16_to_np(A).astype(np.float64), bf16_to_np(B).astype(np.float64)
+    At = dev16(np.ascontiguousarray(A.T)) if ta else dev16(A)
+    Bt = dev16(np.ascontiguousarray(B.T)) if tb else dev16(B)
+    C = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    S.gemm_splitk(At, Bt, C, ta, tb)
+    ref, scale = Af @ Bf, np.abs(Af) @ np.abs(Bf)
+    assert (np.abs(C.cpu().numpy() - ref) <= 2e-6 * scale + 1e-6).all()
+    C2 = torch.empty_like(C)
+    S.gemm_splitk(At, Bt, C2, ta, tb)
+    assert torch.equal(C, C2)                # deterministic
+
+
+def test_colsum_two_pass_and_single_pass():
+    rng = np.random.default_rng(41)
+    M, N = 1000, 300                        # ragged against 256-row slices and 64-column tiles
+    X = bf16_round(rng.normal(size=(M, N)))
+    ref = bf16_to_np(X).astype(np.float64).sum(axis=0)
+    tX = dev16(X)
+    L = S._lib()
+    outs = []
+    for scratch in (S._colsum_scratch(M, N, "cuda"), None):
+        out = torch.empty(N, dtype=torch.float32, device="cuda")
+        S._check(L.supa_colsum_bf16(S._stream(), M, N, S._p(tX), N, S._p(out), S._p(scratch)))
+        outs.append(out.cpu().numpy())
+    bound = 2e-6 * np.abs(bf16_to_np(X)).astype(np.float64).sum(axis=0) + 1e-6
+    for o in outs:
+        assert (np.abs(o - ref) <= bound).all()
