@@ -23,6 +23,7 @@ import hashlib
 import os
 import re
 import statistics
+import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -165,7 +166,52 @@ def traffic_if_current(profiles_dir: str, kernel: str, workload: str):
         return None
 
 
+# SIMDs of the device (256 compute units x 4) and cycles one wave64 VALU
+# instruction holds its 16-lane SIMD
+N_SIMD = 1024
+VALU_CYCLES = 4
+
+
+def summarize_counters(pmc_dir, kernel, workload, commands, out_dir, skip=2):
+    """Per-dispatch averages of the SQ/GRBM counters of one kernel, and its
+    VALU issue fraction: SQ_INSTS_VALU * 4 cycles / (1024 SIMDs *
+    GRBM_GUI_ACTIVE cycles of the dispatch)."""
+    vals = {}
+    for r in _rows(pmc_dir, "counter_collection.csv"):
+        if short_name(r["Kernel_Name"]) != kernel:
+            continue
+        vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    avg = {k: steady(v, skip) for k, v in sorted(vals.items())}
+    lines = [f"# {kernel} -- instruction counters -- {workload}", "",
+             "Command (run from the repository root; `cd /tmp && export TMPDIR=/tmp` first):", "",
+             *[f"    {c}" for c in commands], "",
+             f"source_sha256: {source_hash(kernel)}",
+             f"dispatches: {len(next(iter(vals.values()), []))} (first {skip} skipped)", ""]
+    lines += [f"{k}: {v:.0f}" for k, v in avg.items()]
+    if "SQ_INSTS_VALU" in avg and avg.get("GRBM_GUI_ACTIVE"):
+        frac = avg["SQ_INSTS_VALU"] * VALU_CYCLES / (N_SIMD * avg["GRBM_GUI_ACTIVE"])
+        lines += ["", f"valu_issue_fraction: {frac:.3f} (SQ_INSTS_VALU * {VALU_CYCLES} / ({N_SIMD} SIMDs * "
+                  "GRBM_GUI_ACTIVE))"]
+    path = os.path.join(out_dir, f"{kernel}_counters_{workload}.md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return path
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "counters":
+        ap = argparse.ArgumentParser()
+        ap.add_argument("mode")
+        ap.add_argument("pmc_dir")
+        ap.add_argument("--kernel", required=True)
+        ap.add_argument("--workload", required=True)
+        ap.add_argument("--command", action="append", default=[])
+        ap.add_argument("--out", required=True)
+        ap.add_argument("--skip", type=int, default=2)
+        a = ap.parse_args()
+        os.makedirs(a.out, exist_ok=True)
+        print(summarize_counters(a.pmc_dir, a.kernel, a.workload, a.command, a.out, a.skip))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("trace_dir")
     ap.add_argument("fetch_dir")

@@ -278,6 +278,49 @@ def test_full_size_100k_sampled_parity():
         parity.check_all(gpu, ref, geom, images=True, tree=True)
 
 
+@pytest.mark.slow
+def test_full_size_1m_sampled_parity():
+    """The 1,000,000-shower, 20-plane workload with E0 log-uniform on
+    [1, 1000] (particle counts over three decades) at full size, hit clouds
+    as the benchmark runs it; invariants over every shower, the oracle on
+    sampled blocks (the first, the last, and three at random)."""
+    w = workloads.WORKLOADS["loge1to1000_20planes_1m"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w)
+    sim = supa.Simulator(geom, supa.OUT_HITS | supa.OUT_KEYS)
+    out = sim.simulate(dev_t(e0), dev_t(pol), dev_t(az), w.seed)
+    torch.cuda.synchronize()
+    counts = out["counts"].cpu().numpy()
+    ledger = out["ledger"].cpu().numpy().astype(np.uint64)
+    assert (ledger[:, 1] + ledger[:, 2] + ledger[:, 3] == ledger[:, 0]).all()
+    assert (counts[:, 0] == 1 + 2 * counts[:, 3]).all()
+    assert out["total_hits"] == counts[:, 1].sum()
+    offs = out["hit_offsets"].cpu().numpy()
+    assert offs[0] == 0 and (offs[1:] == (offs + counts[:, 1])[:-1]).all()
+    rng = np.random.default_rng(1)
+    for start in [0, w.n - 64] + list(rng.integers(0, w.n - 64, 3)):
+        rows = np.arange(start, start + 64)
+        gpu = sampled_segments(out, rows)
+        ref = O.simulate(geom, e0[rows], pol[rows], az[rows], w.seed, shower_id_base=int(start))
+        parity.check_all(gpu, ref, geom)
+
+
+def test_maximum_sizes():
+    """Limits of the interface in one call: 63 planes (the most), an initial
+    energy just below the top of the fixed-point range, images 1024 cells
+    wide (the widest) in bucketed slabs, and showers from zero energy up."""
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = workloads.geometry(w, n_planes=63, e_cut=1.0, img_nx=1024, img_ny=8, img_x0=-5.0, img_x1=5.0,
+                              img_y0=-5.0, img_y1=5.0)
+    top = (2.0 ** 32 - 4096.0) / 2.0 ** geom["frac_bits"]
+    e0 = np.array([top, 1000.0, 0.0, 0.5, 1.0, 300.0, 2.0, top], dtype=np.float32)
+    assert float(e0[0]) * 2.0 ** geom["frac_bits"] < 2.0 ** 32
+    pol = np.array([0.0, 0.1, 0.2, 0.0, 0.05, 0.25, 0.1, 0.02])
+    az = np.linspace(0.0, 6.0, 8)
+    gpu, ref = check(geom, ALL, e0, pol, az, seed=11)
+    assert ref["counts"][0, 1] > 1000
+
+
 def test_autotune_keeps_results():
     """The launch-setting search leaves one setting of its grid in the
     context, and the outputs (from the winning setting) match the oracle."""
