@@ -271,7 +271,10 @@ def main():
                  "unit": "T lane-ops/s", "frac": round(alu / PEAK_ALU_TOPS, 4),
                  "traffic": prof_summary.traffic_if_current(prof_dir, "supa_propagate", w.name),
                  "kernel": "supa_propagate", "kernel_ms": round(k_prop, 4),
-                 "alg_lane_ops": alg_ops}
+                 "alg_lane_ops": alg_ops,
+                 # measured VALU instruction issue (rocprofv3 counters, committed summary)
+                 "valu_issue_frac": prof_summary.counter_if_current(prof_dir, "supa_propagate", w.name,
+                                                                    "valu_issue_fraction")}
     # placement kernel: algorithmic bytes = the outputs it writes (HBM roofline)
     roof = roof_prop
     roof_other = None

@@ -23,6 +23,7 @@
 #include <stdint.h>
 
 #include "supa_device.hpp"
+#include "supa_mlp.hpp"
 
 namespace supa {
 

@@ -8,6 +8,7 @@
 
 #include "../../include/supa_surrogate.h"
 #include "supa_device.hpp"
+#include "supa_mlp.hpp"
 
 namespace supa {
 hipError_t launch_gemm(int ta, int tb, int epi, const GemmArgs &g, hipStream_t s);

@@ -166,16 +166,18 @@ def traffic_if_current(profiles_dir: str, kernel: str, workload: str):
         return None
 
 
-# SIMDs of the device (256 compute units x 4) and cycles one wave64 VALU
-# instruction holds its 16-lane SIMD
+# SIMDs of the device (256 compute units x 4), cycles one wave64 VALU
+# instruction holds its 16-lane SIMD, and accelerator dies (GRBM_GUI_ACTIVE
+# is summed over the 8 XCDs: it reads about 8x the kernel's clock cycles)
 N_SIMD = 1024
 VALU_CYCLES = 4
+N_XCD = 8
 
 
 def summarize_counters(pmc_dir, kernel, workload, commands, out_dir, skip=2):
     """Per-dispatch averages of the SQ/GRBM counters of one kernel, and its
-    VALU issue fraction: SQ_INSTS_VALU * 4 cycles / (1024 SIMDs *
-    GRBM_GUI_ACTIVE cycles of the dispatch)."""
+    VALU issue fraction: SQ_INSTS_VALU * 4 cycles / (1024 SIMDs * cycles of
+    the dispatch), the cycles being GRBM_GUI_ACTIVE / 8 (one GRBM per XCD)."""
     vals = {}
     for r in _rows(pmc_dir, "counter_collection.csv"):
         if short_name(r["Kernel_Name"]) != kernel:
@@ -189,13 +191,33 @@ def summarize_counters(pmc_dir, kernel, workload, commands, out_dir, skip=2):
              f"dispatches: {len(next(iter(vals.values()), []))} (first {skip} skipped)", ""]
     lines += [f"{k}: {v:.0f}" for k, v in avg.items()]
     if "SQ_INSTS_VALU" in avg and avg.get("GRBM_GUI_ACTIVE"):
-        frac = avg["SQ_INSTS_VALU"] * VALU_CYCLES / (N_SIMD * avg["GRBM_GUI_ACTIVE"])
-        lines += ["", f"valu_issue_fraction: {frac:.3f} (SQ_INSTS_VALU * {VALU_CYCLES} / ({N_SIMD} SIMDs * "
-                  "GRBM_GUI_ACTIVE))"]
+        cycles = avg["GRBM_GUI_ACTIVE"] / N_XCD
+        frac = avg["SQ_INSTS_VALU"] * VALU_CYCLES / (N_SIMD * cycles)
+        lines += ["", f"kernel_cycles: {cycles:.0f} (GRBM_GUI_ACTIVE / {N_XCD} XCDs)",
+                  f"valu_issue_fraction: {frac:.3f} (SQ_INSTS_VALU * {VALU_CYCLES} / ({N_SIMD} SIMDs * kernel_cycles))"]
+        if "SQ_ACTIVE_INST_VALU" in avg:
+            busy = avg["SQ_ACTIVE_INST_VALU"] * VALU_CYCLES / (N_SIMD * cycles)
+            lines += [f"valu_busy_fraction: {busy:.3f} (SQ_ACTIVE_INST_VALU * {VALU_CYCLES} / ({N_SIMD} SIMDs * "
+                      "kernel_cycles))"]
     path = os.path.join(out_dir, f"{kernel}_counters_{workload}.md")
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     return path
+
+
+def counter_if_current(profiles_dir: str, kernel: str, workload: str, key: str):
+    """A value of the kernel's counter summary, or None when there is none or
+    the kernel's sources changed since it was taken."""
+    path = os.path.join(profiles_dir, f"{kernel}_counters_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    d = read_summary(path)
+    if d.get("source_sha256") != source_hash(kernel):
+        return None
+    try:
+        return float(d[key])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
