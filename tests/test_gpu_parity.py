@@ -321,6 +321,21 @@ def test_maximum_sizes():
     assert ref["counts"][0, 1] > 1000
 
 
+def test_huge_shower_takes_the_unbucketed_paths():
+    """A shower of 400,000 hits among 256x256 images of 50 layers: more hits
+    than a workgroup's slab bucket holds, so its images come from the
+    per-slab pass over every record window, and its hit cloud from the
+    scattered (unstaged) placement; a small shower beside it takes the
+    bucketed path in the same launch."""
+    w = workloads.WORKLOADS["loge10to1000_50planes_tree_img256_1m"]
+    geom = workloads.geometry(w, e_cut=0.01)
+    e0 = np.array([2000.0, 30.0], dtype=np.float32)
+    pol = np.array([0.05, 0.1])
+    az = np.array([1.0, 2.0])
+    gpu, ref = check(geom, ALL, e0, pol, az, seed=5)
+    assert ref["counts"][0, 1] > 65536 > ref["counts"][1, 1]
+
+
 def test_autotune_keeps_results():
     """The launch-setting search leaves one setting of its grid in the
     context, and the outputs (from the winning setting) match the oracle."""
