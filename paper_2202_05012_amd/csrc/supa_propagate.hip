@@ -210,8 +210,10 @@ struct SlotSums {
     }
 };
 
-template <bool TREE, int PC>
-__global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
+// TREE: node records; KEYS: path ids with hit and node records (compile-time,
+// so that neither flag occupies a scalar register through the loop)
+template <bool TREE, bool KEYS, int PC>
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) supa_propagate(Params P) {
     extern __shared__ uint32_t lds[];
     const uint32_t lane = lane_id();
     const int64_t wave = blockIdx.x;
@@ -228,7 +230,7 @@ __global__ void __launch_bounds__(WAVE) supa_propagate(Params P) {
 
     const int64_t G = P.spill_cap;
     uint32_t *const spill = P.spill + wave * POOL_FIELDS * G;
-    const bool keys = P.keys;
+    constexpr bool keys = KEYS;
     const bool recs = (P.outputs & 3u) != 0;        // hit records (clouds or images)
 
     Slots S;
@@ -733,13 +735,13 @@ size_t propagate_lds_bytes(int pool_cap) {
     return (size_t)lds_words(pool_cap) * 4;
 }
 
-template <bool TREE>
+template <bool TREE, bool KEYS>
 static hipError_t launch_pc(const Params &P, int blocks, size_t lds, hipStream_t s) {
     switch (P.pool_cap) {
-    case 128: hipLaunchKernelGGL((supa_propagate<TREE, 128>), dim3(blocks), dim3(WAVE), lds, s, P); break;
-    case 256: hipLaunchKernelGGL((supa_propagate<TREE, 256>), dim3(blocks), dim3(WAVE), lds, s, P); break;
-    case 512: hipLaunchKernelGGL((supa_propagate<TREE, 512>), dim3(blocks), dim3(WAVE), lds, s, P); break;
-    case 1024: hipLaunchKernelGGL((supa_propagate<TREE, 1024>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 128: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 128>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 256: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 256>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 512: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 512>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 1024: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 1024>), dim3(blocks), dim3(WAVE), lds, s, P); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -747,7 +749,10 @@ static hipError_t launch_pc(const Params &P, int blocks, size_t lds, hipStream_t
 
 hipError_t launch_propagate(const Params &P, int blocks, hipStream_t s) {
     const size_t lds = propagate_lds_bytes(P.pool_cap);
-    return (P.outputs & 4u) ? launch_pc<true>(P, blocks, lds, s) : launch_pc<false>(P, blocks, lds, s);
+    const bool tree = (P.outputs & 4u) != 0;
+    if (tree)
+        return P.keys ? launch_pc<true, true>(P, blocks, lds, s) : launch_pc<true, false>(P, blocks, lds, s);
+    return P.keys ? launch_pc<false, true>(P, blocks, lds, s) : launch_pc<false, false>(P, blocks, lds, s);
 }
 
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
