@@ -28,8 +28,20 @@
 namespace supa {
 
 constexpr int WAVE = 64;
-// Read a field of the per-call Cold block at its point of use.
-#define COLD(field) (((const volatile Cold *)P.cold)->field)
+// global-memory (address space 1) element types
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) u32x4 gu4;
+typedef __attribute__((address_space(1))) u32x2 gu2;
+// Read a field of the per-call Cold block at its point of use, as a global
+// memory pointer (a plain pointer read from memory would be accessed with flat
+// instructions, which also count against the LDS wait counter).
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+#define COLD(field) as_global(((const volatile __attribute__((address_space(1))) Cold *)P.cold)->field)
 
 struct Daughters {
     float txa, tya, txb, tyb;
@@ -43,9 +55,9 @@ struct Daughters {
 // turn by theta*(1-f) and theta*f to opposite sides of the plane through the
 // parent direction at azimuth omega (frame: rotation taking +z to d).
 __device__ __forceinline__ Daughters split_particle(const Params &P, float tx, float ty,
-                                                    uint32_t e, uint4 w) {
+                                                    uint32_t e, uint4 w, uint32_t f_lo, uint64_t f_w) {
     Daughters D;
-    const uint32_t F = P.f_lo + (uint32_t)(((uint64_t)w.y * P.f_w) >> 32);
+    const uint32_t F = f_lo + (uint32_t)(((uint64_t)w.y * f_w) >> 32);
     D.ea = (uint32_t)(((uint64_t)e * F) >> 32);
     D.eb = e - D.ea;
     const float f = (float)F * 0x1p-32f;     // fraction carried by daughter a
@@ -229,6 +241,15 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
     }
 
     const int64_t G = P.spill_cap;
+    // Values the step reads but that are uniform, kept in vector registers:
+    // the scalar file is full, and from a spilled scalar each use costs a
+    // v_readlane on the step's path.
+    uint32_t f_lo = P.f_lo, fw_lo = (uint32_t)P.f_w, fw_hi = (uint32_t)(P.f_w >> 32);
+    uint32_t hl_lo = (uint32_t)(uintptr_t)P.hlog, hl_hi = (uint32_t)((uintptr_t)P.hlog >> 32);
+    asm volatile("" : "+v"(f_lo), "+v"(fw_lo), "+v"(fw_hi), "+v"(hl_lo), "+v"(hl_hi));
+    const uint64_t f_w = ((uint64_t)fw_hi << 32) | fw_lo;
+    // (rebuilt as a global-memory pointer, so stores through it stay global)
+    gu32 *const hlog = (gu32 *)(((uint64_t)hl_hi << 32) | hl_lo);
     uint32_t *const spill = P.spill + wave * POOL_FIELDS * G;
     constexpr bool keys = KEYS;
     const bool recs = (P.outputs & 3u) != 0;        // hit records (clouds or images)
@@ -291,9 +312,9 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
         uint32_t e, k, lo, hi;
     };
     auto write_hit = [&](int c, int pos, const Hit &h) {
-        uint32_t *chunk = P.hlog + (int64_t)c * HIT_CHUNK_WORDS;
-        *(uint4 *)(chunk + HIT_REC_WORDS * pos) = make_uint4(__float_as_uint(h.x), __float_as_uint(h.y), h.e, h.k);
-        if (keys) *(uint2 *)(chunk + HIT_REC_WORDS * HIT_CHUNK + HIT_KEY_WORDS * pos) = make_uint2(h.lo, h.hi);
+        gu32 *chunk = hlog + (int64_t)c * HIT_CHUNK_WORDS;
+        *(gu4 *)(chunk + HIT_REC_WORDS * pos) = u32x4{__float_as_uint(h.x), __float_as_uint(h.y), h.e, h.k};
+        if (keys) *(gu2 *)(chunk + HIT_REC_WORDS * HIT_CHUNK + HIT_KEY_WORDS * pos) = u32x2{h.lo, h.hi};
     };
     // appends the hit records of slot s0 to the slot's chain: lanes of m1
     // have hit h1, lanes of m2 hit h2 (a lane of both: h1 first)
@@ -374,7 +395,7 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
                 if ((int)lane < b_left) {
                     // initial condition (section "Using SUPA": energy, angle, impact point)
                     const int item = (int)base + (int)lane;
-                    const int32_t *ord = COLD(order);
+                    const auto ord = COLD(order);
                     const int i = ord ? ord[item] : item;
                     const float sc = COLD(e0)[i] * P.e_scale;
                     const bool ok = sc >= 0.0f && sc < 4294967296.0f;
@@ -382,7 +403,7 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
                     sincosf(COLD(polar)[i], &sp, &cp);
                     sincosf(COLD(azimuth)[i], &sa, &ca);
                     const float tpol = sp / cp;
-                    const float *x0p = COLD(x0), *y0p = COLD(y0);
+                    const auto x0p = COLD(x0), y0p = COLD(y0);
                     w_i = i;
                     w_ok = ok ? 1 : 0;
                     w_e = ok ? (uint32_t)rintf(sc) : 0u;
@@ -497,7 +518,7 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             D.fwd_a = D.fwd_b = false;
             D.ea = D.eb = 0;
             D.txa = D.tya = D.txb = D.tyb = 0.f;
-            if (is_split) D = split_particle(P, p.tx, p.ty, p.e, w);
+            if (is_split) D = split_particle(P, p.tx, p.ty, p.e, w, f_lo, f_w);
             // outgoing particles: a = first daughter or the passer, b = second daughter
             const bool has_a = is_split || is_pass, has_b = is_split;
             const uint32_t ea = is_split ? D.ea : p.e, eb = D.eb;
