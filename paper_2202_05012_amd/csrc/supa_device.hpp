@@ -77,8 +77,9 @@ struct Cold {
 };
 
 // Hit records leave the propagation kernel through a log of chunks of
-// HIT_CHUNK records: per record one 16-byte word {x, y, integer energy,
-// plane}, and with keys the path id in a second array of the chunk.  Each
+// HIT_CHUNK records: per record 12 bytes {x, y, integer energy}, its plane in
+// a byte array of the chunk (the placement counts hits per plane from the
+// bytes alone), and with keys the path id in a third array.  Each
 // shower slot of a wave fills its own chain of chunks: when the slot's chunk
 // is full the next one is claimed with one atomic and linked from it, so the
 // records of one shower follow each other along the chain, starting at the
@@ -86,9 +87,11 @@ struct Cold {
 // placement kernel walks each shower's chain once.
 constexpr int HIT_CHUNK_LOG2 = 10;
 constexpr int HIT_CHUNK = 1 << HIT_CHUNK_LOG2;
-constexpr int HIT_REC_WORDS = 4;                  // x, y, e, k
+constexpr int HIT_REC_WORDS = 3;                  // x, y, e
 constexpr int HIT_KEY_WORDS = 2;                  // path id low, high
-constexpr int64_t HIT_CHUNK_WORDS = (int64_t)HIT_CHUNK * (HIT_REC_WORDS + HIT_KEY_WORDS);
+constexpr int HIT_PLANE_OFF = HIT_REC_WORDS * HIT_CHUNK;          // plane bytes (words from the chunk start)
+constexpr int HIT_KEY_OFF = HIT_PLANE_OFF + HIT_CHUNK / 4;        // path ids
+constexpr int64_t HIT_CHUNK_WORDS = HIT_KEY_OFF + (int64_t)HIT_KEY_WORDS * HIT_CHUNK;
 
 // Tree nodes go to a log of chunks of LOG_CHUNK records that a wave fills in
 // the order its phases produce them (a chunk is claimed with one atomic and

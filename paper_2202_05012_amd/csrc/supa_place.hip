@@ -122,13 +122,13 @@ __device__ __forceinline__ Window<KEYS> load_window(const PlaceParams &Q, const 
             if (c < 0 || c >= Q.h_chunks) continue;          // never outside the log
             const uint32_t *chunk = Q.hlog + (int64_t)c * HIT_CHUNK_WORDS;
             const int o = pos & (HIT_CHUNK - 1);
-            const uint4 r = *(const uint4 *)(chunk + HIT_REC_WORDS * o);
-            W.x[u] = __uint_as_float(r.x);
-            W.y[u] = __uint_as_float(r.y);
-            W.e[u] = r.z;
-            W.k[u] = (int)r.w;
+            const uint32_t *rec = chunk + HIT_REC_WORDS * o;
+            W.x[u] = __uint_as_float(rec[0]);
+            W.y[u] = __uint_as_float(rec[1]);
+            W.e[u] = rec[2];
+            W.k[u] = (int)((const uint8_t *)(chunk + HIT_PLANE_OFF))[o];
             if (KEYS) {
-                const uint2 kk = *(const uint2 *)(chunk + HIT_REC_WORDS * HIT_CHUNK + HIT_KEY_WORDS * o);
+                const uint2 kk = *(const uint2 *)(chunk + HIT_KEY_OFF + HIT_KEY_WORDS * o);
                 W.lo[KEYS ? u : 0] = kk.x;
                 W.hi[KEYS ? u : 0] = kk.y;
             }
@@ -142,6 +142,26 @@ __device__ __forceinline__ void count_planes(const Window<KEYS> &W, uint32_t *cn
 #pragma unroll
     for (int u = 0; u < PL_UNROLL; ++u)
         if (W.k[u] >= 0 && W.k[u] < N) atomicAdd(&cnt[W.k[u]], 1u);
+}
+
+// counts per plane of window w (after walk_to_window(w)) from the plane bytes
+// alone: one byte per record read instead of the whole record
+__device__ __forceinline__ void count_window_planes(const PlaceParams &Q, const Chain &ch, int w, int nh,
+                                                    uint32_t *cnt, int N) {
+    if (ch.bad) return;
+    const int lo = (ch.f0 + w * PL_WIN) >> HIT_CHUNK_LOG2;
+#pragma unroll
+    for (int u = 0; u < PL_UNROLL; ++u) {
+        const int j = w * PL_WIN + u * PL_THREADS + (int)threadIdx.x;
+        if (j < nh) {
+            const int pos = ch.f0 + j;
+            const int hop = (pos >> HIT_CHUNK_LOG2) - lo;
+            const int c = (hop >= 0 && hop < 3) ? ch.win[hop] : -1;
+            if (c < 0 || c >= Q.h_chunks) continue;          // never outside the log
+            const int k = ((const uint8_t *)(Q.hlog + (int64_t)c * HIT_CHUNK_WORDS + HIT_PLANE_OFF))[pos & (HIT_CHUNK - 1)];
+            if (k < N) atomicAdd(&cnt[k], 1u);
+        }
+    }
 }
 
 template <bool KEYS>
@@ -322,7 +342,7 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
                 count_planes(W0, cnt, N);
                 for (int w = 1; w < nwin; ++w) {
                     walk_to_window(Q, ch, w, nh);
-                    count_planes(load_window<false>(Q, ch, w, nh), cnt, N);
+                    count_window_planes(Q, ch, w, nh, cnt, N);
                 }
                 lds_barrier();
                 if (threadIdx.x < 64) {

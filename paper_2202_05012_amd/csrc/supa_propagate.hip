@@ -32,6 +32,7 @@ constexpr int WAVE = 64;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) uint8_t gu8;
 typedef __attribute__((address_space(1))) u32x4 gu4;
 typedef __attribute__((address_space(1))) u32x2 gu2;
 // Read a field of the per-call Cold block at its point of use, as a global
@@ -313,8 +314,12 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
     };
     auto write_hit = [&](int c, int pos, const Hit &h) {
         gu32 *chunk = hlog + (int64_t)c * HIT_CHUNK_WORDS;
-        *(gu4 *)(chunk + HIT_REC_WORDS * pos) = u32x4{__float_as_uint(h.x), __float_as_uint(h.y), h.e, h.k};
-        if (keys) *(gu2 *)(chunk + HIT_REC_WORDS * HIT_CHUNK + HIT_KEY_WORDS * pos) = u32x2{h.lo, h.hi};
+        gu32 *rec = chunk + HIT_REC_WORDS * pos;
+        rec[0] = __float_as_uint(h.x);
+        rec[1] = __float_as_uint(h.y);
+        rec[2] = h.e;
+        ((gu8 *)(chunk + HIT_PLANE_OFF))[pos] = (uint8_t)h.k;
+        if (keys) *(gu2 *)(chunk + HIT_KEY_OFF + HIT_KEY_WORDS * pos) = u32x2{h.lo, h.hi};
     };
     // appends the hit records of slot s0 to the slot's chain: lanes of m1
     // have hit h1, lanes of m2 hit h2 (a lane of both: h1 first)
