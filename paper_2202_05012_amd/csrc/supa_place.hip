@@ -31,6 +31,7 @@ constexpr int PL_SLAB_WORDS = 16384;                // image slab: 64 KB of LDS 
 constexpr int PL_STAGE_WORDS = 4 * PL_WIN;          // hit staging: 32 KB (hit clouds only)
 constexpr int PL_MAX_SLABS = 1024;                  // slabs per image bucketed in LDS counts
 constexpr int PL_BUCKET_MIN_SLABS = 9;              // fewer slabs: bin the cached hits per slab
+constexpr int PL_CLIST = 512;                       // chunk ids of a shower's chain listed in LDS
 static_assert(PL_WIN <= 2 * HIT_CHUNK, "a window spans at most three chunks");
 
 // Barrier for hand-offs through LDS only: waits for this wave's LDS
@@ -57,7 +58,29 @@ struct Chain {
     int cur_h, cur_c;            // last chunk reached (hop index, chunk id)
     int win[3];                  // chunks of the current window
     int bad;                     // a link pointed outside the log
+    int listed;                  // the whole chain is in the chunk list (no walks per window)
 };
+
+// Thread 0 walks a shower's whole chain once and lists its chunk ids in LDS
+// (when it has at most PL_CLIST chunks): every window then finds its chunks
+// there, with no walk and no barrier per window.
+__device__ __forceinline__ void list_chain(const PlaceParams &Q, Chain &ch, int *clist, int nh) {
+    ch.listed = 0;
+    if (ch.bad || nh <= 0) return;
+    const int nch = ((ch.f0 + nh - 1) >> HIT_CHUNK_LOG2) + 1;
+    if (nch > PL_CLIST) return;
+    int c = ch.c0;
+    clist[0] = c;
+    for (int h = 1; h < nch; ++h) {
+        c = (int)Q.hnext[c];
+        if (c < 0 || c >= Q.h_chunks) {
+            ch.bad = 1;
+            return;
+        }
+        clist[h] = c;
+    }
+    ch.listed = 1;
+}
 
 // Thread 0 follows the links up to the chunks of window w (records
 // [w*PL_WIN, min(nh, (w+1)*PL_WIN))); every thread then reads them from ch.
@@ -108,17 +131,19 @@ __device__ __forceinline__ Window<KEYS> empty_window() {
 // Records of window w held by this thread (after walk_to_window(w); nothing
 // when a link of the chain was bad).
 template <bool KEYS>
-__device__ __forceinline__ Window<KEYS> load_window(const PlaceParams &Q, const Chain &ch, int w, int nh) {
+__device__ __forceinline__ Window<KEYS> load_window(const PlaceParams &Q, const Chain &ch, const int *clist, int w,
+                                                   int nh) {
     Window<KEYS> W = empty_window<KEYS>();
     if (ch.bad) return W;
     const int lo = (ch.f0 + w * PL_WIN) >> HIT_CHUNK_LOG2;
+    const bool listed = ch.listed;
 #pragma unroll
     for (int u = 0; u < PL_UNROLL; ++u) {
         const int j = w * PL_WIN + u * PL_THREADS + (int)threadIdx.x;
         if (j < nh) {
             const int pos = ch.f0 + j;
             const int hop = (pos >> HIT_CHUNK_LOG2) - lo;
-            const int c = (hop >= 0 && hop < 3) ? ch.win[hop] : -1;
+            const int c = listed ? clist[pos >> HIT_CHUNK_LOG2] : (hop >= 0 && hop < 3) ? ch.win[hop] : -1;
             if (c < 0 || c >= Q.h_chunks) continue;          // never outside the log
             const uint32_t *chunk = Q.hlog + (int64_t)c * HIT_CHUNK_WORDS;
             const int o = pos & (HIT_CHUNK - 1);
@@ -146,17 +171,18 @@ __device__ __forceinline__ void count_planes(const Window<KEYS> &W, uint32_t *cn
 
 // counts per plane of window w (after walk_to_window(w)) from the plane bytes
 // alone: one byte per record read instead of the whole record
-__device__ __forceinline__ void count_window_planes(const PlaceParams &Q, const Chain &ch, int w, int nh,
-                                                    uint32_t *cnt, int N) {
+__device__ __forceinline__ void count_window_planes(const PlaceParams &Q, const Chain &ch, const int *clist, int w,
+                                                    int nh, uint32_t *cnt, int N) {
     if (ch.bad) return;
     const int lo = (ch.f0 + w * PL_WIN) >> HIT_CHUNK_LOG2;
+    const bool listed = ch.listed;
 #pragma unroll
     for (int u = 0; u < PL_UNROLL; ++u) {
         const int j = w * PL_WIN + u * PL_THREADS + (int)threadIdx.x;
         if (j < nh) {
             const int pos = ch.f0 + j;
             const int hop = (pos >> HIT_CHUNK_LOG2) - lo;
-            const int c = (hop >= 0 && hop < 3) ? ch.win[hop] : -1;
+            const int c = listed ? clist[pos >> HIT_CHUNK_LOG2] : (hop >= 0 && hop < 3) ? ch.win[hop] : -1;
             if (c < 0 || c >= Q.h_chunks) continue;          // never outside the log
             const int k = ((const uint8_t *)(Q.hlog + (int64_t)c * HIT_CHUNK_WORDS + HIT_PLANE_OFF))[pos & (HIT_CHUNK - 1)];
             if (k < N) atomicAdd(&cnt[k], 1u);
@@ -302,11 +328,12 @@ template <bool KEYS, int MODE>
 __global__ void __launch_bounds__(PL_THREADS)
 __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_place(PlaceParams Q) {
     constexpr bool BUCKET = MODE == PM_BUCKET;
-    extern __shared__ uint32_t slab[];                 // zero between uses
+    extern __shared__ __attribute__((aligned(16))) uint32_t slab[];    // zero between uses; 16-byte aligned for b128
     uint32_t *const scnt = slab + PL_SLAB_WORDS;       // [PL_MAX_SLABS + 1], BUCKET only
     __shared__ int32_t lay[64];
     __shared__ uint32_t cnt[64];
     __shared__ Chain ch;
+    __shared__ int clist[PL_CLIST];
     // records are valid only when the propagation succeeded; hit outputs
     // only when they all fit
     if (batch_failed(Q.ctr)) return;
@@ -326,14 +353,17 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
             ch.cur_h = 0;
             ch.cur_c = ch.c0;
             ch.bad = (nh > 0 && (st < 0 || ch.c0 >= Q.h_chunks)) ? 1 : 0;
+            list_chain(Q, ch, clist, nh);
         }
         if (threadIdx.x < 64) cnt[threadIdx.x] = 0u;
         lds_barrier();
         const int nwin = (nh + PL_WIN - 1) / PL_WIN;
-        // window 0 stays in registers for every pass
-        walk_to_window(Q, ch, 0, nh);
+        // window 0 stays in registers for every pass; a listed chain needs no
+        // walk (ch.listed is uniform: read after the barrier)
+        const bool listed = ch.listed;
+        if (!listed) walk_to_window(Q, ch, 0, nh);
         const bool ok = !ch.bad;
-        const Window<KEYS> W0 = load_window<KEYS>(Q, ch, 0, nh);
+        const Window<KEYS> W0 = load_window<KEYS>(Q, ch, clist, 0, nh);
 
         if (hits && ok) {
             const int64_t seg = Q.hoff[i];
@@ -341,8 +371,8 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
                 // hits per plane -> first place of each plane in the segment
                 count_planes(W0, cnt, N);
                 for (int w = 1; w < nwin; ++w) {
-                    walk_to_window(Q, ch, w, nh);
-                    count_window_planes(Q, ch, w, nh, cnt, N);
+                    if (!listed) walk_to_window(Q, ch, w, nh);
+                    count_window_planes(Q, ch, clist, w, nh, cnt, N);
                 }
                 lds_barrier();
                 if (threadIdx.x < 64) {
@@ -366,8 +396,8 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
                 } else {
                     place_hits(Q, W0, cnt, lay, seg, nh, N);
                     for (int w = 1; w < nwin; ++w) {
-                        walk_to_window(Q, ch, w, nh);
-                        place_hits(Q, load_window<KEYS>(Q, ch, w, nh), cnt, lay, seg, nh, N);
+                        if (!listed) walk_to_window(Q, ch, w, nh);
+                        place_hits(Q, load_window<KEYS>(Q, ch, clist, w, nh), cnt, lay, seg, nh, N);
                     }
                 }
             }
@@ -384,8 +414,8 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
             for (int q = (int)threadIdx.x; q <= nslab; q += PL_THREADS) scnt[q] = 0u;
             lds_barrier();
             for (int w = 0; w < nwin; ++w) {
-                if (w > 0) walk_to_window(Q, ch, w, nh);
-                const Window<KEYS> W = w == 0 ? W0 : load_window<KEYS>(Q, ch, w, nh);
+                if (w > 0 && !listed) walk_to_window(Q, ch, w, nh);
+                const Window<KEYS> W = w == 0 ? W0 : load_window<KEYS>(Q, ch, clist, w, nh);
                 int row[PL_UNROLL], col[PL_UNROLL];
                 cells(Q, W, lay, N, row, col);
 #pragma unroll
@@ -413,8 +443,8 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
             lds_barrier();
             // scnt[1 + s] now runs as the fill cursor of slab s
             for (int w = 0; w < nwin; ++w) {
-                if (w > 0) walk_to_window(Q, ch, w, nh);
-                const Window<KEYS> W = w == 0 ? W0 : load_window<KEYS>(Q, ch, w, nh);
+                if (w > 0 && !listed) walk_to_window(Q, ch, w, nh);
+                const Window<KEYS> W = w == 0 ? W0 : load_window<KEYS>(Q, ch, clist, w, nh);
                 int row[PL_UNROLL], col[PL_UNROLL];
                 cells(Q, W, lay, N, row, col);
 #pragma unroll
@@ -455,8 +485,8 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
                 if (ok) {
                     bin_window(Q, W0, lay, slab, row0, rows, N);
                     for (int w = 1; w < nwin; ++w) {
-                        walk_to_window(Q, ch, w, nh);
-                        bin_window(Q, load_window<false>(Q, ch, w, nh), lay, slab, row0, rows, N);
+                        if (!listed) walk_to_window(Q, ch, w, nh);
+                        bin_window(Q, load_window<false>(Q, ch, clist, w, nh), lay, slab, row0, rows, N);
                     }
                 }
                 lds_barrier();
