@@ -91,3 +91,48 @@ def test_w1_and_mean_discrepancy():
     # a sample shifted by one reference standard deviation in every column
     shifted = ref + ref.std(axis=0)
     assert SO.mean_discrepancy(ref, shifted) == pytest.approx(1.0, rel=1e-9)
+
+
+def test_hist_w1_closed_forms_and_limit():
+    # two point masses one apart: the bin centres sit h/2 inside the range
+    for n_bins in (1, 2, 7, 100):
+        d = SO.hist_w1(np.zeros(10), np.ones(30), n_bins)
+        assert d == pytest.approx((n_bins - 1) / n_bins, abs=1e-15)
+    rng = np.random.default_rng(5)
+    a, b = rng.normal(size=3000), rng.gamma(2.0, size=2000)
+    assert SO.hist_w1(a, a.copy(), 50) == 0
+    # many bins: within one bin width of the exact distance
+    n_bins = 100_000
+    h = (max(a.max(), b.max()) - min(a.min(), b.min())) / n_bins
+    assert abs(SO.hist_w1(a, b, n_bins) - stats.wasserstein_distance(a, b)) <= h
+
+
+def test_hist_bins_match_numpy_histogram():
+    rng = np.random.default_rng(6)
+    v = rng.normal(size=20000).astype(np.float32).astype(np.float64)
+    lo, hi = v.min(), v.max()
+    for n_bins in (1, 10, 97, 1024):
+        mine = np.bincount(SO.hist_bins(v, lo, hi, n_bins), minlength=n_bins)
+        ref, _ = np.histogram(v, bins=n_bins, range=(lo, hi))
+        assert np.abs(mine - ref).sum() <= 2 and mine.sum() == len(v)
+    assert (SO.hist_bins([3.0, 3.0], 3.0, 3.0, 8) == 0).all()
+
+
+def test_w1_columns_invariances_and_skips():
+    rng = np.random.default_rng(7)
+    ref = rng.normal(size=(4000, 4)) * [1.0, 3.0, 0.5, 1.0]
+    smp = rng.normal(size=(3000, 4)) * [1.2, 3.0, 0.5, 1.0] + [0.1, 0.0, 0.2, 0.0]
+    ref[:, 3] = 2.5                                   # constant reference column
+    smp[::7, 1] = np.nan                              # dropped entries
+    d = SO.w1_columns(ref, smp, 64)
+    assert np.isnan(d[3]) and np.isfinite(d[:3]).all()
+    # normalisation by the reference: an affine map of both samples keeps it
+    d2 = SO.w1_columns(ref * 4.0 - 7.0, smp * 4.0 - 7.0, 64)
+    assert np.allclose(d[:3], d2[:3], rtol=1e-9)
+    # histogram distance -> exact distance as the bins shrink
+    ex = SO.w1_columns(ref, smp, None)
+    fine = SO.w1_columns(ref, smp, 50_000)
+    assert np.allclose(fine[:3], ex[:3], atol=1e-3)
+    assert np.isnan(SO.w1_columns(ref[:1], smp, 8)).all()      # one reference row
+    g = SO.group_means([1.0, np.nan, 3.0, 5.0], [0, 0, 0, 2], 3)
+    assert g[0] == 2.0 and np.isnan(g[1]) and g[2] == 5.0
