@@ -64,3 +64,29 @@ def test_unknown_output_bits_rejected():
 def test_angle_mode_names():
     with pytest.raises(KeyError):
         supa.make_geometry(base_geom(angle_mode="gaussian"), 1)
+
+
+def test_shape_entry_points_reject_bad_arguments_on_the_host():
+    import ctypes as C
+    from paper_2202_05012_amd import shapes
+    L = shapes._lib()
+    fake = C.c_void_p(4096)                       # never dereferenced: rejected first
+    assert L.supa_shower_shapes(None, 10, 65, fake, fake, 1, fake, fake, fake, fake, fake, fake,
+                                fake) == 1
+    assert L.supa_shower_shapes(None, 10, 20, fake, fake, 0, fake, fake, fake, fake, fake, fake,
+                                fake) == 1
+    assert L.supa_shower_shapes(None, 10, 20, fake, fake, 1, C.c_void_p(4100), fake, fake, fake,
+                                fake, fake, fake) == 1     # misaligned hit array
+    assert "aligned" in L.supa_shapes_last_error().decode()
+    assert L.supa_w1_workspace_bytes(0, 10, 5, 5) == 0
+    need = L.supa_w1_workspace_bytes(7, 100, 1000, 2000)
+    assert need > 7 * 100 * 8
+    args = lambda **kw: [kw.get(k, d) for k, d in (
+        ("s", None), ("cols", 7), ("ref", fake), ("nr", 1000), ("ldr", 7), ("smp", fake),
+        ("ns", 2000), ("lds", 7), ("bins", 100), ("g", None), ("ng", 0), ("w1", fake),
+        ("gm", None), ("ws", fake), ("wsb", need))]
+    assert L.supa_w1_normalized(*args(bins=0)) == 1
+    assert L.supa_w1_normalized(*args(bins=4097)) == 1
+    assert L.supa_w1_normalized(*args(ldr=6)) == 1
+    assert L.supa_w1_normalized(*args(wsb=need - 1)) == 1
+    assert L.supa_w1_normalized(*args(g=fake, ng=0)) == 1
