@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--surrogate", action="store_true",
                     help="train the surrogate online, then time surrogate + fallback against "
                          "the plain simulator at the W1 <= 2%% target")
+    ap.add_argument("--shapes", action="store_true",
+                    help="time the shower-shape-variable kernel (and the normalised W1 between "
+                         "two simulated samples) on the workload's hit clouds")
+    ap.add_argument("--bins", type=int, default=100, help="histogram bins of the W1 (--shapes)")
     ap.add_argument("--train-showers", type=int, default=10_000_000)
     ap.add_argument("--eval-showers", type=int, default=1_000_000)
     ap.add_argument("--batch", type=int, default=8192)
@@ -168,6 +172,122 @@ def bench_surrogate(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_shapes(args):
+    """Shower shape variables (supa_shower_shapes) of one simulated sample of
+    the workload, and the normalised W1 of every variable between it and a
+    second sample (supa_w1_normalized).  The hits are simulated once, before
+    anything is timed; a step is one shape-variable call over the batch."""
+    import torch
+    from paper_2202_05012_amd import prof_summary, shapes as SH, supa, workloads
+    from oracle import shape_oracle
+
+    w = workloads.WORKLOADS[args.workload]
+    geom = workloads.geometry(w)
+    L = supa.n_layers(geom)
+    dev = torch.device("cuda", 0)
+    sim = supa.Simulator(geom, supa.OUT_HITS)
+    samples = []
+    for k, seed in enumerate((w.seed, w.seed + 1)):
+        e0, pol, az = workloads.initial_conditions(w, seed=seed)
+        t = [torch.from_numpy(a).to(dev) for a in (e0, pol, az)]
+        samples.append(sim.simulate(*t, seed=seed, shower_id_base=k * w.n))
+    del sim
+    out = samples[0]
+    n = w.n
+    hits = int(out["total_hits"])
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    # the second sample's variables (W1 below), then the timed sample checked
+    # once for the layer rule: dispatches 0 and 1 of the shape kernel
+    lv1, sv1 = SH.simulator_shapes(samples[1], L, check=True)
+    SH.simulator_shapes(out, L, check=True)
+    for _ in range(args.warmup):
+        SH.simulator_shapes(out, L, check=False)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        lv, sv = SH.simulator_shapes(out, L, check=False)
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    k_ms = ev0.elapsed_time(ev1) / args.steps
+    cols = L * len(SH.LAYER_VARS) + len(SH.SHOWER_VARS)
+    alg = BYTES_PER_HIT * hits + n * (8 + 4 + cols * 4)
+    prof_dir = os.path.join(ROOT, "profiles")
+    wl = "shapes_" + w.name
+    gbs = alg / (k_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4),
+            "traffic": prof_summary.traffic_if_current(prof_dir, "shapes_kernel", wl),
+            "kernel": "shapes_kernel", "kernel_ms": round(k_ms, 4), "alg_bytes": alg}
+
+    # normalised W1 of every variable, sample 1 against sample 0 (reference)
+    mats = [torch.cat([a.view(n, -1), b], dim=1).contiguous() for a, b in ((lv, sv), (lv1, sv1))]
+    groups = torch.cat([torch.arange(len(SH.LAYER_VARS)).repeat(L),
+                        len(SH.LAYER_VARS) + torch.arange(len(SH.SHOWER_VARS))]).int().to(dev)
+    ws = SH.W1Workspace(dev)
+    n_groups = len(SH.LAYER_VARS) + len(SH.SHOWER_VARS)
+    for _ in range(max(1, args.warmup)):
+        SH.w1_columns(mats[0], mats[1], args.bins, groups, n_groups, ws)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        d, gm = SH.w1_columns(mats[0], mats[1], args.bins, groups, n_groups, ws)
+    ev1.record()
+    torch.cuda.synchronize()
+    w1_ms = ev0.elapsed_time(ev1) / args.steps
+    w1_bytes = 2 * 2 * n * cols * 4                   # two passes (range, histogram) over both
+    gm_h = gm.cpu().numpy()
+    line = {
+        "metric": "shower-shape-variable showers/s (1 MI355X)",
+        "value": round(n / (ms_per_step / 1e3), 1),
+        "unit": "showers/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 sums, f32 out", "data": "synthetic",
+        "config": {"workload": wl, "showers": n, "layers": L, "hits": hits,
+                   "variables_per_shower": cols},
+        "roofline": roof,
+        "roofline_other": {"bound": "hbm", "kernel": "w1 (stats + histograms + distance)",
+                           "achieved": round(w1_bytes / (w1_ms / 1e3) / 1e9, 1),
+                           "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": round(w1_bytes / (w1_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                           "traffic": None, "ms": round(w1_ms, 4), "alg_bytes": w1_bytes,
+                           "bins": args.bins, "columns": cols},
+        "mean_discrepancy_by_variable": {k: round(float(v), 5) for k, v in
+                                         zip(SH.LAYER_VARS + SH.SHOWER_VARS, gm_h)},
+    }
+    if not args.no_cpu_baseline:
+        # the oracle's shape variables of the first showers, for about
+        # --cpu-seconds of one host core
+        off = out["hit_offsets"].cpu().numpy()
+        cnt = out["counts"][:, 1].cpu().numpy().astype(np.int64)
+        m = 1
+        done, t_cpu = 0, 0.0
+        while t_cpu < args.cpu_seconds and done < n:
+            m = min(2 * m, n - done)
+            a, b = int(off[done]), int(off[done + m - 1] + cnt[done + m - 1])
+            hx, hy, he, hl = (out[k][a:b].cpu().numpy() for k in ("hit_x", "hit_y", "hit_e", "hit_layer"))
+            sid = np.repeat(np.arange(m), cnt[done:done + m])
+            keep = hl >= 0
+            c0 = time.perf_counter()
+            shape_oracle.shapes(m, L, sid[keep], hl[keep], hx[keep].astype(np.float64),
+                                hy[keep].astype(np.float64), he[keep].astype(np.float64))
+            t_cpu += time.perf_counter() - c0
+            done += m
+        line["cpu_baseline"] = {"value": round(done / t_cpu, 1), "unit": "showers/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"shape variables of the first {done} showers "
+                                          f"({t_cpu:.1f} s, one thread)"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -176,6 +296,8 @@ def main():
         sys.exit(2)
     if args.surrogate:
         return bench_surrogate(args)
+    if args.shapes:
+        return bench_shapes(args)
 
     import torch
     from paper_2202_05012_amd import supa, workloads

@@ -137,15 +137,94 @@ __global__ void shapes_clear(int32_t *work) {
     if (threadIdx.x < 4) work[threadIdx.x] = 0;
 }
 
-// One wave per workgroup; dynamic LDS: float [L][64], the layer energies of
-// each lane's current shower (for the fractions, written once E_tot is known).
+// Records of finished layer runs wait in a per-wave LDS ring until 64 are
+// ready, then the wave computes and writes 64 records at once (one per lane):
+// the division and square roots of a record run with every lane busy instead
+// of once per lane whose run happens to end.
+constexpr int QCAP = 128;      // ring entries (a step adds at most 64)
+constexpr int BLK = 16;        // hits per lane per step: one 64-byte sector per array
+
+struct Ring {
+    double d[12][QCAP];
+    int n[QCAP], s[QCAP], l[QCAP];
+    float e1[QCAP], e2[QCAP];
+};
+
+// Adds the runs of the lanes with `cond` to the ring at t (wave-uniform).
+__device__ inline void ring_put(Ring &q, int &t, bool cond, int s, int l, const Run &a) {
+    const uint64_t m = __ballot(cond);
+    if (cond) {
+        const int slot = (t + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0))) &
+                         (QCAP - 1);
+        q.d[0][slot] = a.sx;
+        q.d[1][slot] = a.sxx;
+        q.d[2][slot] = a.sy;
+        q.d[3][slot] = a.syy;
+        q.d[4][slot] = a.sr;
+        q.d[5][slot] = a.se;
+        q.d[6][slot] = a.see;
+        q.d[7][slot] = a.sex;
+        q.d[8][slot] = a.sexx;
+        q.d[9][slot] = a.sey;
+        q.d[10][slot] = a.seyy;
+        q.d[11][slot] = a.ser;
+        q.n[slot] = a.n;
+        q.s[slot] = s;
+        q.l[slot] = l;
+        q.e1[slot] = a.e1;
+        q.e2[slot] = a.e2;
+    }
+    t += __builtin_popcountll(m);
+}
+
+// Writes up to `most` (<= 64) records from the ring head h (wave-uniform call).
+__device__ inline void ring_drain(Ring &q, int &h, int t, int most, float *lv, int L) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int k = (t - h) < most ? (t - h) : most;
+    const int lane = threadIdx.x;
+    if (lane < k) {
+        const int slot = (h + lane) & (QCAP - 1);
+        Run a;
+        a.sx = q.d[0][slot];
+        a.sxx = q.d[1][slot];
+        a.sy = q.d[2][slot];
+        a.syy = q.d[3][slot];
+        a.sr = q.d[4][slot];
+        a.se = q.d[5][slot];
+        a.see = q.d[6][slot];
+        a.sex = q.d[7][slot];
+        a.sexx = q.d[8][slot];
+        a.sey = q.d[9][slot];
+        a.seyy = q.d[10][slot];
+        a.ser = q.d[11][slot];
+        a.n = q.n[slot];
+        a.e1 = q.e1[slot];
+        a.e2 = q.e2[slot];
+        write_layer(lv + ((size_t)q.s[slot] * L + q.l[slot]) * LV, a);
+    }
+    h += k;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wave per workgroup; static LDS: the ring; dynamic LDS: float [L][64],
+// the layer energies of each lane's current shower (for the fractions,
+// written once E_tot is known).  Every cross-lane step (ring, drain, exit)
+// runs in wave-uniform control flow.
 __global__ void __launch_bounds__(WAVE) shapes_kernel(ShapeArgs A) {
+    __shared__ Ring q;
     extern __shared__ float ef[];
     const int lane = threadIdx.x;
     const int L = A.L;
     const float nan = __builtin_nanf("");
     uint32_t *queue = (uint32_t *)A.work + 1;
 
+    int h = 0, t = 0;  // ring head and tail (wave-uniform)
+    bool active = true;
     int64_t s = -1, pos = 0, end = 0;
     int cur = -1, depth = -1;
     bool bad = false;
@@ -155,100 +234,122 @@ __global__ void __launch_bounds__(WAVE) shapes_kernel(ShapeArgs A) {
     run_clear(acc);
 
     for (;;) {
-        if (pos >= end) {
-            if (s >= 0) {
-                // close the shower: last run, empty layers, fractions, totals
+        // --- lanes whose shower is done: last run, empty layers, totals
+        const bool closing = active && s >= 0 && pos >= end;
+        ring_put(q, t, closing && !bad && cur >= 0, (int)s, cur, acc);
+        if (closing && !bad) {
+            float *base = A.lv + (size_t)s * L * LV;
+            if (cur >= 0) {
+                ef[cur * WAVE + lane] = (float)acc.se;
+                etot += acc.se;
+                ld += (double)cur * acc.se;
+                ld2 += (double)cur * (double)cur * acc.se;
+                if (acc.se > 0.0 && cur > depth) depth = cur;
+            }
+            const double it = 1.0 / etot;
+            for (int l = 0; l < L; ++l) {
+                float *rec = base + (size_t)l * LV;
+                if (!((seen >> l) & 1)) write_empty_layer(rec);
+                rec[SUPA_LV_FRACTION] = etot > 0.0 ? (float)((double)ef[l * WAVE + lane] * it) : nan;
+            }
+            float *sv = A.sv + (size_t)s * SV;
+            const double sd = ld * it;
+            sv[SUPA_SV_E_TOT] = (float)etot;
+            sv[SUPA_SV_DEPTH] = (float)depth;
+            sv[SUPA_SV_L_D] = (float)ld;
+            sv[SUPA_SV_S_D] = etot > 0.0 ? (float)sd : nan;
+            sv[SUPA_SV_S_D_WIDTH] = etot > 0.0 ? dev_of(sd, ld2 * it) : nan;
+        }
+        // a shower in error: its earlier runs leave the ring first, then NaN
+        if (__ballot(closing && bad)) {
+            while (t - h > 0) ring_drain(q, h, t, WAVE, A.lv, L);
+            if (closing && bad) {
                 float *base = A.lv + (size_t)s * L * LV;
-                if (cur >= 0) {
-                    write_layer(base + (size_t)cur * LV, acc);
-                    ef[cur * WAVE + lane] = (float)acc.se;
-                    etot += acc.se;
-                    ld += (double)cur * acc.se;
-                    ld2 += (double)cur * (double)cur * acc.se;
-                    if (acc.se > 0.0 && cur > depth) depth = cur;
-                }
-                const double it = 1.0 / etot;
-                for (int l = 0; l < L; ++l) {
-                    float *rec = base + (size_t)l * LV;
-                    if (bad) {
-                        for (int f = 0; f < LV; ++f) rec[f] = nan;
-                        continue;
-                    }
-                    if (!((seen >> l) & 1)) write_empty_layer(rec);
-                    rec[SUPA_LV_FRACTION] = etot > 0.0 ? (float)((double)ef[l * WAVE + lane] * it) : nan;
-                }
-                float *sv = A.sv + (size_t)s * SV;
-                if (bad) {
-                    for (int f = 0; f < SV; ++f) sv[f] = nan;
-                    atomicAdd(A.work, 1);
-                } else {
-                    const double sd = ld * it;
-                    sv[SUPA_SV_E_TOT] = (float)etot;
-                    sv[SUPA_SV_DEPTH] = (float)depth;
-                    sv[SUPA_SV_L_D] = (float)ld;
-                    sv[SUPA_SV_S_D] = etot > 0.0 ? (float)sd : nan;
-                    sv[SUPA_SV_S_D_WIDTH] = etot > 0.0 ? dev_of(sd, ld2 * it) : nan;
+                for (int f = 0; f < L * LV; ++f) base[f] = nan;
+                for (int f = 0; f < SV; ++f) A.sv[(size_t)s * SV + f] = nan;
+                atomicAdd(A.work, 1);
+            }
+        }
+        if (t - h >= WAVE) ring_drain(q, h, t, WAVE, A.lv, L);
+        // --- next shower from the queue
+        if (active && pos >= end) {
+            const uint32_t next = atomicAdd(queue, 1u);
+            if ((int64_t)next >= A.n) {
+                active = false;
+            } else {
+                s = next;
+                pos = A.off[s];
+                end = pos + A.cnt[(size_t)s * A.cstride];
+                cur = -1;
+                depth = -1;
+                bad = false;
+                seen = 0;
+                etot = ld = ld2 = 0.0;
+                run_clear(acc);
+                for (int l = 0; l < L; ++l) ef[l * WAVE + lane] = 0.0f;
+            }
+        }
+        if (!__ballot(active)) break;
+
+        // --- one aligned block of BLK hits per lane, clipped to [pos, end)
+        const bool work = active && pos < end;
+        const int64_t b0 = pos & ~(int64_t)(BLK - 1);
+        float vx[BLK], vy[BLK], ve[BLK];
+        int vl[BLK];
+        if (work && pos == b0 && b0 + BLK <= end) {
+#pragma unroll
+            for (int k = 0; k < BLK; k += 4) {
+                const f32x4 a = *(const f32x4 *)(A.x + b0 + k);
+                const f32x4 b = *(const f32x4 *)(A.y + b0 + k);
+                const f32x4 c = *(const f32x4 *)(A.e + b0 + k);
+                const i32x4 d = *(const i32x4 *)(A.layer + b0 + k);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    vx[k + j] = a[j];
+                    vy[k + j] = b[j];
+                    ve[k + j] = c[j];
+                    vl[k + j] = d[j];
                 }
             }
-            const uint32_t next = atomicAdd(queue, 1u);
-            if ((int64_t)next >= A.n) break;
-            s = next;
-            pos = A.off[s];
-            end = pos + A.cnt[(size_t)s * A.cstride];
-            cur = -1;
-            depth = -1;
-            bad = false;
-            seen = 0;
-            etot = ld = ld2 = 0.0;
-            run_clear(acc);
-            for (int l = 0; l < L; ++l) ef[l * WAVE + lane] = 0.0f;
-            continue;
-        }
-        // one aligned block of four hits, [b0, b0 + 4) clipped to [pos, end)
-        const int64_t b0 = pos & ~(int64_t)3;
-        f32x4 vx, vy, ve;
-        i32x4 vl;
-        if (pos == b0 && b0 + 4 <= end) {
-            vx = *(const f32x4 *)(A.x + b0);
-            vy = *(const f32x4 *)(A.y + b0);
-            ve = *(const f32x4 *)(A.e + b0);
-            vl = *(const i32x4 *)(A.layer + b0);
         } else {
-            for (int j = 0; j < 4; ++j) {
+#pragma unroll
+            for (int j = 0; j < BLK; ++j) {
                 const int64_t i = b0 + j;
-                const bool in = i >= pos && i < end;
+                const bool in = work && i >= pos && i < end;
                 vx[j] = in ? A.x[i] : 0.0f;
                 vy[j] = in ? A.y[i] : 0.0f;
                 ve[j] = in ? A.e[i] : 0.0f;
                 vl[j] = in ? A.layer[i] : -1;
             }
         }
-        for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int j = 0; j < BLK; ++j) {
             const int l = vl[j];
-            if (l < 0 || bad) continue;
-            if (l != cur) {
+            const bool sw = l >= 0 && !bad && l != cur;  // a new run starts here
+            ring_put(q, t, sw && cur >= 0, (int)s, cur, acc);
+            if (sw) {
                 if (cur >= 0) {
-                    write_layer(A.lv + ((size_t)s * L + cur) * LV, acc);
                     ef[cur * WAVE + lane] = (float)acc.se;
                     etot += acc.se;
                     ld += (double)cur * acc.se;
                     ld2 += (double)cur * (double)cur * acc.se;
                     if (acc.se > 0.0 && cur > depth) depth = cur;
-                    run_clear(acc);
                 }
+                run_clear(acc);
                 if (l >= L || ((seen >> l) & 1)) {
                     bad = true;
                     cur = -1;
-                    continue;
+                } else {
+                    seen |= 1ull << l;
+                    cur = l;
                 }
-                seen |= 1ull << l;
-                cur = l;
             }
-            run_add(acc, vx[j], vy[j], ve[j]);
+            if (l >= 0 && !bad) run_add(acc, vx[j], vy[j], ve[j]);
+            if (t - h >= WAVE) ring_drain(q, h, t, WAVE, A.lv, L);
         }
-        pos = (b0 + 4 < end) ? b0 + 4 : end;
-        if (bad) pos = end;
+        if (work) pos = bad ? end : (b0 + BLK < end ? b0 + BLK : end);
     }
+    while (t - h > 0) ring_drain(q, h, t, WAVE, A.lv, L);
 }
 
 __global__ void radius_kernel(int64_t n, const float *x, const float *y, float *r) {

@@ -35,6 +35,9 @@ KERNEL_SOURCES = {
     "supa_propagate": ["supa_propagate.hip", "supa_device.hpp"],
     "supa_place": ["supa_place.hip", "supa_device.hpp"],
     "scatter_nodes": ["supa_scatter.hip", "supa_device.hpp"],
+    "shapes_kernel": ["supa_shapes.hip"],
+    "w1_stats": ["supa_shapes.hip"],
+    "w1_hist": ["supa_shapes.hip"],
 }
 
 
@@ -47,7 +50,8 @@ def source_hash(kernel: str) -> str:
 
 
 def short_name(full: str) -> str:
-    m = re.search(r"(supa_propagate|supa_place|scatter_nodes|scan_tiles|scan_top|scan_apply)", full)
+    m = re.search(r"(supa_propagate|supa_place|scatter_nodes|scan_tiles|scan_top|scan_apply|shapes_kernel|"
+                  r"shapes_clear|w1_stats|w1_hist|w1_colinfo|w1_distance|w1_groups|w1_zero)\b", full)
     return m.group(1) if m else full
 
 
@@ -92,7 +96,7 @@ def steady(vals, skip):
     return statistics.fmean(v) if v else float("nan")
 
 
-def summarize(trace_dir, fetch_dir, write_dir, workload, commands, out_dir, skip=2):
+def summarize(trace_dir, fetch_dir, write_dir, workload, commands, out_dir, skip=2, kernels=None):
     dur = durations(trace_dir)
     fetch, fcopy = counter(fetch_dir, "FETCH_SIZE")
     write, wcopy = counter(write_dir, "WRITE_SIZE")
@@ -100,7 +104,7 @@ def summarize(trace_dir, fetch_dir, write_dir, workload, commands, out_dir, skip
     w_scale = COPY_BYTES / 1024.0 / wcopy if wcopy else float("nan")
     written = []
     for k in KERNEL_SOURCES:
-        if k not in dur:
+        if k not in dur or (kernels and k not in kernels):
             continue
         ms = steady(dur[k], skip)
         fk = steady(fetch.get(k, []), skip)
@@ -114,7 +118,7 @@ def summarize(trace_dir, fetch_dir, write_dir, workload, commands, out_dir, skip
             *[f"    {c}" for c in commands],
             "",
             f"source_sha256: {source_hash(k)}",
-            f"dispatches_traced: {len(dur[k])} (first {skip} skipped: sizing probe, first warm-up)",
+            f"dispatches_traced: {len(dur[k])} (first {skip} skipped: sizing or checking call, first warm-up)",
             f"avg_duration_ms: {ms:.4f}",
             f"min_duration_ms: {min(dur[k][skip:] or dur[k]):.4f}",
             f"max_duration_ms: {max(dur[k][skip:] or dur[k]):.4f}",
@@ -242,9 +246,12 @@ def main():
     ap.add_argument("--command", action="append", default=[])
     ap.add_argument("--out", required=True)
     ap.add_argument("--skip", type=int, default=2)
+    ap.add_argument("--kernel", action="append", default=[],
+                    help="summarise only these kernels (default: every known kernel traced)")
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
-    for p in summarize(a.trace_dir, a.fetch_dir, a.write_dir, a.workload, a.command, a.out, a.skip):
+    for p in summarize(a.trace_dir, a.fetch_dir, a.write_dir, a.workload, a.command, a.out, a.skip,
+                       a.kernel or None):
         print(p)
 
 
