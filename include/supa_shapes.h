@@ -71,7 +71,10 @@ enum {
  * Shape variables of n showers whose hits are stored segment by segment (the
  * hit layout of supa_simulate): the hits of shower s are the entries
  * [hit_offsets[s], hit_offsets[s] + hit_counts[s * counts_stride]) of
- * hit_x, hit_y, hit_e (float) and hit_layer (int32).  Hits of layer -1 (planes
+ * hit_x, hit_y, hit_e (float) and hit_layer (int32), arrays of hit_len
+ * entries; every segment must lie inside [0, hit_len) (the kernel reads
+ * aligned blocks of 32 entries that may reach outside a segment, never
+ * outside the arrays; it cannot check the segments).  Hits of layer -1 (planes
  * not read out) are skipped.  Within a segment the hits of one layer must be
  * contiguous (true for supa_simulate's output whenever layer_of_plane is
  * non-decreasing over the read-out planes, i.e. layers are ranges of planes).
@@ -87,7 +90,8 @@ enum {
  */
 supa_status supa_shower_shapes(void *hip_stream, int64_t n, int32_t n_layers,
                                const int64_t *hit_offsets, const int32_t *hit_counts,
-                               int32_t counts_stride, const float *hit_x, const float *hit_y,
+                               int32_t counts_stride, int64_t hit_len, const float *hit_x,
+                               const float *hit_y,
                                const float *hit_e, const int32_t *hit_layer, float *layer_vars,
                                float *shower_vars, int32_t *work);
 

@@ -41,6 +41,7 @@ struct ShapeArgs {
     const int64_t *off;
     const int32_t *cnt;
     int cstride;
+    int64_t len;  // entries of each hit array
     const float *x, *y, *e;
     const int32_t *layer;
     float *lv, *sv;
@@ -54,6 +55,24 @@ struct Run {
     float e1, e2;  // the two largest point energies
 };
 
+// sqrt of s >= 0: hardware reciprocal square root, then one Newton step on
+// the residual (relative error about 1e-15), 0 for s = 0.
+__device__ inline double sqrt_pos(double s) {
+    const double y = __builtin_amdgcn_rsq(s);
+    const double r0 = s * y;
+    const double e = __builtin_fma(-r0, r0, s);
+    const double r = __builtin_fma(0.5 * y, e, r0);
+    return s > 0.0 ? r : 0.0;
+}
+
+// 1 / v for v > 0: hardware reciprocal and two Newton steps (about 1 ulp).
+__device__ inline double recip(double v) {
+    double y = __builtin_amdgcn_rcp(v);
+    y = __builtin_fma(__builtin_fma(-v, y, 1.0), y, y);
+    y = __builtin_fma(__builtin_fma(-v, y, 1.0), y, y);
+    return y;
+}
+
 __device__ inline void run_clear(Run &a) {
     a.sx = a.sxx = a.sy = a.syy = a.sr = a.se = a.see = 0.0;
     a.sex = a.sexx = a.sey = a.seyy = a.ser = 0.0;
@@ -64,7 +83,7 @@ __device__ inline void run_clear(Run &a) {
 __device__ inline void run_add(Run &a, float xf, float yf, float ef) {
     const double x = xf, y = yf, e = ef;
     const double xx = x * x, yy = y * y;
-    const double r = __builtin_sqrt(xx + yy);
+    const double r = sqrt_pos(xx + yy);
     const double ex = e * x, ey = e * y;
     a.sx += x;
     a.sxx += xx;
@@ -89,14 +108,14 @@ __device__ inline void run_add(Run &a, float xf, float yf, float ef) {
 
 __device__ inline float dev_of(double m1, double m2) {
     const double v = __builtin_fma(-m1, m1, m2);
-    return __builtin_sqrtf((float)(v > 0.0 ? v : 0.0));
+    return __builtin_amdgcn_sqrtf((float)(v > 0.0 ? v : 0.0));
 }
 
 // Writes every field of a layer record except FRACTION.  Sum of E r^2 is
 // sum E x^2 + sum E y^2; sum r^2 is sum x^2 + sum y^2.
 __device__ inline void write_layer(float *rec, const Run &a) {
     const float nan = __builtin_nanf("");
-    const double in = 1.0 / (double)a.n;
+    const double in = recip((double)a.n);
     const double mx = a.sx * in, my = a.sy * in, mr = a.sr * in, me = a.se * in;
     f32x2 *r2 = (f32x2 *)rec;
     r2[0] = f32x2{(float)a.n, (float)mx};
@@ -105,7 +124,7 @@ __device__ inline void write_layer(float *rec, const Run &a) {
     r2[3] = f32x2{dev_of(my, a.syy * in), dev_of(mr, (a.sxx + a.syy) * in)};
     r2[4] = f32x2{dev_of(me, a.see * in), (float)a.se};
     if (a.se > 0.0) {
-        const double ie = 1.0 / a.se;
+        const double ie = recip(a.se);
         const double cx = a.sex * ie, cy = a.sey * ie, cr = a.ser * ie;
         r2[5] = f32x2{(float)cx, (float)cy};
         r2[6] = f32x2{(float)cr, dev_of(cx, a.sexx * ie)};
@@ -142,7 +161,7 @@ __global__ void shapes_clear(int32_t *work) {
 // the division and square roots of a record run with every lane busy instead
 // of once per lane whose run happens to end.
 constexpr int QCAP = 128;      // ring entries (a step adds at most 64)
-constexpr int BLK = 16;        // hits per lane per step: one 64-byte sector per array
+constexpr int BLK = 32;        // hits per lane per step: one 128-byte line per array
 
 struct Ring {
     double d[12][QCAP];
@@ -246,7 +265,7 @@ __global__ void __launch_bounds__(WAVE) shapes_kernel(ShapeArgs A) {
                 ld2 += (double)cur * (double)cur * acc.se;
                 if (acc.se > 0.0 && cur > depth) depth = cur;
             }
-            const double it = 1.0 / etot;
+            const double it = etot > 0.0 ? recip(etot) : 0.0;
             for (int l = 0; l < L; ++l) {
                 float *rec = base + (size_t)l * LV;
                 if (!((seen >> l) & 1)) write_empty_layer(rec);
@@ -296,7 +315,10 @@ __global__ void __launch_bounds__(WAVE) shapes_kernel(ShapeArgs A) {
         const int64_t b0 = pos & ~(int64_t)(BLK - 1);
         float vx[BLK], vy[BLK], ve[BLK];
         int vl[BLK];
-        if (work && pos == b0 && b0 + BLK <= end) {
+        // whole aligned blocks are read with 16-byte loads whenever they lie
+        // inside the arrays (entries outside [pos, end) are then dropped);
+        // only the arrays' last partial block is read entry by entry
+        if (work && b0 + BLK <= A.len) {
 #pragma unroll
             for (int k = 0; k < BLK; k += 4) {
                 const f32x4 a = *(const f32x4 *)(A.x + b0 + k);
@@ -305,10 +327,11 @@ __global__ void __launch_bounds__(WAVE) shapes_kernel(ShapeArgs A) {
                 const i32x4 d = *(const i32x4 *)(A.layer + b0 + k);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
+                    const int64_t i = b0 + k + j;
                     vx[k + j] = a[j];
                     vy[k + j] = b[j];
                     ve[k + j] = c[j];
-                    vl[k + j] = d[j];
+                    vl[k + j] = (i >= pos && i < end) ? d[j] : -1;
                 }
             }
         } else {
@@ -630,13 +653,14 @@ extern "C" const char *supa_shapes_last_error(void) { return t_err.c_str(); }
 
 extern "C" supa_status supa_shower_shapes(void *stream, int64_t n, int32_t n_layers,
                                           const int64_t *hit_offsets, const int32_t *hit_counts,
-                                          int32_t counts_stride, const float *hit_x,
+                                          int32_t counts_stride, int64_t hit_len, const float *hit_x,
                                           const float *hit_y, const float *hit_e,
                                           const int32_t *hit_layer, float *layer_vars,
                                           float *shower_vars, int32_t *work) {
     if (n < 0 || n > INT32_MAX) return bad_arg("n out of range");
     if (n_layers < 1 || n_layers > 64) return bad_arg("n_layers must be 1..64");
     if (counts_stride < 1) return bad_arg("counts_stride must be >= 1");
+    if (hit_len < 0) return bad_arg("hit_len < 0");
     if (!work) return bad_arg("work is NULL");
     if (n > 0 && (!hit_offsets || !hit_counts || !hit_x || !hit_y || !hit_e || !hit_layer ||
                   !layer_vars || !shower_vars))
@@ -648,7 +672,7 @@ extern "C" supa_status supa_shower_shapes(void *stream, int64_t n, int32_t n_lay
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(shapes_clear, dim3(1), dim3(WAVE), 0, s, work);
     if (n == 0) return dev_err(hipGetLastError(), "shapes_clear");
-    ShapeArgs A{n, n_layers, hit_offsets, hit_counts, counts_stride, hit_x, hit_y, hit_e,
+    ShapeArgs A{n, n_layers, hit_offsets, hit_counts, counts_stride, hit_len, hit_x, hit_y, hit_e,
                 hit_layer, layer_vars, shower_vars, work};
     const int64_t waves = (n + WAVE - 1) / WAVE;
     const int64_t cap = (int64_t)cu_count() * 16;

@@ -71,12 +71,14 @@ def test_shape_entry_points_reject_bad_arguments_on_the_host():
     from paper_2202_05012_amd import shapes
     L = shapes._lib()
     fake = C.c_void_p(4096)                       # never dereferenced: rejected first
-    assert L.supa_shower_shapes(None, 10, 65, fake, fake, 1, fake, fake, fake, fake, fake, fake,
-                                fake) == 1
-    assert L.supa_shower_shapes(None, 10, 20, fake, fake, 0, fake, fake, fake, fake, fake, fake,
-                                fake) == 1
-    assert L.supa_shower_shapes(None, 10, 20, fake, fake, 1, C.c_void_p(4100), fake, fake, fake,
-                                fake, fake, fake) == 1     # misaligned hit array
+    assert L.supa_shower_shapes(None, 10, 65, fake, fake, 1, 100, fake, fake, fake, fake, fake,
+                                fake, fake) == 1
+    assert L.supa_shower_shapes(None, 10, 20, fake, fake, 0, 100, fake, fake, fake, fake, fake,
+                                fake, fake) == 1
+    assert L.supa_shower_shapes(None, 10, 20, fake, fake, 1, -1, fake, fake, fake, fake, fake,
+                                fake, fake) == 1
+    assert L.supa_shower_shapes(None, 10, 20, fake, fake, 1, 100, C.c_void_p(4100), fake, fake,
+                                fake, fake, fake, fake) == 1     # misaligned hit array
     assert "aligned" in L.supa_shapes_last_error().decode()
     assert L.supa_w1_workspace_bytes(0, 10, 5, 5) == 0
     need = L.supa_w1_workspace_bytes(7, 100, 1000, 2000)
