@@ -80,8 +80,9 @@ __device__ inline void run_clear(Run &a) {
     a.e1 = a.e2 = -__builtin_inff();
 }
 
-__device__ inline void run_add(Run &a, float xf, float yf, float ef) {
-    const double x = xf, y = yf, e = ef;
+// Adds one point when `take` (otherwise adds zeros: no branch).
+__device__ inline void run_add(Run &a, float xf, float yf, float ef, bool take) {
+    const double x = take ? xf : 0.0f, y = take ? yf : 0.0f, e = take ? ef : 0.0f;
     const double xx = x * x, yy = y * y;
     const double r = sqrt_pos(xx + yy);
     const double ex = e * x, ey = e * y;
@@ -97,13 +98,10 @@ __device__ inline void run_add(Run &a, float xf, float yf, float ef) {
     a.sey += ey;
     a.seyy = __builtin_fma(ey, y, a.seyy);
     a.ser = __builtin_fma(e, r, a.ser);
-    a.n += 1;
-    if (ef > a.e1) {
-        a.e2 = a.e1;
-        a.e1 = ef;
-    } else if (ef > a.e2) {
-        a.e2 = ef;
-    }
+    a.n += take ? 1 : 0;
+    const float et = take ? ef : -__builtin_inff();  // running two largest
+    a.e2 = __builtin_fmaxf(a.e2, __builtin_fminf(a.e1, et));
+    a.e1 = __builtin_fmaxf(a.e1, et);
 }
 
 __device__ inline float dev_of(double m1, double m2) {
@@ -345,30 +343,49 @@ __global__ void __launch_bounds__(WAVE) shapes_kernel(ShapeArgs A) {
                 vl[j] = in ? A.layer[i] : -1;
             }
         }
+        // bit j: a new run starts at hit j of this lane's block; their OR
+        // over the wave decides (uniformly) which steps need the switch code
+        uint32_t msk = 0;
+        {
+            int p = cur;
+#pragma unroll
+            for (int j = 0; j < BLK; ++j) {
+                const int l = vl[j];
+                msk |= (uint32_t)(l >= 0 && l != p) << j;
+                p = l >= 0 ? l : p;
+            }
+            if (bad) msk = 0;
+        }
+        uint32_t any = msk;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) any |= (uint32_t)__shfl_xor((int)any, d);
+        any = __builtin_amdgcn_readfirstlane(any);
 #pragma unroll
         for (int j = 0; j < BLK; ++j) {
             const int l = vl[j];
-            const bool sw = l >= 0 && !bad && l != cur;  // a new run starts here
-            ring_put(q, t, sw && cur >= 0, (int)s, cur, acc);
-            if (sw) {
-                if (cur >= 0) {
-                    ef[cur * WAVE + lane] = (float)acc.se;
-                    etot += acc.se;
-                    ld += (double)cur * acc.se;
-                    ld2 += (double)cur * (double)cur * acc.se;
-                    if (acc.se > 0.0 && cur > depth) depth = cur;
+            if ((any >> j) & 1) {
+                const bool sw = ((msk >> j) & 1) && !bad;  // a new run starts here
+                ring_put(q, t, sw && cur >= 0, (int)s, cur, acc);
+                if (sw) {
+                    if (cur >= 0) {
+                        ef[cur * WAVE + lane] = (float)acc.se;
+                        etot += acc.se;
+                        ld += (double)cur * acc.se;
+                        ld2 += (double)cur * (double)cur * acc.se;
+                        if (acc.se > 0.0 && cur > depth) depth = cur;
+                    }
+                    run_clear(acc);
+                    if (l >= L || ((seen >> l) & 1)) {
+                        bad = true;
+                        cur = -1;
+                    } else {
+                        seen |= 1ull << l;
+                        cur = l;
+                    }
                 }
-                run_clear(acc);
-                if (l >= L || ((seen >> l) & 1)) {
-                    bad = true;
-                    cur = -1;
-                } else {
-                    seen |= 1ull << l;
-                    cur = l;
-                }
+                if (t - h >= WAVE) ring_drain(q, h, t, WAVE, A.lv, L);
             }
-            if (l >= 0 && !bad) run_add(acc, vx[j], vy[j], ve[j]);
-            if (t - h >= WAVE) ring_drain(q, h, t, WAVE, A.lv, L);
+            run_add(acc, vx[j], vy[j], ve[j], l >= 0 && !bad);
         }
         if (work) pos = bad ? end : (b0 + BLK < end ? b0 + BLK : end);
     }
