@@ -244,6 +244,8 @@ def bench_shapes(args):
     torch.cuda.synchronize()
     w1_ms = ev0.elapsed_time(ev1) / args.steps
     w1_bytes = 2 * 2 * n * cols * 4                   # two passes (range, histogram) over both
+    tr = [prof_summary.traffic_if_current(prof_dir, k, wl) for k in ("w1_stats", "w1_hist")]
+    w1_traffic = None if None in tr else 2 * (tr[0] + tr[1])   # each kernel runs once per sample
     gm_h = gm.cpu().numpy()
     line = {
         "metric": "shower-shape-variable showers/s (1 MI355X)",
@@ -258,7 +260,7 @@ def bench_shapes(args):
                            "achieved": round(w1_bytes / (w1_ms / 1e3) / 1e9, 1),
                            "peak": PEAK_HBM_GBS, "unit": "GB/s",
                            "frac": round(w1_bytes / (w1_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
-                           "traffic": None, "ms": round(w1_ms, 4), "alg_bytes": w1_bytes,
+                           "traffic": w1_traffic, "ms": round(w1_ms, 4), "alg_bytes": w1_bytes,
                            "bins": args.bins, "columns": cols},
         "mean_discrepancy_by_variable": {k: round(float(v), 5) for k, v in
                                          zip(SH.LAYER_VARS + SH.SHOWER_VARS, gm_h)},
