@@ -36,6 +36,13 @@
  *     angle of the two daughters is theta; omega is measured in the frame
  *     obtained by the rotation that takes +z to d (Rodrigues), applied to +x
  *     and +y.
+ * With kinematics = ORACLE_KIN_LITERAL the motion is Algorithm 1 as printed
+ * instead: a particle has a lateral position only (the primary starts at its
+ * impact point and moves along +z, whatever its angles); a pass keeps the
+ * position; a split places the daughters at p + dz*(sin(theta/2 + eps),
+ * cos(theta/2 + eps)) and p - dz*(same), the first one carrying E(theta/2 +
+ * eps)/theta, with eps = (f - 1/2)*theta; omega is drawn and not used.  The
+ * daughters are displaced at the split and reach the next plane there.
  */
 #include "supa_oracle.h"
 
@@ -244,6 +251,22 @@ static void split_particle(const oracle_geometry *g, const derived *dv, const pa
 
     *a = *p;
     *b = *p;
+    if (g->kinematics == ORACLE_KIN_LITERAL) {
+        /* Algorithm 1 as printed: one displacement, + for the first daughter, -
+           for the second; directions stay along +z */
+        double eps = (f - 0.5) * theta;
+        double ux = g->dz * sin(theta / 2.0 + eps), uy = g->dz * cos(theta / 2.0 + eps);
+        a->x = p->x + ux;
+        a->y = p->y + uy;
+        b->x = p->x - ux;
+        b->y = p->y - uy;
+        a->e = ea;
+        b->e = eb;
+        a->path = 2 * p->path;
+        b->path = 2 * p->path + 1;
+        a->gen = b->gen = p->gen + 1;
+        return;
+    }
     a->dx = cos(aa) * dx + sin(aa) * nx;
     a->dy = cos(aa) * dy + sin(aa) * ny;
     a->dz = cos(aa) * dz + sin(aa) * nz;
@@ -282,6 +305,11 @@ static int simulate_one(const oracle_geometry *g, const derived *dv, int64_t i,
     p.dx = sin(alpha) * cos(beta);
     p.dy = sin(alpha) * sin(beta);
     p.dz = cos(alpha);
+    if (g->kinematics == ORACLE_KIN_LITERAL) {   /* lateral position only */
+        p.dx = 0.0;
+        p.dy = 0.0;
+        p.dz = 1.0;
+    }
     p.e = e0;
     p.path = 1;
     p.gen = 0;
@@ -383,6 +411,7 @@ static int validate(const oracle_geometry *g)
     if (g->frac_bits < 0 || g->frac_bits > 31) return ORACLE_ERR_INVALID_ARG;
     if (!(g->frac_lo >= 0.0 && g->frac_lo <= g->frac_hi && g->frac_hi <= 1.0)) return ORACLE_ERR_INVALID_ARG;
     if (g->angle_mode < ORACLE_ANGLE_FIXED || g->angle_mode > ORACLE_ANGLE_RAYLEIGH) return ORACLE_ERR_INVALID_ARG;
+    if (g->kinematics != ORACLE_KIN_3D && g->kinematics != ORACLE_KIN_LITERAL) return ORACLE_ERR_INVALID_ARG;
     if (!isfinite(g->angle_a) || !isfinite(g->angle_b)) return ORACLE_ERR_INVALID_ARG;
     for (int32_t k = 0; k < g->n_planes; ++k) {
         double ps = g->p_stop ? g->p_stop[k] : 0.0;

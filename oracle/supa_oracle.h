@@ -23,6 +23,7 @@ extern "C" {
 #endif
 
 enum { ORACLE_ANGLE_FIXED = 0, ORACLE_ANGLE_UNIFORM = 1, ORACLE_ANGLE_RAYLEIGH = 2 };
+enum { ORACLE_KIN_3D = 0, ORACLE_KIN_LITERAL = 1 };
 enum { ORACLE_OK = 0, ORACLE_ERR_INVALID_ARG = 1, ORACLE_ERR_RANGE = 2, ORACLE_ERR_NOMEM = 6 };
 enum { ORACLE_HIT_STOP = 0, ORACLE_HIT_CUT = 1 };
 
@@ -38,6 +39,7 @@ typedef struct {
     double angle_a, angle_b;       /* FIXED(a), UNIFORM(a,b), RAYLEIGH(sigma=a)    */
     double frac_lo, frac_hi;       /* energy fraction f ~ U(frac_lo, frac_hi)      */
     int32_t frac_bits;             /* fixed-point fractional bits of energies      */
+    int32_t kinematics;            /* ORACLE_KIN_*                                 */
 } oracle_geometry;
 
 /* Growable result arrays, all owned by the oracle; free with oracle_free. */

@@ -21,6 +21,7 @@ import numpy as np
 from . import build_oracle
 
 ANGLE_MODES = {"fixed": 0, "uniform": 1, "rayleigh": 2}
+KINEMATICS = {"3d": 0, "literal": 1}
 ERRORS = {1: "invalid argument", 2: "energy out of range", 6: "out of memory"}
 
 _lib = None
@@ -39,6 +40,7 @@ class _Geometry(C.Structure):
         ("angle_a", C.c_double), ("angle_b", C.c_double),
         ("frac_lo", C.c_double), ("frac_hi", C.c_double),
         ("frac_bits", C.c_int32),
+        ("kinematics", C.c_int32),
     ]
 
 
@@ -112,7 +114,8 @@ def simulate(geom: dict, e0, polar, azimuth, seed: int, x0=None, y0=None,
 
     geom keys: n_planes, z_first, dz, layer_of_plane (opt), p_stop (opt),
     p_split (opt), e_cut, angle_mode ('fixed'|'uniform'|'rayleigh'), angle_a,
-    angle_b, frac_lo, frac_hi, frac_bits.
+    angle_b, frac_lo, frac_hi, frac_bits, kinematics ('3d' (default) |
+    'literal').
     """
     e0 = np.ascontiguousarray(np.asarray(e0, dtype=np.float32))
     n = e0.shape[0]
@@ -145,6 +148,7 @@ def simulate(geom: dict, e0, polar, azimuth, seed: int, x0=None, y0=None,
     g.frac_lo = float(geom.get("frac_lo", 0.0))
     g.frac_hi = float(geom.get("frac_hi", 1.0))
     g.frac_bits = int(geom.get("frac_bits", 21))
+    g.kinematics = KINEMATICS[geom.get("kinematics", "3d")]
 
     res = _Result()
     ptr = lambda a: None if a is None else a.ctypes.data

@@ -408,3 +408,82 @@ def test_images_match_histogram2d():
                                      range=[[y0, y1], [x0, x1]],
                                      weights=r["hit_e"][m].astype(np.float64))
             np.testing.assert_array_equal(img[s, layer].astype(np.float64), H)
+
+
+# --------------------------------------------------------------------------
+# Literal kinematics: Algorithm 1 as printed (lateral position only, one
+# displacement +-dz (sin(theta/2 + eps), cos(theta/2 + eps)) per split)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("polar,az", [(0.0, 0.0), (0.35, 2.1)])
+def test_supav1_literal_points_on_a_line(polar, az):
+    """SUPAv1 with eps = 0: after seven splits each point sits at m dz (sin(pi/48),
+    cos(pi/48)) with m the sum of seven signs, so m = -7, -5, ..., 7 with
+    binomial multiplicities C(7, (m + 7)/2); the impact angles play no part."""
+    g = dict(supav1_geom(), kinematics="literal")
+    n = 4
+    r = O.simulate(g, [65.0] * n, [polar] * n, [az] * n, seed=9, x0=[0.25] * n, y0=[-0.5] * n)
+    assert (r["counts"][:, 1] == 128).all() and (r["hit_e"] == 65 * 2 ** 14).all()
+    u = np.array([math.sin(math.pi / 48), math.cos(math.pi / 48)])
+    for sid in range(n):
+        h = r["hit_sid"] == sid
+        d = np.stack([r["hit_x"][h] - 0.25, r["hit_y"][h] + 0.5], 1)
+        m = d @ u                                        # coordinate along the line
+        assert np.abs(d - np.outer(m, u)).max() < 1e-12  # nothing across it
+        mi = np.rint(m).astype(int)
+        assert np.abs(m - mi).max() < 1e-12
+        vals, cnt = np.unique(mi, return_counts=True)
+        assert list(vals) == list(range(-7, 8, 2))
+        assert list(cnt) == [math.comb(7, (v + 7) // 2) for v in vals]
+
+
+def test_literal_hand_traced_single_split_and_pass():
+    """One split at plane 0, a pass at plane 1, a stop at plane 2: the first
+    daughter (energy fraction f = w1/2^32) lands at p + dz (sin(theta/2 + eps),
+    cos(theta/2 + eps)), eps = (f - 1/2) theta, the second at p - the same, and
+    the pass leaves both where they were."""
+    dz = 0.7
+    g = geom(n_planes=3, dz=dz, z_first=1.0, p_split=[1.0, 0.0, 0.0], p_stop=[0.0, 0.0, 1.0],
+             e_cut=0.0, kinematics="literal")
+    seed, n = 31, 40
+    x0 = np.linspace(-1, 1, n)
+    r = O.simulate(g, [1.0] * n, [0.2] * n, [1.0] * n, seed=seed, x0=x0, y0=[0.5] * n)
+    assert (r["counts"][:, 1] == 2).all()
+    for sid in range(n):
+        w = O.philox4x32_10(seed, (0, sid, 1, 0))
+        f = w[1] / TWO32
+        theta = 0.1 * math.sqrt(-2.0 * math.log((w[2] + 0.5) / TWO32))
+        eps = (f - 0.5) * theta
+        ux, uy = dz * math.sin(theta / 2 + eps), dz * math.cos(theta / 2 + eps)
+        h = np.nonzero(r["hit_sid"] == sid)[0]
+        ka = h[r["hit_key"][h] == 2][0]
+        kb = h[r["hit_key"][h] == 3][0]
+        assert r["hit_e"][ka] == (2 ** S * w[1]) >> 32
+        assert abs(r["hit_x"][ka] - (float(np.float32(x0[sid])) + ux)) < 1e-12
+        assert abs(r["hit_y"][ka] - (0.5 + uy)) < 1e-12
+        assert abs(r["hit_x"][kb] - (float(np.float32(x0[sid])) - ux)) < 1e-12
+        assert abs(r["hit_y"][kb] - (0.5 - uy)) < 1e-12
+
+
+def test_literal_keeps_topology_and_energies():
+    """The choices and energies come from the counters alone, so the two
+    kinematics give the same tree, counts, energies and layers whenever no
+    particle turns away from +z in the 3-D reading."""
+    rng = np.random.default_rng(12)
+    N = 12
+    g = geom(n_planes=N, p_split=list(rng.uniform(0.3, 0.8, N)), p_stop=list(rng.uniform(0, 0.2, N)),
+             e_cut=0.2, angle_mode="uniform", angle_a=math.pi / 32, angle_b=math.pi / 16,
+             frac_lo=0.25, frac_hi=0.75, layer_of_plane=[-1] * 3 + [0] * 5 + [1] * 4)
+    n = 60
+    e0 = rng.uniform(1, 50, n)
+    a = O.simulate(g, e0, [0.1] * n, [0.3] * n, seed=4)
+    b = O.simulate(dict(g, kinematics="literal"), e0, [0.1] * n, [0.3] * n, seed=4)
+    assert (a["counts"][:, 5] == 0).all()
+    for k in ("counts", "ledger", "hit_key", "hit_e", "hit_layer", "hit_plane", "node_key", "node_e",
+              "node_parent"):
+        np.testing.assert_array_equal(a[k], b[k])
+    assert not np.allclose(a["hit_x"], b["hit_x"])
+
+
+def test_invalid_kinematics_rejected():
+    with pytest.raises(KeyError):
+        O.simulate(geom(n_planes=2, kinematics="other"), [1.0], [0.0], [0.0], seed=1)
