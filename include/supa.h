@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define SUPA_ABI_VERSION 1
+#define SUPA_ABI_VERSION 2
 
 typedef enum supa_status {
     SUPA_OK = 0,
@@ -63,6 +63,20 @@ typedef enum supa_status {
 } supa_status;
 
 enum { SUPA_ANGLE_FIXED = 0, SUPA_ANGLE_UNIFORM = 1, SUPA_ANGLE_RAYLEIGH = 2 };
+
+/* Kinematics (supa_geometry.kinematics).
+ *   SUPA_KIN_3D       particles fly in straight lines between planes and a
+ *                     split turns the two daughters away from the parent's
+ *                     direction (the reading of the section "Propagation
+ *                     Model" described above);
+ *   SUPA_KIN_LITERAL  Algorithm 1 as printed: a particle has a lateral
+ *                     position only (the primary starts at its impact point,
+ *                     its angles are not used); a pass keeps the position; a
+ *                     split places the daughters at p + dz (sin(theta/2 + eps),
+ *                     cos(theta/2 + eps)) and p - dz (same), the first one
+ *                     carrying the energy fraction f = 1/2 + eps/theta, so
+ *                     theta/2 + eps = f theta; the azimuth is not used. */
+enum { SUPA_KIN_3D = 0, SUPA_KIN_LITERAL = 1 };
 
 /* Output selection bits for supa_geometry.outputs. */
 enum {
@@ -97,6 +111,7 @@ typedef struct supa_geometry {
     double img_x0, img_x1;          /* region of interest [x0, x1) x [y0, y1),         */
     double img_y0, img_y1;          /* cells half-open; x1 > x0, y1 > y0               */
     uint32_t outputs;               /* SUPA_OUT_* bitmask                             */
+    int32_t kinematics;             /* SUPA_KIN_*                                     */
 } supa_geometry;
 
 /* Opaque context: the parameters, their device copies and library scratch. */

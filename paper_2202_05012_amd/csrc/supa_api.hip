@@ -20,7 +20,7 @@
 namespace supa {
 hipError_t launch_zero_counters(unsigned long long *ctr, hipStream_t s);
 hipError_t launch_note_chunks(const unsigned long long *ctr, unsigned long long *sub, hipStream_t s);
-hipError_t launch_propagate(const Params &P, int blocks, hipStream_t s);
+hipError_t launch_propagate(const Params &P, bool literal, int blocks, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t s);
 size_t propagate_lds_bytes(int pool_cap);
@@ -135,6 +135,10 @@ static supa_status validate(const supa_geometry *g, std::string &why) {
         return SUPA_ERR_INVALID_ARG;
     }
     if (!is_fin(g->angle_a) || !is_fin(g->angle_b)) { why = "angles must be finite"; return SUPA_ERR_INVALID_ARG; }
+    if (g->kinematics != SUPA_KIN_3D && g->kinematics != SUPA_KIN_LITERAL) {
+        why = "unknown kinematics";
+        return SUPA_ERR_INVALID_ARG;
+    }
     if (!(g->frac_lo >= 0 && g->frac_lo <= g->frac_hi && g->frac_hi <= 1)) {
         why = "need 0 <= frac_lo <= frac_hi <= 1";
         return SUPA_ERR_INVALID_ARG;
@@ -534,7 +538,7 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
             HIP_TRY(c, supa::launch_cost_order(b->e0 + o, (int)nj, P.e_scale, L.d_ohist, L.d_order + o,
                                                c->n_cu, s_main));
         if (timed) HIP_TRY(c, hipEventRecord(c->ev_prop[j][0], s_main));
-        HIP_TRY(c, supa::launch_propagate(Pj, (int)L.waves, s_main));
+        HIP_TRY(c, supa::launch_propagate(Pj, c->g.kinematics == SUPA_KIN_LITERAL, (int)L.waves, s_main));
         if (L.tree) HIP_TRY(c, supa::launch_note_chunks(c->d_ctr, sub_ctr(j), s_main));
         // the second stream waits on this event (none inside a capture, where
         // both are one stream)

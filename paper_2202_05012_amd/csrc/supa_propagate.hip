@@ -55,6 +55,7 @@ struct Daughters {
 // from w1, opening angle theta from w2, azimuth omega from w3; the daughters
 // turn by theta*(1-f) and theta*f to opposite sides of the plane through the
 // parent direction at azimuth omega (frame: rotation taking +z to d).
+template <bool LIT>
 __device__ __forceinline__ Daughters split_particle(const Params &P, float tx, float ty,
                                                     uint32_t e, uint4 w, uint32_t f_lo, uint64_t f_w) {
     Daughters D;
@@ -72,6 +73,24 @@ __device__ __forceinline__ Daughters split_particle(const Params &P, float tx, f
     } else {
         // Rayleigh(sigma): sigma * sqrt(-2 ln u)
         theta = P.angle_a * __builtin_amdgcn_sqrtf(2.0f * neg_log_unit(w.z));
+    }
+    if constexpr (LIT) {
+        // Algorithm 1 as printed: the daughters are displaced by
+        // +-dz (sin(theta/2 + eps), cos(theta/2 + eps)), theta/2 + eps = f theta;
+        // the flight to the next plane applies it as slopes, which are not kept
+        float sl, cl;
+        const float ang = theta * f;
+        if (__ballot(ang > 0.785398163f) == 0ull) {
+            sincos_poly(ang, &sl, &cl);
+        } else {
+            sincos_f32(ang, &sl, &cl);
+        }
+        D.txa = sl;
+        D.tya = cl;
+        D.txb = -sl;
+        D.tyb = -cl;
+        D.fwd_a = D.fwd_b = true;
+        return D;
     }
     // omega = 2 pi u(w3), taken as pi*(signed w3 + 1/2)/2^31 (same angle mod 2 pi)
     float so, co;
@@ -223,9 +242,10 @@ struct SlotSums {
     }
 };
 
-// TREE: node records; KEYS: path ids with hit and node records (compile-time,
-// so that neither flag occupies a scalar register through the loop)
-template <bool TREE, bool KEYS, int PC>
+// TREE: node records; KEYS: path ids with hit and node records; LIT: literal
+// Algorithm 1 kinematics (compile-time, so that no flag occupies a scalar
+// register through the loop)
+template <bool TREE, bool KEYS, int PC, bool LIT>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) supa_propagate(Params P) {
     extern __shared__ uint32_t lds[];
     const uint32_t lane = lane_id();
@@ -412,9 +432,10 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
                     w_i = i;
                     w_ok = ok ? 1 : 0;
                     w_e = ok ? (uint32_t)rintf(sc) : 0u;
-                    w_fwd = cp > 0.0f ? 1 : 0;
-                    w_tx = tpol * ca;
-                    w_ty = tpol * sa;
+                    // literal kinematics: lateral position only, no drift
+                    w_fwd = (cp > 0.0f || LIT) ? 1 : 0;
+                    w_tx = LIT ? 0.0f : tpol * ca;
+                    w_ty = LIT ? 0.0f : tpol * sa;
                     w_x = x0p ? x0p[i] : 0.0f;
                     w_y = y0p ? y0p[i] : 0.0f;
                 }
@@ -523,7 +544,7 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             D.fwd_a = D.fwd_b = false;
             D.ea = D.eb = 0;
             D.txa = D.tya = D.txb = D.tyb = 0.f;
-            if (is_split) D = split_particle(P, p.tx, p.ty, p.e, w, f_lo, f_w);
+            if (is_split) D = split_particle<LIT>(P, p.tx, p.ty, p.e, w, f_lo, f_w);
             // outgoing particles: a = first daughter or the passer, b = second daughter
             const bool has_a = is_split || is_pass, has_b = is_split;
             const uint32_t ea = is_split ? D.ea : p.e, eb = D.eb;
@@ -659,14 +680,17 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             // survivors go back on the pool, bound for plane k+1
             const int pos = top + (int)lanes_below(mpa) + (int)lanes_below(mpb);
             const uint32_t ks1 = (uint32_t)(k + 1) | ((uint32_t)slot << 8);
+            // (with literal kinematics the displacement was the flight: no slope is kept)
+            const float sxa = LIT ? 0.0f : txa, sya = LIT ? 0.0f : tya;
+            const float sxb = LIT ? 0.0f : D.txb, syb = LIT ? 0.0f : D.tyb;
             if (push_a) {
-                const Entry q = is_split ? Entry{xa, ya, txa, tya, ea, (uint32_t)pa, (uint32_t)(pa >> 32),
+                const Entry q = is_split ? Entry{xa, ya, sxa, sya, ea, (uint32_t)pa, (uint32_t)(pa >> 32),
                                                  node_a, ks1}
-                                         : Entry{xa, ya, txa, tya, ea, p.lo, p.hi, p.node, ks1};
+                                         : Entry{xa, ya, sxa, sya, ea, p.lo, p.hi, p.node, ks1};
                 pool_store(pos, q);
             }
             if (push_b) {
-                const Entry q{xb, yb, D.txb, D.tyb, eb, (uint32_t)pa | 1u, (uint32_t)(pa >> 32),
+                const Entry q{xb, yb, sxb, syb, eb, (uint32_t)pa | 1u, (uint32_t)(pa >> 32),
                               node_a + 1, ks1};
                 pool_store(pos + (push_a ? 1 : 0), q);
             }
@@ -761,24 +785,29 @@ size_t propagate_lds_bytes(int pool_cap) {
     return (size_t)lds_words(pool_cap) * 4;
 }
 
-template <bool TREE, bool KEYS>
+template <bool TREE, bool KEYS, bool LIT>
 static hipError_t launch_pc(const Params &P, int blocks, size_t lds, hipStream_t s) {
     switch (P.pool_cap) {
-    case 128: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 128>), dim3(blocks), dim3(WAVE), lds, s, P); break;
-    case 256: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 256>), dim3(blocks), dim3(WAVE), lds, s, P); break;
-    case 512: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 512>), dim3(blocks), dim3(WAVE), lds, s, P); break;
-    case 1024: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 1024>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 128: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 128, LIT>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 256: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 256, LIT>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 512: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 512, LIT>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 1024: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 1024, LIT>), dim3(blocks), dim3(WAVE), lds, s, P); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_propagate(const Params &P, int blocks, hipStream_t s) {
-    const size_t lds = propagate_lds_bytes(P.pool_cap);
+template <bool LIT>
+static hipError_t launch_kin(const Params &P, int blocks, size_t lds, hipStream_t s) {
     const bool tree = (P.outputs & 4u) != 0;
     if (tree)
-        return P.keys ? launch_pc<true, true>(P, blocks, lds, s) : launch_pc<true, false>(P, blocks, lds, s);
-    return P.keys ? launch_pc<false, true>(P, blocks, lds, s) : launch_pc<false, false>(P, blocks, lds, s);
+        return P.keys ? launch_pc<true, true, LIT>(P, blocks, lds, s) : launch_pc<true, false, LIT>(P, blocks, lds, s);
+    return P.keys ? launch_pc<false, true, LIT>(P, blocks, lds, s) : launch_pc<false, false, LIT>(P, blocks, lds, s);
+}
+
+hipError_t launch_propagate(const Params &P, bool literal, int blocks, hipStream_t s) {
+    const size_t lds = propagate_lds_bytes(P.pool_cap);
+    return literal ? launch_kin<true>(P, blocks, lds, s) : launch_kin<false>(P, blocks, lds, s);
 }
 
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,

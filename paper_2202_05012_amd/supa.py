@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsupa.so")
 
 ANGLE_MODES = {"fixed": 0, "uniform": 1, "rayleigh": 2}
+KINEMATICS = {"3d": 0, "literal": 1}
 OUT_HITS, OUT_IMAGES, OUT_TREE, OUT_KEYS = 1, 2, 4, 8
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "RANGE", 3: "CAPACITY", 4: "DEVICE", 5: "STATE",
           6: "NOMEM"}
@@ -42,6 +43,7 @@ class Geometry(C.Structure):
         ("img_x0", C.c_double), ("img_x1", C.c_double),
         ("img_y0", C.c_double), ("img_y1", C.c_double),
         ("outputs", C.c_uint32),
+        ("kinematics", C.c_int32),
     ]
 
 
@@ -156,6 +158,7 @@ def make_geometry(geom: dict, outputs: int):
     g.img_y0 = float(geom.get("img_y0", 0.0))
     g.img_y1 = float(geom.get("img_y1", 0.0))
     g.outputs = outputs
+    g.kinematics = KINEMATICS[geom.get("kinematics", "3d")]
     return g, keep
 
 

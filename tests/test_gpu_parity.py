@@ -389,3 +389,34 @@ def test_graph_replays_match_oracle():
     torch.cuda.synchronize()
     parity.check_all(parity.to_numpy(out), refb, geom, tree=True)
     g.close()
+
+
+# --------------------------------------------------------------------------
+# Literal Algorithm 1 kinematics and the paper's presets
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("kin", ["3d", "literal"])
+def test_supav1_preset_gpu(kin):
+    from paper_2202_05012_amd import presets
+    g = presets.supa(1, kinematics=kin, image=(16, 16, -8.0, 8.0, -8.0, 8.0))
+    e0, pol, az = presets.incident(64)
+    gpu, ref = check(g, ALL, e0, pol, az, seed=21)
+    assert (gpu["counts"][:, 1] == 128).all()
+
+
+@pytest.mark.parametrize("trial", range(4))
+def test_random_parameters_literal(trial):
+    rng = np.random.default_rng(300 + trial)
+    N = int(rng.integers(1, 30))
+    geom = dict(random_geometry(rng, N, wide=trial >= 2), kinematics="literal")
+    if trial == 3:
+        geom.update(angle_mode="fixed", angle_a=1.5)      # f theta beyond pi/4: the wide sincos
+    n = 120
+    e0 = rng.uniform(0, 20, n)
+    e0[:2] = [0.0, geom["e_cut"]]
+    pol = rng.uniform(0, 3.0, n)                          # not used by this kinematics
+    az = rng.uniform(-7, 7, n)
+    x0 = rng.uniform(-1, 1, n)
+    y0 = rng.uniform(-1, 1, n)
+    gpu, ref = check(geom, ALL, e0, pol, az, seed=int(rng.integers(0, 2 ** 63)), x0=x0, y0=y0,
+                     base=int(rng.integers(0, 2 ** 31)))
+    assert ref["counts"][:, 5].sum() == 0                 # nothing turns back
