@@ -59,7 +59,8 @@ def _rows(d: str, suffix: str):
     files = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
     if not files:
         raise FileNotFoundError(f"no *{suffix} under {d}")
-    with open(files[0]) as fh:
+    newest = max(files, key=os.path.getmtime)      # a reused directory keeps older runs
+    with open(newest) as fh:
         return list(csv.DictReader(fh))
 
 
