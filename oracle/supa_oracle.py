@@ -240,3 +240,27 @@ def images(res: dict, n_layers: int, nx: int, ny: int, x0: float, x1: float,
     local = res["hit_sid"][ok].astype(np.int64) - res["shower_id_base"]
     np.add.at(out, (local, layer[ok], iy[ok], ix[ok]), res["hit_e"][ok].astype(np.uint64))
     return out
+
+
+def grid_images(n: int, sid, layer, x, y, e_int, grids) -> np.ndarray:
+    """Per shower, the concatenation over layers of [ny_l][nx_l] images of
+    summed integer energies (uint64), each layer on its own grid
+    grids[l] = (nx, ny, x0, x1, y0, y1) -- the appendix "Downsampling": a
+    region of interest per layer and a number of cells in each direction.
+    sid in [0, n); hits of layer -1 (or >= len(grids)) and hits outside their
+    layer's region are dropped.  Shape (n, sum_l nx_l * ny_l)."""
+    sid = np.asarray(sid, np.int64)
+    layer = np.asarray(layer)
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    e_int = np.asarray(e_int, np.uint64)
+    cells = [int(g[0]) * int(g[1]) for g in grids]
+    off = np.concatenate([[0], np.cumsum(cells)]).astype(np.int64)
+    out = np.zeros((n, int(off[-1])), dtype=np.uint64)
+    for l, (nx, ny, x0, x1, y0, y1) in enumerate(grids):
+        sel = layer == l
+        ix = bin_index(x[sel], x0, x1, int(nx))
+        iy = bin_index(y[sel], y0, y1, int(ny))
+        ok = (ix >= 0) & (iy >= 0)
+        np.add.at(out, (sid[sel][ok], off[l] + iy[ok] * int(nx) + ix[ok]), e_int[sel][ok])
+    return out

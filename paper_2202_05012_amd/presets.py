@@ -68,3 +68,19 @@ def incident(n: int):
     """Initial conditions of every configuration: E0 = 65, perpendicular
     incidence (polar angle 0), impact point (0, 0)."""
     return [E0] * n, [0.0] * n, [0.0] * n
+
+
+# CaloGAN's read-out (section "Downsampling"/appendix: 3 x 96, 12 x 12 and
+# 12 x 6 cells for layers 0, 1, 2 at the "1x" resolution, multiples at 2x
+# and 3x).  Rows x columns = phi (y) x eta (x) cells; the three layers cover
+# the same square region of interest, as CaloGAN's layers do.
+CALOGAN_CELLS = [(96, 3), (12, 12), (6, 12)]     # (nx, ny) per layer at 1x
+
+
+def calogan_grids(scale: int = 1, half_width: float = 5.0):
+    """Per-layer grids (nx, ny, x0, x1, y0, y1) of the three CaloGAN-like
+    layers at resolution `scale`x over [-half_width, half_width)^2."""
+    if scale < 1:
+        raise ValueError("scale >= 1")
+    w = float(half_width)
+    return [(nx * scale, ny * scale, -w, w, -w, w) for nx, ny in CALOGAN_CELLS]

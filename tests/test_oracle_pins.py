@@ -487,3 +487,32 @@ def test_literal_keeps_topology_and_energies():
 def test_invalid_kinematics_rejected():
     with pytest.raises(KeyError):
         O.simulate(geom(n_planes=2, kinematics="other"), [1.0], [0.0], [0.0], seed=1)
+
+
+def test_grid_images_match_histogram2d_per_layer():
+    """Per-layer grids (the appendix "Downsampling": a region and a cell count
+    per direction for each layer): every layer's image equals numpy's
+    histogram2d of that layer's points, weighted by their energies."""
+    rng = np.random.default_rng(17)
+    n, m = 5, 4000
+    grids = [(96, 3, -4.0, 4.0, -4.0, 4.0), (12, 12, -3.0, 5.0, -4.0, 4.0), (6, 12, -4.0, 4.0, -2.0, 2.5)]
+    sid = rng.integers(0, n, m)
+    layer = rng.integers(-1, 3, m)
+    x = rng.normal(0, 2.5, m)
+    y = rng.normal(0, 2.5, m)
+    e = rng.integers(1, 2 ** 30, m).astype(np.uint64)
+    img = O.grid_images(n, sid, layer, x, y, e, grids)
+    off = 0
+    for l, (nx, ny, x0, x1, y0, y1) in enumerate(grids):
+        for s in range(n):
+            k = (sid == s) & (layer == l)
+            h, _, _ = np.histogram2d(y[k], x[k], bins=[ny, nx], range=[[y0, y1], [x0, x1]],
+                                     weights=e[k].astype(np.float64))
+            # histogram2d closes the last bin on the right; no point sits on an edge here
+            np.testing.assert_array_equal(img[s, off:off + nx * ny].reshape(ny, nx), h.astype(np.uint64))
+        off += nx * ny
+    assert img.shape == (n, off)
+    inside = np.zeros(m, bool)
+    for l, g in enumerate(grids):
+        inside |= (layer == l) & (x >= g[2]) & (x < g[3]) & (y >= g[4]) & (y < g[5])
+    assert img.sum() == e[inside].sum()              # nothing lost or counted twice
