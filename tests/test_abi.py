@@ -92,3 +92,21 @@ def test_shape_entry_points_reject_bad_arguments_on_the_host():
     assert L.supa_w1_normalized(*args(ldr=6)) == 1
     assert L.supa_w1_normalized(*args(wsb=need - 1)) == 1
     assert L.supa_w1_normalized(*args(g=fake, ng=0)) == 1
+
+
+def test_grid_entry_points_reject_bad_arguments_on_the_host():
+    import ctypes as C
+    from paper_2202_05012_amd import grids as GR
+    L = GR._lib()
+    assert GR.cells([(96, 3, -5, 5, -5, 5), (12, 12, -5, 5, -5, 5), (6, 12, -5, 5, -5, 5)]) == 504
+    assert GR.cells([(0, 3, -5, 5, -5, 5)]) == -1
+    assert GR.cells([(3, 3, 5, -5, -5, 5)]) == -1
+    fake = C.c_void_p(4096)
+    big = GR._grids([(128, 128, 0.0, 1.0, 0.0, 1.0)])
+    assert L.supa_bin_grids(None, 10, 1, C.cast(big, C.c_void_p), 21, fake, fake, 1, 100, fake, fake,
+                            fake, fake, fake) == 1
+    ok = GR._grids([(8, 8, 0.0, 1.0, 0.0, 1.0)])
+    assert L.supa_bin_grids(None, 10, 1, C.cast(ok, C.c_void_p), 40, fake, fake, 1, 100, fake, fake,
+                            fake, fake, fake) == 1
+    assert L.supa_bin_grids(None, 10, 17, C.cast(ok, C.c_void_p), 21, fake, fake, 1, 100, fake, fake,
+                            fake, fake, fake) == 1

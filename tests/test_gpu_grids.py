@@ -1,0 +1,92 @@
+"""GPU parity of per-layer grid images (include/supa_grids.h) with the
+oracle's grid_images: bit-exact on seeded clouds fed to both (integer cell
+sums, the same double-precision cell formula), and on simulated showers
+exact except cells next to a hit lying within the coordinate tolerance of a
+cell edge (tests/parity.py)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import supa_oracle as O
+from paper_2202_05012_amd import grids as GR, presets, supa, workloads
+from tests import parity
+from tests.test_gpu_shapes import cloud
+
+pytestmark = pytest.mark.gpu
+S = 21
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def want_images(n, sid, lay, x, y, e, grids):
+    keep = sid >= 0
+    q = np.rint(e[keep].astype(np.float64) * 2.0 ** S).astype(np.uint64)
+    img = O.grid_images(n, sid[keep], lay[keep], x[keep], y[keep], q, grids)
+    return img.astype(np.float64).astype(np.float32) * np.float32(2.0 ** -S)
+
+
+@pytest.mark.parametrize("scale", [1, 2, 3])
+def test_calogan_grids_on_seeded_clouds(scale):
+    rng = np.random.default_rng(40 + scale)
+    n = 500
+    off, cnt, X, Y, E, LAY, sid = cloud(rng, n, 5, centre=1.5)
+    # energies on the simulator's lattice (multiples of 2^-21), some too large for float
+    E = (np.rint(E.astype(np.float64) * 2.0 ** S) * 2.0 ** -S).astype(np.float32)
+    E[::97] = np.float32(123.456789)
+    grids = presets.calogan_grids(scale, half_width=4.0)
+    got = GR.bin_grids(_t(off), _t(cnt), _t(X), _t(Y), _t(E), _t(LAY), grids, S).cpu().numpy()
+    want = want_images(n, sid, LAY, X, Y, E, grids)
+    assert got.shape == want.shape == (n, GR.cells(grids))
+    np.testing.assert_array_equal(got, want)
+
+
+def test_uneven_regions_and_maximum_cells():
+    rng = np.random.default_rng(7)
+    n = 300
+    off, cnt, X, Y, E, LAY, sid = cloud(rng, n, 3, centre=2.0)
+    grids = [(64, 64, -3.0, 3.5, -2.0, 4.0), (64, 48, -1.0, 1.0, -5.0, 5.0), (32, 32, 0.0, 6.0, -6.0, 0.5)]
+    assert GR.cells(grids) == 8192                          # the maximum
+    got = GR.bin_grids(_t(off), _t(cnt), _t(X), _t(Y), _t(E), _t(LAY), grids, S).cpu().numpy()
+    np.testing.assert_array_equal(got, want_images(n, sid, LAY, X, Y, E, grids))
+    with pytest.raises(supa.SupaError):
+        GR.bin_grids(_t(off), _t(cnt), _t(X), _t(Y), _t(E), _t(LAY), grids + [(1, 1, 0.0, 1.0, 0.0, 1.0)])
+    z = torch.zeros(0, dtype=torch.int64, device="cuda")
+    assert GR.bin_grids(z, z.int(), _t(X), _t(Y), _t(E), _t(LAY), grids).shape == (0, 8192)
+
+
+@pytest.mark.parametrize("scale", [1, 3])
+def test_simulated_showers_on_calogan_grids(scale):
+    """GPU simulation + GPU binning against oracle simulation + oracle binning
+    on a three-layer read-out of the 20-plane workload."""
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = dict(workloads.geometry(w), layer_of_plane=[-1] * 2 + [0] * 4 + [1] * 8 + [2] * 6)
+    n = 200
+    e0, pol, az = workloads.initial_conditions(w, n)
+    grids = presets.calogan_grids(scale, half_width=3.0)
+    sim = supa.Simulator(geom, supa.OUT_HITS)
+    out = sim.simulate(_t(e0), _t(pol), _t(az), seed=w.seed)
+    got = GR.simulator_grids(out, grids, S).cpu().numpy()
+    ref = O.simulate(geom, e0, pol, az, seed=w.seed)
+    sid = ref["hit_sid"] - ref["shower_id_base"]
+    e_f = (ref["hit_e"].astype(np.float32) * np.float32(2.0 ** -S))       # the float the GPU holds
+    want = want_images(n, sid, ref["hit_layer"], ref["hit_x"], ref["hit_y"], e_f, grids)
+    # cells that a hit within the coordinate tolerance of an edge may reach
+    mask = np.zeros(got.shape, bool)
+    offs = np.concatenate([[0], np.cumsum([g[0] * g[1] for g in grids])])
+    rr = np.maximum(np.hypot(ref["hit_x"], ref["hit_y"]), 1.0)
+    for l, (nx, ny, x0, x1, y0, y1) in enumerate(grids):
+        fx = (ref["hit_x"] - x0) * nx / (x1 - x0)
+        fy = (ref["hit_y"] - y0) * ny / (y1 - y0)
+        near = (np.abs(fx - np.rint(fx)) <= parity.COORD_RTOL * rr * 2 * nx / (x1 - x0)) | \
+               (np.abs(fy - np.rint(fy)) <= parity.COORD_RTOL * rr * 2 * ny / (y1 - y0))
+        for h in np.nonzero(near & (ref["hit_layer"] == l))[0]:
+            cx, cy = int(np.floor(fx[h])), int(np.floor(fy[h]))
+            for yy in range(max(cy - 1, 0), min(cy + 2, ny)):
+                for xx in range(max(cx - 1, 0), min(cx + 2, nx)):
+                    mask[sid[h], offs[l] + yy * nx + xx] = True
+    diff = got != want
+    assert not (diff & ~mask).any(), f"{int((diff & ~mask).sum())} cells differ"
+    assert got.sum() > 0
