@@ -66,6 +66,10 @@ def parse():
                     help="time the shower-shape-variable kernel (and the normalised W1 between "
                          "two simulated samples) on the workload's hit clouds")
     ap.add_argument("--bins", type=int, default=100, help="histogram bins of the W1 (--shapes)")
+    ap.add_argument("--grids", action="store_true",
+                    help="time per-layer grid images (CaloGAN-like 3x96 / 12x12 / 12x6 at 1x, 2x, 3x) "
+                         "of the workload's hit clouds read out as three layers")
+    ap.add_argument("--scale", type=int, default=3, help="grid resolution timed for the line (--grids)")
     ap.add_argument("--train-showers", type=int, default=10_000_000)
     ap.add_argument("--eval-showers", type=int, default=1_000_000)
     ap.add_argument("--batch", type=int, default=8192)
@@ -290,6 +294,89 @@ def bench_shapes(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_grids(args):
+    """Per-layer grid images (supa_bin_grids) of one simulated sample of the
+    workload read out as three layers (sub-layers 2-5, 6-13, 14-19; 0-1 dead),
+    on the CaloGAN-like grids over [-5, 5)^2.  The hits are simulated once,
+    before anything is timed; a step is one binning call over the batch."""
+    import torch
+    from paper_2202_05012_amd import grids as GR, presets, prof_summary, supa, workloads
+    from oracle import supa_oracle
+
+    w = workloads.WORKLOADS[args.workload]
+    geom = dict(workloads.geometry(w), layer_of_plane=[-1] * 2 + [0] * 4 + [1] * 8 + [2] * 6)
+    if w.n_planes != 20:
+        sys.exit("--grids reads out the 20-plane workloads as three layers")
+    dev = torch.device("cuda", 0)
+    e0, pol, az = workloads.initial_conditions(w)
+    sim = supa.Simulator(geom, supa.OUT_HITS)
+    out = sim.simulate(*[torch.from_numpy(a).to(dev) for a in (e0, pol, az)], seed=w.seed)
+    del sim
+    n, hits = w.n, int(out["total_hits"])
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+        del a
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    per_scale = {}
+    for scale in sorted({1, 2, 3, args.scale}, key=lambda k: k == args.scale):  # timed scale last
+        gr = presets.calogan_grids(scale, half_width=5.0)
+        for _ in range(max(1, args.warmup)):
+            GR.simulator_grids(out, gr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record()
+        for _ in range(args.steps):
+            img = GR.simulator_grids(out, gr)
+        ev1.record()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cells = GR.cells(gr)
+        alg = BYTES_PER_HIT * hits + n * (12 + 4 * cells)
+        k_ms = ev0.elapsed_time(ev1) / args.steps
+        per_scale[scale] = {"cells": cells, "ms": round(k_ms, 4), "alg_bytes": alg,
+                            "GBps": round(alg / (k_ms / 1e3) / 1e9, 1),
+                            "ms_per_step": (t1 - t0) * 1e3 / args.steps}
+    r = per_scale[args.scale]
+    wl = f"grids{args.scale}x_" + w.name
+    prof_dir = os.path.join(ROOT, "profiles")
+    line = {
+        "metric": f"per-layer grid images showers/s ({args.scale}x CaloGAN-like, 1 MI355X)",
+        "value": round(n / (r["ms_per_step"] / 1e3), 1), "unit": "showers/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64 sums, f32 out",
+        "data": "synthetic",
+        "config": {"workload": wl, "showers": n, "hits": hits, "layers": 3, "cells": r["cells"]},
+        "roofline": {"bound": "hbm", "achieved": r["GBps"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(r["GBps"] / PEAK_HBM_GBS, 4),
+                     "traffic": prof_summary.traffic_if_current(prof_dir, "grids_kernel", wl),
+                     "kernel": "grids_kernel", "kernel_ms": r["ms"], "alg_bytes": r["alg_bytes"]},
+        "scales": {f"{k}x": {kk: vv for kk, vv in v.items() if kk != "ms_per_step"}
+                   for k, v in sorted(per_scale.items())},
+    }
+    if not args.no_cpu_baseline:
+        # the oracle's binning of the first showers' hits for about --cpu-seconds
+        gr = presets.calogan_grids(args.scale, half_width=5.0)
+        off = out["hit_offsets"].cpu().numpy()
+        cnt = out["counts"][:, 1].cpu().numpy().astype(np.int64)
+        done, t_cpu, m = 0, 0.0, 64
+        while t_cpu < args.cpu_seconds and done < n:
+            m = min(2 * m, n - done)
+            a, b = int(off[done]), int(off[done + m - 1] + cnt[done + m - 1])
+            hx, hy, he, hl = (out[k][a:b].cpu().numpy() for k in ("hit_x", "hit_y", "hit_e", "hit_layer"))
+            sid = np.repeat(np.arange(m), cnt[done:done + m])
+            c0 = time.perf_counter()
+            q = np.rint(he.astype(np.float64) * 2.0 ** 21).astype(np.uint64)
+            supa_oracle.grid_images(m, sid, hl, hx, hy, q, gr)
+            t_cpu += time.perf_counter() - c0
+            done += m
+        line["cpu_baseline"] = {"value": round(done / t_cpu, 1), "unit": "showers/s", "cores": 1,
+                                "kind": "oracle",
+                                "sample": f"grid images of the first {done} showers ({t_cpu:.1f} s, one thread)"}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -300,6 +387,8 @@ def main():
         return bench_surrogate(args)
     if args.shapes:
         return bench_shapes(args)
+    if args.grids:
+        return bench_grids(args)
 
     import torch
     from paper_2202_05012_amd import supa, workloads

@@ -18,7 +18,7 @@
 
 namespace {
 
-constexpr int THREADS = 256;
+constexpr int THREADS = 512;
 
 struct GridSpec {
     int nx, ny, off;
@@ -41,33 +41,64 @@ struct GridArgs {
     GridSpec g[SUPA_GRID_MAX_LAYERS];
 };
 
+// Adds hit i (if it lands in a cell) to the slab.
+__device__ inline void add_hit(const GridArgs &A, unsigned long long *slab, int l, float xf, float yf,
+                               float ef) {
+    if (l < 0 || l >= A.L) return;
+    if (!(ef >= 0.0f) || !__builtin_isfinite(ef)) return;
+    const GridSpec &G = A.g[l];
+    const double fx = __builtin_floor(((double)xf - G.x0) * G.sx_num / G.sx_den);
+    const double fy = __builtin_floor(((double)yf - G.y0) * G.sy_num / G.sy_den);
+    if (!(fx >= 0.0 && fx < (double)G.nx && fy >= 0.0 && fy < (double)G.ny)) return;
+    const double q = __builtin_rint((double)ef * A.escale);
+    if (!(q < 9.2e18)) return;
+    atomicAdd(&slab[G.off + (int)fy * G.nx + (int)fx], (unsigned long long)q);
+}
+
 __global__ void __launch_bounds__(THREADS) grids_kernel(GridArgs A) {
     extern __shared__ unsigned long long slab[];
     const int t = threadIdx.x;
-    for (int64_t s = blockIdx.x; s < A.n; s += gridDim.x) {
-        for (int c = t; c < A.cells; c += THREADS) slab[c] = 0ull;
-        __syncthreads();
-        int64_t a = A.off[s];
-        int64_t b = a + A.cnt[(size_t)s * A.cstride];
+    for (int c = t; c < A.cells; c += THREADS) slab[c] = 0ull;
+    __syncthreads();
+    // the next shower's segment is requested while the current one is binned
+    int64_t s = blockIdx.x;
+    int64_t na = 0, nc = 0;
+    if (s < A.n) {
+        na = A.off[s];
+        nc = A.cnt[(size_t)s * A.cstride];
+    }
+    for (; s < A.n; s += gridDim.x) {
+        int64_t a = na, b = na + nc;
+        const int64_t sn = s + gridDim.x;
+        if (sn < A.n) {
+            na = A.off[sn];
+            nc = A.cnt[(size_t)sn * A.cstride];
+        }
         a = a < 0 ? 0 : a;               // never outside the arrays
         b = b > A.len ? A.len : b;
-        for (int64_t i = a + t; i < b; i += THREADS) {
-            const int l = A.layer[i];
-            if (l < 0 || l >= A.L) continue;
-            const float ef = A.e[i];
-            if (!(ef >= 0.0f) || !__builtin_isfinite(ef)) continue;
-            const GridSpec &G = A.g[l];
-            const double fx = __builtin_floor(((double)A.x[i] - G.x0) * G.sx_num / G.sx_den);
-            const double fy = __builtin_floor(((double)A.y[i] - G.y0) * G.sy_num / G.sy_den);
-            if (!(fx >= 0.0 && fx < (double)G.nx && fy >= 0.0 && fy < (double)G.ny)) continue;
-            const double q = __builtin_rint((double)ef * A.escale);
-            if (!(q < 9.2e18)) continue;
-            const int c = G.off + (int)fy * G.nx + (int)fx;
-            atomicAdd(&slab[c], (unsigned long long)q);
+        // four hits per thread per round, all requested before any is used
+        for (int64_t i = a + t; i < b; i += 4 * THREADS) {
+            int lv[4];
+            float xv[4], yv[4], ev[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int64_t j = i + (int64_t)k * THREADS;
+                const bool in = j < b;
+                lv[k] = in ? A.layer[j] : -1;
+                xv[k] = in ? A.x[j] : 0.0f;
+                yv[k] = in ? A.y[j] : 0.0f;
+                ev[k] = in ? A.e[j] : 0.0f;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) add_hit(A, slab, lv[k], xv[k], yv[k], ev[k]);
         }
         __syncthreads();
+        // write the image and leave the slab zero for the next shower
         float *o = A.out + (size_t)s * A.cells;
-        for (int c = t; c < A.cells; c += THREADS) o[c] = (float)slab[c] * A.oscale;
+        for (int c = t; c < A.cells; c += THREADS) {
+            o[c] = (float)slab[c] * A.oscale;
+            slab[c] = 0ull;
+        }
         __syncthreads();
     }
 }
@@ -147,7 +178,7 @@ extern "C" supa_status supa_bin_grids(void *stream, int64_t n, int32_t n_layers,
         A.g[l] = GridSpec{g.nx, g.ny, off, 0.0f, g.x0, g.y0, (double)g.nx, g.x1 - g.x0, (double)g.ny, g.y1 - g.y0};
         off += g.nx * g.ny;
     }
-    int64_t blocks = (int64_t)cu_count() * 8;
+    int64_t blocks = (int64_t)cu_count() * 4;
     if (blocks > n) blocks = n;
     hipLaunchKernelGGL(grids_kernel, dim3((unsigned)blocks), dim3(THREADS),
                        (size_t)cells * sizeof(unsigned long long), (hipStream_t)stream, A);

@@ -38,6 +38,7 @@ KERNEL_SOURCES = {
     "shapes_kernel": ["supa_shapes.hip"],
     "w1_stats": ["supa_shapes.hip"],
     "w1_hist": ["supa_shapes.hip"],
+    "grids_kernel": ["supa_grids.hip"],
 }
 
 
@@ -51,7 +52,7 @@ def source_hash(kernel: str) -> str:
 
 def short_name(full: str) -> str:
     m = re.search(r"(supa_propagate|supa_place|scatter_nodes|scan_tiles|scan_top|scan_apply|shapes_kernel|"
-                  r"shapes_clear|w1_stats|w1_hist|w1_colinfo|w1_distance|w1_groups|w1_zero)\b", full)
+                  r"shapes_clear|w1_stats|w1_hist|w1_colinfo|w1_distance|w1_groups|w1_zero|grids_kernel)\b", full)
     return m.group(1) if m else full
 
 
