@@ -28,6 +28,11 @@
  *     2p, 2p+1 for the two daughters of path p;
  *   - an energy threshold is checked first when a particle arrives at a plane:
  *     below it, the particle deposits its energy there (a "cut" hit);
+ *   - regional parameters (section "Extensions": slices divided into regions
+ *     with their own parameters) are taken as concentric rings around the
+ *     beam axis: the ring of a particle arriving at plane k is the number of
+ *     ring radii <= r = sqrt(x^2 + y^2), and its stop / split probabilities are
+ *     those of (ring, plane);
  *   - a particle flies in a straight line between planes ("continues with its
  *     original velocity"); it leaves the detector after the last plane or when
  *     its direction no longer points to +z;
@@ -136,7 +141,7 @@ void oracle_free(oracle_result *r)
     free(r->node_sid); free(r->node_parent); free(r->node_gen);
     free(r->node_vx); free(r->node_vy); free(r->node_vz);
     free(r->node_e); free(r->node_key);
-    free(r->ledger); free(r->counts); free(r->peak_frontier);
+    free(r->ledger); free(r->counts); free(r->peak_frontier); free(r->region_margin);
     memset(r, 0, sizeof(*r));
 }
 
@@ -318,6 +323,7 @@ static int simulate_one(const oracle_geometry *g, const derived *dv, int64_t i,
     if (!add_node(r, sid, -1, 0, p.x, p.y, p.z, p.e, p.path)) return ORACLE_ERR_NOMEM;
 
     uint64_t e_stop = 0, e_cut = 0, e_esc = 0;
+    double margin = INFINITY;
     int32_t n_hits = 0, n_steps = 0, n_splits = 0, n_escaped = 0, n_backward = 0, peak = 1;
 
     plist cur = {0, 0, 0}, nxt = {0, 0, 0};
@@ -351,15 +357,28 @@ static int simulate_one(const oracle_geometry *g, const derived *dv, int64_t i,
                 continue;
             }
 
+            /* the particle's ring (regional parameters) */
+            int32_t ring = 0;
+            if (g->n_regions >= 2) {
+                double rr = sqrt(q.x * q.x + q.y * q.y);
+                for (int32_t b = 0; b < g->n_regions - 1; ++b) {
+                    if (rr >= g->region_r[b]) ++ring;
+                    double d = fabs(rr - g->region_r[b]);
+                    if (d < margin) margin = d;
+                }
+            }
+            const uint64_t c1 = dv->c1[(int64_t)ring * g->n_planes + k];
+            const uint64_t c2 = dv->c2[(int64_t)ring * g->n_planes + k];
+
             /* three-way choice of Algorithm 1 */
             uint32_t w[4];
             oracle_philox4x32_10(k0, k1, (uint32_t)k, sid, (uint32_t)q.path,
                                  (uint32_t)(q.path >> 32), w);
-            if ((uint64_t)w[0] < dv->c1[k]) {             /* stop: deposit */
+            if ((uint64_t)w[0] < c1) {                    /* stop: deposit */
                 if (!add_hit(r, sid, &q, k, layer, ORACLE_HIT_STOP)) { status = ORACLE_ERR_NOMEM; break; }
                 e_stop += q.e;
                 ++n_hits;
-            } else if ((uint64_t)w[0] < dv->c2[k]) {      /* split in two */
+            } else if ((uint64_t)w[0] < c2) {             /* split in two */
                 particle a, b;
                 split_particle(g, dv, &q, w, &a, &b);
                 a.node = n_nodes++;
@@ -399,6 +418,7 @@ static int simulate_one(const oracle_geometry *g, const derived *dv, int64_t i,
     cnt[4] = n_escaped;
     cnt[5] = n_backward;
     r->peak_frontier[i] = peak;
+    r->region_margin[i] = margin;
     return status;
 }
 
@@ -413,10 +433,21 @@ static int validate(const oracle_geometry *g)
     if (g->angle_mode < ORACLE_ANGLE_FIXED || g->angle_mode > ORACLE_ANGLE_RAYLEIGH) return ORACLE_ERR_INVALID_ARG;
     if (g->kinematics != ORACLE_KIN_3D && g->kinematics != ORACLE_KIN_LITERAL) return ORACLE_ERR_INVALID_ARG;
     if (!isfinite(g->angle_a) || !isfinite(g->angle_b)) return ORACLE_ERR_INVALID_ARG;
-    for (int32_t k = 0; k < g->n_planes; ++k) {
-        double ps = g->p_stop ? g->p_stop[k] : 0.0;
-        double pl = g->p_split ? g->p_split[k] : 1.0;
+    if (g->n_regions < 0 || g->n_regions > 4) return ORACLE_ERR_INVALID_ARG;
+    int32_t rings = g->n_regions >= 2 ? g->n_regions : 1;
+    if (rings >= 2) {
+        if (!g->region_r) return ORACLE_ERR_INVALID_ARG;
+        for (int32_t b = 0; b < rings - 1; ++b)
+            if (!(g->region_r[b] > 0.0) || !isfinite(g->region_r[b]) ||
+                (b > 0 && !(g->region_r[b] > g->region_r[b - 1])))
+                return ORACLE_ERR_INVALID_ARG;
+    }
+    for (int64_t j = 0; j < (int64_t)rings * g->n_planes; ++j) {
+        double ps = g->p_stop ? g->p_stop[j] : 0.0;
+        double pl = g->p_split ? g->p_split[j] : 1.0;
         if (!(ps >= 0.0 && pl >= 0.0 && ps + pl <= 1.0)) return ORACLE_ERR_INVALID_ARG;
+    }
+    for (int32_t k = 0; k < g->n_planes; ++k) {
         if (g->layer_of_plane && (g->layer_of_plane[k] < -1 || g->layer_of_plane[k] >= g->n_planes))
             return ORACLE_ERR_INVALID_ARG;
     }
@@ -435,14 +466,15 @@ int oracle_simulate(const oracle_geometry *g, int64_t n, const float *e0,
 
     derived dv;
     dv.t_cut = (uint64_t)ceil(ldexp(g->e_cut, g->frac_bits));
-    dv.c1 = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)g->n_planes);
-    dv.c2 = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)g->n_planes);
+    const int64_t nthr = (int64_t)(g->n_regions >= 2 ? g->n_regions : 1) * g->n_planes;
+    dv.c1 = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)nthr);
+    dv.c2 = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)nthr);
     if (!dv.c1 || !dv.c2) { free(dv.c1); free(dv.c2); return ORACLE_ERR_NOMEM; }
-    for (int32_t k = 0; k < g->n_planes; ++k) {
-        double ps = g->p_stop ? g->p_stop[k] : 0.0;
-        double pl = g->p_split ? g->p_split[k] : 1.0;
-        dv.c1[k] = (uint64_t)floor(ldexp(ps, 32));
-        dv.c2[k] = dv.c1[k] + (uint64_t)floor(ldexp(pl, 32));
+    for (int64_t j = 0; j < nthr; ++j) {
+        double ps = g->p_stop ? g->p_stop[j] : 0.0;
+        double pl = g->p_split ? g->p_split[j] : 1.0;
+        dv.c1[j] = (uint64_t)floor(ldexp(ps, 32));
+        dv.c2[j] = dv.c1[j] + (uint64_t)floor(ldexp(pl, 32));
     }
     dv.f_lo = (uint64_t)floor(ldexp(g->frac_lo, 32));
     dv.f_w = (uint64_t)floor(ldexp(g->frac_hi, 32)) - dv.f_lo;
@@ -451,7 +483,8 @@ int oracle_simulate(const oracle_geometry *g, int64_t n, const float *e0,
     r->ledger = (uint64_t *)calloc((size_t)(n > 0 ? n : 1) * 4, sizeof(uint64_t));
     r->counts = (int32_t *)calloc((size_t)(n > 0 ? n : 1) * 6, sizeof(int32_t));
     r->peak_frontier = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
-    if (!r->ledger || !r->counts || !r->peak_frontier) status = ORACLE_ERR_NOMEM;
+    r->region_margin = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    if (!r->ledger || !r->counts || !r->peak_frontier || !r->region_margin) status = ORACLE_ERR_NOMEM;
 
     for (int64_t i = 0; i < n && status == ORACLE_OK; ++i) {
         status = simulate_one(g, &dv, i, sid_base + (uint32_t)i, seed, e0[i], polar[i],

@@ -40,6 +40,10 @@ typedef struct {
     double frac_lo, frac_hi;       /* energy fraction f ~ U(frac_lo, frac_hi)      */
     int32_t frac_bits;             /* fixed-point fractional bits of energies      */
     int32_t kinematics;            /* ORACLE_KIN_*                                 */
+    int32_t n_regions;             /* 0 or 1: one region; 2..4: lateral rings      */
+    const double *region_r;        /* n_regions - 1 ascending radii; with rings,
+                                      p_stop / p_split hold n_regions * n_planes
+                                      entries, ring-major ([ring][plane])          */
 } oracle_geometry;
 
 /* Growable result arrays, all owned by the oracle; free with oracle_free. */
@@ -61,6 +65,8 @@ typedef struct {
     int32_t *counts;               /* per shower: nodes, hits, steps, splits, escaped,
                                       escaped because the direction no longer points to +z */
     int32_t *peak_frontier;        /* per shower: largest frontier over the planes  */
+    double *region_margin;         /* per shower: smallest |r - ring radius| over the
+                                      three-way choices (infinity without rings)    */
 } oracle_result;
 
 /* One Philox4x32-10 block: key (k0,k1), counter (c0..c3) -> out[4]. */

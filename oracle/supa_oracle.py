@@ -41,6 +41,8 @@ class _Geometry(C.Structure):
         ("frac_lo", C.c_double), ("frac_hi", C.c_double),
         ("frac_bits", C.c_int32),
         ("kinematics", C.c_int32),
+        ("n_regions", C.c_int32),
+        ("region_r", C.POINTER(C.c_double)),
     ]
 
 
@@ -60,6 +62,7 @@ class _Result(C.Structure):
         ("n_showers", C.c_int64),
         ("ledger", C.POINTER(C.c_uint64)), ("counts", C.POINTER(C.c_int32)),
         ("peak_frontier", C.POINTER(C.c_int32)),
+        ("region_margin", C.POINTER(C.c_double)),
     ]
 
 
@@ -115,7 +118,9 @@ def simulate(geom: dict, e0, polar, azimuth, seed: int, x0=None, y0=None,
     geom keys: n_planes, z_first, dz, layer_of_plane (opt), p_stop (opt),
     p_split (opt), e_cut, angle_mode ('fixed'|'uniform'|'rayleigh'), angle_a,
     angle_b, frac_lo, frac_hi, frac_bits, kinematics ('3d' (default) |
-    'literal').
+    'literal'), n_regions (0/1: none; 2..4 lateral rings) with region_r
+    (n_regions - 1 ascending radii), in which case p_stop / p_split have
+    n_regions * n_planes entries, ring-major.
     """
     e0 = np.ascontiguousarray(np.asarray(e0, dtype=np.float32))
     n = e0.shape[0]
@@ -124,13 +129,16 @@ def simulate(geom: dict, e0, polar, azimuth, seed: int, x0=None, y0=None,
     N = int(geom["n_planes"])
     keep = []
 
-    def arr(key, ctype, dtype):
+    R = int(geom.get("n_regions", 0) or 0)
+    rings = R if R >= 2 else 1
+
+    def arr(key, ctype, dtype, size=N):
         v = geom.get(key)
         if v is None:
             return None
-        a = np.ascontiguousarray(np.asarray(v, dtype=dtype))
-        if a.shape != (N,):
-            raise ValueError(f"{key} must have n_planes entries")
+        a = np.ascontiguousarray(np.asarray(v, dtype=dtype)).reshape(-1)
+        if a.shape != (size,):
+            raise ValueError(f"{key} must have {size} entries")
         keep.append(a)
         return a.ctypes.data_as(C.POINTER(ctype))
 
@@ -139,8 +147,10 @@ def simulate(geom: dict, e0, polar, azimuth, seed: int, x0=None, y0=None,
     g.z_first = float(geom.get("z_first", geom["dz"]))
     g.dz = float(geom["dz"])
     g.layer_of_plane = arr("layer_of_plane", C.c_int32, np.int32)
-    g.p_stop = arr("p_stop", C.c_double, np.float64)
-    g.p_split = arr("p_split", C.c_double, np.float64)
+    g.p_stop = arr("p_stop", C.c_double, np.float64, rings * N)
+    g.p_split = arr("p_split", C.c_double, np.float64, rings * N)
+    g.n_regions = R
+    g.region_r = arr("region_r", C.c_double, np.float64, max(R - 1, 0)) if R >= 2 else None
     g.e_cut = float(geom["e_cut"])
     g.angle_mode = ANGLE_MODES[geom["angle_mode"]]
     g.angle_a = float(geom.get("angle_a", 0.0))
@@ -179,6 +189,7 @@ def simulate(geom: dict, e0, polar, azimuth, seed: int, x0=None, y0=None,
             "ledger": _copy(res.ledger, 4 * n, np.uint64).reshape(n, 4),
             "counts": _copy(res.counts, 6 * n, np.int32).reshape(n, 6),
             "peak_frontier": _copy(res.peak_frontier, n, np.int32),
+            "region_margin": _copy(res.region_margin, n, np.float64),
         }
         out["frac_bits"] = g.frac_bits
         out["n"] = n

@@ -516,3 +516,56 @@ def test_grid_images_match_histogram2d_per_layer():
     for l, g in enumerate(grids):
         inside |= (layer == l) & (x >= g[2]) & (x < g[3]) & (y >= g[4]) & (y < g[5])
     assert img.sum() == e[inside].sum()              # nothing lost or counted twice
+
+
+# --------------------------------------------------------------------------
+# Regional parameters: rings around the beam axis with their own p_stop, p_split
+# --------------------------------------------------------------------------
+def test_rings_with_equal_parameters_change_nothing():
+    rng = np.random.default_rng(21)
+    N = 10
+    g = geom(n_planes=N, p_split=list(rng.uniform(0.3, 0.7, N)), p_stop=list(rng.uniform(0, 0.2, N)))
+    rg = dict(g, n_regions=3, region_r=[0.05, 0.2], p_split=g["p_split"] * 3, p_stop=g["p_stop"] * 3)
+    n = 80
+    e0 = rng.uniform(1, 30, n)
+    a = O.simulate(g, e0, [0.1] * n, [0.5] * n, seed=6)
+    b = O.simulate(rg, e0, [0.1] * n, [0.5] * n, seed=6)
+    for k in ("counts", "ledger", "hit_key", "hit_e", "hit_x", "hit_y", "node_key"):
+        np.testing.assert_array_equal(a[k], b[k])
+    assert np.isinf(a["region_margin"]).all() and np.isfinite(b["region_margin"]).all()
+
+
+def test_rings_hand_traced():
+    """Split at plane 0; at plane 1 a daughter inside radius r1 splits (its
+    daughters leave after the last plane) and one outside stops.  The
+    daughters' radii are dz tan(theta (1 - f)) and dz tan(theta f) (normal
+    incidence), so the counts and the margin follow from the Philox words."""
+    r1 = 0.06
+    g = geom(n_planes=2, e_cut=0.0, n_regions=2, region_r=[r1],
+             p_split=[1.0, 1.0] + [1.0, 0.0], p_stop=[0.0, 0.0] + [0.0, 1.0])
+    seed, n = 19, 200
+    r = O.simulate(g, [1.0] * n, [0.0] * n, [0.0] * n, seed=seed)
+    seen = set()
+    for sid in range(n):
+        w = O.philox4x32_10(seed, (0, sid, 1, 0))
+        f = w[1] / TWO32
+        theta = 0.1 * math.sqrt(-2.0 * math.log((w[2] + 0.5) / TWO32))
+        radii = [math.tan(theta * (1 - f)), math.tan(theta * f)]
+        inner = sum(rr < r1 for rr in radii)
+        seen.add(inner)
+        c = r["counts"][sid]
+        assert c[1] == 2 - inner                       # outer daughters stop: one hit each
+        assert c[3] == 1 + inner and c[4] == 2 * inner  # inner ones split and leave
+        want = min([r1] + [abs(rr - r1) for rr in radii])
+        assert abs(r["region_margin"][sid] - want) < 1e-12
+    assert seen == {0, 1, 2}
+
+
+@pytest.mark.parametrize("bad", [dict(n_regions=5, region_r=[0.1, 0.2, 0.3, 0.4]),
+                                 dict(n_regions=3, region_r=[0.2, 0.1]),
+                                 dict(n_regions=2, region_r=[-0.1])])
+def test_bad_rings_rejected(bad):
+    R = bad["n_regions"]
+    g = geom(n_planes=2, p_split=[1.0] * 2 * R, p_stop=[0.0] * 2 * R, **bad)
+    with pytest.raises(ValueError):
+        O.simulate(g, [1.0], [0.0], [0.0], seed=1)
