@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define SUPA_ABI_VERSION 2
+#define SUPA_ABI_VERSION 3
 
 typedef enum supa_status {
     SUPA_OK = 0,
@@ -98,8 +98,9 @@ typedef struct supa_geometry {
     const int32_t *layer_of_plane;  /* host, N entries in [-1, N), or NULL = identity;
                                        -1 = plane not read out (hits keep layer -1 and
                                        are left out of images)                        */
-    const double *p_stop;           /* host, N entries, or NULL = all 0               */
-    const double *p_split;          /* host, N entries, or NULL = all 1;
+    const double *p_stop;           /* host, N entries (n_regions * N with rings),
+                                       or NULL = all 0                                */
+    const double *p_split;          /* host, N entries (n_regions * N), or NULL = all 1;
                                        p_stop[k] + p_split[k] <= 1                    */
     double e_cut;                   /* energy threshold >= 0 (energy units)            */
     int32_t angle_mode;             /* SUPA_ANGLE_*                                   */
@@ -112,6 +113,18 @@ typedef struct supa_geometry {
     double img_y0, img_y1;          /* cells half-open; x1 > x0, y1 > y0               */
     uint32_t outputs;               /* SUPA_OUT_* bitmask                             */
     int32_t kinematics;             /* SUPA_KIN_*                                     */
+    /* Regional parameters (section "Extensions": slices divided into regions
+       with their own parameters), taken as rings around the beam axis: a
+       particle arriving at plane k is in ring j = the number of radii
+       region_r[b] <= r = sqrt(x^2 + y^2), and stops / splits with the
+       probabilities of (ring j, plane k).  n_regions 0 or 1: one region (the
+       arrays above have N entries); 2..4: rings, region_r (host) holds
+       n_regions - 1 ascending radii > 0 and p_stop / p_split hold
+       n_regions * N entries, ring-major (entry j * N + k).  The ring is decided
+       on float coordinates, so a particle within rounding of a radius may
+       take either ring; the oracle reports each shower's margin. */
+    int32_t n_regions;
+    const double *region_r;
 } supa_geometry;
 
 /* Opaque context: the parameters, their device copies and library scratch. */

@@ -20,10 +20,10 @@
 namespace supa {
 hipError_t launch_zero_counters(unsigned long long *ctr, hipStream_t s);
 hipError_t launch_note_chunks(const unsigned long long *ctr, unsigned long long *sub, hipStream_t s);
-hipError_t launch_propagate(const Params &P, bool literal, int blocks, hipStream_t s);
+hipError_t launch_propagate(const Params &P, bool literal, bool rings, int blocks, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t s);
-size_t propagate_lds_bytes(int pool_cap);
+size_t propagate_lds_bytes(int pool_cap, bool rings);
 hipError_t launch_place(const PlaceParams &P, int n_cu, hipStream_t s);
 void place_bucket_size(int L, int nx, int ny, bool keys, int n_cu, int64_t *per_block, int64_t *blocks);
 int64_t scan_partial_words(int64_t n);
@@ -60,12 +60,16 @@ struct DevBuf {
 static constexpr int kMaxImageWidth = 1024;
 static constexpr int64_t kAutoOrderMin = 65536;     // automatic cost order: from this batch size
 
+// threshold table: 4 rings x 64 planes (the propagation kernel's layout)
+constexpr int THR_ENTRIES = 4 * 64;
+
 struct supa_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     supa_geometry g{};                 // host copy (array pointers cleared)
     std::vector<int32_t> layer;        // host copies
     std::vector<double> p_stop, p_split;
+    float ring_r[4] = {0.f, 0.f, 0.f, 0.f};   // ring radii, +inf past the last
     int32_t n_layers = 0;
     // derived constants
     uint64_t t_cut = 0;
@@ -147,13 +151,25 @@ static supa_status validate(const supa_geometry *g, std::string &why) {
         why = "energy_frac_bits must be in [0, 31]";
         return SUPA_ERR_INVALID_ARG;
     }
-    for (int k = 0; k < g->n_planes; ++k) {
-        const double ps = g->p_stop ? g->p_stop[k] : 0.0;
-        const double pl = g->p_split ? g->p_split[k] : 1.0;
+    if (g->n_regions < 0 || g->n_regions > 4) { why = "n_regions must be in [0, 4]"; return SUPA_ERR_INVALID_ARG; }
+    const int rings = g->n_regions >= 2 ? g->n_regions : 1;
+    if (rings >= 2) {
+        if (!g->region_r) { why = "region_r is NULL"; return SUPA_ERR_INVALID_ARG; }
+        for (int b = 0; b < rings - 1; ++b)
+            if (!is_fin(g->region_r[b]) || !(g->region_r[b] > 0) || (b > 0 && !(g->region_r[b] > g->region_r[b - 1]))) {
+                why = "region_r must be finite, > 0 and ascending";
+                return SUPA_ERR_INVALID_ARG;
+            }
+    }
+    for (int j = 0; j < rings * g->n_planes; ++j) {
+        const double ps = g->p_stop ? g->p_stop[j] : 0.0;
+        const double pl = g->p_split ? g->p_split[j] : 1.0;
         if (!(ps >= 0 && pl >= 0 && ps + pl <= 1)) {
             why = "need p_stop, p_split >= 0 and p_stop + p_split <= 1 on every plane";
             return SUPA_ERR_INVALID_ARG;
         }
+    }
+    for (int k = 0; k < g->n_planes; ++k) {
         if (g->layer_of_plane && (g->layer_of_plane[k] < -1 || g->layer_of_plane[k] >= g->n_planes)) {
             why = "layer_of_plane entries must be in [-1, n_planes)";
             return SUPA_ERR_INVALID_ARG;
@@ -212,16 +228,21 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
     c->stream = (hipStream_t)hip_stream;
     c->g = *g;
     const int N = g->n_planes;
+    const int rings = g->n_regions >= 2 ? g->n_regions : 1;
     c->layer.resize(N);
-    c->p_stop.resize(N);
-    c->p_split.resize(N);
+    c->p_stop.resize((size_t)rings * N);
+    c->p_split.resize((size_t)rings * N);
     int32_t max_layer = -1;
     for (int k = 0; k < N; ++k) {
         c->layer[k] = g->layer_of_plane ? g->layer_of_plane[k] : k;
-        c->p_stop[k] = g->p_stop ? g->p_stop[k] : 0.0;
-        c->p_split[k] = g->p_split ? g->p_split[k] : 1.0;
         max_layer = std::max(max_layer, c->layer[k]);
     }
+    for (int j = 0; j < rings * N; ++j) {
+        c->p_stop[j] = g->p_stop ? g->p_stop[j] : 0.0;
+        c->p_split[j] = g->p_split ? g->p_split[j] : 1.0;
+    }
+    for (int b = 0; b < 4; ++b)
+        c->ring_r[b] = b < rings - 1 ? (float)g->region_r[b] : __builtin_inff();
     c->n_layers = max_layer + 1;
     // planes of each layer, as a CSR list (layers need not be contiguous)
     std::vector<int32_t> lps(c->n_layers + 1, 0), lp;
@@ -234,13 +255,16 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
     c->g.layer_of_plane = nullptr;
     c->g.p_stop = nullptr;
     c->g.p_split = nullptr;
+    c->g.region_r = nullptr;
 
-    // integer thresholds: stop iff w0 < C1, split iff C1 <= w0 < C2
-    std::vector<uint64_t> c1(N), c2(N);
-    for (int k = 0; k < N; ++k) {
-        c1[k] = (uint64_t)std::floor(std::ldexp(c->p_stop[k], 32));
-        c2[k] = c1[k] + (uint64_t)std::floor(std::ldexp(c->p_split[k], 32));
-    }
+    // integer thresholds: stop iff w0 < C1, split iff C1 <= w0 < C2; entry
+    // ring * 64 + plane (4 rings of 64 planes, unused entries 0)
+    std::vector<uint64_t> c1(THR_ENTRIES, 0), c2(THR_ENTRIES, 0);
+    for (int j = 0; j < rings; ++j)
+        for (int k = 0; k < N; ++k) {
+            c1[j * 64 + k] = (uint64_t)std::floor(std::ldexp(c->p_stop[j * N + k], 32));
+            c2[j * 64 + k] = c1[j * 64 + k] + (uint64_t)std::floor(std::ldexp(c->p_split[j * N + k], 32));
+        }
     const double tc = std::ceil(std::ldexp(g->e_cut, g->energy_frac_bits));
     c->t_cut = tc >= 18446744073709551615.0 ? ~0ull : (uint64_t)tc;
     c->f_lo = (uint32_t)std::min(std::floor(std::ldexp(g->frac_lo, 32)), 4294967295.0);
@@ -254,21 +278,21 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
         return fail(nullptr, SUPA_ERR_DEVICE, "cannot query compute units");
     }
     bool ok = hipMalloc(&c->d_layer, N * sizeof(int32_t)) == hipSuccess &&
-              hipMalloc(&c->d_c1, N * sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(&c->d_c1, THR_ENTRIES * sizeof(uint64_t)) == hipSuccess &&
               hipMalloc(&c->d_layer_plane_start, lps.size() * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&c->d_layer_planes, lp.size() * sizeof(int32_t)) == hipSuccess &&
               hipMemcpy(c->d_layer_plane_start, lps.data(), lps.size() * sizeof(int32_t),
                         hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->d_layer_planes, lp.data(), lp.size() * sizeof(int32_t),
                         hipMemcpyHostToDevice) == hipSuccess &&
-              hipMalloc(&c->d_c2, N * sizeof(uint64_t)) == hipSuccess &&
+              hipMalloc(&c->d_c2, THR_ENTRIES * sizeof(uint64_t)) == hipSuccess &&
               hipMalloc(&c->d_ctr, supa::CTR_WORDS * sizeof(unsigned long long)) == hipSuccess &&
               hipHostMalloc(&c->h_ctr, supa::CTR_WORDS * sizeof(unsigned long long), 0) == hipSuccess &&
               hipMalloc(&c->d_cold, supa::MAX_SUB * sizeof(supa::Cold)) == hipSuccess &&
               hipHostMalloc(&c->h_cold, supa::MAX_SUB * sizeof(supa::Cold), 0) == hipSuccess &&
               hipMemcpy(c->d_layer, c->layer.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(c->d_c1, c1.data(), N * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(c->d_c2, c2.data(), N * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess;
+              hipMemcpy(c->d_c1, c1.data(), THR_ENTRIES * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(c->d_c2, c2.data(), THR_ENTRIES * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess;
     // default priority, and no implicit synchronisation with the null stream
     ok = ok && hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) == hipSuccess;
     for (hipEvent_t *e : {&c->ev_begin, &c->ev_end, &c->ev_joined})
@@ -513,6 +537,7 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
         K.ledger = out->ledger + 4 * o;
         K.counts = out->counts + 6 * o;
         K.hstart = L.d_hstart ? L.d_hstart + o : nullptr;
+        for (int q = 0; q < 4; ++q) K.ring_r[q] = c->ring_r[q];
     }
     return SUPA_OK;
 }
@@ -538,7 +563,7 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
             HIP_TRY(c, supa::launch_cost_order(b->e0 + o, (int)nj, P.e_scale, L.d_ohist, L.d_order + o,
                                                c->n_cu, s_main));
         if (timed) HIP_TRY(c, hipEventRecord(c->ev_prop[j][0], s_main));
-        HIP_TRY(c, supa::launch_propagate(Pj, c->g.kinematics == SUPA_KIN_LITERAL, (int)L.waves, s_main));
+        HIP_TRY(c, supa::launch_propagate(Pj, c->g.kinematics == SUPA_KIN_LITERAL, c->g.n_regions >= 2, (int)L.waves, s_main));
         if (L.tree) HIP_TRY(c, supa::launch_note_chunks(c->d_ctr, sub_ctr(j), s_main));
         // the second stream waits on this event (none inside a capture, where
         // both are one stream)

@@ -74,6 +74,7 @@ struct Cold {
     uint64_t *ledger;           // [n][4]
     int32_t *counts;            // [n][6]
     int64_t *hstart;            // [n]: log position of the shower's first hit record
+    float ring_r[4];            // ring radii (regional parameters), +inf past the last
 };
 
 // Hit records leave the propagation kernel through a log of chunks of

@@ -206,8 +206,10 @@ __device__ __forceinline__ int wave_excl_scan(int v) {
 }
 
 // LDS words of one wave: pool + the stop / split thresholds of every plane
-__host__ __device__ constexpr int lds_words(int pool_cap) {
-    return POOL_FIELDS * pool_cap + 2 * 2 * 64;
+// pool, then the thresholds c1, c2 (u64) of 64 planes, of 4 rings with
+// regional parameters
+__host__ __device__ constexpr int lds_words(int pool_cap, bool rings = false) {
+    return POOL_FIELDS * pool_cap + 2 * 2 * 64 * (rings ? 4 : 1);
 }
 
 // Keeps a wave-uniform value in scalar registers but hides it from loop-
@@ -243,9 +245,9 @@ struct SlotSums {
 };
 
 // TREE: node records; KEYS: path ids with hit and node records; LIT: literal
-// Algorithm 1 kinematics (compile-time, so that no flag occupies a scalar
-// register through the loop)
-template <bool TREE, bool KEYS, int PC, bool LIT>
+// Algorithm 1 kinematics; REG: regional parameters (rings) (compile-time, so
+// that no flag occupies a scalar register through the loop)
+template <bool TREE, bool KEYS, int PC, bool LIT, bool REG>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) supa_propagate(Params P) {
     extern __shared__ uint32_t lds[];
     const uint32_t lane = lane_id();
@@ -254,11 +256,22 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
     // PC: pool entries in LDS, a power of two >= 2 * WAVE (compile-time, so
     // that the field offsets are instruction immediates)
     uint32_t *const pool = lds;            // [POOL_FIELDS][PC], entry j at slot j & (PC-1)
-    uint64_t *const thr = (uint64_t *)(pool + POOL_FIELDS * PC);    // c1[64], c2[64]
-
-    for (int k = (int)lane; k < 64; k += WAVE) {
-        thr[k] = k < N ? P.c1[k] : 0ull;
-        thr[64 + k] = k < N ? P.c2[k] : 0ull;
+    // c1[ring * 64 + k] then c2 (one ring without regional parameters)
+    uint64_t *const thr = (uint64_t *)(pool + POOL_FIELDS * PC);
+    constexpr int TN = REG ? 4 * 64 : 64;
+    for (int k = (int)lane; k < TN; k += WAVE) {
+        const bool in = (k & 63) < N;
+        thr[k] = in ? P.c1[k] : 0ull;
+        thr[TN + k] = in ? P.c2[k] : 0ull;
+    }
+    float rr1 = 0.f, rr2 = 0.f, rr3 = 0.f;        // squared ring radii
+    if constexpr (REG) {
+        const volatile __attribute__((address_space(1))) Cold *cp =
+            (const volatile __attribute__((address_space(1))) Cold *)P.cold;
+        const float a = cp->ring_r[0], b = cp->ring_r[1], c = cp->ring_r[2];
+        rr1 = a * a;
+        rr2 = b * b;
+        rr3 = c * c;
     }
 
     const int64_t G = P.spill_cap;
@@ -533,7 +546,13 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             const uint32_t sid = (uint32_t)__shfl((int)S.sid, slot, WAVE);
             const uint4 w = philox4x32_10((uint32_t)k, sid, p.lo, p.hi, opaque_u32(P.seed_lo),
                                           opaque_u32(P.seed_hi));
-            const uint64_t c1 = thr[k], c2 = thr[64 + k];
+            int ring = 0;
+            if constexpr (REG) {
+                // ring from the position at arrival: r^2 against the squared radii
+                const float r2 = fmaf(p.x, p.x, p.y * p.y);
+                ring = (r2 >= rr1 ? 1 : 0) + (r2 >= rr2 ? 1 : 0) + (r2 >= rr3 ? 1 : 0);
+            }
+            const uint64_t c1 = thr[ring * 64 + k], c2 = thr[TN + ring * 64 + k];
             const bool is_stop = valid && (uint64_t)w.x < c1;
             const bool is_split = valid && !is_stop && (uint64_t)w.x < c2;
             const bool is_pass = valid && !is_stop && !is_split;
@@ -781,33 +800,36 @@ hipError_t launch_note_chunks(const unsigned long long *ctr, unsigned long long 
     return hipGetLastError();
 }
 
-size_t propagate_lds_bytes(int pool_cap) {
-    return (size_t)lds_words(pool_cap) * 4;
+size_t propagate_lds_bytes(int pool_cap, bool rings) {
+    return (size_t)lds_words(pool_cap, rings) * 4;
 }
 
-template <bool TREE, bool KEYS, bool LIT>
+template <bool TREE, bool KEYS, bool LIT, bool REG>
 static hipError_t launch_pc(const Params &P, int blocks, size_t lds, hipStream_t s) {
     switch (P.pool_cap) {
-    case 128: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 128, LIT>), dim3(blocks), dim3(WAVE), lds, s, P); break;
-    case 256: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 256, LIT>), dim3(blocks), dim3(WAVE), lds, s, P); break;
-    case 512: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 512, LIT>), dim3(blocks), dim3(WAVE), lds, s, P); break;
-    case 1024: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 1024, LIT>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 128: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 128, LIT, REG>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 256: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 256, LIT, REG>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 512: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 512, LIT, REG>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 1024: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 1024, LIT, REG>), dim3(blocks), dim3(WAVE), lds, s, P); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <bool LIT>
+template <bool LIT, bool REG>
 static hipError_t launch_kin(const Params &P, int blocks, size_t lds, hipStream_t s) {
     const bool tree = (P.outputs & 4u) != 0;
     if (tree)
-        return P.keys ? launch_pc<true, true, LIT>(P, blocks, lds, s) : launch_pc<true, false, LIT>(P, blocks, lds, s);
-    return P.keys ? launch_pc<false, true, LIT>(P, blocks, lds, s) : launch_pc<false, false, LIT>(P, blocks, lds, s);
+        return P.keys ? launch_pc<true, true, LIT, REG>(P, blocks, lds, s)
+                      : launch_pc<true, false, LIT, REG>(P, blocks, lds, s);
+    return P.keys ? launch_pc<false, true, LIT, REG>(P, blocks, lds, s)
+                  : launch_pc<false, false, LIT, REG>(P, blocks, lds, s);
 }
 
-hipError_t launch_propagate(const Params &P, bool literal, int blocks, hipStream_t s) {
-    const size_t lds = propagate_lds_bytes(P.pool_cap);
-    return literal ? launch_kin<true>(P, blocks, lds, s) : launch_kin<false>(P, blocks, lds, s);
+hipError_t launch_propagate(const Params &P, bool literal, bool rings, int blocks, hipStream_t s) {
+    const size_t lds = propagate_lds_bytes(P.pool_cap, rings);
+    if (rings) return literal ? launch_kin<true, true>(P, blocks, lds, s) : launch_kin<false, true>(P, blocks, lds, s);
+    return literal ? launch_kin<true, false>(P, blocks, lds, s) : launch_kin<false, false>(P, blocks, lds, s);
 }
 
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,

@@ -44,6 +44,8 @@ class Geometry(C.Structure):
         ("img_y0", C.c_double), ("img_y1", C.c_double),
         ("outputs", C.c_uint32),
         ("kinematics", C.c_int32),
+        ("n_regions", C.c_int32),
+        ("region_r", C.POINTER(C.c_double)),
     ]
 
 
@@ -127,13 +129,17 @@ def make_geometry(geom: dict, outputs: int):
     N = int(geom["n_planes"])
     keep = []
 
-    def arr(key, ctype):
+    R = int(geom.get("n_regions", 0) or 0)
+    rings = R if R >= 2 else 1
+
+    def arr(key, ctype, size=N):
         v = geom.get(key)
         if v is None:
             return None
-        a = (ctype * N)(*[ctype(x).value for x in v])
-        if len(v) != N:
-            raise ValueError(f"{key} must have n_planes entries")
+        v = [float(x) if ctype is C.c_double else int(x) for x in v]
+        if len(v) != size:
+            raise ValueError(f"{key} must have {size} entries")
+        a = (ctype * size)(*[ctype(x).value for x in v])
         keep.append(a)
         return C.cast(a, C.POINTER(ctype))
 
@@ -142,8 +148,10 @@ def make_geometry(geom: dict, outputs: int):
     g.z_first = float(geom.get("z_first", geom["dz"]))
     g.dz = float(geom["dz"])
     g.layer_of_plane = arr("layer_of_plane", C.c_int32)
-    g.p_stop = arr("p_stop", C.c_double)
-    g.p_split = arr("p_split", C.c_double)
+    g.p_stop = arr("p_stop", C.c_double, rings * N)
+    g.p_split = arr("p_split", C.c_double, rings * N)
+    g.n_regions = R
+    g.region_r = arr("region_r", C.c_double, R - 1) if R >= 2 else None
     g.e_cut = float(geom["e_cut"])
     g.angle_mode = ANGLE_MODES[geom["angle_mode"]]
     g.angle_a = float(geom.get("angle_a", 0.0))

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     assert "supa_simulate" in names and "supa_init_geometry" in names
     for name in names:
         assert hasattr(lib, name), f"{name} declared in include/ but not exported"
-    assert lib.supa_abi_version() == 2
+    assert lib.supa_abi_version() == 3
 
 
 def base_geom(**kw):
@@ -110,3 +110,15 @@ def test_grid_entry_points_reject_bad_arguments_on_the_host():
                             fake, fake, fake) == 1
     assert L.supa_bin_grids(None, 10, 17, C.cast(ok, C.c_void_p), 21, fake, fake, 1, 100, fake, fake,
                             fake, fake, fake) == 1
+
+
+@pytest.mark.parametrize("bad", [dict(n_regions=5, region_r=[0.1, 0.2, 0.3, 0.4]),
+                                 dict(n_regions=3, region_r=[0.2, 0.1]),
+                                 dict(n_regions=2, region_r=[0.0])])
+def test_ring_parameters_rejected(bad):
+    R = bad["n_regions"]
+    g = dict(base_geom(), **bad, p_stop=[0.0] * 20 * R, p_split=[1.0] * 20 * R)
+    with pytest.raises(supa.SupaError):
+        supa.validate_geometry(g)
+    ok = dict(base_geom(), n_regions=3, region_r=[0.1, 0.2], p_stop=[0.0] * 60, p_split=[1.0] * 60)
+    supa.validate_geometry(ok)

@@ -420,3 +420,42 @@ def test_random_parameters_literal(trial):
     gpu, ref = check(geom, ALL, e0, pol, az, seed=int(rng.integers(0, 2 ** 63)), x0=x0, y0=y0,
                      base=int(rng.integers(0, 2 ** 31)))
     assert ref["counts"][:, 5].sum() == 0                 # nothing turns back
+
+
+# --------------------------------------------------------------------------
+# Regional parameters (rings): the ring is decided on each side's own
+# coordinates, so a shower is compared exactly when no choice of the oracle
+# came within 1e-4 of a ring radius (ten times the coordinate bar); such
+# showers must be the large majority
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("trial", range(4))
+def test_rings_parity(trial):
+    rng = np.random.default_rng(500 + trial)
+    N = int(rng.integers(4, 10))
+    R = int(rng.integers(2, 5))
+    geom = random_geometry(rng, N)
+    geom.update(n_regions=R, region_r=sorted(rng.uniform(0.01, 0.3, R - 1).tolist()),
+                kinematics="literal" if trial == 3 else "3d")
+    ps = rng.uniform(0, 0.4, R * N)
+    geom.update(p_stop=list(ps), p_split=list(rng.uniform(0, 1, R * N) * (1 - ps)))
+    if trial == 3:
+        geom["dz"] = 0.05                                   # literal steps of the ring scale
+    n = 160
+    e0 = rng.uniform(0.2, 4, n)
+    pol = rng.uniform(0, 0.5, n)
+    az = rng.uniform(-7, 7, n)
+    x0 = rng.uniform(-0.2, 0.2, n)
+    y0 = rng.uniform(-0.2, 0.2, n)
+    base, seed = int(rng.integers(0, 2 ** 31)), int(rng.integers(0, 2 ** 63))
+    gpu, _ = run_gpu(geom, ALL, e0, pol, az, seed, x0, y0, base)
+    ref = O.simulate(geom, e0, pol, az, seed, x0=x0, y0=y0, shower_id_base=base)
+    clear = np.nonzero(ref["region_margin"] > 1e-4)[0]
+    assert len(clear) >= 0.85 * n
+    for i in clear:
+        one = O.simulate(geom, e0[i:i + 1], pol[i:i + 1], az[i:i + 1], seed, x0=x0[i:i + 1],
+                         y0=y0[i:i + 1], shower_id_base=base + int(i))
+        parity.check_all(gpu, one, geom, images=True, tree=True, rows=[int(i)])
+    # the rings matter: a one-region run with ring 0's parameters differs
+    flat = dict(geom, n_regions=0, region_r=None, p_stop=list(ps[:N]), p_split=geom["p_split"][:N])
+    ref0 = O.simulate(flat, e0, pol, az, seed, x0=x0, y0=y0, shower_id_base=base)
+    assert (ref0["counts"] != ref["counts"]).any()
