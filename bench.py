@@ -54,6 +54,11 @@ def parse():
                     help="time replays of a captured HIP graph of the call")
     ap.add_argument("--autotune", action="store_true",
                     help="pick launch settings by measurement before timing")
+    ap.add_argument("--kinematics", default="3d", choices=("3d", "literal"),
+                    help="3-D flight (default) or Algorithm 1's literal displacement kinematics")
+    ap.add_argument("--rings", type=int, default=0,
+                    help="regional parameters: this many rings (2..4) at radii 0.05, 0.15, 0.4, "
+                         "every ring with the workload's probabilities (measures the ring lookup)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="wall time of the oracle's host-CPU baseline")
@@ -400,6 +405,14 @@ def main():
         # the parity tests run it, on up to 400 showers
         sys.exit(f"bench.py does not run {w.name}: its batched run is disabled (open GPU fault)")
     geom = workloads.geometry(w)
+    geom["kinematics"] = args.kinematics
+    wname = w.name + ("" if args.kinematics == "3d" else "_literal") + \
+        (f"_rings{args.rings}" if args.rings >= 2 else "")
+    if args.rings >= 2:
+        R, N = args.rings, int(geom["n_planes"])
+        geom.update(n_regions=R, region_r=[0.05, 0.15, 0.4][:R - 1],
+                    p_stop=list(geom.get("p_stop") or [0.0] * N) * R,
+                    p_split=list(geom.get("p_split") or [1.0] * N) * R)
     outputs = supa.OUT_HITS | (supa.OUT_IMAGES if w.images else 0) | (supa.OUT_TREE if w.tree else 0)
     if args.outputs:
         names = {"hits": supa.OUT_HITS, "images": supa.OUT_IMAGES, "tree": supa.OUT_TREE}
@@ -482,11 +495,11 @@ def main():
     prof_dir = os.path.join(ROOT, "profiles")
     roof_prop = {"bound": "alu", "achieved": round(alu, 3), "peak": round(PEAK_ALU_TOPS, 2),
                  "unit": "T lane-ops/s", "frac": round(alu / PEAK_ALU_TOPS, 4),
-                 "traffic": prof_summary.traffic_if_current(prof_dir, "supa_propagate", w.name),
+                 "traffic": prof_summary.traffic_if_current(prof_dir, "supa_propagate", wname),
                  "kernel": "supa_propagate", "kernel_ms": round(k_prop, 4),
                  "alg_lane_ops": alg_ops,
                  # measured VALU instruction issue (rocprofv3 counters, committed summary)
-                 "valu_issue_frac": prof_summary.counter_if_current(prof_dir, "supa_propagate", w.name,
+                 "valu_issue_frac": prof_summary.counter_if_current(prof_dir, "supa_propagate", wname,
                                                                     "valu_issue_fraction")}
     # placement kernel: algorithmic bytes = the outputs it writes (HBM roofline)
     roof = roof_prop
@@ -504,7 +517,7 @@ def main():
         kname = "supa_place" if outputs & (supa.OUT_HITS | supa.OUT_IMAGES) else "scatter_nodes"
         roof_place = {"bound": "hbm", "achieved": round(hbm, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                       "frac": round(hbm / PEAK_HBM_GBS, 4),
-                      "traffic": prof_summary.traffic_if_current(prof_dir, kname, w.name),
+                      "traffic": prof_summary.traffic_if_current(prof_dir, kname, wname),
                       "kernel": kname, "kernel_ms": round(k_post, 4), "alg_bytes": out_bytes}
         # the dominant kernel (longest) is the headline roofline
         roof, roof_other = (roof_place, roof_prop) if k_post >= k_prop else (roof_prop, roof_place)
@@ -522,7 +535,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+u32",
         "data": "synthetic",
-        "config": {"workload": w.name, "showers": w.n, "planes": w.n_planes,
+        "config": {"workload": wname,
+                   "showers": w.n, "planes": w.n_planes,
                    "outputs": "+".join(n for n, b in (("hits", supa.OUT_HITS),
                                                       ("images", supa.OUT_IMAGES),
                                                       ("tree", supa.OUT_TREE)) if outputs & b)
