@@ -90,3 +90,43 @@ def test_simulated_showers_on_calogan_grids(scale):
     diff = got != want
     assert not (diff & ~mask).any(), f"{int((diff & ~mask).sum())} cells differ"
     assert got.sum() > 0
+
+
+def compare_to_oracle(got, ref, n, grids):
+    """Exact except cells next to a hit within the coordinate tolerance of an edge."""
+    sid = ref["hit_sid"] - ref["shower_id_base"]
+    e_f = (ref["hit_e"].astype(np.float32) * np.float32(2.0 ** -S))
+    want = want_images(n, sid, ref["hit_layer"], ref["hit_x"], ref["hit_y"], e_f, grids)
+    mask = np.zeros(got.shape, bool)
+    offs = np.concatenate([[0], np.cumsum([g[0] * g[1] for g in grids])])
+    rr = np.maximum(np.hypot(ref["hit_x"], ref["hit_y"]), 1.0)
+    for l, (nx, ny, x0, x1, y0, y1) in enumerate(grids):
+        fx = (ref["hit_x"] - x0) * nx / (x1 - x0)
+        fy = (ref["hit_y"] - y0) * ny / (y1 - y0)
+        near = (np.abs(fx - np.rint(fx)) <= parity.COORD_RTOL * rr * 2 * nx / (x1 - x0)) | \
+               (np.abs(fy - np.rint(fy)) <= parity.COORD_RTOL * rr * 2 * ny / (y1 - y0))
+        for h in np.nonzero(near & (ref["hit_layer"] == l))[0]:
+            cx, cy = int(np.floor(fx[h])), int(np.floor(fy[h]))
+            for yy in range(max(cy - 1, 0), min(cy + 2, ny)):
+                for xx in range(max(cx - 1, 0), min(cx + 2, nx)):
+                    mask[sid[h], offs[l] + yy * nx + xx] = True
+    diff = got != want
+    assert not (diff & ~mask).any(), f"{int((diff & ~mask).sum())} cells differ"
+
+
+def test_full_size_100k_grids_sampled():
+    """3x CaloGAN-like grids of the 100,000-shower benchmark sample read out as
+    three layers, one launch over the whole batch as bench.py --grids times
+    it; the oracle simulates and bins sampled blocks of 64 showers."""
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = dict(workloads.geometry(w), layer_of_plane=[-1] * 2 + [0] * 4 + [1] * 8 + [2] * 6)
+    e0, pol, az = workloads.initial_conditions(w)
+    grids = presets.calogan_grids(3, half_width=5.0)
+    sim = supa.Simulator(geom, supa.OUT_HITS)
+    out = sim.simulate(_t(e0), _t(pol), _t(az), seed=w.seed)
+    img = GR.simulator_grids(out, grids, S)
+    rng = np.random.default_rng(3)
+    for start in [0, w.n - 64] + list(rng.integers(0, w.n - 64, 3)):
+        rows = np.arange(start, start + 64)
+        ref = O.simulate(geom, e0[rows], pol[rows], az[rows], w.seed, shower_id_base=int(start))
+        compare_to_oracle(img[torch.from_numpy(rows).cuda()].cpu().numpy(), ref, 64, grids)

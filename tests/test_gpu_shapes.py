@@ -251,3 +251,28 @@ def test_mean_discrepancy_of_two_simulated_samples():
     np.testing.assert_allclose(w1.cpu().numpy(), want, rtol=1e-9)
     np.testing.assert_allclose(gm.cpu().numpy(), SO.group_means(want, groups, 23), rtol=1e-12)
     assert cols == L * 18 + 5
+
+
+def test_full_size_100k_shapes_sampled():
+    """Shape variables of the 100,000-shower benchmark sample at full size, in
+    one launch over the whole batch as bench.py --shapes times it; the oracle
+    simulates and measures sampled blocks of 64 showers (first, last, three
+    at random)."""
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = workloads.geometry(w)
+    L = supa.n_layers(geom)
+    e0, pol, az = workloads.initial_conditions(w)
+    sim = supa.Simulator(geom, supa.OUT_HITS)
+    out = sim.simulate(_t(e0), _t(pol), _t(az), seed=w.seed)
+    lv, sv = SH.simulator_shapes(out, L)
+    assert torch.isfinite(sv[:, SV["e_tot"]]).all()
+    rng = np.random.default_rng(2)
+    for start in [0, w.n - 64] + list(rng.integers(0, w.n - 64, 3)):
+        rows = np.arange(start, start + 64)
+        ref = O.simulate(geom, e0[rows], pol[rows], az[rows], w.seed, shower_id_base=int(start))
+        e = (ref["hit_e"].astype(np.float32) * np.float32(2.0 ** -ref["frac_bits"])).astype(np.float64)
+        sid = ref["hit_sid"] - ref["shower_id_base"]
+        rlv, rsv = SO.shapes(64, L, sid, ref["hit_layer"], ref["hit_x"], ref["hit_y"], e)
+        rmax = float(np.hypot(ref["hit_x"], ref["hit_y"]).max())
+        it = torch.from_numpy(rows).cuda()
+        check_shapes(lv[it], sv[it], rlv, rsv, coord_atol=1e-5 * max(rmax, 1.0))
