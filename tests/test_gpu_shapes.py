@@ -276,3 +276,19 @@ def test_full_size_100k_shapes_sampled():
         rmax = float(np.hypot(ref["hit_x"], ref["hit_y"]).max())
         it = torch.from_numpy(rows).cuda()
         check_shapes(lv[it], sv[it], rlv, rsv, coord_atol=1e-5 * max(rmax, 1.0))
+
+
+def test_usage_example():
+    """The usage example of the README, end to end: SUPAv1 showers, their shape
+    variables and 2x grids (128 points of 65/128 in layer 0, fraction 1)."""
+    from paper_2202_05012_amd import grids, presets
+    geom = presets.supa(1)
+    e0, pol, az = (torch.tensor(v, device="cuda") for v in presets.incident(1000))
+    sim = supa.Simulator(geom, supa.OUT_HITS | supa.OUT_KEYS)
+    out = sim.simulate(e0, pol, az, seed=1)
+    lv, sv = SH.simulator_shapes(out, n_layers=supa.n_layers(geom))
+    img = grids.simulator_grids(out, presets.calogan_grids(2))
+    assert lv.shape == (1000, 1, 18) and sv.shape == (1000, 5) and img.shape == (1000, 2016)
+    assert (lv[:, 0, LV["count"]] == 128).all() and (lv[:, 0, LV["fraction"]] == 1).all()
+    assert torch.allclose(lv[:, 0, LV["mean_e"]], torch.tensor(65.0 / 128, device="cuda"))
+    assert torch.allclose(img.sum(1), torch.tensor(65.0, device="cuda"))
