@@ -297,6 +297,10 @@ __global__ void __launch_bounds__(WAVE) shapes_kernel(ShapeArgs A) {
                 s = next;
                 pos = A.off[s];
                 end = pos + A.cnt[(size_t)s * A.cstride];
+                // a segment reaching outside the arrays is the caller's error;
+                // never read outside them
+                pos = pos < 0 ? 0 : (pos > A.len ? A.len : pos);
+                end = end < pos ? pos : (end > A.len ? A.len : end);
                 cur = -1;
                 depth = -1;
                 bad = false;
