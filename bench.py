@@ -256,6 +256,27 @@ def bench_shapes(args):
     tr = [prof_summary.traffic_if_current(prof_dir, k, wl) for k in ("w1_stats", "w1_hist")]
     w1_traffic = None if None in tr else 2 * (tr[0] + tr[1])   # each kernel runs once per sample
     gm_h = gm.cpu().numpy()
+    # the groups of marginals of the paper's performance table (untimed): the
+    # per-layer variables grouped across layers, and the point-level marginals
+    # of eta = x, phi = y, r and E over every hit of each sample
+    table = {"feature means <eta>,<phi>,<r>": ("mean_x", "mean_y", "mean_r"), "feature mean <E>": ("mean_e",),
+             "deviations of eta, phi, r": ("std_x", "std_y", "std_r"), "deviation of E": ("std_e",),
+             "layer energy": ("energy",), "layer centroids": ("centroid_x", "centroid_y", "centroid_r"),
+             "layer widths": ("width_x", "width_y", "width_r"),
+             "point counts": ("count",), "fraction, energy ratio": ("fraction", "energy_ratio"),
+             "shower variables": SH.SHOWER_VARS}
+    gidx = {v: g for g, vs in enumerate(table.values()) for v in vs}
+    tgroups = torch.tensor([gidx.get(v, -1) for v in SH.LAYER_VARS * L + SH.SHOWER_VARS], dtype=torch.int32, device=dev)
+    _, tg = SH.w1_columns(mats[0], mats[1], args.bins, tgroups, len(table), ws)
+    md = {k: round(float(v), 5) for k, v in zip(table, tg.cpu().numpy())}
+    pts = {}
+    for name, key in (("eta", "hit_x"), ("phi", "hit_y"), ("E", "hit_e")):
+        pts[name] = float(SH.w1_columns(samples[0][key], samples[1][key], args.bins, workspace=ws)[0].item())
+    r0 = SH.hit_radius(samples[0]["hit_x"], samples[0]["hit_y"])
+    r1 = SH.hit_radius(samples[1]["hit_x"], samples[1]["hit_y"])
+    pts["r"] = float(SH.w1_columns(r0, r1, args.bins, workspace=ws)[0].item())
+    md["point features eta, phi, r"] = round((pts["eta"] + pts["phi"] + pts["r"]) / 3, 5)
+    md["point feature E"] = round(pts["E"], 5)
     line = {
         "metric": "shower-shape-variable showers/s (1 MI355X)",
         "value": round(n / (ms_per_step / 1e3), 1),
@@ -273,6 +294,7 @@ def bench_shapes(args):
                            "bins": args.bins, "columns": cols},
         "mean_discrepancy_by_variable": {k: round(float(v), 5) for k, v in
                                          zip(SH.LAYER_VARS + SH.SHOWER_VARS, gm_h)},
+        "mean_discrepancy_by_group": md,
     }
     if not args.no_cpu_baseline:
         # the oracle's shape variables of the first showers, for about
