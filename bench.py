@@ -407,8 +407,9 @@ def bench_grids(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(showers shard by shower_id_base; see the design notes)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (showers are "
+              "independent and keyed by global id, so GPUs would take disjoint shower_id_base "
+              "ranges)", file=sys.stderr)
         sys.exit(2)
     if args.surrogate:
         return bench_surrogate(args)

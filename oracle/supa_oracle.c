@@ -13,8 +13,7 @@
  *   theta, or passes through unchanged.  After the last plane every deposit is
  *   collected; planes are grouped into layers and z is projected out.
  *
- * Readings taken where the paper is silent or garbled (all of them are also
- * listed with their reasons in the design notes of the repository):
+ * Readings taken where the paper is silent or garbled:
  *   - energies are unsigned fixed-point integers with `frac_bits` fractional
  *     bits; the primary is rounded to nearest-even, a split gives
  *     E_a = floor(E*F/2^32) and E_b = E - E_a with F the 32-bit fraction, so the
