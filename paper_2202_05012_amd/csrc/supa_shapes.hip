@@ -452,15 +452,24 @@ __global__ void __launch_bounds__(W1_THREADS)
     if (c < n_cols) {
         const float p0 = m[c];
         const double piv = finite(p0) ? (double)p0 : 0.0;
-        for (int64_t r = r0 + ph; r < r1; r += rpt) {
-            const float v = m[r * ld + c];
-            if (!finite(v)) continue;
-            const double d = (double)v - piv;
-            cnt += 1.0;
-            s1 += d;
-            s2 = __builtin_fma(d, d, s2);
-            mn = v < mn ? v : mn;
-            mx = v > mx ? v : mx;
+        // four rows per round, all requested before any is used
+        for (int64_t r = r0 + ph; r < r1; r += 4 * (int64_t)rpt) {
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int64_t q = r + (int64_t)u * rpt;
+                v[u] = q < r1 ? m[q * ld + c] : __builtin_nanf("");
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (!finite(v[u])) continue;
+                const double d = (double)v[u] - piv;
+                cnt += 1.0;
+                s1 += d;
+                s2 = __builtin_fma(d, d, s2);
+                mn = v[u] < mn ? v[u] : mn;
+                mx = v[u] > mx ? v[u] : mx;
+            }
         }
     }
     sh[0][t] = cnt;
@@ -540,12 +549,20 @@ __global__ void __launch_bounds__(W1_THREADS)
         const ColInfo ci = info[c];
         if (!ci.skip) {
             uint32_t *h = hb + cl * n_bins;
-            for (int64_t r = r0 + ph; r < r1; r += rpt) {
-                const float v = m[r * ld + c];
-                if (!finite(v)) continue;
-                int k = (int)__builtin_floor(((double)v - ci.lo) * ci.scale);
-                k = k < 0 ? 0 : (k >= n_bins ? n_bins - 1 : k);
-                atomicAdd(h + k, 1u);
+            for (int64_t r = r0 + ph; r < r1; r += 4 * (int64_t)rpt) {
+                float v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t q = r + (int64_t)u * rpt;
+                    v[u] = q < r1 ? m[q * ld + c] : __builtin_nanf("");
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (!finite(v[u])) continue;
+                    int k = (int)__builtin_floor(((double)v[u] - ci.lo) * ci.scale);
+                    k = k < 0 ? 0 : (k >= n_bins ? n_bins - 1 : k);
+                    atomicAdd(h + k, 1u);
+                }
             }
         }
     }
