@@ -491,12 +491,16 @@ __global__ void __launch_bounds__(W1_THREADS)
     }
 }
 
-__global__ void w1_colinfo(int n_cols, int n_bins, const Partial *pr, int rbr, const Partial *ps,
-                           int rbs, ColInfo *info) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per column: lane k adds the partials of row blocks k, k + 64, ...
+// in order, then the lanes' sums are combined by a fixed butterfly (the same
+// order on every run).
+__global__ void __launch_bounds__(WAVE) w1_colinfo(int n_cols, int n_bins, const Partial *pr, int rbr,
+                                                   const Partial *ps, int rbs, ColInfo *info) {
+    const int c = blockIdx.x;
+    const int lane = threadIdx.x;
     if (c >= n_cols) return;
     double nr = 0.0, s1 = 0.0, s2 = 0.0, mnr = __builtin_inf(), mxr = -__builtin_inf();
-    for (int b = 0; b < rbr; ++b) {
+    for (int b = lane; b < rbr; b += WAVE) {
         const Partial p = pr[(size_t)b * n_cols + c];
         nr += p.cnt;
         s1 += p.s1;
@@ -505,12 +509,26 @@ __global__ void w1_colinfo(int n_cols, int n_bins, const Partial *pr, int rbr, c
         mxr = p.mx > mxr ? p.mx : mxr;
     }
     double ns = 0.0, mns = __builtin_inf(), mxs = -__builtin_inf();
-    for (int b = 0; b < rbs; ++b) {
+    for (int b = lane; b < rbs; b += WAVE) {
         const Partial p = ps[(size_t)b * n_cols + c];
         ns += p.cnt;
         mns = p.mn < mns ? p.mn : mns;
         mxs = p.mx > mxs ? p.mx : mxs;
     }
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        nr += __shfl_xor(nr, d);
+        s1 += __shfl_xor(s1, d);
+        s2 += __shfl_xor(s2, d);
+        ns += __shfl_xor(ns, d);
+        const double a = __shfl_xor(mnr, d), b = __shfl_xor(mxr, d);
+        const double e = __shfl_xor(mns, d), f = __shfl_xor(mxs, d);
+        mnr = a < mnr ? a : mnr;
+        mxr = b > mxr ? b : mxr;
+        mns = e < mns ? e : mns;
+        mxs = f > mxs ? f : mxs;
+    }
+    if (lane != 0) return;
     ColInfo ci;
     ci.skip = (nr < 2.0 || ns < 1.0 || mnr == mxr) ? 1 : 0;
     ci.pad = 0;
@@ -614,20 +632,27 @@ __global__ void __launch_bounds__(WAVE)
     if (lane == 0) w1[c] = ci.width / (double)n_bins * acc / ci.sigma;
 }
 
-__global__ void w1_groups(int n_cols, const int32_t *group, int n_groups, const double *w1,
-                          double *out) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per group: lanes take columns c = lane, lane + 64, ...; the sums
+// are combined by a fixed butterfly.
+__global__ void __launch_bounds__(WAVE) w1_groups(int n_cols, const int32_t *group, int n_groups,
+                                                  const double *w1, double *out) {
+    const int g = blockIdx.x;
+    const int lane = threadIdx.x;
     if (g >= n_groups) return;
     double s = 0.0;
     int k = 0;
-    for (int c = 0; c < n_cols; ++c) {
-        if (group[c] != g) continue;
+    for (int c = lane; c < n_cols; c += WAVE) {
         const double v = w1[c];
-        if (v != v) continue;
-        s += v;
-        ++k;
+        const bool in = group[c] == g && v == v;
+        s += in ? v : 0.0;
+        k += in ? 1 : 0;
     }
-    out[g] = k ? s / k : __builtin_nan("");
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        s += __shfl_xor(s, d);
+        k += __shfl_xor(k, d);
+    }
+    if (lane == 0) out[g] = k ? s / k : __builtin_nan("");
 }
 
 inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -765,7 +790,7 @@ extern "C" supa_status supa_w1_normalized(void *stream, int32_t n_cols, const fl
                        n_cols, w.ct, w.rbr, pr);
     hipLaunchKernelGGL(w1_stats, dim3(w.tiles, w.rbs), dim3(W1_THREADS), 0, s, smp, n_smp, smp_ld,
                        n_cols, w.ct, w.rbs, ps);
-    hipLaunchKernelGGL(w1_colinfo, dim3((n_cols + 255) / 256), dim3(256), 0, s, n_cols, n_bins, pr,
+    hipLaunchKernelGGL(w1_colinfo, dim3(n_cols), dim3(WAVE), 0, s, n_cols, n_bins, pr,
                        w.rbr, ps, w.rbs, info);
     const size_t lds = (size_t)w.ct * n_bins * 4;
     hipLaunchKernelGGL(w1_hist, dim3(w.tiles, w.rbr), dim3(W1_THREADS), lds, s, ref, n_ref, ref_ld,
@@ -774,7 +799,7 @@ extern "C" supa_status supa_w1_normalized(void *stream, int32_t n_cols, const fl
                        n_cols, w.ct, w.rbs, n_bins, info, hs);
     hipLaunchKernelGGL(w1_distance, dim3(n_cols), dim3(WAVE), 0, s, n_cols, n_bins, info, hr, hs, w1);
     if (group_of_col)
-        hipLaunchKernelGGL(w1_groups, dim3((n_groups + 63) / 64), dim3(64), 0, s, n_cols, group_of_col,
+        hipLaunchKernelGGL(w1_groups, dim3(n_groups), dim3(WAVE), 0, s, n_cols, group_of_col,
                            n_groups, w1, group_mean);
     return dev_err(hipGetLastError(), "w1 kernels");
 }
