@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define SUPA_ABI_VERSION 3
+#define SUPA_ABI_VERSION 4
 
 typedef enum supa_status {
     SUPA_OK = 0,

@@ -82,10 +82,16 @@ enum {
  *   n_layers      L, 1..64; hit layers must be < L
  *   layer_vars    out, float [n][L][SUPA_LAYER_VARS]
  *   shower_vars   out, float [n][SUPA_SHOWER_VARS]
- *   work          device, 4 int32 owned by the caller, overwritten: after the
- *                 call work[0] holds the number of showers that broke the
- *                 contiguity rule or carried a layer >= L (all their
- *                 variables are NaN); the rest is the kernel's own.
+ *   work          device, work_ints >= supa_shapes_work_ints(n) int32 owned
+ *                 by the caller, overwritten: after the call work[0] holds
+ *                 the number of showers that broke the contiguity rule or
+ *                 carried a layer >= L (all their variables are NaN); the
+ *                 rest is the kernel's own (a work queue, and the order in
+ *                 which showers are taken: longest first within windows of
+ *                 consecutive showers, so that the lanes of a wave carry
+ *                 showers of similar length while the showers in flight stay
+ *                 close together in memory).  The results do not depend on
+ *                 that order.
  * Sums are taken in double precision; results are rounded to float.
  */
 supa_status supa_shower_shapes(void *hip_stream, int64_t n, int32_t n_layers,
@@ -93,7 +99,11 @@ supa_status supa_shower_shapes(void *hip_stream, int64_t n, int32_t n_layers,
                                int32_t counts_stride, int64_t hit_len, const float *hit_x,
                                const float *hit_y,
                                const float *hit_e, const int32_t *hit_layer, float *layer_vars,
-                               float *shower_vars, int32_t *work);
+                               float *shower_vars, int32_t *work, int64_t work_ints);
+
+/* int32 entries of supa_shower_shapes' work array for n showers (4 + n;
+ * -1 for n < 0). */
+int64_t supa_shapes_work_ints(int64_t n);
 
 /* r = sqrt(x^2 + y^2) for n points (float, rounded from double), the radial
  * point feature whose marginal the paper compares besides eta, phi and E. */

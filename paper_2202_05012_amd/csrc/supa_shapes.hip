@@ -45,7 +45,8 @@ struct ShapeArgs {
     const float *x, *y, *e;
     const int32_t *layer;
     float *lv, *sv;
-    int32_t *work;  // [0] showers in error, [1] next shower (queue)
+    int32_t *work;         // [0] showers in error, [1] next shower (queue)
+    const int32_t *order;  // [n] showers in the order they are taken
 };
 
 // Sums of one layer run, in double precision.
@@ -152,6 +153,52 @@ __device__ inline void write_empty_layer(float *rec) {
 
 __global__ void shapes_clear(int32_t *work) {
     if (threadIdx.x < 4) work[threadIdx.x] = 0;
+}
+
+// Order in which the lanes take showers: within each window of ORDER_WIN
+// consecutive showers, longest first (ties by index).  A wave's lanes then
+// carry showers of similar length, so fewer lanes idle while the longest one
+// finishes; windows keep the showers in flight close together in memory.  A
+// window holds 63 waves' worth of showers, so that the first (longest) wave
+// of consecutive windows falls on different XCDs.  One workgroup per window:
+// bitonic sort of (count, index) keys in LDS.
+constexpr int ORDER_SLOTS = 4096;
+constexpr int ORDER_WIN = 63 * WAVE;
+constexpr int ORDER_THREADS = 1024;
+
+__global__ void __launch_bounds__(ORDER_THREADS)
+    shapes_order(int64_t n, const int32_t *cnt, int cstride, int32_t *order) {
+    __shared__ uint64_t key[ORDER_SLOTS];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * ORDER_WIN;
+    const int64_t m64 = n - base < ORDER_WIN ? n - base : ORDER_WIN;
+    const int m = (int)m64;
+    for (int i = t; i < ORDER_SLOTS; i += ORDER_THREADS) {
+        uint64_t k = ~0ull;  // empty slots sort last
+        if (i < m) {
+            const int32_t c = cnt[(size_t)(base + i) * cstride];
+            const uint32_t u = c > 0 ? (uint32_t)c : 0u;
+            k = ((uint64_t)(0xFFFFFFFFu - u) << 32) | (uint32_t)i;
+        }
+        key[i] = k;
+    }
+    __syncthreads();
+    for (int k = 2; k <= ORDER_SLOTS; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = t; i < ORDER_SLOTS; i += ORDER_THREADS) {
+                const int p = i ^ j;
+                if (p > i) {
+                    const uint64_t a = key[i], b = key[p];
+                    if ((a > b) == ((i & k) == 0)) {
+                        key[i] = b;
+                        key[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = t; i < m; i += ORDER_THREADS) order[base + i] = (int32_t)(base + (uint32_t)key[i]);
 }
 
 // Records of finished layer runs wait in a per-wave LDS ring until 64 are
@@ -294,7 +341,7 @@ __global__ void __launch_bounds__(WAVE) shapes_kernel(ShapeArgs A) {
             if ((int64_t)next >= A.n) {
                 active = false;
             } else {
-                s = next;
+                s = A.order[next];
                 pos = A.off[s];
                 end = pos + A.cnt[(size_t)s * A.cstride];
                 // a segment reaching outside the arrays is the caller's error;
@@ -714,17 +761,20 @@ supa_status dev_err(hipError_t e, const char *what) {
 
 extern "C" const char *supa_shapes_last_error(void) { return t_err.c_str(); }
 
+extern "C" int64_t supa_shapes_work_ints(int64_t n) { return n < 0 ? -1 : 4 + n; }
+
 extern "C" supa_status supa_shower_shapes(void *stream, int64_t n, int32_t n_layers,
                                           const int64_t *hit_offsets, const int32_t *hit_counts,
                                           int32_t counts_stride, int64_t hit_len, const float *hit_x,
                                           const float *hit_y, const float *hit_e,
                                           const int32_t *hit_layer, float *layer_vars,
-                                          float *shower_vars, int32_t *work) {
+                                          float *shower_vars, int32_t *work, int64_t work_ints) {
     if (n < 0 || n > INT32_MAX) return bad_arg("n out of range");
     if (n_layers < 1 || n_layers > 64) return bad_arg("n_layers must be 1..64");
     if (counts_stride < 1) return bad_arg("counts_stride must be >= 1");
     if (hit_len < 0) return bad_arg("hit_len < 0");
     if (!work) return bad_arg("work is NULL");
+    if (work_ints < supa_shapes_work_ints(n)) return bad_arg("work holds fewer than 4 + n int32");
     if (n > 0 && (!hit_offsets || !hit_counts || !hit_x || !hit_y || !hit_e || !hit_layer ||
                   !layer_vars || !shower_vars))
         return bad_arg("NULL array");
@@ -735,8 +785,11 @@ extern "C" supa_status supa_shower_shapes(void *stream, int64_t n, int32_t n_lay
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(shapes_clear, dim3(1), dim3(WAVE), 0, s, work);
     if (n == 0) return dev_err(hipGetLastError(), "shapes_clear");
+    int32_t *order = work + 4;
+    hipLaunchKernelGGL(shapes_order, dim3((int)((n + ORDER_WIN - 1) / ORDER_WIN)), dim3(ORDER_THREADS), 0, s,
+                       n, hit_counts, counts_stride, order);
     ShapeArgs A{n, n_layers, hit_offsets, hit_counts, counts_stride, hit_len, hit_x, hit_y, hit_e,
-                hit_layer, layer_vars, shower_vars, work};
+                hit_layer, layer_vars, shower_vars, work, order};
     const int64_t waves = (n + WAVE - 1) / WAVE;
     const int64_t cap = (int64_t)cu_count() * 16;
     const int grid = (int)(waves < cap ? waves : cap);

@@ -26,7 +26,9 @@ def _lib():
     if not hasattr(L, "_shapes_bound"):
         vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
         sig = {
-            "supa_shower_shapes": (C.c_int, [vp, i64, i32, vp, vp, i32, i64, vp, vp, vp, vp, vp, vp, vp]),
+            "supa_shower_shapes": (C.c_int, [vp, i64, i32, vp, vp, i32, i64, vp, vp, vp, vp, vp, vp, vp,
+                                             i64]),
+            "supa_shapes_work_ints": (i64, [i64]),
             "supa_hit_radius": (C.c_int, [vp, i64, vp, vp, vp]),
             "supa_w1_workspace_bytes": (sz, [i32, i32, i64, i64]),
             "supa_w1_normalized": (C.c_int, [vp, i32, vp, i64, i64, vp, i64, i64, i32, vp, i32, vp, vp,
@@ -67,13 +69,13 @@ def shower_shapes(hit_offsets, hit_counts, hit_x, hit_y, hit_e, hit_layer, n_lay
     dev = hit_x.device
     lv = torch.empty((n, n_layers, len(LAYER_VARS)), dtype=torch.float32, device=dev)
     sv = torch.empty((n, len(SHOWER_VARS)), dtype=torch.float32, device=dev)
-    work = torch.empty(4, dtype=torch.int32, device=dev)
+    work = torch.empty(int(L.supa_shapes_work_ints(n)), dtype=torch.int32, device=dev)
     if not all(t.is_contiguous() for t in (hit_x, hit_y, hit_e, hit_layer)):
         raise ValueError("hit arrays must be contiguous")
     hit_len = min(int(t.numel()) for t in (hit_x, hit_y, hit_e, hit_layer))
     _check(L.supa_shower_shapes(_stream(), n, n_layers, _p(hit_offsets), _p(hit_counts), counts_stride,
                                 hit_len, _p(hit_x), _p(hit_y), _p(hit_e), _p(hit_layer), _p(lv),
-                                _p(sv), _p(work)))
+                                _p(sv), _p(work), work.numel()))
     if check:
         bad = int(work[0].item())
         if bad:
