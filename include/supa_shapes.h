@@ -86,12 +86,13 @@ enum {
  *                 by the caller, overwritten: after the call work[0] holds
  *                 the number of showers that broke the contiguity rule or
  *                 carried a layer >= L (all their variables are NaN); the
- *                 rest is the kernel's own (a work queue, and the order in
- *                 which showers are taken: longest first within windows of
- *                 consecutive showers, so that the lanes of a wave carry
- *                 showers of similar length while the showers in flight stay
- *                 close together in memory).  The results do not depend on
- *                 that order.
+ *                 rest is the kernel's own (a work queue, bucket counts, and
+ *                 the order in which showers are taken: longest first, over
+ *                 the whole batch when every shower fits in flight at once,
+ *                 else within windows of consecutive showers, so that the
+ *                 lanes of a wave carry showers of similar length while the
+ *                 showers in flight stay close together in memory).  The
+ *                 results do not depend on that order.
  * Sums are taken in double precision; results are rounded to float.
  */
 supa_status supa_shower_shapes(void *hip_stream, int64_t n, int32_t n_layers,
@@ -101,7 +102,7 @@ supa_status supa_shower_shapes(void *hip_stream, int64_t n, int32_t n_layers,
                                const float *hit_e, const int32_t *hit_layer, float *layer_vars,
                                float *shower_vars, int32_t *work, int64_t work_ints);
 
-/* int32 entries of supa_shower_shapes' work array for n showers (4 + n;
+/* int32 entries of supa_shower_shapes' work array for n showers (2052 + n;
  * -1 for n < 0). */
 int64_t supa_shapes_work_ints(int64_t n);
 

@@ -151,54 +151,129 @@ __device__ inline void write_empty_layer(float *rec) {
     rec[SUPA_LV_ENERGY_RATIO] = nan;
 }
 
+// work: [0] showers in error, [1] queue, [2, 4) unused, then the global
+// order's bucket sizes and cursors (ORDER_BUCKETS each), then the order [n].
+constexpr int ORDER_BUCKETS = 1024;
+constexpr int WORK_HEAD = 4 + 2 * ORDER_BUCKETS;
+
 __global__ void shapes_clear(int32_t *work) {
-    if (threadIdx.x < 4) work[threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < WORK_HEAD; i += blockDim.x) work[i] = 0;
 }
 
-// Order in which the lanes take showers: within each window of ORDER_WIN
-// consecutive showers, longest first (ties by index).  A wave's lanes then
-// carry showers of similar length, so fewer lanes idle while the longest one
-// finishes; windows keep the showers in flight close together in memory.  A
-// window holds 63 waves' worth of showers, so that the first (longest) wave
-// of consecutive windows falls on different XCDs.  One workgroup per window:
-// bitonic sort of (count, index) keys in LDS.
-constexpr int ORDER_SLOTS = 4096;
+// Order in which the lanes take showers: longest first, within windows of
+// consecutive showers.  A wave's lanes then carry showers of similar length,
+// so fewer lanes idle while the longest one finishes.  When every shower is
+// in flight at once (one per lane) the window is the whole batch, sorted by
+// two kernels (global bucket sizes, then each block reserves its range of
+// every bucket with one atomic); otherwise windows of ORDER_WIN keep the
+// showers in flight close together in memory, each sorted by one workgroup,
+// and hold 63 waves' worth of showers so that the first (longest) wave of
+// consecutive windows falls on different XCDs.  Both are counting sorts into
+// 1024 buckets of the hit count on a log scale (32 per octave); the order
+// within a bucket is whatever the atomics give, which changes no result (each
+// shower is summed by one lane in its own hit order).
 constexpr int ORDER_WIN = 63 * WAVE;
 constexpr int ORDER_THREADS = 1024;
 
+__device__ inline int count_bucket(int32_t c) {  // 0..1023, non-decreasing in c
+    const uint32_t v = (c > 0 ? (uint32_t)c : 0u) + 1u;
+    const int e = 31 - __builtin_clz(v);
+    const uint32_t m = e >= 5 ? (v >> (e - 5)) & 31u : (v << (5 - e)) & 31u;
+    return e * 32 + (int)m;
+}
+
+// dst[b] = sum of src[0 .. b) over the ORDER_BUCKETS buckets, by one wave
+// (lane t < 64 of the caller); dst may be src.
+__device__ inline void bucket_starts(const uint32_t *src, uint32_t *dst, int t) {
+    constexpr int Q = ORDER_BUCKETS / WAVE;
+    uint32_t v[Q], sum = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        v[q] = src[t * Q + q];
+        sum += v[q];
+    }
+    uint32_t inc = sum;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d);
+        if (t >= d) inc += o;
+    }
+    uint32_t run = inc - sum;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        dst[t * Q + q] = run;
+        run += v[q];
+    }
+}
+
 __global__ void __launch_bounds__(ORDER_THREADS)
-    shapes_order(int64_t n, const int32_t *cnt, int cstride, int32_t *order) {
-    __shared__ uint64_t key[ORDER_SLOTS];
+    shapes_order(int64_t n, int64_t win, const int32_t *cnt, int cstride, int32_t *order) {
+    __shared__ uint32_t hist[ORDER_BUCKETS];
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * ORDER_WIN;
-    const int64_t m64 = n - base < ORDER_WIN ? n - base : ORDER_WIN;
-    const int m = (int)m64;
-    for (int i = t; i < ORDER_SLOTS; i += ORDER_THREADS) {
-        uint64_t k = ~0ull;  // empty slots sort last
-        if (i < m) {
-            const int32_t c = cnt[(size_t)(base + i) * cstride];
-            const uint32_t u = c > 0 ? (uint32_t)c : 0u;
-            k = ((uint64_t)(0xFFFFFFFFu - u) << 32) | (uint32_t)i;
-        }
-        key[i] = k;
+    const int64_t base = (int64_t)blockIdx.x * win;
+    const int64_t m = n - base < win ? n - base : win;
+    for (int i = t; i < ORDER_BUCKETS; i += ORDER_THREADS) hist[i] = 0;
+    __syncthreads();
+    for (int64_t i = t; i < m; i += ORDER_THREADS)
+        atomicAdd(&hist[ORDER_BUCKETS - 1 - count_bucket(cnt[(size_t)(base + i) * cstride])], 1u);
+    __syncthreads();
+    if (t < WAVE) bucket_starts(hist, hist, t);
+    __syncthreads();
+    // hist now holds each bucket's next free position
+    for (int64_t i = t; i < m; i += ORDER_THREADS) {
+        const int b = ORDER_BUCKETS - 1 - count_bucket(cnt[(size_t)(base + i) * cstride]);
+        order[base + atomicAdd(&hist[b], 1u)] = (int32_t)(base + i);
+    }
+}
+
+// Whole-batch order, pass 1: sizes of the buckets (gsize, zeroed before).
+constexpr int ORDER_CHUNK = 4 * ORDER_THREADS;  // showers per block of the two passes
+
+__global__ void __launch_bounds__(ORDER_THREADS)
+    shapes_order_sizes(int64_t n, const int32_t *cnt, int cstride, uint32_t *gsize) {
+    __shared__ uint32_t hist[ORDER_BUCKETS];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * ORDER_CHUNK;
+    const int64_t m = n - base < ORDER_CHUNK ? n - base : ORDER_CHUNK;
+    for (int i = t; i < ORDER_BUCKETS; i += ORDER_THREADS) hist[i] = 0;
+    __syncthreads();
+    for (int64_t i = t; i < m; i += ORDER_THREADS)
+        atomicAdd(&hist[ORDER_BUCKETS - 1 - count_bucket(cnt[(size_t)(base + i) * cstride])], 1u);
+    __syncthreads();
+    for (int i = t; i < ORDER_BUCKETS; i += ORDER_THREADS)
+        if (hist[i]) atomicAdd(&gsize[i], hist[i]);
+}
+
+// Pass 2: each block reserves its range of every bucket (gcur, zeroed
+// before) and places its showers.
+__global__ void __launch_bounds__(ORDER_THREADS)
+    shapes_order_place(int64_t n, const int32_t *cnt, int cstride, const uint32_t *gsize, uint32_t *gcur,
+                       int32_t *order) {
+    __shared__ uint32_t hist[ORDER_BUCKETS], start[ORDER_BUCKETS];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * ORDER_CHUNK;
+    const int64_t m = n - base < ORDER_CHUNK ? n - base : ORDER_CHUNK;
+    for (int i = t; i < ORDER_BUCKETS; i += ORDER_THREADS) {
+        hist[i] = 0;
+        start[i] = gsize[i];
     }
     __syncthreads();
-    for (int k = 2; k <= ORDER_SLOTS; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = t; i < ORDER_SLOTS; i += ORDER_THREADS) {
-                const int p = i ^ j;
-                if (p > i) {
-                    const uint64_t a = key[i], b = key[p];
-                    if ((a > b) == ((i & k) == 0)) {
-                        key[i] = b;
-                        key[p] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    if (t < WAVE) bucket_starts(start, start, t);
+    int bk[4];
+    uint32_t rank[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t i = t + (int64_t)u * ORDER_THREADS;
+        bk[u] = i < m ? ORDER_BUCKETS - 1 - count_bucket(cnt[(size_t)(base + i) * cstride]) : -1;
+        rank[u] = bk[u] >= 0 ? atomicAdd(&hist[bk[u]], 1u) : 0u;
     }
-    for (int i = t; i < m; i += ORDER_THREADS) order[base + i] = (int32_t)(base + (uint32_t)key[i]);
+    __syncthreads();
+    for (int i = t; i < ORDER_BUCKETS; i += ORDER_THREADS)
+        if (hist[i]) start[i] += atomicAdd(&gcur[i], hist[i]);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (bk[u] >= 0) order[start[bk[u]] + rank[u]] = (int32_t)(base + t + (int64_t)u * ORDER_THREADS);
 }
 
 // Records of finished layer runs wait in a per-wave LDS ring until 64 are
@@ -761,7 +836,7 @@ supa_status dev_err(hipError_t e, const char *what) {
 
 extern "C" const char *supa_shapes_last_error(void) { return t_err.c_str(); }
 
-extern "C" int64_t supa_shapes_work_ints(int64_t n) { return n < 0 ? -1 : 4 + n; }
+extern "C" int64_t supa_shapes_work_ints(int64_t n) { return n < 0 ? -1 : WORK_HEAD + n; }
 
 extern "C" supa_status supa_shower_shapes(void *stream, int64_t n, int32_t n_layers,
                                           const int64_t *hit_offsets, const int32_t *hit_counts,
@@ -774,7 +849,7 @@ extern "C" supa_status supa_shower_shapes(void *stream, int64_t n, int32_t n_lay
     if (counts_stride < 1) return bad_arg("counts_stride must be >= 1");
     if (hit_len < 0) return bad_arg("hit_len < 0");
     if (!work) return bad_arg("work is NULL");
-    if (work_ints < supa_shapes_work_ints(n)) return bad_arg("work holds fewer than 4 + n int32");
+    if (work_ints < supa_shapes_work_ints(n)) return bad_arg("work holds fewer than supa_shapes_work_ints(n) int32");
     if (n > 0 && (!hit_offsets || !hit_counts || !hit_x || !hit_y || !hit_e || !hit_layer ||
                   !layer_vars || !shower_vars))
         return bad_arg("NULL array");
@@ -783,16 +858,25 @@ extern "C" supa_status supa_shower_shapes(void *stream, int64_t n, int32_t n_lay
         return bad_arg("hit arrays must be 16-byte aligned");
     if (n > 0 && ((uintptr_t)layer_vars & 7)) return bad_arg("layer_vars must be 8-byte aligned");
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(shapes_clear, dim3(1), dim3(WAVE), 0, s, work);
+    hipLaunchKernelGGL(shapes_clear, dim3(1), dim3(1024), 0, s, work);
     if (n == 0) return dev_err(hipGetLastError(), "shapes_clear");
-    int32_t *order = work + 4;
-    hipLaunchKernelGGL(shapes_order, dim3((int)((n + ORDER_WIN - 1) / ORDER_WIN)), dim3(ORDER_THREADS), 0, s,
-                       n, hit_counts, counts_stride, order);
-    ShapeArgs A{n, n_layers, hit_offsets, hit_counts, counts_stride, hit_len, hit_x, hit_y, hit_e,
-                hit_layer, layer_vars, shower_vars, work, order};
     const int64_t waves = (n + WAVE - 1) / WAVE;
     const int64_t cap = (int64_t)cu_count() * 16;
     const int grid = (int)(waves < cap ? waves : cap);
+    int32_t *order = work + WORK_HEAD;
+    if (waves <= cap) {  // every shower in flight at once (one per lane): one order
+        uint32_t *gsize = (uint32_t *)work + 4, *gcur = gsize + ORDER_BUCKETS;
+        const int blocks = (int)((n + ORDER_CHUNK - 1) / ORDER_CHUNK);
+        hipLaunchKernelGGL(shapes_order_sizes, dim3(blocks), dim3(ORDER_THREADS), 0, s, n, hit_counts,
+                           counts_stride, gsize);
+        hipLaunchKernelGGL(shapes_order_place, dim3(blocks), dim3(ORDER_THREADS), 0, s, n, hit_counts,
+                           counts_stride, gsize, gcur, order);
+    } else {
+        hipLaunchKernelGGL(shapes_order, dim3((int)((n + ORDER_WIN - 1) / ORDER_WIN)), dim3(ORDER_THREADS), 0,
+                           s, n, (int64_t)ORDER_WIN, hit_counts, counts_stride, order);
+    }
+    ShapeArgs A{n, n_layers, hit_offsets, hit_counts, counts_stride, hit_len, hit_x, hit_y, hit_e,
+                hit_layer, layer_vars, shower_vars, work, order};
     hipLaunchKernelGGL(shapes_kernel, dim3(grid), dim3(WAVE), (size_t)n_layers * WAVE * sizeof(float),
                        s, A);
     return dev_err(hipGetLastError(), "shapes_kernel");

@@ -72,17 +72,17 @@ def test_shape_entry_points_reject_bad_arguments_on_the_host():
     L = shapes._lib()
     fake = C.c_void_p(4096)                       # never dereferenced: rejected first
     assert L.supa_shower_shapes(None, 10, 65, fake, fake, 1, 100, fake, fake, fake, fake, fake,
-                                fake, fake, 14) == 1
+                                fake, fake, 2062) == 1
     assert L.supa_shower_shapes(None, 10, 20, fake, fake, 0, 100, fake, fake, fake, fake, fake,
-                                fake, fake, 14) == 1
+                                fake, fake, 2062) == 1
     assert L.supa_shower_shapes(None, 10, 20, fake, fake, 1, -1, fake, fake, fake, fake, fake,
-                                fake, fake, 14) == 1
+                                fake, fake, 2062) == 1
     assert L.supa_shower_shapes(None, 10, 20, fake, fake, 1, 100, C.c_void_p(4100), fake, fake,
-                                fake, fake, fake, fake, 14) == 1     # misaligned hit array
+                                fake, fake, fake, fake, 2062) == 1     # misaligned hit array
     assert "aligned" in L.supa_shapes_last_error().decode()
-    assert L.supa_shapes_work_ints(10) == 14 and L.supa_shapes_work_ints(-1) == -1
+    assert L.supa_shapes_work_ints(10) == 2062 and L.supa_shapes_work_ints(-1) == -1
     assert L.supa_shower_shapes(None, 10, 20, fake, fake, 1, 100, fake, fake, fake, fake, fake,
-                                fake, fake, 13) == 1     # work too short for 10 showers
+                                fake, fake, 2061) == 1     # work too short for 10 showers
     assert "work" in L.supa_shapes_last_error().decode()
     assert L.supa_w1_workspace_bytes(0, 10, 5, 5) == 0
     need = L.supa_w1_workspace_bytes(7, 100, 1000, 2000)

@@ -278,6 +278,44 @@ def test_full_size_100k_shapes_sampled():
         check_shapes(lv[it], sv[it], rlv, rsv, coord_atol=1e-5 * max(rmax, 1.0))
 
 
+@pytest.mark.parametrize("n", [5_000, 600_000])
+def test_every_shower_once_in_either_order(n):
+    """Showers are taken longest first: by one order over the whole batch when
+    every shower is in flight at once, by windows of consecutive showers when
+    there are more showers than lanes (600,000 > 256 CUs x 16 waves x 64).
+    Either way every shower is measured once: counts per (shower, layer) and
+    layer energies against bincounts over all showers, every variable against
+    the oracle on 300 sampled showers."""
+    rng = np.random.default_rng(11)
+    L = 12
+    m = rng.integers(0, 41, n)
+    m[rng.random(n) < 0.02] = 400                   # a few long showers
+    off = np.concatenate([[0], np.cumsum(m)[:-1]]).astype(np.int64)
+    sid = np.repeat(np.arange(n), m)
+    j = np.arange(len(sid)) - off[sid]              # hit index within its shower
+    nl = rng.integers(1, L + 1, n)
+    first = rng.integers(0, L - nl + 1)
+    lay = (first[sid] + (j * nl[sid]) // m[sid]).astype(np.int32)
+    x = rng.normal(0, 3, len(sid)).astype(np.float32)
+    y = rng.normal(0, 3, len(sid)).astype(np.float32)
+    e = rng.exponential(1.0, len(sid)).astype(np.float32)
+    lv, sv = SH.shower_shapes(_t(off), _t(m.astype(np.int32)), _t(x), _t(y), _t(e), _t(lay), L)
+    glv, gsv = lv.cpu().numpy(), sv.cpu().numpy()
+    key = sid * L + lay
+    cnt = np.bincount(key, minlength=n * L).reshape(n, L)
+    np.testing.assert_array_equal(glv[..., LV["count"]], cnt)
+    en = np.bincount(key, weights=e.astype(np.float64), minlength=n * L).reshape(n, L)
+    np.testing.assert_allclose(glv[..., LV["energy"]], en, rtol=4e-7, atol=0)
+    np.testing.assert_allclose(gsv[:, SV["e_tot"]], en.sum(1), rtol=4e-7, atol=0)
+    pick = np.sort(rng.choice(n, 300, replace=False))
+    sel = np.isin(sid, pick)
+    local = np.searchsorted(pick, sid[sel])
+    rlv, rsv = SO.shapes(len(pick), L, local, lay[sel], x[sel].astype(np.float64),
+                         y[sel].astype(np.float64), e[sel].astype(np.float64))
+    it = torch.from_numpy(pick).cuda()
+    check_shapes(lv[it], sv[it], rlv, rsv)
+
+
 def test_usage_example():
     """The usage example of the README, end to end: SUPAv1 showers, their shape
     variables and 2x grids (128 points of 65/128 in layer 0, fraction 1)."""
