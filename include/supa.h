@@ -278,7 +278,11 @@ supa_status supa_autotune(supa_ctx *ctx, const supa_batch *b, uint64_t seed, sup
  *                      total hits, nodes, steps.
  *   supa_graph_destroy frees the graph.
  * A graph shares the context's counters and scratch: replays and other calls
- * on one context must not overlap in time.
+ * on one context must not overlap in time.  A later call on the context that
+ * needs more scratch than the capture's (a larger batch, more hits or nodes,
+ * other launch settings) reallocates it; the graph is then stale, and
+ * supa_graph_launch and supa_graph_check return SUPA_ERR_STATE without
+ * launching anything: capture it again.
  */
 typedef struct supa_graph supa_graph;
 supa_status supa_graph_create(supa_ctx *ctx, const supa_batch *b, uint64_t seed, supa_output *out,

@@ -34,12 +34,15 @@ hipError_t launch_cost_order(const float *e0, int n, float e_scale, uint32_t *hi
                              int n_cu, hipStream_t s);
 }  // namespace supa
 
-// A device buffer that only grows (its contents are scratch).
+// A device buffer that only grows (its contents are scratch).  Every
+// reallocation advances *gen, so that a captured graph holding the old
+// address can tell that it is stale.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
-    bool ensure(size_t need) {
+    bool ensure(size_t need, uint64_t *gen) {
         if (need <= bytes) return true;
+        ++*gen;
         if (p) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
@@ -93,6 +96,7 @@ struct supa_ctx {
     int cost_order = -1;                 // hand out expensive showers first: 1 on, 0 off, -1 auto
     int last_sub_batches = 0;
     DevBuf spill, hlog, nlog, shower, bucket;
+    uint64_t scratch_gen = 0;            // advanced by every scratch reallocation
     // the placement of a sub-batch runs on a second stream, overlapping the
     // propagation of the next one
     hipStream_t aux = nullptr;
@@ -312,7 +316,10 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
 extern "C" supa_status supa_destroy(supa_ctx *c) {
     if (!c) return SUPA_ERR_STATE;
     (void)hipSetDevice(c->device);
-    if (c->stream || true) (void)hipStreamSynchronize(c->stream);
+    // both streams drain before their scratch is freed (a null stream is
+    // the default stream, also synchronised)
+    (void)hipStreamSynchronize(c->stream);
+    if (c->aux) (void)hipStreamSynchronize(c->aux);
     for (DevBuf *d : {&c->spill, &c->hlog, &c->nlog, &c->shower, &c->bucket}) d->release();
     if (c->d_layer) (void)hipFree(c->d_layer);
     if (c->d_layer_plane_start) (void)hipFree(c->d_layer_plane_start);
@@ -323,7 +330,6 @@ extern "C" supa_status supa_destroy(supa_ctx *c) {
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     if (c->d_cold) (void)hipFree(c->d_cold);
     if (c->h_cold) (void)hipHostFree(c->h_cold);
-    if (c->aux) (void)hipStreamSynchronize(c->aux);
     for (hipEvent_t e : {c->ev_begin, c->ev_end, c->ev_joined})
         if (e) (void)hipEventDestroy(e);
     for (int b = 0; b < supa::MAX_SUB; ++b)
@@ -456,19 +462,19 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
 
     // scratch: per-wave spill, logs, per-shower log starts, scan tile sums, work order
     const size_t spill_b = al256((size_t)L.waves * supa::POOL_FIELDS * c->spill_cap * 4);
-    if (!c->spill.ensure(spill_b)) return nomem(c, "spill area", spill_b);
+    if (!c->spill.ensure(spill_b, &c->scratch_gen)) return nomem(c, "spill area", spill_b);
     const size_t hnext_b = L.recs ? al256((size_t)c->h_chunks * 4) : 0;
     const size_t hlog_b = L.recs ? hnext_b + (size_t)c->h_chunks * supa::HIT_CHUNK_WORDS * 4 : 0;
-    if (L.recs && !c->hlog.ensure(hlog_b)) return nomem(c, "hit log", hlog_b);
+    if (L.recs && !c->hlog.ensure(hlog_b, &c->scratch_gen)) return nomem(c, "hit log", hlog_b);
     const size_t nfill_b = L.tree ? al256((size_t)c->n_chunks * 4) : 0;
     const size_t nlog_b = L.tree ? nfill_b + (size_t)c->n_chunks * supa::NL_FIELDS * supa::LOG_CHUNK * 4 : 0;
-    if (L.tree && !c->nlog.ensure(nlog_b)) return nomem(c, "node log", nlog_b);
+    if (L.tree && !c->nlog.ensure(nlog_b, &c->scratch_gen)) return nomem(c, "node log", nlog_b);
     const size_t hstart_b = L.recs ? al256((size_t)n * 8) : 0;
     const size_t part_b = al256((size_t)supa::scan_partial_words(n) * 8);
     const bool ordered = c->cost_order > 0 || (c->cost_order < 0 && n >= kAutoOrderMin);
     const size_t order_b = ordered ? al256((size_t)n * 4) + al256((size_t)supa::order_scratch_words() * 4) : 0;
     const size_t shower_b = hstart_b + part_b + order_b;
-    if (!c->shower.ensure(shower_b)) return nomem(c, "per-shower scratch", shower_b);
+    if (!c->shower.ensure(shower_b, &c->scratch_gen)) return nomem(c, "per-shower scratch", shower_b);
     char *sh = (char *)c->shower.p;
     L.d_hstart = L.recs ? (int64_t *)sh : nullptr;
     L.d_part = (int64_t *)(sh + hstart_b);
@@ -484,7 +490,7 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
         supa::place_bucket_size(c->n_layers, c->g.img_nx, c->g.img_ny, L.place_keys, c->n_cu, &per, &blocks);
         if (per > 0) {
             const size_t bb = (size_t)per * blocks * sizeof(uint2);
-            if (!c->bucket.ensure(bb)) return nomem(c, "image buckets", bb);
+            if (!c->bucket.ensure(bb, &c->scratch_gen)) return nomem(c, "image buckets", bb);
             L.d_bucket = (uint2 *)c->bucket.p;
             L.bucket_cap = (int32_t)per;
         }
@@ -732,6 +738,7 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
 // per-call input/output block so that replays do not depend on later calls.
 struct supa_graph {
     supa_ctx *ctx = nullptr;
+    uint64_t gen = 0;                    // the context's scratch generation at capture
     hipGraphExec_t exec = nullptr;
     supa::Cold *d_cold = nullptr;
     Plan plan{};
@@ -760,6 +767,7 @@ extern "C" supa_status supa_graph_create(supa_ctx *c, const supa_batch *b, uint6
         delete g;
         return st;
     }
+    g->gen = c->scratch_gen;
     hipGraph_t graph = nullptr;
     hipError_t e = hipMalloc(&g->d_cold, sizeof(supa::Cold));
     if (e == hipSuccess) e = hipMemcpy(g->d_cold, c->h_cold, sizeof(supa::Cold), hipMemcpyHostToDevice);
@@ -781,9 +789,19 @@ extern "C" supa_status supa_graph_create(supa_ctx *c, const supa_batch *b, uint6
     return SUPA_OK;
 }
 
+// the graph's kernels hold the scratch addresses of the capture: after a
+// reallocation they would read and write freed memory
+static supa_status graph_current(supa_graph *g) {
+    if (g->gen == g->ctx->scratch_gen) return SUPA_OK;
+    return fail(g->ctx, SUPA_ERR_STATE,
+                "the context's scratch was reallocated after this graph was captured: create the graph again");
+}
+
 extern "C" supa_status supa_graph_launch(supa_graph *g, void *hip_stream) {
     if (!g || !g->ctx) return SUPA_ERR_STATE;
     supa_ctx *c = g->ctx;
+    const supa_status cur = graph_current(g);
+    if (cur != SUPA_OK) return cur;
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, hipGraphLaunch(g->exec, hip_stream ? (hipStream_t)hip_stream : c->stream));
     return SUPA_OK;
@@ -792,6 +810,8 @@ extern "C" supa_status supa_graph_launch(supa_graph *g, void *hip_stream) {
 extern "C" supa_status supa_graph_check(supa_graph *g, void *hip_stream, int64_t *totals3) {
     if (!g || !g->ctx) return SUPA_ERR_STATE;
     supa_ctx *c = g->ctx;
+    const supa_status cur = graph_current(g);
+    if (cur != SUPA_OK) return cur;
     const hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
     HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_WORDS * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, s));

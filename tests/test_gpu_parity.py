@@ -391,6 +391,39 @@ def test_graph_replays_match_oracle():
     g.close()
 
 
+def test_graph_refuses_replay_after_scratch_grows():
+    """A larger eager call on the same context reallocates its scratch; the
+    graph captured before it is then refused on the host (nothing launched),
+    and a graph captured again replays correctly."""
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w, 4000)
+    te0, tpol, taz = dev_t(e0), dev_t(pol), dev_t(az)
+    n = 100
+    ref = O.simulate(geom, e0[:n], pol[:n], az[:n], w.seed)
+    sim = supa.Simulator(geom, ALL)
+    out = sim.allocate(n, 2 * len(ref["hit_e"]), 2 * len(ref["node_e"]))
+    a, b, c = te0[:n].clone(), tpol[:n].clone(), taz[:n].clone()
+    g = sim.graph(a, b, c, w.seed, out)
+    g.launch()
+    g.check()
+    sim.simulate(te0, tpol, taz, w.seed)           # 40x the showers: scratch grows
+    with pytest.raises(supa.SupaError, match="reallocated"):
+        g.launch()
+    with pytest.raises(supa.SupaError, match="reallocated"):
+        g.check()
+    g.close()
+    g2 = sim.graph(a, b, c, w.seed, out)
+    for k, v in out.items():
+        if isinstance(v, torch.Tensor):
+            v.fill_(-7)
+    g2.launch()
+    g2.check()
+    torch.cuda.synchronize()
+    parity.check_all(parity.to_numpy(out), ref, geom, tree=True)
+    g2.close()
+
+
 # --------------------------------------------------------------------------
 # Literal Algorithm 1 kinematics and the paper's presets
 # --------------------------------------------------------------------------
