@@ -52,6 +52,9 @@ def parse():
                     help="hand out expensive showers first (1), batch order (0), automatic (-1)")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of a captured HIP graph of the call")
+    ap.add_argument("--chunk", type=int, default=0,
+                    help="showers per call for the workload whose outputs do not fit one call "
+                         "(0: 2000)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick launch settings by measurement before timing")
     ap.add_argument("--kinematics", default="3d", choices=("3d", "literal"),
@@ -404,6 +407,98 @@ def bench_grids(args):
     print(json.dumps(line), flush=True)
 
 
+def chunk_slices(n: int, chunk: int):
+    """(first shower, showers) of each call when n showers run in calls of at
+    most `chunk` showers."""
+    return [(s0, min(chunk, n - s0)) for s0 in range(0, n, chunk)]
+
+
+def bench_batched(args, w):
+    """A workload whose outputs do not fit one call (1M showers of 50 layers
+    of 256x256 images = 13 TB): one step runs every shower in calls of
+    --chunk showers, each into the same outputs sized for one call (a
+    consumer would copy or reduce them between calls).  Timed: the calls of
+    one step, back to back."""
+    import torch
+    from paper_2202_05012_amd import supa, workloads
+
+    geom = workloads.geometry(w)
+    outputs = supa.OUT_HITS | supa.OUT_IMAGES | supa.OUT_TREE
+    dev = torch.device("cuda", 0)
+    e0, pol, az = workloads.initial_conditions(w)
+    te0, tpol, taz = (torch.from_numpy(a).to(dev) for a in (e0, pol, az))
+    chunk = args.chunk if args.chunk > 0 else 2000
+    calls = chunk_slices(w.n, chunk)
+    sim = supa.Simulator(geom, outputs, waves_per_cu=args.waves_per_cu, frontier_cap=args.lds_cap,
+                         sub_batches=args.sub_batches, cost_order=args.cost_order)
+
+    def call(out, s0, m):
+        sl = slice(s0, s0 + m)
+        return sim.run(te0[sl], tpol[sl], taz[sl], w.seed, out, shower_id_base=s0)
+
+    # capacities: the largest call's totals (zero-capacity outputs: each call
+    # reports its totals; this also grows the library's scratch)
+    probe = sim.allocate(chunk, 0, 0)
+    need_h = need_n = 0
+    for s0, m in calls:
+        call(probe, s0, m)
+        need_h, need_n = max(need_h, probe["total_hits"]), max(need_n, probe["total_nodes"])
+    del probe
+    out = sim.allocate(chunk, int(need_h) + 1, int(need_n) + 1)
+    for s0, m in calls[:args.warmup]:
+        assert call(out, s0, m) == 0
+    torch.cuda.synchronize()
+    prop_ms = post_ms = 0.0
+    nodes_total = hits_total = steps_total = splits_total = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for s0, m in calls:
+            st = call(out, s0, m)
+            assert st == 0, f"call at shower {s0} returned {st}"
+            tm = sim.timing()
+            prop_ms += tm[0]
+            post_ms += tm[1]
+            # totals the call returned (host values); a split adds two nodes
+            # to a shower's primary one
+            nodes_total += out["total_nodes"]
+            hits_total += out["total_hits"]
+            steps_total += out["total_steps"]
+            splits_total += (out["total_nodes"] - m) // 2
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    nodes_total, hits_total, steps_total, splits_total = (v // args.steps for v in
+                                                          (nodes_total, hits_total, steps_total, splits_total))
+    k_prop, k_post = prop_ms / args.steps, post_ms / args.steps
+    draws = steps_total - hits_total
+    alg_ops = OPS_PER_ARRIVAL * steps_total + OPS_PER_DRAW * draws + OPS_PER_SPLIT * splits_total
+    alu = alg_ops / (k_prop / 1e3) / 1e12
+    img_bytes = w.n * supa.n_layers(geom) * geom["img_nx"] * geom["img_ny"] * 4
+    out_bytes = BYTES_PER_HIT * hits_total + img_bytes + BYTES_PER_NODE * nodes_total
+    hbm = out_bytes / (k_post / 1e3) / 1e9
+    roof_prop = {"bound": "alu", "achieved": round(alu, 3), "peak": round(PEAK_ALU_TOPS, 2),
+                 "unit": "T lane-ops/s", "frac": round(alu / PEAK_ALU_TOPS, 4), "traffic": None,
+                 "kernel": "supa_propagate", "kernel_ms": round(k_prop, 3), "alg_lane_ops": alg_ops,
+                 "per": "step (sum over calls)"}
+    roof_post = {"bound": "hbm", "achieved": round(hbm, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                 "frac": round(hbm / PEAK_HBM_GBS, 4), "traffic": None,
+                 "kernel": "supa_place + scatter_nodes", "kernel_ms": round(k_post, 3), "alg_bytes": out_bytes,
+                 "per": "step (sum over calls)"}
+    roof, other = (roof_post, roof_prop) if k_post >= k_prop else (roof_prop, roof_post)
+    line = {
+        "metric": "showers/s (1 MI355X)", "value": round(w.n / (ms_per_step / 1e3), 1), "unit": "showers/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+u32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "showers": w.n, "planes": w.n_planes, "outputs": "hits+images+tree",
+                   "showers_per_call": chunk, "calls_per_step": len(calls)},
+        "particle_steps_per_s": round(steps_total / (ms_per_step / 1e3), 1),
+        "particle_steps": steps_total, "hits": hits_total, "nodes": nodes_total,
+        "roofline": roof, "roofline_other": other,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -423,10 +518,7 @@ def main():
 
     w = workloads.WORKLOADS[args.workload]
     if w.tree and w.images:
-        # batched runs of this workload (hit clouds + 50 x 256x256 images +
-        # tree) ended in a GPU memory fault whose cause is not found yet; only
-        # the parity tests run it, on up to 400 showers
-        sys.exit(f"bench.py does not run {w.name}: its batched run is disabled (open GPU fault)")
+        return bench_batched(args, w)
     geom = workloads.geometry(w)
     geom["kinematics"] = args.kinematics
     wname = w.name + ("" if args.kinematics == "3d" else "_literal") + \

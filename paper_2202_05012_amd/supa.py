@@ -272,6 +272,7 @@ class Simulator:
                                      "tensors of equal length on the simulator's device")
         b = Batch(_ptr(e0), _ptr(polar), _ptr(azimuth), _ptr(x0), _ptr(y0), n,
                   shower_id_base & 0xFFFFFFFF)
+        self._check_output_sizes(out, n)
         o = Output()
         for name, _ in Output._fields_:
             if name in out and isinstance(out[name], torch.Tensor):
@@ -279,6 +280,32 @@ class Simulator:
         o.hit_capacity = int(out.get("hit_capacity", 0))
         o.node_capacity = int(out.get("node_capacity", 0))
         return b, o
+
+    # elements per shower of the per-shower outputs (images: L * ny * nx)
+    _PER_SHOWER = {"ledger": 4, "counts": 6, "hit_offsets": 1, "node_offsets": 1, "images": None}
+    _PER_HIT = ("hit_x", "hit_y", "hit_e", "hit_layer", "hit_key")
+    _PER_NODE = ("node_parent", "node_gen", "node_vx", "node_vy", "node_vz", "node_e", "node_key")
+
+    def _check_output_sizes(self, out, n):
+        """The library writes per-shower outputs for all n showers of a call
+        and per-record outputs up to the stated capacities through plain
+        pointers: refuse tensors too small for that before anything runs."""
+        per_img = self.L * int(self.geom.get("img_ny", 0) or 0) * int(self.geom.get("img_nx", 0) or 0)
+        need = {}
+        for name, k in self._PER_SHOWER.items():
+            need[name] = n * (per_img if k is None else k)
+        for name in self._PER_HIT:
+            need[name] = int(out.get("hit_capacity", 0))
+        for name in self._PER_NODE:
+            need[name] = int(out.get("node_capacity", 0))
+        for name, m in need.items():
+            t = out.get(name)
+            if not isinstance(t, torch.Tensor):
+                continue
+            if t.device != self.device or not t.is_contiguous() or t.numel() < m:
+                raise ValueError(f"output '{name}' must be a contiguous tensor on the simulator's device "
+                                 f"holding at least {m} elements for this call ({n} showers); it has "
+                                 f"{t.numel()}")
 
     @staticmethod
     def _totals(out, o):

@@ -492,3 +492,23 @@ def test_rings_parity(trial):
     flat = dict(geom, n_regions=0, region_r=None, p_stop=list(ps[:N]), p_split=geom["p_split"][:N])
     ref0 = O.simulate(flat, e0, pol, az, seed, x0=x0, y0=y0, shower_id_base=base)
     assert (ref0["counts"] != ref["counts"]).any()
+
+
+def test_outputs_smaller_than_the_batch_are_refused_on_the_host():
+    """The library writes per-shower outputs for every shower of a call
+    through plain pointers; the binding refuses outputs sized for fewer
+    showers (or records) before anything is launched."""
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w, 50)
+    sim = supa.Simulator(geom, ALL)
+    small = sim.allocate(20, 100, 100)
+    with pytest.raises(ValueError, match="at least"):
+        sim.run(dev_t(e0), dev_t(pol), dev_t(az), w.seed, small)
+    out = sim.allocate(50, 100, 100)
+    out["hit_x"] = out["hit_x"][:50]
+    with pytest.raises(ValueError, match="hit_x"):
+        sim.run(dev_t(e0), dev_t(pol), dev_t(az), w.seed, out)
+    ok = sim.simulate(dev_t(e0), dev_t(pol), dev_t(az), w.seed)
+    torch.cuda.synchronize()
+    assert ok["counts"].shape[0] == 50
