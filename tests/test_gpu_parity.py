@@ -512,3 +512,32 @@ def test_outputs_smaller_than_the_batch_are_refused_on_the_host():
     ok = sim.simulate(dev_t(e0), dev_t(pol), dev_t(az), w.seed)
     torch.cuda.synchronize()
     assert ok["counts"].shape[0] == 50
+
+
+@pytest.mark.slow
+def test_full_size_50plane_call_sampled_parity():
+    """The 50-plane workload (E0 log-uniform on [10, 1000], hit clouds, 50
+    256x256 images, tree) as the benchmark runs it: one call of 10,000
+    showers, a slice from the middle of the 1,000,000 (path ids added for the
+    hit comparison).  Invariants over every shower of the call; the oracle
+    on sampled blocks, images included."""
+    w = workloads.WORKLOADS["loge10to1000_50planes_tree_img256_1m"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w)
+    s0, m = 500_000, 10_000
+    sl = slice(s0, s0 + m)
+    sim = supa.Simulator(geom, ALL)
+    out = sim.simulate(dev_t(e0[sl]), dev_t(pol[sl]), dev_t(az[sl]), w.seed, shower_id_base=s0)
+    torch.cuda.synchronize()
+    counts = out["counts"].cpu().numpy()
+    ledger = out["ledger"].cpu().numpy().astype(np.uint64)
+    assert (ledger[:, 1] + ledger[:, 2] + ledger[:, 3] == ledger[:, 0]).all()
+    assert (counts[:, 0] == 1 + 2 * counts[:, 3]).all()
+    assert out["total_hits"] == counts[:, 1].sum() and out["total_nodes"] == counts[:, 0].sum()
+    rng = np.random.default_rng(4)
+    for start in [0, m - 24] + list(rng.integers(0, m - 24, 2)):
+        rows = np.arange(start, start + 24)
+        gpu = sampled_segments(out, rows)
+        ref = O.simulate(geom, e0[sl][rows], pol[sl][rows], az[sl][rows], w.seed,
+                         shower_id_base=int(s0 + start))
+        parity.check_all(gpu, ref, geom, images=True, tree=True)
