@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define SUPA_ABI_VERSION 4
+#define SUPA_ABI_VERSION 5
 
 typedef enum supa_status {
     SUPA_OK = 0,
@@ -181,6 +181,11 @@ typedef struct supa_output {
     int32_t *counts;                 /* n * 6: nodes, hits, particle-steps,
                                         splits, escaped particles, escapes
                                         because the direction turned away from +z */
+    /* showers that every per-shower array above holds (ledger, counts,
+       hit_offsets, node_offsets, images): a call with n > shower_capacity is
+       refused with SUPA_ERR_INVALID_ARG before anything is launched, so the
+       library never writes past the caller's per-shower rows */
+    int64_t shower_capacity;
     /* host outputs, set on SUPA_OK and on SUPA_ERR_CAPACITY: */
     int64_t total_hits, total_nodes, total_steps;
 } supa_output;
@@ -191,6 +196,16 @@ int32_t supa_abi_version(void);
 /* Checks parameters on the host only (no device call): SUPA_OK or
  * SUPA_ERR_INVALID_ARG.  Same checks as supa_init_geometry. */
 supa_status supa_validate_geometry(const supa_geometry *g);
+
+/*
+ * Checks the arguments of a supa_simulate call on the host only (no device
+ * call, no context needed): the same checks supa_simulate makes before it
+ * launches anything -- parameters (as supa_validate_geometry), 0 <= n <=
+ * 2^31 - 1, the input arrays and every output array the selected outputs
+ * need are non-NULL, capacities >= 0 and n <= out->shower_capacity.
+ * SUPA_OK or SUPA_ERR_INVALID_ARG (supa_last_error(NULL) says why).
+ */
+supa_status supa_validate_call(const supa_geometry *g, const supa_batch *b, const supa_output *out);
 
 /*
  * Creates a context for device `device` and HIP stream `hip_stream`
@@ -207,7 +222,8 @@ supa_status supa_destroy(supa_ctx *ctx);
 /*
  * Simulates a batch with 64-bit `seed` (Algorithm 1 applied plane by plane to
  * every live particle of every shower).  Fills `out` as described above.
- * Errors: INVALID_ARG (NULL pointers for requested outputs, bad n),
+ * Errors: INVALID_ARG (NULL pointers for requested outputs, bad n, n larger
+ * than out->shower_capacity),
  * RANGE (an initial energy out of range: nothing else is meaningful),
  * CAPACITY (total hits or nodes exceed the capacities: ledger, counts and the
  * host totals are valid, hit/node arrays and images are not; a retry with

@@ -395,30 +395,56 @@ static int64_t round_up_pow2(int64_t v) {
     return p;
 }
 
-// Argument checks of a simulate call (host only).
+// Argument checks of a simulate call against the selected outputs (host
+// only): SUPA_OK or SUPA_ERR_INVALID_ARG with the reason in `why`.
+static supa_status check_args(uint32_t outs, const supa_batch *b, const supa_output *out, std::string &why) {
+    if (!b || !out) { why = "batch or output is NULL"; return SUPA_ERR_INVALID_ARG; }
+    if (b->n < 0 || b->n > 2147483647LL) { why = "n out of range"; return SUPA_ERR_INVALID_ARG; }
+    const int64_t n = b->n;
+    if (n == 0) return SUPA_OK;
+    // every per-shower row the call writes must lie inside the caller's arrays
+    if (out->shower_capacity < n) {
+        why = "outputs hold " + std::to_string(out->shower_capacity) + " showers (shower_capacity), the batch has " +
+              std::to_string(n);
+        return SUPA_ERR_INVALID_ARG;
+    }
+    if (!b->e0 || !b->polar || !b->azimuth) { why = "e0, polar and azimuth are required"; return SUPA_ERR_INVALID_ARG; }
+    if (!out->ledger || !out->counts) { why = "ledger and counts are required"; return SUPA_ERR_INVALID_ARG; }
+    if ((outs & SUPA_OUT_HITS) &&
+        (!out->hit_offsets || ((!out->hit_x || !out->hit_y || !out->hit_e || !out->hit_layer) && out->hit_capacity > 0) ||
+         out->hit_capacity < 0 || ((outs & SUPA_OUT_KEYS) && out->hit_capacity > 0 && !out->hit_key))) {
+        why = "hit outputs missing";
+        return SUPA_ERR_INVALID_ARG;
+    }
+    if ((outs & SUPA_OUT_IMAGES) && !out->images) { why = "images missing"; return SUPA_ERR_INVALID_ARG; }
+    if ((outs & SUPA_OUT_TREE) &&
+        (!out->node_offsets || out->node_capacity < 0 ||
+         ((!out->node_parent || !out->node_gen || !out->node_vx || !out->node_vy || !out->node_vz || !out->node_e) &&
+          out->node_capacity > 0) ||
+         ((outs & SUPA_OUT_KEYS) && out->node_capacity > 0 && !out->node_key))) {
+        why = "tree outputs missing";
+        return SUPA_ERR_INVALID_ARG;
+    }
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_validate_call(const supa_geometry *g, const supa_batch *b, const supa_output *out) {
+    std::string why;
+    supa_status s = validate(g, why);
+    if (s == SUPA_OK) s = check_args(g->outputs, b, out, why);
+    if (s != SUPA_OK) g_init_error = why;
+    return s;
+}
+
+// Argument checks of a simulate call on a context (host only).
 static supa_status check_call(supa_ctx *c, const supa_batch *b, supa_output *out) {
     if (!c) return SUPA_ERR_STATE;
     if (c->broken) return fail(c, SUPA_ERR_STATE, "context unusable after a device error");
     c->err.clear();
-    if (!b || !out) return fail(c, SUPA_ERR_INVALID_ARG, "batch or output is NULL");
-    if (b->n < 0 || b->n > 2147483647LL) return fail(c, SUPA_ERR_INVALID_ARG, "n out of range");
-    const uint32_t outs = c->g.outputs;
-    const int64_t n = b->n;
+    std::string why;
+    const supa_status s = check_args(c->g.outputs, b, out, why);
+    if (s != SUPA_OK) return fail(c, s, why);
     out->total_hits = out->total_nodes = out->total_steps = 0;
-    if (n > 0 && (!b->e0 || !b->polar || !b->azimuth))
-        return fail(c, SUPA_ERR_INVALID_ARG, "e0, polar and azimuth are required");
-    if (n > 0 && (!out->ledger || !out->counts)) return fail(c, SUPA_ERR_INVALID_ARG, "ledger and counts are required");
-    if ((outs & SUPA_OUT_HITS) && n > 0 &&
-        (!out->hit_offsets || ((!out->hit_x || !out->hit_y || !out->hit_e || !out->hit_layer) && out->hit_capacity > 0) ||
-         out->hit_capacity < 0 || ((outs & SUPA_OUT_KEYS) && out->hit_capacity > 0 && !out->hit_key)))
-        return fail(c, SUPA_ERR_INVALID_ARG, "hit outputs missing");
-    if ((outs & SUPA_OUT_IMAGES) && n > 0 && !out->images) return fail(c, SUPA_ERR_INVALID_ARG, "images missing");
-    if ((outs & SUPA_OUT_TREE) && n > 0 &&
-        (!out->node_offsets || out->node_capacity < 0 ||
-         ((!out->node_parent || !out->node_gen || !out->node_vx || !out->node_vy || !out->node_vz || !out->node_e) &&
-          out->node_capacity > 0) ||
-         ((outs & SUPA_OUT_KEYS) && out->node_capacity > 0 && !out->node_key)))
-        return fail(c, SUPA_ERR_INVALID_ARG, "tree outputs missing");
     return SUPA_OK;
 }
 

@@ -67,12 +67,12 @@ class Output(C.Structure):
         ("node_parent", C.c_void_p), ("node_gen", C.c_void_p),
         ("node_vx", C.c_void_p), ("node_vy", C.c_void_p), ("node_vz", C.c_void_p),
         ("node_e", C.c_void_p), ("node_key", C.c_void_p), ("node_capacity", C.c_int64),
-        ("ledger", C.c_void_p), ("counts", C.c_void_p),
+        ("ledger", C.c_void_p), ("counts", C.c_void_p), ("shower_capacity", C.c_int64),
         ("total_hits", C.c_int64), ("total_nodes", C.c_int64), ("total_steps", C.c_int64),
     ]
 
 
-EXPORTS = ["supa_abi_version", "supa_validate_geometry", "supa_init_geometry", "supa_destroy",
+EXPORTS = ["supa_abi_version", "supa_validate_geometry", "supa_validate_call", "supa_init_geometry", "supa_destroy",
            "supa_simulate", "supa_set_launch", "supa_set_schedule", "supa_autotune",
            "supa_graph_create", "supa_graph_launch", "supa_graph_check", "supa_graph_destroy", "supa_last_timing", "supa_philox",
            "supa_last_error"]
@@ -91,6 +91,8 @@ def load():
         L.supa_abi_version.restype = C.c_int32
         L.supa_validate_geometry.restype = C.c_int
         L.supa_validate_geometry.argtypes = [C.POINTER(Geometry)]
+        L.supa_validate_call.restype = C.c_int
+        L.supa_validate_call.argtypes = [C.POINTER(Geometry), C.POINTER(Batch), C.POINTER(Output)]
         L.supa_init_geometry.restype = C.c_int
         L.supa_init_geometry.argtypes = [C.POINTER(Geometry), C.c_int, C.c_void_p,
                                          C.POINTER(C.c_void_p)]
@@ -260,6 +262,7 @@ class Simulator:
                 o["node_key"] = torch.empty(node_capacity, dtype=torch.int64, device=dev)
         o["hit_capacity"] = hit_capacity
         o["node_capacity"] = node_capacity
+        o["shower_capacity"] = n
         return o
 
     def _marshal(self, e0, polar, azimuth, out, x0, y0, shower_id_base):
@@ -279,18 +282,45 @@ class Simulator:
                 setattr(o, name, out[name].data_ptr())
         o.hit_capacity = int(out.get("hit_capacity", 0))
         o.node_capacity = int(out.get("node_capacity", 0))
+        o.shower_capacity = self._shower_capacity(out)
         return b, o
 
     # elements per shower of the per-shower outputs (images: L * ny * nx)
     _PER_SHOWER = {"ledger": 4, "counts": 6, "hit_offsets": 1, "node_offsets": 1, "images": None}
     _PER_HIT = ("hit_x", "hit_y", "hit_e", "hit_layer", "hit_key")
     _PER_NODE = ("node_parent", "node_gen", "node_vx", "node_vy", "node_vz", "node_e", "node_key")
+    # element types the library writes through each pointer
+    _DTYPES = {"ledger": (torch.int64, torch.uint64), "counts": (torch.int32,),
+               "hit_offsets": (torch.int64,), "node_offsets": (torch.int64,),
+               "hit_x": (torch.float32,), "hit_y": (torch.float32,), "hit_e": (torch.float32,),
+               "hit_layer": (torch.int32,), "hit_key": (torch.int64, torch.uint64),
+               "images": (torch.float32,), "node_parent": (torch.int32,), "node_gen": (torch.int32,),
+               "node_vx": (torch.float32,), "node_vy": (torch.float32,), "node_vz": (torch.float32,),
+               "node_e": (torch.float32,), "node_key": (torch.int64, torch.uint64)}
+
+    def _per_image(self):
+        return self.L * int(self.geom.get("img_ny", 0) or 0) * int(self.geom.get("img_nx", 0) or 0)
+
+    def _shower_capacity(self, out):
+        """Showers every per-shower output tensor holds (the library's bound on
+        the rows it writes)."""
+        per_img = self._per_image()
+        cap = None
+        for name, k in self._PER_SHOWER.items():
+            t = out.get(name)
+            if isinstance(t, torch.Tensor):
+                per = per_img if k is None else k
+                if per > 0:
+                    c = t.numel() // per
+                    cap = c if cap is None else min(cap, c)
+        return 0 if cap is None else cap
 
     def _check_output_sizes(self, out, n):
         """The library writes per-shower outputs for all n showers of a call
         and per-record outputs up to the stated capacities through plain
-        pointers: refuse tensors too small for that before anything runs."""
-        per_img = self.L * int(self.geom.get("img_ny", 0) or 0) * int(self.geom.get("img_nx", 0) or 0)
+        pointers: refuse tensors of the wrong element type or too small for
+        that before anything runs."""
+        per_img = self._per_image()
         need = {}
         for name, k in self._PER_SHOWER.items():
             need[name] = n * (per_img if k is None else k)
@@ -302,6 +332,9 @@ class Simulator:
             t = out.get(name)
             if not isinstance(t, torch.Tensor):
                 continue
+            if t.dtype not in self._DTYPES[name]:
+                raise ValueError(f"output '{name}' must have dtype "
+                                 f"{' or '.join(str(d) for d in self._DTYPES[name])}, not {t.dtype}")
             if t.device != self.device or not t.is_contiguous() or t.numel() < m:
                 raise ValueError(f"output '{name}' must be a contiguous tensor on the simulator's device "
                                  f"holding at least {m} elements for this call ({n} showers); it has "
@@ -360,7 +393,15 @@ class Simulator:
         out = self.allocate(n, hc, nc)
         st = self.run(e0, polar, azimuth, seed, out, x0, y0, shower_id_base)
         if st == 3:
-            out = self.allocate(n, max(hc, out["total_hits"]), max(nc, out["total_nodes"]))
+            # only the record arrays grow: the per-shower outputs (images
+            # included) are kept, so the device never holds two sets of them
+            hc, nc = max(hc, out["total_hits"]), max(nc, out["total_nodes"])
+            for k in self._PER_HIT + self._PER_NODE:
+                out.pop(k, None)
+            grown = self.allocate(0, hc, nc)
+            for k in self._PER_HIT + self._PER_NODE + ("hit_capacity", "node_capacity"):
+                if k in grown:
+                    out[k] = grown[k]
             st = self.run(e0, polar, azimuth, seed, out, x0, y0, shower_id_base)
             self._check(st)
         th, tn = out["total_hits"], out["total_nodes"]
@@ -386,6 +427,24 @@ def validate_geometry(geom: dict, outputs: int = OUT_HITS):
     lib = load()
     g, keep = make_geometry(geom, outputs)
     st = lib.supa_validate_geometry(C.byref(g))
+    if st != 0:
+        raise SupaError(st, lib.supa_last_error(None).decode())
+
+
+def validate_call(geom: dict, outputs: int, n: int, out: dict):
+    """Host-only check of a simulate call's arguments through the C ABI
+    (supa_validate_call: no GPU needed).  `out` maps output names to
+    integers standing for device addresses (never dereferenced) plus
+    hit_capacity, node_capacity and shower_capacity; raises SupaError."""
+    lib = load()
+    g, keep = make_geometry(geom, outputs)
+    fake = 4096
+    b = Batch(fake, fake, fake, None, None, n, 0)
+    o = Output()
+    for name, _ in Output._fields_:
+        if name in out:
+            setattr(o, name, out[name])
+    st = lib.supa_validate_call(C.byref(g), C.byref(b), C.byref(o))
     if st != 0:
         raise SupaError(st, lib.supa_last_error(None).decode())
 

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     assert "supa_simulate" in names and "supa_init_geometry" in names
     for name in names:
         assert hasattr(lib, name), f"{name} declared in include/ but not exported"
-    assert lib.supa_abi_version() == 4
+    assert lib.supa_abi_version() == 5
 
 
 def base_geom(**kw):
@@ -126,3 +126,82 @@ def test_ring_parameters_rejected(bad):
         supa.validate_geometry(g)
     ok = dict(base_geom(), n_regions=3, region_r=[0.1, 0.2], p_stop=[0.0] * 60, p_split=[1.0] * 60)
     supa.validate_geometry(ok)
+
+
+def call_outputs(n, **kw):
+    """Fake device addresses (never dereferenced) for every output of a call."""
+    names = ("hit_offsets", "hit_x", "hit_y", "hit_e", "hit_layer", "hit_key", "images",
+             "node_offsets", "node_parent", "node_gen", "node_vx", "node_vy", "node_vz", "node_e",
+             "node_key", "ledger", "counts")
+    o = {k: 4096 * (i + 1) for i, k in enumerate(names)}
+    o.update(hit_capacity=1000, node_capacity=1000, shower_capacity=n)
+    o.update(kw)
+    return o
+
+
+ALL_OUT = supa.OUT_HITS | supa.OUT_IMAGES | supa.OUT_TREE | supa.OUT_KEYS
+
+
+def test_call_validation_accepts_a_well_formed_call():
+    supa.validate_call(base_geom(), ALL_OUT, 100, call_outputs(100))
+    supa.validate_call(base_geom(), ALL_OUT, 100, call_outputs(250))
+    supa.validate_call(base_geom(), supa.OUT_HITS, 0, call_outputs(0, ledger=None, counts=None))
+
+
+@pytest.mark.parametrize("n,bad", [
+    (100, dict(shower_capacity=99)),        # per-shower rows past the caller's arrays
+    (100, dict(shower_capacity=0)),
+    (1, dict(shower_capacity=-1)),
+    (100, dict(ledger=None)), (100, dict(counts=None)),
+    (100, dict(hit_offsets=None)), (100, dict(hit_x=None)), (100, dict(hit_key=None)),
+    (100, dict(images=None)), (100, dict(node_offsets=None)), (100, dict(node_vz=None)),
+    (100, dict(node_key=None)), (100, dict(hit_capacity=-1)), (100, dict(node_capacity=-5)),
+    (-1, {}), (2 ** 31, dict(shower_capacity=2 ** 31)),
+])
+def test_call_validation_rejects_on_the_host(n, bad):
+    with pytest.raises(supa.SupaError) as e:
+        supa.validate_call(base_geom(), ALL_OUT, n, call_outputs(max(n, 0), **bad))
+    assert e.value.status == 1
+    if "shower_capacity" in bad and 0 < n < 2 ** 31:
+        assert "shower_capacity" in str(e.value)
+
+
+def test_call_validation_checks_parameters_too():
+    with pytest.raises(supa.SupaError) as e:
+        supa.validate_call(base_geom(dz=0.0), ALL_OUT, 10, call_outputs(10))
+    assert e.value.status == 1
+
+
+def test_binding_refuses_wrong_dtypes_and_short_outputs():
+    """The binding's own size and type check, run on host tensors (no GPU):
+    each per-shower and per-record tensor must have the element type the
+    library writes and hold the call's showers or the stated capacity."""
+    import torch
+    sim = object.__new__(supa.Simulator)
+    sim.geom, sim.L, sim.device = base_geom(), 20, torch.device("cpu")
+    n = 10
+
+    def outputs():
+        return {"ledger": torch.zeros((n, 4), dtype=torch.int64), "counts": torch.zeros((n, 6), dtype=torch.int32),
+                "hit_offsets": torch.zeros(n, dtype=torch.int64),
+                "hit_x": torch.zeros(50), "hit_y": torch.zeros(50), "hit_e": torch.zeros(50),
+                "hit_layer": torch.zeros(50, dtype=torch.int32), "hit_capacity": 50,
+                "images": torch.zeros((n, 20, 32, 32))}
+
+    sim._check_output_sizes(outputs(), n)
+    assert sim._shower_capacity(outputs()) == n
+    for name, bad in (("ledger", torch.zeros((n, 4), dtype=torch.int32)),
+                      ("counts", torch.zeros((n, 6), dtype=torch.int64)),
+                      ("hit_offsets", torch.zeros(n, dtype=torch.int32)),
+                      ("hit_x", torch.zeros(50, dtype=torch.float64)),
+                      ("hit_layer", torch.zeros(50, dtype=torch.float32)),
+                      ("images", torch.zeros((n, 20, 32, 32), dtype=torch.float64))):
+        o = outputs()
+        o[name] = bad
+        with pytest.raises(ValueError, match=name):
+            sim._check_output_sizes(o, n)
+    o = outputs()
+    o["images"] = torch.zeros((n - 1, 20, 32, 32))
+    with pytest.raises(ValueError, match="images"):
+        sim._check_output_sizes(o, n)
+    assert sim._shower_capacity(o) == n - 1

@@ -514,6 +514,32 @@ def test_outputs_smaller_than_the_batch_are_refused_on_the_host():
     assert ok["counts"].shape[0] == 50
 
 
+def test_library_refuses_a_batch_larger_than_its_outputs():
+    """Bypassing the binding's checks: the C ABI itself refuses a call whose
+    batch has more showers than the outputs' shower capacity, before any
+    launch (the per-shower rows would land past the caller's arrays), and
+    the context stays usable."""
+    import ctypes as C
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w, 64)
+    sim = supa.Simulator(geom, ALL)
+    out = sim.allocate(32, 1 << 16, 1 << 16)
+    guard = {k: v.clone() for k, v in out.items() if isinstance(v, torch.Tensor)}
+    te0, tpol, taz = dev_t(e0), dev_t(pol), dev_t(az)
+    b, o = sim._marshal(te0[:32], tpol[:32], taz[:32], out, None, None, 0)
+    b.n = 64                                    # the real arrays hold 64 showers of input
+    assert o.shower_capacity == 32
+    st = sim.lib.supa_simulate(sim.ctx, C.byref(b), w.seed, C.byref(o))
+    assert st == 1 and "shower_capacity" in sim.lib.supa_last_error(sim.ctx).decode()
+    torch.cuda.synchronize()
+    for k, v in guard.items():
+        assert torch.equal(v, out[k]), k         # nothing was written
+    gpu = parity.to_numpy(sim.simulate(te0[:32], tpol[:32], taz[:32], w.seed))
+    ref = O.simulate(geom, e0[:32], pol[:32], az[:32], w.seed)
+    parity.check_all(gpu, ref, geom, images=True, tree=True)
+
+
 @pytest.mark.slow
 def test_full_size_50plane_call_sampled_parity():
     """The 50-plane workload (E0 log-uniform on [10, 1000], hit clouds, 50
