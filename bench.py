@@ -1,10 +1,14 @@
 """Throughput of the SUPA propagation path on one MI355X.
 
-One step = one supa_simulate call over the whole batch of the named workload
-(initial conditions resident in HBM before timing): every particle of every
-shower propagated plane by plane, hit clouds and per-layer images written.
+One step = every shower of the named workload simulated once (initial
+conditions resident in HBM before timing): every particle propagated plane by
+plane, hit clouds, per-layer images and (50-plane workload) the propagation
+tree written.  The default workload is the largest: 1,000,000 showers, E0
+log-uniform on [10, 1000], 50 planes, hits + tree + 50 x 256x256 images, run
+in calls of 10,000 showers (its 13 TB of images do not fit one call).
 Prints one JSON line (see the keys below).  The CPU oracle is timed on a
-bounded sample on the host's cores and reported beside it.
+random sample of the workload's showers on the host's cores and reported
+beside it.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -40,7 +44,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="e1to100_20planes_img32_100k")
+    ap.add_argument("--workload", default="loge10to1000_50planes_tree_img256_1m")
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--lds-cap", type=int, default=0,
                     help="frontier entries per buffer kept in LDS (0 = library default)")
@@ -64,7 +68,9 @@ def parse():
                          "every ring with the workload's probabilities (measures the ring lookup)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="wall time of the oracle's host-CPU baseline")
+                    help="wall time of the oracle's host-CPU baseline (all threads)")
+    ap.add_argument("--cpu-seconds-1t", type=float, default=4.0,
+                    help="wall time of the oracle's one-thread leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--surrogate", action="store_true",
@@ -84,34 +90,57 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, geom, seconds: float, images: bool):
-    """The oracle on the host: blocks of 128 showers of the workload, taken
-    in order (wrapping around) by min(cores, 16) threads until `seconds` of
-    wall time have passed; rate = showers finished / elapsed time."""
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Threads for the oracle's all-core leg: the CPUs this process may run
+    on, capped by OMP_NUM_THREADS when set (the host's share for one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
+
+
+def oracle_sample_rate(w, geom, ids, threads: int, seconds: float, images: bool):
+    """The oracle on the showers `ids` of workload w (each its own call, with
+    its global shower id), taken in order by `threads` host threads until
+    `seconds` of wall time have passed: simulation with the tree, plus the
+    per-layer images when asked.  Returns (showers done, particle-steps,
+    elapsed s)."""
     import threading
     from oracle import supa_oracle as O
     from paper_2202_05012_amd import workloads
-    threads = min(os.cpu_count() or 1, 16)
     e0, pol, az = workloads.initial_conditions(w)
-    block = 128
-    nblocks = (w.n + block - 1) // block
     lock = threading.Lock()
     state = {"next": 0, "showers": 0, "steps": 0}
+    L = int(max(geom["layer_of_plane"])) + 1 if geom.get("layer_of_plane") else int(geom["n_planes"])
     t0 = time.perf_counter()
 
     def worker():
         while time.perf_counter() - t0 < seconds:
             with lock:
-                b = state["next"]
+                j = state["next"]
                 state["next"] += 1
-            s = (b % nblocks) * block
-            m = min(block, w.n - s)
-            r = O.simulate(geom, e0[s:s + m], pol[s:s + m], az[s:s + m], w.seed, shower_id_base=s)
+            i = int(ids[j % len(ids)])
+            r = O.simulate(geom, e0[i:i + 1], pol[i:i + 1], az[i:i + 1], w.seed, shower_id_base=i)
             if images:
-                O.images(r, geom["n_planes"], geom["img_nx"], geom["img_ny"], geom["img_x0"],
-                         geom["img_x1"], geom["img_y0"], geom["img_y1"])
+                O.images(r, L, geom["img_nx"], geom["img_ny"], geom["img_x0"], geom["img_x1"],
+                         geom["img_y0"], geom["img_y1"])
             with lock:
-                state["showers"] += m
+                state["showers"] += 1
                 state["steps"] += int(r["counts"][:, 2].sum())
 
     ts = [threading.Thread(target=worker) for _ in range(threads)]
@@ -119,13 +148,30 @@ def cpu_baseline(w, geom, seconds: float, images: bool):
         t.start()
     for t in ts:
         t.join()
-    dt = time.perf_counter() - t0
-    n = state["showers"]
-    return {"value": n / dt, "unit": "showers/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} showers ({n / w.n:.2f} passes over the workload's showers, in blocks of "
-                      f"{block}), oracle simulation{' + image binning' if images else ''}, "
-                      f"{threads} host threads, {dt:.1f} s",
-            "particle_steps_per_s": state["steps"] / dt, "seconds": dt}
+    return state["showers"], state["steps"], time.perf_counter() - t0
+
+
+def cpu_baseline_sampled(w, geom, seconds: float, seconds_1t: float, images: bool):
+    """The oracle timed on a random subset of the workload's showers (drawn
+    uniformly over all of them, so the per-shower mean of the subset
+    estimates the workload's), once on every host thread and once on one
+    thread; the showers/s of the whole workload is extrapolated from the
+    subset's per-shower rate."""
+    ids = np.random.default_rng(20260).permutation(w.n)
+    threads = host_threads()
+    n1, s1, t1 = oracle_sample_rate(w, geom, ids, 1, seconds_1t, images)
+    n, steps, dt = oracle_sample_rate(w, geom, ids[n1:], threads, seconds, images)
+    what = "simulation + tree" + (" + per-layer images" if images else "")
+    return {"value": round(n / dt, 2), "unit": "showers/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} showers drawn at random from the {w.n:,} ({what}, one oracle call per "
+                      f"shower) on {threads} host threads in {dt:.1f} s; rate extrapolated per shower "
+                      f"to the whole workload",
+            "extrapolated": True, "seconds": round(dt, 2),
+            "particle_steps_per_s": round(steps / dt, 1),
+            "one_thread": {"value": round(n1 / t1, 2), "unit": "showers/s", "showers": n1,
+                           "seconds": round(t1, 2), "particle_steps_per_s": round(s1 / t1, 1)},
+            "workload_seconds_all_threads": round(w.n / (n / dt), 1),
+            "cpu_model": host_cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def bench_surrogate(args):
@@ -418,9 +464,9 @@ def bench_batched(args, w):
     of 256x256 images = 13 TB): one step runs every shower in calls of
     --chunk showers, each into the same outputs sized for one call (a
     consumer would copy or reduce them between calls).  Timed: the calls of
-    one step, back to back."""
+    K steps, back to back, after W untimed steps."""
     import torch
-    from paper_2202_05012_amd import supa, workloads
+    from paper_2202_05012_amd import prof_summary, supa, workloads
 
     geom = workloads.geometry(w)
     outputs = supa.OUT_HITS | supa.OUT_IMAGES | supa.OUT_TREE
@@ -446,15 +492,19 @@ def bench_batched(args, w):
         need_h, need_n = max(need_h, probe["total_hits"]), max(need_n, probe["total_nodes"])
     del probe
     out = sim.allocate(chunk, int(need_h) + 1, int(need_n) + 1)
+    print(f"sized: {len(calls)} calls of {chunk} showers, <= {need_h} hits and {need_n} nodes per call",
+          file=sys.stderr, flush=True)
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         torch.empty_like(a).copy_(a)
         torch.cuda.synchronize()
         del a
-    for s0, m in calls[:args.warmup]:
-        assert call(out, s0, m) == 0
+    for _ in range(args.warmup):
+        for s0, m in calls:
+            assert call(out, s0, m) == 0
     torch.cuda.synchronize()
-    prop_ms = post_ms = 0.0
+    print(f"warm-up: {args.warmup} steps done", file=sys.stderr, flush=True)
+    prop_ms = place_ms = scatter_ms = 0.0
     nodes_total = hits_total = steps_total = splits_total = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -463,7 +513,8 @@ def bench_batched(args, w):
             assert st == 0, f"call at shower {s0} returned {st}"
             tm = sim.timing()
             prop_ms += tm[0]
-            post_ms += tm[1]
+            place_ms += tm[3]
+            scatter_ms += tm[4]
             # totals the call returned (host values); a split adds two nodes
             # to a shower's primary one
             nodes_total += out["total_nodes"]
@@ -472,36 +523,56 @@ def bench_batched(args, w):
             splits_total += (out["total_nodes"] - m) // 2
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    print(f"timed: {args.steps} steps in {t1 - t0:.2f} s", file=sys.stderr, flush=True)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     nodes_total, hits_total, steps_total, splits_total = (v // args.steps for v in
                                                           (nodes_total, hits_total, steps_total, splits_total))
-    k_prop, k_post = prop_ms / args.steps, post_ms / args.steps
-    draws = steps_total - hits_total
+    launches = args.steps * len(calls)
+    k_prop, k_place, k_scatter = prop_ms / launches, place_ms / launches, scatter_ms / launches
+    draws = steps_total - hits_total          # p_stop = 0 here: every hit is a cut
     alg_ops = OPS_PER_ARRIVAL * steps_total + OPS_PER_DRAW * draws + OPS_PER_SPLIT * splits_total
-    alu = alg_ops / (k_prop / 1e3) / 1e12
-    img_bytes = w.n * supa.n_layers(geom) * geom["img_nx"] * geom["img_ny"] * 4
-    out_bytes = BYTES_PER_HIT * hits_total + img_bytes + BYTES_PER_NODE * nodes_total
-    hbm = out_bytes / (k_post / 1e3) / 1e9
+    alu = alg_ops / len(calls) / (k_prop / 1e3) / 1e12
+    L = supa.n_layers(geom)
+    img_bytes = w.n * L * geom["img_nx"] * geom["img_ny"] * 4
+    # per launch (average over the step's calls): what the kernel must write
+    place_alg = (BYTES_PER_HIT * hits_total + img_bytes) / len(calls)
+    scatter_alg = BYTES_PER_NODE * nodes_total / len(calls)
+    prof_dir = os.path.join(ROOT, "profiles")
+
+    def hbm(kernel, alg, ms):
+        gbs = alg / (ms / 1e3) / 1e9
+        return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4),
+                "traffic": prof_summary.traffic_if_current(prof_dir, kernel, w.name),
+                "kernel": kernel, "kernel_ms": round(ms, 4), "alg_bytes": int(alg), "per": "launch",
+                "launches_per_step": len(calls)}
+
+    roof_place = hbm("supa_place", place_alg, k_place)
+    roof_scatter = hbm("scatter_nodes", scatter_alg, k_scatter)
     roof_prop = {"bound": "alu", "achieved": round(alu, 3), "peak": round(PEAK_ALU_TOPS, 2),
-                 "unit": "T lane-ops/s", "frac": round(alu / PEAK_ALU_TOPS, 4), "traffic": None,
-                 "kernel": "supa_propagate", "kernel_ms": round(k_prop, 3), "alg_lane_ops": alg_ops,
-                 "per": "step (sum over calls)"}
-    roof_post = {"bound": "hbm", "achieved": round(hbm, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                 "frac": round(hbm / PEAK_HBM_GBS, 4), "traffic": None,
-                 "kernel": "supa_place + scatter_nodes", "kernel_ms": round(k_post, 3), "alg_bytes": out_bytes,
-                 "per": "step (sum over calls)"}
-    roof, other = (roof_post, roof_prop) if k_post >= k_prop else (roof_prop, roof_post)
+                 "unit": "T lane-ops/s", "frac": round(alu / PEAK_ALU_TOPS, 4),
+                 "traffic": prof_summary.traffic_if_current(prof_dir, "supa_propagate", w.name),
+                 "kernel": "supa_propagate", "kernel_ms": round(k_prop, 4),
+                 "alg_lane_ops": int(alg_ops / len(calls)), "per": "launch", "launches_per_step": len(calls)}
+    kern = sorted([(k_place, roof_place), (k_prop, roof_prop), (k_scatter, roof_scatter)], key=lambda t: -t[0])
     line = {
         "metric": "showers/s (1 MI355X)", "value": round(w.n / (ms_per_step / 1e3), 1), "unit": "showers/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+u32",
         "data": "synthetic",
         "config": {"workload": w.name, "showers": w.n, "planes": w.n_planes, "outputs": "hits+images+tree",
+                   "image": f"{L}x{geom['img_ny']}x{geom['img_nx']}",
                    "showers_per_call": chunk, "calls_per_step": len(calls)},
         "particle_steps_per_s": round(steps_total / (ms_per_step / 1e3), 1),
         "particle_steps": steps_total, "hits": hits_total, "nodes": nodes_total,
-        "roofline": roof, "roofline_other": other,
+        "roofline": kern[0][1], "roofline_other": kern[1][1], "roofline_third": kern[2][1],
+        "kernel_ms_per_step": {"supa_propagate": round(prop_ms / args.steps, 2),
+                               "supa_place": round(place_ms / args.steps, 2),
+                               "scatter_nodes": round(scatter_ms / args.steps, 2)},
     }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_sampled(w, geom, args.cpu_seconds, args.cpu_seconds_1t, True)
+        print("oracle baseline done", file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 
@@ -578,7 +649,7 @@ def main():
         sim.run(te0, tpol, taz, w.seed, out)          # kernel times of one eager call
         tm = sim.timing()
         prop_ms.append(tm[0])
-        post_ms.append(tm[1])
+        post_ms.append(tm[3] if outputs & (supa.OUT_HITS | supa.OUT_IMAGES) else tm[4])
         for _ in range(args.warmup):
             g.launch()
         torch.cuda.synchronize()
@@ -595,7 +666,7 @@ def main():
             st = sim.run(te0, tpol, taz, w.seed, out)
             tm = sim.timing()
             prop_ms.append(tm[0])
-            post_ms.append(tm[1])
+            post_ms.append(tm[3] if outputs & (supa.OUT_HITS | supa.OUT_IMAGES) else tm[4])
         torch.cuda.synchronize()
         t1 = time.perf_counter()
     assert st == 0
@@ -626,13 +697,14 @@ def main():
     roof = roof_prop
     roof_other = None
     if outputs & (supa.OUT_HITS | supa.OUT_IMAGES | supa.OUT_TREE):
+        # the placement kernel alone (hits, images), else the node scatter
         k_post = float(np.mean(post_ms))
         out_bytes = 0
         if outputs & supa.OUT_HITS:
             out_bytes += BYTES_PER_HIT * hits_total
         if outputs & supa.OUT_IMAGES:
             out_bytes += w.n * supa.n_layers(geom) * geom["img_nx"] * geom["img_ny"] * 4
-        if outputs & supa.OUT_TREE:
+        if not outputs & (supa.OUT_HITS | supa.OUT_IMAGES):
             out_bytes += BYTES_PER_NODE * int(counts[:, 0].sum())
         hbm = out_bytes / (k_post / 1e3) / 1e9
         kname = "supa_place" if outputs & (supa.OUT_HITS | supa.OUT_IMAGES) else "scatter_nodes"
@@ -674,7 +746,8 @@ def main():
     if roof_other is not None:
         line["roofline_other"] = roof_other
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, geom, args.cpu_seconds, bool(w.images))
+        line["cpu_baseline"] = cpu_baseline_sampled(w, geom, args.cpu_seconds, args.cpu_seconds_1t,
+                                                    bool(w.images))
     print(json.dumps(line), flush=True)
 
 

@@ -317,6 +317,15 @@ supa_status supa_graph_destroy(supa_graph *graph);
 supa_status supa_last_timing(const supa_ctx *ctx, float *ms3);
 
 /*
+ * The same device times split by kernel: ms[0] propagation, [1] placement
+ * and node scatter, [2] whole call, [3] hit / image placement kernel alone,
+ * [4] node scatter kernel alone (each summed over sub-batches; 0 for parts
+ * the call does not run).  Host pointer to `count` floats; entries past the
+ * fifth are set to 0.
+ */
+supa_status supa_last_kernel_times(const supa_ctx *ctx, float *ms, int32_t count);
+
+/*
  * One Philox4x32-10 block per counter, on the device: ctr and out are device
  * arrays of 4*n uint32 (counter words c0..c3 / output words w0..w3).  For
  * checking the device generator against independent implementations.

@@ -103,7 +103,10 @@ struct supa_ctx {
     hipEvent_t ev_begin = nullptr, ev_end = nullptr, ev_joined = nullptr;
     hipEvent_t ev_prop[supa::MAX_SUB][2] = {};    // propagation start / end (stream)
     hipEvent_t ev_post[supa::MAX_SUB][2] = {};    // placement start / end (aux)
-    float timing[3] = {0, 0, 0};
+    hipEvent_t ev_place[supa::MAX_SUB] = {};      // end of the hit / image placement (aux)
+    // propagation, placement + node scatter, whole call, placement alone,
+    // node scatter alone (ms, summed over sub-batches)
+    float timing[5] = {0, 0, 0, 0, 0};
     std::string err;
     bool broken = false;
 };
@@ -304,6 +307,7 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
     for (int b = 0; b < supa::MAX_SUB && ok; ++b)
         for (int q = 0; q < 2 && ok; ++q)
             ok = hipEventCreate(&c->ev_prop[b][q]) == hipSuccess && hipEventCreate(&c->ev_post[b][q]) == hipSuccess;
+    for (int b = 0; b < supa::MAX_SUB && ok; ++b) ok = hipEventCreate(&c->ev_place[b]) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         supa_destroy(c);
@@ -337,6 +341,8 @@ extern "C" supa_status supa_destroy(supa_ctx *c) {
             if (c->ev_prop[b][q]) (void)hipEventDestroy(c->ev_prop[b][q]);
             if (c->ev_post[b][q]) (void)hipEventDestroy(c->ev_post[b][q]);
         }
+    for (int b = 0; b < supa::MAX_SUB; ++b)
+        if (c->ev_place[b]) (void)hipEventDestroy(c->ev_place[b]);
     if (c->aux) (void)hipStreamDestroy(c->aux);
     delete c;
     return SUPA_OK;
@@ -371,7 +377,16 @@ extern "C" supa_status supa_set_schedule(supa_ctx *c, int32_t sub_batches, int32
 extern "C" supa_status supa_last_timing(const supa_ctx *c, float *ms3) {
     if (!c) return SUPA_ERR_STATE;
     if (!ms3) return SUPA_ERR_INVALID_ARG;
-    std::memcpy(ms3, c->timing, sizeof(c->timing));
+    std::memcpy(ms3, c->timing, 3 * sizeof(float));
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_last_kernel_times(const supa_ctx *c, float *ms, int32_t count) {
+    if (!c) return SUPA_ERR_STATE;
+    if (!ms || count < 0) return SUPA_ERR_INVALID_ARG;
+    const int m = std::min<int>(count, 5);
+    std::memcpy(ms, c->timing, (size_t)m * sizeof(float));
+    for (int q = m; q < count; ++q) ms[q] = 0.0f;
     return SUPA_OK;
 }
 
@@ -666,6 +681,7 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
         HIP_TRY(c, supa::launch_scan(SP, s_aux));
         if (timed) HIP_TRY(c, hipEventRecord(c->ev_post[j][0], s_aux));
         if (L.recs) HIP_TRY(c, supa::launch_place(H, c->n_cu, s_aux));
+        if (timed) HIP_TRY(c, hipEventRecord(c->ev_place[j], s_aux));
         if (L.tree) HIP_TRY(c, supa::launch_scatter_nodes(Q, (int32_t)nj, c->n_cu, s_aux));
         if (timed || two) HIP_TRY(c, hipEventRecord(c->ev_post[j][1], s_aux));
     }
@@ -742,16 +758,20 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
                                   hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
-        float t_prop = 0, t_post = 0, t_all = 0, t = 0;
+        float t_prop = 0, t_post = 0, t_all = 0, t_place = 0, t_scatter = 0, t = 0;
         for (int j = 0; j < L.nsub; ++j) {
             if (hipEventElapsedTime(&t, c->ev_prop[j][0], c->ev_prop[j][1]) == hipSuccess) t_prop += t;
             if (L.post && hipEventElapsedTime(&t, c->ev_post[j][0], c->ev_post[j][1]) == hipSuccess) t_post += t;
+            if (L.recs && hipEventElapsedTime(&t, c->ev_post[j][0], c->ev_place[j]) == hipSuccess) t_place += t;
+            if (L.tree && hipEventElapsedTime(&t, c->ev_place[j], c->ev_post[j][1]) == hipSuccess) t_scatter += t;
         }
         (void)hipEventElapsedTime(&t_all, c->ev_begin, c->ev_end);
         (void)hipGetLastError();
         c->timing[0] = t_prop;
         c->timing[1] = t_post;
         c->timing[2] = t_all;
+        c->timing[3] = t_place;
+        c->timing[4] = t_scatter;
         c->last_sub_batches = L.nsub;
         const int r = finish(c, L, out);
         if (r >= 0) return (supa_status)r;

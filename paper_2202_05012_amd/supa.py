@@ -74,7 +74,7 @@ class Output(C.Structure):
 
 EXPORTS = ["supa_abi_version", "supa_validate_geometry", "supa_validate_call", "supa_init_geometry", "supa_destroy",
            "supa_simulate", "supa_set_launch", "supa_set_schedule", "supa_autotune",
-           "supa_graph_create", "supa_graph_launch", "supa_graph_check", "supa_graph_destroy", "supa_last_timing", "supa_philox",
+           "supa_graph_create", "supa_graph_launch", "supa_graph_check", "supa_graph_destroy", "supa_last_timing", "supa_last_kernel_times", "supa_philox",
            "supa_last_error"]
 
 _lib = None
@@ -118,6 +118,8 @@ def load():
         L.supa_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.supa_last_timing.restype = C.c_int
         L.supa_last_timing.argtypes = [C.c_void_p, C.POINTER(C.c_float)]
+        L.supa_last_kernel_times.restype = C.c_int
+        L.supa_last_kernel_times.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int32]
         L.supa_philox.restype = C.c_int
         L.supa_philox.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p]
         L.supa_last_error.restype = C.c_char_p
@@ -233,8 +235,10 @@ class Simulator:
             pass
 
     def timing(self):
-        ms = (C.c_float * 3)()
-        self._check(self.lib.supa_last_timing(self.ctx, ms))
+        """Device ms of the last call: propagation, placement + node scatter,
+        whole call, placement alone, node scatter alone."""
+        ms = (C.c_float * 5)()
+        self._check(self.lib.supa_last_kernel_times(self.ctx, ms, 5))
         return list(ms)
 
     def allocate(self, n: int, hit_capacity: int = 0, node_capacity: int = 0) -> dict:
