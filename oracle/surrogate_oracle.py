@@ -16,6 +16,12 @@ definition, written out:
         (the Gaussian negative log-likelihood without its constant),
   Adam (Kingma & Ba, 2015) with bias correction,
   W1(a, b) = integral |F_a - F_b| = mean |a_(i) - b_(i)| for equal sizes.
+
+Its random parts (noise inputs, sampled per-layer energies) take their
+uniform words from Philox4x32-10 (Salmon et al., SC'11) and turn them into
+normals by the Box-Muller transform; a layer's sampled energy treats its
+bins as equicorrelated normals, whose sum has variance
+(1 - rho) sum sigma^2 + rho (sum sigma)^2.
 """
 from __future__ import annotations
 
@@ -143,3 +149,100 @@ def w1(a, b):
     Fa = np.searchsorted(a, xs[:-1], side="right") / len(a)
     Fb = np.searchsorted(b, xs[:-1], side="right") / len(b)
     return float(np.sum(np.abs(Fa - Fb) * np.diff(xs)))
+
+
+# ---------------------------------------------------------------------------
+# The surrogate's random parts: Philox4x32-10 words, Box-Muller normals, the
+# noise features of the network's inputs and the sampled per-layer energies
+# of the gate.  The random numbers are not inputs here: both sides draw them
+# from the same counter-based generator, each from its own implementation of
+# the published definition.
+# ---------------------------------------------------------------------------
+_M32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(key: int, c0, c1, c2, c3):
+    """Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) over arrays of
+    counters: ten rounds, each multiplying counter words 0 and 2 by the two
+    round multipliers (full 64-bit products), the high halves mixed with
+    words 1 and 3 and the round key, the key advanced by the two Weyl
+    constants between rounds.  Returns the four output words (uint64 arrays
+    holding 32-bit values)."""
+    c = [np.asarray(v, np.uint64) & _M32 for v in np.broadcast_arrays(c0, c1, c2, c3)]
+    k0, k1 = np.uint64(key & 0xFFFFFFFF), np.uint64((key >> 32) & 0xFFFFFFFF)
+    m0, m1 = np.uint64(0xD2511F53), np.uint64(0xCD9E8D57)
+    for _ in range(10):
+        p0 = m0 * c[0]
+        p1 = m1 * c[2]
+        c = [(p1 >> np.uint64(32)) ^ c[1] ^ k0, p1 & _M32, (p0 >> np.uint64(32)) ^ c[3] ^ k1, p0 & _M32]
+        k0 = (k0 + np.uint64(0x9E3779B9)) & _M32
+        k1 = (k1 + np.uint64(0xBB67AE85)) & _M32
+    return c
+
+
+def unit(w):
+    """u(w) = (w + 1/2) / 2^32, in (0, 1)."""
+    return (np.asarray(w, np.float64) + 0.5) * 2.0 ** -32
+
+
+def box_muller(w_a, w_b):
+    """Two independent standard normals from two uniform words (Box and
+    Muller, 1958): r = sqrt(-2 ln u_a), angle 2 pi u_b; (r cos, r sin)."""
+    r = np.sqrt(-2.0 * np.log(unit(w_a)))
+    t = 2.0 * np.pi * unit(w_b)
+    return r * np.cos(t), r * np.sin(t)
+
+
+NOISE_TAG = 0x5EED
+GATE_TAG = 0x9A7E
+
+
+def features(e0, polar, az, e_scale, polar_scale, az_scale, n_noise, seed, row_base=0, stream_id=0):
+    """Input rows of the network: the scaled initial condition, then n_noise
+    standard normals.  Row b draws Philox blocks counted by (row_base + b,
+    stream_id, NOISE_TAG, q), q = 0, 4, 8, ...; the words (w0, w1) and
+    (w2, w3) of a block give normals q, q+1 and q+2, q+3."""
+    e0 = np.asarray(e0, np.float64)
+    B = len(e0)
+    x = np.zeros((B, 3 + n_noise))
+    x[:, 0] = e0 * e_scale
+    x[:, 1] = np.asarray(polar, np.float64) * polar_scale
+    x[:, 2] = np.asarray(az, np.float64) * az_scale
+    rows = (np.arange(B, dtype=np.uint64) + np.uint64(row_base)) & _M32
+    for q in range(0, n_noise, 4):
+        w = philox4x32_10(seed, rows, stream_id, NOISE_TAG, q)
+        z = list(box_muller(w[0], w[1])) + list(box_muller(w[2], w[3]))
+        for e in range(4):
+            if q + e < n_noise:
+                x[:, 3 + q + e] = z[e]
+    return x
+
+
+def gate(out, e0, n_layers, y_scale, s_clamp=S_CLAMP, rho=-1.0, seed=0, row_base=0):
+    """Per-layer energies and uncertainty score of each row of out = [mu | s].
+
+    Layer l of row b: the bins' means and variances exp(s) (s clamped) are
+    summed; with rho < 0 the energy is e0/y_scale * sum mu; with 0 <= rho <= 1
+    it is a sample, e0/y_scale * (sum mu + sd z), where the bins of a layer
+    are normal with correlation rho between any two of them, so the variance
+    of their sum is sd^2 = (1 - rho) sum sigma^2 + rho (sum sigma)^2, and z is
+    the first Box-Muller normal of the Philox block counted by
+    (row_base + b, l, GATE_TAG, 0).  The score is sqrt(sum of all variances)
+    / max(sum of all means, 1e-6)."""
+    out = np.asarray(out, np.float64)
+    B, D2 = out.shape
+    D = D2 // 2
+    mu, s, _ = split_out(out, s_clamp)
+    m = layer_sums(mu, n_layers)
+    var = layer_sums(np.exp(s), n_layers)
+    sig = layer_sums(np.exp(0.5 * s), n_layers)
+    v = m.copy()
+    if rho >= 0:
+        rows = ((np.arange(B, dtype=np.uint64) + np.uint64(row_base)) & _M32)[:, None]
+        layers = np.arange(n_layers, dtype=np.uint64)[None, :]
+        w = philox4x32_10(seed, rows, layers, GATE_TAG, 0)
+        z, _ = box_muller(w[0], w[1])
+        v = m + np.sqrt((1.0 - rho) * var + rho * sig * sig) * z
+    scale = np.asarray(e0, np.float64)[:, None] / y_scale
+    unc = np.sqrt(var.sum(axis=1)) / np.maximum(m.sum(axis=1), 1e-6)
+    return v * scale, unc
