@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+import pytest
 from scipy import stats
 
 from oracle import surrogate_oracle as S
@@ -118,3 +119,83 @@ def test_mse_mean_gradient_finite_differences():
     g0 = S.nll_grad(out, y, s_clamp=20.0)
     np.testing.assert_array_equal(g0[:, 4:], g[:, 4:])
     assert not np.allclose(g0[:, :4], g[:, :4])
+
+
+# ---------------------------------------------------------------------------
+# the random parts: Philox words, Box-Muller normals, noise features and the
+# sampled per-layer energies, pinned to published vectors, an independent
+# generator and distributions derived separately
+# ---------------------------------------------------------------------------
+def test_numpy_philox_matches_published_vectors_and_the_c_oracle():
+    import os
+    from oracle import supa_oracle
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert rows
+    for r in rows:
+        v = [int(t, 16) for t in r if t != "->"]
+        ctr, key, want = v[0:4], v[4] | (v[5] << 32), v[6:10]
+        got = S.philox4x32_10(key, *ctr)
+        assert [int(g) for g in got] == want
+    rng = np.random.default_rng(9)
+    c = rng.integers(0, 2 ** 32, size=(4, 3000), dtype=np.uint64)
+    key = int(rng.integers(0, 2 ** 63))
+    w = S.philox4x32_10(key, *c)
+    for i in range(0, 3000, 131):
+        assert tuple(int(x[i]) for x in w) == supa_oracle.philox4x32_10(key, [int(t[i]) for t in c])
+
+
+def test_noise_features_are_independent_standard_normals():
+    from scipy import stats
+    B = 40000
+    x = S.features(np.linspace(1, 100, B), np.zeros(B), np.zeros(B), 0.01, 1.0, 1.0, 16, seed=77,
+                    row_base=5, stream_id=2)
+    np.testing.assert_allclose(x[:, 0], np.linspace(1, 100, B) * 0.01)
+    z = x[:, 3:]
+    assert stats.kstest(z.ravel(), "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 0.005 and abs(z.std() - 1) < 0.005
+    # columns uncorrelated (the two normals of a pair, and across blocks)
+    cc = np.corrcoef(z.T)
+    assert np.abs(cc - np.eye(16)).max() < 0.03
+    # another stream or seed gives other numbers; the same ones repeat
+    y = S.features(np.ones(B), np.zeros(B), np.zeros(B), 1, 1, 1, 16, seed=77, row_base=5, stream_id=3)
+    assert np.abs(np.corrcoef(z[:, 0], y[:, 3])[0, 1]) < 0.03
+    x2 = S.features(np.linspace(1, 100, B), np.zeros(B), np.zeros(B), 0.01, 1.0, 1.0, 16, seed=77,
+                     row_base=5, stream_id=2)
+    np.testing.assert_array_equal(x, x2)
+    # a row's noise depends on its global row id only
+    x3 = S.features(np.ones(10), np.zeros(10), np.zeros(10), 1, 1, 1, 16, seed=77, row_base=105,
+                     stream_id=2)
+    np.testing.assert_array_equal(x3[:, 3:], z[100:110])
+
+
+@pytest.mark.parametrize("rho", [0.0, 0.4, 1.0])
+def test_sampled_layer_energy_is_the_sum_of_correlated_bins(rho):
+    """The sampled energy of a layer against a Monte Carlo of what it stands
+    for: bins drawn as normals N(mu_b, sigma_b^2) with correlation rho
+    between any two (a common normal with weight sqrt(rho), an own one with
+    weight sqrt(1 - rho)), summed.  Two-sample KS test on many rows of the
+    same prediction."""
+    from scipy import stats
+    rng = np.random.default_rng(int(rho * 10) + 1)
+    L, bins, B = 3, 16, 30000
+    D = L * bins
+    mu = rng.uniform(0, 2, D)
+    s = rng.uniform(-3, 1, D)
+    out = np.tile(np.concatenate([mu, s]), (B, 1))
+    e0 = np.full(B, 50.0)
+    le, unc = S.gate(out, e0, L, y_scale=100.0, rho=rho, seed=3, row_base=11)
+    sig = np.exp(0.5 * s)
+    common = rng.normal(size=(B, 1))
+    own = rng.normal(size=(B, D))
+    bins_mc = mu + sig * (np.sqrt(rho) * common + np.sqrt(1 - rho) * own)
+    mc = bins_mc.reshape(B, L, bins).sum(axis=2) * 0.5
+    for l in range(L):
+        assert stats.ks_2samp(le[:, l], mc[:, l]).pvalue > 1e-3, l
+    # rho < 0: the means, and the score of the oracle's uncertainty()
+    lm, um = S.gate(out[:5], e0[:5], L, y_scale=100.0)
+    np.testing.assert_allclose(lm, S.layer_sums(out[:5, :D], L) * 0.5)
+    np.testing.assert_allclose(um, S.uncertainty(out[:5, :D], out[:5, D:], L))
+    # layers of a row draw independent normals
+    z = (le - mu.reshape(L, bins).sum(axis=1) * 0.5)
+    assert np.abs(np.corrcoef(z.T) - np.eye(L)).max() < 0.03
