@@ -153,3 +153,82 @@ def check_all(gpu: dict, ref: dict, geom: dict, images=False, tree=False, rows=N
         check_tree(gpu, ref, rows, max_slope)
     if images:
         check_images(gpu, ref, geom, rows)
+
+
+def tree_path_ids(parent) -> np.ndarray:
+    """Path ids of one shower's nodes from their parent indices alone.
+
+    The output layout fixes the numbering: node 0 is the primary (path 1) and
+    the two daughters of a split are consecutive, the first of them at an odd
+    index, so node 2m+1 has path 2 * path(parent) and node 2m+2 has path
+    2 * path(parent) + 1; a parent always precedes its daughters."""
+    parent = np.asarray(parent, np.int64)
+    n = len(parent)
+    path = np.zeros(n, np.uint64)
+    if n == 0:
+        return path
+    assert parent[0] == -1, "node 0 must be the primary"
+    j = np.arange(1, n)
+    assert ((parent[1:] >= 0) & (parent[1:] < j)).all(), "a parent must precede its daughters"
+    assert (parent[2::2] == parent[1:-1:2][:len(parent[2::2])]).all(), \
+        "the daughters of a split must be adjacent"
+    second = (np.arange(n) % 2 == 0).astype(np.uint64)      # node 2m+2: the second daughter
+    known = np.zeros(n, bool)
+    path[0], known[0] = 1, True
+    par = np.maximum(parent, 0)
+    while not known.all():                 # one generation per pass
+        todo = ~known & known[par]
+        assert todo.any()
+        path[todo] = np.uint64(2) * path[par[todo]] + second[todo]
+        known[todo] = True
+    return path
+
+
+def with_tree_keys(gpu: dict, rows=None) -> dict:
+    """A copy of the GPU outputs with node_key filled in from the tree's
+    numbering (outputs written without path ids)."""
+    g = dict(gpu)
+    key = np.zeros(len(gpu["node_parent"]), np.uint64)
+    rows = np.arange(len(gpu["counts"])) if rows is None else np.asarray(rows)
+    for i in rows:
+        off, cnt = int(gpu["node_offsets"][i]), int(gpu["counts"][i, 0])
+        key[off:off + cnt] = tree_path_ids(gpu["node_parent"][off:off + cnt])
+    g["node_key"] = key
+    return g
+
+
+def check_hits_unkeyed(gpu: dict, ref: dict, rows=None):
+    """Hit clouds written without path ids: per shower, the multiset of
+    (layer, energy) is exact, and each hit's coordinates match the oracle's
+    hit of the same layer and energy (hits tied on both are matched in x
+    order) within the coordinate bar."""
+    fb = ref["frac_bits"]
+    n = ref["n"]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    base = ref["shower_id_base"]
+    order = np.argsort(ref["hit_sid"], kind="stable")
+    rs = ref["hit_sid"][order]
+    starts = np.searchsorted(rs, base + np.arange(n))
+    ends = np.searchsorted(rs, base + np.arange(n), side="right")
+    for s in range(n):
+        g = rows[s]
+        off, cnt = int(gpu["hit_offsets"][g]), int(gpu["counts"][g, 1])
+        sl = slice(off, off + cnt)
+        ri = order[starts[s]:ends[s]]
+        assert cnt == len(ri), f"shower {s}: {cnt} hits vs {len(ri)}"
+        # grouped by plane: layers never decrease along a segment when the
+        # layer map is monotone (identity here)
+        ge = np.asarray(gpu["hit_e"][sl], np.float32)
+        re = _f32_energy(ref["hit_e"][ri], fb)
+        gk = np.lexsort((np.asarray(gpu["hit_x"][sl], np.float64), ge, gpu["hit_layer"][sl]))
+        rk = np.lexsort((ref["hit_x"][ri], re, ref["hit_layer"][ri]))
+        np.testing.assert_array_equal(gpu["hit_layer"][sl][gk], ref["hit_layer"][ri][rk],
+                                      err_msg=f"shower {s}: layers")
+        np.testing.assert_array_equal(ge[gk], re[rk], err_msg=f"shower {s}: hit energies")
+        r = np.hypot(ref["hit_x"][ri][rk], ref["hit_y"][ri][rk])
+        for c in ("x", "y"):
+            ok = _coord_ok(gpu["hit_" + c][sl][gk], ref["hit_" + c][ri][rk], r)
+            if not ok.all():
+                bad = np.nonzero(~ok)[0][0]
+                raise AssertionError(f"shower {s}: hit {c} {gpu['hit_' + c][sl][gk][bad]} vs "
+                                     f"{ref['hit_' + c][ri][rk][bad]}")

@@ -1,0 +1,78 @@
+"""The comparison helpers used by the GPU parity tests, checked on the CPU
+against the oracle's own outputs (no GPU)."""
+import numpy as np
+import pytest
+
+from oracle import supa_oracle as O
+from paper_2202_05012_amd import workloads
+from tests import parity
+
+
+def oracle_as_gpu(ref, rng):
+    """The oracle's outputs laid out as the library writes them (segments in
+    batch order, float32, hits shuffled within each shower, no path ids)."""
+    n = ref["n"]
+    hs = np.argsort(ref["hit_sid"], kind="stable")
+    h = {k: ref[k][hs] for k in ("hit_x", "hit_y", "hit_e", "hit_layer")}
+    cnt = ref["counts"][:, 1]
+    off = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+    perm = np.concatenate([o + rng.permutation(c) for o, c in zip(off, cnt)]).astype(np.int64)
+    fb = ref["frac_bits"]
+    return {"counts": ref["counts"].copy(), "ledger": ref["ledger"].copy(), "hit_offsets": off,
+            "hit_x": h["hit_x"][perm].astype(np.float32), "hit_y": h["hit_y"][perm].astype(np.float32),
+            "hit_e": (h["hit_e"][perm].astype(np.float32) * np.float32(2.0 ** -fb)),
+            "hit_layer": h["hit_layer"][perm],
+            "node_offsets": np.concatenate([[0], np.cumsum(ref["counts"][:, 0])[:-1]]),
+            "node_parent": ref["node_parent"], "node_gen": ref["node_gen"],
+            "node_vx": ref["node_vx"].astype(np.float32), "node_vy": ref["node_vy"].astype(np.float32),
+            "node_vz": ref["node_vz"].astype(np.float32),
+            "node_e": ref["node_e"].astype(np.float32) * np.float32(2.0 ** -fb)}
+
+
+@pytest.fixture(scope="module")
+def fifty_plane():
+    w = workloads.WORKLOADS["loge10to1000_50planes_tree_img256_1m"]
+    g = workloads.geometry(w)
+    e0, p, a = workloads.initial_conditions(w, 12)
+    return O.simulate(g, e0, p, a, w.seed)
+
+
+def test_path_ids_rebuilt_from_the_tree_numbering(fifty_plane):
+    ref = fifty_plane
+    st = np.concatenate([[0], np.cumsum(ref["counts"][:, 0])])
+    for s in range(ref["n"]):
+        sl = slice(st[s], st[s + 1])
+        np.testing.assert_array_equal(parity.tree_path_ids(ref["node_parent"][sl]), ref["node_key"][sl])
+
+
+def test_path_ids_refuse_a_numbering_that_breaks_the_layout():
+    with pytest.raises(AssertionError):
+        parity.tree_path_ids([0, 0, 0])                 # node 0 is not the primary
+    with pytest.raises(AssertionError):
+        parity.tree_path_ids([-1, 0, 1])                # daughters of one split not adjacent
+    with pytest.raises(AssertionError):
+        parity.tree_path_ids([-1, 2, 2])                # parent after its daughter
+
+
+def test_unkeyed_comparisons_accept_the_oracle_and_catch_changes(fifty_plane):
+    ref = fifty_plane
+    rng = np.random.default_rng(3)
+    gpu = oracle_as_gpu(ref, rng)
+    parity.check_counts(gpu, ref)
+    parity.check_hits_unkeyed(gpu, ref)
+    parity.check_tree(parity.with_tree_keys(gpu), ref)
+    # a moved hit, a changed energy and a rewired parent are caught
+    bad = dict(gpu, hit_x=gpu["hit_x"].copy())
+    bad["hit_x"][5] += np.float32(1e-3)
+    with pytest.raises(AssertionError):
+        parity.check_hits_unkeyed(bad, ref)
+    bad = dict(gpu, hit_e=gpu["hit_e"].copy())
+    bad["hit_e"][7] = np.nextafter(bad["hit_e"][7], np.float32(1))
+    with pytest.raises(AssertionError):
+        parity.check_hits_unkeyed(bad, ref)
+    bad = dict(gpu, node_parent=gpu["node_parent"].copy())
+    i = int(np.nonzero(bad["node_parent"] > 1)[0][0])
+    j = i + 1 if i % 2 else i - 1                      # keep the pair adjacent
+    bad["node_parent"][[i, j]] = bad["node_parent"][i] - 1
+    with pytest.raises(AssertionError):
+        parity.check_tree(parity.with_tree_keys(bad), ref)
