@@ -525,6 +525,9 @@ def test_library_refuses_a_batch_larger_than_its_outputs():
     e0, pol, az = workloads.initial_conditions(w, 64)
     sim = supa.Simulator(geom, ALL)
     out = sim.allocate(32, 1 << 16, 1 << 16)
+    for v in out.values():
+        if isinstance(v, torch.Tensor):
+            v.fill_(-7)                          # a known pattern (fresh memory may hold NaNs)
     guard = {k: v.clone() for k, v in out.items() if isinstance(v, torch.Tensor)}
     te0, tpol, taz = dev_t(e0), dev_t(pol), dev_t(az)
     b, o = sim._marshal(te0[:32], tpol[:32], taz[:32], out, None, None, 0)
@@ -567,3 +570,104 @@ def test_full_size_50plane_call_sampled_parity():
         ref = O.simulate(geom, e0[sl][rows], pol[sl][rows], az[sl][rows], w.seed,
                          shower_id_base=int(s0 + start))
         parity.check_all(gpu, ref, geom, images=True, tree=True)
+
+
+def _gpu_rows(out, rows, images):
+    """Host copies of the showers `rows` of a call: per-shower rows, their
+    hit and node segments (offsets rebased), images if asked."""
+    res = sampled_segments({k: v for k, v in out.items() if k != "images"}, rows)
+    if images:
+        res["images"] = out["images"][torch.from_numpy(np.asarray(rows)).cuda()].cpu().numpy()
+    return res
+
+
+@pytest.mark.slow
+def test_fifty_plane_1000_showers_as_benchmarked():
+    """The 50-plane workload (E0 log-uniform on [10, 1000]) in the benchmark's
+    exact configuration: calls of 10,000 showers writing hits, 50 x 256x256
+    images and the tree, without path ids (the kernels the benchmark times).
+    Five calls spread over the 1,000,000 showers; in each, 200 showers in
+    blocks of 20 at random are compared with the oracle -- 1,000 in all:
+    counts and ledgers exactly, the tree exactly through path ids rebuilt
+    from its numbering (parents, generations, energies, vertices), hits as
+    exact (layer, energy) multisets with matching coordinates; the images of
+    one block of 4 showers per call exactly (up to cells at the edge
+    tolerance)."""
+    w = workloads.WORKLOADS["loge10to1000_50planes_tree_img256_1m"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w)
+    m = 10_000
+    sim = supa.Simulator(geom, supa.OUT_HITS | supa.OUT_IMAGES | supa.OUT_TREE)
+    starts = (0, 240_000, 500_000, 760_000, w.n - m)
+    # capacities: the largest of the five calls' totals (zero-capacity probes)
+    probe = sim.allocate(m, 0, 0)
+    need_h = need_n = 0
+    for s0 in starts:
+        sl = slice(s0, s0 + m)
+        sim.run(dev_t(e0[sl]), dev_t(pol[sl]), dev_t(az[sl]), w.seed, probe, shower_id_base=s0)
+        need_h, need_n = max(need_h, probe["total_hits"]), max(need_n, probe["total_nodes"])
+    del probe
+    out = sim.allocate(m, int(need_h), int(need_n))
+    rng = np.random.default_rng(44)
+    compared = 0
+    for s0 in starts:
+        sl = slice(s0, s0 + m)
+        args = (dev_t(e0[sl]), dev_t(pol[sl]), dev_t(az[sl]), w.seed)
+        print(f"50-plane call at shower {s0}", flush=True)
+        assert sim.run(*args, out, shower_id_base=s0) == 0
+        torch.cuda.synchronize()
+        for b, start in enumerate(sorted(rng.choice(m // 20, 10, replace=False) * 20)):
+            rows = np.arange(start, start + 20)
+            gpu = _gpu_rows(out, rows, images=False)
+            ref = O.simulate(geom, e0[sl][rows], pol[sl][rows], az[sl][rows], w.seed,
+                             shower_id_base=int(s0 + start))
+            parity.check_counts(gpu, ref)
+            parity.check_tree(parity.with_tree_keys(gpu), ref)
+            parity.check_hits_unkeyed(gpu, ref)
+            if b == 0:
+                img_rows = rows[:4]
+                gi = _gpu_rows(out, img_rows, images=True)
+                ri = O.simulate(geom, e0[sl][img_rows], pol[sl][img_rows], az[sl][img_rows], w.seed,
+                                shower_id_base=int(s0 + start))
+                parity.check_images(gi, ri, geom)
+            compared += len(rows)
+    assert compared == 1000
+
+
+@pytest.mark.slow
+def test_1m_20plane_1000_showers_as_benchmarked():
+    """The 1,000,000-shower, 20-plane workload with E0 log-uniform on
+    [1, 1000] as its benchmark line runs it: launch settings picked by the
+    autotuner, the call captured as a graph and replayed, hit clouds without
+    path ids.  1,000 showers (50 blocks of 20 at random over the batch)
+    compared with the oracle: counts and ledgers exactly, hits as exact
+    (layer, energy) multisets with matching coordinates."""
+    w = workloads.WORKLOADS["loge1to1000_20planes_1m"]
+    geom = workloads.geometry(w)
+    e0, pol, az = workloads.initial_conditions(w)
+    te0, tpol, taz = dev_t(e0), dev_t(pol), dev_t(az)
+    sim = supa.Simulator(geom, supa.OUT_HITS)
+    probe = sim.allocate(w.n, 0, 0)
+    sim.run(te0, tpol, taz, w.seed, probe)
+    out = sim.allocate(w.n, int(probe["total_hits"]) + 1, 0)
+    del probe
+    best = sim.autotune(te0, tpol, taz, w.seed, out)
+    print(f"autotuned: {best}", flush=True)
+    g = sim.graph(te0, tpol, taz, w.seed, out)
+    for v in (out["hit_x"], out["counts"], out["ledger"]):
+        v.fill_(-7)
+    g.launch()
+    g.check()
+    torch.cuda.synchronize()
+    counts = out["counts"].cpu().numpy()
+    ledger = out["ledger"].cpu().numpy().astype(np.uint64)
+    assert (ledger[:, 1] + ledger[:, 2] + ledger[:, 3] == ledger[:, 0]).all()
+    assert out["total_hits"] == counts[:, 1].sum()
+    rng = np.random.default_rng(45)
+    for start in sorted(rng.choice(w.n // 20, 50, replace=False) * 20):
+        rows = np.arange(start, start + 20)
+        gpu = _gpu_rows(out, rows, images=False)
+        ref = O.simulate(geom, e0[rows], pol[rows], az[rows], w.seed, shower_id_base=int(start))
+        parity.check_counts(gpu, ref)
+        parity.check_hits_unkeyed(gpu, ref)
+    g.close()

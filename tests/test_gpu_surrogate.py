@@ -271,3 +271,192 @@ def test_colsum_two_pass_and_single_pass():
     bound = 2e-6 * np.abs(bf16_to_np(X)).astype(np.float64).sum(axis=0) + 1e-6
     for o in outs:
         assert (np.abs(o - ref) <= bound).all()
+
+
+# ---------------------------------------------------------------------------
+# the random parts and the whole network at the workload's shapes, against
+# the FP64 oracle element by element
+# ---------------------------------------------------------------------------
+def test_features_match_oracle():
+    """Input rows against the oracle's scaled initial conditions and its
+    Philox + Box-Muller normals on the same counters (FP64).  Bar per entry:
+    half a bf16 unit (2^-8 relative) plus 5e-4: the device forms u from a
+    float, whose rounding of a word near 2^32 moves u by up to 2^-25 and so
+    sqrt(-2 ln u) by up to sqrt(2 * 2^-25 * 2) ~ 3.5e-4 where u is within 1e-7
+    of 1 (elsewhere the float error is ~1e-6 relative)."""
+    rng = np.random.default_rng(12)
+    B = 6000
+    e0 = rng.uniform(1, 100, B).astype(np.float32)
+    pol = rng.uniform(0, math.radians(15), B).astype(np.float32)
+    az = rng.uniform(0, 2 * math.pi, B).astype(np.float32)
+    seed, row_base, stream = 0x1234567890ABCDEF, 2 ** 32 - 3000, 7      # row ids wrap past 2^32
+    t = lambda a: torch.from_numpy(a).cuda()
+    x = S.features(t(e0), t(pol), t(az), seed=seed, row_base=row_base, stream_id=stream)
+    got = S.bf16_to_float(x).cpu().numpy().astype(np.float64)
+    ref = SO.features(e0, pol, az, np.float32(1 / 100), np.float32(1 / math.radians(15)),
+                      np.float32(1 / (2 * math.pi)), S.N_NOISE, seed, row_base, stream)
+    n = 3 + S.N_NOISE
+    tol = 2.0 ** -8 * np.abs(ref) * (1 + 1e-4)
+    tol[:, 3:] += 5e-4
+    err = np.abs(got[:, :n] - ref)
+    assert (err <= tol).all(), (np.unravel_index(np.argmax(err - tol), err.shape), float((err - tol).max()))
+    assert (got[:, n:] == 0).all()
+
+
+def _gate_case(rng, B, L, bins):
+    D = L * bins
+    out = np.empty((B, 2 * D), np.float32)
+    out[:, :D] = rng.uniform(-0.2, 2.0, size=(B, D)) / bins * 30
+    out[:, D:] = rng.uniform(-9, 3, size=(B, D))
+    out[: B // 8, D:D + 7] = rng.choice([-30.0, 25.0], size=(B // 8, 7))      # beyond the clamp
+    e0 = rng.uniform(1, 100, B).astype(np.float32)
+    return out, e0
+
+
+def _gate_tol(out, e0, L, rho, ref_le):
+    """Bar of a layer energy: float sums over a layer's bins (2e-5 of the sum
+    of |mu|, 1e-5 of sd), z within 5e-4 (see the features test) and 5e-5
+    relative, times the row's scale."""
+    D = out.shape[1] // 2
+    mu = out[:, :D].astype(np.float64)
+    s = np.clip(out[:, D:].astype(np.float64), -S.S_CLAMP, S.S_CLAMP)
+    scale = e0.astype(np.float64)[:, None] / S.Y_SCALE
+    m = SO.layer_sums(mu, L)
+    sd = np.sqrt((1 - rho) * SO.layer_sums(np.exp(s), L) + rho * SO.layer_sums(np.exp(s / 2), L) ** 2) \
+        if rho >= 0 else np.zeros_like(m)
+    z = (ref_le / scale - m) / np.where(sd > 0, sd, 1)
+    return scale * (3e-5 * SO.layer_sums(np.abs(mu), L) + sd * (5e-4 + 5e-5 * np.abs(z))) + 1e-30
+
+
+@pytest.mark.parametrize("rho", [-1.0, 0.0, 0.35, 1.0])
+def test_gate_matches_oracle(rho):
+    """Per-layer energies (means, or samples at bin correlation rho) and
+    uncertainty scores against the oracle on the same outputs, at the
+    workload's 20 layers x 256 bins, log-variances inside and beyond the
+    clamp."""
+    rng = np.random.default_rng(40 + int(10 * rho))
+    B, L, bins = 301, 20, 256
+    out, e0 = _gate_case(rng, B, L, bins)
+    seed, row_base = 0xC0FFEE12345, 17
+    le, unc, _ = S.gate(torch.from_numpy(out).cuda(), torch.from_numpy(e0).cuda(), L, rho=rho, seed=seed,
+                        row_base=row_base)
+    ref_le, ref_unc = SO.gate(out, e0, L, S.Y_SCALE, S.S_CLAMP, rho, seed, row_base)
+    err = np.abs(le.cpu().numpy() - ref_le)
+    tol = _gate_tol(out, e0, L, rho, ref_le)
+    assert (err <= tol).all(), float((err / tol).max())
+    np.testing.assert_allclose(unc.cpu().numpy(), ref_unc, rtol=1e-4)
+
+
+@pytest.mark.parametrize("rho", [-1.0, 0.5])
+def test_gate_fused_matches_oracle_at_workload_shapes(rho):
+    """The fused final layer + gate (20 layers x 256 bins, K = 256 hidden
+    units) against the oracle's gate on the FP64 product of the same bf16
+    operands; the product adds float32 accumulation error, 2e-6 of
+    sum |h||W| per output, carried through the layer sums (bar: the gate's
+    bar plus that, summed over a layer's bins, and 2e-4 relative for the
+    exponentials of the log-variances)."""
+    rng = np.random.default_rng(61)
+    B, K, L, bins = 300, 256, 20, 256
+    D = L * bins
+    h = bf16_round(np.abs(rng.normal(size=(B, K))))
+    W = (rng.normal(size=(K, 2 * D)) * 0.02).astype(np.float32)
+    bias = np.concatenate([np.full(D, 0.05), np.full(D, -4.0)]).astype(np.float32)
+    e0 = rng.uniform(1, 100, B).astype(np.float32)
+    Wb = bf16_round(W)
+    hf, Wf = bf16_to_np(h).astype(np.float64), bf16_to_np(Wb).astype(np.float64)
+    o = hf @ Wf + bias
+    wt = S.transpose_to_bf16(torch.from_numpy(W).cuda())
+    le, unc = S.gate_fused(dev16(h), wt, torch.from_numpy(bias).cuda(), torch.from_numpy(e0).cuda(), L,
+                           rho=rho, seed=5, row_base=3)
+    ref_le, ref_unc = SO.gate(o, e0, L, S.Y_SCALE, S.S_CLAMP, rho, 5, 3)
+    acc = 2e-6 * (np.abs(hf) @ np.abs(Wf))
+    scale = e0.astype(np.float64)[:, None] / S.Y_SCALE
+    s = np.clip(o[:, D:], -S.S_CLAMP, S.S_CLAMP)
+    tol = _gate_tol(o.astype(np.float32), e0, L, rho, ref_le) + scale * SO.layer_sums(acc[:, :D], L)
+    if rho >= 0:
+        tol += scale * 4 * SO.layer_sums(np.exp(s / 2) * (acc[:, D:] + 2e-4), L)
+    err = np.abs(le.cpu().numpy() - ref_le)
+    assert (err <= tol).all(), float((err / tol).max())
+    np.testing.assert_allclose(unc.cpu().numpy(), ref_unc, rtol=3e-4)
+
+
+@pytest.mark.slow
+def test_network_at_workload_shapes_vs_oracle():
+    """The surrogate's network at its workload shapes (inputs 32 = 3 + 16
+    noise + padding, 4 x 256 GELU, output 2 x 20 x 256 = 10240) on 1,024
+    rows: every layer's product and epilogue element by element against
+    FP64 on the same bf16 operands (the device's own inputs to that layer),
+    forward and backward; the whole network's outputs and weight gradients
+    within a relative Frobenius error of 1e-2 of the FP64 chain.
+
+    Per-layer bars: float32 accumulation, 2e-6 * sum_k |a_ik||b_kj| (K <=
+    1024, well above the ~K * 2^-24 / sqrt(3) a sum of K rounded products
+    drifts by), plus half a bf16 unit (2^-8 relative) where the epilogue
+    writes bf16; GELU and GELU' are 1.13-Lipschitz in the accumulated value."""
+    from paper_2202_05012_amd import surrogate_pipeline as SP  # noqa: F401 (dims)
+    dims = S.surrogate_dims()
+    assert dims == [32, 256, 256, 256, 256, 10240]
+    B = 1024
+    net = S.MLP(dims, seed=3)
+    rng = np.random.default_rng(77)
+    for l in range(len(dims) - 1):                      # non-zero biases exercise the epilogues
+        net.b[l].copy_(torch.from_numpy(rng.normal(0, 0.1, dims[l + 1]).astype(np.float32)))
+    e0 = torch.from_numpy(rng.uniform(1, 100, B).astype(np.float32)).cuda()
+    pol = torch.from_numpy(rng.uniform(0, math.radians(15), B).astype(np.float32)).cuda()
+    az = torch.from_numpy(rng.uniform(0, 2 * math.pi, B).astype(np.float32)).cuda()
+    x = S.features(e0, pol, az, seed=9)
+    out, acts, pres = net.forward(x, keep=True)
+    Wf = [bf16_to_np(host16(w)).astype(np.float64) for w in net.Wb]
+    bf = [b.cpu().numpy().astype(np.float64) for b in net.b]
+    A = [bf16_to_np(host16(a)).astype(np.float64) for a in acts]
+    P = [bf16_to_np(host16(p)).astype(np.float64) for p in pres]
+    nl = len(Wf)
+    for l in range(nl):
+        ref = A[l] @ Wf[l] + bf[l]
+        acc = 2e-6 * (np.abs(A[l]) @ np.abs(Wf[l])) + 1e-7
+        if l < nl - 1:
+            assert (np.abs(P[l] - ref) <= 2.0 ** -8 * np.abs(ref) + acc).all(), ("pre", l)
+            g = SO.gelu(ref)
+            assert (np.abs(A[l + 1] - g) <= 2.0 ** -8 * np.abs(g) + 1.13 * acc).all(), ("act", l)
+        else:
+            got = out.cpu().numpy().astype(np.float64)
+            assert (np.abs(got - ref) <= acc).all(), "output"
+    # the whole chain in FP64 from the same bf16 weights and inputs
+    params = [[W, b] for W, b in zip(Wf, bf)]
+    ref_out, cache = SO.forward(params, A[0])
+    e_fwd = rel_fro(out.cpu().numpy(), ref_out)
+    assert e_fwd <= 1e-2, e_fwd
+
+    # backward: the loss gradient at simulated-looking targets, then every
+    # layer's three products on the device's own bf16 operands
+    D = dims[-1] // 2
+    img = torch.from_numpy(rng.exponential(0.05, size=(B, D)).astype(np.float32)).cuda()
+    dout = torch.empty((B, 2 * D), dtype=torch.int16, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    S._check(S._lib().supa_nll_grad(S._stream(), B, D, S._p(out), S._p(img), S._p(e0), S.Y_SCALE,
+                                    S.S_CLAMP, 1, S._p(dout), S._p(loss)))
+    g = dout
+    G = bf16_to_np(host16(dout)).astype(np.float64)
+    dWs, dbs = net.backward(acts, pres, dout)
+    for l in range(nl - 1, -1, -1):
+        ref_dw = A[l].T @ G
+        assert (np.abs(dWs[l].cpu().numpy() - ref_dw) <= 2e-6 * (np.abs(A[l]).T @ np.abs(G)) + 1e-9).all(), \
+            ("dW", l)
+        ref_db = G.sum(axis=0)
+        assert (np.abs(dbs[l].cpu().numpy() - ref_db) <= 2e-6 * np.abs(G).sum(axis=0) + 1e-9).all(), ("db", l)
+        if l > 0:
+            gn = torch.empty((B, dims[l]), dtype=torch.int16, device="cuda")
+            S.gemm(g, net.Wb[l], gn, trans_a=0, trans_b=1, epilogue=3, pre=pres[l - 1])
+            GN = bf16_to_np(host16(gn)).astype(np.float64)
+            back = G @ Wf[l].T
+            ref_gn = back * SO.gelu_grad(P[l - 1])
+            # float accumulation, GELU' in float (a few 1e-6 relative), bf16 rounding
+            acc = 1.01 * (2e-6 * (np.abs(G) @ np.abs(Wf[l]).T) * 1.13 + 4e-6 * np.abs(back)) + 1e-12
+            assert (np.abs(GN - ref_gn) <= 2.0 ** -8 * np.abs(ref_gn) + acc).all(), ("dX", l)
+            g, G = gn, GN
+    # whole backward in FP64 from the same output gradient
+    ref_g = SO.backward(params, cache, bf16_to_np(host16(dout)).astype(np.float64))
+    for l in range(nl):
+        e_w = rel_fro(dWs[l].cpu().numpy(), ref_g[l][0])
+        e_b = rel_fro(dbs[l].cpu().numpy(), ref_g[l][1])
+        assert e_w <= 1e-2 and e_b <= 1e-2, (l, e_w, e_b)
