@@ -233,6 +233,28 @@ supa_status supa_simulate(supa_ctx *ctx, const supa_batch *b, uint64_t seed,
                           supa_output *out);
 
 /*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, outputs, numerics and errors as supa_simulate, but the library's
+ * scratch (particle spill, hit and node logs, per-shower log starts, scan
+ * partial sums, work order, image buckets) is carved out of one fixed device
+ * array of SUPA_FIXED_SCRATCH_BYTES per GPU -- a static array of the library,
+ * resolved once per device by supa_init_geometry and held until the process
+ * ends -- and the call makes no hipMalloc, hipFree or other allocation, never
+ * grows its scratch and never reruns.  Limits: the per-shower part (8 bytes
+ * per shower with hits or images, 4 more with the cost order, plus scan
+ * sums) must fit, and the particles a batch leaves pending and the hit and
+ * node records it writes must fit the rest; otherwise SUPA_ERR_NOMEM, with
+ * nothing meaningful in the outputs (a call of fewer showers, or
+ * supa_simulate, then runs it).  Every call on one GPU uses that GPU's one
+ * array: calls that overlap in time on the same GPU (any context, stream or
+ * thread) race on it and give wrong results.  Calls of supa_simulate do not
+ * touch it.
+ */
+#define SUPA_FIXED_SCRATCH_BYTES (256ull << 20)
+supa_status supa_simulate_noalloc(supa_ctx *ctx, const supa_batch *b, uint64_t seed, supa_output *out);
+
+/*
  * Launch settings of the propagation kernel (affect speed only, never
  * results; 0 keeps the current value of a setting).
  *   waves_per_cu  waves launched per compute unit, 1..32 (each wave keeps a

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -63,6 +64,32 @@ struct DevBuf {
 static constexpr int kMaxImageWidth = 1024;
 static constexpr int64_t kAutoOrderMin = 65536;     // automatic cost order: from this batch size
 
+// Scratch of supa_simulate_noalloc: one fixed array per GPU, held from the
+// library's first use of a device until the process ends.  Host code never
+// passes `scratch` itself to a kernel (on the host it is only a stand-in for
+// the symbol): it uses the device address resolved once per device below.
+static constexpr size_t kFixedBytes = SUPA_FIXED_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kFixedBytes];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_fixed_mu;
+static void *g_fixed[kMaxDevices];
+
+// The device address of `device`'s copy of the fixed array; the device must
+// be current.  Resolved on the first call for a device, then reused.
+static hipError_t fixed_scratch(int device, void **ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_fixed_mu);
+    if (!g_fixed[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_fixed[device] = p;
+    }
+    *ptr = g_fixed[device];
+    return hipSuccess;
+}
+
 // threshold table: 4 rings x 64 planes (the propagation kernel's layout)
 constexpr int THR_ENTRIES = 4 * 64;
 
@@ -97,6 +124,7 @@ struct supa_ctx {
     int last_sub_batches = 0;
     DevBuf spill, hlog, nlog, shower, bucket;
     uint64_t scratch_gen = 0;            // advanced by every scratch reallocation
+    char *fixed = nullptr;               // this device's fixed scratch array (device address)
     // the placement of a sub-batch runs on a second stream, overlapping the
     // propagation of the next one
     hipStream_t aux = nullptr;
@@ -284,6 +312,13 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
         delete c;
         return fail(nullptr, SUPA_ERR_DEVICE, "cannot query compute units");
     }
+    void *fx = nullptr;
+    e = fixed_scratch(device, &fx);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(nullptr, e, "hipGetSymbolAddress of the fixed scratch array");
+    }
+    c->fixed = (char *)fx;
     bool ok = hipMalloc(&c->d_layer, N * sizeof(int32_t)) == hipSuccess &&
               hipMalloc(&c->d_c1, THR_ENTRIES * sizeof(uint64_t)) == hipSuccess &&
               hipMalloc(&c->d_layer_plane_start, lps.size() * sizeof(int32_t)) == hipSuccess &&
@@ -481,9 +516,12 @@ struct Plan {
 
 static constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Sizes the scratch for the call (growing it when needed) and fills the plan.
+// Sizes the scratch for the call and fills the plan.  fixed == nullptr: the
+// context's buffers, grown when needed; otherwise every piece is carved out
+// of the fixed array at `fixed` (kFixedBytes), nothing is allocated, and the
+// pieces are sized to fit it (a batch that needs more fails, see finish).
 static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa_output *out, Plan &L,
-                           int force_nsub) {
+                           int force_nsub, char *fixed = nullptr) {
     const uint32_t outs = c->g.outputs;
     const int64_t n = b->n;
     L.n = n;
@@ -500,42 +538,95 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
     int nsub = force_nsub > 0 ? force_nsub : (c->sub_batches > 0 ? c->sub_batches : 1);
     if (!L.post) nsub = 1;
     L.nsub = (int)std::min<int64_t>(std::min(nsub, supa::MAX_SUB), n);
+    // the placement kernel's variant (with path ids): sizes and launch must agree
+    L.place_keys = L.hits_out && (outs & SUPA_OUT_KEYS) && out->hit_key != nullptr;
 
-    // scratch: per-wave spill, logs, per-shower log starts, scan tile sums, work order
-    const size_t spill_b = al256((size_t)L.waves * supa::POOL_FIELDS * c->spill_cap * 4);
-    if (!c->spill.ensure(spill_b, &c->scratch_gen)) return nomem(c, "spill area", spill_b);
-    const size_t hnext_b = L.recs ? al256((size_t)c->h_chunks * 4) : 0;
-    const size_t hlog_b = L.recs ? hnext_b + (size_t)c->h_chunks * supa::HIT_CHUNK_WORDS * 4 : 0;
-    if (L.recs && !c->hlog.ensure(hlog_b, &c->scratch_gen)) return nomem(c, "hit log", hlog_b);
-    const size_t nfill_b = L.tree ? al256((size_t)c->n_chunks * 4) : 0;
-    const size_t nlog_b = L.tree ? nfill_b + (size_t)c->n_chunks * supa::NL_FIELDS * supa::LOG_CHUNK * 4 : 0;
-    if (L.tree && !c->nlog.ensure(nlog_b, &c->scratch_gen)) return nomem(c, "node log", nlog_b);
+    // scratch: per-shower log starts, scan tile sums, work order; per-wave
+    // spill; image buckets; hit and node logs
     const size_t hstart_b = L.recs ? al256((size_t)n * 8) : 0;
     const size_t part_b = al256((size_t)supa::scan_partial_words(n) * 8);
     const bool ordered = c->cost_order > 0 || (c->cost_order < 0 && n >= kAutoOrderMin);
     const size_t order_b = ordered ? al256((size_t)n * 4) + al256((size_t)supa::order_scratch_words() * 4) : 0;
     const size_t shower_b = hstart_b + part_b + order_b;
-    if (!c->shower.ensure(shower_b, &c->scratch_gen)) return nomem(c, "per-shower scratch", shower_b);
-    char *sh = (char *)c->shower.p;
+    int64_t bucket_per = 0, bucket_blocks = 0;
+    if (L.images)
+        supa::place_bucket_size(c->n_layers, c->g.img_nx, c->g.img_ny, L.place_keys, c->n_cu, &bucket_per,
+                                &bucket_blocks);
+    const size_t hit_chunk_b = (size_t)supa::HIT_CHUNK_WORDS * 4, node_chunk_b = (size_t)supa::NL_FIELDS * supa::LOG_CHUNK * 4;
+    char *sh = nullptr, *spill_p = nullptr, *hlog_p = nullptr, *nlog_p = nullptr;
+    uint2 *bucket_p = nullptr;
+    int32_t bucket_cap = 0;
+    int spill_cap = c->spill_cap;
+    int64_t h_chunks = c->h_chunks, n_chunks = c->n_chunks;
+    if (!fixed) {
+        const size_t spill_b = al256((size_t)L.waves * supa::POOL_FIELDS * c->spill_cap * 4);
+        if (!c->spill.ensure(spill_b, &c->scratch_gen)) return nomem(c, "spill area", spill_b);
+        const size_t hlog_b = L.recs ? al256((size_t)h_chunks * 4) + (size_t)h_chunks * hit_chunk_b : 0;
+        if (L.recs && !c->hlog.ensure(hlog_b, &c->scratch_gen)) return nomem(c, "hit log", hlog_b);
+        const size_t nlog_b = L.tree ? al256((size_t)n_chunks * 4) + (size_t)n_chunks * node_chunk_b : 0;
+        if (L.tree && !c->nlog.ensure(nlog_b, &c->scratch_gen)) return nomem(c, "node log", nlog_b);
+        if (!c->shower.ensure(shower_b, &c->scratch_gen)) return nomem(c, "per-shower scratch", shower_b);
+        if (bucket_per > 0) {
+            const size_t bb = (size_t)bucket_per * bucket_blocks * sizeof(uint2);
+            if (!c->bucket.ensure(bb, &c->scratch_gen)) return nomem(c, "image buckets", bb);
+            bucket_p = (uint2 *)c->bucket.p;
+            bucket_cap = (int32_t)bucket_per;
+        }
+        sh = (char *)c->shower.p;
+        spill_p = (char *)c->spill.p;
+        hlog_p = (char *)c->hlog.p;
+        nlog_p = (char *)c->nlog.p;
+    } else {
+        size_t used = 0;
+        auto take = [&](size_t bytes) -> char * {
+            bytes = al256(bytes);
+            if (bytes > kFixedBytes - used) return nullptr;
+            char *p = fixed + used;
+            used += bytes;
+            return p;
+        };
+        sh = take(shower_b);
+        if (!sh)
+            return fail(c, SUPA_ERR_NOMEM, "a batch of " + std::to_string(n) + " showers needs " +
+                                               std::to_string(shower_b) + " bytes of per-shower scratch; the fixed array holds " +
+                                               std::to_string(kFixedBytes));
+        // a wave takes SLOTS showers at a time: more waves than that would
+        // idle (speed only), and each launched wave owns a spill area
+        L.waves = std::min<int64_t>(L.waves, (n + supa::SLOTS - 1) / supa::SLOTS);
+        const int64_t per_entry = L.waves * supa::POOL_FIELDS * 4;
+        spill_cap = (int)std::min<int64_t>(c->spill_cap, (int64_t)(kFixedBytes / 8) / per_entry);
+        spill_p = take((size_t)per_entry * spill_cap);
+        if (!spill_p) return fail(c, SUPA_ERR_NOMEM, "no room left for the particle spill area in the fixed scratch array");
+        if (bucket_per > 0) {
+            bucket_cap = (int32_t)std::min<int64_t>(bucket_per, (int64_t)(kFixedBytes / 8) / (bucket_blocks * 8));
+            bucket_p = bucket_cap > 0 ? (uint2 *)take((size_t)bucket_cap * bucket_blocks * 8) : nullptr;
+            if (!bucket_p) bucket_cap = 0;
+        }
+        // the logs share what is left, in proportion to what the caller's
+        // capacities suggest they need
+        const size_t rest = kFixedBytes - used;
+        const int64_t hint_h = (outs & SUPA_OUT_HITS) ? out->hit_capacity : 64 * n;
+        const double need_h = L.recs ? (double)hit_chunks_for(std::min<int64_t>(hint_h, (int64_t)1 << 28), L.waves) * hit_chunk_b : 0.0;
+        const double need_n = L.tree ? (double)node_chunks_for(std::min<int64_t>(out->node_capacity, (int64_t)1 << 28), L.waves) * node_chunk_b : 0.0;
+        const size_t room_h = (need_h + need_n) > 0 ? (size_t)((double)rest * need_h / (need_h + need_n)) : 0;
+        const size_t room_n = rest - room_h;
+        h_chunks = L.recs ? (int64_t)((room_h > 512 ? room_h - 512 : 0) / (hit_chunk_b + 4)) : 0;
+        n_chunks = L.tree ? (int64_t)((room_n > 512 ? room_n - 512 : 0) / (node_chunk_b + 4)) : 0;
+        if ((L.recs && h_chunks < 1) || (L.tree && n_chunks < 1))
+            return fail(c, SUPA_ERR_NOMEM, "no room left for the hit and node logs in the fixed scratch array");
+        hlog_p = L.recs ? take(al256((size_t)h_chunks * 4) + (size_t)h_chunks * hit_chunk_b) : nullptr;
+        nlog_p = L.tree ? take(al256((size_t)n_chunks * 4) + (size_t)n_chunks * node_chunk_b) : nullptr;
+        if ((L.recs && !hlog_p) || (L.tree && !nlog_p))
+            return fail(c, SUPA_ERR_NOMEM, "fixed scratch layout does not fit");
+    }
     L.d_hstart = L.recs ? (int64_t *)sh : nullptr;
     L.d_part = (int64_t *)(sh + hstart_b);
     L.d_order = ordered ? (int32_t *)(sh + hstart_b + part_b) : nullptr;
     L.d_ohist = ordered ? (uint32_t *)(sh + hstart_b + part_b + al256((size_t)n * 4)) : nullptr;
-    // the placement kernel's variant (with path ids): sizes and launch must agree
-    L.place_keys = L.hits_out && (outs & SUPA_OUT_KEYS) && out->hit_key != nullptr;
     // images of many slabs: per-workgroup buckets sorting a shower's hits by slab
-    L.d_bucket = nullptr;
-    L.bucket_cap = 0;
-    if (L.images) {
-        int64_t per = 0, blocks = 0;
-        supa::place_bucket_size(c->n_layers, c->g.img_nx, c->g.img_ny, L.place_keys, c->n_cu, &per, &blocks);
-        if (per > 0) {
-            const size_t bb = (size_t)per * blocks * sizeof(uint2);
-            if (!c->bucket.ensure(bb, &c->scratch_gen)) return nomem(c, "image buckets", bb);
-            L.d_bucket = (uint2 *)c->bucket.p;
-            L.bucket_cap = (int32_t)per;
-        }
-    }
+    L.d_bucket = bucket_p;
+    L.bucket_cap = bucket_cap;
+    const size_t hnext_b = al256((size_t)h_chunks * 4), nfill_b = al256((size_t)n_chunks * 4);
 
     supa::Params &P = L.P;
     P = supa::Params{};
@@ -558,14 +649,14 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
     P.outputs = outs;
     P.keys = (outs & SUPA_OUT_KEYS) != 0;
     P.pool_cap = c->pool_cap;
-    P.spill_cap = c->spill_cap;
-    P.spill = (uint32_t *)c->spill.p;
-    P.hnext = L.recs ? (uint32_t *)c->hlog.p : nullptr;
-    P.hlog = L.recs ? (uint32_t *)((char *)c->hlog.p + hnext_b) : nullptr;
-    P.h_chunks = L.recs ? (int32_t)c->h_chunks : 0;
-    P.nfill = L.tree ? (uint32_t *)c->nlog.p : nullptr;
-    P.nlog = L.tree ? (uint32_t *)((char *)c->nlog.p + nfill_b) : nullptr;
-    P.n_chunks = L.tree ? (int32_t)c->n_chunks : 0;
+    P.spill_cap = spill_cap;
+    P.spill = (uint32_t *)spill_p;
+    P.hnext = L.recs ? (uint32_t *)hlog_p : nullptr;
+    P.hlog = L.recs ? (uint32_t *)(hlog_p + hnext_b) : nullptr;
+    P.h_chunks = L.recs ? (int32_t)h_chunks : 0;
+    P.nfill = L.tree ? (uint32_t *)nlog_p : nullptr;
+    P.nlog = L.tree ? (uint32_t *)(nlog_p + nfill_b) : nullptr;
+    P.n_chunks = L.tree ? (int32_t)n_chunks : 0;
     P.ctr = c->d_ctr;
     P.sub = nullptr;
     L.e_unscale = std::ldexp(1.0f, -c->g.energy_frac_bits);
@@ -691,13 +782,17 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
 
 // Outcome of a call from the counters it left (host copy in c->h_ctr):
 // OK, CAPACITY, RANGE, DEVICE, or -1 when scratch ran out (grown here; rerun).
-static int finish(supa_ctx *c, const Plan &L, supa_output *out) {
+static int finish(supa_ctx *c, const Plan &L, supa_output *out, bool fixed = false) {
     const unsigned long long *h = c->h_ctr;
     const unsigned long long flags = h[supa::CTR_FLAGS];
     if (flags & supa::FLAG_RANGE)
         return fail(c, SUPA_ERR_RANGE, "an initial energy is negative, NaN or too large for the fixed-point format");
     const unsigned long long *last = h + supa::CTR_BLOCK * L.nsub;    // running totals
     const int64_t total_hits = (int64_t)last[supa::SUB_HITS], total_nodes = (int64_t)last[supa::SUB_NODES];
+    if ((flags & supa::FLAG_OVERFLOW) && fixed)
+        return fail(c, SUPA_ERR_NOMEM, "the batch needs more scratch (particle spill, hit or node log) than the "
+                                       "fixed array of " + std::to_string(kFixedBytes) + " bytes holds: run it in "
+                                       "smaller calls, or with supa_simulate");
     if (flags & supa::FLAG_OVERFLOW) {
         // grow what ran out: the spill area to the largest pool seen, a log
         // to the totals (exact unless the spill overflowed too)
@@ -740,6 +835,35 @@ static void size_logs(supa_ctx *c, const supa_batch *b, const supa_output *out) 
                                node_chunks_for(std::min<int64_t>(out->node_capacity, (int64_t)1 << 28), waves));
 }
 
+// Runs a prepared call once: launches it, reads back its counters (one
+// synchronisation) and records the kernel times.
+static supa_status run_once(supa_ctx *c, const supa_batch *b, supa_output *out, const Plan &L) {
+    HIP_TRY(c, hipMemcpyAsync(c->d_cold, c->h_cold, L.nsub * sizeof(supa::Cold), hipMemcpyHostToDevice,
+                              c->stream));
+    supa_status st = enqueue(c, b, out, L, c->d_cold, c->stream, c->aux, true);
+    if (st != SUPA_OK) return st;
+    HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_WORDS * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    float t_prop = 0, t_post = 0, t_all = 0, t_place = 0, t_scatter = 0, t = 0;
+    for (int j = 0; j < L.nsub; ++j) {
+        if (hipEventElapsedTime(&t, c->ev_prop[j][0], c->ev_prop[j][1]) == hipSuccess) t_prop += t;
+        if (L.post && hipEventElapsedTime(&t, c->ev_post[j][0], c->ev_post[j][1]) == hipSuccess) t_post += t;
+        if (L.recs && hipEventElapsedTime(&t, c->ev_post[j][0], c->ev_place[j]) == hipSuccess) t_place += t;
+        if (L.tree && hipEventElapsedTime(&t, c->ev_place[j], c->ev_post[j][1]) == hipSuccess) t_scatter += t;
+    }
+    (void)hipEventElapsedTime(&t_all, c->ev_begin, c->ev_end);
+    (void)hipGetLastError();
+    c->timing[0] = t_prop;
+    c->timing[1] = t_post;
+    c->timing[2] = t_all;
+    c->timing[3] = t_place;
+    c->timing[4] = t_scatter;
+    c->last_sub_batches = L.nsub;
+    return SUPA_OK;
+}
+
 extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t seed,
                                      supa_output *out) {
     supa_status st = check_call(c, b, out);
@@ -750,33 +874,28 @@ extern "C" supa_status supa_simulate(supa_ctx *c, const supa_batch *b, uint64_t 
         Plan L{};
         st = prepare(c, b, seed, out, L, 0);
         if (st != SUPA_OK) return st;
-        HIP_TRY(c, hipMemcpyAsync(c->d_cold, c->h_cold, L.nsub * sizeof(supa::Cold), hipMemcpyHostToDevice,
-                                  c->stream));
-        st = enqueue(c, b, out, L, c->d_cold, c->stream, c->aux, true);
+        st = run_once(c, b, out, L);
         if (st != SUPA_OK) return st;
-        HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_WORDS * sizeof(unsigned long long),
-                                  hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
-        float t_prop = 0, t_post = 0, t_all = 0, t_place = 0, t_scatter = 0, t = 0;
-        for (int j = 0; j < L.nsub; ++j) {
-            if (hipEventElapsedTime(&t, c->ev_prop[j][0], c->ev_prop[j][1]) == hipSuccess) t_prop += t;
-            if (L.post && hipEventElapsedTime(&t, c->ev_post[j][0], c->ev_post[j][1]) == hipSuccess) t_post += t;
-            if (L.recs && hipEventElapsedTime(&t, c->ev_post[j][0], c->ev_place[j]) == hipSuccess) t_place += t;
-            if (L.tree && hipEventElapsedTime(&t, c->ev_place[j], c->ev_post[j][1]) == hipSuccess) t_scatter += t;
-        }
-        (void)hipEventElapsedTime(&t_all, c->ev_begin, c->ev_end);
-        (void)hipGetLastError();
-        c->timing[0] = t_prop;
-        c->timing[1] = t_post;
-        c->timing[2] = t_all;
-        c->timing[3] = t_place;
-        c->timing[4] = t_scatter;
-        c->last_sub_batches = L.nsub;
         const int r = finish(c, L, out);
         if (r >= 0) return (supa_status)r;
     }
     return fail(c, SUPA_ERR_NOMEM, "scratch sizes did not converge");
+}
+
+// supa_simulate with the library's scratch carved out of this device's fixed
+// array: no allocation, no growth, one attempt.
+extern "C" supa_status supa_simulate_noalloc(supa_ctx *c, const supa_batch *b, uint64_t seed,
+                                             supa_output *out) {
+    supa_status st = check_call(c, b, out);
+    if (st != SUPA_OK || b->n == 0) return st;
+    if (!c->fixed) return fail(c, SUPA_ERR_STATE, "the fixed scratch array of this device is not resolved");
+    HIP_TRY(c, hipSetDevice(c->device));
+    Plan L{};
+    st = prepare(c, b, seed, out, L, 0, c->fixed);
+    if (st != SUPA_OK) return st;
+    st = run_once(c, b, out, L);
+    if (st != SUPA_OK) return st;
+    return (supa_status)finish(c, L, out, true);
 }
 
 // A captured call: the launch sequence of one supa_simulate (one sub-batch,

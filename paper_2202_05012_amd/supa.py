@@ -73,7 +73,7 @@ class Output(C.Structure):
 
 
 EXPORTS = ["supa_abi_version", "supa_validate_geometry", "supa_validate_call", "supa_init_geometry", "supa_destroy",
-           "supa_simulate", "supa_set_launch", "supa_set_schedule", "supa_autotune",
+           "supa_simulate", "supa_simulate_noalloc", "supa_set_launch", "supa_set_schedule", "supa_autotune",
            "supa_graph_create", "supa_graph_launch", "supa_graph_check", "supa_graph_destroy", "supa_last_timing", "supa_last_kernel_times", "supa_philox",
            "supa_last_error"]
 
@@ -100,6 +100,8 @@ def load():
         L.supa_destroy.argtypes = [C.c_void_p]
         L.supa_simulate.restype = C.c_int
         L.supa_simulate.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_uint64, C.POINTER(Output)]
+        L.supa_simulate_noalloc.restype = C.c_int
+        L.supa_simulate_noalloc.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_uint64, C.POINTER(Output)]
         L.supa_set_launch.restype = C.c_int
         L.supa_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
         L.supa_autotune.restype = C.c_int
@@ -355,6 +357,18 @@ class Simulator:
         (OK or CAPACITY) and fills out['total_*']."""
         b, o = self._marshal(e0, polar, azimuth, out, x0, y0, shower_id_base)
         st = self.lib.supa_simulate(self.ctx, C.byref(b), seed & 0xFFFFFFFFFFFFFFFF, C.byref(o))
+        self._totals(out, o)
+        if st not in (0, 3):
+            self._check(st)
+        return st
+
+    def run_noalloc(self, e0, polar, azimuth, seed: int, out: dict, x0=None, y0=None,
+                    shower_id_base: int = 0) -> int:
+        """supa_simulate_noalloc into preallocated outputs (the library's
+        scratch from its fixed per-GPU array); returns the status (OK or
+        CAPACITY) and fills out['total_*'], raises on other errors."""
+        b, o = self._marshal(e0, polar, azimuth, out, x0, y0, shower_id_base)
+        st = self.lib.supa_simulate_noalloc(self.ctx, C.byref(b), seed & 0xFFFFFFFFFFFFFFFF, C.byref(o))
         self._totals(out, o)
         if st not in (0, 3):
             self._check(st)
