@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0,
                     help="showers per call for the workload whose outputs do not fit one call "
                          "(0: 10000)")
+    ap.add_argument("--serial-calls", action="store_true",
+                    help="run that workload's calls one supa_simulate at a time instead of "
+                         "supa_simulate_batches (propagation of call j+1 beside the placement of j)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick launch settings by measurement before timing")
     ap.add_argument("--kinematics", default="3d", choices=("3d", "literal"),
@@ -462,9 +465,12 @@ def chunk_slices(n: int, chunk: int):
 def bench_batched(args, w):
     """A workload whose outputs do not fit one call (1M showers of 50 layers
     of 256x256 images = 13 TB): one step runs every shower in calls of
-    --chunk showers, each into the same outputs sized for one call (a
-    consumer would copy or reduce them between calls).  Timed: the calls of
-    K steps, back to back, after W untimed steps."""
+    --chunk showers.  By default the step is one supa_simulate_batches call
+    over all of them (the propagation of call j+1 runs beside the placement
+    of call j); the calls share one set of hit, node and image arrays sized
+    for one call (a consumer would copy or reduce them between calls), each
+    call having its own ledger, counts and offsets.  Timed: K steps after W
+    untimed ones."""
     import torch
     from paper_2202_05012_amd import prof_summary, supa, workloads
 
@@ -479,19 +485,28 @@ def bench_batched(args, w):
     sim = supa.Simulator(geom, outputs, waves_per_cu=args.waves_per_cu, frontier_cap=args.lds_cap,
                          sub_batches=args.sub_batches, cost_order=args.cost_order)
 
-    def call(out, s0, m):
-        sl = slice(s0, s0 + m)
-        return sim.run(te0[sl], tpol[sl], taz[sl], w.seed, out, shower_id_base=s0)
+    def per_call_outputs(shared):
+        """Each call: ledger, counts and offsets of its own; the hit, node and
+        image arrays of `shared`."""
+        outs = []
+        for _, m in calls:
+            o = {k: v for k, v in shared.items()
+                 if k not in ("ledger", "counts", "hit_offsets", "node_offsets", "shower_capacity")}
+            o.update(ledger=torch.empty((m, 4), dtype=torch.int64, device=dev),
+                     counts=torch.empty((m, 6), dtype=torch.int32, device=dev),
+                     hit_offsets=torch.empty(m, dtype=torch.int64, device=dev),
+                     node_offsets=torch.empty(m, dtype=torch.int64, device=dev), shower_capacity=m)
+            outs.append(o)
+        return outs
 
     # capacities: the largest call's totals (zero-capacity outputs: each call
     # reports its totals; this also grows the library's scratch)
-    probe = sim.allocate(chunk, 0, 0)
-    need_h = need_n = 0
-    for s0, m in calls:
-        call(probe, s0, m)
-        need_h, need_n = max(need_h, probe["total_hits"]), max(need_n, probe["total_nodes"])
+    probe = per_call_outputs(sim.allocate(chunk, 0, 0))
+    sim.run_batches(te0, tpol, taz, w.seed, calls, probe)
+    need_h = max(o["total_hits"] for o in probe)
+    need_n = max(o["total_nodes"] for o in probe)
     del probe
-    out = sim.allocate(chunk, int(need_h) + 1, int(need_n) + 1)
+    outs = per_call_outputs(sim.allocate(chunk, int(need_h) + 1, int(need_n) + 1))
     print(f"sized: {len(calls)} calls of {chunk} showers, <= {need_h} hits and {need_n} nodes per call",
           file=sys.stderr, flush=True)
     if args.copy_calibration:
@@ -499,34 +514,43 @@ def bench_batched(args, w):
         torch.empty_like(a).copy_(a)
         torch.cuda.synchronize()
         del a
+
+    def step():
+        """One pass over the workload; returns the kernel times (ms) and the
+        calls' totals."""
+        tot = np.zeros(4, np.int64)            # nodes, hits, steps, splits
+        kt = np.zeros(3)
+        if args.serial_calls:
+            for (s0, m), o in zip(calls, outs):
+                sl = slice(s0, s0 + m)
+                assert sim.run(te0[sl], tpol[sl], taz[sl], w.seed, o, shower_id_base=s0) == 0
+                tm = sim.timing()
+                kt += (tm[0], tm[3], tm[4])
+        else:
+            assert sim.run_batches(te0, tpol, taz, w.seed, calls, outs) == 0
+            tm = sim.timing()
+            kt += (tm[0], tm[3], tm[4])
+        for (s0, m), o in zip(calls, outs):
+            # a split adds two nodes to a shower's primary one
+            tot += (o["total_nodes"], o["total_hits"], o["total_steps"], (o["total_nodes"] - m) // 2)
+        return kt, tot
+
     for _ in range(args.warmup):
-        for s0, m in calls:
-            assert call(out, s0, m) == 0
+        step()
     torch.cuda.synchronize()
     print(f"warm-up: {args.warmup} steps done", file=sys.stderr, flush=True)
-    prop_ms = place_ms = scatter_ms = 0.0
-    nodes_total = hits_total = steps_total = splits_total = 0
+    kt = np.zeros(3)
+    tot = None
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        for s0, m in calls:
-            st = call(out, s0, m)
-            assert st == 0, f"call at shower {s0} returned {st}"
-            tm = sim.timing()
-            prop_ms += tm[0]
-            place_ms += tm[3]
-            scatter_ms += tm[4]
-            # totals the call returned (host values); a split adds two nodes
-            # to a shower's primary one
-            nodes_total += out["total_nodes"]
-            hits_total += out["total_hits"]
-            steps_total += out["total_steps"]
-            splits_total += (out["total_nodes"] - m) // 2
+        k, tot = step()
+        kt += k
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     print(f"timed: {args.steps} steps in {t1 - t0:.2f} s", file=sys.stderr, flush=True)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    nodes_total, hits_total, steps_total, splits_total = (v // args.steps for v in
-                                                          (nodes_total, hits_total, steps_total, splits_total))
+    nodes_total, hits_total, steps_total, splits_total = (int(v) for v in tot)
+    prop_ms, place_ms, scatter_ms = kt
     launches = args.steps * len(calls)
     k_prop, k_place, k_scatter = prop_ms / launches, place_ms / launches, scatter_ms / launches
     draws = steps_total - hits_total          # p_stop = 0 here: every hit is a cut
@@ -562,7 +586,8 @@ def bench_batched(args, w):
         "data": "synthetic",
         "config": {"workload": w.name, "showers": w.n, "planes": w.n_planes, "outputs": "hits+images+tree",
                    "image": f"{L}x{geom['img_ny']}x{geom['img_nx']}",
-                   "showers_per_call": chunk, "calls_per_step": len(calls)},
+                   "showers_per_call": chunk, "calls_per_step": len(calls),
+                   "calls": "one at a time" if args.serial_calls else "pipelined (supa_simulate_batches)"},
         "particle_steps_per_s": round(steps_total / (ms_per_step / 1e3), 1),
         "particle_steps": steps_total, "hits": hits_total, "nodes": nodes_total,
         "roofline": kern[0][1], "roofline_other": kern[1][1], "roofline_third": kern[2][1],

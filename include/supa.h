@@ -233,6 +233,24 @@ supa_status supa_simulate(supa_ctx *ctx, const supa_batch *b, uint64_t seed,
                           supa_output *out);
 
 /*
+ * k calls in one (a workload whose outputs do not fit one call, run slice
+ * by slice): the same as supa_simulate(ctx, &b[j], seed, &out[j]) for j = 0
+ * .. k-1, with one synchronisation at the end, and the propagation of call
+ * j+1 running on the GPU while the hits, images and tree of call j are
+ * placed (the library keeps two sets of logs for the two calls in flight).
+ * Sharing: the hit, node and image arrays of different calls may be the
+ * same memory (placements run in call order, so a later call overwrites an
+ * earlier one's), as may hit_offsets and node_offsets; the ledger and counts
+ * rows of consecutive calls must not overlap (refused with INVALID_ARG).
+ * Returns OK, or the first RANGE / DEVICE error, else CAPACITY if any call's
+ * records exceeded its capacities (out[j].total_* are set for every call);
+ * scratch that runs out grows and every call is rerun (bit-identical).
+ * supa_last_kernel_times sums the kernel times over the calls.
+ */
+supa_status supa_simulate_batches(supa_ctx *ctx, int32_t k, const supa_batch *b, uint64_t seed,
+                                  supa_output *out);
+
+/*
  * For callers that cannot allocate device memory: code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
  * arguments, outputs, numerics and errors as supa_simulate, but the library's

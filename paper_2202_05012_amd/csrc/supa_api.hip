@@ -123,6 +123,18 @@ struct supa_ctx {
     int cost_order = -1;                 // hand out expensive showers first: 1 on, 0 off, -1 auto
     int last_sub_batches = 0;
     DevBuf spill, hlog, nlog, shower, bucket;
+    // second set of the buffers that the propagation of one call writes while
+    // the placement of the previous call reads them (supa_simulate_batches)
+    DevBuf hlog2, nlog2, hstart2;
+    DevBuf snap;                         // per-call copies of the counters (batches)
+    unsigned long long *h_snap = nullptr;    // pinned host copy of snap
+    size_t h_snap_bytes = 0;
+    supa::Cold *h_calls = nullptr;       // pinned per-call input/output blocks (batches)
+    size_t h_calls_n = 0;
+    DevBuf d_calls;
+    std::vector<hipEvent_t> call_ev;     // 5 per call: propagation start/end, scan done,
+                                         // placement end, node scatter end (batches)
+    hipEvent_t ev_set_free[2] = {};      // second stream done with a set of buffers
     uint64_t scratch_gen = 0;            // advanced by every scratch reallocation
     char *fixed = nullptr;               // this device's fixed scratch array (device address)
     // the placement of a sub-batch runs on a second stream, overlapping the
@@ -328,7 +340,7 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
               hipMemcpy(c->d_layer_planes, lp.data(), lp.size() * sizeof(int32_t),
                         hipMemcpyHostToDevice) == hipSuccess &&
               hipMalloc(&c->d_c2, THR_ENTRIES * sizeof(uint64_t)) == hipSuccess &&
-              hipMalloc(&c->d_ctr, supa::CTR_WORDS * sizeof(unsigned long long)) == hipSuccess &&
+              hipMalloc(&c->d_ctr, 2 * supa::CTR_WORDS * sizeof(unsigned long long)) == hipSuccess &&
               hipHostMalloc(&c->h_ctr, supa::CTR_WORDS * sizeof(unsigned long long), 0) == hipSuccess &&
               hipMalloc(&c->d_cold, supa::MAX_SUB * sizeof(supa::Cold)) == hipSuccess &&
               hipHostMalloc(&c->h_cold, supa::MAX_SUB * sizeof(supa::Cold), 0) == hipSuccess &&
@@ -343,6 +355,7 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
         for (int q = 0; q < 2 && ok; ++q)
             ok = hipEventCreate(&c->ev_prop[b][q]) == hipSuccess && hipEventCreate(&c->ev_post[b][q]) == hipSuccess;
     for (int b = 0; b < supa::MAX_SUB && ok; ++b) ok = hipEventCreate(&c->ev_place[b]) == hipSuccess;
+    for (int q = 0; q < 2 && ok; ++q) ok = hipEventCreate(&c->ev_set_free[q]) == hipSuccess;
     if (!ok) {
         (void)hipGetLastError();
         supa_destroy(c);
@@ -359,7 +372,15 @@ extern "C" supa_status supa_destroy(supa_ctx *c) {
     // the default stream, also synchronised)
     (void)hipStreamSynchronize(c->stream);
     if (c->aux) (void)hipStreamSynchronize(c->aux);
-    for (DevBuf *d : {&c->spill, &c->hlog, &c->nlog, &c->shower, &c->bucket}) d->release();
+    for (DevBuf *d : {&c->spill, &c->hlog, &c->nlog, &c->shower, &c->bucket, &c->hlog2, &c->nlog2, &c->hstart2,
+                      &c->snap, &c->d_calls})
+        d->release();
+    if (c->h_snap) (void)hipHostFree(c->h_snap);
+    if (c->h_calls) (void)hipHostFree(c->h_calls);
+    for (hipEvent_t e : c->call_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (int q = 0; q < 2; ++q)
+        if (c->ev_set_free[q]) (void)hipEventDestroy(c->ev_set_free[q]);
     if (c->d_layer) (void)hipFree(c->d_layer);
     if (c->d_layer_plane_start) (void)hipFree(c->d_layer_plane_start);
     if (c->d_layer_planes) (void)hipFree(c->d_layer_planes);
@@ -511,6 +532,7 @@ struct Plan {
     bool place_keys;                 // placement writes path ids
     uint2 *d_bucket;                 // placement's per-workgroup hit buckets, or null
     int32_t bucket_cap;
+    unsigned long long *ctr;         // the call's counters (set 0 or 1)
     int64_t off(int j) const { return n * j / nsub; }
 };
 
@@ -521,7 +543,7 @@ static constexpr size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 // of the fixed array at `fixed` (kFixedBytes), nothing is allocated, and the
 // pieces are sized to fit it (a batch that needs more fails, see finish).
 static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa_output *out, Plan &L,
-                           int force_nsub, char *fixed = nullptr) {
+                           int force_nsub, char *fixed = nullptr, int set = 0) {
     const uint32_t outs = c->g.outputs;
     const int64_t n = b->n;
     L.n = n;
@@ -561,11 +583,16 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
     if (!fixed) {
         const size_t spill_b = al256((size_t)L.waves * supa::POOL_FIELDS * c->spill_cap * 4);
         if (!c->spill.ensure(spill_b, &c->scratch_gen)) return nomem(c, "spill area", spill_b);
+        // set 1 (the second call in flight of supa_simulate_batches) has logs
+        // and log starts of its own; the rest is used by one call at a time
+        DevBuf &hl = set ? c->hlog2 : c->hlog, &nl = set ? c->nlog2 : c->nlog;
         const size_t hlog_b = L.recs ? al256((size_t)h_chunks * 4) + (size_t)h_chunks * hit_chunk_b : 0;
-        if (L.recs && !c->hlog.ensure(hlog_b, &c->scratch_gen)) return nomem(c, "hit log", hlog_b);
+        if (L.recs && !hl.ensure(hlog_b, &c->scratch_gen)) return nomem(c, "hit log", hlog_b);
         const size_t nlog_b = L.tree ? al256((size_t)n_chunks * 4) + (size_t)n_chunks * node_chunk_b : 0;
-        if (L.tree && !c->nlog.ensure(nlog_b, &c->scratch_gen)) return nomem(c, "node log", nlog_b);
+        if (L.tree && !nl.ensure(nlog_b, &c->scratch_gen)) return nomem(c, "node log", nlog_b);
         if (!c->shower.ensure(shower_b, &c->scratch_gen)) return nomem(c, "per-shower scratch", shower_b);
+        if (set && hstart_b && !c->hstart2.ensure(hstart_b, &c->scratch_gen))
+            return nomem(c, "per-shower log starts", hstart_b);
         if (bucket_per > 0) {
             const size_t bb = (size_t)bucket_per * bucket_blocks * sizeof(uint2);
             if (!c->bucket.ensure(bb, &c->scratch_gen)) return nomem(c, "image buckets", bb);
@@ -574,8 +601,8 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
         }
         sh = (char *)c->shower.p;
         spill_p = (char *)c->spill.p;
-        hlog_p = (char *)c->hlog.p;
-        nlog_p = (char *)c->nlog.p;
+        hlog_p = (char *)hl.p;
+        nlog_p = (char *)nl.p;
     } else {
         size_t used = 0;
         auto take = [&](size_t bytes) -> char * {
@@ -619,7 +646,7 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
         if ((L.recs && !hlog_p) || (L.tree && !nlog_p))
             return fail(c, SUPA_ERR_NOMEM, "fixed scratch layout does not fit");
     }
-    L.d_hstart = L.recs ? (int64_t *)sh : nullptr;
+    L.d_hstart = L.recs ? (int64_t *)(set ? (char *)c->hstart2.p : sh) : nullptr;
     L.d_part = (int64_t *)(sh + hstart_b);
     L.d_order = ordered ? (int32_t *)(sh + hstart_b + part_b) : nullptr;
     L.d_ohist = ordered ? (uint32_t *)(sh + hstart_b + part_b + al256((size_t)n * 4)) : nullptr;
@@ -657,7 +684,8 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
     P.nfill = L.tree ? (uint32_t *)nlog_p : nullptr;
     P.nlog = L.tree ? (uint32_t *)(nlog_p + nfill_b) : nullptr;
     P.n_chunks = L.tree ? (int32_t)n_chunks : 0;
-    P.ctr = c->d_ctr;
+    L.ctr = c->d_ctr + (set ? supa::CTR_WORDS : 0);
+    P.ctr = L.ctr;
     P.sub = nullptr;
     L.e_unscale = std::ldexp(1.0f, -c->g.energy_frac_bits);
 
@@ -684,12 +712,16 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
 // the propagation (main stream) and the scan, placement and node scatter
 // (second stream, after the propagation of the same sub-batch).  d_cold
 // holds the per-sub-batch blocks.  With timed, events bracket the parts.
+// ev_prop[j], ev_post[j], ev_place[j]: the events of sub-batch j (the
+// context's, or a call's own in supa_simulate_batches).  join: the main
+// stream waits for the second stream at the end.
 static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, const Plan &L,
-                           supa::Cold *d_cold, hipStream_t s_main, hipStream_t s_aux, bool timed) {
-    auto sub_ctr = [&](int j) { return c->d_ctr + supa::CTR_BLOCK * (1 + j); };
+                           supa::Cold *d_cold, hipStream_t s_main, hipStream_t s_aux, bool timed,
+                           hipEvent_t (*ev_prop)[2], hipEvent_t (*ev_post)[2], hipEvent_t *ev_place,
+                           bool join = true) {
+    auto sub_ctr = [&](int j) { return L.ctr + supa::CTR_BLOCK * (1 + j); };
     const supa::Params &P = L.P;
-    if (timed) HIP_TRY(c, hipEventRecord(c->ev_begin, s_main));
-    HIP_TRY(c, supa::launch_zero_counters(c->d_ctr, s_main));
+    HIP_TRY(c, supa::launch_zero_counters(L.ctr, s_main));
     for (int j = 0; j < L.nsub; ++j) {
         const int64_t o = L.off(j), nj = L.off(j + 1) - o;
         supa::Params Pj = P;
@@ -700,13 +732,13 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
         if (L.d_order)
             HIP_TRY(c, supa::launch_cost_order(b->e0 + o, (int)nj, P.e_scale, L.d_ohist, L.d_order + o,
                                                c->n_cu, s_main));
-        if (timed) HIP_TRY(c, hipEventRecord(c->ev_prop[j][0], s_main));
+        if (timed) HIP_TRY(c, hipEventRecord(ev_prop[j][0], s_main));
         HIP_TRY(c, supa::launch_propagate(Pj, c->g.kinematics == SUPA_KIN_LITERAL, c->g.n_regions >= 2, (int)L.waves, s_main));
-        if (L.tree) HIP_TRY(c, supa::launch_note_chunks(c->d_ctr, sub_ctr(j), s_main));
+        if (L.tree) HIP_TRY(c, supa::launch_note_chunks(L.ctr, sub_ctr(j), s_main));
         // the second stream waits on this event (none inside a capture, where
         // both are one stream)
         const bool two = s_aux != s_main;
-        if (timed || two) HIP_TRY(c, hipEventRecord(c->ev_prop[j][1], s_main));
+        if (timed || two) HIP_TRY(c, hipEventRecord(ev_prop[j][1], s_main));
         if (!L.post) continue;
 
         supa::ScanParams SP{};
@@ -729,7 +761,7 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
         H.sx = L.images ? (float)(c->g.img_nx / (c->g.img_x1 - c->g.img_x0)) : 0.0f;
         H.sy = L.images ? (float)(c->g.img_ny / (c->g.img_y1 - c->g.img_y0)) : 0.0f;
         H.e_unscale = L.e_unscale;
-        H.ctr = c->d_ctr;
+        H.ctr = L.ctr;
         H.sub = sub_ctr(j);
         H.counts = SP.counts;
         H.hstart = L.d_hstart ? L.d_hstart + o : nullptr;
@@ -752,7 +784,7 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
         Q.z_first = P.z_first;
         Q.dz = P.dz;
         Q.e_unscale = L.e_unscale;
-        Q.ctr = c->d_ctr;
+        Q.ctr = L.ctr;
         Q.sub = sub_ctr(j);
         Q.prev = SP.prev;
         Q.nlog = P.nlog;
@@ -768,22 +800,23 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
         Q.ne = out->node_e;
         Q.nk = (L.tree && P.keys) ? out->node_key : nullptr;
 
-        if (two) HIP_TRY(c, hipStreamWaitEvent(s_aux, c->ev_prop[j][1], 0));
+        if (two) HIP_TRY(c, hipStreamWaitEvent(s_aux, ev_prop[j][1], 0));
         HIP_TRY(c, supa::launch_scan(SP, s_aux));
-        if (timed) HIP_TRY(c, hipEventRecord(c->ev_post[j][0], s_aux));
+        if (timed) HIP_TRY(c, hipEventRecord(ev_post[j][0], s_aux));
         if (L.recs) HIP_TRY(c, supa::launch_place(H, c->n_cu, s_aux));
-        if (timed) HIP_TRY(c, hipEventRecord(c->ev_place[j], s_aux));
+        if (timed) HIP_TRY(c, hipEventRecord(ev_place[j], s_aux));
         if (L.tree) HIP_TRY(c, supa::launch_scatter_nodes(Q, (int32_t)nj, c->n_cu, s_aux));
-        if (timed || two) HIP_TRY(c, hipEventRecord(c->ev_post[j][1], s_aux));
+        if (timed || two) HIP_TRY(c, hipEventRecord(ev_post[j][1], s_aux));
     }
-    if (L.post && s_aux != s_main) HIP_TRY(c, hipStreamWaitEvent(s_main, c->ev_post[L.nsub - 1][1], 0));
+    if (join && L.post && s_aux != s_main) HIP_TRY(c, hipStreamWaitEvent(s_main, ev_post[L.nsub - 1][1], 0));
     return SUPA_OK;
 }
 
 // Outcome of a call from the counters it left (host copy in c->h_ctr):
 // OK, CAPACITY, RANGE, DEVICE, or -1 when scratch ran out (grown here; rerun).
-static int finish(supa_ctx *c, const Plan &L, supa_output *out, bool fixed = false) {
-    const unsigned long long *h = c->h_ctr;
+static int finish(supa_ctx *c, const Plan &L, supa_output *out, bool fixed = false,
+                  const unsigned long long *h = nullptr) {
+    if (!h) h = c->h_ctr;
     const unsigned long long flags = h[supa::CTR_FLAGS];
     if (flags & supa::FLAG_RANGE)
         return fail(c, SUPA_ERR_RANGE, "an initial energy is negative, NaN or too large for the fixed-point format");
@@ -840,9 +873,10 @@ static void size_logs(supa_ctx *c, const supa_batch *b, const supa_output *out) 
 static supa_status run_once(supa_ctx *c, const supa_batch *b, supa_output *out, const Plan &L) {
     HIP_TRY(c, hipMemcpyAsync(c->d_cold, c->h_cold, L.nsub * sizeof(supa::Cold), hipMemcpyHostToDevice,
                               c->stream));
-    supa_status st = enqueue(c, b, out, L, c->d_cold, c->stream, c->aux, true);
+    HIP_TRY(c, hipEventRecord(c->ev_begin, c->stream));
+    supa_status st = enqueue(c, b, out, L, c->d_cold, c->stream, c->aux, true, c->ev_prop, c->ev_post, c->ev_place);
     if (st != SUPA_OK) return st;
-    HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_WORDS * sizeof(unsigned long long),
+    HIP_TRY(c, hipMemcpyAsync(c->h_ctr, L.ctr, supa::CTR_WORDS * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -898,6 +932,153 @@ extern "C" supa_status supa_simulate_noalloc(supa_ctx *c, const supa_batch *b, u
     return (supa_status)finish(c, L, out, true);
 }
 
+// ---------------------------------------------------------------------------
+// Several calls in one: the propagation of call j+1 (main stream) overlaps
+// the scan, placement and node scatter of call j (second stream).  The logs,
+// log starts and counters that a propagation writes and the next steps read
+// come in two sets, used by alternate calls; a call reuses a set once the
+// second stream is done with the call before the previous one.  Each call's
+// counters are copied aside when its second-stream work ends and read back
+// together with one synchronisation at the end.
+// ---------------------------------------------------------------------------
+static bool ensure_pinned(void **p, size_t *have, size_t need) {
+    if (need <= *have) return true;
+    if (*p) (void)hipHostFree(*p);
+    *p = nullptr;
+    *have = 0;
+    if (hipHostMalloc(p, need, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    *have = need;
+    return true;
+}
+
+extern "C" supa_status supa_simulate_batches(supa_ctx *c, int32_t k, const supa_batch *b, uint64_t seed,
+                                             supa_output *out) {
+    if (!c) return SUPA_ERR_STATE;
+    if (k < 0 || (k > 0 && (!b || !out))) return fail(c, SUPA_ERR_INVALID_ARG, "bad call list");
+    for (int32_t j = 0; j < k; ++j) {
+        const supa_status st = check_call(c, &b[j], &out[j]);
+        if (st != SUPA_OK) {
+            c->err = "call " + std::to_string(j) + ": " + c->err;
+            return st;
+        }
+    }
+    if (k == 0) return SUPA_OK;
+    HIP_TRY(c, hipSetDevice(c->device));
+    for (int32_t j = 0; j < k; ++j) size_logs(c, &b[j], &out[j]);
+    // pinned per-call staging, device per-call blocks, counters and events
+    size_t calls_n = c->h_calls_n;
+    if (!ensure_pinned((void **)&c->h_calls, &calls_n, (size_t)k * sizeof(supa::Cold)))
+        return nomem(c, "pinned per-call blocks", (size_t)k * sizeof(supa::Cold));
+    c->h_calls_n = calls_n;
+    const size_t snap_b = (size_t)k * supa::CTR_WORDS * sizeof(unsigned long long);
+    if (!ensure_pinned((void **)&c->h_snap, &c->h_snap_bytes, snap_b)) return nomem(c, "pinned counters", snap_b);
+    if (!c->snap.ensure(snap_b, &c->scratch_gen)) return nomem(c, "per-call counters", snap_b);
+    if (!c->d_calls.ensure((size_t)k * sizeof(supa::Cold), &c->scratch_gen))
+        return nomem(c, "per-call blocks", (size_t)k * sizeof(supa::Cold));
+    while (c->call_ev.size() < (size_t)k * 5) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(c, hipEventCreate(&e));
+        c->call_ev.push_back(e);
+    }
+    // consecutive calls are in flight together: the per-shower rows that one
+    // call's propagation writes (ledger, counts) must not be read by the
+    // other's placement
+    for (int32_t j = 0; j + 1 < k; ++j) {
+        auto span = [](const void *p, int64_t bytes) { return std::make_pair((uintptr_t)p, (uintptr_t)p + bytes); };
+        const auto la = span(out[j].ledger, b[j].n * 32), lb = span(out[j + 1].ledger, b[j + 1].n * 32);
+        const auto ca = span(out[j].counts, b[j].n * 24), cb = span(out[j + 1].counts, b[j + 1].n * 24);
+        auto meet = [](std::pair<uintptr_t, uintptr_t> x, std::pair<uintptr_t, uintptr_t> y) {
+            return x.first < x.second && y.first < y.second && x.first < y.second && y.first < x.second;
+        };
+        if (meet(la, lb) || meet(ca, cb) || meet(la, cb) || meet(ca, lb))
+            return fail(c, SUPA_ERR_INVALID_ARG, "calls " + std::to_string(j) + " and " + std::to_string(j + 1) +
+                                                     " share ledger or counts rows (consecutive calls run at once)");
+    }
+    std::vector<Plan> plans((size_t)k);
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        // sizes first (buffers may grow: nothing is in flight), then the
+        // plans, whose pointers no later preparation moves
+        supa_status st = SUPA_OK;
+        for (int pass = 0; pass < 2 && st == SUPA_OK; ++pass)
+            for (int32_t j = 0; j < k && st == SUPA_OK; ++j) {
+                st = prepare(c, &b[j], seed, &out[j], plans[j], 1, nullptr, j & 1);
+                if (pass == 1) c->h_calls[j] = c->h_cold[0];
+            }
+        if (st != SUPA_OK) return st;
+        supa::Cold *d_calls = (supa::Cold *)c->d_calls.p;
+        HIP_TRY(c, hipEventRecord(c->ev_begin, c->stream));
+        HIP_TRY(c, hipMemcpyAsync(d_calls, c->h_calls, (size_t)k * sizeof(supa::Cold), hipMemcpyHostToDevice,
+                                  c->stream));
+        unsigned long long *snap = (unsigned long long *)c->snap.p;
+        for (int32_t j = 0; j < k; ++j) {
+            const int q = j & 1;
+            // the set's buffers are free once the second stream is done with call j - 2
+            if (j >= 2) HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_set_free[q], 0));
+            hipEvent_t *e = &c->call_ev[(size_t)j * 5];
+            hipEvent_t ev_prop[1][2] = {{e[0], e[1]}}, ev_post[1][2] = {{e[2], e[4]}}, ev_place[1] = {e[3]};
+            st = enqueue(c, &b[j], &out[j], plans[j], d_calls + j, c->stream, c->aux, true, ev_prop, ev_post,
+                         ev_place, false);
+            if (st != SUPA_OK) return st;
+            // counters-only calls have no second-stream part: order after the propagation
+            if (!plans[j].post) HIP_TRY(c, hipStreamWaitEvent(c->aux, e[1], 0));
+            HIP_TRY(c, hipMemcpyAsync(snap + (size_t)j * supa::CTR_WORDS, plans[j].ctr,
+                                      supa::CTR_WORDS * sizeof(unsigned long long), hipMemcpyDeviceToDevice,
+                                      c->aux));
+            HIP_TRY(c, hipEventRecord(c->ev_set_free[q], c->aux));
+        }
+        HIP_TRY(c, hipEventRecord(c->ev_joined, c->aux));
+        HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_joined, 0));
+        HIP_TRY(c, hipMemcpyAsync(c->h_snap, snap, snap_b, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        float t_prop = 0, t_post = 0, t_all = 0, t_place = 0, t_scatter = 0, t = 0;
+        for (int32_t j = 0; j < k; ++j) {
+            const hipEvent_t *e = &c->call_ev[(size_t)j * 5];
+            if (hipEventElapsedTime(&t, e[0], e[1]) == hipSuccess) t_prop += t;
+            if (plans[j].post && hipEventElapsedTime(&t, e[2], e[4]) == hipSuccess) t_post += t;
+            if (plans[j].recs && hipEventElapsedTime(&t, e[2], e[3]) == hipSuccess) t_place += t;
+            if (plans[j].tree && hipEventElapsedTime(&t, e[3], e[4]) == hipSuccess) t_scatter += t;
+        }
+        (void)hipEventElapsedTime(&t_all, c->ev_begin, c->ev_end);
+        (void)hipGetLastError();
+        c->timing[0] = t_prop;
+        c->timing[1] = t_post;
+        c->timing[2] = t_all;
+        c->timing[3] = t_place;
+        c->timing[4] = t_scatter;
+        c->last_sub_batches = 1;
+        // outcome: a range error anywhere wins, then a capacity error; an
+        // overflow of library scratch grows it and reruns every call
+        bool rerun = false, cap = false;
+        int first_cap = -1;
+        for (int32_t j = 0; j < k; ++j) {
+            const int r = finish(c, plans[j], &out[j], false, c->h_snap + (size_t)j * supa::CTR_WORDS);
+            if (r < 0) {
+                rerun = true;
+            } else if (r == SUPA_ERR_RANGE || r == SUPA_ERR_DEVICE) {
+                c->err = "call " + std::to_string(j) + ": " + c->err;
+                return (supa_status)r;
+            } else if (r == SUPA_ERR_CAPACITY) {
+                if (!cap) first_cap = j;
+                cap = true;
+            }
+        }
+        if (rerun) continue;
+        if (cap) {
+            // finish() of later calls cleared the message: restate the first
+            return fail(c, SUPA_ERR_CAPACITY, "call " + std::to_string(first_cap) + ": hit or node arrays too small "
+                                              "(need " + std::to_string(out[first_cap].total_hits) + " hits, " +
+                                              std::to_string(out[first_cap].total_nodes) + " nodes)");
+        }
+        c->err.clear();
+        return SUPA_OK;
+    }
+    return fail(c, SUPA_ERR_NOMEM, "scratch sizes did not converge");
+}
+
 // A captured call: the launch sequence of one supa_simulate (one sub-batch,
 // no host work) as an instantiated HIP graph, with its own copy of the
 // per-call input/output block so that replays do not depend on later calls.
@@ -938,7 +1119,7 @@ extern "C" supa_status supa_graph_create(supa_ctx *c, const supa_batch *b, uint6
     if (e == hipSuccess) e = hipMemcpy(g->d_cold, c->h_cold, sizeof(supa::Cold), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamBeginCapture(c->aux, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
-        st = enqueue(c, b, out, g->plan, g->d_cold, c->aux, c->aux, false);
+        st = enqueue(c, b, out, g->plan, g->d_cold, c->aux, c->aux, false, c->ev_prop, c->ev_post, c->ev_place);
         const hipError_t e2 = hipStreamEndCapture(c->aux, &graph);
         if (st == SUPA_OK && e2 != hipSuccess) e = e2;
     }
@@ -978,7 +1159,7 @@ extern "C" supa_status supa_graph_check(supa_graph *g, void *hip_stream, int64_t
     const supa_status cur = graph_current(g);
     if (cur != SUPA_OK) return cur;
     const hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
-    HIP_TRY(c, hipMemcpyAsync(c->h_ctr, c->d_ctr, supa::CTR_WORDS * sizeof(unsigned long long),
+    HIP_TRY(c, hipMemcpyAsync(c->h_ctr, g->plan.ctr, supa::CTR_WORDS * sizeof(unsigned long long),
                               hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipStreamSynchronize(s));
     supa_output o = g->out;

@@ -73,7 +73,7 @@ class Output(C.Structure):
 
 
 EXPORTS = ["supa_abi_version", "supa_validate_geometry", "supa_validate_call", "supa_init_geometry", "supa_destroy",
-           "supa_simulate", "supa_simulate_noalloc", "supa_set_launch", "supa_set_schedule", "supa_autotune",
+           "supa_simulate", "supa_simulate_batches", "supa_simulate_noalloc", "supa_set_launch", "supa_set_schedule", "supa_autotune",
            "supa_graph_create", "supa_graph_launch", "supa_graph_check", "supa_graph_destroy", "supa_last_timing", "supa_last_kernel_times", "supa_philox",
            "supa_last_error"]
 
@@ -100,6 +100,9 @@ def load():
         L.supa_destroy.argtypes = [C.c_void_p]
         L.supa_simulate.restype = C.c_int
         L.supa_simulate.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_uint64, C.POINTER(Output)]
+        L.supa_simulate_batches.restype = C.c_int
+        L.supa_simulate_batches.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Batch), C.c_uint64,
+                                            C.POINTER(Output)]
         L.supa_simulate_noalloc.restype = C.c_int
         L.supa_simulate_noalloc.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_uint64, C.POINTER(Output)]
         L.supa_set_launch.restype = C.c_int
@@ -358,6 +361,27 @@ class Simulator:
         b, o = self._marshal(e0, polar, azimuth, out, x0, y0, shower_id_base)
         st = self.lib.supa_simulate(self.ctx, C.byref(b), seed & 0xFFFFFFFFFFFFFFFF, C.byref(o))
         self._totals(out, o)
+        if st not in (0, 3):
+            self._check(st)
+        return st
+
+    def run_batches(self, e0, polar, azimuth, seed: int, calls, outs) -> int:
+        """supa_simulate_batches: call j simulates showers calls[j] = (s0, m)
+        of the initial-condition arrays (global ids s0 .. s0+m-1) into outs[j]
+        (dicts as from allocate; record and image tensors may be shared
+        between calls, ledger and counts of consecutive calls may not).
+        Returns the status (OK or CAPACITY); fills outs[j]['total_*']."""
+        k = len(calls)
+        if len(outs) != k:
+            raise ValueError("one output dict per call")
+        bs, os_ = (Batch * max(k, 1))(), (Output * max(k, 1))()
+        for j, ((s0, m), out) in enumerate(zip(calls, outs)):
+            sl = slice(s0, s0 + m)
+            b, o = self._marshal(e0[sl], polar[sl], azimuth[sl], out, None, None, s0)
+            bs[j], os_[j] = b, o
+        st = self.lib.supa_simulate_batches(self.ctx, k, bs, seed & 0xFFFFFFFFFFFFFFFF, os_)
+        for j, out in enumerate(outs):
+            self._totals(out, os_[j])
         if st not in (0, 3):
             self._check(st)
         return st

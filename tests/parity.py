@@ -232,3 +232,33 @@ def check_hits_unkeyed(gpu: dict, ref: dict, rows=None):
                 bad = np.nonzero(~ok)[0][0]
                 raise AssertionError(f"shower {s}: hit {c} {gpu['hit_' + c][sl][gk][bad]} vs "
                                      f"{ref['hit_' + c][ri][rk][bad]}")
+
+
+def check_same_outputs(a, b, images=True):
+    """Two runs of one call through different entry points or launch
+    settings: equal bit for bit (the order of records within a plane and the
+    numbering of nodes may differ, so hits and nodes are compared in path-id
+    order and parents by their path ids)."""
+    a, b = to_numpy(a), to_numpy(b)
+    assert a["total_hits"] == b["total_hits"] and a["total_nodes"] == b["total_nodes"]
+    assert a["total_steps"] == b["total_steps"]
+    for k in ("counts", "ledger", "hit_offsets", "node_offsets") + (("images",) if images else ()):
+        if k in a or k in b:
+            np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    n = a["counts"].shape[0]
+    for pre, off, col, fields in (("hit", "hit_offsets", 1, ("x", "y", "e", "layer", "key")),
+                                  ("node", "node_offsets", 0, ("gen", "vx", "vy", "vz", "e", "key"))):
+        if off not in a:
+            continue
+        for i in range(n):
+            sl = slice(int(a[off][i]), int(a[off][i]) + int(a["counts"][i, col]))
+            ka, kb = a[pre + "_key"][sl], b[pre + "_key"][sl]
+            oa, ob = np.argsort(ka), np.argsort(kb)
+            for f in fields:
+                np.testing.assert_array_equal(a[f"{pre}_{f}"][sl][oa], b[f"{pre}_{f}"][sl][ob],
+                                              err_msg=f"shower {i}: {pre}_{f}")
+            if pre == "node":
+                pa, pb = a["node_parent"][sl], b["node_parent"][sl]
+                pka = np.where(pa >= 0, ka[np.maximum(pa, 0)], 0)
+                pkb = np.where(pb >= 0, kb[np.maximum(pb, 0)], 0)
+                np.testing.assert_array_equal(pka[oa], pkb[ob], err_msg=f"shower {i}: parents")

@@ -671,3 +671,73 @@ def test_1m_20plane_1000_showers_as_benchmarked():
         parity.check_counts(gpu, ref)
         parity.check_hits_unkeyed(gpu, ref)
     g.close()
+
+
+# --------------------------------------------------------------------------
+# several calls in one (supa_simulate_batches): the propagation of a call
+# runs while the previous one's hits, images and tree are placed
+# --------------------------------------------------------------------------
+def test_batches_match_single_calls():
+    """Five calls (the last one ragged) with outputs of their own, and with
+    the library's logs forced to grow (the whole set is rerun): every call
+    bit for bit equal to the same call made alone, and the oracle on one."""
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    geom = workloads.geometry(w)
+    n = 1370
+    e0, pol, az = workloads.initial_conditions(w, n)
+    te0, tpol, taz = dev_t(e0), dev_t(pol), dev_t(az)
+    calls = [(s0, min(300, n - s0)) for s0 in range(0, n, 300)]
+    single = supa.Simulator(geom, ALL)
+    refs = [single.simulate(te0[s0:s0 + m], tpol[s0:s0 + m], taz[s0:s0 + m], w.seed, shower_id_base=s0)
+            for s0, m in calls]
+    for launch in (dict(), dict(hit_cap=64, node_cap=64, waves_per_cu=4)):
+        sim = supa.Simulator(geom, ALL, **launch)
+        outs = [sim.allocate(m, int(r["total_hits"]), int(r["total_nodes"])) for (s0, m), r in zip(calls, refs)]
+        for o in outs:
+            for v in o.values():
+                if isinstance(v, torch.Tensor):
+                    v.fill_(-7)
+        assert sim.run_batches(te0, tpol, taz, w.seed, calls, outs) == 0
+        torch.cuda.synchronize()
+        for (s0, m), o, r in zip(calls, outs, refs):
+            parity.check_same_outputs(o, r)
+    s0, m = calls[2]
+    ref = O.simulate(geom, e0[s0:s0 + m], pol[s0:s0 + m], az[s0:s0 + m], w.seed, shower_id_base=s0)
+    parity.check_all(parity.to_numpy(outs[2]), ref, geom, images=True, tree=True)
+
+
+def test_batches_share_records_and_images():
+    """The 50-plane workload as its benchmark step runs it: calls that share
+    one set of hit, node and image arrays (each call's ledger, counts and
+    offsets its own).  Every call's per-shower results equal a call made
+    alone, and the shared arrays end up holding the last call's outputs."""
+    w = workloads.WORKLOADS["loge10to1000_50planes_tree_img256_1m"]
+    geom = workloads.geometry(w)
+    n = 800
+    e0, pol, az = workloads.initial_conditions(w, n)
+    te0, tpol, taz = dev_t(e0), dev_t(pol), dev_t(az)
+    calls = [(s0, 200) for s0 in range(0, n, 200)]
+    single = supa.Simulator(geom, ALL)
+    refs = [single.simulate(te0[s0:s0 + m], tpol[s0:s0 + m], taz[s0:s0 + m], w.seed, shower_id_base=s0)
+            for s0, m in calls]
+    hc = max(int(r["total_hits"]) for r in refs)
+    nc = max(int(r["total_nodes"]) for r in refs)
+    sim = supa.Simulator(geom, ALL)
+    shared = sim.allocate(200, hc, nc)
+    outs = []
+    for _ in calls:
+        o = sim.allocate(200, 0, 0)
+        for k, v in shared.items():
+            if k not in ("ledger", "counts", "hit_offsets", "node_offsets"):
+                o[k] = v
+        outs.append(o)
+    assert sim.run_batches(te0, tpol, taz, w.seed, calls, outs) == 0
+    torch.cuda.synchronize()
+    for o, r in zip(outs, refs):
+        for k in ("counts", "ledger", "hit_offsets", "node_offsets"):
+            np.testing.assert_array_equal(o[k].cpu().numpy(), r[k].cpu().numpy(), err_msg=k)
+    parity.check_same_outputs(outs[-1], refs[-1])
+    # consecutive calls may not share ledger or counts rows
+    bad = [outs[0], dict(outs[1], counts=outs[0]["counts"])]
+    with pytest.raises(supa.SupaError, match="share ledger or counts"):
+        sim.run_batches(te0, tpol, taz, w.seed, calls[:2], bad)

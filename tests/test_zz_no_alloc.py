@@ -33,30 +33,6 @@ def poisoned(sim, n, hc, nc):
     return out
 
 
-def assert_same(a, b):
-    """Outputs of the two entry points for one call: equal bit for bit."""
-    a, b = parity.to_numpy(a), parity.to_numpy(b)
-    assert a["total_hits"] == b["total_hits"] and a["total_nodes"] == b["total_nodes"]
-    assert a["total_steps"] == b["total_steps"]
-    for k in ("counts", "ledger", "hit_offsets", "node_offsets", "images"):
-        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
-    n = a["counts"].shape[0]
-    for pre, off, col, fields in (("hit", "hit_offsets", 1, ("x", "y", "e", "layer", "key")),
-                                  ("node", "node_offsets", 0, ("gen", "vx", "vy", "vz", "e", "key"))):
-        for i in range(n):
-            sl = slice(int(a[off][i]), int(a[off][i]) + int(a["counts"][i, col]))
-            ka, kb = a[pre + "_key"][sl], b[pre + "_key"][sl]
-            oa, ob = np.argsort(ka), np.argsort(kb)
-            for f in fields:
-                np.testing.assert_array_equal(a[f"{pre}_{f}"][sl][oa], b[f"{pre}_{f}"][sl][ob],
-                                              err_msg=f"shower {i}: {pre}_{f}")
-            if pre == "node":
-                pa, pb = a["node_parent"][sl], b["node_parent"][sl]
-                pka = np.where(pa >= 0, ka[np.maximum(pa, 0)], 0)
-                pkb = np.where(pb >= 0, kb[np.maximum(pb, 0)], 0)
-                np.testing.assert_array_equal(pka[oa], pkb[ob], err_msg=f"shower {i}: parents")
-
-
 def test_noalloc_matches_simulate_on_two_calls_in_a_row():
     w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
     geom = workloads.geometry(w)
@@ -73,7 +49,7 @@ def test_noalloc_matches_simulate_on_two_calls_in_a_row():
         st = fix_sim.run_noalloc(*args, out, shower_id_base=s0)
         assert st == 0, st
         torch.cuda.synchronize()
-        assert_same(out, ref)
+        parity.check_same_outputs(out, ref)
     # the smaller call also against the oracle
     orc = O.simulate(geom, e0[sl], pol[sl], az[sl], w.seed, shower_id_base=s0)
     parity.check_all(parity.to_numpy(out), orc, geom, images=True, tree=True)
