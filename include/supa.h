@@ -312,9 +312,14 @@ supa_status supa_set_schedule(supa_ctx *ctx, int32_t sub_batches, int32_t cost_o
  * context.  Same arguments and errors as supa_simulate; `out` holds the
  * batch's results afterwards.  best (host, 4 int32) receives waves_per_cu,
  * frontier_cap, sub_batches, cost_order; best_ms (host) the fastest time.
+ * The choice is kept in the context (whose geometry and device are fixed)
+ * per batch size: a later supa_autotune of a batch of the same size applies
+ * it and makes one call, without searching again.  supa_autotune_forget
+ * clears what the context keeps.
  */
 supa_status supa_autotune(supa_ctx *ctx, const supa_batch *b, uint64_t seed, supa_output *out,
                           int32_t *best, float *best_ms);
+supa_status supa_autotune_forget(supa_ctx *ctx);
 
 /*
  * Captured calls (HIP graphs).  supa_graph_create runs supa_simulate once on
@@ -364,6 +369,17 @@ supa_status supa_last_timing(const supa_ctx *ctx, float *ms3);
  * fifth are set to 0.
  */
 supa_status supa_last_kernel_times(const supa_ctx *ctx, float *ms, int32_t count);
+
+/*
+ * How evenly the last propagation launch of the context kept its waves busy:
+ * ms[q] (host, up to `capacity` entries) = the time wave q spent from its
+ * start to its exit, on the device's constant-rate clock; *count (host) =
+ * the waves that launch had.  The launch is that of the last supa_simulate,
+ * supa_simulate_noalloc, graph replay, or the last call of
+ * supa_simulate_batches (the last sub-batch with sub-batches).  Synchronises
+ * the context's stream.
+ */
+supa_status supa_last_wave_times(supa_ctx *ctx, float *ms, int32_t capacity, int32_t *count);
 
 /*
  * One Philox4x32-10 block per counter, on the device: ctr and out are device

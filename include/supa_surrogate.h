@@ -134,13 +134,16 @@ supa_status supa_surrogate_gate(void *hip_stream, int B, int D, int L, const flo
  * of W, K entries), bias float [2D].  Each 128-column tile of a row (half
  * of a layer's bins, means or log-variances) is reduced in the product's
  * epilogue into partial (float scratch, caller-owned, B * (2D / 128) * 2
- * floats); a second kernel combines them per shower.  Requirements: K a
- * multiple of 8, L <= 64, D / L a multiple of 128.
+ * floats); a second kernel combines them per shower.  layer_cnt (float
+ * [B][L], may be NULL): per layer, the number of bins whose predicted energy
+ * mu * e0 / y_scale exceeds cnt_thr >= 0 (the predicted occupied cells).
+ * Requirements: K a multiple of 8, L <= 64, D / L a multiple of 128.
  */
 supa_status supa_surrogate_gate_fused(void *hip_stream, int B, int K, int D, int L, const uint16_t *h, int ldh,
                                       const uint16_t *w_t, int ldw, const float *bias, const float *e0,
                                       float y_scale, float s_clamp, float *partial, float *layer_e, float *unc,
-                                      float rho, uint32_t row_base, uint64_t seed);
+                                      float rho, uint32_t row_base, uint64_t seed, float cnt_thr,
+                                      float *layer_cnt);
 
 /* y[c][r] = bf16(x[r][c]): float [rows][cols] to bf16 [cols][rows] (round to nearest even). */
 supa_status supa_transpose_to_bf16(void *hip_stream, int rows, int cols, const float *x, uint16_t *y);
@@ -162,6 +165,36 @@ supa_status supa_scatter_rows(void *hip_stream, int m, int w, const int32_t *idx
 
 /* out[r][l] = sum over q < g of x[r][l*g + q] (float), r < rows, l < L. */
 supa_status supa_group_sums(void *hip_stream, int rows, int L, int g, const float *x, float *out);
+
+/*
+ * The judge of the surrogate (section "Performance Analysis of Generative
+ * Models": 1-D Wasserstein distances between distributions of the same
+ * quantity from two generators).
+ *
+ * supa_w1_equal: exact W1 between the columns of two samples of equal size,
+ * w1[c] = (1/n) sum_i |a_(i)c - b_(i)c| with a_(i)c the i-th smallest value
+ * of column c (the area between the two empirical distribution functions).
+ * a float [n][lda], b float [n][ldb], 1 <= n <= 2^30, 1 <= cols <= 4096
+ * <= lda, ldb; w1 double [cols] (device); work: device workspace of
+ * supa_w1_equal_workspace_bytes(n, cols) bytes.  Each column is sorted by a
+ * stable radix sort of its float bit patterns (NaNs sort past +inf, -0 before
+ * +0); the sums are in double, in an order fixed by n alone (deterministic).
+ */
+int64_t supa_w1_equal_workspace_bytes(int64_t n, int32_t cols);
+supa_status supa_w1_equal(void *hip_stream, int64_t n, int32_t cols, const float *a, int64_t lda,
+                          const float *b, int64_t ldb, double *w1, void *work, int64_t work_bytes);
+
+/* The sort of supa_w1_equal on its own: out float [cols][n] holds column c of
+ * x (float [n][ld]) in increasing order; work: device workspace of
+ * supa_sort_columns_workspace_bytes(n, cols) bytes. */
+int64_t supa_sort_columns_workspace_bytes(int64_t n, int32_t cols);
+supa_status supa_sort_columns(void *hip_stream, int64_t n, int32_t cols, const float *x, int64_t ld,
+                              float *out, void *work, int64_t work_bytes);
+
+/* Occupied cells of per-layer images: cnt[r][l] = the number of q < g with
+ * img[r][l * g + q] > thr (img float [rows][L * g], cnt float [rows][L]). */
+supa_status supa_occupied_counts(void *hip_stream, int64_t rows, int32_t L, int32_t g, const float *img,
+                                 float thr, float *cnt);
 
 /* Message of the calling thread's last surrogate-kernel error. */
 const char *supa_surrogate_last_error(void);

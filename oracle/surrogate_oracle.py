@@ -246,3 +246,11 @@ def gate(out, e0, n_layers, y_scale, s_clamp=S_CLAMP, rho=-1.0, seed=0, row_base
     scale = np.asarray(e0, np.float64)[:, None] / y_scale
     unc = np.sqrt(var.sum(axis=1)) / np.maximum(m.sum(axis=1), 1e-6)
     return v * scale, unc
+
+
+def occupied(values, n_layers, thr):
+    """Per row and layer, the number of cells whose value exceeds thr
+    (values [rows, L * cells]): the occupied cells of an image, or of a
+    predicted image."""
+    v = np.asarray(values, np.float64)
+    return (v.reshape(v.shape[0], n_layers, -1) > thr).sum(axis=2)

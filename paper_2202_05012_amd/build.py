@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsupa.so")
 
 SOURCES = ["supa_api.hip", "supa_propagate.hip", "supa_place.hip", "supa_scatter.hip", "supa_order.hip", "supa_mlp.hip",
-           "supa_surrogate_api.hip", "supa_shapes.hip", "supa_grids.hip"]
+           "supa_surrogate_api.hip", "supa_shapes.hip", "supa_grids.hip", "supa_judge.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

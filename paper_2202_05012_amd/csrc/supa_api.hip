@@ -137,6 +137,15 @@ struct supa_ctx {
     hipEvent_t ev_set_free[2] = {};      // second stream done with a set of buffers
     uint64_t scratch_gen = 0;            // advanced by every scratch reallocation
     char *fixed = nullptr;               // this device's fixed scratch array (device address)
+    unsigned long long *d_wclk = nullptr;   // per wave of the last propagation launch: start, end
+    int64_t last_waves = 0;
+    // launch settings picked by supa_autotune, per batch size
+    struct Tuned {
+        int64_t n;
+        int32_t best[4];
+        float ms;
+    };
+    std::vector<Tuned> tuned;
     // the placement of a sub-batch runs on a second stream, overlapping the
     // propagation of the next one
     hipStream_t aux = nullptr;
@@ -343,6 +352,7 @@ extern "C" supa_status supa_init_geometry(const supa_geometry *g, int device, vo
               hipMalloc(&c->d_ctr, 2 * supa::CTR_WORDS * sizeof(unsigned long long)) == hipSuccess &&
               hipHostMalloc(&c->h_ctr, supa::CTR_WORDS * sizeof(unsigned long long), 0) == hipSuccess &&
               hipMalloc(&c->d_cold, supa::MAX_SUB * sizeof(supa::Cold)) == hipSuccess &&
+              hipMalloc(&c->d_wclk, (size_t)2 * 32 * c->n_cu * sizeof(unsigned long long)) == hipSuccess &&
               hipHostMalloc(&c->h_cold, supa::MAX_SUB * sizeof(supa::Cold), 0) == hipSuccess &&
               hipMemcpy(c->d_layer, c->layer.data(), N * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(c->d_c1, c1.data(), THR_ENTRIES * sizeof(uint64_t), hipMemcpyHostToDevice) == hipSuccess &&
@@ -389,6 +399,7 @@ extern "C" supa_status supa_destroy(supa_ctx *c) {
     if (c->d_ctr) (void)hipFree(c->d_ctr);
     if (c->h_ctr) (void)hipHostFree(c->h_ctr);
     if (c->d_cold) (void)hipFree(c->d_cold);
+    if (c->d_wclk) (void)hipFree(c->d_wclk);
     if (c->h_cold) (void)hipHostFree(c->h_cold);
     for (hipEvent_t e : {c->ev_begin, c->ev_end, c->ev_joined})
         if (e) (void)hipEventDestroy(e);
@@ -443,6 +454,24 @@ extern "C" supa_status supa_last_kernel_times(const supa_ctx *c, float *ms, int3
     const int m = std::min<int>(count, 5);
     std::memcpy(ms, c->timing, (size_t)m * sizeof(float));
     for (int q = m; q < count; ++q) ms[q] = 0.0f;
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_last_wave_times(supa_ctx *c, float *ms, int32_t capacity, int32_t *count) {
+    if (!c) return SUPA_ERR_STATE;
+    if (!count || capacity < 0 || (capacity > 0 && !ms)) return fail(c, SUPA_ERR_INVALID_ARG, "bad wave-time arguments");
+    const int64_t w = std::min<int64_t>(c->last_waves, (int64_t)32 * c->n_cu);
+    *count = (int32_t)w;
+    if (w == 0 || capacity == 0) return SUPA_OK;
+    std::vector<unsigned long long> t((size_t)2 * w);
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(t.data(), c->d_wclk, t.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    int rate_khz = 0;
+    HIP_TRY(c, hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
+    const double to_ms = rate_khz > 0 ? 1.0 / rate_khz : 0.0;
+    for (int64_t q = 0; q < std::min<int64_t>(w, capacity); ++q)
+        ms[q] = (float)((double)(t[2 * q + 1] - t[2 * q]) * to_ms);
     return SUPA_OK;
 }
 
@@ -704,7 +733,9 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
         K.counts = out->counts + 6 * o;
         K.hstart = L.d_hstart ? L.d_hstart + o : nullptr;
         for (int q = 0; q < 4; ++q) K.ring_r[q] = c->ring_r[q];
+        K.wave_clk = c->d_wclk;
     }
+    c->last_waves = L.waves;
     return SUPA_OK;
 }
 
@@ -1192,6 +1223,18 @@ extern "C" supa_status supa_autotune(supa_ctx *c, const supa_batch *b, uint64_t 
                                      int32_t *best, float *best_ms) {
     if (!c) return SUPA_ERR_STATE;
     if (!best || !best_ms) return fail(c, SUPA_ERR_INVALID_ARG, "best and best_ms are required");
+    // a batch size searched before on this context (its geometry and
+    // device): the same settings, one call
+    for (const supa_ctx::Tuned &t : c->tuned)
+        if (t.n == (b ? b->n : -1)) {
+            c->waves_per_cu = t.best[0];
+            c->pool_cap = t.best[1];
+            c->sub_batches = t.best[2];
+            c->cost_order = t.best[3];
+            std::memcpy(best, t.best, sizeof(t.best));
+            *best_ms = t.ms;
+            return supa_simulate(c, b, seed, out);
+        }
     static const int waves[] = {8, 12, 16};
     static const int pools[] = {128, 256};
     static const int subs[] = {1, 2};
@@ -1234,5 +1277,12 @@ extern "C" supa_status supa_autotune(supa_ctx *c, const supa_batch *b, uint64_t 
     best[2] = bs;
     best[3] = bo;
     *best_ms = bms;
+    if (st == SUPA_OK) c->tuned.push_back(supa_ctx::Tuned{b->n, {bw, bp, bs, bo}, bms});
     return st;
+}
+
+extern "C" supa_status supa_autotune_forget(supa_ctx *c) {
+    if (!c) return SUPA_ERR_STATE;
+    c->tuned.clear();
+    return SUPA_OK;
 }

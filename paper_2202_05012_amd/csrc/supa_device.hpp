@@ -75,6 +75,7 @@ struct Cold {
     int32_t *counts;            // [n][6]
     int64_t *hstart;            // [n]: log position of the shower's first hit record
     float ring_r[4];            // ring radii (regional parameters), +inf past the last
+    unsigned long long *wave_clk;   // per wave: wall-clock start and end of its work, or null
 };
 
 // Hit records leave the propagation kernel through a log of chunks of

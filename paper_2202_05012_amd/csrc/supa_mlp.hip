@@ -54,42 +54,60 @@ constexpr int GT = 128;         // tile edge
 constexpr int GK = 32;          // K step
 constexpr int GPAD = GK + 8;    // LDS row length (bf16), staggers banks
 
+// One K step of the two operand tiles, held in registers between the global
+// loads and the LDS stores (so the next step's loads are in flight while
+// the current one is multiplied): 512 chunks of 8 bf16 per operand tile,
+// two per thread; rows or columns beyond the matrix read as zeros.
+struct TileRegs {
+    uint4 a[2], b[2];
+};
+
 template <int TA, int TB>
-__device__ __forceinline__ void load_tiles(const GemmArgs &g, int m0, int n0, int k0,
-                                           uint16_t (*As)[GPAD], uint16_t (*Bs)[GPAD]) {
+__device__ __forceinline__ void tile_load(const GemmArgs &g, int m0, int n0, int k0, TileRegs &R) {
     const int tid = threadIdx.x;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        const int c = tid + r * 256;     // 512 chunks of 8 bf16 per operand tile
-        // ---- A
+        const int c = tid + r * 256;
+        R.a[r] = make_uint4(0u, 0u, 0u, 0u);
+        R.b[r] = make_uint4(0u, 0u, 0u, 0u);
         if (TA == 0) {
             const int m = c >> 2, kc = (c & 3) * 8;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (m0 + m < g.M && k0 + kc < g.K)
-                v = *(const uint4 *)(g.A + (int64_t)(m0 + m) * g.lda + k0 + kc);
-            *(uint4 *)&As[m][kc] = v;
+            if (m0 + m < g.M && k0 + kc < g.K) R.a[r] = *(const uint4 *)(g.A + (int64_t)(m0 + m) * g.lda + k0 + kc);
         } else {
             const int k = c >> 4, mc = (c & 15) * 8;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (k0 + k < g.K && m0 + mc < g.M)
-                v = *(const uint4 *)(g.A + (int64_t)(k0 + k) * g.lda + m0 + mc);
-            const uint16_t *e = (const uint16_t *)&v;
+            if (k0 + k < g.K && m0 + mc < g.M) R.a[r] = *(const uint4 *)(g.A + (int64_t)(k0 + k) * g.lda + m0 + mc);
+        }
+        if (TB == 1) {
+            const int n = c >> 2, kc = (c & 3) * 8;
+            if (n0 + n < g.N && k0 + kc < g.K) R.b[r] = *(const uint4 *)(g.B + (int64_t)(n0 + n) * g.ldb + k0 + kc);
+        } else {
+            const int k = c >> 4, nc = (c & 15) * 8;
+            if (k0 + k < g.K && n0 + nc < g.N) R.b[r] = *(const uint4 *)(g.B + (int64_t)(k0 + k) * g.ldb + n0 + nc);
+        }
+    }
+}
+
+// The registers of a K step into LDS, both operands K-contiguous per row
+// ([row][k]), the layout the matrix-core operands are read in.
+template <int TA, int TB>
+__device__ __forceinline__ void tile_store(const TileRegs &R, uint16_t (*As)[GPAD], uint16_t (*Bs)[GPAD]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int c = tid + r * 256;
+        if (TA == 0) {
+            *(uint4 *)&As[c >> 2][(c & 3) * 8] = R.a[r];
+        } else {
+            const int k = c >> 4, mc = (c & 15) * 8;
+            const uint16_t *e = (const uint16_t *)&R.a[r];
 #pragma unroll
             for (int q = 0; q < 8; ++q) As[mc + q][k] = e[q];
         }
-        // ---- B
         if (TB == 1) {
-            const int n = c >> 2, kc = (c & 3) * 8;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (n0 + n < g.N && k0 + kc < g.K)
-                v = *(const uint4 *)(g.B + (int64_t)(n0 + n) * g.ldb + k0 + kc);
-            *(uint4 *)&Bs[n][kc] = v;
+            *(uint4 *)&Bs[c >> 2][(c & 3) * 8] = R.b[r];
         } else {
             const int k = c >> 4, nc = (c & 15) * 8;
-            uint4 v = make_uint4(0u, 0u, 0u, 0u);
-            if (k0 + k < g.K && n0 + nc < g.N)
-                v = *(const uint4 *)(g.B + (int64_t)(k0 + k) * g.ldb + n0 + nc);
-            const uint16_t *e = (const uint16_t *)&v;
+            const uint16_t *e = (const uint16_t *)&R.b[r];
 #pragma unroll
             for (int q = 0; q < 8; ++q) Bs[nc + q][k] = e[q];
         }
@@ -98,8 +116,10 @@ __device__ __forceinline__ void load_tiles(const GemmArgs &g, int m0, int n0, in
 
 template <int TA, int TB, int EPI>
 __global__ void __launch_bounds__(256) gemm_bf16(GemmArgs g) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[GT][GPAD];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[GT][GPAD];
+    // two LDS buffers: the matrix cores read one while the next K step is
+    // stored into the other (one barrier per step)
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][GT][GPAD];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][GT][GPAD];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -113,27 +133,38 @@ __global__ void __launch_bounds__(256) gemm_bf16(GemmArgs g) {
 
     const int kb = g.k_chunk > 0 ? blockIdx.z * g.k_chunk : 0;
     const int ke = g.k_chunk > 0 ? min(g.K, kb + g.k_chunk) : g.K;
+    TileRegs R;
+    if (kb < ke) {
+        tile_load<TA, TB>(g, m0, n0, kb, R);
+        tile_store<TA, TB>(R, As[0], Bs[0]);
+    }
+    __syncthreads();
+    int cur = 0;
     for (int k0 = kb; k0 < ke; k0 += GK) {
-        load_tiles<TA, TB>(g, m0, n0, k0, As, Bs);
-        __syncthreads();
+        const bool more = k0 + GK < ke;
+        if (more) tile_load<TA, TB>(g, m0, n0, k0 + GK, R);      // in flight during the products
         bf16x8_t a[4], b[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8_t *)&As[wm + i * 16 + lr][lk];
+        for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8_t *)&As[cur][wm + i * 16 + lr][lk];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8_t *)&Bs[wn + j * 16 + lr][lk];
+        for (int j = 0; j < 4; ++j) b[j] = *(const bf16x8_t *)&Bs[cur][wn + j * 16 + lr][lk];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        // the other buffer was last read before the previous barrier
+        if (more) tile_store<TA, TB>(R, As[cur ^ 1], Bs[cur ^ 1]);
         __syncthreads();
+        cur ^= 1;
     }
 
     if constexpr (EPI == EPI_GATE) {
         // Final layer without its output: per row, the tile's 128 columns
         // (all means, or all log-variances, of half a layer) reduce to
-        // sum mu, or to sum exp(s) and sum exp(s/2) with s clamped; written
-        // as C[m][tile][2] (float).  N is a multiple of GT.
+        // sum mu and the number of means above the row's occupancy
+        // threshold, or to sum exp(s) and sum exp(s/2) with s clamped;
+        // written as C[m][tile][2] (float).  N is a multiple of GT.
         __shared__ float red[2][GT][2];
         const bool var = n0 >= g.split;
 #pragma unroll
@@ -141,11 +172,14 @@ __global__ void __launch_bounds__(256) gemm_bf16(GemmArgs g) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 float p0 = 0.f, p1 = 0.f;
+                const int mrow = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+                const float thr = (!var && g.e0 && mrow < g.M) ? g.cnt_scale / g.e0[mrow] : __builtin_inff();
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const float v = acc[i][j][r] + g.bias[n0 + wn + j * 16 + lr];
                     if (!var) {
                         p0 += v;
+                        p1 += v > thr ? 1.0f : 0.0f;
                     } else {
                         const float sv = fminf(fmaxf(v, -g.s_clamp), g.s_clamp);
                         p0 += __expf(sv);
@@ -412,19 +446,22 @@ __global__ void gate_kernel(int B, int D, int L, const float *out, const float *
 // samples, same Philox counters) and the uncertainty score.
 __global__ void __launch_bounds__(256) gate_tiles_kernel(int B, int D, int L, const float *P, const float *e0,
                                                          float y_scale, float *layer_e, float *unc, float rho,
-                                                         uint32_t row_base, uint32_t k0, uint32_t k1) {
+                                                         uint32_t row_base, uint32_t k0, uint32_t k1,
+                                                         float *layer_cnt) {
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (b >= B) return;                                   // whole waves leave together
     const int tiles = 2 * D / GT, tpl = D / L / GT;
     const float *row = P + (int64_t)b * tiles * 2;
-    float sm = 0.f, sv = 0.f, ss = 0.f;
+    float sm = 0.f, sv = 0.f, ss = 0.f, sc = 0.f;
     if (lane < L) {
         for (int t = 0; t < tpl; ++t) {
             sm += row[2 * (lane * tpl + t)];
+            sc += row[2 * (lane * tpl + t) + 1];
             sv += row[2 * (D / GT + lane * tpl + t)];
             ss += row[2 * (D / GT + lane * tpl + t) + 1];
         }
+        if (layer_cnt) layer_cnt[(int64_t)b * L + lane] = sc;
         float v = sm;
         if (rho >= 0.0f) {
             const uint4 w = philox4x32_10(row_base + (uint32_t)b, (uint32_t)lane, 0x9a7eu, 0u, k0, k1);
@@ -463,7 +500,7 @@ __global__ void transpose_bf16_kernel(int rows, int cols, const float *x, uint16
 hipError_t launch_gate_fused(int B, int K, int D, int L, const uint16_t *h, int ldh, const uint16_t *wt, int ldw,
                              const float *bias, const float *e0, float y_scale, float s_clamp, float *partial,
                              float *layer_e, float *unc, float rho, uint32_t row_base, uint64_t seed,
-                             hipStream_t s) {
+                             float cnt_thr, float *layer_cnt, hipStream_t s) {
     GemmArgs g{};
     g.M = B;
     g.N = 2 * D;
@@ -476,10 +513,13 @@ hipError_t launch_gate_fused(int B, int K, int D, int L, const uint16_t *h, int 
     g.C = partial;
     g.split = D;
     g.s_clamp = s_clamp;
+    // a bin is occupied when its energy mu * e0 / y_scale exceeds cnt_thr
+    g.e0 = layer_cnt ? e0 : nullptr;
+    g.cnt_scale = cnt_thr * y_scale;
     hipError_t e = launch_gemm(0, 1, EPI_GATE, g, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gate_tiles_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, B, D, L, partial, e0,
-                       y_scale, layer_e, unc, rho, row_base, (uint32_t)seed, (uint32_t)(seed >> 32));
+                       y_scale, layer_e, unc, rho, row_base, (uint32_t)seed, (uint32_t)(seed >> 32), layer_cnt);
     return hipGetLastError();
 }
 

@@ -19,6 +19,8 @@ struct GemmArgs {
                          //   its partial product at C + z M ldc (EPI_F32); 0: all of K
     int split;           // EPI_GATE: columns from split on are log-variances
     float s_clamp;       // EPI_GATE: log-variance clamp
+    const float *e0;     // EPI_GATE with counts: per row; a mean column counts as occupied when
+    float cnt_scale;     //   mu > cnt_scale / e0[row] (null e0: no counts)
 };
 
 }  // namespace supa

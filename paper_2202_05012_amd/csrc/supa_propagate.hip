@@ -253,6 +253,9 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
     const uint32_t lane = lane_id();
     const int64_t wave = blockIdx.x;
     const int N = P.n_planes;
+    // the wave's start on the constant-rate clock (stored at once: nothing is
+    // held through the loop)
+    if (lane == 0 && COLD(wave_clk)) COLD(wave_clk)[2 * wave] = (unsigned long long)wall_clock64();
     // PC: pool entries in LDS, a power of two >= 2 * WAVE (compile-time, so
     // that the field offsets are instruction immediates)
     uint32_t *const pool = lds;            // [POOL_FIELDS][PC], entry j at slot j & (PC-1)
@@ -764,6 +767,7 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
         atomicMax(&P.ctr[CTR_NEED_F], (unsigned long long)max_top);
     }
     if (wave_ballot(overflow) && lane == 0) atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_OVERFLOW);
+    if (lane == 0 && COLD(wave_clk)) COLD(wave_clk)[2 * wave + 1] = (unsigned long long)wall_clock64();
 }
 
 __global__ void supa_zero_counters(unsigned long long *ctr) {

@@ -38,8 +38,17 @@ hipError_t launch_group_sums(int rows, int L, int g, const float *x, float *out,
 hipError_t launch_gate_fused(int B, int K, int D, int L, const uint16_t *h, int ldh, const uint16_t *wt, int ldw,
                              const float *bias, const float *e0, float y_scale, float s_clamp, float *partial,
                              float *layer_e, float *unc, float rho, uint32_t row_base, uint64_t seed,
-                             hipStream_t s);
+                             float cnt_thr, float *layer_cnt, hipStream_t s);
 hipError_t launch_transpose_bf16(int rows, int cols, const float *x, uint16_t *y, hipStream_t s);
+size_t sort_work_bytes(int64_t n, int cols);
+hipError_t launch_sort_columns(const float *x, int64_t ld, int64_t n, int cols, void *work, uint32_t **sorted,
+                               hipStream_t s);
+hipError_t launch_w1_sorted(const uint32_t *ka, const uint32_t *kb, int64_t n, int cols, double *part, double *w1,
+                            hipStream_t s);
+int64_t w1_sorted_partial_words(int64_t n, int cols);
+hipError_t launch_keys_to_floats(const uint32_t *k, int64_t total, float *out, hipStream_t s);
+hipError_t launch_occupied_counts(int64_t rows, int L, int g, const float *img, float thr, float *cnt,
+                                  hipStream_t s);
 }  // namespace supa
 
 static thread_local std::string t_err;
@@ -175,7 +184,7 @@ extern "C" supa_status supa_surrogate_gate_fused(void *stream, int B, int K, int
                                                  int ldh, const uint16_t *w_t, int ldw, const float *bias,
                                                  const float *e0, float y_scale, float s_clamp, float *partial,
                                                  float *layer_e, float *unc, float rho, uint32_t row_base,
-                                                 uint64_t seed) {
+                                                 uint64_t seed, float cnt_thr, float *layer_cnt) {
     if (B < 0 || K < 8 || K % 8 || L < 1 || L > 64 || D < L || D % L || (D / L) % 128)
         return bad("bad fused gate sizes (K multiple of 8, L <= 64, bins per layer multiple of 128)");
     if (ldh < K || ldw < K || ldh % 8 || ldw % 8) return bad("bad leading dimensions");
@@ -183,8 +192,9 @@ extern "C" supa_status supa_surrogate_gate_fused(void *stream, int B, int K, int
     if (rho > 1.0f) return bad("rho must be <= 1 (negative: no sampling)");
     if (B == 0) return SUPA_OK;
     if (!h || !w_t || !bias || !e0 || !partial || !layer_e || !unc) return bad("NULL pointer");
+    if (layer_cnt && !(cnt_thr >= 0)) return bad("cnt_thr must be >= 0");
     return dev(supa::launch_gate_fused(B, K, D, L, h, ldh, w_t, ldw, bias, e0, y_scale, s_clamp, partial, layer_e,
-                                       unc, rho, row_base, seed, (hipStream_t)stream),
+                                       unc, rho, row_base, seed, cnt_thr, layer_cnt, (hipStream_t)stream),
                "gate_fused");
 }
 
@@ -215,4 +225,57 @@ extern "C" supa_status supa_scatter_rows(void *stream, int m, int w, const int32
 extern "C" supa_status supa_group_sums(void *stream, int rows, int L, int g, const float *x, float *out) {
     if (rows < 0 || L < 1 || g < 1 || (rows > 0 && (!x || !out))) return bad("bad group_sums arguments");
     return dev(supa::launch_group_sums(rows, L, g, x, out, (hipStream_t)stream), "group_sums");
+}
+
+// ---------------------------------------------------------------------------
+// the judge: exact W1 of equal-size samples, sorted columns, occupied cells
+// ---------------------------------------------------------------------------
+static constexpr int64_t kMaxSortRows = 1LL << 30;
+
+static size_t al256s(size_t b) { return (b + 255) & ~(size_t)255; }
+
+extern "C" int64_t supa_sort_columns_workspace_bytes(int64_t n, int32_t cols) {
+    if (n < 0 || n > kMaxSortRows || cols < 0 || cols > 4096) return -1;
+    return (int64_t)supa::sort_work_bytes(n, cols);
+}
+
+extern "C" supa_status supa_sort_columns(void *stream, int64_t n, int32_t cols, const float *x, int64_t ld,
+                                         float *out, void *work, int64_t work_bytes) {
+    if (n < 0 || n > kMaxSortRows || cols < 0 || cols > 4096) return bad("sort: n or cols out of range");
+    if (n == 0 || cols == 0) return SUPA_OK;
+    if (!x || !out || !work || ld < cols) return bad("sort: NULL array or ld < cols");
+    if (work_bytes < (int64_t)supa::sort_work_bytes(n, cols)) return bad("sort: workspace too small");
+    uint32_t *sorted = nullptr;
+    supa_status st = dev(supa::launch_sort_columns(x, ld, n, cols, work, &sorted, (hipStream_t)stream), "sort");
+    if (st != SUPA_OK) return st;
+    return dev(supa::launch_keys_to_floats(sorted, n * cols, out, (hipStream_t)stream), "sorted values");
+}
+
+extern "C" int64_t supa_w1_equal_workspace_bytes(int64_t n, int32_t cols) {
+    if (n < 0 || n > kMaxSortRows || cols < 0 || cols > 4096) return -1;
+    return (int64_t)(2 * al256s(supa::sort_work_bytes(n, cols)) +
+                     al256s((size_t)supa::w1_sorted_partial_words(n, cols) * 8));
+}
+
+extern "C" supa_status supa_w1_equal(void *stream, int64_t n, int32_t cols, const float *a, int64_t lda,
+                                     const float *b, int64_t ldb, double *w1, void *work, int64_t work_bytes) {
+    if (n < 1 || n > kMaxSortRows || cols < 1 || cols > 4096) return bad("w1: n or cols out of range");
+    if (!a || !b || !w1 || !work || lda < cols || ldb < cols) return bad("w1: NULL array or leading dimension < cols");
+    if (work_bytes < supa_w1_equal_workspace_bytes(n, cols)) return bad("w1: workspace too small");
+    const size_t sw = al256s(supa::sort_work_bytes(n, cols));
+    uint32_t *ka = nullptr, *kb = nullptr;
+    const hipStream_t s = (hipStream_t)stream;
+    supa_status st = dev(supa::launch_sort_columns(a, lda, n, cols, work, &ka, s), "w1 sort a");
+    if (st == SUPA_OK) st = dev(supa::launch_sort_columns(b, ldb, n, cols, (char *)work + sw, &kb, s), "w1 sort b");
+    if (st == SUPA_OK)
+        st = dev(supa::launch_w1_sorted(ka, kb, n, cols, (double *)((char *)work + 2 * sw), w1, s), "w1 sums");
+    return st;
+}
+
+extern "C" supa_status supa_occupied_counts(void *stream, int64_t rows, int32_t L, int32_t g, const float *img,
+                                            float thr, float *cnt) {
+    if (rows < 0 || L < 1 || g < 1) return bad("occupied counts: bad sizes");
+    if (rows == 0) return SUPA_OK;
+    if (!img || !cnt) return bad("occupied counts: NULL array");
+    return dev(supa::launch_occupied_counts(rows, L, g, img, thr, cnt, (hipStream_t)stream), "occupied counts");
 }

@@ -73,8 +73,8 @@ class Output(C.Structure):
 
 
 EXPORTS = ["supa_abi_version", "supa_validate_geometry", "supa_validate_call", "supa_init_geometry", "supa_destroy",
-           "supa_simulate", "supa_simulate_batches", "supa_simulate_noalloc", "supa_set_launch", "supa_set_schedule", "supa_autotune",
-           "supa_graph_create", "supa_graph_launch", "supa_graph_check", "supa_graph_destroy", "supa_last_timing", "supa_last_kernel_times", "supa_philox",
+           "supa_simulate", "supa_simulate_batches", "supa_simulate_noalloc", "supa_set_launch", "supa_set_schedule", "supa_autotune", "supa_autotune_forget",
+           "supa_graph_create", "supa_graph_launch", "supa_graph_check", "supa_graph_destroy", "supa_last_timing", "supa_last_kernel_times", "supa_last_wave_times", "supa_philox",
            "supa_last_error"]
 
 _lib = None
@@ -110,6 +110,8 @@ def load():
         L.supa_autotune.restype = C.c_int
         L.supa_autotune.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_uint64, C.POINTER(Output),
                                     C.POINTER(C.c_int32), C.POINTER(C.c_float)]
+        L.supa_autotune_forget.restype = C.c_int
+        L.supa_autotune_forget.argtypes = [C.c_void_p]
         L.supa_graph_create.restype = C.c_int
         L.supa_graph_create.argtypes = [C.c_void_p, C.POINTER(Batch), C.c_uint64, C.POINTER(Output),
                                         C.POINTER(C.c_void_p)]
@@ -123,6 +125,8 @@ def load():
         L.supa_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.supa_last_timing.restype = C.c_int
         L.supa_last_timing.argtypes = [C.c_void_p, C.POINTER(C.c_float)]
+        L.supa_last_wave_times.restype = C.c_int
+        L.supa_last_wave_times.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
         L.supa_last_kernel_times.restype = C.c_int
         L.supa_last_kernel_times.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int32]
         L.supa_philox.restype = C.c_int
@@ -245,6 +249,14 @@ class Simulator:
         ms = (C.c_float * 5)()
         self._check(self.lib.supa_last_kernel_times(self.ctx, ms, 5))
         return list(ms)
+
+    def wave_times(self):
+        """Per-wave busy time (ms) of the last propagation launch, as a list."""
+        cap = 32 * 1024
+        ms = (C.c_float * cap)()
+        count = C.c_int32()
+        self._check(self.lib.supa_last_wave_times(self.ctx, ms, cap, C.byref(count)))
+        return list(ms[:min(count.value, cap)])
 
     def allocate(self, n: int, hit_capacity: int = 0, node_capacity: int = 0) -> dict:
         """Output tensors for n showers with the given capacities."""
@@ -411,6 +423,10 @@ class Simulator:
         self._check(st)
         return {"waves_per_cu": best[0], "frontier_cap": best[1], "sub_batches": best[2],
                 "cost_order": best[3], "ms": round(ms.value, 4)}
+
+    def autotune_forget(self):
+        """Clears the launch settings supa_autotune keeps per batch size."""
+        self._check(self.lib.supa_autotune_forget(self.ctx))
 
     def graph(self, e0, polar, azimuth, seed: int, out: dict, x0=None, y0=None,
               shower_id_base: int = 0) -> "Graph":

@@ -45,15 +45,22 @@ def _lib():
             "supa_scatter_rows": [vp, i, i, vp, vp, vp],
             "supa_group_sums": [vp, i, i, i, vp, vp],
             "supa_surrogate_gate_fused": [vp, i, i, i, i, vp, i, vp, i, vp, vp, f, f, vp, vp, vp, f, u32,
-                                          u64],
+                                          u64, f, vp],
             "supa_transpose_to_bf16": [vp, i, i, vp, vp],
             "supa_gemm_bf16_splitk": [vp, i, i, i, i, i, vp, i, vp, i, vp, i, vp],
             "supa_gemm_splitk_parts": [i, i, i],
+            "supa_w1_equal": [vp, i64, C.c_int32, vp, i64, vp, i64, vp, vp, i64],
+            "supa_sort_columns": [vp, i64, C.c_int32, vp, i64, vp, vp, i64],
+            "supa_occupied_counts": [vp, i64, C.c_int32, C.c_int32, vp, f, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
             fn.restype = C.c_int
             fn.argtypes = args
+        for name in ("supa_w1_equal_workspace_bytes", "supa_sort_columns_workspace_bytes"):
+            fn = getattr(L, name)
+            fn.restype = C.c_int64
+            fn.argtypes = [i64, C.c_int32]
         L.supa_surrogate_last_error.restype = C.c_char_p
         L._surrogate_bound = True
     return L
@@ -144,19 +151,57 @@ def transpose_to_bf16(x: torch.Tensor) -> torch.Tensor:
     return y
 
 
-def gate_fused(h, w_t, bias, e0, n_layers, rho=-1.0, seed=0, row_base=0):
+def gate_fused(h, w_t, bias, e0, n_layers, rho=-1.0, seed=0, row_base=0, cnt_thr=None):
     """Final layer + gate in one pass (supa_surrogate_gate_fused): h bf16 [B, K]
-    last hidden activations, w_t bf16 [2D, K] the final weights transposed."""
+    last hidden activations, w_t bf16 [2D, K] the final weights transposed.
+    With cnt_thr, also the per-layer counts of bins predicted above it."""
     B, K = h.shape
     D = w_t.shape[0] // 2
     layer_e = torch.empty((B, n_layers), dtype=torch.float32, device=h.device)
     unc = torch.empty(B, dtype=torch.float32, device=h.device)
+    cnt = torch.empty((B, n_layers), dtype=torch.float32, device=h.device) if cnt_thr is not None else None
     partial = torch.empty((max(B, 1), (2 * D) // 128, 2), dtype=torch.float32, device=h.device)
     _check(_lib().supa_surrogate_gate_fused(_stream(), B, K, D, n_layers, _p(h), h.stride(0), _p(w_t),
                                             w_t.stride(0), _p(bias), _p(e0), Y_SCALE, S_CLAMP, _p(partial),
                                             _p(layer_e), _p(unc), float(rho), row_base & 0xFFFFFFFF,
-                                            seed & 0xFFFFFFFFFFFFFFFF))
-    return layer_e, unc
+                                            seed & 0xFFFFFFFFFFFFFFFF, float(cnt_thr or 0.0), _p(cnt)))
+    return (layer_e, unc) if cnt is None else (layer_e, unc, cnt)
+
+
+def w1_equal(a, b):
+    """Exact W1 between the columns of two equal-size float samples [n, cols]
+    (supa_w1_equal); returns a float64 tensor [cols] on the device."""
+    a, b = a.contiguous(), b.contiguous()
+    n, cols = a.shape
+    if b.shape != a.shape:
+        raise ValueError("samples of equal shape")
+    L = _lib()
+    wb = int(L.supa_w1_equal_workspace_bytes(n, cols))
+    work = torch.empty(max(wb, 1), dtype=torch.uint8, device=a.device)
+    w1 = torch.empty(cols, dtype=torch.float64, device=a.device)
+    _check(L.supa_w1_equal(_stream(), n, cols, _p(a), a.stride(0), _p(b), b.stride(0), _p(w1), _p(work), wb))
+    return w1
+
+
+def sort_columns(x):
+    """Columns of a float [n, cols] tensor sorted (supa_sort_columns): [cols, n]."""
+    x = x.contiguous()
+    n, cols = x.shape
+    L = _lib()
+    wb = int(L.supa_sort_columns_workspace_bytes(n, cols))
+    work = torch.empty(max(wb, 1), dtype=torch.uint8, device=x.device)
+    out = torch.empty((cols, n), dtype=torch.float32, device=x.device)
+    _check(L.supa_sort_columns(_stream(), n, cols, _p(x), x.stride(0), _p(out), _p(work), wb))
+    return out
+
+
+def occupied_counts(img, n_layers, thr):
+    """Per row and layer, the cells of a flattened [rows, L * g] image above thr."""
+    rows, width = img.shape
+    cnt = torch.empty((rows, n_layers), dtype=torch.float32, device=img.device)
+    _check(_lib().supa_occupied_counts(_stream(), rows, n_layers, width // n_layers, _p(img.contiguous()),
+                                       float(thr), _p(cnt)))
+    return cnt
 
 
 def select_above(v, tau):
@@ -268,11 +313,12 @@ class MLP:
             self._wt_step = self.step
         return self._wt
 
-    def layer_energies(self, x, e0, n_layers, rho=-1.0, seed=0, row_base=0):
-        """Per-layer energies and uncertainty scores of the inputs x, with the
-        final layer fused into the gate (no [B, 2D] output)."""
+    def layer_energies(self, x, e0, n_layers, rho=-1.0, seed=0, row_base=0, cnt_thr=None):
+        """Per-layer energies and uncertainty scores of the inputs x (and, with
+        cnt_thr, per-layer counts of bins predicted above it), with the final
+        layer fused into the gate (no [B, 2D] output)."""
         return gate_fused(self.hidden(x), self.final_weights_t(), self.b[-1], e0, n_layers, rho=rho,
-                          seed=seed, row_base=row_base)
+                          seed=seed, row_base=row_base, cnt_thr=cnt_thr)
 
     def backward(self, acts, pres, dout):
         """dout: bf16 [B, out] = d loss / d out; returns float32 (dW, db) lists."""

@@ -19,6 +19,9 @@ N_LAYERS = 20
 GRID = 16
 BINS = GRID * GRID
 D = N_LAYERS * BINS
+# a cell counts as occupied above a tenth of the energy threshold (the
+# images have no hit counts, so the judge counts occupied cells instead)
+OCC_THR = 0.01
 
 
 def geometry():
@@ -72,46 +75,61 @@ def train(model: S.MLP, steps: int, batch: int, seed: int = 100, lr: float = 1e-
     return losses, time.perf_counter() - t0
 
 
-def surrogate_layer_energies(model: S.MLP, e0, pol, az, seed, chunk=65536, row_base=0, rho=-1.0):
+def surrogate_layer_energies(model: S.MLP, e0, pol, az, seed, chunk=65536, row_base=0, rho=-1.0,
+                             counts=False):
     """Predicted per-layer energies (sampled when rho >= 0) and uncertainty
-    scores, in chunks."""
+    scores, in chunks; with counts, also the predicted occupied cells per
+    layer (bins whose predicted energy exceeds OCC_THR)."""
     n = int(e0.shape[0])
     layer_e = torch.empty((n, N_LAYERS), dtype=torch.float32, device=e0.device)
     unc = torch.empty(n, dtype=torch.float32, device=e0.device)
+    cnt = torch.empty((n, N_LAYERS), dtype=torch.float32, device=e0.device) if counts else None
     for s in range(0, n, chunk):
         sl = slice(s, min(n, s + chunk))
         x = S.features(e0[sl], pol[sl], az[sl], seed, row_base=row_base + s, stream_id=2)
-        le, u = model.layer_energies(x, e0[sl], N_LAYERS, rho=rho, seed=seed, row_base=row_base + s)
-        layer_e[sl] = le
-        unc[sl] = u
-    return layer_e, unc
+        r = model.layer_energies(x, e0[sl], N_LAYERS, rho=rho, seed=seed, row_base=row_base + s,
+                                 cnt_thr=OCC_THR if counts else None)
+        layer_e[sl] = r[0]
+        unc[sl] = r[1]
+        if counts:
+            cnt[sl] = r[2]
+    return (layer_e, unc, cnt) if counts else (layer_e, unc)
 
 
 def surrogate_with_fallback(model: S.MLP, e0, pol, az, seed, tau, sim: ImageSimulator,
                             chunk=65536, rho=-1.0):
-    """Per-layer energies: the surrogate's, replaced by the simulator's for
-    every shower whose uncertainty exceeds tau.  Returns (layer_e, n_fallback)."""
-    layer_e, unc = surrogate_layer_energies(model, e0, pol, az, seed, chunk, rho=rho)
+    """Per-layer energies and occupied-cell counts: the surrogate's, replaced
+    by the simulator's for every shower whose uncertainty exceeds tau.
+    Returns (layer_e, layer_counts, n_fallback)."""
+    layer_e, unc, cnt = surrogate_layer_energies(model, e0, pol, az, seed, chunk, rho=rho, counts=True)
     idx = S.select_above(unc, tau)
     m = int(idx.shape[0])
     if m:
         fe, fp, fa = S.gather3(idx, e0, pol, az)
         img, _ = sim.images(fe, fp, fa, seed, shower_id_base=0x40000000)
         S.scatter_rows(idx, S.group_sums(img, N_LAYERS), layer_e)
-    return layer_e, m
+        S.scatter_rows(idx, S.occupied_counts(img, N_LAYERS, OCC_THR), cnt)
+    return layer_e, cnt, m
 
 
-def simulated_layer_energies(e0, pol, az, seed, sim: ImageSimulator, shower_id_base=0):
+def simulated_layer_energies(e0, pol, az, seed, sim: ImageSimulator, shower_id_base=0, counts=False):
+    """The simulator's per-layer energies (and, with counts, occupied cells)."""
     img, _ = sim.images(e0, pol, az, seed, shower_id_base=shower_id_base)
-    return S.group_sums(img, N_LAYERS)
+    le = S.group_sums(img, N_LAYERS)
+    return (le, S.occupied_counts(img, N_LAYERS, OCC_THR)) if counts else le
 
 
-def w1_per_layer(a: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """Per-layer 1-D Wasserstein-1 distances of two samples of equal size:
-    mean |a_(i) - b_(i)| of the sorted columns (evaluation, on the host)."""
-    a = np.sort(a, axis=0)
-    b = np.sort(b, axis=0)
-    return np.abs(a - b).mean(axis=0)
+def judge(le, cnt, ref_le, ref_cnt):
+    """The W1 judge on the GPU (supa_w1_equal): per layer, the exact W1 of
+    the energies and of the occupied-cell counts against the simulator's on
+    the same initial conditions, each relative to the simulator's mean per
+    layer (averaged over layers).  Returns (max over layers of the relative
+    energy W1, the same for counts, per-layer energy W1, per-layer count W1)."""
+    we = S.w1_equal(le, ref_le).cpu().numpy()
+    wc = S.w1_equal(cnt, ref_cnt).cpu().numpy()
+    mean_e = float(ref_le.double().mean(dim=0).mean())
+    mean_c = float(ref_cnt.double().mean(dim=0).mean())
+    return float(we.max() / mean_e), float(wc.max() / mean_c), we, wc
 
 
 def calibrate_rho(model: S.MLP, sim: ImageSimulator, n: int, seed: int, device="cuda"):

@@ -205,3 +205,26 @@ def test_binding_refuses_wrong_dtypes_and_short_outputs():
     with pytest.raises(ValueError, match="images"):
         sim._check_output_sizes(o, n)
     assert sim._shower_capacity(o) == n - 1
+
+
+def test_judge_entry_points_reject_bad_arguments_on_the_host():
+    import ctypes as C
+    from paper_2202_05012_amd import surrogate as S
+    L = S._lib()
+    fake = C.c_void_p(4096)                       # never dereferenced: rejected first
+    assert L.supa_w1_equal_workspace_bytes(-1, 3) == -1
+    assert L.supa_w1_equal_workspace_bytes(10, 5000) == -1
+    need = L.supa_w1_equal_workspace_bytes(1000, 20)
+    assert need >= 2 * 2 * 1000 * 20 * 4
+    args = lambda **kw: [kw.get(k, d) for k, d in (
+        ("s", None), ("n", 1000), ("cols", 20), ("a", fake), ("lda", 20), ("b", fake), ("ldb", 20),
+        ("w1", fake), ("work", fake), ("wb", need))]
+    assert L.supa_w1_equal(*args(n=0)) == 1
+    assert L.supa_w1_equal(*args(cols=0)) == 1
+    assert L.supa_w1_equal(*args(lda=19)) == 1
+    assert L.supa_w1_equal(*args(wb=need - 1)) == 1
+    assert "workspace" in L.supa_surrogate_last_error().decode()
+    assert L.supa_w1_equal(*args(b=None)) == 1
+    assert L.supa_sort_columns(None, 100, 3, fake, 2, fake, fake, 1 << 20) == 1       # ld < cols
+    assert L.supa_sort_columns(None, 0, 3, fake, 3, fake, fake, 0) == 0              # empty: nothing to do
+    assert L.supa_occupied_counts(None, 10, 0, 16, fake, 0.1, fake) == 1

@@ -350,6 +350,25 @@ def test_autotune_keeps_results():
     assert best["sub_batches"] in (1, 2) and best["cost_order"] in (0, 1) and best["ms"] > 0
     torch.cuda.synchronize()
     parity.check_all(parity.to_numpy(out), ref, geom, tree=True)
+    # the choice is kept per batch size: a second search is one call
+    import time
+    for v in out.values():
+        if isinstance(v, torch.Tensor):
+            v.fill_(-7)
+    t0 = time.perf_counter()
+    again = sim.autotune(dev_t(e0), dev_t(pol), dev_t(az), w.seed, out)
+    torch.cuda.synchronize()
+    assert again == best
+    parity.check_all(parity.to_numpy(out), ref, geom, tree=True)
+    # per-wave busy times of that call's propagation launch
+    wt = np.array(sim.wave_times())
+    assert len(wt) == 256 * best["waves_per_cu"] and (wt >= 0).all() and wt.max() > 0
+    assert wt.max() <= 1e3 * (time.perf_counter() - t0)
+    sim.autotune_forget()
+    e1, p1, a1 = e0[:200], pol[:200], az[:200]
+    small = sim.allocate(200, len(ref["hit_e"]), len(ref["node_e"]))
+    other = sim.autotune(dev_t(e1), dev_t(p1), dev_t(a1), w.seed, small)      # a new search
+    assert other["ms"] > 0
 
 
 def test_graph_replays_match_oracle():
@@ -488,6 +507,20 @@ def test_rings_parity(trial):
         one = O.simulate(geom, e0[i:i + 1], pol[i:i + 1], az[i:i + 1], seed, x0=x0[i:i + 1],
                          y0=y0[i:i + 1], shower_id_base=base + int(i))
         parity.check_all(gpu, one, geom, images=True, tree=True, rows=[int(i)])
+    # showers with a choice within 1e-4 of a ring radius: where both sides
+    # took the same rings (the usual case) they agree exactly; a shower that
+    # differs must still be a valid tree with an exact ledger
+    agree = 0
+    near = np.nonzero(ref["region_margin"] <= 1e-4)[0]
+    for i in near:
+        one = O.simulate(geom, e0[i:i + 1], pol[i:i + 1], az[i:i + 1], seed, x0=x0[i:i + 1],
+                         y0=y0[i:i + 1], shower_id_base=base + int(i))
+        try:
+            parity.check_all(gpu, one, geom, images=True, tree=True, rows=[int(i)])
+            agree += 1
+        except AssertionError:
+            parity.check_valid_shower(gpu, int(i))
+    assert agree >= 0.5 * len(near), (agree, len(near))
     # the rings matter: a one-region run with ring 0's parameters differs
     flat = dict(geom, n_regions=0, region_r=None, p_stop=list(ps[:N]), p_split=geom["p_split"][:N])
     ref0 = O.simulate(flat, e0, pol, az, seed, x0=x0, y0=y0, shower_id_base=base)
@@ -741,3 +774,17 @@ def test_batches_share_records_and_images():
     bad = [outs[0], dict(outs[1], counts=outs[0]["counts"])]
     with pytest.raises(supa.SupaError, match="share ledger or counts"):
         sim.run_batches(te0, tpol, taz, w.seed, calls[:2], bad)
+
+
+def test_zz_coordinate_errors_meet_the_component_bar():
+    """The coordinates compared by this file's earlier tests (every geometry
+    but the grazing stress, where flight nearly parallel to the planes is
+    ill-conditioned): the largest error relative to max(|component|, 1) stays
+    within 1e-5, the scope table's bar, although the tests assert the bar
+    scaled by the distance from the beam axis."""
+    st = parity.COORD_STATS
+    if st["points"] == 0:
+        pytest.skip("no coordinates compared in this process (run with the other parity tests)")
+    print(f"coordinates compared: {st['points']}, largest error / max(|x|, 1): "
+          f"{st['max_rel_component']:.3g}, / max(r, 1): {st['max_rel_r']:.3g}", flush=True)
+    assert st["max_rel_component"] <= 1e-5, st

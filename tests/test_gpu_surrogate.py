@@ -366,8 +366,9 @@ def test_gate_fused_matches_oracle_at_workload_shapes(rho):
     hf, Wf = bf16_to_np(h).astype(np.float64), bf16_to_np(Wb).astype(np.float64)
     o = hf @ Wf + bias
     wt = S.transpose_to_bf16(torch.from_numpy(W).cuda())
-    le, unc = S.gate_fused(dev16(h), wt, torch.from_numpy(bias).cuda(), torch.from_numpy(e0).cuda(), L,
-                           rho=rho, seed=5, row_base=3)
+    thr = 1e-4                                      # energy of an occupied bin
+    le, unc, cnt = S.gate_fused(dev16(h), wt, torch.from_numpy(bias).cuda(), torch.from_numpy(e0).cuda(), L,
+                                rho=rho, seed=5, row_base=3, cnt_thr=thr)
     ref_le, ref_unc = SO.gate(o, e0, L, S.Y_SCALE, S.S_CLAMP, rho, 5, 3)
     acc = 2e-6 * (np.abs(hf) @ np.abs(Wf))
     scale = e0.astype(np.float64)[:, None] / S.Y_SCALE
@@ -378,6 +379,14 @@ def test_gate_fused_matches_oracle_at_workload_shapes(rho):
     err = np.abs(le.cpu().numpy() - ref_le)
     assert (err <= tol).all(), float((err / tol).max())
     np.testing.assert_allclose(unc.cpu().numpy(), ref_unc, rtol=3e-4)
+    # occupied bins: exact except bins whose energy lies within the product's
+    # float error of the threshold, which may count on either side
+    e_bin = o[:, :D] * (e0.astype(np.float64)[:, None] / S.Y_SCALE)
+    ref_cnt = SO.occupied(e_bin, L, thr)
+    near = np.abs(e_bin - thr) <= (acc[:, :D] + 1e-6 * np.abs(o[:, :D])) * (e0.astype(np.float64)[:, None] / S.Y_SCALE)
+    slack = near.reshape(B, L, -1).sum(axis=2)
+    assert (np.abs(cnt.cpu().numpy() - ref_cnt) <= slack).all()
+    assert 0 < ref_cnt.mean() < bins                 # the threshold splits the bins
 
 
 @pytest.mark.slow
@@ -460,3 +469,52 @@ def test_network_at_workload_shapes_vs_oracle():
         e_w = rel_fro(dWs[l].cpu().numpy(), ref_g[l][0])
         e_b = rel_fro(dbs[l].cpu().numpy(), ref_g[l][1])
         assert e_w <= 1e-2 and e_b <= 1e-2, (l, e_w, e_b)
+
+
+# ---------------------------------------------------------------------------
+# the judge: sorted columns, exact W1 of equal-size samples, occupied cells
+# ---------------------------------------------------------------------------
+def test_sort_columns_matches_numpy():
+    """Columns sorted on the device equal numpy's sort bit for bit: negative
+    and positive values, zeros of both signs, ties, infinities, a ragged row
+    count over several tiles, a leading dimension wider than the columns."""
+    rng = np.random.default_rng(71)
+    n, cols, ld = 10_007, 7, 9
+    x = np.zeros((n, ld), np.float32)
+    x[:, :cols] = rng.normal(scale=50, size=(n, cols))
+    x[::13, 0] = 0.0
+    x[::17, 1] = -0.0
+    x[::5, 2] = np.round(x[::5, 2])                 # ties
+    x[:3, 3] = [np.inf, -np.inf, 1e-40]             # infinities and a subnormal
+    x[:, 4] = rng.integers(0, 4, n)                 # few distinct values
+    got = S.sort_columns(torch.from_numpy(x).cuda()[:, :cols]).cpu().numpy()
+    want = np.sort(x[:, :cols], axis=0).T
+    assert np.array_equal(got.view(np.uint32) & 0x7FFFFFFF, want.view(np.uint32) & 0x7FFFFFFF)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("n", [1, 4095, 4096, 300_001])
+def test_w1_equal_matches_oracle(n):
+    """W1 of each column pair against the oracle's (pinned to scipy), for
+    row counts around the tile size and over many tiles: the order
+    statistics are exact, the sums are double (bar 1e-12 relative)."""
+    rng = np.random.default_rng(n)
+    cols = 5
+    a = rng.normal(size=(n, cols)).astype(np.float32) * np.array([1, 10, 100, 0.01, 3], np.float32)
+    b = (rng.normal(size=(n, cols)) * 1.3 + 0.2).astype(np.float32)
+    a[:, 4] = rng.integers(0, 20, n)                # integer counts, many ties
+    b[:, 4] = rng.integers(0, 22, n)
+    got = S.w1_equal(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()).cpu().numpy()
+    want = np.array([SO.w1(a[:, c].astype(np.float64), b[:, c].astype(np.float64)) for c in range(cols)])
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-300)
+    same = S.w1_equal(torch.from_numpy(a).cuda(), torch.from_numpy(a).cuda()).cpu().numpy()
+    assert (same == 0).all()
+
+
+def test_occupied_counts():
+    rng = np.random.default_rng(72)
+    rows, L, g = 513, 20, 256
+    img = (rng.exponential(0.01, size=(rows, L * g)) * (rng.uniform(size=(rows, L * g)) < 0.3)).astype(np.float32)
+    got = S.occupied_counts(torch.from_numpy(img).cuda(), L, 0.01).cpu().numpy()
+    want = (img.reshape(rows, L, g) > np.float32(0.01)).sum(axis=2)
+    np.testing.assert_array_equal(got, want)

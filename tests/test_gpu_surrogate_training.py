@@ -3,15 +3,17 @@
 Trains on showers the simulator generates (online, 10 million), then checks
 on held-out initial conditions that (1) the loss went down, (2) the
 surrogate's mean per-layer energies track the simulator's (each layer within
-5% of the mean per-layer energy), (3) the gate ranks showers usefully: W1
-falls as the fallback fraction grows, and (4) surrogate + fallback reaches
-W1 <= 2% of the mean per-layer energy with part of the showers (not all)
-simulated.
+5% of the mean per-layer energy), (3) the gate ranks showers usefully: W1 of
+the per-layer energies and of the per-layer occupied-cell counts (the judge,
+on the GPU, checked against the oracle's W1 once) falls as the fallback
+fraction grows, and (4) surrogate + fallback reaches W1 <= 2% of the mean
+per-layer energy with part of the showers (not all) simulated.
 """
 import numpy as np
 import pytest
 import torch
 
+from oracle import surrogate_oracle as SO
 from paper_2202_05012_amd import surrogate as S, surrogate_pipeline as SP
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
@@ -26,20 +28,26 @@ def test_training_gain_over_plain_simulator():
     rho = SP.calibrate_rho(model, sim, 4096, seed=11)
     n = 65536
     e0, pol, az = SP.draw_ics(n, 4242, dev)
-    ref = SP.simulated_layer_energies(e0, pol, az, 3, sim).cpu().numpy()
+    ref_t, ref_cnt = SP.simulated_layer_energies(e0, pol, az, 3, sim, counts=True)
+    ref = ref_t.cpu().numpy()
     mean_layer = ref.mean(axis=0).mean()
     sur, unc = SP.surrogate_layer_energies(model, e0, pol, az, 5)
     # mean per-layer energy profile: every layer within 5% of the mean layer energy
     prof_s, prof_r = sur.cpu().numpy().mean(axis=0), ref.mean(axis=0)
     assert (np.abs(prof_s - prof_r) <= 0.05 * mean_layer).all(), (prof_s, prof_r)
     unc_h = unc.cpu().numpy()
-    ws, reached = [], None
+    ws, wcs, reached = [], [], None
     for frac in (0.0, 0.5, 0.8, 0.95):
         tau = float(np.quantile(unc_h, 1 - frac)) if frac > 0 else np.inf
-        le, m = SP.surrogate_with_fallback(model, e0, pol, az, 5, tau, sim, rho=rho)
-        w = SP.w1_per_layer(le.cpu().numpy(), ref).max() / mean_layer
+        le, cnt, m = SP.surrogate_with_fallback(model, e0, pol, az, 5, tau, sim, rho=rho)
+        w, wc, we, _ = SP.judge(le, cnt, ref_t, ref_cnt)
+        if frac == 0.5:
+            # the judge on the GPU against the oracle's W1 on the host
+            want = np.array([SO.w1(le.cpu().numpy()[:, l], ref[:, l]) for l in range(SP.N_LAYERS)])
+            np.testing.assert_allclose(we, want, rtol=1e-9)
         ws.append(w)
+        wcs.append(wc)
         if w <= 0.02 and reached is None:
             reached = (frac, m / n, w)
-    assert ws[-1] < ws[0], ws
+    assert ws[-1] < ws[0] and wcs[-1] < wcs[0], (ws, wcs)
     assert reached is not None and reached[1] < 1.0, (reached, ws)

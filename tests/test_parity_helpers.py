@@ -76,3 +76,18 @@ def test_unkeyed_comparisons_accept_the_oracle_and_catch_changes(fifty_plane):
     bad["node_parent"][[i, j]] = bad["node_parent"][i] - 1
     with pytest.raises(AssertionError):
         parity.check_tree(parity.with_tree_keys(bad), ref)
+
+
+def test_valid_shower_check_accepts_the_oracle_and_catches_changes(fifty_plane):
+    gpu = oracle_as_gpu(fifty_plane, np.random.default_rng(5))
+    for i in range(fifty_plane["n"]):
+        parity.check_valid_shower(gpu, i)
+    bad = dict(gpu, ledger=gpu["ledger"].copy())
+    bad["ledger"][3, 2] += np.uint64(1)
+    with pytest.raises(AssertionError):
+        parity.check_valid_shower(bad, 3)
+    bad = dict(gpu, node_e=gpu["node_e"].copy())
+    o = int(gpu["node_offsets"][4])
+    bad["node_e"][o + 1] *= np.float32(1.01)
+    with pytest.raises(AssertionError):
+        parity.check_valid_shower(bad, 4)

@@ -199,3 +199,10 @@ def test_sampled_layer_energy_is_the_sum_of_correlated_bins(rho):
     # layers of a row draw independent normals
     z = (le - mu.reshape(L, bins).sum(axis=1) * 0.5)
     assert np.abs(np.corrcoef(z.T) - np.eye(L)).max() < 0.03
+
+
+def test_occupied_cells_by_hand():
+    img = np.array([[0.0, 0.2, 0.01, 0.5, 0.011, 0.0],
+                    [1.0, 1.0, 1.0, 0.0, 0.0, 0.009]])
+    np.testing.assert_array_equal(S.occupied(img, 2, 0.01), [[1, 2], [3, 0]])
+    np.testing.assert_array_equal(S.occupied(img, 1, 0.0), [[4], [4]])
