@@ -575,9 +575,45 @@ hipError_t launch_features(int B, int ld, int n_noise, const float *e0, const fl
     return hipGetLastError();
 }
 
+// The gate of an output with one bin per layer (a per-layer head: [mean of
+// each layer | log-variance of each layer]): one thread per shower, the same
+// quantities as gate_kernel (with one bin the layer's sd is its sigma for
+// every rho, and the same Philox counters give z).
+__global__ void gate_rows_kernel(int B, int L, const float *out, const float *e0, float y_scale, float s_clamp,
+                                 float *layer_e, float *unc, float rho, uint32_t row_base, uint32_t k0,
+                                 uint32_t k1) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const float *row = out + (int64_t)b * 2 * L;
+    const float scale = e0[b] / y_scale;
+    float tm = 0.f, tv = 0.f;
+    for (int l = 0; l < L; ++l) {
+        const float mu = row[l];
+        const float sv = fminf(fmaxf(row[L + l], -s_clamp), s_clamp);
+        float v = mu;
+        if (rho >= 0.0f) {
+            const uint4 w = philox4x32_10(row_base + (uint32_t)b, (uint32_t)l, 0x9a7eu, 0u, k0, k1);
+            const float u1 = ((float)w.x + 0.5f) * 0x1p-32f, u2 = ((float)w.y + 0.5f) * 0x1p-32f;
+            float sn, cs;
+            sincospif(2.0f * u2, &sn, &cs);
+            const float z = sqrtf(-2.0f * logf(u1)) * cs;
+            v += __expf(0.5f * sv) * z;
+        }
+        layer_e[(int64_t)b * L + l] = v * scale;
+        tm += mu;
+        tv += __expf(sv);
+    }
+    unc[b] = sqrtf(tv) / fmaxf(tm, 1e-6f);
+}
+
 hipError_t launch_gate(int B, int D, int L, const float *out, const float *e0, float y_scale,
                        float s_clamp, float *layer_e, float *unc, float *img, float rho,
                        uint32_t row_base, uint64_t seed, hipStream_t s) {
+    if (D == L && !img) {
+        hipLaunchKernelGGL(gate_rows_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, B, L, out, e0,
+                           y_scale, s_clamp, layer_e, unc, rho, row_base, (uint32_t)seed, (uint32_t)(seed >> 32));
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(gate_kernel, dim3(B), dim3(256), 0, s, B, D, L, out, e0, y_scale, s_clamp,
                        layer_e, unc, img, rho, row_base, (uint32_t)seed, (uint32_t)(seed >> 32));
     return hipGetLastError();

@@ -128,7 +128,7 @@ def features(e0, polar, az, seed, row_base=0, stream_id=0):
     return x
 
 
-def gate(out, e0, n_layers, want_image=False, rho=-1.0, seed=0, row_base=0):
+def gate(out, e0, n_layers, want_image=False, rho=-1.0, seed=0, row_base=0, y_scale=None):
     """Per-layer energies (means, or samples when rho >= 0), uncertainty
     scores and optionally the predicted images; see supa_surrogate.h."""
     B, D2 = out.shape
@@ -136,7 +136,8 @@ def gate(out, e0, n_layers, want_image=False, rho=-1.0, seed=0, row_base=0):
     layer_e = torch.empty((B, n_layers), dtype=torch.float32, device=out.device)
     unc = torch.empty(B, dtype=torch.float32, device=out.device)
     img = torch.empty((B, D), dtype=torch.float32, device=out.device) if want_image else None
-    _check(_lib().supa_surrogate_gate(_stream(), B, D, n_layers, _p(out), _p(e0), Y_SCALE, S_CLAMP,
+    ys = Y_SCALE if y_scale is None else y_scale
+    _check(_lib().supa_surrogate_gate(_stream(), B, D, n_layers, _p(out), _p(e0), ys, S_CLAMP,
                                       _p(layer_e), _p(unc), _p(img), float(rho),
                                       row_base & 0xFFFFFFFF, seed & 0xFFFFFFFFFFFFFFFF))
     return layer_e, unc, img
@@ -350,17 +351,18 @@ class MLP:
             _check(L.supa_adam(_stream(), self.b[l].numel(), _p(self.b[l]), _p(dbs[l]),
                                _p(self.mb[l]), _p(self.vb[l]), None, lr, b1, b2, eps, self.step))
 
-    def train_step(self, x, img, e0, lr=1e-3, s_clamp=None, mse_mean=True):
-        """One step on targets Y_SCALE * img / e0 (img float [B, D]); returns
-        the mean NLL.  Means are fitted by squared error (mse_mean) or by the
-        NLL, log-variances by the NLL; s_clamp = 0 holds the log-variances
-        at 0."""
+    def train_step(self, x, img, e0, lr=1e-3, s_clamp=None, mse_mean=True, y_scale=None):
+        """One step on targets y_scale * img / e0 (img float [B, D]; default
+        scale Y_SCALE); returns the mean NLL.  Means are fitted by squared
+        error (mse_mean) or by the NLL, log-variances by the NLL; s_clamp = 0
+        holds the log-variances at 0."""
         out, acts, pres = self.forward(x, keep=True)
         B, D2 = out.shape
         dout = torch.empty((B, D2), dtype=torch.int16, device=self.device)
         loss = torch.zeros(1, dtype=torch.float32, device=self.device)
         sc = S_CLAMP if s_clamp is None else s_clamp
-        _check(_lib().supa_nll_grad(_stream(), B, D2 // 2, _p(out), _p(img), _p(e0), Y_SCALE,
+        ys = Y_SCALE if y_scale is None else y_scale
+        _check(_lib().supa_nll_grad(_stream(), B, D2 // 2, _p(out), _p(img), _p(e0), ys,
                                     sc, 1 if mse_mean else 0, _p(dout), _p(loss)))
         dWs, dbs = self.backward(acts, pres, dout)
         self.adam(dWs, dbs, lr=lr)

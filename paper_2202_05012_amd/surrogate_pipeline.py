@@ -22,11 +22,20 @@ D = N_LAYERS * BINS
 # a cell counts as occupied above a tenth of the energy threshold (the
 # images have no hit counts, so the judge counts occupied cells instead)
 OCC_THR = 0.01
+# the per-layer head's targets: y_scale * (layer energy) / E0, of order one
+# (a layer holds about 1/20 of E0)
+Y_SCALE_HEAD = 20.0
 
 
-def geometry():
+def layer_head_dims():
+    """The per-layer head: the image model's inputs and hidden layers, with the
+    mean and log-variance of each of the 20 per-layer energies as outputs."""
+    return [S.IN_PAD, 256, 256, 256, 256, 2 * N_LAYERS]
+
+
+def geometry(grid=GRID):
     w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
-    return workloads.geometry(w, img_nx=GRID, img_ny=GRID, img_x0=-5.0, img_x1=5.0,
+    return workloads.geometry(w, img_nx=grid, img_ny=grid, img_x0=-5.0, img_x1=5.0,
                               img_y0=-5.0, img_y1=5.0)
 
 
@@ -39,28 +48,33 @@ def draw_ics(n, seed, device):
 
 
 class ImageSimulator:
-    """supa_simulate producing only 16x16 per-layer images (no hit arrays)."""
+    """supa_simulate producing only per-layer images (no hit arrays): 16x16
+    cells by default; with grid=1 one cell per layer over the same window,
+    i.e. the per-layer energies alone."""
 
-    def __init__(self, device=0):
-        self.sim = supa.Simulator(geometry(), supa.OUT_IMAGES, device=device)
+    def __init__(self, device=0, grid=GRID):
+        self.sim = supa.Simulator(geometry(grid), supa.OUT_IMAGES, device=device)
+        self.d = N_LAYERS * grid * grid
 
     def images(self, e0, pol, az, seed, shower_id_base=0):
         n = int(e0.shape[0])
         out = self.sim.allocate(n)
         st = self.sim.run(e0, pol, az, seed, out, shower_id_base=shower_id_base)
         assert st == 0
-        return out["images"].view(n, D), out
+        return out["images"].view(n, self.d), out
 
 
-def train(model: S.MLP, steps: int, batch: int, seed: int = 100, lr: float = 1e-3,
+def train(model: S.MLP | None, steps: int, batch: int, seed: int = 100, lr: float = 1e-3,
           log_every: int = 0, sim: ImageSimulator | None = None, device="cuda",
-          mean_first: float = 0.0):
+          mean_first: float = 0.0, head: S.MLP | None = None):
     """Online training: every step simulates a fresh batch (shower ids never
     repeat) and takes one Adam step on the Gaussian NLL; the first
     `mean_first` fraction of the steps fit the means only (log-variance held
-    at 0, i.e. squared error)."""
+    at 0, i.e. squared error).  With `head`, the per-layer head takes a step
+    on the same batch, its targets the images' per-layer sums.  Returns the
+    image model's loss curve (and the head's) and the seconds taken."""
     sim = sim or ImageSimulator()
-    losses = []
+    losses, head_losses = [], []
     t0 = time.perf_counter()
     for step in range(steps):
         e0, pol, az = draw_ics(batch, seed + 1000003 * (step + 1), device)
@@ -68,10 +82,18 @@ def train(model: S.MLP, steps: int, batch: int, seed: int = 100, lr: float = 1e-
         x = S.features(e0, pol, az, seed, row_base=step * batch, stream_id=1)
         cur_lr = lr * (0.5 * (1 + math.cos(math.pi * step / max(steps, 1))) * 0.9 + 0.1)
         loss = model.train_step(x, img, e0, lr=cur_lr,
-                                s_clamp=0.0 if step < mean_first * steps else None)
+                                s_clamp=0.0 if step < mean_first * steps else None) \
+            if model is not None else None
+        hloss = head.train_step(x, S.group_sums(img, N_LAYERS), e0, lr=cur_lr, y_scale=Y_SCALE_HEAD) \
+            if head is not None else None
         if log_every and (step % log_every == 0 or step == steps - 1):
-            losses.append((step, float(loss.item())))
+            if model is not None:
+                losses.append((step, float(loss.item())))
+            if head is not None:
+                head_losses.append((step, float(hloss.item())))
     torch.cuda.synchronize()
+    if head is not None:
+        return losses, head_losses, time.perf_counter() - t0
     return losses, time.perf_counter() - t0
 
 
@@ -94,6 +116,37 @@ def surrogate_layer_energies(model: S.MLP, e0, pol, az, seed, chunk=65536, row_b
         if counts:
             cnt[sl] = r[2]
     return (layer_e, unc, cnt) if counts else (layer_e, unc)
+
+
+def head_layer_energies(head: S.MLP, e0, pol, az, seed, chunk=1 << 20, row_base=0):
+    """Per-layer energies sampled from the per-layer head (mean + sigma z per
+    layer) and its uncertainty score sqrt(sum of layer variances) / (sum of
+    layer means), in chunks."""
+    n = int(e0.shape[0])
+    layer_e = torch.empty((n, N_LAYERS), dtype=torch.float32, device=e0.device)
+    unc = torch.empty(n, dtype=torch.float32, device=e0.device)
+    for s in range(0, n, chunk):
+        sl = slice(s, min(n, s + chunk))
+        x = S.features(e0[sl], pol[sl], az[sl], seed, row_base=row_base + s, stream_id=2)
+        le, u, _ = S.gate(head.forward(x), e0[sl], N_LAYERS, rho=0.0, seed=seed, row_base=row_base + s,
+                          y_scale=Y_SCALE_HEAD)
+        layer_e[sl] = le
+        unc[sl] = u
+    return layer_e, unc
+
+
+def head_with_fallback(head: S.MLP, e0, pol, az, seed, tau, sim: ImageSimulator):
+    """Per-layer energies from the per-layer head, replaced by the
+    simulator's (sim: a one-cell-per-layer ImageSimulator) for every shower
+    whose uncertainty exceeds tau.  Returns (layer_e, n_fallback)."""
+    layer_e, unc = head_layer_energies(head, e0, pol, az, seed)
+    idx = S.select_above(unc, tau)
+    m = int(idx.shape[0])
+    if m:
+        fe, fp, fa = S.gather3(idx, e0, pol, az)
+        img, _ = sim.images(fe, fp, fa, seed, shower_id_base=0x40000000)
+        S.scatter_rows(idx, S.group_sums(img, N_LAYERS), layer_e)
+    return layer_e, m
 
 
 def surrogate_with_fallback(model: S.MLP, e0, pol, az, seed, tau, sim: ImageSimulator,

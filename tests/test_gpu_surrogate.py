@@ -328,6 +328,31 @@ def _gate_tol(out, e0, L, rho, ref_le):
     return scale * (3e-5 * SO.layer_sums(np.abs(mu), L) + sd * (5e-4 + 5e-5 * np.abs(z))) + 1e-30
 
 
+@pytest.mark.parametrize("rho", [-1.0, 0.0, 1.0])
+def test_layer_head_gate_matches_oracle(rho):
+    """The gate of a per-layer head (one bin per layer: mean and log-variance
+    of each layer's energy, taken by a one-thread-per-shower kernel) against
+    the oracle's gate, which treats it as layers of one bin."""
+    rng = np.random.default_rng(50 + int(10 * rho))
+    B, L = 5000, 20
+    out = np.empty((B, 2 * L), np.float32)
+    out[:, :L] = rng.uniform(0.0, 3.0, size=(B, L))
+    out[:, L:] = rng.uniform(-9, 3, size=(B, L))
+    out[:7, L:L + 2] = [[-30.0, 25.0]] * 7                # beyond the clamp
+    e0 = rng.uniform(1, 100, B).astype(np.float32)
+    ys = 20.0
+    le, unc, _ = S.gate(torch.from_numpy(out).cuda(), torch.from_numpy(e0).cuda(), L, rho=rho, seed=77,
+                        row_base=2 ** 32 - 100, y_scale=ys)
+    ref_le, ref_unc = SO.gate(out, e0, L, ys, S.S_CLAMP, rho, 77, 2 ** 32 - 100)
+    scale = e0.astype(np.float64)[:, None] / ys
+    sd = np.exp(0.5 * np.clip(out[:, L:].astype(np.float64), -S.S_CLAMP, S.S_CLAMP)) if rho >= 0 else 0.0
+    z = (ref_le / scale - out[:, :L]) / np.where(np.asarray(sd) > 0, sd, 1)
+    tol = scale * (1e-6 * np.abs(out[:, :L]) + sd * (5e-4 + 5e-5 * np.abs(z))) + 1e-30
+    err = np.abs(le.cpu().numpy() - ref_le)
+    assert (err <= tol).all(), float((err / tol).max())
+    np.testing.assert_allclose(unc.cpu().numpy(), ref_unc, rtol=1e-5)
+
+
 @pytest.mark.parametrize("rho", [-1.0, 0.0, 0.35, 1.0])
 def test_gate_matches_oracle(rho):
     """Per-layer energies (means, or samples at bin correlation rho) and
