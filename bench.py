@@ -258,8 +258,19 @@ def bench_surrogate(args):
     best = max(ok, key=lambda r: r["showers_per_s"]) if ok else None
     plain = {"image": n / t_sim, "layer_head": n / t_sim1}
 
-    # roofline of the dominant kernel: the final layer fused into the gate
-    # (2 B K 2D flops per launch), timed with events on the launch stream
+    if args.copy_calibration:
+        # one device copy of exactly 1 GiB: what the HBM counters read for it
+        # calibrates them (see prof_summary)
+        ca = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        cb = torch.empty_like(ca)
+        cb.copy_(ca)
+        torch.cuda.synchronize()
+        del ca, cb
+    # roofline of the dominant kernel: the final layer's product fused into
+    # the gate (gate_fused_k256_kernel, two launches per call: the mean tiles
+    # then the log-variance tiles, 2 B K D flops each), timed with the HIP
+    # events the library records on the launch stream
+    from paper_2202_05012_amd import prof_summary
     B = 65536
     x = S.features(e0[:B], pol[:B], az[:B], 5, stream_id=2)
     h = model.hidden(x)
@@ -267,22 +278,26 @@ def bench_surrogate(args):
     K, D2 = h.shape[1], wt.shape[0]
     for _ in range(3):
         S.gate_fused(h, wt, model.b[-1], e0[:B], SP.N_LAYERS, rho=rho)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    reps = 20
-    ev0.record()
-    for _ in range(reps):
+    S.timing(True)
+    times = []
+    for _ in range(20):
         S.gate_fused(h, wt, model.b[-1], e0[:B], SP.N_LAYERS, rho=rho)
-    ev1.record()
-    torch.cuda.synchronize()
-    k_ms = ev0.elapsed_time(ev1) / reps
-    flops = 2.0 * B * K * D2
+        times.append(S.last_times())
+    S.timing(False)
+    t_mean = float(np.mean([t[0] for t in times]))
+    t_var = float(np.mean([t[1] for t in times]))
+    t_gate = float(np.mean([t[2] for t in times]))
+    k_ms = (t_mean + t_var) / 2
+    flops = 2.0 * B * K * (D2 // 2)
     tf = flops / (k_ms / 1e3) / 1e12
+    workload_name = "surrogate_20layers_16x16"
+    traffic = prof_summary.traffic_if_current(os.path.join(ROOT, "profiles"), "gate_fused_k256_kernel", workload_name)
     line = {
         "metric": "surrogate+fallback showers/s at W1 <= 2% of the mean per-layer energy",
         "value": round(best["showers_per_s"], 1) if best else None,
         "unit": "showers/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
         "dtype": "bf16 mfma (f32 accumulate) + f32/u32 simulation", "data": "synthetic",
-        "config": {"workload": "surrogate_20layers_16x16", "eval_showers": n,
+        "config": {"workload": workload_name, "eval_showers": n,
                    "train_showers": steps * args.batch, "batch": args.batch,
                    "mlp": "19 -> 4x256 GELU -> 10240", "layer_head": "19 -> 4x256 GELU -> 40",
                    "occupied_cell_threshold": SP.OCC_THR},
@@ -292,8 +307,12 @@ def bench_surrogate(args):
         "beats_plain_simulator": bool(best and best["showers_per_s"] > plain[best["model"]]),
         "speedup_over_plain_simulator": round(best["showers_per_s"] / plain[best["model"]], 2) if best else None,
         "roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": round(tf / 2500.0, 4), "traffic": None, "kernel": "gemm_bf16 (fused final layer + gate)",
-                     "kernel_ms": round(k_ms, 4), "alg_flops": flops, "rows": B},
+                     "frac": round(tf / 2500.0, 4), "traffic": traffic,
+                     "kernel": "gate_fused_k256_kernel (final layer product + tile sums; per launch half the "
+                               "columns: means, then log-variances)",
+                     "kernel_ms": round(k_ms, 4), "launch_ms": {"means": round(t_mean, 4), "log_variances":
+                                                                 round(t_var, 4), "gate_rows": round(t_gate, 4)},
+                     "alg_flops": flops, "rows": B},
         "train_seconds": round(t_train, 2), "loss_curve": losses, "head_loss_curve": head_losses,
         "rho": rho, "chosen": best, "sweep": rows, "sweep_layer_head": hrows,
     }

@@ -44,7 +44,8 @@ enum { SUPA_EPI_F32 = 0, SUPA_EPI_BIAS_F32 = 1, SUPA_EPI_BIAS_GELU = 2, SUPA_EPI
  *   F32        C float [M][ldc] = acc
  *   BIAS_F32   C float = acc + bias[n]
  *   BIAS_GELU  pre bf16 [M][ldc] = acc + bias[n]; C bf16 = GELU(pre),
- *              GELU(a) = a Phi(a) (exact, erf form)
+ *              GELU(a) = a Phi(a) (exact, erf form); pre may be NULL
+ *              (inference: the pre-activation is not stored)
  *   GELU_GRAD  C bf16 = acc * GELU'(pre[m][n]) (pre read, bf16 [M][ldc])
  * M, N, K >= 1 and multiples of 8; leading dimensions multiples of 8.
  */
@@ -137,13 +138,30 @@ supa_status supa_surrogate_gate(void *hip_stream, int B, int D, int L, const flo
  * floats); a second kernel combines them per shower.  layer_cnt (float
  * [B][L], may be NULL): per layer, the number of bins whose predicted energy
  * mu * e0 / y_scale exceeds cnt_thr >= 0 (the predicted occupied cells).
- * Requirements: K a multiple of 8, L <= 64, D / L a multiple of 128.
+ * For K = 256 the product runs transposed, each workgroup holding 256 rows
+ * of h in registers and streaming W^T through LDS (one launch for the mean
+ * tiles, one for the log-variance tiles); other K take 128 x 128 tiles.
+ * Requirements: K a multiple of 8, L <= 64, D / L a multiple of 128, h and
+ * w_t 16-byte aligned.
  */
 supa_status supa_surrogate_gate_fused(void *hip_stream, int B, int K, int D, int L, const uint16_t *h, int ldh,
                                       const uint16_t *w_t, int ldw, const float *bias, const float *e0,
                                       float y_scale, float s_clamp, float *partial, float *layer_e, float *unc,
                                       float rho, uint32_t row_base, uint64_t seed, float cnt_thr,
                                       float *layer_cnt);
+
+/*
+ * Timing of supa_surrogate_gate_fused, for measurement: with on != 0, every
+ * later call made while the device current at this call is current records
+ * HIP events on its stream around its kernels (off: no events).  Not thread
+ * safe: the events are the process's.  supa_surrogate_last_times waits for
+ * the last timed call and writes up to three durations (ms): the product's
+ * mean tiles, its log-variance tiles (0 when K != 256: one launch covers
+ * both), the per-row gate.  SUPA_ERR_STATE if no call was timed since
+ * timing was switched on.
+ */
+supa_status supa_surrogate_timing(int on);
+supa_status supa_surrogate_last_times(float *ms, int32_t count);
 
 /* y[c][r] = bf16(x[r][c]): float [rows][cols] to bf16 [cols][rows] (round to nearest even). */
 supa_status supa_transpose_to_bf16(void *hip_stream, int rows, int cols, const float *x, uint16_t *y);

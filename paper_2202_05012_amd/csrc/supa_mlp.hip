@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(256) gemm_bf16(GemmArgs g) {
                     ((float *)g.C)[o] = v + g.bias[n];
                 } else if (EPI == EPI_BIAS_GELU) {
                     v += g.bias[n];
-                    g.pre[o] = f2bf(v);
+                    if (g.pre) g.pre[o] = f2bf(v);
                     ((uint16_t *)g.C)[o] = f2bf(gelu_f(v));
                 } else {   // EPI_GELU_GRAD
                     ((uint16_t *)g.C)[o] = f2bf(v * gelu_grad_f(bf2f(g.pre[o])));
@@ -497,10 +497,237 @@ __global__ void transpose_bf16_kernel(int rows, int cols, const float *x, uint16
     }
 }
 
+// ---------------------------------------------------------------------------
+// The final layer fused into the gate for the hidden width K = 256, taken
+// transposed: C^T[n][m] = sum_k Wt[n][k] h[m][k] (n an output column, m a
+// row), so that a row's sum over a tile's columns is mostly a sum within
+// each lane.  A workgroup of four waves (one per SIMD) covers 256 rows and
+// holds them in registers for the whole launch: wave w keeps rows
+// 64 w .. + 64 as matrix-core B operands and takes all 128 columns of every
+// tile, in two halves of 64.  W^T streams through LDS a tile (128 columns
+// by all of K) at a time, two buffers, copied straight from memory into LDS
+// (no registers on the way) while the matrix cores work on the previous
+// tile.  Every W^T element fetched serves 256 rows and h is read once (the
+// 128 x 128 tiles of gemm_bf16 fetch both operands per tile, more than the
+// L2 can feed at the matrix cores' rate when K is this short).  Two
+// accumulator sets, one per half: the reduction of one half (exponentials,
+// sums, counts) is issued between the matrix products of the next.  One
+// launch covers tiles of one kind (means, or log-variances); writes the
+// same (row, tile) pairs as the EPI_GATE epilogue.
+// ---------------------------------------------------------------------------
+constexpr int GF_K = 256, GF_NT = 128, GF_ROWS = 256;
+constexpr int GF_JW = 1;                     // blocks of 32 rows per wave (see GfState)
+constexpr float GF_HALF_LOG2E = 0.72134752044448170f;     // exp(s / 2) = 2^(s * this)
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef float floatx16_t __attribute__((ext_vector_type(16)));
+typedef uint16_t GfTile[GF_NT][GF_K];
+template <int JW> using GfAcc = floatx16_t[2][JW];      // [32-column block i][32-row block j]
+
+// JW: blocks of 32 rows per wave (2: four waves of 64 rows, one per SIMD;
+// 1: eight waves of 32 rows, two per SIMD)
+template <int JW>
+struct GfState {
+    static constexpr int NW = 8 / JW;        // waves per workgroup
+    const GemmArgs *g;
+    int tid, wave, lane, lc, lh, mw, tiles;
+    bf16x8_t hb[JW][16];
+    float thr[JW];
+    float c0[JW], c1[JW];                    // the first half's sums of the tile in flight
+};
+
+// LDS image of a W^T tile, in 16-byte chunks (8 bf16): chunk c of row n
+// sits at byte 8192 (c >> 2) + 64 n + 16 ((c & 3) ^ ((n >> 2) & 3)).  Sixteen
+// consecutive rows read at the same c fall on sixteen distinct bank groups,
+// a K step's address is one of two per-lane bases plus a constant, and a
+// copy instruction takes 64 contiguous bytes from each of 16 rows.
+template <int JW>
+__device__ __forceinline__ void gf_issue(const GfState<JW> &S, int t, GfTile &W, float *Bt) {
+    // the eight chunk groups (chunks 4 g .. + 4 of every row) split evenly
+    // over the waves; copy q of a group covers rows 16 q .. + 16, lane l
+    // landing at byte 16 l of its 1 KB; waves 0 and 1 also copy 64 floats of
+    // the bias
+    constexpr int G = 8 / GfState<JW>::NW;
+#pragma unroll
+    for (int gs = 0; gs < G; ++gs)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int grp = G * S.wave + gs;
+            const int row = 16 * q + (S.lane >> 2);
+            const int c = 4 * grp + ((S.lane & 3) ^ ((row >> 2) & 3));
+            const uint16_t *src = S.g->B + (int64_t)(t * GF_NT + row) * S.g->ldb + c * 8;
+            __builtin_amdgcn_global_load_lds(
+                src, (__attribute__((address_space(3))) void *)((char *)&W[0][0] + 8192 * grp + 1024 * q), 16, 0, 0);
+        }
+    if (S.wave < 2)
+        __builtin_amdgcn_global_load_lds(S.g->bias + t * GF_NT + 64 * S.wave + S.lane,
+                                         (__attribute__((address_space(3))) void *)(Bt + 64 * S.wave), 4, 0, 0);
+}
+
+// One half-tile step: the matrix products of half PH of the tile in W into
+// acc (if PROD), and in the same straight-line block the reduction of the
+// previous half (prev, half RH of the tile with bias Bp; RED 1 means,
+// 2 means with counts, 3 log-variances), so that its vector instructions
+// issue while the matrix cores are busy.  prev[i][j][r] = column
+// 64 RH + 32 i + 8 (r >> 2) + 4 lh + (r & 3) of row mw + 32 j + lc.  Per
+// row, means reduce to sum mu and the number above the row's occupancy
+// threshold, log-variances (clamped) to sum exp(s) and sum exp(s/2).  After
+// half 0 the sums wait in S.c0 / S.c1; after half 1 the row's pair for
+// tile tp is written.
+template <bool PROD, int PH, int RED, int RH, int JW>
+__device__ __forceinline__ void gf_half(GfState<JW> &S, const GfTile &W, GfAcc<JW> &acc, const GfAcc<JW> &prev,
+                                        const float *Bp, int tp) {
+    float p0[JW] = {}, p1[JW] = {};
+    int cnt[JW] = {};
+    const float lim = S.g->s_clamp * GF_HALF_LOG2E;
+    const char *base[2][2];
+    if constexpr (PROD) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int row = 64 * PH + 32 * i + S.lc;
+#pragma unroll
+            for (int odd = 0; odd < 2; ++odd)
+                base[i][odd] = (const char *)&W[0][0] + 64 * row + 16 * ((2 * odd + S.lh) ^ ((row >> 2) & 3));
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+        if constexpr (PROD) {
+            bf16x8_t a[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) a[i] = *(const bf16x8_t *)(base[i][kk & 1] + 8192 * (kk >> 1));
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < JW; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                        a[i], S.hb[j][kk], kk == 0 ? floatx16_t{} : acc[i][j], 0, 0, 0);
+        }
+        if constexpr (RED != 0) {
+            if (kk < 8) {
+                // step kk reduces column group (i, q) = (kk >> 2, kk & 3)
+                const int i = kk >> 2, q = kk & 3;
+                floatx4_t bv = *(const floatx4_t *)&Bp[64 * RH + 32 * i + 8 * q + 4 * S.lh];
+                if constexpr (RED == 3) bv *= GF_HALF_LOG2E;
+#pragma unroll
+                for (int j = 0; j < JW; ++j)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float a = prev[i][j][4 * q + r];
+                        if constexpr (RED == 3) {
+                            const float x = __builtin_amdgcn_fmed3f(fmaf(a, GF_HALF_LOG2E, bv[r]), -lim, lim);
+                            const float e = __builtin_amdgcn_exp2f(x);
+                            p0[j] = fmaf(e, e, p0[j]);
+                            p1[j] += e;
+                        } else {
+                            const float v = a + bv[r];
+                            p0[j] += v;
+                            if constexpr (RED == 2) cnt[j] += v > S.thr[j] ? 1 : 0;
+                        }
+                    }
+            }
+        }
+    }
+    if constexpr (RED != 0) {
+#pragma unroll
+        for (int j = 0; j < JW; ++j) {
+            if constexpr (RED == 2) p1[j] = (float)cnt[j];
+            p0[j] += __shfl_xor(p0[j], 32, 64);
+            p1[j] += __shfl_xor(p1[j], 32, 64);
+            if constexpr (RH == 0) {
+                S.c0[j] = p0[j];
+                S.c1[j] = p1[j];
+            } else {
+                const int m = S.mw + 32 * j + S.lc;
+                if (S.lh == 0 && m < S.g->M) {
+                    float *P = (float *)S.g->C + ((int64_t)m * S.tiles + tp) * 2;
+                    P[0] = S.c0[j] + p0[j];
+                    P[1] = S.c1[j] + p1[j];
+                }
+            }
+        }
+    }
+}
+
+// Tile t's interval: the next tile copied into Wn / Bn while the halves of
+// tile t (from Wc) are multiplied beside the reductions of tile t - 1's
+// second half (bias Bp) and tile t's first half (bias Bc).  Wn, Bn were
+// last read before the previous barrier; all buffers are distinct LDS
+// variables chosen at compile time, so the compiler sees that reads of Wc,
+// Bc and Bp need not wait for the copies.
+template <int RED, bool FIRST, int JW>
+__device__ __forceinline__ void gf_interval(GfState<JW> &S, int t, int t1, const GfTile &Wc, GfTile &Wn, float *Bn,
+                                            const float *Bc, const float *Bp, GfAcc<JW> &acc0, GfAcc<JW> &acc1) {
+    if (t + 1 < t1) gf_issue(S, t + 1, Wn, Bn);
+    if constexpr (FIRST) gf_half<true, 0, 0, 1, JW>(S, Wc, acc0, acc1, Bp, t - 1);
+    else gf_half<true, 0, RED, 1, JW>(S, Wc, acc0, acc1, Bp, t - 1);
+    gf_half<true, 1, RED, 0, JW>(S, Wc, acc1, acc0, Bc, t);
+    __builtin_amdgcn_s_waitcnt(0);                  // this wave's copies into LDS have landed
+    __syncthreads();
+}
+
+// Tiles [t0, t1) of the product, all of one kind: RED 1 (means), 2 (means
+// with counts) or 3 (log-variances).
+template <int RED, int JW>
+__global__ void __launch_bounds__(512 / JW, 1) gate_fused_k256_kernel(GemmArgs g, int t0, int t1) {
+    __shared__ __attribute__((aligned(1024))) GfTile W0, W1;
+    __shared__ __attribute__((aligned(16))) float B0[GF_NT], B1[GF_NT], B2[GF_NT], B3[GF_NT];
+    GfState<JW> S;
+    S.g = &g;
+    S.tid = threadIdx.x;
+    S.wave = __builtin_amdgcn_readfirstlane(S.tid >> 6);     // wave-uniform: scalar registers
+    S.lane = S.tid & 63;
+    S.lc = S.lane & 31;
+    S.lh = S.lane >> 5;
+    S.mw = blockIdx.x * GF_ROWS + S.wave * 32 * JW;
+    S.tiles = g.N / GF_NT;
+#pragma unroll
+    for (int j = 0; j < JW; ++j) S.c0[j] = S.c1[j] = 0.f;
+
+    // hb[j][kk]: row mw + 32 j + lc, k = 16 kk + 8 lh .. + 8 (zeros beyond M)
+#pragma unroll
+    for (int j = 0; j < JW; ++j) {
+        const int m = S.mw + 32 * j + S.lc;
+        S.thr[j] = (RED == 2 && m < g.M) ? g.cnt_scale / g.e0[m] : __builtin_inff();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            u32x4_t v = {0u, 0u, 0u, 0u};
+            if (m < g.M) v = *(const u32x4_t *)(g.A + (int64_t)m * g.lda + 16 * kk + 8 * S.lh);
+            S.hb[j][kk] = __builtin_bit_cast(bf16x8_t, v);
+        }
+    }
+
+    // tile t0 + u: W(u & 1), bias slot u & 3
+    GfAcc<JW> acc0, acc1;
+    gf_issue(S, t0, W0, B0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    gf_interval<RED, true, JW>(S, t0, t1, W0, W1, B1, B0, B3, acc0, acc1);
+    int t = t0 + 1;
+    for (; t + 4 <= t1; t += 4) {
+        gf_interval<RED, false, JW>(S, t, t1, W1, W0, B2, B1, B0, acc0, acc1);
+        gf_interval<RED, false, JW>(S, t + 1, t1, W0, W1, B3, B2, B1, acc0, acc1);
+        gf_interval<RED, false, JW>(S, t + 2, t1, W1, W0, B0, B3, B2, acc0, acc1);
+        gf_interval<RED, false, JW>(S, t + 3, t1, W0, W1, B1, B0, B3, acc0, acc1);
+    }
+    // the remaining tiles (fewer than four), then the last tile's second half
+    const int left = t1 - t;
+    if (left >= 1) gf_interval<RED, false, JW>(S, t, t1, W1, W0, B2, B1, B0, acc0, acc1);
+    if (left >= 2) gf_interval<RED, false, JW>(S, t + 1, t1, W0, W1, B3, B2, B1, acc0, acc1);
+    if (left >= 3) gf_interval<RED, false, JW>(S, t + 2, t1, W1, W0, B0, B3, B2, acc0, acc1);
+    switch (left) {
+    case 0: gf_half<false, 0, RED, 1, JW>(S, W0, acc0, acc1, B0, t1 - 1); break;
+    case 1: gf_half<false, 0, RED, 1, JW>(S, W0, acc0, acc1, B1, t1 - 1); break;
+    case 2: gf_half<false, 0, RED, 1, JW>(S, W0, acc0, acc1, B2, t1 - 1); break;
+    default: gf_half<false, 0, RED, 1, JW>(S, W0, acc0, acc1, B3, t1 - 1); break;
+    }
+}
+
 hipError_t launch_gate_fused(int B, int K, int D, int L, const uint16_t *h, int ldh, const uint16_t *wt, int ldw,
                              const float *bias, const float *e0, float y_scale, float s_clamp, float *partial,
                              float *layer_e, float *unc, float rho, uint32_t row_base, uint64_t seed,
-                             float cnt_thr, float *layer_cnt, hipStream_t s) {
+                             float cnt_thr, float *layer_cnt, const hipEvent_t *ev, hipStream_t s) {
+    // ev (optional): four events recorded before the products, between the
+    // mean and the log-variance tiles, after the products and after the gate
     GemmArgs g{};
     g.M = B;
     g.N = 2 * D;
@@ -516,11 +743,28 @@ hipError_t launch_gate_fused(int B, int K, int D, int L, const uint16_t *h, int 
     // a bin is occupied when its energy mu * e0 / y_scale exceeds cnt_thr
     g.e0 = layer_cnt ? e0 : nullptr;
     g.cnt_scale = cnt_thr * y_scale;
-    hipError_t e = launch_gemm(0, 1, EPI_GATE, g, s);
-    if (e != hipSuccess) return e;
+    auto mark = [&](int i) { return ev ? hipEventRecord(ev[i], s) : hipSuccess; };
+    if (hipError_t e = mark(0); e != hipSuccess) return e;
+    if (K == GF_K) {
+        // the mean tiles, then the log-variance tiles
+        constexpr int JW = GF_JW;
+        const dim3 grid((unsigned)((B + GF_ROWS - 1) / GF_ROWS)), block(512 / JW);
+        const int tm = D / GF_NT, tiles = 2 * D / GF_NT;
+        if (layer_cnt) hipLaunchKernelGGL((gate_fused_k256_kernel<2, JW>), grid, block, 0, s, g, 0, tm);
+        else hipLaunchKernelGGL((gate_fused_k256_kernel<1, JW>), grid, block, 0, s, g, 0, tm);
+        if (hipError_t e = mark(1); e != hipSuccess) return e;
+        hipLaunchKernelGGL((gate_fused_k256_kernel<3, JW>), grid, block, 0, s, g, tm, tiles);
+    } else {
+        hipError_t e = launch_gemm(0, 1, EPI_GATE, g, s);
+        if (e != hipSuccess) return e;
+        if (e = mark(1); e != hipSuccess) return e;
+    }
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    if (hipError_t e = mark(2); e != hipSuccess) return e;
     hipLaunchKernelGGL(gate_tiles_kernel, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, B, D, L, partial, e0,
                        y_scale, layer_e, unc, rho, row_base, (uint32_t)seed, (uint32_t)(seed >> 32), layer_cnt);
-    return hipGetLastError();
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+    return mark(3);
 }
 
 hipError_t launch_transpose_bf16(int rows, int cols, const float *x, uint16_t *y, hipStream_t s) {
@@ -578,40 +822,65 @@ hipError_t launch_features(int B, int ld, int n_noise, const float *e0, const fl
 // The gate of an output with one bin per layer (a per-layer head: [mean of
 // each layer | log-variance of each layer]): one thread per shower, the same
 // quantities as gate_kernel (with one bin the layer's sd is its sigma for
-// every rho, and the same Philox counters give z).
-__global__ void gate_rows_kernel(int B, int L, const float *out, const float *e0, float y_scale, float s_clamp,
-                                 float *layer_e, float *unc, float rho, uint32_t row_base, uint32_t k0,
-                                 uint32_t k1) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
-    const float *row = out + (int64_t)b * 2 * L;
-    const float scale = e0[b] / y_scale;
-    float tm = 0.f, tv = 0.f;
-    for (int l = 0; l < L; ++l) {
-        const float mu = row[l];
-        const float sv = fminf(fmaxf(row[L + l], -s_clamp), s_clamp);
-        float v = mu;
-        if (rho >= 0.0f) {
-            const uint4 w = philox4x32_10(row_base + (uint32_t)b, (uint32_t)l, 0x9a7eu, 0u, k0, k1);
-            const float u1 = ((float)w.x + 0.5f) * 0x1p-32f, u2 = ((float)w.y + 0.5f) * 0x1p-32f;
-            float sn, cs;
-            sincospif(2.0f * u2, &sn, &cs);
-            const float z = sqrtf(-2.0f * logf(u1)) * cs;
-            v += __expf(0.5f * sv) * z;
-        }
-        layer_e[(int64_t)b * L + l] = v * scale;
-        tm += mu;
-        tv += __expf(sv);
+// every rho, and the same Philox counters give z).  A wave's 64 rows pass
+// through LDS in both directions, so that global reads and writes are
+// contiguous; rows are padded to an odd length against bank conflicts.
+constexpr int GR_ROWS = 64;
+
+__global__ void __launch_bounds__(GR_ROWS) gate_rows_kernel(int B, int L, const float *out, const float *e0,
+                                                            float y_scale, float s_clamp, float *layer_e, float *unc,
+                                                            float rho, uint32_t row_base, uint32_t k0, uint32_t k1) {
+    extern __shared__ float gr_lds[];
+    const int in_ld = 2 * L + 1, out_ld = L + 1;
+    float *tin = gr_lds, *tout = gr_lds + GR_ROWS * in_ld;
+    const int b0 = blockIdx.x * GR_ROWS;
+    const int rows = min(GR_ROWS, B - b0);
+    const float *src = out + (int64_t)b0 * 2 * L;
+    for (int i = threadIdx.x; i < rows * 2 * L; i += GR_ROWS) {
+        const int r = i / (2 * L);
+        tin[r * in_ld + (i - r * 2 * L)] = src[i];
     }
-    unc[b] = sqrtf(tv) / fmaxf(tm, 1e-6f);
+    __syncthreads();
+    const int r = threadIdx.x;
+    if (r < rows) {
+        const int b = b0 + r;
+        const float *row = tin + r * in_ld;
+        const float scale = e0[b] / y_scale;
+        float tm = 0.f, tv = 0.f;
+        for (int l = 0; l < L; ++l) {
+            const float mu = row[l];
+            const float sv = fminf(fmaxf(row[L + l], -s_clamp), s_clamp);
+            float v = mu;
+            if (rho >= 0.0f) {
+                const uint4 w = philox4x32_10(row_base + (uint32_t)b, (uint32_t)l, 0x9a7eu, 0u, k0, k1);
+                const float u1 = ((float)w.x + 0.5f) * 0x1p-32f, u2 = ((float)w.y + 0.5f) * 0x1p-32f;
+                float sn, cs;
+                sincospif(2.0f * u2, &sn, &cs);
+                const float z = sqrtf(-2.0f * logf(u1)) * cs;
+                v += __expf(0.5f * sv) * z;
+            }
+            tout[r * out_ld + l] = v * scale;
+            tm += mu;
+            tv += __expf(sv);
+        }
+        unc[b] = sqrtf(tv) / fmaxf(tm, 1e-6f);
+    }
+    __syncthreads();
+    float *dst = layer_e + (int64_t)b0 * L;
+    for (int i = threadIdx.x; i < rows * L; i += GR_ROWS) {
+        const int rr = i / L;
+        dst[i] = tout[rr * out_ld + (i - rr * L)];
+    }
 }
 
 hipError_t launch_gate(int B, int D, int L, const float *out, const float *e0, float y_scale,
                        float s_clamp, float *layer_e, float *unc, float *img, float rho,
                        uint32_t row_base, uint64_t seed, hipStream_t s) {
-    if (D == L && !img) {
-        hipLaunchKernelGGL(gate_rows_kernel, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, s, B, L, out, e0,
-                           y_scale, s_clamp, layer_e, unc, rho, row_base, (uint32_t)seed, (uint32_t)(seed >> 32));
+    if (D == L && L <= 64 && !img) {
+        const size_t lds = (size_t)GR_ROWS * (3 * L + 2) * sizeof(float);      // <= 50 KB for L <= 64
+        hipLaunchKernelGGL(gate_rows_kernel, dim3((unsigned)((B + GR_ROWS - 1) / GR_ROWS)), dim3(GR_ROWS), lds, s, B,
+                           L, out, e0, y_scale, s_clamp, layer_e, unc, rho, row_base, (uint32_t)seed,
+                           (uint32_t)(seed >> 32));
         return hipGetLastError();
     }
     hipLaunchKernelGGL(gate_kernel, dim3(B), dim3(256), 0, s, B, D, L, out, e0, y_scale, s_clamp,

@@ -38,7 +38,7 @@ hipError_t launch_group_sums(int rows, int L, int g, const float *x, float *out,
 hipError_t launch_gate_fused(int B, int K, int D, int L, const uint16_t *h, int ldh, const uint16_t *wt, int ldw,
                              const float *bias, const float *e0, float y_scale, float s_clamp, float *partial,
                              float *layer_e, float *unc, float rho, uint32_t row_base, uint64_t seed,
-                             float cnt_thr, float *layer_cnt, hipStream_t s);
+                             float cnt_thr, float *layer_cnt, const hipEvent_t *ev, hipStream_t s);
 hipError_t launch_transpose_bf16(int rows, int cols, const float *x, uint16_t *y, hipStream_t s);
 size_t sort_work_bytes(int64_t n, int cols);
 hipError_t launch_sort_columns(const float *x, int64_t ld, int64_t n, int cols, void *work, uint32_t **sorted,
@@ -66,6 +66,38 @@ static supa_status dev(hipError_t e, const char *what) {
 
 extern "C" const char *supa_surrogate_last_error(void) { return t_err.c_str(); }
 
+// Timing of supa_surrogate_gate_fused: four events on the device that was
+// current when timing was switched on.
+static struct {
+    bool on = false, recorded = false;
+    int device = -1;
+    hipEvent_t ev[4] = {};
+} g_gate_timing;
+
+extern "C" supa_status supa_surrogate_timing(int on) {
+    if (on && !g_gate_timing.ev[0]) {
+        if (hipError_t e = hipGetDevice(&g_gate_timing.device); e != hipSuccess) return dev(e, "timing");
+        for (hipEvent_t &e : g_gate_timing.ev)
+            if (hipError_t r = hipEventCreate(&e); r != hipSuccess) return dev(r, "timing");
+    }
+    g_gate_timing.on = on != 0;
+    g_gate_timing.recorded = false;
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_surrogate_last_times(float *ms, int32_t count) {
+    if (!ms || count < 1 || count > 3) return bad("ms must hold 1 to 3 floats");
+    if (!g_gate_timing.recorded) {
+        t_err = "no timed gate_fused call since timing was switched on";
+        return SUPA_ERR_STATE;
+    }
+    if (hipError_t e = hipEventSynchronize(g_gate_timing.ev[3]); e != hipSuccess) return dev(e, "timing");
+    for (int i = 0; i < count; ++i)
+        if (hipError_t e = hipEventElapsedTime(&ms[i], g_gate_timing.ev[i], g_gate_timing.ev[i + 1]); e != hipSuccess)
+            return dev(e, "timing");
+    return SUPA_OK;
+}
+
 extern "C" supa_status supa_gemm_bf16(void *stream, int trans_a, int trans_b, int epilogue, int M,
                                       int N, int K, const uint16_t *A, int lda, const uint16_t *B,
                                       int ldb, const float *bias, void *C, int ldc, uint16_t *pre) {
@@ -79,7 +111,7 @@ extern "C" supa_status supa_gemm_bf16(void *stream, int trans_a, int trans_b, in
                     (trans_a == 1 && trans_b == 0 && epilogue == SUPA_EPI_F32);
     if (!ok) return bad("unsupported layout / epilogue combination");
     if ((epilogue == SUPA_EPI_BIAS_F32 || epilogue == SUPA_EPI_BIAS_GELU) && !bias) return bad("bias is NULL");
-    if ((epilogue == SUPA_EPI_BIAS_GELU || epilogue == SUPA_EPI_GELU_GRAD) && !pre) return bad("pre is NULL");
+    if (epilogue == SUPA_EPI_GELU_GRAD && !pre) return bad("pre is NULL");
     supa::GemmArgs g{M, N, K, A, B, lda, ldb, bias, C, ldc, pre};
     return dev(supa::launch_gemm(trans_a, trans_b, epilogue, g, (hipStream_t)stream), "gemm");
 }
@@ -192,10 +224,19 @@ extern "C" supa_status supa_surrogate_gate_fused(void *stream, int B, int K, int
     if (rho > 1.0f) return bad("rho must be <= 1 (negative: no sampling)");
     if (B == 0) return SUPA_OK;
     if (!h || !w_t || !bias || !e0 || !partial || !layer_e || !unc) return bad("NULL pointer");
+    if (((uintptr_t)h | (uintptr_t)w_t) & 15) return bad("h and w_t must be 16-byte aligned");
     if (layer_cnt && !(cnt_thr >= 0)) return bad("cnt_thr must be >= 0");
-    return dev(supa::launch_gate_fused(B, K, D, L, h, ldh, w_t, ldw, bias, e0, y_scale, s_clamp, partial, layer_e,
-                                       unc, rho, row_base, seed, cnt_thr, layer_cnt, (hipStream_t)stream),
-               "gate_fused");
+    const hipEvent_t *ev = nullptr;
+    if (g_gate_timing.on) {
+        int d = -1;
+        if (hipGetDevice(&d) == hipSuccess && d == g_gate_timing.device) ev = g_gate_timing.ev;
+    }
+    const supa_status st = dev(supa::launch_gate_fused(B, K, D, L, h, ldh, w_t, ldw, bias, e0, y_scale, s_clamp,
+                                                       partial, layer_e, unc, rho, row_base, seed, cnt_thr, layer_cnt,
+                                                       ev, (hipStream_t)stream),
+                               "gate_fused");
+    if (ev && st == SUPA_OK) g_gate_timing.recorded = true;
+    return st;
 }
 
 extern "C" supa_status supa_transpose_to_bf16(void *stream, int rows, int cols, const float *x, uint16_t *y) {

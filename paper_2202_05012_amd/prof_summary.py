@@ -39,6 +39,8 @@ KERNEL_SOURCES = {
     "w1_stats": ["supa_shapes.hip"],
     "w1_hist": ["supa_shapes.hip"],
     "grids_kernel": ["supa_grids.hip"],
+    "gate_fused_k256_kernel": ["supa_mlp.hip", "supa_mlp.hpp"],
+    "gemm_bf16": ["supa_mlp.hip", "supa_mlp.hpp"],
 }
 
 
@@ -52,7 +54,8 @@ def source_hash(kernel: str) -> str:
 
 def short_name(full: str) -> str:
     m = re.search(r"(supa_propagate|supa_place|scatter_nodes|scan_tiles|scan_top|scan_apply|shapes_kernel|"
-                  r"shapes_clear|w1_stats|w1_hist|w1_colinfo|w1_distance|w1_groups|w1_zero|grids_kernel)\b", full)
+                  r"shapes_clear|w1_stats|w1_hist|w1_colinfo|w1_distance|w1_groups|w1_zero|grids_kernel|"
+                  r"gate_fused_k256_kernel|gemm_bf16|gate_tiles_kernel|gate_rows_kernel|features_kernel)\b", full)
     return m.group(1) if m else full
 
 
@@ -91,14 +94,17 @@ def counter(pmc_dir: str, name: str):
     return out, copy
 
 
-def steady(vals, skip):
+def steady(vals, skip, last=None):
     """Mean over the dispatches after the first `skip` (sizing probe and
-    warm-up)."""
-    v = vals[skip:] if len(vals) > skip else vals
+    warm-up), or over the last `last` dispatches when given."""
+    if last:
+        v = vals[-last:]
+    else:
+        v = vals[skip:] if len(vals) > skip else vals
     return statistics.fmean(v) if v else float("nan")
 
 
-def summarize(trace_dir, fetch_dir, write_dir, workload, commands, out_dir, skip=2, kernels=None):
+def summarize(trace_dir, fetch_dir, write_dir, workload, commands, out_dir, skip=2, kernels=None, last=None):
     dur = durations(trace_dir)
     fetch, fcopy = counter(fetch_dir, "FETCH_SIZE")
     write, wcopy = counter(write_dir, "WRITE_SIZE")
@@ -108,9 +114,10 @@ def summarize(trace_dir, fetch_dir, write_dir, workload, commands, out_dir, skip
     for k in KERNEL_SOURCES:
         if k not in dur or (kernels and k not in kernels):
             continue
-        ms = steady(dur[k], skip)
-        fk = steady(fetch.get(k, []), skip)
-        wk = steady(write.get(k, []), skip)
+        ms = steady(dur[k], skip, last)
+        fk = steady(fetch.get(k, []), skip, last)
+        wk = steady(write.get(k, []), skip, last)
+        sel = dur[k][-last:] if last else (dur[k][skip:] or dur[k])
         traffic = (fk * f_scale + wk * w_scale) * 1024.0
         lines = [
             f"# {k} -- {workload}",
@@ -120,10 +127,11 @@ def summarize(trace_dir, fetch_dir, write_dir, workload, commands, out_dir, skip
             *[f"    {c}" for c in commands],
             "",
             f"source_sha256: {source_hash(k)}",
-            f"dispatches_traced: {len(dur[k])} (first {skip} skipped: sizing or checking call, first warm-up)",
+            (f"dispatches_traced: {len(dur[k])} (averaged: the last {last}, the timed calls)" if last else
+             f"dispatches_traced: {len(dur[k])} (first {skip} skipped: sizing or checking call, first warm-up)"),
             f"avg_duration_ms: {ms:.4f}",
-            f"min_duration_ms: {min(dur[k][skip:] or dur[k]):.4f}",
-            f"max_duration_ms: {max(dur[k][skip:] or dur[k]):.4f}",
+            f"min_duration_ms: {min(sel):.4f}",
+            f"max_duration_ms: {max(sel):.4f}",
             f"fetch_kib_per_dispatch: {fk:.1f}",
             f"write_kib_per_dispatch: {wk:.1f}",
             f"copy_calibration_fetch_kib: {fcopy:.1f} (1 GiB copy; factor {f_scale:.4f})",
@@ -250,10 +258,12 @@ def main():
     ap.add_argument("--skip", type=int, default=2)
     ap.add_argument("--kernel", action="append", default=[],
                     help="summarise only these kernels (default: every known kernel traced)")
+    ap.add_argument("--last", type=int, default=None,
+                    help="average each kernel's last N dispatches (the timed calls) instead")
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
     for p in summarize(a.trace_dir, a.fetch_dir, a.write_dir, a.workload, a.command, a.out, a.skip,
-                       a.kernel or None):
+                       a.kernel or None, a.last):
         print(p)
 
 

@@ -52,6 +52,8 @@ def _lib():
             "supa_w1_equal": [vp, i64, C.c_int32, vp, i64, vp, i64, vp, vp, i64],
             "supa_sort_columns": [vp, i64, C.c_int32, vp, i64, vp, vp, i64],
             "supa_occupied_counts": [vp, i64, C.c_int32, C.c_int32, vp, f, vp],
+            "supa_surrogate_timing": [i],
+            "supa_surrogate_last_times": [vp, C.c_int32],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -169,6 +171,19 @@ def gate_fused(h, w_t, bias, e0, n_layers, rho=-1.0, seed=0, row_base=0, cnt_thr
     return (layer_e, unc) if cnt is None else (layer_e, unc, cnt)
 
 
+def timing(on: bool):
+    """Switch the event timing of gate_fused on or off (supa_surrogate_timing)."""
+    _check(_lib().supa_surrogate_timing(1 if on else 0))
+
+
+def last_times():
+    """Milliseconds of the last timed gate_fused call: (mean-tile product,
+    log-variance product, per-row gate)."""
+    ms = (C.c_float * 3)()
+    _check(_lib().supa_surrogate_last_times(C.cast(ms, C.c_void_p), 3))
+    return tuple(float(v) for v in ms)
+
+
 def w1_equal(a, b):
     """Exact W1 between the columns of two equal-size float samples [n, cols]
     (supa_w1_equal); returns a float64 tensor [cols] on the device."""
@@ -278,7 +293,8 @@ class MLP:
 
     def forward(self, x, keep=False):
         """x: bf16 [B, IN_PAD] -> float32 [B, out]; keep=True also returns
-        the activations and pre-activations the backward needs."""
+        the activations and pre-activations the backward needs (without it
+        the pre-activations are not stored)."""
         B = x.shape[0]
         h = x
         acts, pres = [x], []
@@ -287,7 +303,7 @@ class MLP:
             dout = self.dims[l + 1]
             if l < nl - 1:
                 y = torch.empty((B, dout), dtype=torch.int16, device=self.device)
-                pre = torch.empty((B, dout), dtype=torch.int16, device=self.device)
+                pre = torch.empty((B, dout), dtype=torch.int16, device=self.device) if keep else None
                 gemm(h, self.Wb[l], y, epilogue=2, bias=self.b[l], pre=pre)
                 pres.append(pre)
                 acts.append(y)
@@ -302,8 +318,7 @@ class MLP:
         h = x
         for l in range(len(self.Wb) - 1):
             y = torch.empty((x.shape[0], self.dims[l + 1]), dtype=torch.int16, device=self.device)
-            pre = torch.empty_like(y)
-            gemm(h, self.Wb[l], y, epilogue=2, bias=self.b[l], pre=pre)
+            gemm(h, self.Wb[l], y, epilogue=2, bias=self.b[l])
             h = y
         return h
 

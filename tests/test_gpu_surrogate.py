@@ -70,6 +70,10 @@ def test_gemm_variants(ta, tb, epi):
         y_got = bf16_to_np(host16(C)).astype(np.float64)
         slope = np.abs(SO.gelu_grad(pre_ref))
         assert (np.abs(y_got - y_ref) <= 2e-6 * scale * slope + 2 ** -8 * np.abs(y_ref) + 1e-6).all()
+        # inference form: no pre-activation stored, the same activations
+        C2 = torch.empty((M, N), dtype=torch.int16, device="cuda")
+        S.gemm(At, Bt, C2, ta, tb, epi, bias=torch.from_numpy(bias).cuda(), M=M, N=N, K=K)
+        assert torch.equal(C2, C)
     else:
         C = torch.empty((M, N), dtype=torch.int16, device="cuda")
         S.gemm(At, Bt, C, ta, tb, epi, pre=dev16(pre_in), M=M, N=N, K=K)
@@ -200,18 +204,21 @@ def test_gate_select_gather_scatter():
     np.testing.assert_allclose(gs, SO.layer_sums(mu, L), rtol=1e-5, atol=1e-5)
 
 
+@pytest.mark.parametrize("K,B", [(64, 296), (256, 1096)])
 @pytest.mark.parametrize("rho", [-1.0, 0.5])
-def test_gate_fused_matches_gate_and_oracle(rho):
+def test_gate_fused_matches_gate_and_oracle(rho, K, B):
     """The final layer fused into the gate (per-tile reductions in the matrix
     product's epilogue, no [B, 2D] output) gives the per-layer energies and
     uncertainty scores of the unfused product + gate, and of the FP64 oracle
     on the same bf16 inputs (exact sums of the float32-accumulated products
-    up to the order of additions)."""
+    up to the order of additions).  K = 64 takes the 128 x 128 tile product
+    (B ragged against its 128-row tiles); K = 256 the transposed product
+    with h held in registers (five 256-row workgroups, the last one ragged)."""
     rng = np.random.default_rng(31)
-    B, K, L, bins = 296, 64, 4, 128                 # B ragged against the 128-row tiles
+    L, bins = 4, 128
     D = L * bins
     h = bf16_round(rng.normal(size=(B, K)))
-    W = (rng.normal(size=(K, 2 * D)) * 0.1).astype(np.float32)
+    W = (rng.normal(size=(K, 2 * D)) * 0.1 * np.sqrt(64 / K)).astype(np.float32)
     W[:, D:] *= 3.0                                 # log-variances over a few units
     bias = rng.normal(size=2 * D).astype(np.float32) * 0.1
     bias[:D] += 1.0                                 # positive means: a well-conditioned score
@@ -329,12 +336,15 @@ def _gate_tol(out, e0, L, rho, ref_le):
 
 
 @pytest.mark.parametrize("rho", [-1.0, 0.0, 1.0])
-def test_layer_head_gate_matches_oracle(rho):
+@pytest.mark.parametrize("L", [20, 64])
+def test_layer_head_gate_matches_oracle(rho, L):
     """The gate of a per-layer head (one bin per layer: mean and log-variance
-    of each layer's energy, taken by a one-thread-per-shower kernel) against
-    the oracle's gate, which treats it as layers of one bin."""
-    rng = np.random.default_rng(50 + int(10 * rho))
-    B, L = 5000, 20
+    of each layer's energy, taken by a one-thread-per-shower kernel through
+    LDS, 64 rows a block: 5000 rows leave a ragged last block; L = 64 the
+    largest it takes) against the oracle's gate, which treats it as layers
+    of one bin."""
+    rng = np.random.default_rng(50 + int(10 * rho) + L)
+    B = 5000
     out = np.empty((B, 2 * L), np.float32)
     out[:, :L] = rng.uniform(0.0, 3.0, size=(B, L))
     out[:, L:] = rng.uniform(-9, 3, size=(B, L))
