@@ -163,6 +163,33 @@ supa_status supa_surrogate_gate_fused(void *hip_stream, int B, int K, int D, int
 supa_status supa_surrogate_timing(int on);
 supa_status supa_surrogate_last_times(float *ms, int32_t count);
 
+/*
+ * The network's forward pass in one kernel (inference): n_hidden (1..8)
+ * layers of 256 units, bias + GELU (erf form), on k_in inputs (x bf16
+ * [B][ldx], k_in a multiple of 16 up to 256), then with n_out > 0 a linear
+ * layer of n_out outputs (a multiple of 4, at most 64) into out (float
+ * [B][ldo]), else the last hidden activations into h (bf16 [B][ldh]).  The
+ * activations stay in registers: a workgroup takes 256 rows through every
+ * layer, each layer's weights streaming through LDS.  The same values as
+ * supa_gemm_bf16 layer by layer (BIAS_GELU, then BIAS_F32) up to the order
+ * of the float sums.  wt and bias: host arrays of device pointers, one per
+ * layer (hidden layers, then the output layer): wt[l] bf16 [out][in] as
+ * written by supa_mlp_fused_weights (layer 0 with permute = 0, the others
+ * with permute = 1), bias[l] float [out].  x, weights and the output
+ * 16-byte aligned; ldo and ldh multiples of 4.
+ */
+supa_status supa_mlp_forward_fused(void *hip_stream, int B, int k_in, int n_hidden, const uint16_t *x, int ldx,
+                                   const uint16_t *const *wt, const float *const *bias, int n_out, float *out,
+                                   int ldo, uint16_t *h, int ldh);
+
+/*
+ * A layer's weights for supa_mlp_forward_fused: wt[n][k'] = bf16(W[k][n])
+ * (W float [in][out], round to nearest even), with k' = k, or with permute
+ * the index the fused pass keeps the previous layer's outputs at: bits 2 and
+ * 3 of k swapped (in a multiple of 32).
+ */
+supa_status supa_mlp_fused_weights(void *hip_stream, int in, int out, const float *W, int permute, uint16_t *wt);
+
 /* y[c][r] = bf16(x[r][c]): float [rows][cols] to bf16 [cols][rows] (round to nearest even). */
 supa_status supa_transpose_to_bf16(void *hip_stream, int rows, int cols, const float *x, uint16_t *y);
 

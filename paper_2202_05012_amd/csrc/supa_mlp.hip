@@ -722,6 +722,214 @@ __global__ void __launch_bounds__(512 / JW, 1) gate_fused_k256_kernel(GemmArgs g
     }
 }
 
+// ---------------------------------------------------------------------------
+// The forward pass of the whole MLP in one kernel (inference): a workgroup
+// of eight waves (two per SIMD) takes 256 rows through every layer with the
+// activations in registers, never in memory.  Wave w holds its 32 rows as
+// `v_mfma_f32_32x32x16_bf16` B operands (all 256 inputs: 64 registers); a
+// layer's products (transposed, as in gate_fused_k256_kernel: W^T from LDS
+// is the A operand) leave each lane the outputs 32 i + 8 g + 4 lh + q of its
+// row, which bias + GELU + bf16 turn straight into the next layer's B
+// operands: element 4 (g & 1) + q of K step 2 i + (g >> 1).  The next layer
+// therefore sees its inputs in an order that swaps bits 2 and 3 of the index
+// within each block of 32; its weights are stored with the input index
+// permuted the same way (mlp_permute_k), so nothing moves between lanes.
+// Each layer's W^T streams through LDS in tiles of 128 outputs by all its
+// inputs, two buffers copied straight into LDS while the previous tile is
+// multiplied (the tile layout of gate_fused_k256_kernel), the tile's bias
+// beside it.  Out: the last hidden activations (bf16, natural order) or,
+// with FINAL, a linear layer of n_out <= 64 outputs (float).
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int mlp_permute_k(int k) {
+    return (k & ~12) | ((k & 4) << 1) | ((k & 8) >> 1);
+}
+
+// GELU(a) = a Phi(a), Phi(a) = erfc(-a / sqrt 2) / 2, with erfc(x) for x >= 0
+// from Abramowitz & Stegun 7.1.26 (absolute error <= 1.5e-7, far below the
+// bf16 rounding that follows): t = 1 / (1 + p x),
+// erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2); about a
+// third of the instructions of the erfcf form (gelu_f, kept for training)
+__device__ __forceinline__ float gelu_as(float a) {
+    const float x = fabsf(a) * 0.707106781f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
+    const float poly =
+        t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+    const float h = 0.5f * poly * __builtin_amdgcn_exp2f(-1.44269504f * x * x);     // Phi(-|a|)
+    return a * (a >= 0.0f ? 1.0f - h : h);
+}
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+// two floats to a pair of bf16 (round to nearest even: v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+struct MfState {
+    const MlpFusedArgs *a;
+    int tid, wave, lane, lc, lh, row, tiles;
+    u32x4_t hb[16], hn[16];          // 8 bf16 each: B operands of K steps
+};
+
+// tile u: hidden layer u / 2, outputs 128 (u % 2) .. + 128; with FINAL the
+// last tile is the output layer
+__device__ __forceinline__ void mf_issue(const MfState &S, int u, GfTile &W, float *Bt) {
+    const MlpFusedArgs &a = *S.a;
+    const bool fin = u >= 2 * a.n_hidden;
+    const int l = fin ? a.n_hidden : u >> 1;
+    const int K = l == 0 ? a.k_in : GF_K;
+    const int r0 = fin ? 0 : 128 * (u & 1), rows = fin ? a.n_out : 128;
+    const uint16_t *src = a.wt[l] + (int64_t)r0 * K;
+    // wave w copies rows 16 w .. + 16 of every chunk group (4 chunks of 8)
+    const int r = 16 * S.wave + (S.lane >> 2);
+    for (int g = 0; g < K / 32; ++g)
+        if (r < rows) {
+            const int c = 4 * g + ((S.lane & 3) ^ ((r >> 2) & 3));
+            __builtin_amdgcn_global_load_lds(
+                src + (int64_t)r * K + c * 8,
+                (__attribute__((address_space(3))) void *)((char *)&W[0][0] + 8192 * g + 1024 * S.wave), 16, 0, 0);
+        }
+    const int bi = 64 * S.wave + S.lane;
+    if (S.wave < 2 && bi < rows)
+        __builtin_amdgcn_global_load_lds(a.bias[l] + r0 + bi,
+                                         (__attribute__((address_space(3))) void *)(Bt + 64 * S.wave), 4, 0, 0);
+}
+
+// acc[i] = the products of tile rows 32 i + .. (i < NI) with this wave's rows
+template <int NI>
+__device__ __forceinline__ void mf_products(const MfState &S, const GfTile &W, int ks, floatx16_t (&acc)[4]) {
+    const char *base[NI][2];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+        const int r = 32 * i + S.lc;
+#pragma unroll
+        for (int odd = 0; odd < 2; ++odd)
+            base[i][odd] = (const char *)&W[0][0] + 64 * r + 16 * ((2 * odd + S.lh) ^ ((r >> 2) & 3));
+    }
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+        if (kk < ks) {
+            bf16x8_t w[NI];
+#pragma unroll
+            for (int i = 0; i < NI; ++i) w[i] = *(const bf16x8_t *)(base[i][kk & 1] + 8192 * (kk >> 1));
+#pragma unroll
+            for (int i = 0; i < NI; ++i)
+                acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[i], __builtin_bit_cast(bf16x8_t, S.hb[kk]),
+                                                                  kk == 0 ? floatx16_t{} : acc[i], 0, 0, 0);
+        }
+    }
+}
+
+// tile u from Wc / Bc, the next tile copied into Wn / Bn meanwhile (distinct
+// LDS variables chosen at compile time: reads of Wc need not wait for it)
+template <bool FINAL>
+__device__ __forceinline__ void mf_tile(MfState &S, int u, const GfTile &Wc, const float *Bc, GfTile &Wn,
+                                        float *Bn) {
+    const MlpFusedArgs &a = *S.a;
+    if (u + 1 < S.tiles) mf_issue(S, u + 1, Wn, Bn);
+    floatx16_t acc[4];
+    if (FINAL && u == 2 * a.n_hidden) {
+        mf_products<2>(S, Wc, 16, acc);
+        // outputs 32 i + 8 g + 4 lh + q of this lane's row
+        if (S.row < a.B) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int f = 32 * i + 8 * g + 4 * S.lh;
+                    if (f < a.n_out) {
+                        const floatx4_t bv = *(const floatx4_t *)&Bc[f];
+                        floatx4_t v;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) v[q] = acc[i][4 * g + q] + bv[q];
+                        *(floatx4_t *)(a.out + (int64_t)S.row * a.ldo + f) = v;
+                    }
+                }
+        }
+    } else {
+        const int l = u >> 1, hf = u & 1;
+        mf_products<4>(S, Wc, l == 0 ? a.k_in / 16 : 16, acc);
+        const bool out_h = !FINAL && l == a.n_hidden - 1;
+        // bias + GELU + bf16: outputs 128 hf + 32 i + 8 g + 4 lh + q become
+        // element 4 (g & 1) + q of the next layer's K step 8 hf + 2 i + (g >> 1)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const floatx4_t bv = *(const floatx4_t *)&Bc[32 * i + 8 * g + 4 * S.lh];
+                float y[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) y[q] = gelu_as(acc[i][4 * g + q] + bv[q]);
+                const uint32_t lo = pack_bf16x2(y[0], y[1]), hi = pack_bf16x2(y[2], y[3]);
+                u32x4_t &t = S.hn[8 * hf + 2 * i + (g >> 1)];
+                t[2 * (g & 1)] = lo;
+                t[2 * (g & 1) + 1] = hi;
+                if (out_h && S.row < a.B)
+                    *(uint2 *)(a.h + (int64_t)S.row * a.ldh + 128 * hf + 32 * i + 8 * g + 4 * S.lh) = make_uint2(lo, hi);
+            }
+        if (hf == 1) {
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) S.hb[kk] = S.hn[kk];
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);                  // this wave's copies into LDS have landed
+    __syncthreads();
+}
+
+template <bool FINAL>
+__global__ void __launch_bounds__(512, 1) mlp_fused_kernel(MlpFusedArgs a) {
+    __shared__ __attribute__((aligned(1024))) GfTile W0, W1;
+    __shared__ __attribute__((aligned(16))) float B0[GF_NT], B1[GF_NT];
+    MfState S;
+    S.a = &a;
+    S.tid = threadIdx.x;
+    S.wave = __builtin_amdgcn_readfirstlane(S.tid >> 6);     // wave-uniform: scalar registers
+    S.lane = S.tid & 63;
+    S.lc = S.lane & 31;
+    S.lh = S.lane >> 5;
+    S.row = blockIdx.x * GF_ROWS + S.wave * 32 + S.lc;
+    S.tiles = 2 * a.n_hidden + (FINAL ? 1 : 0);
+    // the first layer's inputs: k = 16 kk + 8 lh .. + 8 of this lane's row
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+        u32x4_t v = {0u, 0u, 0u, 0u};
+        if (S.row < a.B && 16 * kk < a.k_in) v = *(const u32x4_t *)(a.x + (int64_t)S.row * a.ldx + 16 * kk + 8 * S.lh);
+        S.hb[kk] = v;
+    }
+    mf_issue(S, 0, W0, B0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int u = 0; u < S.tiles; u += 2) {
+        mf_tile<FINAL>(S, u, W0, B0, W1, B1);
+        if (u + 1 < S.tiles) mf_tile<FINAL>(S, u + 1, W1, B1, W0, B0);
+    }
+}
+
+hipError_t launch_mlp_fused(const MlpFusedArgs &a, hipStream_t s) {
+    const dim3 grid((unsigned)((a.B + GF_ROWS - 1) / GF_ROWS)), block(512);
+    if (a.n_out > 0) hipLaunchKernelGGL(mlp_fused_kernel<true>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(mlp_fused_kernel<false>, grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+// wt[n][k'] = bf16(W[k][n]) for k' = permute ? mlp_permute_k(k) : k: the
+// transposed weights of a layer of the fused forward pass (W float [in][out])
+__global__ void mlp_weights_kernel(int in, int out, const float *W, int permute, uint16_t *wt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)in * out) return;
+    const int n = (int)(t / in), kp = (int)(t - (int64_t)n * in);
+    const int k = permute ? mlp_permute_k(kp) : kp;
+    wt[t] = f2bf(W[(int64_t)k * out + n]);
+}
+
+hipError_t launch_mlp_weights(int in, int out, const float *W, int permute, uint16_t *wt, hipStream_t s) {
+    const int64_t n = (int64_t)in * out;
+    hipLaunchKernelGGL(mlp_weights_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, out, W, permute,
+                       wt);
+    return hipGetLastError();
+}
+
 hipError_t launch_gate_fused(int B, int K, int D, int L, const uint16_t *h, int ldh, const uint16_t *wt, int ldw,
                              const float *bias, const float *e0, float y_scale, float s_clamp, float *partial,
                              float *layer_e, float *unc, float rho, uint32_t row_base, uint64_t seed,

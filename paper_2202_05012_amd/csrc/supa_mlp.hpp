@@ -23,4 +23,23 @@ struct GemmArgs {
     float cnt_scale;     //   mu > cnt_scale / e0[row] (null e0: no counts)
 };
 
+// Arguments of the fused forward pass (mlp_fused_kernel): an MLP of
+// n_hidden GELU layers 256 wide on k_in inputs, then either the last hidden
+// activations (n_out == 0) or a final linear layer of n_out outputs.
+constexpr int MLP_FUSED_MAX_HIDDEN = 8;
+struct MlpFusedArgs {
+    int B, k_in, n_hidden, n_out;
+    const uint16_t *x;   // bf16 [B][ldx], k_in columns
+    int ldx;
+    // layer l's weights transposed, bf16 [out][in]: in = k_in for l = 0, else
+    // 256 with the input index permuted (the order the previous layer's
+    // products leave the activations in registers)
+    const uint16_t *wt[MLP_FUSED_MAX_HIDDEN + 1];
+    const float *bias[MLP_FUSED_MAX_HIDDEN + 1];
+    float *out;          // n_out > 0: float [B][ldo]
+    int ldo;
+    uint16_t *h;         // n_out == 0: bf16 [B][ldh], the last hidden activations
+    int ldh;
+};
+
 }  // namespace supa

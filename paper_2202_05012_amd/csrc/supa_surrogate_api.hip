@@ -40,6 +40,8 @@ hipError_t launch_gate_fused(int B, int K, int D, int L, const uint16_t *h, int 
                              float *layer_e, float *unc, float rho, uint32_t row_base, uint64_t seed,
                              float cnt_thr, float *layer_cnt, const hipEvent_t *ev, hipStream_t s);
 hipError_t launch_transpose_bf16(int rows, int cols, const float *x, uint16_t *y, hipStream_t s);
+hipError_t launch_mlp_fused(const MlpFusedArgs &a, hipStream_t s);
+hipError_t launch_mlp_weights(int in, int out, const float *W, int permute, uint16_t *wt, hipStream_t s);
 size_t sort_work_bytes(int64_t n, int cols);
 hipError_t launch_sort_columns(const float *x, int64_t ld, int64_t n, int cols, void *work, uint32_t **sorted,
                                hipStream_t s);
@@ -237,6 +239,48 @@ extern "C" supa_status supa_surrogate_gate_fused(void *stream, int B, int K, int
                                "gate_fused");
     if (ev && st == SUPA_OK) g_gate_timing.recorded = true;
     return st;
+}
+
+extern "C" supa_status supa_mlp_forward_fused(void *stream, int B, int k_in, int n_hidden, const uint16_t *x,
+                                             int ldx, const uint16_t *const *wt, const float *const *bias, int n_out,
+                                             float *out, int ldo, uint16_t *h, int ldh) {
+    if (B < 0 || k_in < 16 || k_in > 256 || k_in % 16 || n_hidden < 1 || n_hidden > supa::MLP_FUSED_MAX_HIDDEN)
+        return bad("fused forward: k_in a multiple of 16 in [16, 256], 1 to 8 hidden layers");
+    if (n_out < 0 || n_out > 64 || n_out % 4) return bad("fused forward: n_out a multiple of 4 in [0, 64]");
+    if (ldx < k_in || ldx % 8) return bad("fused forward: ldx >= k_in, a multiple of 8");
+    if (n_out > 0 && (ldo < n_out || ldo % 4)) return bad("fused forward: ldo >= n_out, a multiple of 4");
+    if (n_out == 0 && (ldh < 256 || ldh % 4)) return bad("fused forward: ldh >= 256, a multiple of 4");
+    if (!wt || !bias) return bad("fused forward: NULL weight or bias list");
+    if (B == 0) return SUPA_OK;
+    if (!x || (n_out > 0 ? !out : !h)) return bad("fused forward: NULL input or output");
+    supa::MlpFusedArgs a{};
+    a.B = B;
+    a.k_in = k_in;
+    a.n_hidden = n_hidden;
+    a.n_out = n_out;
+    a.x = x;
+    a.ldx = ldx;
+    const int layers = n_hidden + (n_out > 0 ? 1 : 0);
+    uintptr_t align = (uintptr_t)x | (n_out > 0 ? (uintptr_t)out : (uintptr_t)h);
+    for (int l = 0; l < layers; ++l) {
+        if (!wt[l] || !bias[l]) return bad("fused forward: NULL weights or bias of a layer");
+        a.wt[l] = wt[l];
+        a.bias[l] = bias[l];
+        align |= (uintptr_t)wt[l];
+    }
+    if (align & 15) return bad("fused forward: x, weights and the output must be 16-byte aligned");
+    a.out = out;
+    a.ldo = ldo;
+    a.h = h;
+    a.ldh = ldh;
+    return dev(supa::launch_mlp_fused(a, (hipStream_t)stream), "mlp_forward_fused");
+}
+
+extern "C" supa_status supa_mlp_fused_weights(void *stream, int in, int out, const float *W, int permute,
+                                              uint16_t *wt) {
+    if (in < 1 || out < 1 || (permute && in % 32)) return bad("fused weights: bad sizes");
+    if (!W || !wt) return bad("fused weights: NULL pointer");
+    return dev(supa::launch_mlp_weights(in, out, W, permute ? 1 : 0, wt, (hipStream_t)stream), "mlp_fused_weights");
 }
 
 extern "C" supa_status supa_transpose_to_bf16(void *stream, int rows, int cols, const float *x, uint16_t *y) {

@@ -53,6 +53,8 @@ def _lib():
             "supa_sort_columns": [vp, i64, C.c_int32, vp, i64, vp, vp, i64],
             "supa_occupied_counts": [vp, i64, C.c_int32, C.c_int32, vp, f, vp],
             "supa_surrogate_timing": [i],
+            "supa_mlp_forward_fused": [vp, i, i, i, vp, i, vp, vp, i, vp, i, vp, i],
+            "supa_mlp_fused_weights": [vp, i, i, vp, i, vp],
             "supa_surrogate_last_times": [vp, C.c_int32],
         }
         for name, args in sig.items():
@@ -322,6 +324,51 @@ class MLP:
             h = y
         return h
 
+    def fused_ok(self):
+        """True when the fused forward pass takes this network: hidden layers
+        of 256 (1..8), inputs a multiple of 16 up to 256."""
+        hid = self.dims[1:-1]
+        return (1 <= len(hid) <= 8 and all(d == 256 for d in hid) and self.dims[0] % 16 == 0
+                and self.dims[0] <= 256)
+
+    def fused_weights(self):
+        """The layers' weights for the fused forward pass (transposed, inputs of
+        layers after the first permuted), cached per optimiser step."""
+        if getattr(self, "_fw_step", None) != self.step:
+            ws = []
+            for l, W in enumerate(self.W):
+                din, dout = W.shape
+                wt = torch.empty((dout, din), dtype=torch.int16, device=self.device)
+                _check(_lib().supa_mlp_fused_weights(_stream(), din, dout, _p(W), 1 if l > 0 else 0, _p(wt)))
+                ws.append(wt)
+            self._fw, self._fw_step = ws, self.step
+        return self._fw
+
+    def _fused(self, x, n_hidden, n_out, out, h):
+        ws = self.fused_weights()
+        layers = n_hidden + (1 if n_out else 0)
+        wt = (C.c_void_p * layers)(*[w.data_ptr() for w in ws[:layers]])
+        bs = (C.c_void_p * layers)(*[b.data_ptr() for b in self.b[:layers]])
+        _check(_lib().supa_mlp_forward_fused(_stream(), x.shape[0], self.dims[0], n_hidden, _p(x), x.stride(0),
+                                             C.cast(wt, C.c_void_p), C.cast(bs, C.c_void_p), n_out, _p(out),
+                                             out.stride(0) if out is not None else 0, _p(h),
+                                             h.stride(0) if h is not None else 0))
+
+    def forward_fused(self, x):
+        """The whole forward pass in one kernel (supa_mlp_forward_fused; the
+        output layer at most 64 wide): x bf16 [B, in] -> float32 [B, out]."""
+        n_out = self.dims[-1]
+        out = torch.empty((x.shape[0], n_out), dtype=torch.float32, device=self.device)
+        self._fused(x, len(self.dims) - 2, n_out, out, None)
+        return out
+
+    def hidden_fused(self, x):
+        """The hidden layers in one kernel: x bf16 [B, in] -> the last hidden
+        activations, bf16 [B, 256]."""
+        h = torch.empty((x.shape[0], 256), dtype=torch.int16, device=self.device)
+        self._fused(x, len(self.dims) - 2, 0, None, h)
+        return h
+
     def final_weights_t(self):
         """bf16 transpose of the final layer's weights (cached per optimiser step)."""
         if getattr(self, "_wt_step", None) != self.step:
@@ -333,7 +380,8 @@ class MLP:
         """Per-layer energies and uncertainty scores of the inputs x (and, with
         cnt_thr, per-layer counts of bins predicted above it), with the final
         layer fused into the gate (no [B, 2D] output)."""
-        return gate_fused(self.hidden(x), self.final_weights_t(), self.b[-1], e0, n_layers, rho=rho,
+        h = self.hidden_fused(x) if self.fused_ok() else self.hidden(x)
+        return gate_fused(h, self.final_weights_t(), self.b[-1], e0, n_layers, rho=rho,
                           seed=seed, row_base=row_base, cnt_thr=cnt_thr)
 
     def backward(self, acts, pres, dout):

@@ -128,7 +128,7 @@ def head_layer_energies(head: S.MLP, e0, pol, az, seed, chunk=1 << 20, row_base=
     for s in range(0, n, chunk):
         sl = slice(s, min(n, s + chunk))
         x = S.features(e0[sl], pol[sl], az[sl], seed, row_base=row_base + s, stream_id=2)
-        le, u, _ = S.gate(head.forward(x), e0[sl], N_LAYERS, rho=0.0, seed=seed, row_base=row_base + s,
+        le, u, _ = S.gate(head.forward_fused(x), e0[sl], N_LAYERS, rho=0.0, seed=seed, row_base=row_base + s,
                           y_scale=Y_SCALE_HEAD)
         layer_e[sl] = le
         unc[sl] = u

@@ -553,3 +553,72 @@ def test_occupied_counts():
     got = S.occupied_counts(torch.from_numpy(img).cuda(), L, 0.01).cpu().numpy()
     want = (img.reshape(rows, L, g) > np.float32(0.01)).sum(axis=2)
     np.testing.assert_array_equal(got, want)
+
+
+def fused_chain_bound(x, Ws, bs, n_hidden, final):
+    """The FP64 forward chain of an MLP on bf16 inputs and weights (no rounding
+    of the activations) and a bound on how far a device pass may be from it
+    per element: each hidden activation is rounded to bf16 (2^-8 relative)
+    after a float32 sum (2e-6 * sum |a||w|), GELU is 1.13-Lipschitz and is
+    evaluated through an erfc approximation of absolute error 1.5e-7 (Phi off
+    by 1e-7 with the float rounding of its terms, GELU by 1e-7 |z|), and the
+    errors of a layer's inputs pass through |W|."""
+    a, err = x, np.zeros_like(x)
+    for l in range(n_hidden):
+        z = a @ Ws[l] + bs[l]
+        acc = 2e-6 * (np.abs(a) @ np.abs(Ws[l])) + 1e-7
+        g = SO.gelu(z)
+        err = 2.0 ** -8 * np.abs(g) + 1e-7 * np.abs(z) + 1.13 * (acc + err @ np.abs(Ws[l]))
+        a = g
+    if not final:
+        return a, err
+    out = a @ Ws[n_hidden] + bs[n_hidden]
+    return out, err @ np.abs(Ws[n_hidden]) + 2e-6 * (np.abs(a) @ np.abs(Ws[n_hidden])) + 1e-7
+
+
+@pytest.mark.parametrize("dims,B,final", [([32, 256, 40], 1000, True), ([32, 256, 256, 8], 776, False),
+                                          ([64, 256, 256, 64], 296, True),
+                                          ([32, 256, 256, 256, 256, 40], 2048, True),
+                                          ([32, 256, 256, 256, 256, 10240], 1496, False)])
+def test_mlp_fused_matches_fp64(dims, B, final):
+    """The fused forward pass (supa_mlp_forward_fused: activations kept in
+    registers through all layers, the inputs of every layer after the first
+    in the permuted order) against the FP64 chain on the same bf16 inputs and
+    weights, element by element within the propagated rounding bound; output
+    layers of 40 and 64 units, or the last hidden activations; batches ragged
+    against the 256-row workgroups.  Also the same as the layer-by-layer
+    products (supa_gemm_bf16) within that bound."""
+    rng = np.random.default_rng(sum(dims) + B)
+    net = S.MLP(dims, seed=5)
+    for l in range(len(dims) - 1):
+        net.b[l].copy_(torch.from_numpy(rng.normal(0, 0.2, dims[l + 1]).astype(np.float32)))
+    x = bf16_round(rng.normal(size=(B, dims[0])))
+    tx = dev16(x)
+    n_hidden = len(dims) - 2             # without `final`: the hidden activations only
+    Wf = [bf16_to_np(host16(w)).astype(np.float64) for w in net.Wb]
+    bf = [b.cpu().numpy().astype(np.float64) for b in net.b]
+    ref, bound = fused_chain_bound(bf16_to_np(x).astype(np.float64), Wf, bf, n_hidden, final)
+    if final:
+        got = net.forward_fused(tx).cpu().numpy().astype(np.float64)
+        unfused = net.forward(tx).cpu().numpy().astype(np.float64)
+    else:
+        got = bf16_to_np(host16(net.hidden_fused(tx))).astype(np.float64)
+        unfused = bf16_to_np(host16(net.hidden(tx))).astype(np.float64)
+    assert got.shape == ref.shape
+    assert (np.abs(got - ref) <= bound).all(), float((np.abs(got - ref) / bound).max())
+    assert (np.abs(got - unfused) <= 2 * bound).all()
+    assert np.linalg.norm(got - ref) <= 1e-2 * np.linalg.norm(ref)
+
+
+def test_mlp_fused_weights_permutation():
+    """supa_mlp_fused_weights: the transpose to bf16, with the input index's
+    bits 2 and 3 swapped when permuting."""
+    rng = np.random.default_rng(8)
+    W = rng.normal(size=(64, 24)).astype(np.float32)
+    for perm in (0, 1):
+        wt = torch.empty((24, 64), dtype=torch.int16, device="cuda")
+        S._check(S._lib().supa_mlp_fused_weights(S._stream(), 64, 24, S._p(torch.from_numpy(W).cuda()), perm,
+                                                 S._p(wt)))
+        k = np.arange(64)
+        src = ((k & ~12) | ((k & 4) << 1) | ((k & 8) >> 1)) if perm else k
+        assert np.array_equal(host16(wt), bf16_round(W.T[:, src]))
