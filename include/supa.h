@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define SUPA_ABI_VERSION 5
+#define SUPA_ABI_VERSION 6
 
 typedef enum supa_status {
     SUPA_OK = 0,
@@ -303,6 +303,49 @@ supa_status supa_set_launch(supa_ctx *ctx, int32_t waves_per_cu, int32_t frontie
  *                order; -1 (default): automatic.
  */
 supa_status supa_set_schedule(supa_ctx *ctx, int32_t sub_batches, int32_t cost_order);
+
+/*
+ * Subtree work items (affect speed only, never results; section "Propagation
+ * Model": a particle's further history depends only on its own state, its
+ * plane and its path id, not on the rest of its shower, so any wave can
+ * finish it).  With phases > 1 a call runs that many propagation launches on
+ * its stream.  In every launch but the last, a wave whose pool of pending
+ * particles holds export_pool + 64 or more entries takes its 64 oldest, and
+ * those of the shower with most of them (at least 16) leave the wave as one
+ * item; the next launch hands the items out to all its waves.  The shower
+ * then becomes shared: a device record collects the tallies of every party
+ * working on it, the last party to finish writes its ledger and counts, its
+ * hit records continue one run of the hit log (chunks reserved for it when
+ * it is shared), and with a tree its node indices are taken from a shared
+ * counter, so node numbering and the order of records within a plane may
+ * differ from a call without items (the sets are the same).  Showers of a
+ * small batch then spread over all waves instead of the few that started
+ * them.  A wave exports only once its claim for new showers has come back
+ * empty (while showers remain to be started every wave is busy anyway).
+ *   phases       0 (default): automatic -- 2 when the batch's showers all
+ *                start at once on at most a quarter of the waves (4 n <= the
+ *                waves launched), the kinematics are plain and no sub-batches
+ *                are asked for, else 1; 1: no items; 2 .. 4: that many
+ *                launches;
+ *   export_pool  pending particles beyond one step (64) from which a wave
+ *                exports (default 0: every wave with 64 or more).
+ * Items need the plain kinematics without regional parameters (INVALID_ARG
+ * for phases > 1 otherwise; automatic then means 1).  A call with items runs
+ * as one sub-batch; supa_simulate_noalloc decides automatic as 1.  Items and shared
+ * showers are bounded per call (16,384 each; 1,024 with
+ * supa_simulate_noalloc); beyond that waves keep their particles.  A shared
+ * shower whose hits outgrow the reserve is rerun with a larger one
+ * (bit-identical sets; SUPA_ERR_NOMEM from supa_simulate_noalloc).
+ */
+supa_status supa_set_subtrees(supa_ctx *ctx, int32_t phases, int32_t export_pool);
+
+/*
+ * Subtree work items of the context's last supa_simulate or
+ * supa_simulate_noalloc call (or the last supa_graph_check): counts5 (host,
+ * 5 int64) receives the showers that became shared, then the items exported
+ * by launches 0 .. 3.  All zero without items.
+ */
+supa_status supa_last_subtrees(const supa_ctx *ctx, int64_t *counts5);
 
 /*
  * Picks launch settings by measurement: runs the batch under every

@@ -62,6 +62,11 @@ struct DevBuf {
 };
 
 static constexpr int kMaxImageWidth = 1024;
+// subtree work items: items per launch phase and shared showers per call
+// (context scratch; the fixed array holds fewer).  When they run out, waves
+// stop exporting and finish their showers themselves.
+static constexpr int kItemCap = 16384, kShareCap = 16384;
+static constexpr int kFixedItemCap = 1024, kFixedShareCap = 1024;
 static constexpr int64_t kAutoOrderMin = 65536;     // automatic cost order: from this batch size
 
 // Scratch of supa_simulate_noalloc: one fixed array per GPU, held from the
@@ -121,6 +126,14 @@ struct supa_ctx {
     int64_t h_chunks = 0, n_chunks = 0;  // log chunks (grow on demand)
     int sub_batches = 0;                 // 0: chosen from the batch size
     int cost_order = -1;                 // hand out expensive showers first: 1 on, 0 off, -1 auto
+    // subtree work items: propagation launches per call (1: none), the pool
+    // size beyond one step from which a wave exports, the reserve of hit-log
+    // chunks per shared shower relative to its expected hits
+    int phases = 0;                      // 0: automatic
+    int export_top = 0;
+    float share_margin = 1.5f;
+    DevBuf items, shares;
+    int64_t last_item_cap = 0, last_share_cap = 0;   // of the last prepared call
     int last_sub_batches = 0;
     DevBuf spill, hlog, nlog, shower, bucket;
     // second set of the buffers that the propagation of one call writes while
@@ -383,7 +396,7 @@ extern "C" supa_status supa_destroy(supa_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     if (c->aux) (void)hipStreamSynchronize(c->aux);
     for (DevBuf *d : {&c->spill, &c->hlog, &c->nlog, &c->shower, &c->bucket, &c->hlog2, &c->nlog2, &c->hstart2,
-                      &c->snap, &c->d_calls})
+                      &c->snap, &c->d_calls, &c->items, &c->shares})
         d->release();
     if (c->h_snap) (void)hipHostFree(c->h_snap);
     if (c->h_calls) (void)hipHostFree(c->h_calls);
@@ -438,6 +451,28 @@ extern "C" supa_status supa_set_schedule(supa_ctx *c, int32_t sub_batches, int32
     if (cost_order < -1 || cost_order > 1) return fail(c, SUPA_ERR_INVALID_ARG, "cost_order must be -1, 0 or 1");
     c->sub_batches = sub_batches;
     c->cost_order = cost_order;
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_set_subtrees(supa_ctx *c, int32_t phases, int32_t export_pool) {
+    if (!c) return SUPA_ERR_STATE;
+    if (phases < 0 || phases > supa::MAX_PHASES)
+        return fail(c, SUPA_ERR_INVALID_ARG, "phases must be in [0, " + std::to_string(supa::MAX_PHASES) + "]");
+    if (export_pool < 0 || export_pool > 1 << 20)
+        return fail(c, SUPA_ERR_INVALID_ARG, "export_pool must be in [0, 2^20]");
+    if (phases > 1 && (c->g.kinematics == SUPA_KIN_LITERAL || c->g.n_regions >= 2))
+        return fail(c, SUPA_ERR_INVALID_ARG, "subtree work items need the plain kinematics without regional parameters");
+    c->phases = phases;
+    c->export_top = export_pool;
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_last_subtrees(const supa_ctx *c, int64_t *counts5) {
+    if (!c) return SUPA_ERR_STATE;
+    if (!counts5) return SUPA_ERR_INVALID_ARG;
+    counts5[0] = std::min<int64_t>((int64_t)c->h_ctr[supa::CTR_ST_SHARES], c->last_share_cap);
+    for (int p = 0; p < supa::MAX_PHASES; ++p)
+        counts5[1 + p] = std::min<int64_t>((int64_t)c->h_ctr[supa::ctr_st_out(p)], c->last_item_cap);
     return SUPA_OK;
 }
 
@@ -551,7 +586,7 @@ static supa_status check_call(supa_ctx *c, const supa_batch *b, supa_output *out
 // Everything one call launches: parameters and scratch pointers.
 struct Plan {
     bool tree, hits_out, images, recs, post;
-    int N, nsub;
+    int N, nsub, phases;
     int64_t n, waves, img_words;
     supa::Params P;
     float e_unscale;
@@ -587,7 +622,17 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
     // sub-batches: the placement of sub-batch j (aux stream) overlaps the
     // propagation of sub-batch j+1 (the context's stream); one by default
     int nsub = force_nsub > 0 ? force_nsub : (c->sub_batches > 0 ? c->sub_batches : 1);
-    if (!L.post) nsub = 1;
+    // subtree work items: automatic (0) = one export round when every shower
+    // of the batch starts at once on at most a quarter of the waves (the
+    // rest would idle behind the largest showers) and nothing else asks for
+    // the single-launch path; measured to cost more than it saves once the
+    // showers fill the waves
+    const bool plain = c->g.kinematics != SUPA_KIN_LITERAL && c->g.n_regions < 2;
+    int phases = c->phases;
+    if (phases == 0)
+        phases = (plain && !fixed && nsub <= 1 && force_nsub <= 1 && (int64_t)supa::SLOTS * n <= L.waves) ? 2 : 1;
+    L.phases = plain ? phases : 1;
+    if (!L.post || L.phases > 1) nsub = 1;
     L.nsub = (int)std::min<int64_t>(std::min(nsub, supa::MAX_SUB), n);
     // the placement kernel's variant (with path ids): sizes and launch must agree
     L.place_keys = L.hits_out && (outs & SUPA_OUT_KEYS) && out->hit_key != nullptr;
@@ -605,6 +650,9 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
                                 &bucket_blocks);
     const size_t hit_chunk_b = (size_t)supa::HIT_CHUNK_WORDS * 4, node_chunk_b = (size_t)supa::NL_FIELDS * supa::LOG_CHUNK * 4;
     char *sh = nullptr, *spill_p = nullptr, *hlog_p = nullptr, *nlog_p = nullptr;
+    char *items_p = nullptr, *shares_p = nullptr;
+    int item_cap = 0, share_cap = 0;
+    const bool subtrees = L.phases > 1;
     uint2 *bucket_p = nullptr;
     int32_t bucket_cap = 0;
     int spill_cap = c->spill_cap;
@@ -627,6 +675,16 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
             if (!c->bucket.ensure(bb, &c->scratch_gen)) return nomem(c, "image buckets", bb);
             bucket_p = (uint2 *)c->bucket.p;
             bucket_cap = (int32_t)bucket_per;
+        }
+        if (subtrees) {
+            const size_t items_b = (size_t)2 * kItemCap * supa::ITEM_WORDS * 4;
+            const size_t shares_b = (size_t)kShareCap * supa::SHARE_WORDS * 4;
+            if (!c->items.ensure(items_b, &c->scratch_gen)) return nomem(c, "subtree items", items_b);
+            if (!c->shares.ensure(shares_b, &c->scratch_gen)) return nomem(c, "share records", shares_b);
+            items_p = (char *)c->items.p;
+            shares_p = (char *)c->shares.p;
+            item_cap = kItemCap;
+            share_cap = kShareCap;
         }
         sh = (char *)c->shower.p;
         spill_p = (char *)c->spill.p;
@@ -651,12 +709,22 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
         L.waves = std::min<int64_t>(L.waves, (n + supa::SLOTS - 1) / supa::SLOTS);
         const int64_t per_entry = L.waves * supa::POOL_FIELDS * 4;
         spill_cap = (int)std::min<int64_t>(c->spill_cap, (int64_t)(kFixedBytes / 8) / per_entry);
+        // with exports the spill area is a ring indexed modulo its size
+        if (subtrees)
+            while (spill_cap & (spill_cap - 1)) spill_cap &= spill_cap - 1;
         spill_p = take((size_t)per_entry * spill_cap);
         if (!spill_p) return fail(c, SUPA_ERR_NOMEM, "no room left for the particle spill area in the fixed scratch array");
         if (bucket_per > 0) {
             bucket_cap = (int32_t)std::min<int64_t>(bucket_per, (int64_t)(kFixedBytes / 8) / (bucket_blocks * 8));
             bucket_p = bucket_cap > 0 ? (uint2 *)take((size_t)bucket_cap * bucket_blocks * 8) : nullptr;
             if (!bucket_p) bucket_cap = 0;
+        }
+        if (subtrees) {
+            items_p = take((size_t)2 * kFixedItemCap * supa::ITEM_WORDS * 4);
+            shares_p = take((size_t)kFixedShareCap * supa::SHARE_WORDS * 4);
+            if (!items_p || !shares_p) return fail(c, SUPA_ERR_NOMEM, "no room left for subtree items in the fixed scratch array");
+            item_cap = kFixedItemCap;
+            share_cap = kFixedShareCap;
         }
         // the logs share what is left, in proportion to what the caller's
         // capacities suggest they need
@@ -716,6 +784,16 @@ static supa_status prepare(supa_ctx *c, const supa_batch *b, uint64_t seed, supa
     L.ctr = c->d_ctr + (set ? supa::CTR_WORDS : 0);
     P.ctr = L.ctr;
     P.sub = nullptr;
+    P.phase = 0;
+    P.last_phase = subtrees ? L.phases - 1 : 0;
+    P.export_top = c->export_top;
+    P.items = (uint32_t *)items_p;
+    P.item_cap = item_cap;
+    P.shares = (uint32_t *)shares_p;
+    P.share_cap = share_cap;
+    P.share_margin = c->share_margin;
+    c->last_item_cap = item_cap;
+    c->last_share_cap = share_cap;
     L.e_unscale = std::ldexp(1.0f, -c->g.energy_frac_bits);
 
     // the per-sub-batch input/output blocks, staged on the host
@@ -765,6 +843,12 @@ static supa_status enqueue(supa_ctx *c, const supa_batch *b, supa_output *out, c
                                                c->n_cu, s_main));
         if (timed) HIP_TRY(c, hipEventRecord(ev_prop[j][0], s_main));
         HIP_TRY(c, supa::launch_propagate(Pj, c->g.kinematics == SUPA_KIN_LITERAL, c->g.n_regions >= 2, (int)L.waves, s_main));
+        // later launches finish the subtree items the previous one exported
+        for (int ph = 1; ph <= P.last_phase; ++ph) {
+            supa::Params Pp = Pj;
+            Pp.phase = ph;
+            HIP_TRY(c, supa::launch_propagate(Pp, false, false, (int)L.waves, s_main));
+        }
         if (L.tree) HIP_TRY(c, supa::launch_note_chunks(L.ctr, sub_ctr(j), s_main));
         // the second stream waits on this event (none inside a capture, where
         // both are one stream)
@@ -853,10 +937,18 @@ static int finish(supa_ctx *c, const Plan &L, supa_output *out, bool fixed = fal
         return fail(c, SUPA_ERR_RANGE, "an initial energy is negative, NaN or too large for the fixed-point format");
     const unsigned long long *last = h + supa::CTR_BLOCK * L.nsub;    // running totals
     const int64_t total_hits = (int64_t)last[supa::SUB_HITS], total_nodes = (int64_t)last[supa::SUB_NODES];
-    if ((flags & supa::FLAG_OVERFLOW) && fixed)
+    if ((flags & (supa::FLAG_OVERFLOW | supa::FLAG_SHARE)) && fixed)
         return fail(c, SUPA_ERR_NOMEM, "the batch needs more scratch (particle spill, hit or node log) than the "
                                        "fixed array of " + std::to_string(kFixedBytes) + " bytes holds: run it in "
                                        "smaller calls, or with supa_simulate");
+    if (flags & supa::FLAG_SHARE) {
+        // a shared shower outgrew the hit-log chunks reserved for it (the
+        // records that did not fit were dropped): rerun with a larger reserve
+        if (c->share_margin >= 64.0f)
+            return fail(c, SUPA_ERR_DEVICE, "shared showers' hit reserves did not converge");
+        c->share_margin *= 2.0f;
+        if (!(flags & supa::FLAG_OVERFLOW)) return -1;
+    }
     if (flags & supa::FLAG_OVERFLOW) {
         // grow what ran out: the spill area to the largest pool seen, a log
         // to the totals (exact unless the spill overflowed too)

@@ -131,6 +131,18 @@ struct Params {
     int32_t h_chunks, n_chunks;
     unsigned long long *ctr;    // the call's counters (CTR_*)
     unsigned long long *sub;    // the sub-batch's counters (SUB_*)
+    // subtree work items (section "Propagation Model": a particle's subtree
+    // depends only on its own state and path id, so it can be finished by
+    // any wave).  Launch `phase` 0 runs the showers; launch p >= 1 runs the
+    // items that launch p-1 exported.  Launches before `last_phase` export
+    // pending particles of a shower whose pool holds export_top + WAVE or
+    // more entries; export_top < 0 disables it.
+    int32_t phase, last_phase, export_top;
+    uint32_t *items;            // two regions of item_cap items, ITEM_WORDS each
+    int32_t item_cap;
+    uint32_t *shares;           // share_cap records of SHARE_WORDS
+    int32_t share_cap;
+    float share_margin;         // hit-log chunks reserved per shared shower / expected
 };
 
 // Offsets of the showers' segments: exclusive prefix sums of their hit and
@@ -203,14 +215,40 @@ enum {
     SUB_NCHUNK_END = 3   // node-log chunks claimed when the sub-batch's propagation ended
 };
 constexpr int MAX_SUB = 8;
-constexpr int CTR_WORDS = CTR_BLOCK * (1 + MAX_SUB);
+// Subtree work items: after the sub-batch blocks, the shares handed out,
+// then per launch phase the items it exported and the items claimed from it.
+constexpr int MAX_PHASES = 4;
+constexpr int CTR_ST = CTR_BLOCK * (1 + MAX_SUB);
+constexpr int CTR_ST_SHARES = CTR_ST;
+__host__ __device__ constexpr int ctr_st_out(int phase) { return CTR_ST + 1 + phase; }
+__host__ __device__ constexpr int ctr_st_claim(int phase) { return CTR_ST + 1 + MAX_PHASES + phase; }
+constexpr int CTR_WORDS = CTR_ST + 1 + 2 * MAX_PHASES;
 
-enum { FLAG_OVERFLOW = 1, FLAG_RANGE = 2, FLAG_INTERNAL = 4 };
+enum { FLAG_OVERFLOW = 1, FLAG_RANGE = 2, FLAG_INTERNAL = 4, FLAG_SHARE = 8 };
+
+// A shared shower: one whose pending particles were handed to other waves as
+// work items.  Every party (the wave that started the shower, and each item)
+// adds its tallies here when its last particle is done; the party that
+// brings `SH_OUT` to zero writes the shower's ledger, counts and log start.
+// Hit records of all parties continue the shower's run of the log: from the
+// conversion point (SH_CONV_C, SH_CONV_F) to the end of that chunk, then
+// through SH_KCAP chunks reserved and linked at conversion (SH_BASE ...), at
+// positions taken from SH_FILL.  With a tree, node indices come from SH_NODES.
+enum {
+    SH_I = 0, SH_SID, SH_E0, SH_HS_LO, SH_HS_HI, SH_FILL, SH_CONV_C, SH_CONV_F, SH_BASE, SH_KCAP,
+    SH_NODES, SH_HITS, SH_PASSES, SH_ESC, SH_BACK, SH_EESC, SH_ECUT, SH_ESTOP, SH_OUT, SH_FIELDS
+};
+constexpr int SHARE_WORDS = 32;
+static_assert(SH_FIELDS <= SHARE_WORDS, "share record fits");
+// An item: up to 64 pending particles of one shared shower, as pool fields
+// [POOL_FIELDS][64] (KS = plane | share << 8), then the count.
+constexpr int ITEM_WORDS = 9 * 64 + 1;
+constexpr int ITEM_MIN = 16;          // fewer particles of one shower are not exported
 
 // true when the propagation of this call failed (its outputs are rerun or
 // discarded): the later kernels then write nothing
 __device__ __forceinline__ bool batch_failed(const unsigned long long *ctr) {
-    return (ctr[CTR_FLAGS] & (unsigned long long)(FLAG_OVERFLOW | FLAG_RANGE | FLAG_INTERNAL)) != 0;
+    return (ctr[CTR_FLAGS] & (unsigned long long)(FLAG_OVERFLOW | FLAG_RANGE | FLAG_INTERNAL | FLAG_SHARE)) != 0;
 }
 
 constexpr int SLOTS = 4;              // showers in flight per wave
@@ -218,6 +256,7 @@ constexpr int QCAP = 128;             // draw-queue entries per wave
 
 // fields of a pending particle (pool, draw queue, spill); KS = plane | slot << 8
 enum { PF_X = 0, PF_Y, PF_TX, PF_TY, PF_E, PF_LO, PF_HI, PF_NODE, PF_KS, POOL_FIELDS };
+static_assert(ITEM_WORDS == POOL_FIELDS * 64 + 1, "item layout");
 
 // ---------------------------------------------------------------------------
 // Single-precision elementary functions for the split kinematics.

@@ -23,6 +23,10 @@
 // arrays and bins the images; tree nodes go through a log of their own.
 // Results depend only on (seed, shower id, path id): the random stream is
 // keyed by the particle, not by the lane or wave that happens to process it.
+// That also lets a shower be split: with subtree work items (SUB), a wave
+// whose pool grows hands its oldest pending particles of one shower to a
+// later launch as an item; any wave there finishes their subtrees, and the
+// shower's tallies meet in a share record (supa_device.hpp).
 #include "supa_device.hpp"
 
 namespace supa {
@@ -171,7 +175,9 @@ struct Slots {
     int hits, nodes, passes, escaped, backward;
     uint32_t e_esc;  // escaped energy (fits: energies of a shower sum to e0)
     int hc, hf;      // the slot's hit-log chunk (-1: none) and its fill
-    int hs_c, hs_f;  // where the shower's first hit record goes
+    int hs_c, hs_f;  // where the shower's first hit record goes (shared
+                     // showers: the reserved chunks' base and count)
+    int sh;          // share record of a shared shower, -1 otherwise
 };
 
 __device__ __forceinline__ int slot_get(int v, int s) { return __builtin_amdgcn_readlane(v, s); }
@@ -205,11 +211,14 @@ __device__ __forceinline__ int wave_excl_scan(int v) {
     return incl - v;
 }
 
+// parameters of subtree work items, kept in LDS (the scalar file is full)
+enum { SL_EXPORT = 0, SL_PHASE, SL_ITEMS_IN, SL_ITEM_CAP, SL_SHARE_CAP, SL_MARGIN, SL_ITEMS, SL_SHARES = SL_ITEMS + 2,
+       SUB_LDS_WORDS = 16 };
 // LDS words of one wave: pool + the stop / split thresholds of every plane
 // pool, then the thresholds c1, c2 (u64) of 64 planes, of 4 rings with
 // regional parameters
 __host__ __device__ constexpr int lds_words(int pool_cap, bool rings = false) {
-    return POOL_FIELDS * pool_cap + 2 * 2 * 64 * (rings ? 4 : 1);
+    return POOL_FIELDS * pool_cap + 2 * 2 * 64 * (rings ? 4 : 1) + SUB_LDS_WORDS;
 }
 
 // Keeps a wave-uniform value in scalar registers but hides it from loop-
@@ -247,15 +256,16 @@ struct SlotSums {
 // TREE: node records; KEYS: path ids with hit and node records; LIT: literal
 // Algorithm 1 kinematics; REG: regional parameters (rings) (compile-time, so
 // that no flag occupies a scalar register through the loop)
-template <bool TREE, bool KEYS, int PC, bool LIT, bool REG>
+template <bool TREE, bool KEYS, int PC, bool LIT, bool REG, bool SUB>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) supa_propagate(Params P) {
     extern __shared__ uint32_t lds[];
     const uint32_t lane = lane_id();
     const int64_t wave = blockIdx.x;
     const int N = P.n_planes;
     // the wave's start on the constant-rate clock (stored at once: nothing is
-    // held through the loop)
-    if (lane == 0 && COLD(wave_clk)) COLD(wave_clk)[2 * wave] = (unsigned long long)wall_clock64();
+    // held through the loop); the first launch of a call only
+    if (lane == 0 && COLD(wave_clk) && (!SUB || P.phase == 0))
+        COLD(wave_clk)[2 * wave] = (unsigned long long)wall_clock64();
     // PC: pool entries in LDS, a power of two >= 2 * WAVE (compile-time, so
     // that the field offsets are instruction immediates)
     uint32_t *const pool = lds;            // [POOL_FIELDS][PC], entry j at slot j & (PC-1)
@@ -267,6 +277,23 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
         thr[k] = in ? P.c1[k] : 0ull;
         thr[TN + k] = in ? P.c2[k] : 0ull;
     }
+    // subtree parameters: export threshold (-1: none in this launch), launch
+    // phase, items exported by the previous launch, capacities, buffers
+    uint32_t *const sub_l = (uint32_t *)(thr + 2 * TN);
+    if (SUB && lane == 0) {
+        const int ph = P.phase;
+        sub_l[SL_EXPORT] = (uint32_t)((ph < P.last_phase && P.export_top >= 0) ? P.export_top : -1);
+        sub_l[SL_PHASE] = (uint32_t)ph;
+        const unsigned long long got =
+            ph > 0 ? __hip_atomic_load(&P.ctr[ctr_st_out(ph - 1)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+        sub_l[SL_ITEMS_IN] = (uint32_t)min<unsigned long long>(got, (unsigned long long)P.item_cap);
+        sub_l[SL_ITEM_CAP] = (uint32_t)P.item_cap;
+        sub_l[SL_SHARE_CAP] = (uint32_t)P.share_cap;
+        sub_l[SL_MARGIN] = __float_as_uint(P.share_margin);
+        *(uint64_t *)(sub_l + SL_ITEMS) = (uint64_t)(uintptr_t)P.items;
+        *(uint64_t *)(sub_l + SL_SHARES) = (uint64_t)(uintptr_t)P.shares;
+    }
+    if (SUB) __syncthreads();
     float rr1 = 0.f, rr2 = 0.f, rr3 = 0.f;        // squared ring radii
     if constexpr (REG) {
         const volatile __attribute__((address_space(1))) Cold *cp =
@@ -298,13 +325,15 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
     S.e_esc = 0u;
     S.hc = S.hs_c = -1;
     S.hf = S.hs_f = 0;
+    S.sh = -1;
     // per-lane partial sums of the energy each slot's shower deposited by
     // cuts and by stops (a shower's energies sum to e0 < 2^32)
     SlotSums ecut, estop;
     ecut.zero();
     estop.zero();
 
-    int top = 0, lo = 0, max_top = 0;
+    // pool: logical entries [bot, top); bot > 0 only after exports
+    int top = 0, lo = 0, max_top = 0, bot = 0;
     bool exhausted = false, overflow = false;
     unsigned long long steps = 0;
     const float zf = P.z_first, dzp = P.dz;
@@ -401,10 +430,12 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
     uint32_t w_e = 0u;
     float w_x = 0.f, w_y = 0.f, w_tx = 0.f, w_ty = 0.f;
 
-    // ---- pool access: logical entries [lo, top) are in LDS, [0, lo) spilled
+    // ---- pool access: logical entries [lo, top) are in LDS, [bot, lo)
+    // spilled (with exports the spill area is a ring: G is a power of two)
+    auto spill_at = [&](int j) -> int { return SUB ? (j & (G - 1)) : j; };
     auto pool_load = [&](int j) -> Entry {
         if (j >= lo) return load_entry(pool, PC, j & (PC - 1));
-        if (j < G) return load_entry(spill, (int64_t)opaque_u32((uint32_t)G), j);
+        if (j - bot < G) return load_entry(spill, (int64_t)opaque_u32((uint32_t)G), spill_at(j));
         overflow = true;          // was never stored: the batch is rerun
         return Entry{0.f, 0.f, 0.f, 0.f, 0u, 0u, 0u, 0, 0u};
     };
@@ -412,18 +443,131 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
         const int sl = j & (PC - 1);
         if (j - PC >= lo) {            // slot holds live entry j - PC: move it out
             const Entry old = load_entry(pool, PC, sl);
-            if (j - PC < G) store_entry(spill, (int64_t)opaque_u32((uint32_t)G), j - PC, old);
+            if (j - PC - bot < G) store_entry(spill, (int64_t)opaque_u32((uint32_t)G), spill_at(j - PC), old);
             else overflow = true;
         }
         store_entry(pool, PC, sl, p);
     };
+    // rewrites live entry j where it is (LDS or spill)
+    auto pool_put = [&](int j, const Entry &p) {
+        if (j >= lo) store_entry(pool, PC, j & (PC - 1), p);
+        else if (j - bot < G) store_entry(spill, (int64_t)opaque_u32((uint32_t)G), spill_at(j), p);
+        else overflow = true;
+    };
+    // share records and items (subtree work items)
+    auto share_ptr = [&](int sh, int f) -> uint32_t * {
+        uint32_t *base = (uint32_t *)(uintptr_t)(*(const uint64_t *)(sub_l + SL_SHARES));
+        return base + (int64_t)sh * SHARE_WORDS + f;
+    };
+    auto share_load = [&](int sh, int f) -> uint32_t {
+        return __hip_atomic_load(share_ptr(sh, f), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    // Turns the shower of slot q into a shared one: a share record holding
+    // its identity, where its hit run continues (the rest of the slot's
+    // current chunk, then kc chunks reserved and linked now, enough for the
+    // expected hits of its energy times the margin) and, with a tree, the
+    // next node index (every other tally is added by each party at its end).
+    // Returns the share, or -1 (no share or log room left: not exported).
+    auto convert = [&](int q) -> int {
+        unsigned long long g = 0;
+        if (lane == 0) g = atomicAdd(&P.ctr[CTR_ST_SHARES], 1ull);
+        const uint32_t sh = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)g);
+        if (sh >= (uint32_t)__builtin_amdgcn_readfirstlane((int)sub_l[SL_SHARE_CAP])) return -1;
+        const int hc = slot_get(S.hc, q), hf = slot_get(S.hf, q);
+        const uint32_t e0q = (uint32_t)slot_get((int)S.e0, q);
+        int base = 0, kc = 0;
+        if (recs) {
+            // a shower of E splits until its parts fall below the threshold:
+            // about 2 E / threshold deposits
+            const float margin = __uint_as_float(sub_l[SL_MARGIN]);
+            const float want = P.t_cut > 0ull ? 2.0f * (float)e0q / (float)P.t_cut : 1048576.0f;
+            kc = (int)fminf(4096.0f, ceilf(margin * (want + 256.0f) * (1.0f / HIT_CHUNK)) + 1.0f);
+            kc = __builtin_amdgcn_readfirstlane(max(kc, 2));
+            unsigned long long gb = 0;
+            if (lane == 0) gb = atomicAdd(&P.ctr[CTR_HCHUNK], (unsigned long long)kc);
+            base = __builtin_amdgcn_readfirstlane((int)(uint32_t)gb);
+            if ((int64_t)(uint32_t)base + kc > (int64_t)P.h_chunks) {
+                hlog_full = true;
+                overflow = true;        // rerun with a larger log
+                return -1;
+            }
+            for (int t = (int)lane; t < kc - 1; t += WAVE) P.hnext[base + t] = (uint32_t)(base + t + 1);
+            if (lane == 0 && hc >= 0) P.hnext[hc] = (uint32_t)base;
+        }
+        const int hs_c = slot_get(S.hs_c, q), hs_f = slot_get(S.hs_f, q);
+        const int64_t hs = hs_c < 0 ? -1 : (int64_t)hs_c * HIT_CHUNK + hs_f;
+        const uint32_t f = lane;
+        const uint32_t v = f == SH_I ? (uint32_t)slot_get(S.i, q) : f == SH_SID ? (uint32_t)slot_get((int)S.sid, q)
+                         : f == SH_E0 ? e0q : f == SH_HS_LO ? (uint32_t)hs : f == SH_HS_HI ? (uint32_t)((uint64_t)hs >> 32)
+                         : f == SH_CONV_C ? (uint32_t)hc : f == SH_CONV_F ? (uint32_t)hf
+                         : f == SH_BASE ? (uint32_t)base : f == SH_KCAP ? (uint32_t)kc
+                         : f == SH_NODES ? (TREE ? (uint32_t)slot_get(S.nodes, q) : 0u)
+                         : f == SH_OUT ? 1u : 0u;
+        if (f < (uint32_t)SH_FIELDS) *share_ptr((int)sh, (int)f) = v;
+        __threadfence();
+        if ((int)lane == q) {
+            S.sh = (int)sh;
+            S.hs_c = base;
+            S.hs_f = kc;
+        }
+        return (int)sh;
+    };
 
     for (;;) {
+        if (SUB && top == bot) top = bot = lo = 0;
         // ---- refill: start showers while the pool is short of a full wave
-        while (top < WAVE && !exhausted) {
+        while (top - bot < WAVE && !exhausted) {
             const uint64_t free_slots = wave_ballot((int)lane < SLOTS && S.i < 0);
             if (!free_slots) break;
             const int s = __builtin_ctzll(free_slots);
+            const int ph = SUB ? __builtin_amdgcn_readfirstlane((int)sub_l[SL_PHASE]) : 0;
+            if (SUB && ph > 0) {
+                // an item exported by the previous launch: pending particles
+                // of one shared shower, taken into slot s as one more party
+                unsigned long long got = 0;
+                if (lane == 0) got = atomicAdd(&P.ctr[ctr_st_claim(ph)], 1ull);
+                const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)got);
+                if (it >= (uint32_t)__builtin_amdgcn_readfirstlane((int)sub_l[SL_ITEMS_IN])) {
+                    exhausted = true;
+                    break;
+                }
+                const uint32_t *items = (const uint32_t *)(uintptr_t)(*(const uint64_t *)(sub_l + SL_ITEMS));
+                const int64_t cap = (int64_t)__builtin_amdgcn_readfirstlane((int)sub_l[SL_ITEM_CAP]);
+                const uint32_t *item = items + ((int64_t)((ph - 1) & 1) * cap + it) * ITEM_WORDS;
+                const int cnt = min(WAVE, __builtin_amdgcn_readfirstlane((int)item[POOL_FIELDS * WAVE]));
+                Entry e{0.f, 0.f, 0.f, 0.f, 0u, 0u, 0u, 0, 0u};
+                if ((int)lane < cnt) e = load_entry(item, WAVE, lane);
+                const int sh = __builtin_amdgcn_readfirstlane((int)(e.ks >> 8));
+                const uint32_t fv = (int)lane < SH_NODES ? share_load(sh, (int)lane) : 0u;
+                const int v_i = __builtin_amdgcn_readlane((int)fv, SH_I);
+                const uint32_t v_sid = (uint32_t)__builtin_amdgcn_readlane((int)fv, SH_SID);
+                const uint32_t v_e0 = (uint32_t)__builtin_amdgcn_readlane((int)fv, SH_E0);
+                const int v_cc = __builtin_amdgcn_readlane((int)fv, SH_CONV_C);
+                const int v_cf = __builtin_amdgcn_readlane((int)fv, SH_CONV_F);
+                const int v_base = __builtin_amdgcn_readlane((int)fv, SH_BASE);
+                const int v_kc = __builtin_amdgcn_readlane((int)fv, SH_KCAP);
+                if ((int)lane == s) {
+                    S.i = v_i;
+                    S.sid = v_sid;
+                    S.e0 = v_e0;
+                    S.sh = sh;
+                    S.hc = v_cc;
+                    S.hf = v_cf;
+                    S.hs_c = v_base;
+                    S.hs_f = v_kc;
+                    S.live = cnt;
+                    S.hits = S.nodes = S.passes = S.escaped = S.backward = 0;
+                    S.e_esc = 0u;
+                }
+                if ((int)lane < cnt) {
+                    e.ks = (e.ks & 255u) | ((uint32_t)s << 8);
+                    pool_store(top + (int)lane, e);
+                }
+                top += cnt;
+                lo = max(lo, top - PC);
+                max_top = max(max_top, top - bot);
+                continue;
+            }
             if (b_at == b_left) {
                 const uint32_t base = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)next_base);
                 if (base >= (uint32_t)P.n) {
@@ -533,11 +677,11 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
         const uint64_t active = wave_ballot((int)lane < SLOTS && S.i >= 0);
         if (!active) break;
 
-        if (top > 0) {
+        if (top > bot) {
             // ---- one step of Algorithm 1 for up to 64 particles, each at its
             // own plane k: draw, three-way choice, split; what goes on flies
             // to plane k+1 at once, and deposits there if below threshold
-            const int nb = min(WAVE, top);
+            const int nb = min(WAVE, top - bot);
             const bool valid = (int)lane < nb;
             const int j = top - 1 - (int)lane;
             if (top - nb < lo) __threadfence_block();    // spilled entries: see other lanes' stores
@@ -606,14 +750,22 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             const uint64_t sm2 = wave_ballot(valid && slot == 2), sm3 = wave_ballot(valid && slot == 3);
             const uint64_t mine = slot == 0 ? sm0 : slot == 1 ? sm1 : slot == 2 ? sm2 : sm3;
             const uint64_t own = lane == 0 ? sm0 : lane == 1 ? sm1 : lane == 2 ? sm2 : lane == 3 ? sm3 : 0ull;
-            // node index of daughter a: the slot's node count + 2 per split below
+            // node index of daughter a: the slot's node count + 2 per split
+            // below (a shared shower's next indices come from its share)
+            if (SUB && TREE && msplit) {
+                const bool shs = (int)lane < SLOTS && S.sh >= 0;
+                if (wave_ballot(shs)) {
+                    const int ns = (int)__popcll(msplit & own);
+                    if (shs && ns > 0) S.nodes = (int)atomicAdd(share_ptr(S.sh, SH_NODES), (uint32_t)(2 * ns));
+                }
+            }
             const int node_a = __shfl(S.nodes, slot, WAVE) + 2 * (int)lanes_below(msplit & mine);
             if (recs && (mh1 | mh2)) {
                 // hit records of every slot at once: the slot's chain position
                 // + this lane's rank among the slot's records of the step
                 const int c = __shfl(S.hc, slot, WAVE), f = __shfl(S.hf, slot, WAVE);
                 const int cnt_own = (int)__popcll(mh1 & own) + (int)__popcll(mh2 & own);
-                const bool over_own = S.hc >= 0 && S.hf + cnt_own > HIT_CHUNK;
+                const bool over_own = S.hc >= 0 && (!SUB || S.sh < 0) && S.hf + cnt_own > HIT_CHUNK;
                 // a slot whose chunk fills up links a fresh one (rare)
                 int c2_own = -1;
                 for (uint64_t mo = wave_ballot(over_own); mo; mo &= mo - 1) {
@@ -624,20 +776,51 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
                     if ((int)lane == q) c2_own = c2;
                 }
                 const int c2 = __shfl(c2_own, slot, WAVE);
-                const int p1 = f + (int)lanes_below(mh1 & mine) + (int)lanes_below(mh2 & mine);
+                const int r1 = (int)lanes_below(mh1 & mine) + (int)lanes_below(mh2 & mine);
+                const int p1 = f + r1;
                 const int p2 = p1 + (hit1 ? 1 : 0);
+                int cc1 = p1 < HIT_CHUNK ? c : c2, o1 = p1 & (HIT_CHUNK - 1);
+                int cc2 = p2 < HIT_CHUNK ? c : c2, o2 = p2 & (HIT_CHUNK - 1);
+                if (SUB) {
+                    // shared showers: positions in the shower's run from its
+                    // fill counter, past the conversion point (c, f), then
+                    // through the reserved chunks
+                    const bool shs = (int)lane < SLOTS && S.sh >= 0;
+                    if (wave_ballot(shs)) {
+                        int fb = 0;
+                        if (shs && cnt_own > 0) fb = (int)atomicAdd(share_ptr(S.sh, SH_FILL), (uint32_t)cnt_own);
+                        const int fbs = __shfl(fb, slot, WAVE);
+                        const bool mysh = __shfl(S.sh, slot, WAVE) >= 0;
+                        const int kb = __shfl(S.hs_c, slot, WAVE), kn = __shfl(S.hs_f, slot, WAVE);
+                        if (mysh) {
+                            const int room = c >= 0 ? HIT_CHUNK - f : 0;
+                            auto place = [&](int q, int &cc, int &o) {
+                                if (q < room) {
+                                    cc = c;
+                                    o = f + q;
+                                } else {
+                                    const int t = q - room;
+                                    cc = (t >> HIT_CHUNK_LOG2) < kn ? kb + (t >> HIT_CHUNK_LOG2) : -1;
+                                    o = t & (HIT_CHUNK - 1);
+                                }
+                            };
+                            place(fbs + r1, cc1, o1);
+                            place(fbs + r1 + (hit1 ? 1 : 0), cc2, o2);
+                            if ((hit1 && cc1 < 0) || (hit2 && cc2 < 0))
+                                atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_SHARE);
+                        }
+                    }
+                }
                 if (hit1) {
-                    const int cc = p1 < HIT_CHUNK ? c : c2;
                     const Hit h1 = is_stop ? Hit{p.x, p.y, p.e, (uint32_t)k, p.lo, p.hi}
                                            : Hit{xa, ya, ea, (uint32_t)k + 1u, (uint32_t)pa, (uint32_t)(pa >> 32)};
-                    if (cc >= 0) write_hit(cc, p1 & (HIT_CHUNK - 1), h1);
+                    if (cc1 >= 0) write_hit(cc1, o1, h1);
                 }
                 if (hit2) {
-                    const int cc = p2 < HIT_CHUNK ? c : c2;
                     const Hit h2{xb, yb, eb, (uint32_t)k + 1u, (uint32_t)pa | 1u, (uint32_t)(pa >> 32)};
-                    if (cc >= 0) write_hit(cc, p2 & (HIT_CHUNK - 1), h2);
+                    if (cc2 >= 0) write_hit(cc2, o2, h2);
                 }
-                if ((int)lane < SLOTS && S.hc >= 0) {
+                if ((int)lane < SLOTS && S.hc >= 0 && (!SUB || S.sh < 0)) {
                     if (over_own) {
                         S.hc = c2_own;
                         S.hf += cnt_own - HIT_CHUNK;
@@ -718,7 +901,59 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             }
             top += (int)__popcll(mpa) + (int)__popcll(mpb);
             lo = max(lo, top - PC);
-            max_top = max(max_top, top);
+            max_top = max(max_top, top - bot);
+            if (SUB) {
+                // ---- export: once the wave has no new work to take and its
+                // pool holds export_top + WAVE entries, the oldest WAVE are
+                // looked at, and those of the shower with most of them (at
+                // least ITEM_MIN) leave as an item that the next launch
+                // finishes; the others move up against the new bottom of the
+                // pool.  (While showers remain to be started, every wave is
+                // busy and an export would only add shared-shower traffic;
+                // the wave's claim of its next showers is already back.)
+                const int et = __builtin_amdgcn_readfirstlane((int)sub_l[SL_EXPORT]);
+                const bool no_new = __builtin_amdgcn_readfirstlane((int)sub_l[SL_PHASE]) > 0 ||
+                                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)next_base) >= (uint32_t)P.n;
+                if (no_new && et >= 0 && top - bot >= et + WAVE) {
+                    if (bot < lo) __threadfence_block();
+                    const Entry e = pool_load(bot + (int)lane);
+                    const int es = (int)(e.ks >> 8);
+                    const uint64_t b0 = wave_ballot(es == 0), b1 = wave_ballot(es == 1);
+                    const uint64_t b2 = wave_ballot(es == 2), b3 = wave_ballot(es == 3);
+                    int q = 0;
+                    uint64_t m = b0;
+                    if (__popcll(b1) > __popcll(m)) { q = 1; m = b1; }
+                    if (__popcll(b2) > __popcll(m)) { q = 2; m = b2; }
+                    if (__popcll(b3) > __popcll(m)) { q = 3; m = b3; }
+                    const int cnt = (int)__popcll(m);
+                    int sh = cnt >= ITEM_MIN ? slot_get(S.sh, q) : -1;
+                    if (cnt >= ITEM_MIN && sh < 0) sh = convert(q);
+                    if (sh >= 0) {
+                        const int ph = __builtin_amdgcn_readfirstlane((int)sub_l[SL_PHASE]);
+                        unsigned long long got = 0;
+                        if (lane == 0) got = atomicAdd(&P.ctr[ctr_st_out(ph)], 1ull);
+                        const uint32_t it = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)got);
+                        const int64_t cap = (int64_t)__builtin_amdgcn_readfirstlane((int)sub_l[SL_ITEM_CAP]);
+                        if ((int64_t)it < cap) {
+                            if (lane == 0) atomicAdd(share_ptr(sh, SH_OUT), 1u);
+                            uint32_t *items = (uint32_t *)(uintptr_t)(*(const uint64_t *)(sub_l + SL_ITEMS));
+                            uint32_t *item = items + ((int64_t)(ph & 1) * cap + it) * ITEM_WORDS;
+                            const bool out_e = (m >> lane) & 1ull;
+                            if (out_e) {
+                                Entry x = e;
+                                x.ks = (e.ks & 255u) | ((uint32_t)sh << 8);
+                                store_entry(item, WAVE, (int64_t)lanes_below(m), x);
+                            } else {
+                                pool_put(bot + cnt + (int)lanes_below(~m), e);
+                            }
+                            if (lane == 0) item[POOL_FIELDS * WAVE] = (uint32_t)cnt;
+                            bot += cnt;
+                            lo = max(lo, bot);
+                            if ((int)lane == q) S.live -= cnt;
+                        }
+                    }
+                }
+            }
         } else if (wave_ballot((int)lane < SLOTS && S.i >= 0 && S.live > 0)) {
             // nothing pending although a shower still counts live particles:
             // its accounting is inconsistent; report it and close it
@@ -743,6 +978,61 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             const int nsplit = (nn - 1) / 2;
             const uint32_t e_cut = wave_sum_u32(ecut.take(s));
             const uint32_t e_stop = wave_sum_u32(estop.take(s));
+            if (SUB && slot_get(S.sh, s) >= 0) {
+                // one party of a shared shower is done: its tallies go to the
+                // share; the last party writes the shower's results
+                const int shs = slot_get(S.sh, s);
+                uint32_t last_party = 0;
+                if (lane == 0) {
+                    atomicAdd(share_ptr(shs, SH_HITS), (uint32_t)nh);
+                    if (!TREE) atomicAdd(share_ptr(shs, SH_NODES), (uint32_t)nn);
+                    atomicAdd(share_ptr(shs, SH_PASSES), (uint32_t)npass);
+                    atomicAdd(share_ptr(shs, SH_ESC), (uint32_t)nesc);
+                    atomicAdd(share_ptr(shs, SH_BACK), (uint32_t)nback);
+                    atomicAdd(share_ptr(shs, SH_EESC), eesc);
+                    atomicAdd(share_ptr(shs, SH_ECUT), e_cut);
+                    atomicAdd(share_ptr(shs, SH_ESTOP), e_stop);
+                    __threadfence();
+                    last_party = atomicSub(share_ptr(shs, SH_OUT), 1u) == 1u ? 1u : 0u;
+                }
+                if (__builtin_amdgcn_readfirstlane((int)last_party)) {
+                    __threadfence();
+                    const uint32_t v = (int)lane < SH_FIELDS ? share_load(shs, (int)lane) : 0u;
+                    const int fi = __builtin_amdgcn_readlane((int)v, SH_I);
+                    const int fnn = __builtin_amdgcn_readlane((int)v, SH_NODES);
+                    const int fnh = __builtin_amdgcn_readlane((int)v, SH_HITS);
+                    const int fpass = __builtin_amdgcn_readlane((int)v, SH_PASSES);
+                    const int fesc = __builtin_amdgcn_readlane((int)v, SH_ESC);
+                    const int fback = __builtin_amdgcn_readlane((int)v, SH_BACK);
+                    const uint32_t fe0 = (uint32_t)__builtin_amdgcn_readlane((int)v, SH_E0);
+                    const uint32_t fstop = (uint32_t)__builtin_amdgcn_readlane((int)v, SH_ESTOP);
+                    const uint32_t fcut = (uint32_t)__builtin_amdgcn_readlane((int)v, SH_ECUT);
+                    const uint32_t fesce = (uint32_t)__builtin_amdgcn_readlane((int)v, SH_EESC);
+                    const uint32_t hs_lo = (uint32_t)__builtin_amdgcn_readlane((int)v, SH_HS_LO);
+                    const uint32_t hs_hi = (uint32_t)__builtin_amdgcn_readlane((int)v, SH_HS_HI);
+                    const int fsplit = (fnn - 1) / 2;
+                    if (recs && lane == 0) COLD(hstart)[fi] = (int64_t)(((uint64_t)hs_hi << 32) | hs_lo);
+                    steps += (unsigned long long)(fnh + fsplit + fpass);
+                    if ((int)lane < 4) {
+                        const uint32_t w = lane == 0 ? fe0 : lane == 1 ? fstop : lane == 2 ? fcut : fesce;
+                        COLD(ledger)[4 * (int64_t)fi + lane] = w;
+                    }
+                    if ((int)lane < 6) {
+                        const int w = lane == 0 ? fnn : lane == 1 ? fnh : lane == 2 ? fnh + fsplit + fpass
+                                    : lane == 3 ? fsplit : lane == 4 ? fesc : fback;
+                        COLD(counts)[6 * (int64_t)fi + lane] = w;
+                    }
+                }
+                // the slot's next shower starts a fresh chunk: this one's
+                // chunk belongs to the shared run
+                if ((int)lane == s) {
+                    S.i = -1;
+                    S.sh = -1;
+                    S.hc = -1;
+                    S.hf = 0;
+                }
+                continue;
+            }
             if (recs && lane == 0) {
                 const int hs_c = slot_get(S.hs_c, s), hs_f = slot_get(S.hs_f, s);
                 COLD(hstart)[i] = hs_c < 0 ? -1 : (int64_t)hs_c * HIT_CHUNK + hs_f;
@@ -767,7 +1057,8 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
         atomicMax(&P.ctr[CTR_NEED_F], (unsigned long long)max_top);
     }
     if (wave_ballot(overflow) && lane == 0) atomicOr(&P.ctr[CTR_FLAGS], (unsigned long long)FLAG_OVERFLOW);
-    if (lane == 0 && COLD(wave_clk)) COLD(wave_clk)[2 * wave + 1] = (unsigned long long)wall_clock64();
+    if (lane == 0 && COLD(wave_clk) && (!SUB || P.phase == 0))
+        COLD(wave_clk)[2 * wave + 1] = (unsigned long long)wall_clock64();
 }
 
 __global__ void supa_zero_counters(unsigned long long *ctr) {
@@ -808,32 +1099,37 @@ size_t propagate_lds_bytes(int pool_cap, bool rings) {
     return (size_t)lds_words(pool_cap, rings) * 4;
 }
 
-template <bool TREE, bool KEYS, bool LIT, bool REG>
+template <bool TREE, bool KEYS, bool LIT, bool REG, bool SUB>
 static hipError_t launch_pc(const Params &P, int blocks, size_t lds, hipStream_t s) {
     switch (P.pool_cap) {
-    case 128: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 128, LIT, REG>), dim3(blocks), dim3(WAVE), lds, s, P); break;
-    case 256: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 256, LIT, REG>), dim3(blocks), dim3(WAVE), lds, s, P); break;
-    case 512: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 512, LIT, REG>), dim3(blocks), dim3(WAVE), lds, s, P); break;
-    case 1024: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 1024, LIT, REG>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 128: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 128, LIT, REG, SUB>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 256: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 256, LIT, REG, SUB>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 512: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 512, LIT, REG, SUB>), dim3(blocks), dim3(WAVE), lds, s, P); break;
+    case 1024: hipLaunchKernelGGL((supa_propagate<TREE, KEYS, 1024, LIT, REG, SUB>), dim3(blocks), dim3(WAVE), lds, s, P); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-template <bool LIT, bool REG>
+template <bool LIT, bool REG, bool SUB>
 static hipError_t launch_kin(const Params &P, int blocks, size_t lds, hipStream_t s) {
     const bool tree = (P.outputs & 4u) != 0;
     if (tree)
-        return P.keys ? launch_pc<true, true, LIT, REG>(P, blocks, lds, s)
-                      : launch_pc<true, false, LIT, REG>(P, blocks, lds, s);
-    return P.keys ? launch_pc<false, true, LIT, REG>(P, blocks, lds, s)
-                  : launch_pc<false, false, LIT, REG>(P, blocks, lds, s);
+        return P.keys ? launch_pc<true, true, LIT, REG, SUB>(P, blocks, lds, s)
+                      : launch_pc<true, false, LIT, REG, SUB>(P, blocks, lds, s);
+    return P.keys ? launch_pc<false, true, LIT, REG, SUB>(P, blocks, lds, s)
+                  : launch_pc<false, false, LIT, REG, SUB>(P, blocks, lds, s);
 }
 
+// Subtree work items (P.last_phase > 0) exist for the plain kinematics only.
 hipError_t launch_propagate(const Params &P, bool literal, bool rings, int blocks, hipStream_t s) {
     const size_t lds = propagate_lds_bytes(P.pool_cap, rings);
-    if (rings) return literal ? launch_kin<true, true>(P, blocks, lds, s) : launch_kin<false, true>(P, blocks, lds, s);
-    return literal ? launch_kin<true, false>(P, blocks, lds, s) : launch_kin<false, false>(P, blocks, lds, s);
+    if (P.last_phase > 0) {
+        if (literal || rings) return hipErrorInvalidValue;
+        return launch_kin<false, false, true>(P, blocks, lds, s);
+    }
+    if (rings) return literal ? launch_kin<true, true, false>(P, blocks, lds, s) : launch_kin<false, true, false>(P, blocks, lds, s);
+    return literal ? launch_kin<true, false, false>(P, blocks, lds, s) : launch_kin<false, false, false>(P, blocks, lds, s);
 }
 
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,

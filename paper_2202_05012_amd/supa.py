@@ -73,7 +73,7 @@ class Output(C.Structure):
 
 
 EXPORTS = ["supa_abi_version", "supa_validate_geometry", "supa_validate_call", "supa_init_geometry", "supa_destroy",
-           "supa_simulate", "supa_simulate_batches", "supa_simulate_noalloc", "supa_set_launch", "supa_set_schedule", "supa_autotune", "supa_autotune_forget",
+           "supa_simulate", "supa_simulate_batches", "supa_simulate_noalloc", "supa_set_launch", "supa_set_schedule", "supa_set_subtrees", "supa_last_subtrees", "supa_autotune", "supa_autotune_forget",
            "supa_graph_create", "supa_graph_launch", "supa_graph_check", "supa_graph_destroy", "supa_last_timing", "supa_last_kernel_times", "supa_last_wave_times", "supa_philox",
            "supa_last_error"]
 
@@ -123,6 +123,10 @@ def load():
         L.supa_graph_destroy.argtypes = [C.c_void_p]
         L.supa_set_schedule.restype = C.c_int
         L.supa_set_schedule.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+        L.supa_set_subtrees.restype = C.c_int
+        L.supa_set_subtrees.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+        L.supa_last_subtrees.restype = C.c_int
+        L.supa_last_subtrees.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
         L.supa_last_timing.restype = C.c_int
         L.supa_last_timing.argtypes = [C.c_void_p, C.POINTER(C.c_float)]
         L.supa_last_wave_times.restype = C.c_int
@@ -199,7 +203,8 @@ class Simulator:
 
     def __init__(self, geom: dict, outputs: int = OUT_HITS, device: int = 0,
                  waves_per_cu: int = 0, frontier_cap: int = 0, hit_cap: int = 0,
-                 node_cap: int = 0, sub_batches: int = 0, cost_order: int = -1):
+                 node_cap: int = 0, sub_batches: int = 0, cost_order: int = -1,
+                 subtree_phases: int | None = None, export_pool: int = 0):
         self.lib = load()
         if not torch.cuda.is_available():
             raise RuntimeError("libsupa needs a GPU; none is visible")
@@ -220,6 +225,8 @@ class Simulator:
             self.set_launch(waves_per_cu, frontier_cap, hit_cap, node_cap)
         if sub_batches or cost_order != -1:
             self.set_schedule(sub_batches, cost_order)
+        if subtree_phases is not None:
+            self.set_subtrees(subtree_phases, export_pool)
 
     def set_launch(self, waves_per_cu=0, frontier_cap=0, hit_cap=0, node_cap=0):
         st = self.lib.supa_set_launch(self.ctx, waves_per_cu, frontier_cap, hit_cap, node_cap)
@@ -227,6 +234,18 @@ class Simulator:
 
     def set_schedule(self, sub_batches=0, cost_order=-1):
         self._check(self.lib.supa_set_schedule(self.ctx, sub_batches, cost_order))
+
+    def set_subtrees(self, phases=0, export_pool=0):
+        """supa_set_subtrees: propagation launches per call (0 = automatic,
+        1 = no subtree work items) and the pool size beyond one step from
+        which a wave exports."""
+        self._check(self.lib.supa_set_subtrees(self.ctx, phases, export_pool))
+
+    def subtree_counts(self):
+        """Shared showers and items exported per launch of the last call."""
+        v = (C.c_int64 * 5)()
+        self._check(self.lib.supa_last_subtrees(self.ctx, v))
+        return {"shared": v[0], "items": list(v[1:])}
 
     def _check(self, st):
         if st != 0:

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol():
     assert "supa_simulate" in names and "supa_init_geometry" in names
     for name in names:
         assert hasattr(lib, name), f"{name} declared in include/ but not exported"
-    assert lib.supa_abi_version() == 5
+    assert lib.supa_abi_version() == 6
 
 
 def base_geom(**kw):

@@ -190,8 +190,9 @@ def test_determinism_across_launch_settings():
     """Tiny logs force the grow-and-rerun path, a small LDS pool makes large
     showers spill to global memory, different wave counts change which wave
     runs which shower and which showers share a wave, sub-batches split the
-    call into overlapping propagation and placement launches; results must
-    not change."""
+    call into overlapping propagation and placement launches, subtree work
+    items split showers across waves and launches; results must not
+    change."""
     w = workloads.WORKLOADS["loge1to1000_20planes_1m"]
     geom = workloads.geometry(w)
     e0, pol, az = workloads.initial_conditions(w, 200)
@@ -200,7 +201,8 @@ def test_determinism_across_launch_settings():
                    dict(waves_per_cu=16), dict(waves_per_cu=4, frontier_cap=512),
                    dict(waves_per_cu=12, frontier_cap=128),
                    dict(sub_batches=3, cost_order=1), dict(waves_per_cu=4, cost_order=1),
-                   dict(waves_per_cu=2, sub_batches=8, hit_cap=64, node_cap=64)):
+                   dict(waves_per_cu=2, sub_batches=8, hit_cap=64, node_cap=64),
+                   dict(subtree_phases=3, export_pool=0), dict(subtree_phases=4, waves_per_cu=2)):
         gpu, _ = run_gpu(geom, HITS_TREE, e0, pol, az, w.seed, **launch)
         parity.check_all(gpu, ref, geom, tree=True)
 
