@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--serial-calls", action="store_true",
                     help="run that workload's calls one supa_simulate at a time instead of "
                          "supa_simulate_batches (propagation of call j+1 beside the placement of j)")
+    ap.add_argument("--subtrees", type=int, default=None,
+                    help="propagation launches per call with subtree work items (0 automatic, the "
+                         "library default; 1 none; 2..4)")
     ap.add_argument("--autotune", action="store_true",
                     help="pick launch settings by measurement before timing")
     ap.add_argument("--kinematics", default="3d", choices=("3d", "literal"),
@@ -169,12 +172,16 @@ def cpu_baseline_sampled(w, geom, seconds: float, seconds_1t: float, images: boo
     ids = np.random.default_rng(20260).permutation(w.n)
     threads = host_threads()
     n1, s1, t1 = oracle_sample_rate(w, geom, ids, 1, seconds_1t, images)
-    n, steps, dt = oracle_sample_rate(w, geom, ids[n1:], threads, seconds, images)
+    # the all-thread leg takes showers the one-thread leg did not (a small
+    # workload it exhausted is taken again from the start)
+    rest = ids[n1:] if n1 < len(ids) else ids
+    n, steps, dt = oracle_sample_rate(w, geom, rest, threads, seconds, images)
     what = "simulation + tree" + (" + per-layer images" if images else "")
     return {"value": round(n / dt, 2), "unit": "showers/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} showers drawn at random from the {w.n:,} ({what}, one oracle call per "
-                      f"shower) on {threads} host threads in {dt:.1f} s; rate extrapolated per shower "
-                      f"to the whole workload",
+            "sample": f"{n} showers drawn at random from the {w.n:,}" +
+                      (" in repeated passes" if n > len(rest) else "") +
+                      f" ({what}, one oracle call per shower) on {threads} host threads in {dt:.1f} s; "
+                      f"rate extrapolated per shower to the whole workload",
             "extrapolated": True, "seconds": round(dt, 2),
             "particle_steps_per_s": round(steps / dt, 1),
             "one_thread": {"value": round(n1 / t1, 2), "unit": "showers/s", "showers": n1,
@@ -747,7 +754,7 @@ def main():
     te0, tpol, taz = (torch.from_numpy(a).to(dev) for a in (e0, pol, az))
     sim = supa.Simulator(geom, outputs, waves_per_cu=args.waves_per_cu,
                          frontier_cap=args.lds_cap, sub_batches=args.sub_batches,
-                         cost_order=args.cost_order)
+                         cost_order=args.cost_order, subtree_phases=args.subtrees)
 
     # size the outputs from one untimed run (also grows the per-wave scratch)
     probe = sim.allocate(w.n, 0, 0)
@@ -877,6 +884,9 @@ def main():
                                      "p90_ms": round(float(np.quantile(wt, 0.9)), 4),
                                      "max_ms": round(float(wt.max()), 4),
                                      "max_over_median": round(float(wt.max() / max(np.median(wt), 1e-9)), 3)}
+    sub = sim.subtree_counts()
+    if sub["shared"]:
+        line["subtree_items"] = {"shared_showers": sub["shared"], "items_per_launch": sub["items"]}
     if launch is not None:
         line["launch"] = launch
     if args.graph:

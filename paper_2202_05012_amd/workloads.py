@@ -59,6 +59,11 @@ WORKLOADS = {
                  ("uniform", 0.0, TWO_PI), 1, (256, 256, -5.0, 5.0, -5.0, 5.0), tree=True,
                  description="1,000,000 showers, E0 log-uniform on [10,1000], 50 planes, "
                              "propagation tree + 50 x 256x256 images"),
+        Workload("e1000_20planes_tree_256", 256, 20, ("fixed", 1000.0), ("uniform", 0.0, 15.0),
+                 ("uniform", 0.0, TWO_PI), 2, None, tree=True,
+                 description="256 showers of E0 = 1000 (the top of the log-uniform range), same "
+                             "angles, 20 planes, hit clouds + propagation tree: a small call "
+                             "whose showers occupy 64 of the GPU's waves unless they are split"),
     ]
 }
 
