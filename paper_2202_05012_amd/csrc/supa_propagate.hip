@@ -182,6 +182,22 @@ struct Slots {
 
 __device__ __forceinline__ int slot_get(int v, int s) { return __builtin_amdgcn_readlane(v, s); }
 
+// m0 .. m3 (wave-uniform, in scalar registers) in lanes 0 .. 3, zero in the
+// other lanes: one lane write each (constant lane numbers)
+__device__ __forceinline__ uint64_t lanes_of_slots(uint64_t m0, uint64_t m1, uint64_t m2, uint64_t m3) {
+    uint32_t lo = 0u, hi = 0u;
+    asm volatile("v_writelane_b32 %0, %1, 0" : "+v"(lo) : "s"((uint32_t)m0));
+    asm volatile("v_writelane_b32 %0, %1, 0" : "+v"(hi) : "s"((uint32_t)(m0 >> 32)));
+    asm volatile("v_writelane_b32 %0, %1, 1" : "+v"(lo) : "s"((uint32_t)m1));
+    asm volatile("v_writelane_b32 %0, %1, 1" : "+v"(hi) : "s"((uint32_t)(m1 >> 32)));
+    asm volatile("v_writelane_b32 %0, %1, 2" : "+v"(lo) : "s"((uint32_t)m2));
+    asm volatile("v_writelane_b32 %0, %1, 2" : "+v"(hi) : "s"((uint32_t)(m2 >> 32)));
+    asm volatile("v_writelane_b32 %0, %1, 3" : "+v"(lo) : "s"((uint32_t)m3));
+    asm volatile("v_writelane_b32 %0, %1, 3" : "+v"(hi) : "s"((uint32_t)(m3 >> 32)));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+
 // Calls f(s, m) once for every distinct slot s among the lanes of mask, with
 // m the lanes of mask whose slot is s (mask is wave-uniform).
 template <class F>
@@ -217,8 +233,9 @@ enum { SL_EXPORT = 0, SL_PHASE, SL_ITEMS_IN, SL_ITEM_CAP, SL_SHARE_CAP, SL_MARGI
 // LDS words of one wave: pool + the stop / split thresholds of every plane
 // pool, then the thresholds c1, c2 (u64) of 64 planes, of 4 rings with
 // regional parameters
+// (then the energy tallies: cut and stop energy per slot and lane)
 __host__ __device__ constexpr int lds_words(int pool_cap, bool rings = false) {
-    return POOL_FIELDS * pool_cap + 2 * 2 * 64 * (rings ? 4 : 1) + SUB_LDS_WORDS;
+    return POOL_FIELDS * pool_cap + 2 * 2 * 64 * (rings ? 4 : 1) + SUB_LDS_WORDS + 2 * SLOTS * WAVE;
 }
 
 // Keeps a wave-uniform value in scalar registers but hides it from loop-
@@ -229,29 +246,6 @@ __device__ __forceinline__ uint32_t opaque_u32(uint32_t v) {
     return v;
 }
 
-// One 32-bit value per shower slot in every lane, as named registers (an
-// array indexed by a run-time slot would be placed in scratch memory).
-static_assert(SLOTS == 4, "SlotSums holds four slots");
-struct SlotSums {
-    uint32_t v0, v1, v2, v3;
-    __device__ __forceinline__ void zero() { v0 = v1 = v2 = v3 = 0u; }
-    // adds x to the slot of this lane's particle
-    __device__ __forceinline__ void add(int slot, uint32_t x) {
-        v0 += slot == 0 ? x : 0u;
-        v1 += slot == 1 ? x : 0u;
-        v2 += slot == 2 ? x : 0u;
-        v3 += slot == 3 ? x : 0u;
-    }
-    // value of slot s (wave-uniform), which is cleared
-    __device__ __forceinline__ uint32_t take(int s) {
-        const uint32_t r = s == 0 ? v0 : s == 1 ? v1 : s == 2 ? v2 : v3;
-        v0 = s == 0 ? 0u : v0;
-        v1 = s == 1 ? 0u : v1;
-        v2 = s == 2 ? 0u : v2;
-        v3 = s == 3 ? 0u : v3;
-        return r;
-    }
-};
 
 // TREE: node records; KEYS: path ids with hit and node records; LIT: literal
 // Algorithm 1 kinematics; REG: regional parameters (rings) (compile-time, so
@@ -293,7 +287,13 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
         *(uint64_t *)(sub_l + SL_ITEMS) = (uint64_t)(uintptr_t)P.items;
         *(uint64_t *)(sub_l + SL_SHARES) = (uint64_t)(uintptr_t)P.shares;
     }
-    if (SUB) __syncthreads();
+    // per-lane partial sums of the energy each slot's shower deposited by
+    // cuts ([slot][lane]) and by stops (then [slot][lane]): every lane adds
+    // to its own word (LDS atomics without conflicts), a shower's words are
+    // summed once when it ends (its energies sum to e0 < 2^32)
+    uint32_t *const esum = sub_l + SUB_LDS_WORDS;
+    for (int q = 0; q < 2 * SLOTS; ++q) esum[q * WAVE + lane] = 0u;
+    __syncthreads();
     float rr1 = 0.f, rr2 = 0.f, rr3 = 0.f;        // squared ring radii
     if constexpr (REG) {
         const volatile __attribute__((address_space(1))) Cold *cp =
@@ -326,11 +326,6 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
     S.hc = S.hs_c = -1;
     S.hf = S.hs_f = 0;
     S.sh = -1;
-    // per-lane partial sums of the energy each slot's shower deposited by
-    // cuts and by stops (a shower's energies sum to e0 < 2^32)
-    SlotSums ecut, estop;
-    ecut.zero();
-    estop.zero();
 
     // pool: logical entries [bot, top); bot > 0 only after exports
     int top = 0, lo = 0, max_top = 0, bot = 0;
@@ -647,7 +642,7 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
                 const Hit h{x1, y1, e_first, 0u, 1u, 0u};
                 if (recs) append_hits(s, 1ull, 0ull, h, h);
                 if ((int)lane == s) S.hits = 1;
-                ecut.add(s, lane == 0 ? e_first : 0u);
+                if (lane == 0) atomicAdd(&esum[s * WAVE], e_first);
             } else if (fwd0) {
                 if (lane == 0) {
                     const Entry p0{x1, y1, tx0, ty0, e_first, 1u, 0u, 0, (uint32_t)s << 8};
@@ -735,8 +730,8 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             // deposits: a stop at plane k, daughters below threshold at k+1
             const bool hit1 = is_stop || cut_a, hit2 = cut_b;
             const uint64_t pa = path << 1;
-            estop.add(slot, is_stop ? p.e : 0u);
-            ecut.add(slot, (cut_a ? ea : 0u) + (cut_b ? eb : 0u));
+            atomicAdd(&esum[slot * WAVE + (int)lane], (cut_a ? ea : 0u) + (cut_b ? eb : 0u));
+            if (wave_ballot(is_stop)) atomicAdd(&esum[(SLOTS + slot) * WAVE + (int)lane], is_stop ? p.e : 0u);
 
             const uint64_t mh1 = wave_ballot(hit1), mh2 = wave_ballot(hit2);
             const uint64_t mpa = wave_ballot(push_a), mpb = wave_ballot(push_b);
@@ -748,8 +743,10 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             // go to scratch memory.
             const uint64_t sm0 = wave_ballot(valid && slot == 0), sm1 = wave_ballot(valid && slot == 1);
             const uint64_t sm2 = wave_ballot(valid && slot == 2), sm3 = wave_ballot(valid && slot == 3);
+            // (own: written lane by lane from the scalar masks, which does
+            // not depend on the active lanes; mine: a select per lane)
+            const uint64_t own = lanes_of_slots(sm0, sm1, sm2, sm3);
             const uint64_t mine = slot == 0 ? sm0 : slot == 1 ? sm1 : slot == 2 ? sm2 : sm3;
-            const uint64_t own = lane == 0 ? sm0 : lane == 1 ? sm1 : lane == 2 ? sm2 : lane == 3 ? sm3 : 0ull;
             // node index of daughter a: the slot's node count + 2 per split
             // below (a shared shower's next indices come from its share)
             if (SUB && TREE && msplit) {
@@ -833,7 +830,7 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             if ((int)lane < SLOTS) {
                 S.hits += (int)__popcll(mh1 & own) + (int)__popcll(mh2 & own);
                 S.live += (int)__popcll(mpa & own) + (int)__popcll(mpb & own) - (int)__popcll(own);
-                S.passes += (int)__popcll(mpass & own);
+                if (mpass) S.passes += (int)__popcll(mpass & own);
                 S.nodes += 2 * (int)__popcll(msplit & own);
             }
             // leaks (after the last plane or backward): rare, per slot
@@ -976,8 +973,10 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             const uint32_t eesc = (uint32_t)slot_get((int)S.e_esc, s);
             const uint32_t e_first = (uint32_t)slot_get((int)S.e0, s);
             const int nsplit = (nn - 1) / 2;
-            const uint32_t e_cut = wave_sum_u32(ecut.take(s));
-            const uint32_t e_stop = wave_sum_u32(estop.take(s));
+            const uint32_t e_cut = wave_sum_u32(esum[s * WAVE + lane]);
+            const uint32_t e_stop = wave_sum_u32(esum[(SLOTS + s) * WAVE + lane]);
+            esum[s * WAVE + lane] = 0u;
+            esum[(SLOTS + s) * WAVE + lane] = 0u;
             if (SUB && slot_get(S.sh, s) >= 0) {
                 // one party of a shared shower is done: its tallies go to the
                 // share; the last party writes the shower's results
