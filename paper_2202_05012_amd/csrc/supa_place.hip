@@ -32,6 +32,15 @@ constexpr int PL_STAGE_WORDS = 4 * PL_WIN;          // hit staging: 32 KB (hit c
 constexpr int PL_MAX_SLABS = 1024;                  // slabs per image bucketed in LDS counts
 constexpr int PL_BUCKET_MIN_SLABS = 9;              // fewer slabs: bin the cached hits per slab
 constexpr int PL_CLIST = 512;                       // chunk ids of a shower's chain listed in LDS
+// Hits per plane are counted into PL_COPIES histograms, thread t adding to
+// copy t mod PL_COPIES, and summed afterwards: a wave's count instruction
+// then has at most four lanes on one LDS word (one histogram had up to 64
+// lanes of a plane on one word, serialised by the LDS).  Copies are
+// PL_CSTRIDE words apart, so equal planes of different copies fall on
+// different banks.  (Placing through one cursor per copy as well spread the
+// lanes of a plane over sixteen ranges and broke up the stores: twice as
+// slow; placement keeps one cursor per plane.)
+constexpr int PL_COPIES = 16, PL_CSTRIDE = 65;
 static_assert(PL_WIN <= 2 * HIT_CHUNK, "a window spans at most three chunks");
 
 // Barrier for hand-offs through LDS only: waits for this wave's LDS
@@ -163,17 +172,19 @@ __device__ __forceinline__ Window<KEYS> load_window(const PlaceParams &Q, const 
 }
 
 template <bool KEYS>
-__device__ __forceinline__ void count_planes(const Window<KEYS> &W, uint32_t *cnt, int N) {
+__device__ __forceinline__ void count_planes(const Window<KEYS> &W, uint32_t *hcnt, int N) {
+    uint32_t *const mine = hcnt + (threadIdx.x & (PL_COPIES - 1)) * PL_CSTRIDE;
 #pragma unroll
     for (int u = 0; u < PL_UNROLL; ++u)
-        if (W.k[u] >= 0 && W.k[u] < N) atomicAdd(&cnt[W.k[u]], 1u);
+        if (W.k[u] >= 0 && W.k[u] < N) atomicAdd(&mine[W.k[u]], 1u);
 }
 
 // counts per plane of window w (after walk_to_window(w)) from the plane bytes
 // alone: one byte per record read instead of the whole record
 __device__ __forceinline__ void count_window_planes(const PlaceParams &Q, const Chain &ch, const int *clist, int w,
-                                                    int nh, uint32_t *cnt, int N) {
+                                                    int nh, uint32_t *hcnt, int N) {
     if (ch.bad) return;
+    uint32_t *const mine = hcnt + (threadIdx.x & (PL_COPIES - 1)) * PL_CSTRIDE;
     const int lo = (ch.f0 + w * PL_WIN) >> HIT_CHUNK_LOG2;
     const bool listed = ch.listed;
 #pragma unroll
@@ -185,8 +196,48 @@ __device__ __forceinline__ void count_window_planes(const PlaceParams &Q, const 
             const int c = listed ? clist[pos >> HIT_CHUNK_LOG2] : (hop >= 0 && hop < 3) ? ch.win[hop] : -1;
             if (c < 0 || c >= Q.h_chunks) continue;          // never outside the log
             const int k = ((const uint8_t *)(Q.hlog + (int64_t)c * HIT_CHUNK_WORDS + HIT_PLANE_OFF))[pos & (HIT_CHUNK - 1)];
-            if (k < N) atomicAdd(&cnt[k], 1u);
+            if (k < N) atomicAdd(&mine[k], 1u);
         }
+    }
+}
+
+// counts per plane of a listed shower's records beyond window 0 from their
+// plane bytes, sixteen at a time: one 16-byte load per thread and aligned
+// group of sixteen chain positions (a group never straddles a chunk), two
+// groups in flight per thread; bytes outside the shower are skipped.  (Read
+// window by window, one byte per thread and record, the count pass of a
+// large shower was a chain of dependent round trips.)
+__device__ __forceinline__ void count_listed_planes(const PlaceParams &Q, const Chain &ch, const int *clist,
+                                                    int nh, uint32_t *hcnt, int N) {
+    if (ch.bad) return;
+    uint32_t *const mine = hcnt + (threadIdx.x & (PL_COPIES - 1)) * PL_CSTRIDE;
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(1))) const u32x4 gcu4;
+    const int p0 = ch.f0 + PL_WIN, p1 = ch.f0 + nh;
+    const int g0 = p0 >> 4, g1 = (p1 + 15) >> 4;
+    auto group = [&](int g) -> uint4 {
+        const int pos = g << 4;
+        const int c = clist[pos >> HIT_CHUNK_LOG2];
+        if (c < 0 || c >= Q.h_chunks) return make_uint4(~0u, ~0u, ~0u, ~0u);   // never outside the log
+        const uint8_t *pb = (const uint8_t *)(Q.hlog + (int64_t)c * HIT_CHUNK_WORDS + HIT_PLANE_OFF);
+        const u32x4 v = *(gcu4 *)(pb + (pos & (HIT_CHUNK - 1)));
+        return make_uint4(v.x, v.y, v.z, v.w);
+    };
+    auto add = [&](int g, uint4 b) {
+        const uint32_t wv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int p = (g << 4) + q;
+            const int k = (int)((wv[q >> 2] >> (8 * (q & 3))) & 255u);
+            if (p >= p0 && p < p1 && k < N) atomicAdd(&mine[k], 1u);
+        }
+    };
+    for (int g = g0 + (int)threadIdx.x; g < g1; g += 2 * PL_THREADS) {
+        const int g2 = g + PL_THREADS;
+        const uint4 a = group(g);
+        const uint4 b = g2 < g1 ? group(g2) : make_uint4(~0u, ~0u, ~0u, ~0u);
+        add(g, a);
+        if (g2 < g1) add(g2, b);
     }
 }
 
@@ -332,6 +383,7 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
     uint32_t *const scnt = slab + PL_SLAB_WORDS;       // [PL_MAX_SLABS + 1], BUCKET only
     __shared__ int32_t lay[64];
     __shared__ uint32_t cnt[64];
+    __shared__ uint32_t hcnt[PL_COPIES * PL_CSTRIDE];     // zero between showers
     __shared__ Chain ch;
     __shared__ int clist[PL_CLIST];
     // records are valid only when the propagation succeeded; hit outputs
@@ -342,6 +394,7 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
     const int N = Q.n_planes;
     if (threadIdx.x < 64) lay[threadIdx.x] = (int)threadIdx.x < N ? Q.layer[threadIdx.x] : -1;
     clear_slab(slab, MODE == PM_HITS ? PL_STAGE_WORDS : PL_SLAB_WORDS);
+    for (int q = (int)threadIdx.x; q < PL_COPIES * PL_CSTRIDE; q += PL_THREADS) hcnt[q] = 0u;
     const int total_rows = Q.L * Q.ny;
 
     for (int i = blockIdx.x; i < Q.n; i += gridDim.x) {
@@ -355,7 +408,6 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
             ch.bad = (nh > 0 && (st < 0 || ch.c0 >= Q.h_chunks)) ? 1 : 0;
             list_chain(Q, ch, clist, nh);
         }
-        if (threadIdx.x < 64) cnt[threadIdx.x] = 0u;
         lds_barrier();
         const int nwin = (nh + PL_WIN - 1) / PL_WIN;
         // window 0 stays in registers for every pass; a listed chain needs no
@@ -369,14 +421,25 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
             const int64_t seg = Q.hoff[i];
             if (seg >= 0 && seg + nh <= Q.hcap) {
                 // hits per plane -> first place of each plane in the segment
-                count_planes(W0, cnt, N);
-                for (int w = 1; w < nwin; ++w) {
-                    if (!listed) walk_to_window(Q, ch, w, nh);
-                    count_window_planes(Q, ch, clist, w, nh, cnt, N);
+                count_planes(W0, hcnt, N);
+                if (listed) {
+                    count_listed_planes(Q, ch, clist, nh, hcnt, N);
+                } else {
+                    for (int w = 1; w < nwin; ++w) {
+                        walk_to_window(Q, ch, w, nh);
+                        count_window_planes(Q, ch, clist, w, nh, hcnt, N);
+                    }
                 }
                 lds_barrier();
                 if (threadIdx.x < 64) {
-                    const uint32_t v = cnt[threadIdx.x];
+                    // the copies summed (and cleared for the next shower),
+                    // plane totals -> plane starts
+                    uint32_t v = 0u;
+#pragma unroll
+                    for (int c = 0; c < PL_COPIES; ++c) {
+                        v += hcnt[c * PL_CSTRIDE + threadIdx.x];
+                        hcnt[c * PL_CSTRIDE + threadIdx.x] = 0u;
+                    }
                     uint32_t incl = v;
 #pragma unroll
                     for (int off = 1; off < 64; off <<= 1) {
