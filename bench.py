@@ -76,7 +76,7 @@ def parse():
                          "every ring with the workload's probabilities (measures the ring lookup)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="wall time of the oracle's host-CPU baseline (all threads)")
+                    help="wall time of the oracle's host-CPU baseline (all cores)")
     ap.add_argument("--cpu-seconds-1t", type=float, default=4.0,
                     help="wall time of the oracle's one-thread leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -126,51 +126,58 @@ def host_threads() -> int:
     return max(1, n)
 
 
-def oracle_sample_rate(w, geom, ids, threads: int, seconds: float, images: bool):
-    """The oracle on the showers `ids` of workload w (each its own call, with
-    its global shower id), taken in order by `threads` host threads until
-    `seconds` of wall time have passed: simulation with the tree, plus the
-    per-layer images when asked.  Returns (showers done, particle-steps,
-    elapsed s)."""
-    import threading
+def _oracle_showers(wname, geom, ids, seconds: float, images: bool):
+    """One host process: the oracle on the showers `ids` of workload wname in
+    order (each its own call, with its global shower id; the list is taken
+    again from the start if it runs out) until `seconds` have passed:
+    simulation with the tree, plus the per-layer images when asked.  Returns
+    (showers done, particle-steps, elapsed s)."""
     from oracle import supa_oracle as O
     from paper_2202_05012_amd import workloads
+    w = workloads.WORKLOADS[wname]
     e0, pol, az = workloads.initial_conditions(w)
-    lock = threading.Lock()
-    state = {"next": 0, "showers": 0, "steps": 0}
     L = int(max(geom["layer_of_plane"])) + 1 if geom.get("layer_of_plane") else int(geom["n_planes"])
+    showers = steps = 0
     t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        i = int(ids[showers % len(ids)])
+        r = O.simulate(geom, e0[i:i + 1], pol[i:i + 1], az[i:i + 1], w.seed, shower_id_base=i)
+        if images:
+            O.images(r, L, geom["img_nx"], geom["img_ny"], geom["img_x0"], geom["img_x1"],
+                     geom["img_y0"], geom["img_y1"])
+        showers += 1
+        steps += int(r["counts"][:, 2].sum())
+    return showers, steps, time.perf_counter() - t0
 
-    def worker():
-        while time.perf_counter() - t0 < seconds:
-            with lock:
-                j = state["next"]
-                state["next"] += 1
-            i = int(ids[j % len(ids)])
-            r = O.simulate(geom, e0[i:i + 1], pol[i:i + 1], az[i:i + 1], w.seed, shower_id_base=i)
-            if images:
-                O.images(r, L, geom["img_nx"], geom["img_ny"], geom["img_x0"], geom["img_x1"],
-                         geom["img_y0"], geom["img_y1"])
-            with lock:
-                state["showers"] += 1
-                state["steps"] += int(r["counts"][:, 2].sum())
 
-    ts = [threading.Thread(target=worker) for _ in range(threads)]
-    for t in ts:
-        t.start()
-    for t in ts:
-        t.join()
-    return state["showers"], state["steps"], time.perf_counter() - t0
+def _oracle_showers_star(args):
+    return _oracle_showers(*args)
+
+
+def oracle_sample_rate(w, geom, ids, procs: int, seconds: float, images: bool):
+    """The oracle on the showers `ids` of workload w for `seconds` of wall
+    time, in this process (procs = 1) or in `procs` host processes started
+    for it, each taking every procs-th shower of `ids` (processes, not
+    threads: the oracle's Python parts hold the interpreter lock, and threads
+    of one process ran slower together than one alone).  Returns (showers
+    done, particle-steps, elapsed s of the slowest process)."""
+    if procs <= 1:
+        return _oracle_showers(w.name, geom, ids, seconds, images)
+    import multiprocessing as mp
+    parts = [(w.name, geom, ids[q::procs], seconds, images) for q in range(procs)]
+    with mp.get_context("spawn").Pool(procs) as pool:
+        res = pool.map(_oracle_showers_star, parts)
+    return sum(r[0] for r in res), sum(r[1] for r in res), max(r[2] for r in res)
 
 
 def cpu_baseline_sampled(w, geom, seconds: float, seconds_1t: float, images: bool):
     """The oracle timed on a random subset of the workload's showers (drawn
     uniformly over all of them, so the per-shower mean of the subset
-    estimates the workload's), once on every host thread and once on one
-    thread; the showers/s of the whole workload is extrapolated from the
-    subset's per-shower rate."""
+    estimates the workload's), once in one host process per host core and
+    once in this process alone; the showers/s of the whole workload is
+    extrapolated from the subset's per-shower rate."""
     ids = np.random.default_rng(20260).permutation(w.n)
-    threads = host_threads()
+    threads = host_threads()        # host processes of the all-core leg
     n1, s1, t1 = oracle_sample_rate(w, geom, ids, 1, seconds_1t, images)
     # the all-thread leg takes showers the one-thread leg did not (a small
     # workload it exhausted is taken again from the start)
@@ -180,7 +187,7 @@ def cpu_baseline_sampled(w, geom, seconds: float, seconds_1t: float, images: boo
     return {"value": round(n / dt, 2), "unit": "showers/s", "cores": threads, "kind": "oracle",
             "sample": f"{n} showers drawn at random from the {w.n:,}" +
                       (" in repeated passes" if n > len(rest) else "") +
-                      f" ({what}, one oracle call per shower) on {threads} host threads in {dt:.1f} s; "
+                      f" ({what}, one oracle call per shower) in {threads} host processes for {dt:.1f} s; "
                       f"rate extrapolated per shower to the whole workload",
             "extrapolated": True, "seconds": round(dt, 2),
             "particle_steps_per_s": round(steps / dt, 1),
