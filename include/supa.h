@@ -147,8 +147,12 @@ typedef struct supa_batch {
  * [hit_offsets[i], hit_offsets[i] + counts[6*i+1]) of every hit array, with
  * hit_offsets the exclusive prefix sums of the hit counts in batch order, so
  * the segments tile [0, total_hits) in shower order.  Within a segment hits
- * are grouped by plane in increasing order; their order within a plane is
- * unspecified (the path id, SUPA_OUT_KEYS, is a canonical key).  Nodes: same
+ * are grouped by layer in increasing order (layer -1, planes not read out,
+ * first) and within a layer by plane in increasing order, so with a
+ * non-decreasing layer map (the identity by default) they are in plane
+ * order, and with any map the hits of one layer are contiguous; their order
+ * within a plane is unspecified (the path id, SUPA_OUT_KEYS, is a canonical
+ * key).  Nodes: same
  * rule with node_offsets and counts[6*i]; within a segment node j is the one
  * node_parent of its children refers to: the primary is node 0 and the two
  * daughters of a split are consecutive (a first), in the order the splits

@@ -76,8 +76,8 @@ enum {
  * aligned blocks of 32 entries that may reach outside a segment, never
  * outside the arrays; it cannot check the segments).  Hits of layer -1 (planes
  * not read out) are skipped.  Within a segment the hits of one layer must be
- * contiguous (true for supa_simulate's output whenever layer_of_plane is
- * non-decreasing over the read-out planes, i.e. layers are ranges of planes).
+ * contiguous (true for supa_simulate's output, which groups each segment by
+ * layer, whatever its layer map).
  *   n             showers, 0 <= n <= 2^31 - 1 (0: nothing is launched)
  *   n_layers      L, 1..64; hit layers must be < L
  *   layer_vars    out, float [n][L][SUPA_LAYER_VARS]

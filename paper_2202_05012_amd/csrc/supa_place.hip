@@ -4,9 +4,11 @@
 // log chunks that holds its hit records (the propagation kernel wrote them
 // there in the order it produced them):
 //   hit clouds  count the records per plane (LDS), turn the counts into plane
-//               starts within the shower's segment, and put every record at
-//               segment start + the next free place of its plane, so the
-//               segment is grouped by plane (order within a plane is free);
+//               starts within the shower's segment, planes taken in order of
+//               (layer, plane), and put every record at segment start + the
+//               next free place of its plane, so the segment is grouped by
+//               layer and, within a layer, by plane (order within a plane is
+//               free; with a non-decreasing layer map this is plane order);
 //               a segment of up to PL_WIN hits is sorted in LDS first and
 //               leaves with contiguous stores;
 //   images      (paper, appendix "Downsampling": a region of interest per
@@ -382,6 +384,7 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
     extern __shared__ __attribute__((aligned(16))) uint32_t slab[];    // zero between uses; 16-byte aligned for b128
     uint32_t *const scnt = slab + PL_SLAB_WORDS;       // [PL_MAX_SLABS + 1], BUCKET only
     __shared__ int32_t lay[64];
+    __shared__ int32_t pord[64];     // planes in order of (layer, plane)
     __shared__ uint32_t cnt[64];
     __shared__ uint32_t hcnt[PL_COPIES * PL_CSTRIDE];     // zero between showers
     __shared__ Chain ch;
@@ -393,6 +396,18 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
     if (hits && (int64_t)Q.sub[SUB_HITS] > Q.hcap) return;
     const int N = Q.n_planes;
     if (threadIdx.x < 64) lay[threadIdx.x] = (int)threadIdx.x < N ? Q.layer[threadIdx.x] : -1;
+    lds_barrier();
+    if (threadIdx.x < 64) {
+        // the rank of plane t among the planes in order of (layer, plane);
+        // planes past the last keep their place (they have no hits)
+        const int t = (int)threadIdx.x;
+        int r = t;
+        if (t < N) {
+            r = 0;
+            for (int k = 0; k < N; ++k) r += (lay[k] < lay[t] || (lay[k] == lay[t] && k < t)) ? 1 : 0;
+        }
+        pord[r] = t;
+    }
     clear_slab(slab, MODE == PM_HITS ? PL_STAGE_WORDS : PL_SLAB_WORDS);
     for (int q = (int)threadIdx.x; q < PL_COPIES * PL_CSTRIDE; q += PL_THREADS) hcnt[q] = 0u;
     const int total_rows = Q.L * Q.ny;
@@ -433,12 +448,14 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
                 lds_barrier();
                 if (threadIdx.x < 64) {
                     // the copies summed (and cleared for the next shower),
-                    // plane totals -> plane starts
+                    // plane totals -> plane starts, thread t taking the t-th
+                    // plane in order of (layer, plane)
+                    const int pl = pord[threadIdx.x];
                     uint32_t v = 0u;
 #pragma unroll
                     for (int c = 0; c < PL_COPIES; ++c) {
-                        v += hcnt[c * PL_CSTRIDE + threadIdx.x];
-                        hcnt[c * PL_CSTRIDE + threadIdx.x] = 0u;
+                        v += hcnt[c * PL_CSTRIDE + pl];
+                        hcnt[c * PL_CSTRIDE + pl] = 0u;
                     }
                     uint32_t incl = v;
 #pragma unroll
@@ -446,7 +463,7 @@ __attribute__((amdgpu_waves_per_eu((!KEYS && MODE == PM_HITS) ? 8 : 1))) supa_pl
                         const uint32_t t = __shfl_up(incl, off, 64);
                         if ((int)threadIdx.x >= off) incl += t;
                     }
-                    cnt[threadIdx.x] = incl - v;
+                    cnt[pl] = incl - v;
                 }
                 lds_barrier();
                 if (nh <= PL_WIN) {

@@ -24,6 +24,7 @@ torch = pytest.importorskip("torch")
 from oracle import shape_oracle as SO
 from oracle import supa_oracle as O
 from paper_2202_05012_amd import shapes as SH, supa, workloads
+from tests import parity
 
 pytestmark = pytest.mark.gpu
 
@@ -178,6 +179,35 @@ def test_shapes_of_simulated_showers_match_the_oracle_end_to_end():
     out = sim.simulate(_t(e0), _t(pol), _t(az), seed=w.seed)
     glv, gsv = SH.simulator_shapes(out, L)
     ref = O.simulate(geom, e0, pol, az, seed=w.seed)
+    e = (ref["hit_e"].astype(np.float32) * np.float32(2.0 ** -ref["frac_bits"])).astype(np.float64)
+    sid = ref["hit_sid"] - ref["shower_id_base"]
+    keep = ref["hit_layer"] >= 0
+    rlv, rsv = SO.shapes(n, L, sid[keep], ref["hit_layer"][keep], ref["hit_x"][keep],
+                         ref["hit_y"][keep], e[keep])
+    rmax = float(np.hypot(ref["hit_x"], ref["hit_y"]).max())
+    check_shapes(glv, gsv, rlv, rsv, coord_atol=1e-5 * max(rmax, 1.0))
+
+
+def test_simulated_showers_with_a_non_monotone_layer_map():
+    """Layers that are not ranges of planes (plane k read out as layer k mod 4,
+    plane 3 not read out): the simulator groups each segment by layer, so the
+    shape kernel takes its output as it is, and both match the oracle."""
+    w = workloads.WORKLOADS["e1to100_20planes_img32_100k"]
+    lmap = [k % 4 for k in range(20)]
+    lmap[3] = -1
+    geom = dict(workloads.geometry(w), layer_of_plane=lmap)
+    n = 96
+    e0, pol, az = workloads.initial_conditions(w, n)
+    L = supa.n_layers(geom)
+    sim = supa.Simulator(geom, supa.OUT_HITS | supa.OUT_KEYS)
+    out = sim.simulate(_t(e0), _t(pol), _t(az), seed=w.seed)
+    gpu = parity.to_numpy(out)
+    ref = O.simulate(geom, e0, pol, az, seed=w.seed)
+    parity.check_all(gpu, ref, geom)
+    for i in range(n):
+        seg = gpu["hit_layer"][gpu["hit_offsets"][i]:gpu["hit_offsets"][i] + gpu["counts"][i, 1]]
+        assert (np.diff(seg) >= 0).all(), f"shower {i}: layers not grouped"
+    glv, gsv = SH.simulator_shapes(out, L)
     e = (ref["hit_e"].astype(np.float32) * np.float32(2.0 ** -ref["frac_bits"])).astype(np.float64)
     sid = ref["hit_sid"] - ref["shower_id_base"]
     keep = ref["hit_layer"] >= 0
