@@ -100,10 +100,13 @@ constexpr int64_t HIT_CHUNK_WORDS = HIT_KEY_OFF + (int64_t)HIT_KEY_WORDS * HIT_C
 // its fill count written when it is closed); the scatter kernel moves every
 // record to its place once all showers are counted.
 constexpr int LOG_CHUNK = 2048;
-// node record: shower index, index within the shower, parent index,
-// generation | plane << 8 (plane 255: the primary, vertex z = 0), vertex
-// x and y, integer energy, path id (with keys)
-enum { NL_I = 0, NL_IDX, NL_PARENT, NL_GK, NL_X, NL_Y, NL_E, NL_LO, NL_HI, NL_FIELDS };
+// A node record holds the two daughters of one split, nodes IDX and IDX + 1
+// (IDX odd), which share shower, parent, generation, plane and vertex, or
+// the primary (IDX 0, one node): shower index, IDX, parent index,
+// generation | plane << 8 (plane 255: the primary, vertex z = 0), vertex x
+// and y, the integer energies of node IDX and of node IDX + 1, and with keys
+// the path id of node IDX (node IDX + 1: the same with the low bit set).
+enum { NL_I = 0, NL_IDX, NL_PARENT, NL_GK, NL_X, NL_Y, NL_E, NL_E2, NL_LO, NL_HI, NL_FIELDS };
 constexpr uint32_t GK_PRIMARY = 255u << 8;
 
 // Parameters of one simulate call that the hot loop reads, by value.

@@ -182,20 +182,6 @@ struct Slots {
 
 __device__ __forceinline__ int slot_get(int v, int s) { return __builtin_amdgcn_readlane(v, s); }
 
-// m0 .. m3 (wave-uniform, in scalar registers) in lanes 0 .. 3, zero in the
-// other lanes: one lane write each (constant lane numbers)
-__device__ __forceinline__ uint64_t lanes_of_slots(uint64_t m0, uint64_t m1, uint64_t m2, uint64_t m3) {
-    uint32_t lo = 0u, hi = 0u;
-    asm volatile("v_writelane_b32 %0, %1, 0" : "+v"(lo) : "s"((uint32_t)m0));
-    asm volatile("v_writelane_b32 %0, %1, 0" : "+v"(hi) : "s"((uint32_t)(m0 >> 32)));
-    asm volatile("v_writelane_b32 %0, %1, 1" : "+v"(lo) : "s"((uint32_t)m1));
-    asm volatile("v_writelane_b32 %0, %1, 1" : "+v"(hi) : "s"((uint32_t)(m1 >> 32)));
-    asm volatile("v_writelane_b32 %0, %1, 2" : "+v"(lo) : "s"((uint32_t)m2));
-    asm volatile("v_writelane_b32 %0, %1, 2" : "+v"(hi) : "s"((uint32_t)(m2 >> 32)));
-    asm volatile("v_writelane_b32 %0, %1, 3" : "+v"(lo) : "s"((uint32_t)m3));
-    asm volatile("v_writelane_b32 %0, %1, 3" : "+v"(hi) : "s"((uint32_t)(m3 >> 32)));
-    return ((uint64_t)hi << 32) | lo;
-}
 
 
 // Calls f(s, m) once for every distinct slot s among the lanes of mask, with
@@ -661,6 +647,7 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
                     r[NL_X * LOG_CHUNK] = __float_as_uint(x_first);
                     r[NL_Y * LOG_CHUNK] = __float_as_uint(y_first);
                     r[NL_E * LOG_CHUNK] = e_first;
+                    r[NL_E2 * LOG_CHUNK] = 0u;
                     if (keys) {
                         r[NL_LO * LOG_CHUNK] = 1u;
                         r[NL_HI * LOG_CHUNK] = 0u;
@@ -743,10 +730,8 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             // go to scratch memory.
             const uint64_t sm0 = wave_ballot(valid && slot == 0), sm1 = wave_ballot(valid && slot == 1);
             const uint64_t sm2 = wave_ballot(valid && slot == 2), sm3 = wave_ballot(valid && slot == 3);
-            // (own: written lane by lane from the scalar masks, which does
-            // not depend on the active lanes; mine: a select per lane)
-            const uint64_t own = lanes_of_slots(sm0, sm1, sm2, sm3);
             const uint64_t mine = slot == 0 ? sm0 : slot == 1 ? sm1 : slot == 2 ? sm2 : sm3;
+            const uint64_t own = lane == 0 ? sm0 : lane == 1 ? sm1 : lane == 2 ? sm2 : lane == 3 ? sm3 : 0ull;
             // node index of daughter a: the slot's node count + 2 per split
             // below (a shared shower's next indices come from its share)
             if (SUB && TREE && msplit) {
@@ -848,32 +833,30 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
                 });
             }
             if (TREE && msplit) {
-                const int m = 2 * (int)__popcll(msplit);
+                // one record per split: both daughters; the step's records
+                // grouped by slot, so that consecutive records are
+                // consecutive nodes of one shower (the scatter then writes
+                // runs instead of single nodes)
+                const int m = (int)__popcll(msplit);
                 const int ish = __shfl(S.i, slot, WAVE);
                 if (claim_nodes(m)) {
                     if (is_split) {
-                        uint32_t *r = P.nlog + (int64_t)nc * (NL_FIELDS * LOG_CHUNK) + nf +
-                                      2 * (int)lanes_below(msplit);
-                        const uint32_t gk = (uint32_t)(64 - __clzll(path)) | ((uint32_t)k << 8);
+                        const int n0 = (int)__popcll(msplit & sm0), n1 = (int)__popcll(msplit & sm1);
+                        const int n2 = (int)__popcll(msplit & sm2);
+                        const int below = slot == 0 ? 0 : slot == 1 ? n0 : slot == 2 ? n0 + n1 : n0 + n1 + n2;
+                        uint32_t *r = P.nlog + (int64_t)nc * (NL_FIELDS * LOG_CHUNK) + nf + below +
+                                      (int)lanes_below(msplit & mine);
                         r[NL_I * LOG_CHUNK] = (uint32_t)ish;
-                        r[NL_I * LOG_CHUNK + 1] = (uint32_t)ish;
                         r[NL_IDX * LOG_CHUNK] = (uint32_t)node_a;
-                        r[NL_IDX * LOG_CHUNK + 1] = (uint32_t)node_a + 1u;
                         r[NL_PARENT * LOG_CHUNK] = (uint32_t)p.node;
-                        r[NL_PARENT * LOG_CHUNK + 1] = (uint32_t)p.node;
-                        r[NL_GK * LOG_CHUNK] = gk;
-                        r[NL_GK * LOG_CHUNK + 1] = gk;
+                        r[NL_GK * LOG_CHUNK] = (uint32_t)(64 - __clzll(path)) | ((uint32_t)k << 8);
                         r[NL_X * LOG_CHUNK] = __float_as_uint(p.x);
-                        r[NL_X * LOG_CHUNK + 1] = __float_as_uint(p.x);
                         r[NL_Y * LOG_CHUNK] = __float_as_uint(p.y);
-                        r[NL_Y * LOG_CHUNK + 1] = __float_as_uint(p.y);
                         r[NL_E * LOG_CHUNK] = D.ea;
-                        r[NL_E * LOG_CHUNK + 1] = D.eb;
+                        r[NL_E2 * LOG_CHUNK] = D.eb;
                         if (keys) {
                             r[NL_LO * LOG_CHUNK] = (uint32_t)pa;
                             r[NL_HI * LOG_CHUNK] = (uint32_t)(pa >> 32);
-                            r[NL_LO * LOG_CHUNK + 1] = (uint32_t)pa | 1u;
-                            r[NL_HI * LOG_CHUNK + 1] = (uint32_t)(pa >> 32);
                         }
                     }
                     nf += m;

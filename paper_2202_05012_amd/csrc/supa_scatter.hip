@@ -120,6 +120,7 @@ __global__ void __launch_bounds__(SCAN_THREADS) scan_apply(ScanParams S) {
 }
 
 constexpr int SCATTER_THREADS = 256;
+constexpr int SCATTER_UNROLL = 4;      // records per thread in flight
 
 __global__ void __launch_bounds__(SCATTER_THREADS) scatter_nodes(ScatterParams Q, int32_t n) {
     if (batch_failed(Q.ctr) || (int64_t)Q.sub[SUB_NODES] > Q.ncap) return;
@@ -129,21 +130,50 @@ __global__ void __launch_bounds__(SCATTER_THREADS) scatter_nodes(ScatterParams Q
     for (int c = c_begin + (int)blockIdx.x; c < c_end; c += gridDim.x) {
         const int fill = min((int)Q.nfill[c], LOG_CHUNK);
         const uint32_t *rec = Q.nlog + (int64_t)c * (NL_FIELDS * LOG_CHUNK);
-        for (int j = (int)threadIdx.x; j < fill; j += SCATTER_THREADS) {
-            const uint32_t i = rec[NL_I * LOG_CHUNK + j];
-            if (i >= (uint32_t)n) continue;
-            const int64_t o = Q.noff[i] + rec[NL_IDX * LOG_CHUNK + j];
-            if (o < 0 || o >= Q.ncap) continue;
-            const uint32_t gk = rec[NL_GK * LOG_CHUNK + j];
-            const uint32_t k = gk >> 8;
-            Q.np[o] = (int32_t)rec[NL_PARENT * LOG_CHUNK + j];
-            Q.ng[o] = (int32_t)(gk & 255u);
-            Q.nvx[o] = __uint_as_float(rec[NL_X * LOG_CHUNK + j]);
-            Q.nvy[o] = __uint_as_float(rec[NL_Y * LOG_CHUNK + j]);
-            Q.nvz[o] = k == 255u ? 0.0f : Q.z_first + (float)k * Q.dz;
-            Q.ne[o] = (float)rec[NL_E * LOG_CHUNK + j] * Q.e_unscale;
-            if (Q.nk)
-                Q.nk[o] = ((uint64_t)rec[NL_HI * LOG_CHUNK + j] << 32) | rec[NL_LO * LOG_CHUNK + j];
+        // a record: the primary (index 0) or the two daughters of a split;
+        // SCATTER_UNROLL records per thread are read before any is written
+        // (one round trip for the records, one for their showers' offsets)
+        for (int j0 = 0; j0 < fill; j0 += SCATTER_THREADS * SCATTER_UNROLL) {
+            uint32_t ri[SCATTER_UNROLL], rx[SCATTER_UNROLL], rp[SCATTER_UNROLL], rg[SCATTER_UNROLL];
+            uint32_t xx[SCATTER_UNROLL], yy[SCATTER_UNROLL], e1[SCATTER_UNROLL], e2[SCATTER_UNROLL];
+            uint32_t lo[SCATTER_UNROLL], hi[SCATTER_UNROLL];
+            int64_t o[SCATTER_UNROLL];
+#pragma unroll
+            for (int u = 0; u < SCATTER_UNROLL; ++u) {
+                const int j = j0 + u * SCATTER_THREADS + (int)threadIdx.x;
+                const bool in = j < fill;
+                ri[u] = in ? rec[NL_I * LOG_CHUNK + j] : 0xffffffffu;
+                rx[u] = in ? rec[NL_IDX * LOG_CHUNK + j] : 0u;
+                rp[u] = in ? rec[NL_PARENT * LOG_CHUNK + j] : 0u;
+                rg[u] = in ? rec[NL_GK * LOG_CHUNK + j] : 0u;
+                xx[u] = in ? rec[NL_X * LOG_CHUNK + j] : 0u;
+                yy[u] = in ? rec[NL_Y * LOG_CHUNK + j] : 0u;
+                e1[u] = in ? rec[NL_E * LOG_CHUNK + j] : 0u;
+                e2[u] = in ? rec[NL_E2 * LOG_CHUNK + j] : 0u;
+                lo[u] = (in && Q.nk) ? rec[NL_LO * LOG_CHUNK + j] : 0u;
+                hi[u] = (in && Q.nk) ? rec[NL_HI * LOG_CHUNK + j] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < SCATTER_UNROLL; ++u)
+                o[u] = ri[u] < (uint32_t)n ? Q.noff[ri[u]] + rx[u] : -1;
+#pragma unroll
+            for (int u = 0; u < SCATTER_UNROLL; ++u) {
+                if (o[u] < 0) continue;
+                const uint32_t k = rg[u] >> 8;
+                const float z = k == 255u ? 0.0f : Q.z_first + (float)k * Q.dz;
+                const int nn = rx[u] == 0u ? 1 : 2;
+                for (int q = 0; q < nn; ++q) {
+                    const int64_t oq = o[u] + q;
+                    if (oq >= Q.ncap) continue;
+                    Q.np[oq] = (int32_t)rp[u];
+                    Q.ng[oq] = (int32_t)(rg[u] & 255u);
+                    Q.nvx[oq] = __uint_as_float(xx[u]);
+                    Q.nvy[oq] = __uint_as_float(yy[u]);
+                    Q.nvz[oq] = z;
+                    Q.ne[oq] = (float)(q ? e2[u] : e1[u]) * Q.e_unscale;
+                    if (Q.nk) Q.nk[oq] = (((uint64_t)hi[u] << 32) | lo[u]) | (uint64_t)q;
+                }
+            }
         }
     }
 }
