@@ -219,9 +219,10 @@ enum { SL_EXPORT = 0, SL_PHASE, SL_ITEMS_IN, SL_ITEM_CAP, SL_SHARE_CAP, SL_MARGI
 // LDS words of one wave: pool + the stop / split thresholds of every plane
 // pool, then the thresholds c1, c2 (u64) of 64 planes, of 4 rings with
 // regional parameters
-// (then the energy tallies: cut and stop energy per slot and lane)
+// (then the energy tallies: cut and stop energy per slot and lane, and the
+// slot masks of a step)
 __host__ __device__ constexpr int lds_words(int pool_cap, bool rings = false) {
-    return POOL_FIELDS * pool_cap + 2 * 2 * 64 * (rings ? 4 : 1) + SUB_LDS_WORDS + 2 * SLOTS * WAVE;
+    return POOL_FIELDS * pool_cap + 2 * 2 * 64 * (rings ? 4 : 1) + SUB_LDS_WORDS + 2 * SLOTS * WAVE + 2 * SLOTS;
 }
 
 // Keeps a wave-uniform value in scalar registers but hides it from loop-
@@ -278,6 +279,7 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
     // to its own word (LDS atomics without conflicts), a shower's words are
     // summed once when it ends (its energies sum to e0 < 2^32)
     uint32_t *const esum = sub_l + SUB_LDS_WORDS;
+    uint32_t *const smask = esum + 2 * SLOTS * WAVE;     // the four slot masks of a step
     for (int q = 0; q < 2 * SLOTS; ++q) esum[q * WAVE + lane] = 0u;
     __syncthreads();
     float rr1 = 0.f, rr2 = 0.f, rr3 = 0.f;        // squared ring radii
@@ -731,7 +733,14 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             const uint64_t sm0 = wave_ballot(valid && slot == 0), sm1 = wave_ballot(valid && slot == 1);
             const uint64_t sm2 = wave_ballot(valid && slot == 2), sm3 = wave_ballot(valid && slot == 3);
             const uint64_t mine = slot == 0 ? sm0 : slot == 1 ? sm1 : slot == 2 ? sm2 : sm3;
-            const uint64_t own = lane == 0 ? sm0 : lane == 1 ? sm1 : lane == 2 ? sm2 : lane == 3 ? sm3 : 0ull;
+            // own: the scalar masks through LDS (lane 0 writes all four,
+            // lane q < SLOTS reads mask q), with no divergent selection
+            if (lane == 0) {
+                *(uint4 *)(smask) = make_uint4((uint32_t)sm0, (uint32_t)(sm0 >> 32), (uint32_t)sm1, (uint32_t)(sm1 >> 32));
+                *(uint4 *)(smask + 4) = make_uint4((uint32_t)sm2, (uint32_t)(sm2 >> 32), (uint32_t)sm3, (uint32_t)(sm3 >> 32));
+            }
+            const uint2 ow = *(const uint2 *)(smask + 2 * (lane & (SLOTS - 1)));
+            const uint64_t own = (int)lane < SLOTS ? (((uint64_t)ow.y << 32) | ow.x) : 0ull;
             // node index of daughter a: the slot's node count + 2 per split
             // below (a shared shower's next indices come from its share)
             if (SUB && TREE && msplit) {
