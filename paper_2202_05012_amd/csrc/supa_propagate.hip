@@ -732,15 +732,17 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             // go to scratch memory.
             const uint64_t sm0 = wave_ballot(valid && slot == 0), sm1 = wave_ballot(valid && slot == 1);
             const uint64_t sm2 = wave_ballot(valid && slot == 2), sm3 = wave_ballot(valid && slot == 3);
-            const uint64_t mine = slot == 0 ? sm0 : slot == 1 ? sm1 : slot == 2 ? sm2 : sm3;
-            // own: the scalar masks through LDS (lane 0 writes all four,
-            // lane q < SLOTS reads mask q), with no divergent selection
+            // own and mine: the scalar masks through LDS (lane 0 writes all
+            // four; lane q < SLOTS reads mask q, every lane the mask of its
+            // particle's slot), with no selection per lane
             if (lane == 0) {
                 *(uint4 *)(smask) = make_uint4((uint32_t)sm0, (uint32_t)(sm0 >> 32), (uint32_t)sm1, (uint32_t)(sm1 >> 32));
                 *(uint4 *)(smask + 4) = make_uint4((uint32_t)sm2, (uint32_t)(sm2 >> 32), (uint32_t)sm3, (uint32_t)(sm3 >> 32));
             }
             const uint2 ow = *(const uint2 *)(smask + 2 * (lane & (SLOTS - 1)));
             const uint64_t own = (int)lane < SLOTS ? (((uint64_t)ow.y << 32) | ow.x) : 0ull;
+            const uint2 mn = *(const uint2 *)(smask + 2 * (slot & (SLOTS - 1)));
+            const uint64_t mine = ((uint64_t)mn.y << 32) | mn.x;
             // node index of daughter a: the slot's node count + 2 per split
             // below (a shared shower's next indices come from its share)
             if (SUB && TREE && msplit) {
