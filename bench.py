@@ -306,6 +306,30 @@ def bench_surrogate(args):
     tf = flops / (k_ms / 1e3) / 1e12
     workload_name = "surrogate_20layers_16x16"
     traffic = prof_summary.traffic_if_current(os.path.join(ROOT, "profiles"), "gate_fused_k256_kernel", workload_name)
+    # the per-layer head's whole forward pass in one kernel (mlp_fused_kernel)
+    # over 2^20 rows, timed with events on the stream it is launched on
+    # (torch's current stream); algorithmic flops from the network's own
+    # widths (19 inputs, not the zero-padded 32)
+    Bh = 1 << 20
+    eh, ph, ah = SP.draw_ics(Bh, 54321, dev)
+    xh_in = S.features(eh, ph, ah, 5, stream_id=2)
+    for _ in range(3):
+        head.forward_fused(xh_in)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    h_times = []
+    for _ in range(20):
+        ev0.record()
+        head.forward_fused(xh_in)
+        ev1.record()
+        ev1.synchronize()
+        h_times.append(ev0.elapsed_time(ev1))
+    h_ms = float(np.mean(h_times))
+    hdims = [S.IN_FEATURES + S.N_NOISE] + SP.layer_head_dims()[1:]
+    h_flops = 2.0 * Bh * sum(hdims[i] * hdims[i + 1] for i in range(len(hdims) - 1))
+    h_tf = h_flops / (h_ms / 1e3) / 1e12
+    h_workload = "surrogate_layer_head_1m_rows"
+    h_traffic = prof_summary.traffic_if_current(os.path.join(ROOT, "profiles"), "mlp_fused_kernel", h_workload)
+    del eh, ph, ah, xh_in
     line = {
         "metric": "surrogate+fallback showers/s at W1 <= 2% of the mean per-layer energy",
         "value": round(best["showers_per_s"], 1) if best else None,
@@ -327,6 +351,12 @@ def bench_surrogate(args):
                      "kernel_ms": round(k_ms, 4), "launch_ms": {"means": round(t_mean, 4), "log_variances":
                                                                  round(t_var, 4), "gate_rows": round(t_gate, 4)},
                      "alg_flops": flops, "rows": B},
+        "roofline_head": {"bound": "mfma", "achieved": round(h_tf, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                          "frac": round(h_tf / 2500.0, 4), "traffic": h_traffic,
+                          "kernel": "mlp_fused_kernel (the per-layer head's forward pass, "
+                                    "19 -> 4x256 GELU -> 40, in one launch)",
+                          "kernel_ms": round(h_ms, 4), "alg_flops": h_flops, "rows": Bh,
+                          "profile_workload": h_workload},
         "train_seconds": round(t_train, 2), "loss_curve": losses, "head_loss_curve": head_losses,
         "rho": rho, "chosen": best, "sweep": rows, "sweep_layer_head": hrows,
     }

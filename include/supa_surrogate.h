@@ -165,14 +165,16 @@ supa_status supa_surrogate_last_times(float *ms, int32_t count);
 
 /*
  * The network's forward pass in one kernel (inference): n_hidden (1..8)
- * layers of 256 units, bias + GELU (erf form), on k_in inputs (x bf16
+ * layers of 256 units, bias + GELU, on k_in inputs (x bf16
  * [B][ldx], k_in a multiple of 16 up to 256), then with n_out > 0 a linear
  * layer of n_out outputs (a multiple of 4, at most 64) into out (float
  * [B][ldo]), else the last hidden activations into h (bf16 [B][ldh]).  The
  * activations stay in registers: a workgroup takes 256 rows through every
  * layer, each layer's weights streaming through LDS.  The same values as
  * supa_gemm_bf16 layer by layer (BIAS_GELU, then BIAS_F32) up to the order
- * of the float sums.  wt and bias: host arrays of device pointers, one per
+ * of the float sums (the bias first here) and the GELU, evaluated through a
+ * polynomial of Phi within 5.9e-5 |a| of the exact one (erf form) at every
+ * a.  wt and bias: host arrays of device pointers, one per
  * layer (hidden layers, then the output layer): wt[l] bf16 [out][in] as
  * written by supa_mlp_fused_weights (layer 0 with permute = 0, the others
  * with permute = 1), bias[l] float [out].  x, weights and the output

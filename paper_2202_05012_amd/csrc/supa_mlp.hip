@@ -744,18 +744,27 @@ __host__ __device__ constexpr int mlp_permute_k(int k) {
     return (k & ~12) | ((k & 4) << 1) | ((k & 8) >> 1);
 }
 
-// GELU(a) = a Phi(a), Phi(a) = erfc(-a / sqrt 2) / 2, with erfc(x) for x >= 0
-// from Abramowitz & Stegun 7.1.26 (absolute error <= 1.5e-7, far below the
-// bf16 rounding that follows): t = 1 / (1 + p x),
-// erfc(x) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2); about a
-// third of the instructions of the erfcf form (gelu_f, kept for training)
-__device__ __forceinline__ float gelu_as(float a) {
-    const float x = fabsf(a) * 0.707106781f;
-    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, x, 1.0f));
-    const float poly =
-        t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
-    const float h = 0.5f * poly * __builtin_amdgcn_exp2f(-1.44269504f * x * x);     // Phi(-|a|)
-    return a * (a >= 0.0f ? 1.0f - h : h);
+// GELU(a) = a Phi(a) with Phi(a) - 1/2 = c a P(c^2), c = a clamped to
+// [-3.7, 3.7] and P a polynomial of degree 6: a weighted least-squares fit
+// driven to equal ripple (Lawson's iteration, Chebyshev basis on the clamped
+// range, then powers of c^2; gelu_poly_fit.py prints the coefficients).  In
+// float32 its Phi is within 5.9e-5 of the exact one for every a (the clamp
+// included: Phi(-3.7) ~ 1.1e-4 is split between both ends), so GELU is off by
+// at most 5.9e-5 |a|: a fiftieth of the bf16 rounding of the result.  Seven
+// multiply-adds and no transcendental: the erfc forms cost two
+// quarter-rate instructions and ten more per element (gelu_f, exact, is kept
+// for training).
+__device__ __forceinline__ float gelu_poly(float a) {
+    const float c = __builtin_amdgcn_fmed3f(a, -3.7f, 3.7f);
+    const float s = c * c;
+    float p = 4.174848555749122e-08f;
+    p = fmaf(p, s, -2.483809566911077e-06f);
+    p = fmaf(p, s, 6.402656435966492e-05f);
+    p = fmaf(p, s, -0.0009566032676957548f);
+    p = fmaf(p, s, 0.009406556375324726f);
+    p = fmaf(p, s, -0.06585532426834106f);
+    p = fmaf(p, s, 0.398733526468277f);       // ~ 1 / sqrt(2 pi) = Phi'(0)
+    return a * fmaf(c, p, 0.5f);
 }
 
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
@@ -796,7 +805,7 @@ __device__ __forceinline__ void mf_issue(const MfState &S, int u, GfTile &W, flo
                                          (__attribute__((address_space(3))) void *)(Bt + 64 * S.wave), 4, 0, 0);
 }
 
-// acc[i] = the products of tile rows 32 i + .. (i < NI) with this wave's rows
+// acc[i] += the products of tile rows 32 i + .. (i < NI) with this wave's rows
 template <int NI>
 __device__ __forceinline__ void mf_products(const MfState &S, const GfTile &W, int ks, floatx16_t (&acc)[4]) {
     const char *base[NI][2];
@@ -816,7 +825,7 @@ __device__ __forceinline__ void mf_products(const MfState &S, const GfTile &W, i
 #pragma unroll
             for (int i = 0; i < NI; ++i)
                 acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w[i], __builtin_bit_cast(bf16x8_t, S.hb[kk]),
-                                                                  kk == 0 ? floatx16_t{} : acc[i], 0, 0, 0);
+                                                                  acc[i], 0, 0, 0);
         }
     }
 }
@@ -828,7 +837,19 @@ __device__ __forceinline__ void mf_tile(MfState &S, int u, const GfTile &Wc, con
                                         float *Bn) {
     const MlpFusedArgs &a = *S.a;
     if (u + 1 < S.tiles) mf_issue(S, u + 1, Wn, Bn);
+    // the accumulators start from the bias of their outputs (output 32 i +
+    // 8 g + 4 lh + q in element 4 g + q of acc[i]): no add per element after
+    // the products.  Bias words past a final layer's n_out are whatever the
+    // buffer held; their outputs are not stored.
     floatx16_t acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const floatx4_t bv = *(const floatx4_t *)&Bc[32 * i + 8 * g + 4 * S.lh];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[i][4 * g + q] = bv[q];
+        }
     if (FINAL && u == 2 * a.n_hidden) {
         mf_products<2>(S, Wc, 16, acc);
         // outputs 32 i + 8 g + 4 lh + q of this lane's row
@@ -839,10 +860,9 @@ __device__ __forceinline__ void mf_tile(MfState &S, int u, const GfTile &Wc, con
                 for (int g = 0; g < 4; ++g) {
                     const int f = 32 * i + 8 * g + 4 * S.lh;
                     if (f < a.n_out) {
-                        const floatx4_t bv = *(const floatx4_t *)&Bc[f];
                         floatx4_t v;
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) v[q] = acc[i][4 * g + q] + bv[q];
+                        for (int q = 0; q < 4; ++q) v[q] = acc[i][4 * g + q];
                         *(floatx4_t *)(a.out + (int64_t)S.row * a.ldo + f) = v;
                     }
                 }
@@ -851,16 +871,15 @@ __device__ __forceinline__ void mf_tile(MfState &S, int u, const GfTile &Wc, con
         const int l = u >> 1, hf = u & 1;
         mf_products<4>(S, Wc, l == 0 ? a.k_in / 16 : 16, acc);
         const bool out_h = !FINAL && l == a.n_hidden - 1;
-        // bias + GELU + bf16: outputs 128 hf + 32 i + 8 g + 4 lh + q become
+        // GELU + bf16: outputs 128 hf + 32 i + 8 g + 4 lh + q become
         // element 4 (g & 1) + q of the next layer's K step 8 hf + 2 i + (g >> 1)
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
-                const floatx4_t bv = *(const floatx4_t *)&Bc[32 * i + 8 * g + 4 * S.lh];
                 float y[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) y[q] = gelu_as(acc[i][4 * g + q] + bv[q]);
+                for (int q = 0; q < 4; ++q) y[q] = gelu_poly(acc[i][4 * g + q]);
                 const uint32_t lo = pack_bf16x2(y[0], y[1]), hi = pack_bf16x2(y[2], y[3]);
                 u32x4_t &t = S.hn[8 * hf + 2 * i + (g >> 1)];
                 t[2 * (g & 1)] = lo;

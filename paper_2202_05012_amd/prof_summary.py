@@ -41,6 +41,7 @@ KERNEL_SOURCES = {
     "grids_kernel": ["supa_grids.hip"],
     "gate_fused_k256_kernel": ["supa_mlp.hip", "supa_mlp.hpp"],
     "gemm_bf16": ["supa_mlp.hip", "supa_mlp.hpp"],
+    "mlp_fused_kernel": ["supa_mlp.hip", "supa_mlp.hpp"],
 }
 
 
@@ -55,7 +56,7 @@ def source_hash(kernel: str) -> str:
 def short_name(full: str) -> str:
     m = re.search(r"(supa_propagate|supa_place|scatter_nodes|scan_tiles|scan_top|scan_apply|shapes_kernel|"
                   r"shapes_clear|w1_stats|w1_hist|w1_colinfo|w1_distance|w1_groups|w1_zero|grids_kernel|"
-                  r"gate_fused_k256_kernel|gemm_bf16|gate_tiles_kernel|gate_rows_kernel|features_kernel)\b", full)
+                  r"gate_fused_k256_kernel|gemm_bf16|gate_tiles_kernel|gate_rows_kernel|features_kernel|mlp_fused_kernel)\b", full)
     return m.group(1) if m else full
 
 

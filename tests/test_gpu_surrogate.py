@@ -559,21 +559,22 @@ def fused_chain_bound(x, Ws, bs, n_hidden, final):
     """The FP64 forward chain of an MLP on bf16 inputs and weights (no rounding
     of the activations) and a bound on how far a device pass may be from it
     per element: each hidden activation is rounded to bf16 (2^-8 relative)
-    after a float32 sum (2e-6 * sum |a||w|), GELU is 1.13-Lipschitz and is
-    evaluated through an erfc approximation of absolute error 1.5e-7 (Phi off
-    by 1e-7 with the float rounding of its terms, GELU by 1e-7 |z|), and the
-    errors of a layer's inputs pass through |W|."""
+    after a float32 sum that starts from the bias (2e-6 * (sum |a||w| + |b|)),
+    GELU is 1.13-Lipschitz and is evaluated through a polynomial of Phi
+    within 5.9e-5 of the exact one (GELU off by 5.9e-5 |z|), and the errors of
+    a layer's inputs pass through |W|."""
     a, err = x, np.zeros_like(x)
     for l in range(n_hidden):
         z = a @ Ws[l] + bs[l]
-        acc = 2e-6 * (np.abs(a) @ np.abs(Ws[l])) + 1e-7
+        acc = 2e-6 * (np.abs(a) @ np.abs(Ws[l]) + np.abs(bs[l])) + 1e-7
         g = SO.gelu(z)
-        err = 2.0 ** -8 * np.abs(g) + 1e-7 * np.abs(z) + 1.13 * (acc + err @ np.abs(Ws[l]))
+        err = 2.0 ** -8 * np.abs(g) + 5.9e-5 * np.abs(z) + 1.13 * (acc + err @ np.abs(Ws[l]))
         a = g
     if not final:
         return a, err
     out = a @ Ws[n_hidden] + bs[n_hidden]
-    return out, err @ np.abs(Ws[n_hidden]) + 2e-6 * (np.abs(a) @ np.abs(Ws[n_hidden])) + 1e-7
+    return out, (err @ np.abs(Ws[n_hidden]) + 2e-6 * (np.abs(a) @ np.abs(Ws[n_hidden]) + np.abs(bs[n_hidden]))
+                 + 1e-7)
 
 
 @pytest.mark.parametrize("dims,B,final", [([32, 256, 40], 1000, True), ([32, 256, 256, 8], 776, False),
