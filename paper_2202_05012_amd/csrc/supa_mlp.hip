@@ -744,7 +744,7 @@ __host__ __device__ constexpr int mlp_permute_k(int k) {
     return (k & ~12) | ((k & 4) << 1) | ((k & 8) >> 1);
 }
 
-// GELU(a) = a Phi(a) with Phi(a) - 1/2 = c a P(c^2), c = a clamped to
+// GELU(a) = a Phi(a) with Phi(a) - 1/2 = c P(c^2), c = a clamped to
 // [-3.7, 3.7] and P a polynomial of degree 6: a weighted least-squares fit
 // driven to equal ripple (Lawson's iteration, Chebyshev basis on the clamped
 // range, then powers of c^2; gelu_poly_fit.py prints the coefficients).  In
