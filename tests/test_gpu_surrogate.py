@@ -310,6 +310,28 @@ def test_features_match_oracle():
     assert (got[:, n:] == 0).all()
 
 
+def test_features_row_layouts_agree():
+    """The network's 32-wide rows (built in registers, 16-byte stores) and
+    the general kernel's rows (any width; here 40, one store per input) hold
+    the same bits in their first 32 inputs, and the general rows zeros after
+    them; ragged against the 128-row blocks."""
+    rng = np.random.default_rng(21)
+    B = 1000
+    e0 = torch.from_numpy(rng.uniform(1, 100, B).astype(np.float32)).cuda()
+    pol = torch.from_numpy(rng.uniform(0, math.radians(15), B).astype(np.float32)).cuda()
+    az = torch.from_numpy(rng.uniform(0, 2 * math.pi, B).astype(np.float32)).cuda()
+    seed, row_base, stream = 0xFEDCBA9876543210, 12345, 3
+    fast = S.features(e0, pol, az, seed=seed, row_base=row_base, stream_id=stream)
+    wide = torch.full((B, 40), -1, dtype=torch.int16, device=e0.device)
+    S._check(S._lib().supa_surrogate_features(S._stream(), B, 40, S.N_NOISE, S._p(e0), S._p(pol), S._p(az),
+                                              1.0 / 100.0, 1.0 / math.radians(15.0), 1.0 / (2 * math.pi),
+                                              row_base, stream, seed, S._p(wide)))
+    f, w = fast.cpu().numpy(), wide.cpu().numpy()
+    np.testing.assert_array_equal(f, w[:, :32])
+    assert (w[:, 32:] == 0).all()
+    assert (f[:, 3 + S.N_NOISE:] == 0).all()
+
+
 def _gate_case(rng, B, L, bins):
     D = L * bins
     out = np.empty((B, 2 * D), np.float32)
