@@ -1095,15 +1095,19 @@ hipError_t launch_features(int B, int ld, int n_noise, const float *e0, const fl
 // quantities as gate_kernel (with one bin the layer's sd is its sigma for
 // every rho, and the same Philox counters give z).  A wave's 64 rows pass
 // through LDS in both directions, so that global reads and writes are
-// contiguous; rows are padded to an odd length against bank conflicts.
+// contiguous; rows are padded to an odd length against bank conflicts, and
+// a row's outputs overwrite its means (layer l's mean is read before its
+// output is written), which keeps the LDS per workgroup small enough for
+// about fifteen waves per CU.  The layers' Philox blocks are independent:
+// the loop is unrolled by four so that their work interleaves.
 constexpr int GR_ROWS = 64;
 
 __global__ void __launch_bounds__(GR_ROWS) gate_rows_kernel(int B, int L, const float *out, const float *e0,
                                                             float y_scale, float s_clamp, float *layer_e, float *unc,
                                                             float rho, uint32_t row_base, uint32_t k0, uint32_t k1) {
     extern __shared__ float gr_lds[];
-    const int in_ld = 2 * L + 1, out_ld = L + 1;
-    float *tin = gr_lds, *tout = gr_lds + GR_ROWS * in_ld;
+    const int in_ld = 2 * L + 1, out_ld = in_ld;
+    float *tin = gr_lds, *tout = gr_lds;
     const int b0 = blockIdx.x * GR_ROWS;
     const int rows = min(GR_ROWS, B - b0);
     const float *src = out + (int64_t)b0 * 2 * L;
@@ -1118,6 +1122,7 @@ __global__ void __launch_bounds__(GR_ROWS) gate_rows_kernel(int B, int L, const 
         const float *row = tin + r * in_ld;
         const float scale = e0[b] / y_scale;
         float tm = 0.f, tv = 0.f;
+#pragma unroll 4
         for (int l = 0; l < L; ++l) {
             const float mu = row[l];
             const float sv = fminf(fmaxf(row[L + l], -s_clamp), s_clamp);
@@ -1148,7 +1153,7 @@ hipError_t launch_gate(int B, int D, int L, const float *out, const float *e0, f
                        float s_clamp, float *layer_e, float *unc, float *img, float rho,
                        uint32_t row_base, uint64_t seed, hipStream_t s) {
     if (D == L && L <= 64 && !img) {
-        const size_t lds = (size_t)GR_ROWS * (3 * L + 2) * sizeof(float);      // <= 50 KB for L <= 64
+        const size_t lds = (size_t)GR_ROWS * (2 * L + 1) * sizeof(float);      // <= 33 KB for L <= 64
         hipLaunchKernelGGL(gate_rows_kernel, dim3((unsigned)((B + GR_ROWS - 1) / GR_ROWS)), dim3(GR_ROWS), lds, s, B,
                            L, out, e0, y_scale, s_clamp, layer_e, unc, rho, row_base, (uint32_t)seed,
                            (uint32_t)(seed >> 32));
