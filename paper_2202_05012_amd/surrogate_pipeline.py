@@ -68,11 +68,14 @@ def train(model: S.MLP | None, steps: int, batch: int, seed: int = 100, lr: floa
           log_every: int = 0, sim: ImageSimulator | None = None, device="cuda",
           mean_first: float = 0.0, head: S.MLP | None = None):
     """Online training: every step simulates a fresh batch (shower ids never
-    repeat) and takes one Adam step on the Gaussian NLL; the first
-    `mean_first` fraction of the steps fit the means only (log-variance held
-    at 0, i.e. squared error).  With `head`, the per-layer head takes a step
-    on the same batch, its targets the images' per-layer sums.  Returns the
-    image model's loss curve (and the head's) and the seconds taken."""
+    repeat) and takes one Adam step for the image model: its log-variances on
+    the Gaussian NLL, its means by squared error (fitted by the NLL, the many
+    near-empty cells with tiny variances dominate the shared layers and the
+    per-layer sums drift); the first `mean_first` fraction of the steps fit
+    the means only (log-variance held at 0).  With `head`, the per-layer head
+    takes a step on the same batch, its targets the images' per-layer sums,
+    means and log-variances both on the Gaussian NLL.  Returns the image
+    model's loss curve (and the head's) and the seconds taken."""
     sim = sim or ImageSimulator()
     losses, head_losses = [], []
     t0 = time.perf_counter()
@@ -84,8 +87,10 @@ def train(model: S.MLP | None, steps: int, batch: int, seed: int = 100, lr: floa
         loss = model.train_step(x, img, e0, lr=cur_lr,
                                 s_clamp=0.0 if step < mean_first * steps else None) \
             if model is not None else None
-        hloss = head.train_step(x, S.group_sums(img, N_LAYERS), e0, lr=cur_lr, y_scale=Y_SCALE_HEAD) \
-            if head is not None else None
+        # the head fits means and log-variances by the Gaussian NLL (it has no
+        # near-empty outputs to dominate the fit; see the image model's step)
+        hloss = head.train_step(x, S.group_sums(img, N_LAYERS), e0, lr=cur_lr, y_scale=Y_SCALE_HEAD,
+                                mse_mean=False) if head is not None else None
         if log_every and (step % log_every == 0 or step == steps - 1):
             if model is not None:
                 losses.append((step, float(loss.item())))
