@@ -727,6 +727,13 @@ def bench_batched(args, w):
                  "traffic": prof_summary.traffic_if_current(prof_dir, "supa_propagate", w.name),
                  "kernel": "supa_propagate", "kernel_ms": round(k_prop, 4),
                  "alg_lane_ops": int(alg_ops / len(calls)), "per": "launch", "launches_per_step": len(calls)}
+    if not args.serial_calls:
+        # pipelined calls: the propagation of call j + 1 runs on its own stream
+        # beside the placement of call j, with the wave slots the placement
+        # leaves, and a call of this size fills part of the persistent grid
+        waves = len(sim.wave_times())             # the last launch's persistent grid
+        roof_prop["note"] = (f"runs beside supa_place (off the critical path); {chunk} showers per call "
+                             f"fill {(chunk + 3) // 4} of the launch's {waves} four-shower waves")
     kern = sorted([(k_place, roof_place), (k_prop, roof_prop), (k_scatter, roof_scatter)], key=lambda t: -t[0])
     line = {
         "metric": "showers/s (1 MI355X)", "value": round(w.n / (ms_per_step / 1e3), 1), "unit": "showers/s",
