@@ -669,8 +669,10 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             const bool valid = (int)lane < nb;
             const int j = top - 1 - (int)lane;
             if (top - nb < lo) __threadfence_block();    // spilled entries: see other lanes' stores
-            Entry p{0.f, 0.f, 0.f, 0.f, 0u, 0u, 0u, 0, 0u};
-            if (valid) p = pool_load(j);
+            // lanes past the pending particles load the top entry again: every
+            // use of p below is masked by this step's flags, so its values
+            // need no clearing first
+            const Entry p = pool_load(valid ? j : top - 1);
             top -= nb;
             lo = min(lo, top);
             const int k = (int)(p.ks & 255u), slot = (int)(p.ks >> 8);
