@@ -681,6 +681,26 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             top -= nb;
             lo = min(lo, top);
             const int k = (int)(p.ks & 255u), slot = (int)(p.ks >> 8);
+            // the lanes of each shower slot; `mine`: this lane's slot, `own`:
+            // in lanes 0..SLOTS-1, the lanes of slot `lane` (whose state the
+            // lane holds).  Named registers: a run-time-indexed array would
+            // go to scratch memory.  Taken before the draw, so that lane 0's
+            // write below is a branch around which hardly any lane mask is
+            // live (masks live across a divergent branch are copied through
+            // vector registers, two instructions each)
+            const uint64_t sm0 = wave_ballot(valid && slot == 0), sm1 = wave_ballot(valid && slot == 1);
+            const uint64_t sm2 = wave_ballot(valid && slot == 2), sm3 = wave_ballot(valid && slot == 3);
+            // own and mine: the scalar masks through LDS (lane 0 writes all
+            // four; lane q < SLOTS reads mask q, every lane the mask of its
+            // particle's slot), with no selection per lane
+            if (lane == 0) {
+                *(uint4 *)(smask) = make_uint4((uint32_t)sm0, (uint32_t)(sm0 >> 32), (uint32_t)sm1, (uint32_t)(sm1 >> 32));
+                *(uint4 *)(smask + 4) = make_uint4((uint32_t)sm2, (uint32_t)(sm2 >> 32), (uint32_t)sm3, (uint32_t)(sm3 >> 32));
+            }
+            const uint2 ow = *(const uint2 *)(smask + 2 * (lane & (SLOTS - 1)));
+            const uint64_t own = (int)lane < SLOTS ? (((uint64_t)ow.y << 32) | ow.x) : 0ull;
+            const uint2 mn = *(const uint2 *)(smask + 2 * (slot & (SLOTS - 1)));
+            const uint64_t mine = ((uint64_t)mn.y << 32) | mn.x;
             const uint32_t sid = (uint32_t)__shfl((int)S.sid, slot, WAVE);
             const uint4 w = philox4x32_10((uint32_t)k, sid, p.lo, p.hi, opaque_u32(P.seed_lo),
                                           opaque_u32(P.seed_hi));
@@ -733,23 +753,6 @@ __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(4))) 
             const uint64_t mpa = wave_ballot(push_a), mpb = wave_ballot(push_b);
             const uint64_t msplit = wave_ballot(is_split), mpass = wave_ballot(is_pass);
             const uint64_t mesc = wave_ballot(esc_n > 0);
-            // the lanes of each shower slot; `mine`: this lane's slot, `own`:
-            // in lanes 0..SLOTS-1, the lanes of slot `lane` (whose state the
-            // lane holds).  Named registers: a run-time-indexed array would
-            // go to scratch memory.
-            const uint64_t sm0 = wave_ballot(valid && slot == 0), sm1 = wave_ballot(valid && slot == 1);
-            const uint64_t sm2 = wave_ballot(valid && slot == 2), sm3 = wave_ballot(valid && slot == 3);
-            // own and mine: the scalar masks through LDS (lane 0 writes all
-            // four; lane q < SLOTS reads mask q, every lane the mask of its
-            // particle's slot), with no selection per lane
-            if (lane == 0) {
-                *(uint4 *)(smask) = make_uint4((uint32_t)sm0, (uint32_t)(sm0 >> 32), (uint32_t)sm1, (uint32_t)(sm1 >> 32));
-                *(uint4 *)(smask + 4) = make_uint4((uint32_t)sm2, (uint32_t)(sm2 >> 32), (uint32_t)sm3, (uint32_t)(sm3 >> 32));
-            }
-            const uint2 ow = *(const uint2 *)(smask + 2 * (lane & (SLOTS - 1)));
-            const uint64_t own = (int)lane < SLOTS ? (((uint64_t)ow.y << 32) | ow.x) : 0ull;
-            const uint2 mn = *(const uint2 *)(smask + 2 * (slot & (SLOTS - 1)));
-            const uint64_t mine = ((uint64_t)mn.y << 32) | mn.x;
             // node index of daughter a: the slot's node count + 2 per split
             // below (a shared shower's next indices come from its share)
             if (SUB && TREE && msplit) {
