@@ -436,6 +436,15 @@ supa_status supa_last_wave_times(supa_ctx *ctx, float *ms, int32_t capacity, int
 supa_status supa_philox(supa_ctx *ctx, const uint32_t *ctr, int64_t n, uint64_t key,
                         uint32_t *out);
 
+/*
+ * The sine and cosine of a split's azimuth omega = 2 pi u(w3), u(w) =
+ * (w + 1/2) / 2^32 (Algorithm 1's uniform angle of the split plane), as the
+ * propagation kernel evaluates them, for n words: w device uint32 [n],
+ * sin_out and cos_out device float [n].  For checking them against the
+ * definition.  INVALID_ARG for n < 0 or NULL arrays with n > 0.
+ */
+supa_status supa_azimuth(supa_ctx *ctx, const uint32_t *w, int64_t n, float *sin_out, float *cos_out);
+
 /* Description of the last error of ctx (or of the last failed
  * supa_init_geometry when ctx is NULL); owned by the library. */
 const char *supa_last_error(const supa_ctx *ctx);

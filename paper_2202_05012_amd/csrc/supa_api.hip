@@ -24,6 +24,7 @@ hipError_t launch_note_chunks(const unsigned long long *ctr, unsigned long long 
 hipError_t launch_propagate(const Params &P, bool literal, bool rings, int blocks, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,
                          hipStream_t s);
+hipError_t launch_azimuth(const uint32_t *w, int64_t n, float *sn, float *cs, hipStream_t s);
 size_t propagate_lds_bytes(int pool_cap, bool rings);
 hipError_t launch_place(const PlaceParams &P, int n_cu, hipStream_t s);
 void place_bucket_size(int L, int nx, int ny, bool keys, int n_cu, int64_t *per_block, int64_t *blocks);
@@ -520,6 +521,17 @@ extern "C" supa_status supa_philox(supa_ctx *c, const uint32_t *ctr, int64_t n, 
     if (n < 0 || (n > 0 && (!ctr || !out))) return fail(c, SUPA_ERR_INVALID_ARG, "bad philox arguments");
     HIP_TRY(c, hipSetDevice(c->device));
     HIP_TRY(c, supa::launch_philox(ctr, n, (uint32_t)key, (uint32_t)(key >> 32), out, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return SUPA_OK;
+}
+
+extern "C" supa_status supa_azimuth(supa_ctx *c, const uint32_t *w, int64_t n, float *sin_out,
+                                    float *cos_out) {
+    if (!c) return SUPA_ERR_STATE;
+    if (n < 0 || (n > 0 && (!w || !sin_out || !cos_out)))
+        return fail(c, SUPA_ERR_INVALID_ARG, "bad azimuth arguments");
+    HIP_TRY(c, hipSetDevice(c->device));
+    HIP_TRY(c, supa::launch_azimuth(w, n, sin_out, cos_out, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return SUPA_OK;
 }

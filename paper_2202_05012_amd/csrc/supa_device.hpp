@@ -294,6 +294,17 @@ __device__ __forceinline__ void sincos_f32(float x, float *s, float *c) {
     *c = ((q + 1) & 2) ? -b : b;
 }
 
+// sin and cos of the azimuth omega = 2 pi u(w) of a split: (signed w + 1/2)
+// / 2^32 is the same angle mod 2 pi in revolutions, the argument the
+// hardware sine and cosine take, so there is no range reduction (within
+// 2.5e-7 of the exact values: tests/test_gpu_parity.py checks it against
+// the definition in double precision)
+__device__ __forceinline__ void azimuth_sincos(uint32_t w, float *s, float *c) {
+    const float rev = ((float)(int32_t)w + 0.5f) * 0x1p-32f;
+    *s = __builtin_amdgcn_sinf(rev);
+    *c = __builtin_amdgcn_cosf(rev);
+}
+
 // -ln(u(w)) for u(w) = (w + 1/2) / 2^32 in (0, 1).  Below 1/2 through the
 // hardware base-2 logarithm (accurate relative to |log2 u| >= 1); above, with
 // v = 1 - u, as 2 atanh(t), t = v / (2 - v) <= 1/3, summed to t^15.

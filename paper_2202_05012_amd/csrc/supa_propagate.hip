@@ -96,14 +96,11 @@ __device__ __forceinline__ Daughters split_particle(const Params &P, float tx, f
         D.fwd_a = D.fwd_b = true;
         return D;
     }
-    // omega = 2 pi u(w3), taken as (signed w3 + 1/2) / 2^32 revolutions (the
-    // same angle mod 2 pi), the argument the hardware sine and cosine take:
-    // two instructions instead of a reduction to [-pi/4, pi/4] and two
-    // polynomials; within 1.9e-7 of the exact values over 2^24 words, the
-    // float rounding of the revolutions included (measured on gfx950), and
-    // omega only orients the deflections, whose size the polynomials below set
-    const float rev = ((float)(int32_t)w.w + 0.5f) * 0x1p-32f;
-    const float so = __builtin_amdgcn_sinf(rev), co = __builtin_amdgcn_cosf(rev);
+    // omega = 2 pi u(w3) from the hardware sine and cosine (two instructions
+    // instead of a range reduction and two polynomials): it only orients the
+    // deflections, whose size the polynomials below set
+    float so, co;
+    azimuth_sincos(w.w, &so, &co);
 
     // unit direction from the slopes
     const float dz = __builtin_amdgcn_rsqf(1.0f + fmaf(tx, tx, ty * ty));
@@ -1084,6 +1081,12 @@ __global__ void supa_philox_kernel(const uint32_t *ctr, int64_t n, uint32_t k0, 
     out[4 * t + 3] = w.w;
 }
 
+__global__ void supa_azimuth_kernel(const uint32_t *w, int64_t n, float *s, float *c) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    azimuth_sincos(w[t], &s[t], &c[t]);
+}
+
 // ---------------------------------------------------------------------------
 // host-side launchers (called by the C ABI in supa_api.hip)
 // ---------------------------------------------------------------------------
@@ -1133,6 +1136,14 @@ hipError_t launch_propagate(const Params &P, bool literal, bool rings, int block
     }
     if (rings) return literal ? launch_kin<true, true, false>(P, blocks, lds, s) : launch_kin<false, true, false>(P, blocks, lds, s);
     return literal ? launch_kin<true, false, false>(P, blocks, lds, s) : launch_kin<false, false, false>(P, blocks, lds, s);
+}
+
+hipError_t launch_azimuth(const uint32_t *w, int64_t n, float *sn, float *cs, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int threads = 256;
+    const int64_t blocks = (n + threads - 1) / threads;
+    hipLaunchKernelGGL(supa_azimuth_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, w, n, sn, cs);
+    return hipGetLastError();
 }
 
 hipError_t launch_philox(const uint32_t *ctr, int64_t n, uint32_t k0, uint32_t k1, uint32_t *out,

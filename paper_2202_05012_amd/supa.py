@@ -74,7 +74,7 @@ class Output(C.Structure):
 
 EXPORTS = ["supa_abi_version", "supa_validate_geometry", "supa_validate_call", "supa_init_geometry", "supa_destroy",
            "supa_simulate", "supa_simulate_batches", "supa_simulate_noalloc", "supa_set_launch", "supa_set_schedule", "supa_set_subtrees", "supa_last_subtrees", "supa_autotune", "supa_autotune_forget",
-           "supa_graph_create", "supa_graph_launch", "supa_graph_check", "supa_graph_destroy", "supa_last_timing", "supa_last_kernel_times", "supa_last_wave_times", "supa_philox",
+           "supa_graph_create", "supa_graph_launch", "supa_graph_check", "supa_graph_destroy", "supa_last_timing", "supa_last_kernel_times", "supa_last_wave_times", "supa_philox", "supa_azimuth",
            "supa_last_error"]
 
 _lib = None
@@ -135,6 +135,8 @@ def load():
         L.supa_last_kernel_times.argtypes = [C.c_void_p, C.POINTER(C.c_float), C.c_int32]
         L.supa_philox.restype = C.c_int
         L.supa_philox.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_uint64, C.c_void_p]
+        L.supa_azimuth.restype = C.c_int
+        L.supa_azimuth.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         L.supa_last_error.restype = C.c_char_p
         L.supa_last_error.argtypes = [C.c_void_p]
         _lib = L
@@ -489,6 +491,15 @@ class Simulator:
             if k in out:
                 out[k] = out[k][:tn]
         return out
+
+    def azimuth(self, w: torch.Tensor):
+        """The kernel's sine and cosine of the azimuth 2 pi u(w) for uint32
+        words w (int32 tensor, n) -> (sin, cos), float32 (n)."""
+        w = w.contiguous()
+        sn = torch.empty(w.shape[0], dtype=torch.float32, device=w.device)
+        cs = torch.empty_like(sn)
+        self._check(self.lib.supa_azimuth(self.ctx, w.data_ptr(), w.shape[0], sn.data_ptr(), cs.data_ptr()))
+        return sn, cs
 
     def philox(self, ctr: torch.Tensor, key: int) -> torch.Tensor:
         """Philox4x32-10 blocks on the device: ctr int32/uint32 (n, 4) -> (n, 4)."""
